@@ -1,0 +1,202 @@
+"""CPU oracle for custom-intersector ray traversal (test infrastructure only).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package; the product library never does.
+
+Oracle A (:func:`brute`): float64 brute force over every triangle -- the plain
+definition of the closest-hit / any-hit queries of Section 3.1, with the
+alpha-mask and procedural intersectors of Section 4 evaluated in float64.
+
+Oracle B (:func:`build_bvh`, :func:`traverse`): its own binned-SAH BVH and a
+float32 while-while traversal (Algorithm 1) that counts ray/box and
+ray/triangle tests the way the heat-map intersector of Section 4 does.
+
+The C source is ``rt_oracle.c``; :func:`build` compiles it with gcc.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rt_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+KINDS = {"default": 0, "alpha": 1, "procedural": 2}
+MISS = 0xFFFFFFFF
+
+E_NEAR_TIE = 1
+E_NEAR_EDGE = 2
+E_NEAR_FILTER = 4
+
+NODE_DTYPE = np.dtype([("lo", "<f4", 3), ("hi", "<f4", 3), ("left", "<u4"), ("right", "<u4"),
+                       ("first", "<u4"), ("count", "<u4"), ("depth", "<u4")])
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into ``oracle/liboracle.so`` with gcc."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-pthread", "-Wall", "-Wextra", "-Wno-unused-parameter",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Isect(C.Structure):
+    _fields_ = [("texcoords", C.c_void_p), ("textures", C.c_void_p), ("n_tex", C.c_uint32),
+                ("width", C.c_uint32), ("height", C.c_uint32), ("alpha_min", C.c_uint32),
+                ("checker_n", C.c_uint32)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        lib.orc_brute.argtypes = [P, P, C.c_uint32, P, P, C.c_uint32, C.c_int, P, C.c_int,
+                                  P, P, P, P, P, P, P, P, C.c_int]
+        lib.orc_brute.restype = C.c_int
+        lib.orc_build.argtypes = [P, C.c_uint32, P, P, P, P]
+        lib.orc_build.restype = C.c_int
+        lib.orc_traverse.argtypes = [P, P, C.c_uint32, P, P, C.c_uint32, P, C.c_uint32, C.c_int,
+                                     P, C.c_int, P, P, P, P, P, C.c_int]
+        lib.orc_traverse.restype = C.c_int
+        lib.orc_node_size.restype = C.c_uint32
+        assert lib.orc_node_size() == NODE_DTYPE.itemsize
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _threads(n):
+    if n is not None:
+        return int(n)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def _isect(texcoords, textures, alpha_min, checker_n):
+    is_ = _Isect()
+    keep = []
+    if texcoords is not None:
+        tc = np.ascontiguousarray(texcoords, np.float32)
+        keep.append(tc)
+        is_.texcoords = tc.ctypes.data
+    if textures is not None:
+        tx = np.ascontiguousarray(textures, np.uint32)
+        keep.append(tx)
+        is_.textures = tx.ctypes.data
+        is_.n_tex, is_.height, is_.width = (int(s) for s in tx.shape)
+    is_.alpha_min = int(alpha_min)
+    is_.checker_n = int(checker_n)
+    return is_, keep
+
+
+def _check_kind(kind, geom_ids, texcoords, textures, n_tris):
+    if kind not in KINDS:
+        raise ValueError(f"unknown intersector {kind!r}")
+    if kind == "alpha":
+        if texcoords is None or textures is None:
+            raise ValueError("alpha intersector needs texcoords and textures")
+        if np.asarray(texcoords).shape[0] < n_tris:
+            raise ValueError("texcoords must cover every triangle")
+        if geom_ids is not None and n_tris and int(np.max(geom_ids)) >= np.asarray(textures).shape[0]:
+            raise ValueError("geom_id out of range of the texture array")
+
+
+def brute(vertices, rays, kind="default", *, geom_ids=None, texcoords=None, textures=None,
+          alpha_min=128, checker_n=8, any_hit=False, ray_index=None, threads=None):
+    """Oracle A.  Returns a dict with float64 ``t, u, v, t2, bound_uv, bound_t``,
+    uint32 ``prim`` (``MISS`` for none) and uint8 exception ``flags``; entries
+    follow ``ray_index`` when given."""
+    lib = _load()
+    verts = np.ascontiguousarray(vertices, np.float32).reshape(-1, 9)
+    r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+    n = verts.shape[0]
+    _check_kind(kind, geom_ids, texcoords, textures, n)
+    g = None if geom_ids is None else np.ascontiguousarray(geom_ids, np.uint32)
+    idx = None if ray_index is None else np.ascontiguousarray(ray_index, np.int64)
+    m = r.shape[0] if idx is None else idx.shape[0]
+    out = {k: np.empty(m, np.float64) for k in ("t", "u", "v", "t2", "bound_uv", "bound_t")}
+    out["prim"] = np.empty(m, np.uint32)
+    out["flags"] = np.empty(m, np.uint8)
+    is_, keep = _isect(texcoords, textures, alpha_min, checker_n)
+    rc = lib.orc_brute(_ptr(verts), _ptr(g), n, _ptr(r), _ptr(idx), m, KINDS[kind],
+                       C.byref(is_), int(bool(any_hit)), _ptr(out["t"]), _ptr(out["prim"]),
+                       _ptr(out["u"]), _ptr(out["v"]), _ptr(out["t2"]), _ptr(out["flags"]),
+                       _ptr(out["bound_uv"]), _ptr(out["bound_t"]), _threads(threads))
+    if rc != 0:
+        raise RuntimeError(f"orc_brute failed ({rc})")
+    del keep
+    return out
+
+
+@dataclass
+class OracleBVH:
+    nodes: np.ndarray    # NODE_DTYPE, preorder, node 0 = root
+    perm: np.ndarray     # uint32, leaf order -> input triangle index
+    max_depth: int
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.nodes.shape[0])
+
+
+def build_bvh(vertices) -> OracleBVH:
+    """Oracle B's own BVH build (binned SAH, leaves of at most 4 triangles)."""
+    lib = _load()
+    verts = np.ascontiguousarray(vertices, np.float32).reshape(-1, 9)
+    n = verts.shape[0]
+    nodes = np.zeros(max(1, 2 * n), NODE_DTYPE)
+    perm = np.zeros(max(1, n), np.uint32)
+    nn = C.c_uint32()
+    md = C.c_uint32()
+    rc = lib.orc_build(_ptr(verts), n, _ptr(nodes), _ptr(perm), C.byref(nn), C.byref(md))
+    if rc != 0:
+        raise MemoryError("orc_build failed")
+    return OracleBVH(nodes[: nn.value].copy(), perm[:n].copy(), int(md.value))
+
+
+def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, texcoords=None,
+             textures=None, alpha_min=128, checker_n=8, any_hit=False, count=True, threads=None):
+    """Oracle B traversal.  Returns float32 ``t, u, v``, uint32 ``prim`` and,
+    with ``count``, uint32 ``counters [N, 4]`` = (box tests, triangle tests,
+    candidates handed to the intersector, accepted candidates)."""
+    lib = _load()
+    verts = np.ascontiguousarray(vertices, np.float32).reshape(-1, 9)
+    r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+    n = verts.shape[0]
+    _check_kind(kind, geom_ids, texcoords, textures, n)
+    g = None if geom_ids is None else np.ascontiguousarray(geom_ids, np.uint32)
+    m = r.shape[0]
+    out = {k: np.empty(m, np.float32) for k in ("t", "u", "v")}
+    out["prim"] = np.empty(m, np.uint32)
+    cnt = np.empty((m, 4), np.uint32) if count else None
+    is_, keep = _isect(texcoords, textures, alpha_min, checker_n)
+    rc = lib.orc_traverse(_ptr(verts), _ptr(g), n, _ptr(bvh.nodes), _ptr(bvh.perm), bvh.n_nodes,
+                          _ptr(r), m, KINDS[kind], C.byref(is_), int(bool(any_hit)),
+                          _ptr(out["t"]), _ptr(out["prim"]), _ptr(out["u"]), _ptr(out["v"]),
+                          _ptr(cnt), _threads(threads))
+    if rc != 0:
+        raise RuntimeError(f"orc_traverse failed ({rc})")
+    if count:
+        out["counters"] = cnt
+    del keep
+    return out

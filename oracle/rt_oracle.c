@@ -1,0 +1,745 @@
+/*
+ * rt_oracle.c -- CPU oracle for custom-intersector ray traversal.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header or table with the GPU library.
+ *
+ * Two oracles, both plain and slow on purpose:
+ *
+ * A. orc_brute  -- the plain definition of the visibility queries
+ *    (Section 3.1: closest-hit returns the nearest accepted hit, any-hit the
+ *    first one encountered).  Section 3.2 notes that a query may run over a
+ *    linear primitive list with no BVH at all and must give the same answer,
+ *    so oracle A tests every ray against every triangle in float64.  The
+ *    ray/triangle test is the plane-then-area-ratio formulation (not the
+ *    one the GPU uses), and the intersector (Section 4: alpha mask, procedural
+ *    mask) is evaluated in float64 on the float64 barycentrics.
+ *    It also reports, per ray, the second-nearest accepted distance and the
+ *    flags of the exception set (near-ties, near-edge hits, near filter
+ *    decisions) together with an a-priori float32 forward-error bound.
+ *
+ * B. orc_build + orc_traverse -- the BVH heat-map counts of Section 4 (the
+ *    counting intersector increments one counter per ray/box test and one per
+ *    ray/triangle test) depend on the BVH and on the traversal order, so they
+ *    have no order-free definition.  Oracle B builds its own BVH (binned SAH,
+ *    the reading documented with the build) and walks it with the while-while
+ *    scheme of Algorithm 1 in float32, the precision of the paper's
+ *    basic_triangle<3, float>; box tests are intercepted for counting, and
+ *    triangle tests are followed by the intersector's accept decision, whose
+ *    result is AND-ed into the hit (Listing 3 / Listing 5 semantics).
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared -pthread -lm.
+ * -ffp-contract=off matters: every fused multiply-add below is an explicit
+ * fma()/fmaf() call and nothing else may be contracted.
+ */
+#include <float.h>
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MISS 0xFFFFFFFFu
+
+enum { ORC_DEFAULT = 0, ORC_ALPHA = 1, ORC_PROCEDURAL = 2 };
+
+/* Exception-set flag bits reported by oracle A. */
+enum {
+    ORC_E_NEAR_TIE = 1u,      /* two nearest accepted t within 1e-6 relative */
+    ORC_E_NEAR_EDGE = 2u,     /* a relevant candidate within delta of an edge */
+    ORC_E_NEAR_FILTER = 4u,   /* a relevant accept decision within delta of its boundary */
+};
+
+typedef struct {
+    const float *texcoords;   /* [n_prims][3][2], by input triangle index */
+    const uint32_t *textures; /* [n_tex][height][width] RGBA8, alpha in the high byte */
+    uint32_t n_tex, width, height;
+    uint32_t alpha_min;       /* accept iff alpha byte >= alpha_min */
+    uint32_t checker_n;       /* procedural: accept iff floor(n u)+floor(n v) even */
+} orc_isect;
+
+/* ======================================================================
+ * Oracle A: float64 brute force
+ * ====================================================================== */
+
+typedef struct { double x, y, z; } d3;
+
+static d3 d3_sub(d3 a, d3 b) { d3 r = {a.x - b.x, a.y - b.y, a.z - b.z}; return r; }
+static d3 d3_add(d3 a, d3 b) { d3 r = {a.x + b.x, a.y + b.y, a.z + b.z}; return r; }
+static d3 d3_scale(d3 a, double s) { d3 r = {a.x * s, a.y * s, a.z * s}; return r; }
+static double d3_dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static d3 d3_cross(d3 a, d3 b)
+{
+    d3 r = {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+    return r;
+}
+static double d3_norm(d3 a) { return sqrt(d3_dot(a, a)); }
+static d3 d3_load(const float *p) { d3 r = {p[0], p[1], p[2]}; return r; }
+
+/* Distance of x to the nearest integer. */
+static double frac_dist(double x) { return fabs(x - floor(x + 0.5)); }
+
+/* Alpha-mask decision (Section 4, Listing 5) in float64: interpolate the
+ * three texture coordinates with weights (1-u-v, u, v), take the nearest texel
+ * (clamp to edge) of texture geom_id and compare its alpha byte.
+ * *margin receives the distance (in texels) of the lookup to a texel edge. */
+static int alpha_accept64(const orc_isect *is, uint32_t prim, uint32_t geom,
+                          double u, double v, double *margin)
+{
+    const float *tc = is->texcoords + (size_t)prim * 6;
+    double w0 = 1.0 - u - v;
+    double s = w0 * tc[0] + u * tc[2] + v * tc[4];
+    double t = w0 * tc[1] + u * tc[3] + v * tc[5];
+    double xs = s * is->width, ys = t * is->height;
+    double xf = floor(xs), yf = floor(ys);
+    if (xf < 0) xf = 0;
+    if (xf > is->width - 1.0) xf = is->width - 1.0;
+    if (yf < 0) yf = 0;
+    if (yf > is->height - 1.0) yf = is->height - 1.0;
+    uint32_t texel = is->textures[((size_t)geom * is->height + (size_t)yf) * is->width + (size_t)xf];
+    double mx = frac_dist(xs), my = frac_dist(ys);
+    *margin = mx < my ? mx : my;
+    return (texel >> 24) >= is->alpha_min;
+}
+
+/* Procedural checker in float64; *margin is the distance of n*u or n*v to an
+ * integer. */
+static int checker_accept64(const orc_isect *is, double u, double v, double *margin)
+{
+    double n = (double)is->checker_n;
+    double a = floor(n * u), b = floor(n * v);
+    double mu = frac_dist(n * u), mv = frac_dist(n * v);
+    *margin = mu < mv ? mu : mv;
+    long long k = (long long)a + (long long)b;
+    return (k % 2) == 0;
+}
+
+typedef struct {
+    const float *verts;       /* [n_tris][3][3] */
+    const uint32_t *geom;     /* [n_tris] or NULL */
+    uint32_t n_tris;
+    const float *rays;        /* [n_rays][8] */
+    const int64_t *ray_index; /* optional subset of rays (NULL = all) */
+    uint32_t n_rays;
+    int kind;
+    orc_isect is;
+    int any_hit;
+    /* outputs, indexed like the (sub)set */
+    double *t, *u, *v, *t2, *bound_uv, *bound_t;
+    uint32_t *prim;
+    uint8_t *flags;
+    /* work distribution */
+    uint32_t next;
+    pthread_mutex_t lock;
+} brute_job;
+
+/* One candidate evaluation in float64.  Returns 1 iff the ray meets the
+ * triangle's plane (d.n != 0); then t, u, v, the edge margin
+ * min(u, v, 1-u-v) and the float32 error bounds are filled in. */
+static int plane_hit64(d3 o, d3 d, const float *tri, double *t, double *u, double *v,
+                       double *margin, double *b_uv, double *b_t)
+{
+    d3 v0 = d3_load(tri), v1 = d3_load(tri + 3), v2 = d3_load(tri + 6);
+    d3 e1 = d3_sub(v1, v0), e2 = d3_sub(v2, v0);
+    d3 n = d3_cross(e1, e2);
+    double dn = d3_dot(d, n);
+    if (dn == 0.0) return 0;
+    double tt = d3_dot(d3_sub(v0, o), n) / dn;
+    d3 p = d3_add(o, d3_scale(d, tt));
+    d3 w = d3_sub(p, v0);
+    double nn = d3_dot(n, n);
+    double uu = d3_dot(d3_cross(w, e2), n) / nn;
+    double vv = d3_dot(d3_cross(e1, w), n) / nn;
+    *t = tt; *u = uu; *v = vv;
+    double m = uu < vv ? uu : vv;
+    double w0 = 1.0 - uu - vv;
+    *margin = m < w0 ? m : w0;
+    /* A-priori forward-error bound of a float32 Moller-Trumbore evaluation
+     * from the same float32 inputs (unit roundoff eps = 2^-24).  Term by term:
+     * s = o - v0, e1, e2 are each rounded once (eps relative); p = d x e2 and
+     * q = s x e1 carry under 5 eps of their operand norms; each three-term
+     * fma dot product adds 3 eps; the reciprocal and the final products add
+     * 2 eps.  Summed, |du|, |dv| <= 8 eps |d| (|s|(|e1|+|e2|) + |e1||e2|)/|det|
+     * + 2 eps and |dt| <= 9 eps |e1||e2| (|s| + |t||d|)/|det| + 2 eps |t|,
+     * with |det| = |d.(e1 x e2)|.  The constants are rounded up (10 and 4) to
+     * absorb the difference between the float32 and exact det. */
+    const double eps = 0x1p-24;
+    double nd = d3_norm(d), ne1 = d3_norm(e1), ne2 = d3_norm(e2);
+    double ns = d3_norm(d3_sub(o, v0));
+    double adet = fabs(dn);
+    *b_uv = 10.0 * eps * nd * (ns * (ne1 + ne2) + ne1 * ne2) / adet + 4.0 * eps;
+    *b_t = 10.0 * eps * ne1 * ne2 * (ns + fabs(tt) * nd) / adet + 4.0 * eps * fabs(tt);
+    return 1;
+}
+
+static void brute_one(brute_job *job, uint32_t slot)
+{
+    int64_t ri = job->ray_index ? job->ray_index[slot] : (int64_t)slot;
+    const float *r = job->rays + (size_t)ri * 8;
+    d3 o = {r[0], r[1], r[2]}, d = {r[4], r[5], r[6]};
+    double tmin = r[3], tmax = r[7];
+    double t1 = INFINITY, t2 = INFINITY, u1 = 0, v1 = 0, bu1 = 0, bt1 = 0;
+    uint32_t p1 = ORC_MISS;
+
+    /* Pass 1: nearest and second-nearest accepted hit (ties -> lowest index).
+     * Any-hit keeps the same nearest record: its hit/miss answer is the
+     * existence of an accepted hit, and the nearest is one such hit. */
+    for (uint32_t k = 0; k < job->n_tris; ++k) {
+        double t, u, v, m, bu, bt;
+        if (!plane_hit64(o, d, job->verts + (size_t)k * 9, &t, &u, &v, &m, &bu, &bt)) continue;
+        if (!(m >= 0.0) || !(t > tmin) || !(t < tmax)) continue;
+        int acc = 1;
+        double fm;
+        if (job->kind == ORC_ALPHA)
+            acc = alpha_accept64(&job->is, k, job->geom ? job->geom[k] : 0, u, v, &fm);
+        else if (job->kind == ORC_PROCEDURAL)
+            acc = checker_accept64(&job->is, u, v, &fm);
+        if (!acc) continue;
+        if (t < t1) {
+            t2 = t1;
+            t1 = t; u1 = u; v1 = v; p1 = k; bu1 = bu; bt1 = bt;
+        } else if (t < t2) {
+            t2 = t;
+        }
+    }
+
+    /* Pass 2: exception flags.  Candidates that matter are those whose
+     * plane distance lies inside (tmin, tmax) and no farther than the nearest
+     * accepted hit (plus 1e-6 relative); for a miss, every such candidate. */
+    uint8_t fl = 0;
+    if (p1 != ORC_MISS && t2 - t1 < 1e-6 * fabs(t1)) fl |= ORC_E_NEAR_TIE;
+    double reach = (p1 != ORC_MISS) ? t1 + 1e-6 * fabs(t1) + bt1 : tmax;
+    for (uint32_t k = 0; k < job->n_tris; ++k) {
+        double t, u, v, m, bu, bt;
+        if (!plane_hit64(o, d, job->verts + (size_t)k * 9, &t, &u, &v, &m, &bu, &bt)) continue;
+        if (!(t > tmin - bt) || !(t < tmax + bt) || !(t <= reach + bt)) continue;
+        double delta = bu > 1e-6 ? bu : 1e-6;
+        if (fabs(m) < delta) fl |= ORC_E_NEAR_EDGE;
+        if (m > -delta && job->kind != ORC_DEFAULT) {
+            double fm = 1.0;
+            if (job->kind == ORC_ALPHA) {
+                alpha_accept64(&job->is, k, job->geom ? job->geom[k] : 0, u, v, &fm);
+                /* a lookup coordinate s*W moves by up to ~2*W*delta */
+                if (fm < 4.0 * delta * (job->is.width > job->is.height ? job->is.width : job->is.height))
+                    fl |= ORC_E_NEAR_FILTER;
+            } else {
+                checker_accept64(&job->is, u, v, &fm);
+                if (fm < 2.0 * delta * job->is.checker_n) fl |= ORC_E_NEAR_FILTER;
+            }
+        }
+        /* distance ties between distinct relevant candidates within the
+         * float32 distance error also make the winner ambiguous */
+        if (p1 != ORC_MISS && k != p1 && m > -delta && fabs(t - t1) <= bt + bt1)
+            fl |= ORC_E_NEAR_TIE;
+    }
+
+    job->t[slot] = t1;
+    job->u[slot] = u1;
+    job->v[slot] = v1;
+    job->t2[slot] = t2;
+    job->prim[slot] = p1;
+    job->flags[slot] = fl;
+    job->bound_uv[slot] = bu1;
+    job->bound_t[slot] = bt1;
+}
+
+static void *brute_worker(void *arg)
+{
+    brute_job *job = (brute_job *)arg;
+    for (;;) {
+        pthread_mutex_lock(&job->lock);
+        uint32_t b = job->next;
+        job->next = b + 64 < job->n_rays ? b + 64 : job->n_rays;
+        uint32_t e = job->next;
+        pthread_mutex_unlock(&job->lock);
+        if (b >= e) break;
+        for (uint32_t s = b; s < e; ++s) brute_one(job, s);
+    }
+    return NULL;
+}
+
+static void run_threads(void *(*fn)(void *), void *job, int n_threads)
+{
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    pthread_t th[256];
+    int started = 0;
+    for (int i = 1; i < n_threads; ++i)
+        if (pthread_create(&th[started], NULL, fn, job) == 0) ++started;
+    fn(job);
+    for (int i = 0; i < started; ++i) pthread_join(th[i], NULL);
+}
+
+/* Oracle A entry point.  ray_index may be NULL (all n_rays rays) or list the
+ * n_rays ray indices to evaluate; outputs are indexed by position in that
+ * list.  Misses: prim = ORC_MISS, t = +inf. */
+int orc_brute(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
+              const float *rays, const int64_t *ray_index, uint32_t n_rays,
+              int kind, const orc_isect *is, int any_hit,
+              double *t, uint32_t *prim, double *u, double *v, double *t2,
+              uint8_t *flags, double *bound_uv, double *bound_t, int n_threads)
+{
+    if (kind < ORC_DEFAULT || kind > ORC_PROCEDURAL) return -1;
+    brute_job job;
+    memset(&job, 0, sizeof job);
+    job.verts = verts; job.geom = geom_ids; job.n_tris = n_tris;
+    job.rays = rays; job.ray_index = ray_index; job.n_rays = n_rays;
+    job.kind = kind; job.any_hit = any_hit;
+    if (is) job.is = *is;
+    job.t = t; job.u = u; job.v = v; job.t2 = t2; job.prim = prim; job.flags = flags;
+    job.bound_uv = bound_uv; job.bound_t = bound_t;
+    pthread_mutex_init(&job.lock, NULL);
+    run_threads(brute_worker, &job, n_threads);
+    pthread_mutex_destroy(&job.lock);
+    return 0;
+}
+
+/* ======================================================================
+ * Oracle B part 1: BVH construction (binned SAH)
+ *
+ * The paper uses a BVH without describing its construction.  Reading used
+ * here (and by the product builder, which is a separate implementation):
+ *   - triangle box = exact float min/max of its vertices; centroid (float64)
+ *     = 0.5 * (lo + hi);
+ *   - a node with at most 4 triangles is a leaf;
+ *   - otherwise, per axis with non-zero centroid extent, 32 equal-width bins
+ *     over the centroid range, bin = min(31, (int)((c - cmin) * (32 / ext)));
+ *     every plane between bins is a candidate with cost
+ *     area(L) * |L| + area(R) * |R| (area = box surface in float64); the
+ *     strictly smallest cost wins, ties keep the lower axis, then the lower
+ *     plane; the node's triangles are stably partitioned;
+ *   - when no axis has extent (all centroids equal), or the node sits at
+ *     depth >= 40, the range is split at index count/2 in its current order;
+ *   - nodes are numbered in depth-first preorder, left child first; each
+ *     leaf owns a contiguous range of the final triangle order.
+ * ====================================================================== */
+
+typedef struct {
+    float lo[3], hi[3];
+    uint32_t left, right;  /* children (inner nodes) */
+    uint32_t first, count; /* triangle range (leaves: count > 0) */
+    uint32_t depth;
+} orc_node;
+
+typedef struct {
+    const float *tri_lo, *tri_hi; /* [n][3] float boxes */
+    const double *cen;            /* [n][3] centroids */
+    uint32_t *perm, *tmp;
+    orc_node *nodes;
+    uint32_t n_nodes, cap;
+    uint32_t max_depth;
+} build_ctx;
+
+static double box_area(const float lo[3], const float hi[3])
+{
+    double dx = (double)hi[0] - (double)lo[0];
+    double dy = (double)hi[1] - (double)lo[1];
+    double dz = (double)hi[2] - (double)lo[2];
+    return 2.0 * (dx * dy + dy * dz + dz * dx);
+}
+
+static void box_empty(float lo[3], float hi[3])
+{
+    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+}
+
+static void box_grow(float lo[3], float hi[3], const float *blo, const float *bhi)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (blo[a] < lo[a]) lo[a] = blo[a];
+        if (bhi[a] > hi[a]) hi[a] = bhi[a];
+    }
+}
+
+static int bin_of(double c, double cmin, double scale)
+{
+    int b = (int)((c - cmin) * scale);
+    if (b > 31) b = 31;
+    if (b < 0) b = 0;
+    return b;
+}
+
+static uint32_t build_rec(build_ctx *ctx, uint32_t first, uint32_t count, uint32_t depth)
+{
+    uint32_t id = ctx->n_nodes++;
+    orc_node *nd = &ctx->nodes[id];
+    memset(nd, 0, sizeof *nd);
+    nd->depth = depth;
+    if (depth > ctx->max_depth) ctx->max_depth = depth;
+    box_empty(nd->lo, nd->hi);
+    for (uint32_t i = first; i < first + count; ++i) {
+        uint32_t k = ctx->perm[i];
+        box_grow(nd->lo, nd->hi, ctx->tri_lo + 3 * (size_t)k, ctx->tri_hi + 3 * (size_t)k);
+    }
+    if (count <= 4) {
+        nd->first = first;
+        nd->count = count;
+        return id;
+    }
+
+    double cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t i = first; i < first + count; ++i) {
+        const double *c = ctx->cen + 3 * (size_t)ctx->perm[i];
+        for (int a = 0; a < 3; ++a) {
+            if (c[a] < cmin[a]) cmin[a] = c[a];
+            if (c[a] > cmax[a]) cmax[a] = c[a];
+        }
+    }
+
+    int best_axis = -1, best_plane = 0;
+    double best_cost = INFINITY;
+    if (depth < 40) {
+        for (int a = 0; a < 3; ++a) {
+            double ext = cmax[a] - cmin[a];
+            if (!(ext > 0.0)) continue;
+            double scale = 32.0 / ext;
+            float blo[32][3], bhi[32][3];
+            uint32_t bn[32];
+            for (int b = 0; b < 32; ++b) { box_empty(blo[b], bhi[b]); bn[b] = 0; }
+            for (uint32_t i = first; i < first + count; ++i) {
+                uint32_t k = ctx->perm[i];
+                int b = bin_of(ctx->cen[3 * (size_t)k + a], cmin[a], scale);
+                bn[b]++;
+                box_grow(blo[b], bhi[b], ctx->tri_lo + 3 * (size_t)k, ctx->tri_hi + 3 * (size_t)k);
+            }
+            /* candidate plane s: bins [0, s) left, [s, 32) right */
+            for (int s = 1; s < 32; ++s) {
+                float llo[3], lhi[3], rlo[3], rhi[3];
+                uint32_t nl = 0, nr = 0;
+                box_empty(llo, lhi);
+                box_empty(rlo, rhi);
+                for (int b = 0; b < s; ++b) { nl += bn[b]; if (bn[b]) box_grow(llo, lhi, blo[b], bhi[b]); }
+                for (int b = s; b < 32; ++b) { nr += bn[b]; if (bn[b]) box_grow(rlo, rhi, blo[b], bhi[b]); }
+                if (nl == 0 || nr == 0) continue;
+                double cost = box_area(llo, lhi) * (double)nl + box_area(rlo, rhi) * (double)nr;
+                if (cost < best_cost) { best_cost = cost; best_axis = a; best_plane = s; }
+            }
+        }
+    }
+
+    uint32_t nl;
+    if (best_axis >= 0) {
+        double scale = 32.0 / (cmax[best_axis] - cmin[best_axis]);
+        uint32_t w = first, wr = 0;
+        for (uint32_t i = first; i < first + count; ++i) {
+            uint32_t k = ctx->perm[i];
+            if (bin_of(ctx->cen[3 * (size_t)k + best_axis], cmin[best_axis], scale) < best_plane)
+                ctx->perm[w++] = k;
+            else
+                ctx->tmp[wr++] = k;
+        }
+        nl = w - first;
+        memcpy(ctx->perm + w, ctx->tmp, wr * sizeof(uint32_t));
+    } else {
+        nl = count / 2;
+    }
+    uint32_t l = build_rec(ctx, first, nl, depth + 1);
+    uint32_t r = build_rec(ctx, first + nl, count - nl, depth + 1);
+    nd = &ctx->nodes[id]; /* nodes[] does not move (preallocated) */
+    nd->left = l;
+    nd->right = r;
+    return id;
+}
+
+/* Builds the oracle's BVH.  nodes must hold 2*n_tris (at least 1) entries.
+ * Outputs: node array (preorder, node 0 = root), perm (leaf order -> input
+ * triangle index), node count and maximum node depth. */
+int orc_build(const float *verts, uint32_t n_tris, orc_node *nodes, uint32_t *perm,
+              uint32_t *n_nodes_out, uint32_t *max_depth_out)
+{
+    if (n_tris == 0) {
+        memset(&nodes[0], 0, sizeof nodes[0]);
+        box_empty(nodes[0].lo, nodes[0].hi);
+        *n_nodes_out = 1;
+        *max_depth_out = 0;
+        return 0;
+    }
+    float *tlo = malloc(sizeof(float) * 3 * n_tris);
+    float *thi = malloc(sizeof(float) * 3 * n_tris);
+    double *cen = malloc(sizeof(double) * 3 * n_tris);
+    uint32_t *tmp = malloc(sizeof(uint32_t) * n_tris);
+    if (!tlo || !thi || !cen || !tmp) { free(tlo); free(thi); free(cen); free(tmp); return -1; }
+    for (uint32_t k = 0; k < n_tris; ++k) {
+        const float *t = verts + 9 * (size_t)k;
+        for (int a = 0; a < 3; ++a) {
+            float lo = t[a], hi = t[a];
+            if (t[3 + a] < lo) lo = t[3 + a];
+            if (t[6 + a] < lo) lo = t[6 + a];
+            if (t[3 + a] > hi) hi = t[3 + a];
+            if (t[6 + a] > hi) hi = t[6 + a];
+            tlo[3 * (size_t)k + a] = lo;
+            thi[3 * (size_t)k + a] = hi;
+            cen[3 * (size_t)k + a] = 0.5 * ((double)lo + (double)hi);
+        }
+        perm[k] = k;
+    }
+    build_ctx ctx = {tlo, thi, cen, perm, tmp, nodes, 0, 2 * n_tris, 0};
+    build_rec(&ctx, 0, n_tris, 0);
+    *n_nodes_out = ctx.n_nodes;
+    *max_depth_out = ctx.max_depth;
+    free(tlo); free(thi); free(cen); free(tmp);
+    return 0;
+}
+
+/* ======================================================================
+ * Oracle B part 2: float32 while-while traversal (Algorithm 1)
+ *
+ * Per ray:
+ *   setup   d' = d with components of magnitude < 2^-80 replaced by
+ *           +-2^-80; inv = 1/d'; ood = o*inv; tmax_cur = tmax.
+ *   box     t0 = fma(lo, inv, -ood), t1 = fma(hi, inv, -ood) per axis;
+ *           tn = max(max(max(min x, min y), min z), tmin),
+ *           tf = min(min(min(max x, max y), max z), tmax_cur); hit iff tn <= tf.
+ *           Every box test is counted.
+ *   root    test the root box; a miss ends the ray.
+ *   inner   test both children's boxes; both hit -> visit the one with the
+ *           smaller tn (tie -> left) and push the other with its tn; one hit ->
+ *           visit it; none -> pop.
+ *   pop     discard entries whose tn > tmax_cur; an empty stack ends the ray.
+ *   leaf    test the leaf's triangles in stored order (each counted), then pop.
+ *   tri     Moller-Trumbore, two-sided: p = d x e2, det = e1.p, det == 0 ->
+ *           no hit; r = 1/det; s = o - v0; u = (s.p) r, reject unless
+ *           0 <= u <= 1; q = s x e1; v = (d.q) r, reject unless v >= 0 and
+ *           u + v <= 1; t = (e2.q) r, candidate iff tmin < t < tmax_cur, with
+ *           e1 = v1 - v0, e2 = v2 - v0 rounded to float32,
+ *           dot(a,b) = fma(a.z,b.z, fma(a.y,b.y, a.x*b.x)) and
+ *           cross(a,b)_x = fma(a.y,b.z, -(a.z*b.y)) (cyclically).
+ *           A candidate is handed to the intersector (counted); if accepted:
+ *           closest-hit -> tmax_cur = t and the record is kept; any-hit -> stop.
+ *   alpha   w0 = (1-u)-v; s = fma(v,tc2, fma(u,tc1, w0*tc0)) per coordinate;
+ *           x = clamp(floor(s*W), 0, W-1), y likewise from t and H;
+ *           accept iff texel(geom, y, x) >> 24 >= alpha_min.
+ *   checker accept iff floor(n*u) + floor(n*v) is even.
+ * ====================================================================== */
+
+typedef struct {
+    const float *verts;
+    const uint32_t *geom;
+    uint32_t n_tris;
+    const orc_node *nodes;
+    const uint32_t *perm;
+    uint32_t n_nodes;
+    const float *rays;
+    uint32_t n_rays;
+    int kind;
+    orc_isect is;
+    int any_hit;
+    float *t, *u, *v;
+    uint32_t *prim;
+    uint32_t *counters; /* [n_rays][4]: boxes, triangles, candidates, accepts */
+    uint32_t next;
+    pthread_mutex_t lock;
+} trav_job;
+
+static float dot3f(const float a[3], const float b[3])
+{
+    return fmaf(a[2], b[2], fmaf(a[1], b[1], a[0] * b[0]));
+}
+
+static void cross3f(const float a[3], const float b[3], float r[3])
+{
+    r[0] = fmaf(a[1], b[2], -(a[2] * b[1]));
+    r[1] = fmaf(a[2], b[0], -(a[0] * b[2]));
+    r[2] = fmaf(a[0], b[1], -(a[1] * b[0]));
+}
+
+typedef struct {
+    float o[3], d[3], inv[3], ood[3];
+    float tmin, tmax_cur;
+    /* record */
+    float t, u, v;
+    uint32_t prim;
+    int done;
+    uint32_t n_box, n_tri, n_cand, n_acc;
+} ray_state;
+
+/* Box test (the intersect(ray, aabb) call site of Algorithm 1); the counter
+ * is the heat-map intersector's interception of that call. */
+static int box_test(ray_state *rs, const float lo[3], const float hi[3], float *tn_out)
+{
+    rs->n_box++;
+    float t0[3], t1[3];
+    for (int a = 0; a < 3; ++a) {
+        t0[a] = fmaf(lo[a], rs->inv[a], -rs->ood[a]);
+        t1[a] = fmaf(hi[a], rs->inv[a], -rs->ood[a]);
+    }
+    float tn = fmaxf(fmaxf(fmaxf(fminf(t0[0], t1[0]), fminf(t0[1], t1[1])), fminf(t0[2], t1[2])), rs->tmin);
+    float tf = fminf(fminf(fminf(fmaxf(t0[0], t1[0]), fmaxf(t0[1], t1[1])), fmaxf(t0[2], t1[2])), rs->tmax_cur);
+    *tn_out = tn;
+    return tn <= tf;
+}
+
+static int accept32(const trav_job *job, uint32_t prim, float u, float v)
+{
+    if (job->kind == ORC_ALPHA) {
+        const orc_isect *is = &job->is;
+        const float *tc = is->texcoords + (size_t)prim * 6;
+        float w0 = (1.0f - u) - v;
+        float s = fmaf(v, tc[4], fmaf(u, tc[2], w0 * tc[0]));
+        float t = fmaf(v, tc[5], fmaf(u, tc[3], w0 * tc[1]));
+        float xf = floorf(s * (float)is->width);
+        float yf = floorf(t * (float)is->height);
+        if (xf < 0.0f) xf = 0.0f;
+        if (xf > (float)(is->width - 1)) xf = (float)(is->width - 1);
+        if (yf < 0.0f) yf = 0.0f;
+        if (yf > (float)(is->height - 1)) yf = (float)(is->height - 1);
+        uint32_t g = job->geom ? job->geom[prim] : 0;
+        uint32_t texel = is->textures[((size_t)g * is->height + (uint32_t)yf) * is->width + (uint32_t)xf];
+        return (texel >> 24) >= is->alpha_min;
+    }
+    if (job->kind == ORC_PROCEDURAL) {
+        float n = (float)job->is.checker_n;
+        int a = (int)floorf(n * u), b = (int)floorf(n * v);
+        return ((a + b) & 1) == 0;
+    }
+    return 1;
+}
+
+/* Triangle test (the intersect(ray, prim) call site) followed by the
+ * intersector's decision. */
+static void tri_test(const trav_job *job, ray_state *rs, uint32_t slot)
+{
+    rs->n_tri++;
+    uint32_t prim = job->perm[slot];
+    const float *tv = job->verts + 9 * (size_t)prim;
+    float v0[3] = {tv[0], tv[1], tv[2]};
+    float e1[3] = {tv[3] - tv[0], tv[4] - tv[1], tv[5] - tv[2]};
+    float e2[3] = {tv[6] - tv[0], tv[7] - tv[1], tv[8] - tv[2]};
+    float p[3], q[3], s[3];
+    cross3f(rs->d, e2, p);
+    float det = dot3f(e1, p);
+    if (det == 0.0f) return;
+    float r = 1.0f / det;
+    s[0] = rs->o[0] - v0[0]; s[1] = rs->o[1] - v0[1]; s[2] = rs->o[2] - v0[2];
+    float u = dot3f(s, p) * r;
+    if (!(u >= 0.0f && u <= 1.0f)) return;
+    cross3f(s, e1, q);
+    float v = dot3f(rs->d, q) * r;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return;
+    float t = dot3f(e2, q) * r;
+    if (!(t > rs->tmin && t < rs->tmax_cur)) return;
+    rs->n_cand++;
+    if (!accept32(job, prim, u, v)) return;
+    rs->n_acc++;
+    rs->prim = prim;
+    rs->t = t; rs->u = u; rs->v = v;
+    if (job->any_hit) rs->done = 1;
+    else rs->tmax_cur = t;
+}
+
+static void trav_one(trav_job *job, uint32_t i)
+{
+    const float *r = job->rays + (size_t)i * 8;
+    ray_state rs;
+    memset(&rs, 0, sizeof rs);
+    const float tiny = 0x1p-80f;
+    for (int a = 0; a < 3; ++a) {
+        rs.o[a] = r[a];
+        rs.d[a] = r[4 + a];
+        float dd = rs.d[a];
+        if (fabsf(dd) < tiny) dd = copysignf(tiny, dd);
+        rs.inv[a] = 1.0f / dd;
+        rs.ood[a] = rs.o[a] * rs.inv[a];
+    }
+    rs.tmin = r[3];
+    rs.tmax_cur = r[7];
+    rs.prim = ORC_MISS;
+    rs.t = INFINITY;
+
+    if (job->n_tris > 0) {
+        uint32_t stack_node[128];
+        float stack_tn[128];
+        int sp = 0;
+        float tn;
+        uint32_t cur = 0;
+        int alive = box_test(&rs, job->nodes[0].lo, job->nodes[0].hi, &tn);
+        while (alive && !rs.done) {
+            /* descend through inner nodes */
+            while (job->nodes[cur].count == 0) {
+                const orc_node *nd = &job->nodes[cur];
+                float tl, tr;
+                int hl = box_test(&rs, job->nodes[nd->left].lo, job->nodes[nd->left].hi, &tl);
+                int hr = box_test(&rs, job->nodes[nd->right].lo, job->nodes[nd->right].hi, &tr);
+                if (hl && hr) {
+                    if (tr < tl) { cur = nd->right; stack_node[sp] = nd->left; stack_tn[sp] = tl; }
+                    else { cur = nd->left; stack_node[sp] = nd->right; stack_tn[sp] = tr; }
+                    ++sp;
+                } else if (hl) {
+                    cur = nd->left;
+                } else if (hr) {
+                    cur = nd->right;
+                } else {
+                    alive = 0;
+                    while (sp > 0) {
+                        --sp;
+                        if (!(stack_tn[sp] > rs.tmax_cur)) { cur = stack_node[sp]; alive = 1; break; }
+                    }
+                    if (!alive) break;
+                }
+            }
+            if (!alive) break;
+            /* leaf: test its triangles in stored order */
+            const orc_node *lf = &job->nodes[cur];
+            for (uint32_t j = lf->first; j < lf->first + lf->count && !rs.done; ++j)
+                tri_test(job, &rs, j);
+            if (rs.done) break;
+            alive = 0;
+            while (sp > 0) {
+                --sp;
+                if (!(stack_tn[sp] > rs.tmax_cur)) { cur = stack_node[sp]; alive = 1; break; }
+            }
+        }
+    }
+
+    if (rs.prim == ORC_MISS) { rs.t = INFINITY; rs.u = 0.0f; rs.v = 0.0f; }
+    job->t[i] = rs.t;
+    job->u[i] = rs.u;
+    job->v[i] = rs.v;
+    job->prim[i] = rs.prim;
+    if (job->counters) {
+        uint32_t *c = job->counters + 4 * (size_t)i;
+        c[0] = rs.n_box; c[1] = rs.n_tri; c[2] = rs.n_cand; c[3] = rs.n_acc;
+    }
+}
+
+static void *trav_worker(void *arg)
+{
+    trav_job *job = (trav_job *)arg;
+    for (;;) {
+        pthread_mutex_lock(&job->lock);
+        uint32_t b = job->next;
+        job->next = b + 256 < job->n_rays ? b + 256 : job->n_rays;
+        uint32_t e = job->next;
+        pthread_mutex_unlock(&job->lock);
+        if (b >= e) break;
+        for (uint32_t i = b; i < e; ++i) trav_one(job, i);
+    }
+    return NULL;
+}
+
+/* Oracle B traversal over a BVH made by orc_build.  Outputs t/u/v/prim per
+ * ray (misses: prim = ORC_MISS, t = +inf, u = v = 0; any-hit: the first
+ * accepted hit) and, if counters != NULL, four uint32 counters per ray. */
+int orc_traverse(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
+                 const orc_node *nodes, const uint32_t *perm, uint32_t n_nodes,
+                 const float *rays, uint32_t n_rays, int kind, const orc_isect *is,
+                 int any_hit, float *t, uint32_t *prim, float *u, float *v,
+                 uint32_t *counters, int n_threads)
+{
+    if (kind < ORC_DEFAULT || kind > ORC_PROCEDURAL) return -1;
+    trav_job job;
+    memset(&job, 0, sizeof job);
+    job.verts = verts; job.geom = geom_ids; job.n_tris = n_tris;
+    job.nodes = nodes; job.perm = perm; job.n_nodes = n_nodes;
+    job.rays = rays; job.n_rays = n_rays; job.kind = kind;
+    if (is) job.is = *is;
+    job.any_hit = any_hit;
+    job.t = t; job.u = u; job.v = v; job.prim = prim; job.counters = counters;
+    pthread_mutex_init(&job.lock, NULL);
+    run_threads(trav_worker, &job, n_threads);
+    pthread_mutex_destroy(&job.lock);
+    return 0;
+}
+
+uint32_t orc_node_size(void) { return (uint32_t)sizeof(orc_node); }

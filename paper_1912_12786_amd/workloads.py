@@ -1,0 +1,366 @@
+"""Seeded synthetic scenes, textures and rays.
+
+This module only *draws inputs*: it holds no ray/box/triangle test, no BVH
+logic and no intersector.  Both the GPU path and the CPU oracle receive the
+arrays it returns, so it is the one module the two sides share.
+
+The paper (Section 4 and the teaser figure) shows alpha-masked billboards,
+a procedural alpha mask and a BVH-cost heat map on unnamed 3-d models; those
+models are not available, so the scenes below are synthetic stand-ins with the
+same structure:
+
+* ``tiny``        -- 1,024 small random triangles in the unit cube, 64x64 rays.
+* ``billboards``  -- 100k camera-facing textured quads (200k triangles),
+                     16 RGBA8 256x256 alpha textures (about 40 % zero texels),
+                     1920x1080 primary rays.
+* ``spheres``     -- 2,000 UV-spheres of 500 triangles (1M triangles),
+                     1920x1080 primary rays plus incoherent diffuse bounce rays.
+
+All randomness comes from ``numpy.random.Generator(PCG64(seed))`` with
+``seed = 191212786 + 1000 * config + stream``; geometry is generated in float64
+and rounded once to float32.
+
+Array conventions (shared by every consumer):
+
+* vertices  ``float32 [n_tris, 3, 3]`` (triangle, corner, xyz)
+* rays      ``float32 [n_rays, 8]`` = ``(ox, oy, oz, tmin, dx, dy, dz, tmax)``
+* texcoords ``float32 [n_tris, 3, 2]`` indexed by the input triangle index
+* textures  ``uint32  [n_tex, H, W]`` RGBA8 packed with R in the low byte and
+            alpha in the high byte
+* geom_ids  ``uint32  [n_tris]``
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 191212786
+
+CFG_TINY = 1
+CFG_BILLBOARDS = 2
+CFG_SPHERES = 3
+CFG_BATCHED = 4
+CFG_DIFF = 5
+
+STREAM_GEOMETRY = 0
+STREAM_TEXTURES = 1
+STREAM_RAYS = 2
+STREAM_WEIGHTS = 3
+
+
+def seed_for(config: int, stream: int) -> int:
+    return SEED_BASE + 1000 * config + stream
+
+
+def rng_for(config: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed_for(config, stream)))
+
+
+# --------------------------------------------------------------------------
+# small vector helpers (input synthesis only)
+# --------------------------------------------------------------------------
+def _normalize(v: np.ndarray) -> np.ndarray:
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def _random_unit(rng: np.random.Generator, n: int) -> np.ndarray:
+    return _normalize(rng.standard_normal((n, 3)))
+
+
+def _onb_from_normal(n: np.ndarray):
+    """Branchless orthonormal basis around unit vectors n (Duff et al. 2017)."""
+    sign = np.where(n[:, 2] >= 0.0, 1.0, -1.0)
+    a = -1.0 / (sign + n[:, 2])
+    b = n[:, 0] * n[:, 1] * a
+    t = np.stack([1.0 + sign * n[:, 0] ** 2 * a, sign * b, -sign * n[:, 0]], axis=1)
+    bt = np.stack([b, sign + n[:, 1] ** 2 * a, -n[:, 1]], axis=1)
+    return t, bt
+
+
+# --------------------------------------------------------------------------
+# cameras
+# --------------------------------------------------------------------------
+def pinhole_rays(width: int, height: int, eye, center, fov_deg: float,
+                 tmin: float = 0.0, tmax: float = math.inf) -> np.ndarray:
+    """Primary rays of a pinhole camera, scanline order, row 0 at the top.
+
+    ``fov_deg`` is the vertical field of view.  Returns ``float32 [W*H, 8]``.
+    """
+    eye = np.asarray(eye, np.float64)
+    center = np.asarray(center, np.float64)
+    fwd = _normalize(center - eye)
+    right = _normalize(np.cross(fwd, np.array([0.0, 1.0, 0.0])))
+    up = np.cross(right, fwd)
+    th = math.tan(math.radians(fov_deg) / 2.0)
+    xs = (2.0 * (np.arange(width) + 0.5) / width - 1.0) * th * width / height
+    ys = (1.0 - 2.0 * (np.arange(height) + 0.5) / height) * th
+    d = (fwd[None, None, :] + xs[None, :, None] * right[None, None, :]
+         + ys[:, None, None] * up[None, None, :])
+    d = _normalize(d.reshape(-1, 3))
+    rays = np.empty((width * height, 8), np.float32)
+    rays[:, 0:3] = eye.astype(np.float32)
+    rays[:, 3] = np.float32(tmin)
+    rays[:, 4:7] = d.astype(np.float32)
+    rays[:, 7] = np.float32(tmax)
+    return rays
+
+
+# --------------------------------------------------------------------------
+# geometry
+# --------------------------------------------------------------------------
+def random_triangles(n: int, seed: int, side: float = 0.05,
+                     box=(0.0, 1.0)) -> np.ndarray:
+    """Equilateral triangles with side ``side``, centres uniform in ``box``^3,
+    random plane and spin."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = rng.uniform(box[0], box[1], size=(n, 3))
+    a = _random_unit(rng, n)
+    g = _random_unit(rng, n)
+    b = np.cross(a, g)
+    bn = np.linalg.norm(b, axis=1, keepdims=True)
+    # a degenerate draw (g parallel to a) is replaced deterministically
+    bad = (bn[:, 0] < 1e-6)
+    if bad.any():
+        alt = np.cross(a[bad], np.array([0.0, 0.0, 1.0]))
+        b[bad] = alt
+        bn[bad] = np.linalg.norm(alt, axis=1, keepdims=True)
+    b = b / bn
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=n)
+    r = side / math.sqrt(3.0)
+    v = np.empty((n, 3, 3), np.float64)
+    for k in range(3):
+        th = phi + 2.0 * math.pi * k / 3.0
+        v[:, k, :] = c + r * (np.cos(th)[:, None] * a + np.sin(th)[:, None] * b)
+    return v.astype(np.float32)
+
+
+def billboard_quads(n_quads: int, seed: int, eye, n_tex: int = 16,
+                    box=(0.0, 100.0), side=(0.5, 2.0)):
+    """Camera-facing textured quads, two triangles each.
+
+    Quad ``q`` becomes triangles ``2q = (c00, c10, c11)`` and
+    ``2q+1 = (c00, c11, c01)`` with texture coordinates
+    ``(0,0),(1,0),(1,1)`` and ``(0,0),(1,1),(0,1)``.
+    Returns ``(vertices, texcoords, geom_ids)``.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    eye = np.asarray(eye, np.float64)
+    c = rng.uniform(box[0], box[1], size=(n_quads, 3))
+    s = rng.uniform(side[0], side[1], size=n_quads)
+    tex_of_quad = rng.integers(0, n_tex, size=n_quads, dtype=np.int64)
+    n = _normalize(eye[None, :] - c)
+    right = _normalize(np.cross(np.array([0.0, 1.0, 0.0])[None, :], n))
+    up = np.cross(n, right)
+    h = (s / 2.0)[:, None]
+    c00 = c - h * right - h * up
+    c10 = c + h * right - h * up
+    c11 = c + h * right + h * up
+    c01 = c - h * right + h * up
+    v = np.empty((2 * n_quads, 3, 3), np.float64)
+    v[0::2, 0], v[0::2, 1], v[0::2, 2] = c00, c10, c11
+    v[1::2, 0], v[1::2, 1], v[1::2, 2] = c00, c11, c01
+    tc = np.empty((2 * n_quads, 3, 2), np.float32)
+    tc[0::2] = np.array([[0, 0], [1, 0], [1, 1]], np.float32)
+    tc[1::2] = np.array([[0, 0], [1, 1], [0, 1]], np.float32)
+    geom = np.repeat(tex_of_quad, 2).astype(np.uint32)
+    return v.astype(np.float32), tc, geom
+
+
+def uv_sphere(center, radius: float, slices: int = 25, stacks: int = 11) -> np.ndarray:
+    """Triangles of a UV-sphere: two polar fans plus quad bands.
+
+    ``2*slices*(stacks-1)`` triangles (500 for the defaults)."""
+    center = np.asarray(center, np.float64)
+    th = math.pi * np.arange(1, stacks) / stacks          # ring polar angles
+    ph = 2.0 * math.pi * np.arange(slices) / slices
+    ring = np.stack([np.sin(th)[:, None] * np.cos(ph)[None, :],
+                     np.cos(th)[:, None] * np.ones_like(ph)[None, :],
+                     np.sin(th)[:, None] * np.sin(ph)[None, :]], axis=-1)
+    ring = center + radius * ring                          # [stacks-1, slices, 3]
+    north = center + radius * np.array([0.0, 1.0, 0.0])
+    south = center - radius * np.array([0.0, 1.0, 0.0])
+    tris = []
+    j = np.arange(slices)
+    jn = (j + 1) % slices
+    tris.append(np.stack([np.broadcast_to(north, (slices, 3)), ring[0, j], ring[0, jn]], 1))
+    for i in range(stacks - 2):
+        a, b = ring[i], ring[i + 1]
+        tris.append(np.stack([a[j], b[j], b[jn]], 1))
+        tris.append(np.stack([a[j], b[jn], a[jn]], 1))
+    tris.append(np.stack([ring[-1, j], np.broadcast_to(south, (slices, 3)), ring[-1, jn]], 1))
+    return np.concatenate(tris, 0)
+
+
+def sphere_scene(n_spheres: int, seed: int, box=(0.0, 100.0),
+                 radius=(0.1, 5.0), slices: int = 25, stacks: int = 11):
+    """Random UV-spheres; radii log-uniform.  Returns (vertices, centres, radii)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = rng.uniform(box[0], box[1], size=(n_spheres, 3))
+    r = np.exp(rng.uniform(math.log(radius[0]), math.log(radius[1]), size=n_spheres))
+    unit = uv_sphere(np.zeros(3), 1.0, slices, stacks)     # [T, 3, 3]
+    v = c[:, None, None, :] + r[:, None, None, None] * unit[None]
+    return v.reshape(-1, 3, 3).astype(np.float32), c, r
+
+
+def sphere_bounce_rays(n: int, centres: np.ndarray, radii: np.ndarray,
+                       eye, seed: int) -> np.ndarray:
+    """Incoherent secondary rays leaving sphere surfaces.
+
+    A sphere is drawn with probability proportional to its cross-section
+    (radius squared), a point on its camera-facing hemisphere is drawn
+    uniformly, the origin is placed 1e-4 radii outside the analytic sphere
+    (the tessellation is inscribed, so the origin is outside the mesh), and
+    the direction is cosine-weighted about the outward normal (Malley's
+    method).  A ray leaving a convex body through its outward hemisphere never
+    re-enters it, so no self-intersection is possible.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    eye = np.asarray(eye, np.float64)
+    p = radii ** 2
+    p = p / p.sum()
+    k = rng.choice(len(radii), size=n, p=p)
+    w = _random_unit(rng, n)
+    view = eye[None, :] - centres[k]
+    flip = np.sum(w * view, axis=1) < 0.0
+    w[flip] = -w[flip]
+    org = centres[k] + (radii[k] * (1.0 + 1e-4))[:, None] * w
+    xi1 = rng.uniform(0.0, 1.0, size=n)
+    xi2 = rng.uniform(0.0, 1.0, size=n)
+    rr = np.sqrt(xi1)
+    ph = 2.0 * math.pi * xi2
+    lx, ly = rr * np.cos(ph), rr * np.sin(ph)
+    lz = np.sqrt(np.maximum(0.0, 1.0 - xi1))
+    t, bt = _onb_from_normal(w)
+    d = _normalize(lx[:, None] * t + ly[:, None] * bt + lz[:, None] * w)
+    rays = np.empty((n, 8), np.float32)
+    rays[:, 0:3] = org.astype(np.float32)
+    rays[:, 3] = 0.0
+    rays[:, 4:7] = d.astype(np.float32)
+    rays[:, 7] = np.inf
+    return rays
+
+
+# --------------------------------------------------------------------------
+# alpha textures
+# --------------------------------------------------------------------------
+def alpha_textures(n_tex: int, size: int, seed: int, target_nonzero: float = 0.60,
+                   tol: float = 0.02) -> np.ndarray:
+    """RGBA8 textures whose alpha holds seeded disks and soft Gaussian blobs.
+
+    Alpha starts at zero; opaque disks (radius U[6,40] px) and blobs (sums of
+    3-6 Gaussians, alpha = round(255*min(1, g))) are added one at a time until
+    the fraction of non-zero alpha texels reaches ``target_nonzero - tol``; a
+    shape that would push it above ``target_nonzero + tol`` is redrawn.
+    RGB is uniform random.  Returns ``uint32 [n_tex, size, size]``.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    yy, xx = np.mgrid[0:size, 0:size].astype(np.float64)
+    out = np.empty((n_tex, size, size), np.uint32)
+    for ti in range(n_tex):
+        alpha = np.zeros((size, size), np.float64)
+        frac = 0.0
+        attempts = 0
+        while frac < target_nonzero - tol and attempts < 10000:
+            attempts += 1
+            cand = alpha.copy()
+            if rng.uniform() < 0.5:
+                cx, cy = rng.uniform(0, size, size=2)
+                rad = rng.uniform(6.0, 40.0)
+                cand[(xx - cx) ** 2 + (yy - cy) ** 2 <= rad * rad] = 1.0
+            else:
+                bx, by = rng.uniform(0, size, size=2)
+                g = np.zeros_like(alpha)
+                for _ in range(int(rng.integers(3, 7))):
+                    gx, gy = bx + rng.uniform(-20, 20), by + rng.uniform(-20, 20)
+                    sg = rng.uniform(4.0, 16.0)
+                    amp = rng.uniform(0.5, 1.5)
+                    g += amp * np.exp(-((xx - gx) ** 2 + (yy - gy) ** 2) / (2.0 * sg * sg))
+                cand = np.maximum(cand, np.minimum(1.0, g))
+            cfrac = float(np.mean(np.round(255.0 * cand) > 0))
+            if cfrac > target_nonzero + tol:
+                continue
+            alpha, frac = cand, cfrac
+        a8 = np.round(255.0 * np.minimum(1.0, alpha)).astype(np.uint32)
+        rgb = rng.integers(0, 256, size=(size, size, 3), dtype=np.uint32)
+        out[ti] = rgb[..., 0] | (rgb[..., 1] << 8) | (rgb[..., 2] << 16) | (a8 << 24)
+    return out
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    vertices: np.ndarray                 # float32 [n, 3, 3]
+    rays: np.ndarray                     # float32 [N, 8]
+    geom_ids: np.ndarray | None = None   # uint32 [n]
+    texcoords: np.ndarray | None = None  # float32 [n, 3, 2]
+    textures: np.ndarray | None = None   # uint32 [n_tex, H, W]
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_tris(self) -> int:
+        return int(self.vertices.shape[0])
+
+    @property
+    def n_rays(self) -> int:
+        return int(self.rays.shape[0])
+
+
+BILLBOARD_EYE = (50.0, 50.0, -60.0)
+BILLBOARD_CENTER = (50.0, 50.0, 50.0)
+
+
+def tiny(width: int = 64, height: int = 64) -> Workload:
+    """1,024 random triangles (side 0.05) in the unit cube; 64x64 primary rays
+    from distance 2, vertical fov 40 degrees."""
+    v = random_triangles(1024, seed_for(CFG_TINY, STREAM_GEOMETRY))
+    rays = pinhole_rays(width, height, (0.5, 0.5, 2.5), (0.5, 0.5, 0.5), 40.0)
+    return Workload("tiny_1k_tris_64x64", v, rays,
+                    geom_ids=np.zeros(v.shape[0], np.uint32))
+
+
+def billboards(n_quads: int = 100_000, width: int = 1920, height: int = 1080,
+               n_tex: int = 16, tex_size: int = 256) -> Workload:
+    """Alpha-masked billboards: camera-facing quads with RGBA8 alpha masks."""
+    v, tc, geom = billboard_quads(n_quads, seed_for(CFG_BILLBOARDS, STREAM_GEOMETRY),
+                                  BILLBOARD_EYE, n_tex=n_tex)
+    tex = alpha_textures(n_tex, tex_size, seed_for(CFG_BILLBOARDS, STREAM_TEXTURES))
+    rays = pinhole_rays(width, height, BILLBOARD_EYE, BILLBOARD_CENTER, 60.0)
+    return Workload(f"billboards_{2 * n_quads}_tris_{width}x{height}", v, rays,
+                    geom_ids=geom, texcoords=tc, textures=tex)
+
+
+def spheres(n_spheres: int = 2000, width: int = 1920, height: int = 1080,
+            bounce_fraction: float = 0.8) -> Workload:
+    """Tessellated random spheres; primary rays plus diffuse bounce rays.
+
+    ``extra['n_primary']`` rays come first, then the bounce rays.  The bounce
+    count is ``bounce_fraction`` of the primary count (about the fraction of
+    primary rays that hit a sphere in this scene)."""
+    v, c, r = sphere_scene(n_spheres, seed_for(CFG_SPHERES, STREAM_GEOMETRY))
+    prim = pinhole_rays(width, height, BILLBOARD_EYE, BILLBOARD_CENTER, 60.0)
+    nb = int(round(bounce_fraction * prim.shape[0]))
+    bounce = sphere_bounce_rays(nb, c, r, BILLBOARD_EYE, seed_for(CFG_SPHERES, STREAM_RAYS))
+    rays = np.concatenate([prim, bounce], 0)
+    return Workload(f"spheres_{v.shape[0]}_tris_{width}x{height}_plus_bounce", v, rays,
+                    geom_ids=np.zeros(v.shape[0], np.uint32),
+                    extra={"n_primary": prim.shape[0], "centres": c, "radii": r})
+
+
+def subsample_indices(n_rays: int, width: int | None, height: int | None,
+                      seed: int, stride: int = 8, n_random: int = 8192) -> np.ndarray:
+    """Stratified ray subsample: every ``stride``-th pixel in x and y at a
+    seeded offset, plus ``n_random`` uniformly drawn rays (sorted, unique)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    idx = []
+    if width is not None and height is not None:
+        ox, oy = rng.integers(0, stride, size=2)
+        ys = np.arange(oy, height, stride)
+        xs = np.arange(ox, width, stride)
+        idx.append((ys[:, None] * width + xs[None, :]).ravel())
+    idx.append(rng.integers(0, n_rays, size=min(n_random, n_rays)))
+    return np.unique(np.concatenate(idx)).astype(np.int64)
