@@ -82,25 +82,51 @@ static double frac_dist(double x) { return fabs(x - floor(x + 0.5)); }
 
 /* Alpha-mask decision (Section 4, Listing 5) in float64: interpolate the
  * three texture coordinates with weights (1-u-v, u, v), take the nearest texel
- * (clamp to edge) of texture geom_id and compare its alpha byte.
- * *margin receives the distance (in texels) of the lookup to a texel edge. */
-static int alpha_accept64(const orc_isect *is, uint32_t prim, uint32_t geom,
-                          double u, double v, double *margin)
+ * (clamp to edge) of texture geom_id and compare its alpha byte. */
+static int alpha_texel_ok(const orc_isect *is, uint32_t geom, double xs, double ys)
 {
-    const float *tc = is->texcoords + (size_t)prim * 6;
-    double w0 = 1.0 - u - v;
-    double s = w0 * tc[0] + u * tc[2] + v * tc[4];
-    double t = w0 * tc[1] + u * tc[3] + v * tc[5];
-    double xs = s * is->width, ys = t * is->height;
     double xf = floor(xs), yf = floor(ys);
     if (xf < 0) xf = 0;
     if (xf > is->width - 1.0) xf = is->width - 1.0;
     if (yf < 0) yf = 0;
     if (yf > is->height - 1.0) yf = is->height - 1.0;
     uint32_t texel = is->textures[((size_t)geom * is->height + (size_t)yf) * is->width + (size_t)xf];
-    double mx = frac_dist(xs), my = frac_dist(ys);
-    *margin = mx < my ? mx : my;
     return (texel >> 24) >= is->alpha_min;
+}
+
+static void alpha_lookup64(const orc_isect *is, uint32_t prim, double u, double v,
+                           double *xs, double *ys)
+{
+    const float *tc = is->texcoords + (size_t)prim * 6;
+    double w0 = 1.0 - u - v;
+    double s = w0 * tc[0] + u * tc[2] + v * tc[4];
+    double t = w0 * tc[1] + u * tc[3] + v * tc[5];
+    *xs = s * is->width;
+    *ys = t * is->height;
+}
+
+static int alpha_accept64(const orc_isect *is, uint32_t prim, uint32_t geom, double u, double v)
+{
+    double xs, ys;
+    alpha_lookup64(is, prim, u, v, &xs, &ys);
+    return alpha_texel_ok(is, geom, xs, ys);
+}
+
+/* 1 iff a lookup displaced by at most `reach` texels on each axis could land
+ * on a texel whose accept decision differs from the undisplaced one. */
+static int alpha_decision_fragile(const orc_isect *is, uint32_t prim, uint32_t geom,
+                                  double u, double v, double reach)
+{
+    double xs, ys;
+    alpha_lookup64(is, prim, u, v, &xs, &ys);
+    int ok = alpha_texel_ok(is, geom, xs, ys);
+    if (!(reach < (double)is->width && reach < (double)is->height)) return 1;
+    double x0 = floor(xs - reach), x1 = floor(xs + reach);
+    double y0 = floor(ys - reach), y1 = floor(ys + reach);
+    for (double y = y0; y <= y1; y += 1.0)
+        for (double x = x0; x <= x1; x += 1.0)
+            if (alpha_texel_ok(is, geom, x + 0.5, y + 0.5) != ok) return 1;
+    return 0;
 }
 
 /* Procedural checker in float64; *margin is the distance of n*u or n*v to an
@@ -192,7 +218,7 @@ static void brute_one(brute_job *job, uint32_t slot)
         int acc = 1;
         double fm;
         if (job->kind == ORC_ALPHA)
-            acc = alpha_accept64(&job->is, k, job->geom ? job->geom[k] : 0, u, v, &fm);
+            acc = alpha_accept64(&job->is, k, job->geom ? job->geom[k] : 0, u, v);
         else if (job->kind == ORC_PROCEDURAL)
             acc = checker_accept64(&job->is, u, v, &fm);
         if (!acc) continue;
@@ -219,9 +245,13 @@ static void brute_one(brute_job *job, uint32_t slot)
         if (m > -delta && job->kind != ORC_DEFAULT) {
             double fm = 1.0;
             if (job->kind == ORC_ALPHA) {
-                alpha_accept64(&job->is, k, job->geom ? job->geom[k] : 0, u, v, &fm);
-                /* a lookup coordinate s*W moves by up to ~2*W*delta */
-                if (fm < 4.0 * delta * (job->is.width > job->is.height ? job->is.width : job->is.height))
+                /* s = w0 tc0 + u tc1 + v tc2 with texture coordinates in
+                 * [0, 1] moves by at most 2 delta (+ float32 rounding), i.e.
+                 * 2 delta W texels; the decision is fragile only if a texel
+                 * within that reach decides differently. */
+                double wh = job->is.width > job->is.height ? job->is.width : job->is.height;
+                double reach = (2.0 * delta + 0x1p-20) * wh;
+                if (alpha_decision_fragile(&job->is, k, job->geom ? job->geom[k] : 0, u, v, reach))
                     fl |= ORC_E_NEAR_FILTER;
             } else {
                 checker_accept64(&job->is, u, v, &fm);
