@@ -1,0 +1,204 @@
+/*
+ * rtx.h -- C ABI of librtx: BVH ray traversal with compile-time custom
+ * intersectors on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Section 3.1 of Zellmann, "Adding Custom Intersectors
+ * to the C++ Ray Tracing Template Library Visionaray" (2019):
+ *   - closest_hit(ray, prims, intersector): the nearest hit point that the
+ *     intersector accepts;
+ *   - any_hit(ray, prims, intersector): the first accepted hit encountered;
+ *   - an intersector is a compile-time type that intercepts the ray/box and
+ *     ray/primitive tests of the traversal (Section 3.2, Algorithm 1) and may
+ *     clear a hit (Listing 3); the use cases of Section 4 are built in:
+ *     alpha mask (Listing 5), procedural alpha mask, and the BVH-cost counter
+ *     (Listing 6).
+ * A C ABI cannot take a template, so every built-in intersector x query x
+ * counting combination is a separate kernel instantiation compiled into the
+ * library, and the host selects one per launch.  C++/HIP code can instead
+ * include rt_traverse.hpp and instantiate the traversal with its own functor.
+ *
+ * Conventions
+ *   - Every pointer marked "device" is device memory owned by the caller;
+ *     every pointer marked "host" is host memory owned by the caller.  The
+ *     library never allocates device memory and never frees anything.
+ *   - Device arrays of rays, hits, counters, nodes and triangle records must
+ *     be 16-byte aligned.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Trace
+ *     calls only enqueue work; device faults surface at the caller's next
+ *     synchronisation.
+ *   - Every entry point returns an rt_status; on failure nothing is enqueued
+ *     and rt_last_error() describes the reason (thread-local).
+ *   - Ray components must be finite and tmin <= tmax (tmax may be +inf);
+ *     other rays give unspecified (but memory-safe) results.
+ */
+#ifndef RTX_H
+#define RTX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rt_status {
+    RT_OK = 0,
+    RT_ERR_INVALID_ARG = -1,  /* null pointer, bad size, inconsistent scene */
+    RT_ERR_MISALIGNED = -2,   /* a device array is not 16-byte aligned */
+    RT_ERR_UNSUPPORTED = -3,  /* unknown intersector kind or flag */
+    RT_ERR_WORKSPACE = -4,    /* workspace missing or smaller than required */
+    RT_ERR_HIP = -5,          /* a HIP runtime call failed */
+    RT_ERR_OUT_OF_MEMORY = -6 /* host scratch allocation in the builder failed */
+} rt_status;
+
+/* A ray o + t d, valid for tmin < t < tmax (both ends excluded). 32 bytes. */
+typedef struct rt_ray {
+    float ox, oy, oz, tmin;
+    float dx, dy, dz, tmax;
+} rt_ray;
+
+/* Closest-hit record (the paper's hit_record: distance t, prim_id, and the
+ * barycentrics u, v with P = (1-u-v) v0 + u v1 + v v2).  prim_id is the index
+ * of the triangle in the caller's input array.  A miss has
+ * prim_id = RT_MISS, t = +inf, u = v = 0.  16 bytes. */
+typedef struct rt_hit {
+    float t;
+    uint32_t prim_id;
+    float u, v;
+} rt_hit;
+
+#define RT_MISS 0xFFFFFFFFu
+
+/* Per-ray counts of the heat-map intersector (Section 4, Listing 6):
+ * num_boxes  -- ray/box tests executed (root box + 2 per inner node entered),
+ * num_tris   -- ray/triangle tests executed, misses included,
+ * num_candidates -- geometric hits inside the current interval that were
+ *               handed to the intersector's accept decision,
+ * num_accepted   -- candidates the intersector accepted.  16 bytes. */
+typedef struct rt_counters {
+    uint32_t num_boxes, num_tris, num_candidates, num_accepted;
+} rt_counters;
+
+typedef enum rt_isect_kind {
+    RT_ISECT_DEFAULT = 0,    /* accept every hit; compiled to no code at all */
+    RT_ISECT_ALPHA = 1,      /* alpha mask: params = const rt_alpha_params*    */
+    RT_ISECT_PROCEDURAL = 2  /* checker mask: params = const rt_procedural_params* */
+} rt_isect_kind;
+
+/* Flags.  RT_FLAG_COUNT composes the counting intersector with the chosen
+ * kind and requires a counters array. */
+#define RT_FLAG_COUNT 0x1u
+
+/* Alpha-mask intersector (Listing 5).  For a candidate (prim, u, v):
+ *   (s, t) = (1-u-v) tc[prim][0] + u tc[prim][1] + v tc[prim][2],
+ *   texel  = nearest texel (clamp to edge) of texture geom_id(prim),
+ *   accept iff (texel >> 24) >= alpha_min.
+ * A float threshold tau on alpha/255 is alpha_min = ceil(255 tau). */
+typedef struct rt_alpha_params {
+    const float *texcoords;     /* device, [n_texcoord_prims][3][2] by input triangle index */
+    const uint32_t *textures;   /* device, [n_tex][height][width] RGBA8, R in the low byte */
+    uint32_t n_texcoord_prims;  /* must be >= the scene's n_tris */
+    uint32_t n_tex;             /* must be > the scene's max_geom_id */
+    uint32_t width, height;     /* texel dimensions, each >= 1 */
+    uint32_t alpha_min;         /* 0..255 */
+} rt_alpha_params;
+
+/* Procedural intersector: accept iff floor(n u) + floor(n v) is even. */
+typedef struct rt_procedural_params {
+    uint32_t checker_n;         /* >= 1 */
+} rt_procedural_params;
+
+/* Description of a built BVH (filled by rt_bvh_build). */
+typedef struct rt_bvh_info {
+    uint32_t n_tris;
+    uint32_t n_nodes;        /* inner nodes written (0 when the root is a leaf) */
+    uint32_t max_depth;      /* deepest node; the traversal stack never exceeds it */
+    uint32_t max_geom_id;
+    uint32_t root_ref;       /* packed reference of the root item */
+    float root_lo[3], root_hi[3];
+} rt_bvh_info;
+
+/* A built BVH resident in device memory: a non-owning view. */
+typedef struct rt_scene {
+    const void *nodes;       /* device, n_nodes records of RT_NODE_BYTES */
+    const void *tris;        /* device, n_tris records of RT_TRI_BYTES */
+    rt_bvh_info info;
+} rt_scene;
+
+#define RT_NODE_BYTES 64u
+#define RT_TRI_BYTES 48u
+#define RT_MAX_TRIS 0x1FFFFFFFu  /* 2^29 - 1 */
+
+/* Upper bounds of the host buffers rt_bvh_build writes for n_tris triangles
+ * (BVH construction is not described in the paper -- Section 3.1 only says
+ * the BVH is built over the primitives -- so the builder is this library's:
+ * binned surface-area heuristic, see rt_bvh_build). */
+rt_status rt_bvh_buffer_bytes(uint32_t n_tris, size_t *node_bytes, size_t *tri_bytes);
+
+/* Builds the BVH on the host.
+ *   vertices  host, [n_tris][3][3] float (triangle, corner, xyz)
+ *   geom_ids  host, [n_tris] uint32 or NULL (all 0); used by the alpha mask
+ *   nodes     host output, capacity node_cap bytes (rt_bvh_buffer_bytes)
+ *   tris      host output, capacity tri_cap bytes
+ *   info      host output
+ * Construction: leaves hold at most 4 triangles; a larger node is split at the
+ * cheapest of 32 equal-width centroid bins per axis (surface-area cost,
+ * ties -> lower axis, then lower plane, stable partition), or at the index
+ * median if no axis has centroid extent or the node is 40 levels deep.
+ * Deterministic: the same input gives byte-identical output.  n_tris may be 0
+ * (an empty scene: every ray misses and counts nothing). */
+rt_status rt_bvh_build(const float *vertices, const uint32_t *geom_ids, uint32_t n_tris,
+                       void *nodes, size_t node_cap, void *tris, size_t tri_cap,
+                       rt_bvh_info *info);
+
+/* Device workspace a trace call needs (bytes, possibly 0): overflow space
+ * for traversal stacks deeper than the on-chip stack. */
+rt_status rt_trace_workspace_bytes(const rt_scene *scene, uint32_t n_rays, uint32_t flags,
+                                   size_t *bytes);
+
+/* Closest-hit query (Section 3.1, Listing 4) over the whole scene.
+ *   rays      device, [n_rays] rt_ray
+ *   kind/params  intersector (params: host pointer to the matching struct,
+ *             NULL for RT_ISECT_DEFAULT); the struct is copied at the call
+ *   hits      device output, [n_rays] rt_hit
+ *   counters  device output, [n_rays] rt_counters; required iff RT_FLAG_COUNT
+ *   workspace device, at least rt_trace_workspace_bytes bytes (may be NULL
+ *             when that is 0)
+ * n_rays == 0 returns RT_OK without a launch. */
+rt_status rt_trace_closest(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                           rt_isect_kind kind, const void *params, uint32_t flags,
+                           rt_hit *hits, rt_counters *counters,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* Any-hit query (Section 3.1): occluder[i] = input index of the first hit
+ * the intersector accepted in traversal order, or RT_MISS.  Arguments as for
+ * rt_trace_closest. */
+rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                       rt_isect_kind kind, const void *params, uint32_t flags,
+                       uint32_t *occluder, rt_counters *counters,
+                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* Launch shapes compiled into the library: threads per block and traversal
+ * stack entries per lane kept in LDS (deeper entries use the workspace).
+ * Writes up to cap pairs (either array may be NULL) and returns the number of
+ * shapes.  The first shape is the default. */
+uint32_t rt_launch_shapes(uint32_t *blocks, uint32_t *lds_stacks, uint32_t cap);
+
+/* Selects the launch shape of later trace calls in this process (a tuning
+ * hook; not synchronised with trace calls running on other threads).
+ * Results never depend on the shape; speed and the workspace size do, so
+ * query rt_trace_workspace_bytes again after changing it.
+ * RT_ERR_UNSUPPORTED if the pair is not compiled in. */
+rt_status rt_set_launch_shape(uint32_t block, uint32_t lds_stack);
+
+/* Static description of a status code. */
+const char *rt_status_string(rt_status status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *rt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTX_H */

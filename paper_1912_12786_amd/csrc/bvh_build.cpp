@@ -1,0 +1,285 @@
+// Host BVH builder of librtx.
+//
+// The paper traverses a BVH "built over some primitives" (Section 3.1) but
+// does not describe the construction, so this library fixes one:
+//   * triangle box = exact float min/max of its three vertices; centroid =
+//     0.5 * (lo + hi) evaluated in double;
+//   * a node with <= 4 triangles becomes a leaf;
+//   * otherwise each axis with a non-zero centroid extent is cut into 32
+//     equal-width bins, bin = min(31, int((c - cmin) * (32 / extent))); every
+//     plane between two bins is costed as area(L) |L| + area(R) |R| (box
+//     surface area in double) and the strictly cheapest plane wins, ties going
+//     to the lower axis and then the lower plane; the node's triangles are
+//     partitioned stably (left keeps its relative order, then right);
+//   * with no centroid extent on any axis, or at depth >= 40, the range is
+//     split at index count/2 of its current order;
+//   * inner nodes are numbered in depth-first preorder, left child first, and
+//     the triangle records are written in the final (leaf) order.
+//
+// Output layout (both little-endian, 16-byte aligned records):
+//   inner node, 64 B:  {lo0.x lo0.y lo0.z hi0.x} {hi0.y hi0.z lo1.x lo1.y}
+//                      {lo1.z hi1.x hi1.y hi1.z} {ref0 ref1 0 0}
+//     child c's box is (loc, hic); refc = (count << 29) | index with count = 0
+//     for an inner node (index = its node number) and 1..4 for a leaf (index =
+//     its first triangle record).
+//   triangle record, 48 B: {v0.xyz, prim_id} {e1.xyz, geom_id} {e2.xyz, 0}
+//     with e1 = v1 - v0 and e2 = v2 - v0 rounded to float.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "rt_internal.hpp"
+
+namespace rtx {
+namespace {
+
+constexpr int kBins = 32;
+constexpr uint32_t kMaxLeaf = 4;
+constexpr uint32_t kMedianDepth = 40;
+
+struct Box {
+    float lo[3], hi[3];
+    void clear()
+    {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::numeric_limits<float>::infinity();
+            hi[a] = -std::numeric_limits<float>::infinity();
+        }
+    }
+    void grow(const Box &b)
+    {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = b.lo[a] < lo[a] ? b.lo[a] : lo[a];
+            hi[a] = b.hi[a] > hi[a] ? b.hi[a] : hi[a];
+        }
+    }
+    double area() const
+    {
+        const double dx = double(hi[0]) - double(lo[0]);
+        const double dy = double(hi[1]) - double(lo[1]);
+        const double dz = double(hi[2]) - double(lo[2]);
+        return 2.0 * (dx * dy + dy * dz + dz * dx);
+    }
+};
+
+struct Builder {
+    const float *verts;
+    std::vector<Box> tbox;
+    std::vector<double> cen;   // [n][3]
+    std::vector<uint32_t> order, scratch;
+    NodeRecord *nodes;
+    uint32_t n_inner = 0;
+    uint32_t max_depth = 0;
+
+    struct Split {
+        int axis = -1;
+        int plane = 0;
+        double cmin = 0.0, scale = 0.0;
+    };
+
+    static int bin_index(double c, double cmin, double scale)
+    {
+        int b = int((c - cmin) * scale);
+        return b < 0 ? 0 : (b > kBins - 1 ? kBins - 1 : b);
+    }
+
+    Box range_box(uint32_t first, uint32_t count) const
+    {
+        Box b;
+        b.clear();
+        for (uint32_t i = first; i < first + count; ++i) b.grow(tbox[order[i]]);
+        return b;
+    }
+
+    Split find_split(uint32_t first, uint32_t count, uint32_t depth) const
+    {
+        Split best;
+        if (depth >= kMedianDepth) return best;
+        double cmin[3], cmax[3];
+        for (int a = 0; a < 3; ++a) {
+            cmin[a] = std::numeric_limits<double>::infinity();
+            cmax[a] = -std::numeric_limits<double>::infinity();
+        }
+        for (uint32_t i = first; i < first + count; ++i) {
+            const double *c = &cen[3 * size_t(order[i])];
+            for (int a = 0; a < 3; ++a) {
+                cmin[a] = c[a] < cmin[a] ? c[a] : cmin[a];
+                cmax[a] = c[a] > cmax[a] ? c[a] : cmax[a];
+            }
+        }
+        double best_cost = std::numeric_limits<double>::infinity();
+        for (int a = 0; a < 3; ++a) {
+            const double ext = cmax[a] - cmin[a];
+            if (!(ext > 0.0)) continue;
+            const double scale = double(kBins) / ext;
+            Box bins[kBins];
+            uint32_t cnt[kBins] = {};
+            for (auto &b : bins) b.clear();
+            for (uint32_t i = first; i < first + count; ++i) {
+                const uint32_t k = order[i];
+                const int b = bin_index(cen[3 * size_t(k) + a], cmin[a], scale);
+                ++cnt[b];
+                bins[b].grow(tbox[k]);
+            }
+            // suffix sweep: right side of every plane
+            Box right[kBins];
+            uint32_t nright[kBins];
+            Box acc;
+            acc.clear();
+            uint32_t n = 0;
+            for (int b = kBins - 1; b >= 1; --b) {
+                if (cnt[b]) acc.grow(bins[b]);
+                n += cnt[b];
+                right[b] = acc;
+                nright[b] = n;
+            }
+            // prefix sweep: left side, cost, strict minimum
+            acc.clear();
+            n = 0;
+            for (int s = 1; s < kBins; ++s) {
+                if (cnt[s - 1]) acc.grow(bins[s - 1]);
+                n += cnt[s - 1];
+                if (n == 0 || nright[s] == 0) continue;
+                const double cost = acc.area() * double(n) + right[s].area() * double(nright[s]);
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best.axis = a;
+                    best.plane = s;
+                    best.cmin = cmin[a];
+                    best.scale = scale;
+                }
+            }
+        }
+        return best;
+    }
+
+    uint32_t partition(uint32_t first, uint32_t count, const Split &sp)
+    {
+        if (sp.axis < 0) return count / 2;
+        uint32_t w = first, nr = 0;
+        for (uint32_t i = first; i < first + count; ++i) {
+            const uint32_t k = order[i];
+            if (bin_index(cen[3 * size_t(k) + sp.axis], sp.cmin, sp.scale) < sp.plane)
+                order[w++] = k;
+            else
+                scratch[nr++] = k;
+        }
+        std::memcpy(&order[w], scratch.data(), nr * sizeof(uint32_t));
+        return w - first;
+    }
+
+    static uint32_t leaf_ref(uint32_t first, uint32_t count) { return (count << 29) | first; }
+
+    static void put_box(NodeRecord &nd, int child, const Box &b)
+    {
+        float *f = nd.f;
+        const int o = child * 6;  // lo0 at 0..2, hi0 at 3..5, lo1 at 6..8, hi1 at 9..11
+        f[o + 0] = b.lo[0];
+        f[o + 1] = b.lo[1];
+        f[o + 2] = b.lo[2];
+        f[o + 3] = b.hi[0];
+        f[o + 4] = b.hi[1];
+        f[o + 5] = b.hi[2];
+    }
+
+    // Builds the subtree over order[first, first+count) at `depth`; returns
+    // its packed reference.  `box` is the range's bounding box.
+    uint32_t build(uint32_t first, uint32_t count, uint32_t depth)
+    {
+        if (depth > max_depth) max_depth = depth;
+        if (count <= kMaxLeaf) return leaf_ref(first, count);
+        const uint32_t id = n_inner++;
+        const Split sp = find_split(first, count, depth);
+        const uint32_t nl = partition(first, count, sp);
+        const Box lb = range_box(first, nl);
+        const Box rb = range_box(first + nl, count - nl);
+        const uint32_t lref = build(first, nl, depth + 1);
+        const uint32_t rref = build(first + nl, count - nl, depth + 1);
+        NodeRecord &nd = nodes[id];
+        std::memset(&nd, 0, sizeof nd);
+        put_box(nd, 0, lb);
+        put_box(nd, 1, rb);
+        nd.u[12] = lref;
+        nd.u[13] = rref;
+        return id;
+    }
+};
+
+}  // namespace
+
+uint32_t max_inner_nodes(uint32_t n_tris) { return n_tris > kMaxLeaf ? n_tris - 1 : 0; }
+
+rt_status build_bvh(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
+                    NodeRecord *nodes, TriRecord *tris, rt_bvh_info *info)
+{
+    std::memset(info, 0, sizeof *info);
+    info->n_tris = n_tris;
+    if (n_tris == 0) {
+        for (int a = 0; a < 3; ++a) {
+            info->root_lo[a] = std::numeric_limits<float>::infinity();
+            info->root_hi[a] = -std::numeric_limits<float>::infinity();
+        }
+        return RT_OK;
+    }
+    try {
+        Builder b;
+        b.verts = verts;
+        b.tbox.resize(n_tris);
+        b.cen.resize(3 * size_t(n_tris));
+        b.order.resize(n_tris);
+        b.scratch.resize(n_tris);
+        b.nodes = nodes;
+        for (uint32_t k = 0; k < n_tris; ++k) {
+            const float *t = verts + 9 * size_t(k);
+            Box &bx = b.tbox[k];
+            for (int a = 0; a < 3; ++a) {
+                float lo = t[a], hi = t[a];
+                lo = t[3 + a] < lo ? t[3 + a] : lo;
+                lo = t[6 + a] < lo ? t[6 + a] : lo;
+                hi = t[3 + a] > hi ? t[3 + a] : hi;
+                hi = t[6 + a] > hi ? t[6 + a] : hi;
+                bx.lo[a] = lo;
+                bx.hi[a] = hi;
+                b.cen[3 * size_t(k) + a] = 0.5 * (double(lo) + double(hi));
+            }
+            b.order[k] = k;
+        }
+        const Box root = b.range_box(0, n_tris);
+        info->root_ref = b.build(0, n_tris, 0);
+        info->n_nodes = b.n_inner;
+        info->max_depth = b.max_depth;
+        for (int a = 0; a < 3; ++a) {
+            info->root_lo[a] = root.lo[a];
+            info->root_hi[a] = root.hi[a];
+        }
+        uint32_t gmax = 0;
+        for (uint32_t i = 0; i < n_tris; ++i) {
+            const uint32_t k = b.order[i];
+            const float *t = verts + 9 * size_t(k);
+            TriRecord &r = tris[i];
+            r.f[0] = t[0];
+            r.f[1] = t[1];
+            r.f[2] = t[2];
+            r.u[3] = k;
+            r.f[4] = t[3] - t[0];
+            r.f[5] = t[4] - t[1];
+            r.f[6] = t[5] - t[2];
+            const uint32_t g = geom_ids ? geom_ids[k] : 0u;
+            r.u[7] = g;
+            r.f[8] = t[6] - t[0];
+            r.f[9] = t[7] - t[1];
+            r.f[10] = t[8] - t[2];
+            r.u[11] = 0;
+            gmax = g > gmax ? g : gmax;
+        }
+        info->max_geom_id = gmax;
+    } catch (const std::bad_alloc &) {
+        return RT_ERR_OUT_OF_MEMORY;
+    }
+    return RT_OK;
+}
+
+}  // namespace rtx

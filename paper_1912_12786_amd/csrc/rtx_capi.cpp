@@ -1,0 +1,234 @@
+// C ABI of librtx: argument validation, workspace sizing and the single
+// host-side selection of the kernel instantiation per call.
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "rt_internal.hpp"
+
+using namespace rtx;
+
+namespace {
+
+thread_local std::string g_last_error;
+std::atomic<uint32_t> g_shape_index{0};
+
+rt_status fail(rt_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+rt_status check_scene(const rt_scene *sc)
+{
+    if (!sc) return fail(RT_ERR_INVALID_ARG, "scene is NULL");
+    const rt_bvh_info &in = sc->info;
+    if (in.n_tris > RT_MAX_TRIS) return fail(RT_ERR_INVALID_ARG, "scene has more than 2^29-1 triangles");
+    if (in.n_tris == 0) return RT_OK;
+    if (!sc->tris) return fail(RT_ERR_INVALID_ARG, "scene triangle records are NULL");
+    if (!aligned(sc->tris, 16)) return fail(RT_ERR_MISALIGNED, "scene triangle records not 16-byte aligned");
+    if (in.max_depth >= 128) return fail(RT_ERR_INVALID_ARG, "scene max_depth must be < 128");
+    const uint32_t cnt = in.root_ref >> 29, idx = in.root_ref & 0x1FFFFFFFu;
+    if (cnt == 0) {
+        if (in.n_nodes == 0 || idx >= in.n_nodes)
+            return fail(RT_ERR_INVALID_ARG, "scene root references a missing inner node");
+        if (!sc->nodes) return fail(RT_ERR_INVALID_ARG, "scene nodes are NULL");
+        if (!aligned(sc->nodes, 16)) return fail(RT_ERR_MISALIGNED, "scene nodes not 16-byte aligned");
+        if (in.n_nodes >= in.n_tris) return fail(RT_ERR_INVALID_ARG, "scene has more inner nodes than triangles");
+    } else {
+        if (cnt > 4 || uint64_t(idx) + cnt > in.n_tris)
+            return fail(RT_ERR_INVALID_ARG, "scene root leaf out of range");
+    }
+    return RT_OK;
+}
+
+rt_status check_params(const rt_scene *sc, rt_isect_kind kind, const void *params, TraceRequest &q)
+{
+    q.kind = kind;
+    std::memset(&q.alpha, 0, sizeof q.alpha);
+    q.checker.checker_n = 0;
+    switch (kind) {
+    case RT_ISECT_DEFAULT:
+        return RT_OK;
+    case RT_ISECT_ALPHA: {
+        if (!params) return fail(RT_ERR_INVALID_ARG, "alpha intersector needs rt_alpha_params");
+        const rt_alpha_params &p = *static_cast<const rt_alpha_params *>(params);
+        if (!p.texcoords || !p.textures) return fail(RT_ERR_INVALID_ARG, "alpha texcoords/textures are NULL");
+        if (!aligned(p.texcoords, 8)) return fail(RT_ERR_MISALIGNED, "alpha texcoords not 8-byte aligned");
+        if (!aligned(p.textures, 4)) return fail(RT_ERR_MISALIGNED, "alpha textures not 4-byte aligned");
+        if (p.n_texcoord_prims < sc->info.n_tris)
+            return fail(RT_ERR_INVALID_ARG, "alpha texcoords cover fewer triangles than the scene");
+        if (sc->info.n_tris > 0 && p.n_tex <= sc->info.max_geom_id)
+            return fail(RT_ERR_INVALID_ARG, "alpha n_tex must exceed the scene's max geom_id");
+        if (p.width < 1 || p.height < 1 || p.width > (1u << 24) || p.height > (1u << 24))
+            return fail(RT_ERR_INVALID_ARG, "alpha texture size must be within 1..2^24");
+        if (p.alpha_min > 255) return fail(RT_ERR_INVALID_ARG, "alpha_min must be 0..255");
+        q.alpha = p;
+        return RT_OK;
+    }
+    case RT_ISECT_PROCEDURAL: {
+        if (!params) return fail(RT_ERR_INVALID_ARG, "procedural intersector needs rt_procedural_params");
+        const rt_procedural_params &p = *static_cast<const rt_procedural_params *>(params);
+        if (p.checker_n < 1 || p.checker_n > 65536)
+            return fail(RT_ERR_INVALID_ARG, "checker_n must be within 1..65536");
+        q.checker = p;
+        return RT_OK;
+    }
+    }
+    return fail(RT_ERR_UNSUPPORTED, "unknown intersector kind");
+}
+
+size_t workspace_for(const rt_bvh_info &info, uint32_t n_rays, const LaunchShape &s)
+{
+    const uint64_t stride = (uint64_t(n_rays) + s.block - 1) / s.block * s.block;
+    return size_t(spill_entries(info, s)) * stride * sizeof(uint64_t);
+}
+
+rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                       rt_isect_kind kind, const void *params, uint32_t flags, void *out,
+                       size_t out_align, rt_counters *counters, void *workspace,
+                       size_t workspace_bytes, void *stream)
+{
+    g_last_error.clear();
+    rt_status st = check_scene(scene);
+    if (st != RT_OK) return st;
+    if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    TraceRequest q;
+    st = check_params(scene, kind, params, q);
+    if (st != RT_OK) return st;
+    if (n_rays == 0) return RT_OK;
+    if (!rays) return fail(RT_ERR_INVALID_ARG, "rays are NULL");
+    if (!aligned(rays, 16)) return fail(RT_ERR_MISALIGNED, "rays not 16-byte aligned");
+    if (!out) return fail(RT_ERR_INVALID_ARG, "output array is NULL");
+    if (!aligned(out, out_align)) return fail(RT_ERR_MISALIGNED, "output array misaligned");
+    const bool count = (flags & RT_FLAG_COUNT) != 0;
+    if (count && !counters) return fail(RT_ERR_INVALID_ARG, "RT_FLAG_COUNT needs a counters array");
+    if (count && !aligned(counters, 16)) return fail(RT_ERR_MISALIGNED, "counters not 16-byte aligned");
+    const LaunchShape shape = kShapes[g_shape_index.load(std::memory_order_relaxed)];
+    const size_t need = workspace_for(scene->info, n_rays, shape);
+    if (need > 0) {
+        if (!workspace || workspace_bytes < need)
+            return fail(RT_ERR_WORKSPACE, "workspace smaller than rt_trace_workspace_bytes");
+        if (!aligned(workspace, 16)) return fail(RT_ERR_MISALIGNED, "workspace not 16-byte aligned");
+    }
+    q.scene = scene;
+    q.rays = rays;
+    q.n_rays = n_rays;
+    q.count = count;
+    q.query = query;
+    q.out = out;
+    q.counters = count ? counters : nullptr;
+    q.spill = workspace;
+    q.shape = shape;
+    q.stream = stream;
+    const char *err = "";
+    st = launch_trace(q, &err);
+    if (st != RT_OK) return fail(st, err);
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt_status rt_bvh_buffer_bytes(uint32_t n_tris, size_t *node_bytes, size_t *tri_bytes)
+{
+    g_last_error.clear();
+    if (!node_bytes || !tri_bytes) return fail(RT_ERR_INVALID_ARG, "output pointers are NULL");
+    if (n_tris > RT_MAX_TRIS) return fail(RT_ERR_INVALID_ARG, "more than 2^29-1 triangles");
+    *node_bytes = size_t(max_inner_nodes(n_tris)) * RT_NODE_BYTES;
+    *tri_bytes = size_t(n_tris) * RT_TRI_BYTES;
+    return RT_OK;
+}
+
+rt_status rt_bvh_build(const float *vertices, const uint32_t *geom_ids, uint32_t n_tris,
+                       void *nodes, size_t node_cap, void *tris, size_t tri_cap, rt_bvh_info *info)
+{
+    g_last_error.clear();
+    if (!info) return fail(RT_ERR_INVALID_ARG, "info is NULL");
+    if (n_tris > RT_MAX_TRIS) return fail(RT_ERR_INVALID_ARG, "more than 2^29-1 triangles");
+    if (n_tris > 0 && !vertices) return fail(RT_ERR_INVALID_ARG, "vertices are NULL");
+    const size_t need_nodes = size_t(max_inner_nodes(n_tris)) * RT_NODE_BYTES;
+    const size_t need_tris = size_t(n_tris) * RT_TRI_BYTES;
+    if (need_nodes > 0 && (!nodes || node_cap < need_nodes))
+        return fail(RT_ERR_INVALID_ARG, "node buffer smaller than rt_bvh_buffer_bytes");
+    if (need_tris > 0 && (!tris || tri_cap < need_tris))
+        return fail(RT_ERR_INVALID_ARG, "triangle buffer smaller than rt_bvh_buffer_bytes");
+    if ((nodes && !aligned(nodes, 16)) || (tris && !aligned(tris, 16)))
+        return fail(RT_ERR_MISALIGNED, "host output buffers must be 16-byte aligned");
+    rt_status st = build_bvh(vertices, geom_ids, n_tris, static_cast<NodeRecord *>(nodes),
+                             static_cast<TriRecord *>(tris), info);
+    if (st != RT_OK) return fail(st, "host allocation failed during BVH build");
+    return RT_OK;
+}
+
+rt_status rt_trace_workspace_bytes(const rt_scene *scene, uint32_t n_rays, uint32_t flags,
+                                   size_t *bytes)
+{
+    g_last_error.clear();
+    if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
+    rt_status st = check_scene(scene);
+    if (st != RT_OK) return st;
+    if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    *bytes = workspace_for(scene->info, n_rays, kShapes[g_shape_index.load()]);
+    return RT_OK;
+}
+
+rt_status rt_trace_closest(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                           rt_isect_kind kind, const void *params, uint32_t flags, rt_hit *hits,
+                           rt_counters *counters, void *workspace, size_t workspace_bytes,
+                           void *stream)
+{
+    return trace_common(Query::Closest, scene, rays, n_rays, kind, params, flags, hits, 16,
+                        counters, workspace, workspace_bytes, stream);
+}
+
+rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                       rt_isect_kind kind, const void *params, uint32_t flags, uint32_t *occluder,
+                       rt_counters *counters, void *workspace, size_t workspace_bytes, void *stream)
+{
+    return trace_common(Query::Any, scene, rays, n_rays, kind, params, flags, occluder, 4,
+                        counters, workspace, workspace_bytes, stream);
+}
+
+rt_status rt_set_launch_shape(uint32_t block, uint32_t lds_stack)
+{
+    g_last_error.clear();
+    for (uint32_t i = 0; i < kNumShapes; ++i) {
+        if (kShapes[i].block == block && kShapes[i].lds_stack == lds_stack) {
+            g_shape_index.store(i);
+            return RT_OK;
+        }
+    }
+    return fail(RT_ERR_UNSUPPORTED, "launch shape not compiled into the library");
+}
+
+uint32_t rt_launch_shapes(uint32_t *blocks, uint32_t *lds_stacks, uint32_t cap)
+{
+    for (uint32_t i = 0; i < kNumShapes && i < cap; ++i) {
+        if (blocks) blocks[i] = kShapes[i].block;
+        if (lds_stacks) lds_stacks[i] = kShapes[i].lds_stack;
+    }
+    return kNumShapes;
+}
+
+const char *rt_status_string(rt_status s)
+{
+    switch (s) {
+    case RT_OK: return "RT_OK";
+    case RT_ERR_INVALID_ARG: return "RT_ERR_INVALID_ARG";
+    case RT_ERR_MISALIGNED: return "RT_ERR_MISALIGNED";
+    case RT_ERR_UNSUPPORTED: return "RT_ERR_UNSUPPORTED";
+    case RT_ERR_WORKSPACE: return "RT_ERR_WORKSPACE";
+    case RT_ERR_HIP: return "RT_ERR_HIP";
+    case RT_ERR_OUT_OF_MEMORY: return "RT_ERR_OUT_OF_MEMORY";
+    }
+    return "unknown rt_status";
+}
+
+const char *rt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

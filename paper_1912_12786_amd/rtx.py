@@ -1,0 +1,303 @@
+"""Python binding of librtx (ctypes).
+
+Functions named ``rt_*`` mirror the C ABI in ``include/rtx.h`` one to one and
+only marshal arguments; every step of the traversal runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  The helpers below
+them (:class:`Scene`, :func:`trace`) allocate outputs with torch and call the
+same entry points.
+
+There is no fallback: if ``librtx.so`` is missing or fails to load, every
+entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtx.so")
+
+RT_OK = 0
+RT_MISS = 0xFFFFFFFF
+RT_FLAG_COUNT = 1
+RT_NODE_BYTES = 64
+RT_TRI_BYTES = 48
+KINDS = {"default": 0, "alpha": 1, "procedural": 2}
+
+
+class RtxError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {_status_name(status)}: {detail}")
+        self.status = status
+
+
+class rt_alpha_params(C.Structure):
+    _fields_ = [("texcoords", C.c_void_p), ("textures", C.c_void_p),
+                ("n_texcoord_prims", C.c_uint32), ("n_tex", C.c_uint32),
+                ("width", C.c_uint32), ("height", C.c_uint32), ("alpha_min", C.c_uint32)]
+
+
+class rt_procedural_params(C.Structure):
+    _fields_ = [("checker_n", C.c_uint32)]
+
+
+class rt_bvh_info(C.Structure):
+    _fields_ = [("n_tris", C.c_uint32), ("n_nodes", C.c_uint32), ("max_depth", C.c_uint32),
+                ("max_geom_id", C.c_uint32), ("root_ref", C.c_uint32),
+                ("root_lo", C.c_float * 3), ("root_hi", C.c_float * 3)]
+
+
+class rt_scene(C.Structure):
+    _fields_ = [("nodes", C.c_void_p), ("tris", C.c_void_p), ("info", rt_bvh_info)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every entry point declared in include/rtx.h
+_P, _U32, _SZ = C.c_void_p, C.c_uint32, C.c_size_t
+SIGNATURES = [
+    ("rt_bvh_buffer_bytes", C.c_int, [_U32, C.POINTER(_SZ), C.POINTER(_SZ)]),
+    ("rt_bvh_build", C.c_int, [_P, _P, _U32, _P, _SZ, _P, _SZ, C.POINTER(rt_bvh_info)]),
+    ("rt_trace_workspace_bytes", C.c_int, [C.POINTER(rt_scene), _U32, _U32, C.POINTER(_SZ)]),
+    ("rt_trace_closest", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
+                                   _SZ, _P]),
+    ("rt_trace_any", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
+                               _SZ, _P]),
+    ("rt_launch_shapes", C.c_uint32, [_P, _P, _U32]),
+    ("rt_set_launch_shape", C.c_int, [_U32, _U32]),
+    ("rt_status_string", C.c_char_p, [C.c_int]),
+    ("rt_last_error", C.c_char_p, []),
+]
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads librtx.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"librtx.so not found at {path}; build it with "
+                              f"`python -m paper_1912_12786_amd.build`")
+        lib = C.CDLL(path)
+        for name, res, args in SIGNATURES:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return load_library().rt_status_string(s).decode()
+    except Exception:  # pragma: no cover - only used while formatting errors
+        return str(s)
+
+
+def _check(status: int, where: str):
+    if status != RT_OK:
+        detail = load_library().rt_last_error().decode()
+        raise RtxError(status, where, detail)
+
+
+# ----------------------------------------------------------------------------
+# one-to-one wrappers of the C ABI
+# ----------------------------------------------------------------------------
+def rt_bvh_buffer_bytes(n_tris: int):
+    lib = load_library()
+    nb, tb = C.c_size_t(), C.c_size_t()
+    _check(lib.rt_bvh_buffer_bytes(n_tris, C.byref(nb), C.byref(tb)), "rt_bvh_buffer_bytes")
+    return nb.value, tb.value
+
+
+def rt_bvh_build(vertices: np.ndarray, geom_ids: np.ndarray | None = None):
+    """Host BVH build.  Returns ``(nodes, tris, info)``: uint8 arrays holding
+    ``info.n_nodes`` 64-byte node records and ``n_tris`` 48-byte triangle
+    records, and the filled ``rt_bvh_info``."""
+    lib = load_library()
+    v = np.ascontiguousarray(vertices, np.float32).reshape(-1, 9)
+    n = v.shape[0]
+    g = None if geom_ids is None else np.ascontiguousarray(geom_ids, np.uint32)
+    if g is not None and g.shape[0] != n:
+        raise ValueError("geom_ids must have one entry per triangle")
+    nb, tb = rt_bvh_buffer_bytes(n)
+    # 16-byte aligned host buffers (records are viewed as float4)
+    nodes = np.zeros(max(nb, 16) // 16, dtype=np.dtype((np.void, 16)))
+    tris = np.zeros(max(tb, 16) // 16, dtype=np.dtype((np.void, 16)))
+    info = rt_bvh_info()
+    _check(lib.rt_bvh_build(v.ctypes.data if n else None, None if g is None else g.ctypes.data, n,
+                            nodes.ctypes.data if nb else None, nb,
+                            tris.ctypes.data if tb else None, tb, C.byref(info)),
+           "rt_bvh_build")
+    nodes_u8 = nodes.view(np.uint8)[: info.n_nodes * RT_NODE_BYTES]
+    tris_u8 = tris.view(np.uint8)[: n * RT_TRI_BYTES]
+    return nodes_u8, tris_u8, info
+
+
+def rt_trace_workspace_bytes(scene: rt_scene, n_rays: int, flags: int = 0) -> int:
+    lib = load_library()
+    b = C.c_size_t()
+    _check(lib.rt_trace_workspace_bytes(C.byref(scene), n_rays, flags, C.byref(b)),
+           "rt_trace_workspace_bytes")
+    return b.value
+
+
+def rt_trace_closest(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params,
+                     flags: int, hits_ptr: int, counters_ptr: int | None, workspace_ptr: int | None,
+                     workspace_bytes: int, stream: int | None):
+    lib = load_library()
+    _check(lib.rt_trace_closest(C.byref(scene), rays_ptr, n_rays, kind,
+                                None if params is None else C.cast(C.pointer(params), C.c_void_p),
+                                flags, hits_ptr, counters_ptr, workspace_ptr, workspace_bytes,
+                                stream), "rt_trace_closest")
+
+
+def rt_trace_any(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params, flags: int,
+                 occluder_ptr: int, counters_ptr: int | None, workspace_ptr: int | None,
+                 workspace_bytes: int, stream: int | None):
+    lib = load_library()
+    _check(lib.rt_trace_any(C.byref(scene), rays_ptr, n_rays, kind,
+                            None if params is None else C.cast(C.pointer(params), C.c_void_p),
+                            flags, occluder_ptr, counters_ptr, workspace_ptr, workspace_bytes,
+                            stream), "rt_trace_any")
+
+
+def rt_launch_shapes():
+    lib = load_library()
+    n = lib.rt_launch_shapes(None, None, 0)
+    b = (C.c_uint32 * n)()
+    l = (C.c_uint32 * n)()
+    lib.rt_launch_shapes(b, l, n)
+    return [(int(b[i]), int(l[i])) for i in range(n)]
+
+
+def rt_set_launch_shape(block: int, lds_stack: int):
+    _check(load_library().rt_set_launch_shape(block, lds_stack), "rt_set_launch_shape")
+
+
+def rt_status_string(status: int) -> str:
+    return load_library().rt_status_string(status).decode()
+
+
+def rt_last_error() -> str:
+    return load_library().rt_last_error().decode()
+
+
+# ----------------------------------------------------------------------------
+# torch-side helpers
+# ----------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class Scene:
+    """A BVH resident in device memory plus the optional alpha-mask data."""
+    nodes: object            # torch uint8 tensor on the device (or None)
+    tris: object             # torch uint8 tensor on the device
+    info: rt_bvh_info
+    texcoords: object = None  # torch float32 [n, 3, 2]
+    textures: object = None   # torch int32 [n_tex, H, W] (RGBA8 bits)
+
+    @property
+    def view(self) -> rt_scene:
+        sc = rt_scene()
+        sc.nodes = self.nodes.data_ptr() if self.nodes is not None and self.nodes.numel() else None
+        sc.tris = self.tris.data_ptr() if self.tris.numel() else None
+        sc.info = self.info
+        return sc
+
+    def alpha_params(self, alpha_min: int = 128) -> rt_alpha_params:
+        if self.texcoords is None or self.textures is None:
+            raise ValueError("scene has no alpha-mask data")
+        p = rt_alpha_params()
+        p.texcoords = self.texcoords.data_ptr()
+        p.textures = self.textures.data_ptr()
+        p.n_texcoord_prims = int(self.texcoords.shape[0])
+        p.n_tex, p.height, p.width = (int(s) for s in self.textures.shape)
+        p.alpha_min = int(alpha_min)
+        return p
+
+
+def upload_scene(vertices, geom_ids=None, texcoords=None, textures=None, device="cuda") -> Scene:
+    """Builds the BVH on the host (rt_bvh_build) and copies it to ``device``."""
+    torch = _torch()
+    nodes, tris, info = rt_bvh_build(vertices, geom_ids)
+    dn = torch.from_numpy(nodes.copy()).to(device) if nodes.size else None
+    dt = torch.from_numpy(tris.copy()).to(device)
+    tc = None if texcoords is None else torch.from_numpy(
+        np.ascontiguousarray(texcoords, np.float32)).to(device)
+    tx = None if textures is None else torch.from_numpy(
+        np.ascontiguousarray(textures, np.uint32).view(np.int32)).to(device)
+    return Scene(dn, dt, info, tc, tx)
+
+
+def _params(scene: Scene, intersector: str, alpha_min: int, checker_n: int):
+    if intersector not in KINDS:
+        raise ValueError(f"unknown intersector {intersector!r}")
+    if intersector == "alpha":
+        return scene.alpha_params(alpha_min)
+    if intersector == "procedural":
+        p = rt_procedural_params()
+        p.checker_n = int(checker_n)
+        return p
+    return None
+
+
+class Workspace:
+    """Caller-owned device workspace reused across trace calls."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int):
+        torch = _torch()
+        if nbytes == 0:
+            return None, 0
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.buf.data_ptr(), int(self.buf.numel())
+
+
+def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "closest",
+          count: bool = False, alpha_min: int = 128, checker_n: int = 8, out=None,
+          counters=None, workspace: Workspace | None = None, stream=None):
+    """Traces device rays ``float32 [N, 8]``.
+
+    closest: returns ``hits float32 [N, 4]`` = (t, prim_id bits, u, v); view
+    column 1 as int32/uint32 for prim_id.  any: returns ``int32 [N]``
+    occluders (-1 = none).  With ``count`` also returns ``int32 [N, 4]``
+    counters (box tests, triangle tests, candidates, accepted)."""
+    torch = _torch()
+    if rays.dtype != torch.float32 or rays.dim() != 2 or rays.shape[1] != 8 or not rays.is_contiguous():
+        raise ValueError("rays must be a contiguous float32 [N, 8] tensor")
+    n = int(rays.shape[0])
+    dev = rays.device
+    params = _params(scene, intersector, alpha_min, checker_n)
+    flags = RT_FLAG_COUNT if count else 0
+    sc = scene.view
+    if query == "closest":
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    elif query == "any":
+        if out is None:
+            out = torch.empty((n,), dtype=torch.int32, device=dev)
+    else:
+        raise ValueError("query must be 'closest' or 'any'")
+    if count and counters is None:
+        counters = torch.empty((n, 4), dtype=torch.int32, device=dev)
+    ws = workspace or Workspace(dev)
+    wptr, wbytes = ws.get(rt_trace_workspace_bytes(sc, n, flags))
+    s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    cptr = counters.data_ptr() if count else None
+    if query == "closest":
+        rt_trace_closest(sc, rays.data_ptr(), n, KINDS[intersector], params, flags,
+                         out.data_ptr(), cptr, wptr, wbytes, s)
+    else:
+        rt_trace_any(sc, rays.data_ptr(), n, KINDS[intersector], params, flags,
+                     out.data_ptr(), cptr, wptr, wbytes, s)
+    return (out, counters) if count else out

@@ -1,0 +1,306 @@
+"""CPU tests of librtx: symbols, host BVH builder, argument validation.
+
+No test here launches a kernel: the validation cases fail before any HIP
+call, and n_rays == 0 returns without a launch.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1912_12786_amd import rtx
+from paper_1912_12786_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rtx.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return rtx.load_library()
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ("rt_bvh_build", "rt_trace_closest", "rt_trace_any", "rt_trace_workspace_bytes",
+                 "rt_status_string", "rt_last_error"):
+        assert name in fns
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    # and the binding wraps every one of them
+    wrapped = {s[0] for s in rtx.SIGNATURES}
+    assert set(header_functions()) == wrapped
+
+
+def test_status_strings(lib):
+    for code, name in ((0, "RT_OK"), (-1, "RT_ERR_INVALID_ARG"), (-2, "RT_ERR_MISALIGNED"),
+                       (-3, "RT_ERR_UNSUPPORTED"), (-4, "RT_ERR_WORKSPACE"), (-5, "RT_ERR_HIP"),
+                       (-6, "RT_ERR_OUT_OF_MEMORY")):
+        assert rtx.rt_status_string(code) == name
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """Compiles a probe against include/rtx.h and compares every struct's size
+    and field offsets with the ctypes mirrors of the binding."""
+    import subprocess
+    probe = tmp_path / "probe.c"
+    probe.write_text(r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "rtx.h"
+#define S(t) printf(#t " %zu\n", sizeof(t));
+#define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
+int main(void) {
+  S(rt_ray) S(rt_hit) S(rt_counters) S(rt_alpha_params) S(rt_procedural_params)
+  S(rt_bvh_info) S(rt_scene)
+  O(rt_alpha_params, textures) O(rt_alpha_params, n_texcoord_prims) O(rt_alpha_params, alpha_min)
+  O(rt_bvh_info, root_ref) O(rt_bvh_info, root_lo) O(rt_bvh_info, root_hi)
+  O(rt_scene, tris) O(rt_scene, info)
+  O(rt_hit, prim_id) O(rt_ray, dx)
+  return 0;
+}
+""")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(probe), "-o",
+                    str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    got = {k: int(v) for k, v in got.items()}
+    assert got["rt_ray"] == 32 and got["rt_hit"] == 16 and got["rt_counters"] == 16
+    assert got["rt_hit.prim_id"] == 4 and got["rt_ray.dx"] == 16
+    for name, cls in (("rt_alpha_params", rtx.rt_alpha_params),
+                      ("rt_procedural_params", rtx.rt_procedural_params),
+                      ("rt_bvh_info", rtx.rt_bvh_info), ("rt_scene", rtx.rt_scene)):
+        assert got[name] == C.sizeof(cls), name
+        for field, *_ in cls._fields_:
+            key = f"{name}.{field}"
+            if key in got:
+                assert got[key] == getattr(cls, field).offset, key
+
+
+# ----------------------------------------------------------------------------
+# builder parity with the oracle's independent builder
+# ----------------------------------------------------------------------------
+def decode_product_bvh(nodes_u8, tris_u8, info):
+    """Preorder list of (lo, hi, count, first, depth) over all nodes."""
+    nf = nodes_u8.view(np.float32).reshape(-1, 16)
+    nu = nodes_u8.view(np.uint32).reshape(-1, 16)
+    out = []
+
+    def rec(ref, lo, hi, depth):
+        cnt, idx = ref >> 29, ref & 0x1FFFFFFF
+        out.append((tuple(lo), tuple(hi), cnt, idx if cnt else 0, depth))
+        if cnt == 0:
+            f = nf[idx]
+            rec(int(nu[idx, 12]), f[0:3], f[3:6], depth + 1)
+            rec(int(nu[idx, 13]), f[6:9], f[9:12], depth + 1)
+
+    rec(int(info.root_ref), np.array(info.root_lo[:], np.float32),
+        np.array(info.root_hi[:], np.float32), 0)
+    return out
+
+
+def decode_oracle_bvh(bvh):
+    out = []
+    for nd in bvh.nodes:
+        cnt = int(nd["count"])
+        out.append((tuple(nd["lo"]), tuple(nd["hi"]), cnt, int(nd["first"]) if cnt else 0,
+                    int(nd["depth"])))
+    return out
+
+
+def assert_same_bvh(oracle_lib, verts, geom=None):
+    nodes, tris, info = rtx.rt_bvh_build(verts, geom)
+    ob = oracle_lib.build_bvh(verts)
+    prod = decode_product_bvh(nodes, tris, info)
+    orc = decode_oracle_bvh(ob)
+    assert len(prod) == len(orc)
+    for a, b in zip(prod, orc):
+        assert np.array_equal(np.array(a[0], np.float32).view(np.uint32),
+                              np.array(b[0], np.float32).view(np.uint32))
+        assert np.array_equal(np.array(a[1], np.float32).view(np.uint32),
+                              np.array(b[1], np.float32).view(np.uint32))
+        assert a[2:] == b[2:]
+    tu = tris.view(np.uint32).reshape(-1, 12)
+    tf = tris.view(np.float32).reshape(-1, 12)
+    n = verts.shape[0]
+    assert np.array_equal(tu[:, 3], ob.perm)
+    v = verts[ob.perm]
+    assert np.array_equal(tf[:, 0:3], v[:, 0])
+    assert np.array_equal(tf[:, 4:7], v[:, 1] - v[:, 0])
+    assert np.array_equal(tf[:, 8:11], v[:, 2] - v[:, 0])
+    assert np.all(tu[:, 11] == 0)
+    if geom is not None:
+        assert np.array_equal(tu[:, 7], geom[ob.perm])
+        assert info.max_geom_id == (int(geom.max()) if n else 0)
+    assert info.max_depth == ob.max_depth
+    assert info.n_nodes == sum(1 for p in prod if p[2] == 0)
+    return info
+
+
+def test_builder_matches_oracle_small(oracle_lib):
+    rng = np.random.default_rng(4)
+    for n in (1, 3, 4, 5, 8, 17, 100, 1000):
+        v = rng.uniform(0, 1, size=(n, 3, 3)).astype(np.float32)
+        g = rng.integers(0, 7, size=n).astype(np.uint32)
+        assert_same_bvh(oracle_lib, v, g)
+
+
+def test_builder_matches_oracle_degenerate(oracle_lib):
+    v = np.tile(np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]], np.float32), (37, 1, 1))
+    assert_same_bvh(oracle_lib, v)
+    # collinear centroids along one axis only, with duplicates
+    x = np.repeat(np.arange(20, dtype=np.float32), 3)
+    v = np.zeros((60, 3, 3), np.float32)
+    v[:, :, 0] = x[:, None] + np.array([0, 0.5, 0.25], np.float32)
+    v[:, 1, 1] = 1.0
+    assert_same_bvh(oracle_lib, v)
+
+
+def test_builder_matches_oracle_tiny_workload(oracle_lib):
+    assert_same_bvh(oracle_lib, W.tiny().vertices)
+
+
+def test_builder_matches_oracle_billboards(oracle_lib):
+    wl = W.billboards()
+    info = assert_same_bvh(oracle_lib, wl.vertices, wl.geom_ids)
+    assert info.max_geom_id == 15
+
+
+@pytest.mark.slow
+def test_builder_matches_oracle_spheres(oracle_lib):
+    wl = W.spheres()
+    assert_same_bvh(oracle_lib, wl.vertices)
+
+
+def test_builder_empty_scene():
+    nodes, tris, info = rtx.rt_bvh_build(np.zeros((0, 3, 3), np.float32))
+    assert info.n_tris == 0 and info.n_nodes == 0 and nodes.size == 0 and tris.size == 0
+
+
+def test_builder_deterministic():
+    v = W.tiny().vertices
+    a = rtx.rt_bvh_build(v)
+    b = rtx.rt_bvh_build(v)
+    assert a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
+
+
+def test_buffer_bytes():
+    assert rtx.rt_bvh_buffer_bytes(0) == (0, 0)
+    assert rtx.rt_bvh_buffer_bytes(4) == (0, 4 * 48)
+    assert rtx.rt_bvh_buffer_bytes(5) == (4 * 64, 5 * 48)
+    with pytest.raises(rtx.RtxError):
+        rtx.rt_bvh_buffer_bytes(1 << 29)
+
+
+def test_build_rejects_small_buffers(lib):
+    v = np.zeros((10, 3, 3), np.float32)
+    info = rtx.rt_bvh_info()
+    buf = np.zeros(64, np.float32)
+    st = lib.rt_bvh_build(v.ctypes.data, None, 10, buf.ctypes.data, 64, buf.ctypes.data, 64,
+                          C.byref(info))
+    assert st == -1 and "buffer" in rtx.rt_last_error()
+
+
+# ----------------------------------------------------------------------------
+# validation paths (all fail before any HIP call)
+# ----------------------------------------------------------------------------
+def _fake_scene(n_tris=10, n_nodes=3, root_ref=0, max_depth=3, max_geom=0):
+    sc = rtx.rt_scene()
+    sc.nodes = 0x10000
+    sc.tris = 0x20000
+    sc.info.n_tris = n_tris
+    sc.info.n_nodes = n_nodes
+    sc.info.root_ref = root_ref
+    sc.info.max_depth = max_depth
+    sc.info.max_geom_id = max_geom
+    return sc
+
+
+def _closest(lib, sc, rays=0x30000, n=100, kind=0, params=None, flags=0, hits=0x40000,
+             counters=None, ws=None, wsb=0):
+    p = None if params is None else C.cast(C.pointer(params), C.c_void_p)
+    return lib.rt_trace_closest(C.byref(sc) if sc is not None else None, rays, n, kind, p, flags,
+                                hits, counters, ws, wsb, None)
+
+
+def test_validation_errors(lib):
+    sc = _fake_scene()
+    assert _closest(lib, None) == -1
+    assert _closest(lib, sc, rays=None) == -1
+    assert _closest(lib, sc, rays=0x30004) == -2
+    assert _closest(lib, sc, hits=None) == -1
+    assert _closest(lib, sc, hits=0x40008) == -2
+    assert _closest(lib, sc, kind=7) == -3
+    assert _closest(lib, sc, flags=2) == -3
+    assert _closest(lib, sc, flags=rtx.RT_FLAG_COUNT) == -1          # counters missing
+    assert _closest(lib, sc, flags=rtx.RT_FLAG_COUNT, counters=0x50004) == -2
+    assert _closest(lib, sc, kind=1) == -1                           # alpha params missing
+    assert _closest(lib, sc, kind=2) == -1                           # checker params missing
+    bad = rtx.rt_procedural_params(0)
+    assert _closest(lib, sc, kind=2, params=bad) == -1
+    ap = rtx.rt_alpha_params(0x60000, 0x70000, 10, 1, 4, 4, 128)
+    sc_g = _fake_scene(max_geom=3)
+    assert _closest(lib, sc_g, kind=1, params=ap) == -1              # n_tex <= max geom id
+    ap2 = rtx.rt_alpha_params(0x60000, 0x70000, 9, 4, 4, 4, 128)
+    assert _closest(lib, sc_g, kind=1, params=ap2) == -1             # texcoords too short
+    ap3 = rtx.rt_alpha_params(0x60004, 0x70000, 10, 4, 4, 4, 128)
+    assert _closest(lib, sc_g, kind=1, params=ap3) == -2             # texcoords misaligned
+    ap4 = rtx.rt_alpha_params(0x60000, 0x70000, 10, 4, 4, 4, 256)
+    assert _closest(lib, sc_g, kind=1, params=ap4) == -1             # alpha_min range
+    # inconsistent scenes
+    assert _closest(lib, _fake_scene(n_nodes=0)) == -1               # inner root without nodes
+    assert _closest(lib, _fake_scene(root_ref=(5 << 29))) == -1      # leaf of 5
+    assert _closest(lib, _fake_scene(root_ref=(4 << 29) | 8)) == -1  # leaf past the end
+    assert _closest(lib, _fake_scene(max_depth=200)) == -1
+    sc_mis = _fake_scene()
+    sc_mis.tris = 0x20008
+    assert _closest(lib, sc_mis) == -2
+    # deep scene needs workspace
+    deep = _fake_scene(max_depth=60)
+    assert _closest(lib, deep) == -4
+    assert "workspace" in rtx.rt_last_error()
+
+
+def test_zero_rays_is_a_no_op(lib):
+    sc = _fake_scene()
+    assert _closest(lib, sc, rays=None, n=0, hits=None) == 0
+    assert lib.rt_trace_any(C.byref(sc), None, 0, 0, None, 0, None, None, None, 0, None) == 0
+
+
+def test_workspace_bytes(lib):
+    shapes = rtx.rt_launch_shapes()
+    assert len(shapes) >= 1
+    sc = _fake_scene(max_depth=20)
+    for block, lds in shapes:
+        rtx.rt_set_launch_shape(block, lds)
+        b = rtx.rt_trace_workspace_bytes(sc, 1000)
+        padded = (1000 + block - 1) // block * block
+        assert b == max(0, 20 - lds) * padded * 8
+    rtx.rt_set_launch_shape(*shapes[0])
+    with pytest.raises(rtx.RtxError):
+        rtx.rt_set_launch_shape(3, 3)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    import importlib
+    with pytest.raises(ImportError):
+        # a fresh load from a path with no library must raise, not fall back
+        saved = rtx._lib
+        try:
+            rtx._lib = None
+            rtx.load_library(str(tmp_path / "librtx.so"))
+        finally:
+            rtx._lib = saved
+    importlib.invalidate_caches()
