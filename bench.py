@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark: closest-hit BVH traversal with the alpha-mask intersector at 1080p.
+
+Workload: 100k camera-facing alpha-masked billboards (200k triangles, 16 RGBA8
+256x256 textures, ~40 % zero-alpha texels), 1920x1080 primary rays, alpha
+threshold 0.5 (alpha byte >= 128).  One step = one rt_trace_closest launch
+over all 2,073,600 rays (ray setup, traversal, triangle tests, alpha lookups,
+hit output), inputs and BVH resident in device memory.
+
+Prints ONE JSON line: Mrays/s, the algorithmic-bandwidth roofline of the
+traversal kernel (bytes the method must read and write per ray, from exact
+per-ray counts of a separate counting launch), and the CPU oracle timed on
+this host's cores on the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --copy-calibration   # plain copy kernel for counter scaling
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_trace_alpha_billboards.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1912_12786_amd", "csrc", f)
+                  for f in ("rt_traverse.hpp", "trace_kernels.hip")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_ray(counters: np.ndarray, kind: str) -> np.ndarray:
+    """Algorithmic bytes of one ray: its 32-byte ray record and 16-byte hit
+    record, one 64-byte node record per inner node entered (box tests are the
+    root's plus two per inner node), one 48-byte triangle record per triangle
+    test, and per alpha decision the 24 bytes of texture coordinates plus the
+    4-byte texel."""
+    c = counters.astype(np.int64)
+    b = 32 + 16 + 64 * ((c[:, 0] - 1).clip(min=0) // 2) + 48 * c[:, 1]
+    if kind == "alpha":
+        b = b + 28 * c[:, 2]
+    return b
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28   # 1 GiB of float32
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4,
+                      "launches": 3}), flush=True)
+
+
+def cpu_baseline(wl, kind_kw, threads):
+    """The oracle as it stands, on this host: oracle B (float32 BVH traversal)
+    over every ray, and oracle A (float64 brute force) on a ray sample."""
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    bvh = oracle.build_bvh(wl.vertices)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.traverse(wl.vertices, bvh, wl.rays, "alpha", count=False, threads=threads, **kind_kw)
+    t_b = time.perf_counter() - t0
+    from paper_1912_12786_amd import workloads as W
+    idx = W.subsample_indices(wl.n_rays, None, None, seed=7, n_random=1024)
+    t0 = time.perf_counter()
+    oracle.brute(wl.vertices, wl.rays, "alpha", ray_index=idx, threads=threads, **kind_kw)
+    t_a = time.perf_counter() - t0
+    return {
+        "value": wl.n_rays / t_b / 1e6,
+        "unit": "Mrays/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle B (float32 BVH traversal, own BVH built in {t_build:.2f} s) over all "
+                   f"{wl.n_rays} rays: {t_b:.2f} s; oracle A (float64 brute force over all "
+                   f"{wl.n_tris} triangles) on {len(idx)} sampled rays: {t_a:.2f} s = "
+                   f"{len(idx) / t_a / 1e6:.6f} Mrays/s"),
+        "bruteforce_mrays_s": len(idx) / t_a / 1e6,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the traversal shards by rays with no exchange "
+              "step, so multi-GPU runs are not part of this benchmark", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    from paper_1912_12786_amd import rtx
+    from paper_1912_12786_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(dev)
+    log(f"device {props.name} CUs={props.multi_processor_count} "
+        f"gcn={getattr(props, 'gcnArchName', '?')}")
+    t0 = time.perf_counter()
+    wl = W.billboards()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    scene = rtx.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures, device=dev)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    log(f"workload {wl.name}: gen {t_gen:.2f} s, host BVH build + upload {t_build:.2f} s, "
+        f"{scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}")
+    rays = torch.from_numpy(wl.rays).to(dev)
+    hits = torch.empty((wl.n_rays, 4), dtype=torch.float32, device=dev)
+    ws = rtx.Workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        rtx.trace(scene, rays, "alpha", alpha_min=128, out=hits, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K launches on the current stream, HIP events around each
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        step()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_launch_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    ms_per_step = wall * 1e3 / args.steps
+    mrays = wl.n_rays * args.steps / wall / 1e6
+
+    # exact per-ray counts from a separate (untimed) counting launch
+    _, cnt = rtx.trace(scene, rays, "alpha", alpha_min=128, count=True, workspace=ws)
+    torch.cuda.synchronize()
+    counters = cnt.cpu().numpy().view(np.uint32)
+    alg_bytes = int(bytes_per_ray(counters, "alpha").sum())
+    kernel_ms = float(per_launch_ms.mean())
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tf = json.load(f)
+        if tf.get("kernel_source_sha") == kernel_source_sha():
+            traffic = tf.get("traffic_bytes_per_launch")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = len(os.sched_getaffinity(0))
+        kind_kw = dict(geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures,
+                       alpha_min=128)
+        cpu = cpu_baseline(wl, kind_kw, threads)
+
+    mean_c = counters.mean(axis=0)
+    result = {
+        "metric": "Mrays/s closest-hit w/ alpha-mask intersector at 1080p; HBM GB/s % of peak",
+        "value": round(mrays, 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name,
+            "n_tris": wl.n_tris,
+            "n_rays": wl.n_rays,
+            "intersector": "alpha",
+            "alpha_threshold": "0.5 (alpha byte >= 128)",
+            "query": "closest",
+            "textures": "16 x 256x256 RGBA8",
+            "bvh": f"binary SAH, {scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}",
+            "launch_shape": list(rtx.rt_launch_shapes()[0]),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "kernel": "trace_kernel<alpha_intersector, closest>",
+            "kernel_ms_mean": round(kernel_ms, 4),
+            "kernel_ms_p10_p90": [round(float(np.percentile(per_launch_ms, 10)), 4),
+                                  round(float(np.percentile(per_launch_ms, 90)), 4)],
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "bytes_per_ray_mean": round(alg_bytes / wl.n_rays, 1),
+            "mean_counts_per_ray": {"box_tests": round(float(mean_c[0]), 2),
+                                    "tri_tests": round(float(mean_c[1]), 2),
+                                    "alpha_lookups": round(float(mean_c[2]), 2)},
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -118,7 +118,9 @@ typedef struct rt_bvh_info {
     float root_lo[3], root_hi[3];
 } rt_bvh_info;
 
-/* A built BVH resident in device memory: a non-owning view. */
+/* A built BVH resident in device memory: a non-owning view.  nodes and tris
+ * must be copies of what rt_bvh_build wrote (the kernels follow the child
+ * references without bounds checks; only the root is validated). */
 typedef struct rt_scene {
     const void *nodes;       /* device, n_nodes records of RT_NODE_BYTES */
     const void *tris;        /* device, n_tris records of RT_TRI_BYTES */
@@ -128,6 +130,7 @@ typedef struct rt_scene {
 #define RT_NODE_BYTES 64u
 #define RT_TRI_BYTES 48u
 #define RT_MAX_TRIS 0x1FFFFFFFu  /* 2^29 - 1 */
+#define RT_MAX_RAYS 0x80000000u  /* rays per trace call */
 
 /* Upper bounds of the host buffers rt_bvh_build writes for n_tris triangles
  * (BVH construction is not described in the paper -- Section 3.1 only says
@@ -164,7 +167,8 @@ rt_status rt_trace_workspace_bytes(const rt_scene *scene, uint32_t n_rays, uint3
  *   counters  device output, [n_rays] rt_counters; required iff RT_FLAG_COUNT
  *   workspace device, at least rt_trace_workspace_bytes bytes (may be NULL
  *             when that is 0)
- * n_rays == 0 returns RT_OK without a launch. */
+ * n_rays == 0 returns RT_OK without a launch; n_rays > RT_MAX_RAYS is
+ * RT_ERR_INVALID_ARG. */
 rt_status rt_trace_closest(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
                            rt_isect_kind kind, const void *params, uint32_t flags,
                            rt_hit *hits, rt_counters *counters,

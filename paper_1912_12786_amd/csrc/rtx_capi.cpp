@@ -100,6 +100,7 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     st = check_params(scene, kind, params, q);
     if (st != RT_OK) return st;
     if (n_rays == 0) return RT_OK;
+    if (n_rays > RT_MAX_RAYS) return fail(RT_ERR_INVALID_ARG, "more than 2^31 rays in one call");
     if (!rays) return fail(RT_ERR_INVALID_ARG, "rays are NULL");
     if (!aligned(rays, 16)) return fail(RT_ERR_MISALIGNED, "rays not 16-byte aligned");
     if (!out) return fail(RT_ERR_INVALID_ARG, "output array is NULL");
@@ -173,6 +174,7 @@ rt_status rt_trace_workspace_bytes(const rt_scene *scene, uint32_t n_rays, uint3
     rt_status st = check_scene(scene);
     if (st != RT_OK) return st;
     if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    if (n_rays > RT_MAX_RAYS) return fail(RT_ERR_INVALID_ARG, "more than 2^31 rays in one call");
     *bytes = workspace_for(scene->info, n_rays, kShapes[g_shape_index.load()]);
     return RT_OK;
 }

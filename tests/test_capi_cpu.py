@@ -239,6 +239,7 @@ def test_validation_errors(lib):
     sc = _fake_scene()
     assert _closest(lib, None) == -1
     assert _closest(lib, sc, rays=None) == -1
+    assert _closest(lib, sc, n=(1 << 31) + 1) == -1
     assert _closest(lib, sc, rays=0x30004) == -2
     assert _closest(lib, sc, hits=None) == -1
     assert _closest(lib, sc, hits=0x40008) == -2
