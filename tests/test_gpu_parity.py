@@ -32,6 +32,12 @@ def rtx_mod(torch_cuda):
     return rtx
 
 
+def same_bits(a, b):
+    """Bitwise equality (hit records carry prim_id bits, NaN as floats)."""
+    import torch
+    return a.shape == b.shape and torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
 def announce(msg):
     print(f"[gpu-case] {msg}", flush=True)
 
@@ -163,13 +169,13 @@ def test_tiny_parity(torch_cuda, rtx_mod, oracle_lib, tiny_setup, kind, query, n
     if query == "closest":
         g = P.hits_to_numpy(out)
         P.assert_exact_vs_b(g, B, f"tiny {kind}")
-        assert torch.equal(plain, out)
+        assert same_bits(plain, out)
         A = oracle_lib.brute(wl.vertices, rays, kind, **okw)
         P.compare_vs_a(g, A, np.arange(rays.shape[0]), f"tiny {kind}")
     else:
         occ = P.occluders_to_numpy(out)
         assert np.array_equal(occ, B["prim"])
-        assert torch.equal(plain, out)
+        assert same_bits(plain, out)
         A = oracle_lib.brute(wl.vertices, rays, kind, any_hit=True, **okw)
         P.compare_vs_a({"prim": occ}, A, np.arange(rays.shape[0]), f"tiny {kind} any", any_hit=True)
 
@@ -187,7 +193,7 @@ def test_tiny_all_launch_shapes_identical(torch_cuda, rtx_mod, tiny_setup):
             if ref is None:
                 ref = (hits, cnt)
             else:
-                assert torch.equal(hits, ref[0]) and torch.equal(cnt, ref[1])
+                assert same_bits(hits, ref[0]) and same_bits(cnt, ref[1])
     finally:
         rtx.rt_set_launch_shape(*shapes[0])
 
@@ -304,7 +310,7 @@ def test_nondefault_stream_and_determinism(torch_cuda, rtx_mod, tiny_setup):
         outs = [rtx.trace(scene, rays, "alpha", alpha_min=128) for _ in range(5)]
     s.synchronize()
     for o in outs:
-        assert torch.equal(o, ref)
+        assert same_bits(o, ref)
 
 
 # ----------------------------------------------------------------------------
