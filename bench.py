@@ -121,6 +121,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--shape", default=None,
+                    help="launch shape BLOCK,LDS_SLOTS,CHUNK,QUEUE (default: the library's default)")
+    ap.add_argument("--intersector", default="alpha", choices=["alpha", "default"],
+                    help="default = the same scene and rays with the accept-all intersector")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the traversal shards by rays with no exchange "
@@ -134,6 +138,9 @@ def main():
     from paper_1912_12786_amd import rtx
     from paper_1912_12786_amd import workloads as W
 
+    if args.shape:
+        rtx.rt_set_launch_shape(*(int(x) for x in args.shape.split(",")))
+    kind = args.intersector
     dev = torch.device("cuda:0")
     props = torch.cuda.get_device_properties(dev)
     log(f"device {props.name} CUs={props.multi_processor_count} "
@@ -153,7 +160,7 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     def step():
-        rtx.trace(scene, rays, "alpha", alpha_min=128, out=hits, workspace=ws)
+        rtx.trace(scene, rays, kind, alpha_min=128, out=hits, workspace=ws)
 
     for _ in range(args.warmup):
         step()
@@ -175,10 +182,10 @@ def main():
     mrays = wl.n_rays * args.steps / wall / 1e6
 
     # exact per-ray counts from a separate (untimed) counting launch
-    _, cnt = rtx.trace(scene, rays, "alpha", alpha_min=128, count=True, workspace=ws)
+    _, cnt = rtx.trace(scene, rays, kind, alpha_min=128, count=True, workspace=ws)
     torch.cuda.synchronize()
     counters = cnt.cpu().numpy().view(np.uint32)
-    alg_bytes = int(bytes_per_ray(counters, "alpha").sum())
+    alg_bytes = int(bytes_per_ray(counters, kind).sum())
     kernel_ms = float(per_launch_ms.mean())
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
 
@@ -186,11 +193,12 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tf = json.load(f)
-        if tf.get("kernel_source_sha") == kernel_source_sha():
+        if tf.get("kernel_source_sha") == kernel_source_sha() and kind == "alpha" \
+                and list(rtx.rt_launch_shapes()[0]) == tf.get("launch_shape") and not args.shape:
             traffic = tf.get("traffic_bytes_per_launch")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and kind == "alpha":
         threads = len(os.sched_getaffinity(0))
         kind_kw = dict(geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures,
                        alpha_min=128)
@@ -214,12 +222,13 @@ def main():
             "workload": wl.name,
             "n_tris": wl.n_tris,
             "n_rays": wl.n_rays,
-            "intersector": "alpha",
-            "alpha_threshold": "0.5 (alpha byte >= 128)",
+            "intersector": kind,
+            "alpha_threshold": "0.5 (alpha byte >= 128)" if kind == "alpha" else None,
             "query": "closest",
             "textures": "16 x 256x256 RGBA8",
             "bvh": f"binary SAH, {scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}",
-            "launch_shape": list(rtx.rt_launch_shapes()[0]),
+            "launch_shape": ([int(x) for x in args.shape.split(",")] if args.shape
+                             else list(rtx.rt_launch_shapes()[0])),
         },
         "roofline": {
             "bound": "hbm",
@@ -228,7 +237,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
-            "kernel": "trace_kernel<alpha_intersector, closest>",
+            "kernel": f"trace_kernel<{kind}_intersector, closest>",
             "kernel_ms_mean": round(kernel_ms, 4),
             "kernel_ms_p10_p90": [round(float(np.percentile(per_launch_ms, 10)), 4),
                                   round(float(np.percentile(per_launch_ms, 90)), 4)],

@@ -154,8 +154,10 @@ rt_status rt_bvh_build(const float *vertices, const uint32_t *geom_ids, uint32_t
                        void *nodes, size_t node_cap, void *tris, size_t tri_cap,
                        rt_bvh_info *info);
 
-/* Device workspace a trace call needs (bytes, possibly 0): overflow space
- * for traversal stacks deeper than the on-chip stack. */
+/* Device workspace a trace call needs (bytes, possibly 0): the ray queue
+ * head of persistent launch shapes and overflow space for traversal stacks
+ * deeper than the on-chip stack.  Its contents need no initialisation and
+ * are scratch: calls that share a workspace must be ordered on one stream. */
 rt_status rt_trace_workspace_bytes(const rt_scene *scene, uint32_t n_rays, uint32_t flags,
                                    size_t *bytes);
 
@@ -182,18 +184,27 @@ rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
                        uint32_t *occluder, rt_counters *counters,
                        void *workspace, size_t workspace_bytes, void *stream);
 
-/* Launch shapes compiled into the library: threads per block and traversal
- * stack entries per lane kept in LDS (deeper entries use the workspace).
- * Writes up to cap pairs (either array may be NULL) and returns the number of
- * shapes.  The first shape is the default. */
-uint32_t rt_launch_shapes(uint32_t *blocks, uint32_t *lds_stacks, uint32_t cap);
+/* Launch shapes compiled into the library:
+ *   block      threads per block;
+ *   lds_stack  LDS ring slots per lane for the top of the traversal stack
+ *              (lds_stack - 1 entries stay on chip, older ones move to the
+ *              workspace);
+ *   chunk      rays a wave takes at a time; the wave hands the next ray of
+ *              its chunk to a lane as soon as the lane's ray is finished;
+ *   queue      1: a persistent grid (256 CUs x 32 wave slots) takes chunks
+ *              from a global atomic queue kept in the workspace; 0: wave w
+ *              owns the static chunk w.
+ * Writes up to cap entries per array (any array may be NULL) and returns the
+ * number of shapes; the first shape is the default. */
+uint32_t rt_launch_shapes(uint32_t *blocks, uint32_t *lds_stacks, uint32_t *chunks,
+                          uint32_t *queues, uint32_t cap);
 
 /* Selects the launch shape of later trace calls in this process (a tuning
  * hook; not synchronised with trace calls running on other threads).
  * Results never depend on the shape; speed and the workspace size do, so
  * query rt_trace_workspace_bytes again after changing it.
- * RT_ERR_UNSUPPORTED if the pair is not compiled in. */
-rt_status rt_set_launch_shape(uint32_t block, uint32_t lds_stack);
+ * RT_ERR_UNSUPPORTED if the shape is not compiled in. */
+rt_status rt_set_launch_shape(uint32_t block, uint32_t lds_stack, uint32_t chunk, uint32_t queue);
 
 /* Static description of a status code. */
 const char *rt_status_string(rt_status status);

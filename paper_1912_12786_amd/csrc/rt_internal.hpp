@@ -31,11 +31,22 @@ rt_status build_bvh(const float *verts, const uint32_t *geom_ids, uint32_t n_tri
 
 enum class Query { Closest, Any };
 
-// Launch shape of the traversal kernels: block size and on-chip stack depth.
+// Launch shape of the traversal kernels.
 struct LaunchShape {
     uint32_t block;      // threads per block
-    uint32_t lds_stack;  // stack entries per lane held in LDS
+    uint32_t lds_stack;  // LDS ring slots per lane (holds lds_stack - 1 stack entries)
+    uint32_t chunk;      // rays a wave takes at a time (its lanes refill from them)
+    uint32_t queue;      // 1: persistent grid + global atomic ray queue; 0: static chunks
 };
+
+// Waves of a persistent (queue) grid: 256 CUs x 32 wave slots of MI355X.
+// Surplus waves of a lower-occupancy kernel start late, find the queue
+// drained and exit.
+constexpr uint64_t kPersistentWaves = 256 * 32;
+
+// Workspace layout: the queue heads in the first 1024 bytes (queue shapes:
+// 8 heads, 128 bytes apart), then the spill columns.
+constexpr size_t kQueueBytes = 1024;
 
 // The shapes compiled into the library; the first one is the default.
 extern const LaunchShape kShapes[];
@@ -52,15 +63,29 @@ struct TraceRequest {
     Query query;
     void *out;          // rt_hit* or uint32_t*
     void *counters;     // rt_counters* or null
-    void *spill;        // workspace
+    void *spill;        // workspace past the queue head
+    void *queue;        // queue head (queue shapes)
     LaunchShape shape;
     void *stream;
 };
 
-// Spill entries per ray needed for a scene under a shape.
+// Stack entries per lane that may have to live in global memory: the stack
+// never holds more than max_depth entries and the ring keeps lds_stack - 1.
 inline uint32_t spill_entries(const rt_bvh_info &info, const LaunchShape &s)
 {
-    return info.max_depth > s.lds_stack ? info.max_depth - s.lds_stack : 0u;
+    const uint32_t cap = s.lds_stack - 1;
+    return info.max_depth > cap ? info.max_depth - cap : 0u;
+}
+
+// Threads launched for n_rays rays (one column of spill space each).
+inline uint64_t launch_threads(uint32_t n_rays, const LaunchShape &s)
+{
+    uint64_t waves = (uint64_t(n_rays) + s.chunk - 1) / s.chunk;
+    if (s.queue) {
+        waves = (uint64_t(n_rays) + 63) / 64;
+        if (waves > kPersistentWaves) waves = kPersistentWaves;
+    }
+    return (waves * 64 + s.block - 1) / s.block * s.block;
 }
 
 // Enqueues one traversal kernel; returns RT_OK or RT_ERR_HIP.

@@ -200,39 +200,72 @@ __device__ __forceinline__ bool triangle(const ray_state &r, float4 a, float4 b,
 }
 
 // -------------------------------------------------------------------------
-// traversal stack: kLds entries per lane in LDS, deeper entries spill to a
-// per-ray slice of global memory (so the per-ray visit order never depends
-// on the stack capacity)
+// traversal stack: a ring of kSlots entries per lane in LDS holds the top of
+// the stack; when a push would overflow it, the oldest entry moves to a
+// per-lane column of global memory, and pops below the ring read it back.
+// Every entry survives, so the per-ray visit order never depends on kSlots.
+// Entries [0, base) live in global memory, [base, sp) in the ring at slot
+// i & (kSlots - 1); at most kSlots - 1 live in the ring, so the slot at sp is
+// always free and a push can write it before knowing whether it is kept.
 // -------------------------------------------------------------------------
-template <int kLds, int kBlock>
-struct trav_stack {
-    uint2 (*lds)[kBlock];  // [kLds][kBlock]
-    uint2 *spill;          // [depth - kLds][spill_stride], may be null if never needed
-    uint32_t lane, slot, spill_stride;
-    int sp = 0;
+// A pointer into global memory (address space 1).  Typing the spill column
+// this way keeps the compiler from merging its accesses with the LDS ring's
+// into generic (flat) accesses.
+template <class T>
+using global_ptr = __attribute__((address_space(1))) T *;
 
-    __device__ __forceinline__ void push(uint32_t ref, float tn)
+template <int kSlots, int kBlock>
+struct ring_stack {
+    static_assert((kSlots & (kSlots - 1)) == 0 && kSlots >= 2, "kSlots: power of two >= 2");
+    static constexpr uint32_t kMask = kSlots - 1;
+    uint2 (*ring)[kBlock];  // [kSlots][kBlock] in LDS
+    global_ptr<uint64_t> spill;  // this lane's column: entry i at spill[i * stride]
+    uint32_t tid, stride;
+    uint32_t sp = 0, base = 0;
+
+    __device__ __forceinline__ void reset() { sp = 0; base = 0; }
+
+    // Writes e into the free slot; keeps it iff `keep`.
+    __device__ __forceinline__ void push_if(bool keep, uint2 e)
     {
-        const uint2 e = make_uint2(ref, __float_as_uint(tn));
-        if (kLds > 0 && sp < kLds)
-            lds[sp][lane] = e;
-        else
-            spill[size_t(sp - kLds) * spill_stride + slot] = e;
-        ++sp;
+        ring[sp & kMask][tid] = e;
+        if (keep) {
+            ++sp;
+            if (sp - base == kSlots) {  // ring full: evict the oldest entry
+                spill_store(base, ring[base & kMask][tid]);
+                ++base;
+            }
+        }
     }
-    // Pops entries until one with tn <= tmax; returns false when empty.
+
+    // Pops until an entry with tn <= tmax appears; false when empty.
     __device__ __forceinline__ bool pop(float tmax, uint32_t &ref)
     {
         while (sp > 0) {
             --sp;
-            const uint2 e = (kLds > 0 && sp < kLds) ? lds[sp][lane]
-                                                     : spill[size_t(sp - kLds) * spill_stride + slot];
+            uint2 e;
+            if (sp >= base) {
+                e = ring[sp & kMask][tid];
+            } else {
+                e = spill_load(sp);
+                base = sp;
+            }
             if (!(__uint_as_float(e.y) > tmax)) {
                 ref = e.x;
                 return true;
             }
         }
         return false;
+    }
+
+    __device__ __forceinline__ void spill_store(uint32_t i, uint2 e)
+    {
+        spill[size_t(i) * stride] = uint64_t(e.x) | (uint64_t(e.y) << 32);
+    }
+    __device__ __forceinline__ uint2 spill_load(uint32_t i) const
+    {
+        const uint64_t v = spill[size_t(i) * stride];
+        return make_uint2(uint32_t(v), uint32_t(v >> 32));
     }
 };
 
@@ -249,77 +282,219 @@ struct trace_result {
     uint32_t prim;
 };
 
-// One ray through the BVH (Algorithm 1: while the ray is alive, descend inner
-// nodes, then test the primitives of the leaf reached).  kAny stops at the
-// first accepted hit; otherwise the nearest accepted hit is kept.
-template <bool kAny, class Isect, class Stack>
-__device__ __forceinline__ trace_result traverse(const scene_view &sc, ray_state r, Isect &isect,
-                                                 Stack &stack)
+// One inner-node step: test both children's boxes; visit the nearer hit
+// child (ties -> child 0) and push the other if both are hit; with neither
+// hit, pop.  Returns false when the stack ran empty (ray finished).
+template <class Isect, class Stack>
+__device__ __forceinline__ bool inner_step(const scene_view &sc, const ray_state &r, Isect &isect,
+                                           Stack &st, uint32_t &cur)
 {
-    trace_result res{__builtin_huge_valf(), 0.0f, 0.0f, kMissPrim};
-    if (sc.n_tris == 0) return res;
+    const float4 *nd = sc.nodes + 4 * size_t(cur);
+    const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2];
+    const uint4 n3 = *reinterpret_cast<const uint4 *>(nd + 3);
+    float tl, tr;
+    isect.on_box_test();
+    isect.on_box_test();
+    const bool hl = slab(r, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tl);
+    const bool hr = slab(r, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tr);
+    const bool right_first = tr < tl;
+    const uint32_t near = (hl && !(hr && right_first)) ? n3.x : n3.y;
+    const uint32_t far = right_first ? n3.x : n3.y;
+    const float far_tn = right_first ? tl : tr;
+    st.push_if(hl && hr, make_uint2(far, __float_as_uint(far_tn)));
+    if (hl || hr) {
+        cur = near;
+        return true;
+    }
+    return st.pop(r.tmax, cur);
+}
 
+// The triangles of one leaf, in stored order.  Returns true iff an any-hit
+// query accepted a hit (the ray is then finished).
+template <bool kAny, class Isect>
+__device__ __forceinline__ bool leaf_step(const scene_view &sc, ray_state &r, Isect &isect,
+                                          uint32_t ref, trace_result &res)
+{
+    const uint32_t first = ref_index(ref), count = ref_count(ref);
+    for (uint32_t j = first; j < first + count; ++j) {
+        const float4 *tp = sc.tris + 3 * size_t(j);
+        const float4 a = tp[0], b = tp[1], c = tp[2];
+        isect.on_tri_test();
+        float t, u, v;
+        if (triangle(r, a, b, c, t, u, v)) {
+            bool ok = true;
+            if constexpr (Isect::kFilters)
+                ok = isect.accept(hit_candidate{__float_as_uint(a.w), __float_as_uint(b.w), t, u, v});
+            if (ok) {
+                res.t = t;
+                res.u = u;
+                res.v = v;
+                res.prim = __float_as_uint(a.w);
+                if constexpr (kAny) return true;
+                r.tmax = t;
+            }
+        }
+    }
+    return false;
+}
+
+__device__ __forceinline__ trace_result miss_result()
+{
+    return trace_result{__builtin_huge_valf(), 0.0f, 0.0f, kMissPrim};
+}
+
+// Root test of a fresh ray: false if the ray misses the scene (or the scene
+// is empty), in which case it is finished with a miss.
+template <class Isect>
+__device__ __forceinline__ bool root_step(const scene_view &sc, const ray_state &r, Isect &isect)
+{
+    if (sc.n_tris == 0) return false;
     float tn;
     isect.on_box_test();
-    bool alive = slab(r, sc.root_lo[0], sc.root_lo[1], sc.root_lo[2], sc.root_hi[0],
-                      sc.root_hi[1], sc.root_hi[2], tn);
-    uint32_t cur = sc.root_ref;
+    return slab(r, sc.root_lo[0], sc.root_lo[1], sc.root_lo[2], sc.root_hi[0], sc.root_hi[1],
+                sc.root_hi[2], tn);
+}
 
-    while (alive) {
-        // inner nodes
-        while (ref_count(cur) == 0) {
-            const float4 *nd = sc.nodes + 4 * size_t(cur);
-            const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2];
-            const uint4 n3 = *reinterpret_cast<const uint4 *>(nd + 3);
-            float tl, tr;
-            isect.on_box_test();
-            isect.on_box_test();
-            const bool hl = slab(r, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tl);
-            const bool hr = slab(r, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tr);
-            if (hl && hr) {
-                const bool right_first = tr < tl;
-                cur = right_first ? n3.y : n3.x;
-                stack.push(right_first ? n3.x : n3.y, right_first ? tl : tr);
-            } else if (hl) {
-                cur = n3.x;
-            } else if (hr) {
-                cur = n3.y;
-            } else if (!stack.pop(r.tmax, cur)) {
-                alive = false;
-                break;
+// -------------------------------------------------------------------------
+// the traversal kernel
+// -------------------------------------------------------------------------
+struct kernel_args {
+    scene_view sc;
+    const float4 *rays;  // 2 float4 per ray
+    uint32_t n_rays;
+    void *out;           // float4 hits (closest) or uint32 occluders (any)
+    uint4 *counters;
+    uint64_t *spill;     // [spill entries][gridDim.x * kBlock]
+    uint32_t *queue;     // kQueueHeads work-queue heads, kQueueStride apart, zero at launch
+};
+
+// Work-queue heads of a persistent launch: one per XCD (MI355X has 8), each
+// in its own 128-byte cache line.
+constexpr uint32_t kQueueHeads = 8;
+constexpr uint32_t kQueueStride = 32;  // uint32 words
+
+// Rays are handed to lanes, not to waves: a wave takes kChunk consecutive rays
+// at a time -- from its own static slice (kQueue = false: wave w owns rays
+// [w kChunk, (w+1) kChunk)) or from a global atomic queue shared by a grid of
+// kPersistentWaves resident waves (kQueue = true) -- and gives the next ray
+// of its chunk to any lane whose ray has finished, so that lanes do not idle
+// behind the slowest ray of the wave.  Each ray's own traversal (Algorithm 1:
+// descend inner nodes, then test the leaf's triangles, until the stack is
+// empty) is exactly what it would be alone.
+template <class Isect, bool kAny, int kSlots, int kBlock, int kChunk, bool kQueue>
+__global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename Isect::params p)
+{
+    static_assert(kBlock % 64 == 0 && kChunk % 32 == 0, "wave64 shapes");
+    __shared__ uint2 ring[kSlots][kBlock];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t gtid = blockIdx.x * kBlock + tid;
+    const uint32_t lane = __lane_id();
+    const uint64_t lanes_below = (uint64_t(1) << lane) - 1;
+
+    // the wave's current chunk [next, end) (wave-uniform)
+    uint32_t next, end;
+    bool drained;  // no further chunk will come
+    // queue state (kQueue): chunks past the static ones are dealt round-robin
+    // to kQueueHeads heads; a wave draws from the head of its block's XCD
+    // (blocks are dispatched to the XCDs round-robin) and, once that head is
+    // exhausted, from the others in turn
+    const uint32_t n_chunks = (a.n_rays + uint32_t(kChunk) - 1) / uint32_t(kChunk);
+    const uint32_t first_dynamic = gridDim.x * (uint32_t(kBlock) / 64);
+    uint32_t head = blockIdx.x % kQueueHeads, dead_heads = 0;
+    if constexpr (kQueue) {
+        // every wave's first chunk is static (chunk index = wave index), so
+        // the launch does not start with every wave on an atomic
+        next = (gtid / 64) * uint32_t(kChunk);
+        end = min(next + uint32_t(kChunk), a.n_rays);
+        drained = false;
+    } else {
+        next = (gtid / 64) * uint32_t(kChunk);
+        end = min(next + uint32_t(kChunk), a.n_rays);
+        drained = true;
+        if (next >= a.n_rays) return;
+    }
+
+    ring_stack<kSlots, kBlock> st{ring, (global_ptr<uint64_t>)(a.spill + gtid), tid,
+                                  gridDim.x * uint32_t(kBlock)};
+    bool active = false;
+    uint32_t ray_id = 0, cur = 0;
+    ray_state r{};
+    Isect isect(p);
+    trace_result res = miss_result();
+
+    auto finish = [&]() {
+        if constexpr (kAny) {
+            static_cast<uint32_t *>(a.out)[ray_id] = res.prim;
+        } else {
+            static_cast<float4 *>(a.out)[ray_id] =
+                make_float4(res.t, __uint_as_float(res.prim), res.u, res.v);
+        }
+        if constexpr (Isect::kCounts)
+            a.counters[ray_id] = make_uint4(isect.num_boxes, isect.num_tris, isect.num_candidates,
+                                            isect.num_accepted);
+    };
+
+    for (;;) {
+        const uint64_t idle = __ballot(!active);
+        if constexpr (kQueue) {
+            if (idle != 0 && next >= end && !drained) {
+                while (dead_heads != (1u << kQueueHeads) - 1) {
+                    uint32_t k = 0;
+                    if (lane == 0) k = atomicAdd(a.queue + head * kQueueStride, 1u);
+                    k = __builtin_amdgcn_readfirstlane(k);
+                    const uint64_t chunk = uint64_t(first_dynamic) + head + uint64_t(kQueueHeads) * k;
+                    if (chunk < n_chunks) {
+                        next = uint32_t(chunk) * uint32_t(kChunk);
+                        end = min(next + uint32_t(kChunk), a.n_rays);
+                        break;
+                    }
+                    dead_heads |= 1u << head;
+                    head = (head + 1) % kQueueHeads;
+                }
+                drained = dead_heads == (1u << kQueueHeads) - 1;
             }
         }
-        if (!alive) break;
-
-        // leaf: its triangles in stored order
-        const uint32_t first = ref_index(cur), count = ref_count(cur);
-        for (uint32_t j = first; j < first + count; ++j) {
-            const float4 *tp = sc.tris + 3 * size_t(j);
-            const float4 a = tp[0], b = tp[1], c = tp[2];
-            isect.on_tri_test();
-            float t, u, v;
-            if (triangle(r, a, b, c, t, u, v)) {
-                bool ok = true;
-                if constexpr (Isect::kFilters)
-                    ok = isect.accept(hit_candidate{__float_as_uint(a.w), __float_as_uint(b.w), t, u, v});
-                if (ok) {
-                    res.t = t;
-                    res.u = u;
-                    res.v = v;
-                    res.prim = __float_as_uint(a.w);
-                    if constexpr (kAny) {
-                        alive = false;
-                        break;
-                    } else {
-                        r.tmax = t;
-                    }
+        if (idle != 0 && next < end) {
+            const uint32_t id = next + uint32_t(__popcll(idle & lanes_below));
+            next = min(next + uint32_t(__popcll(idle)), end);
+            if (!active && id < end) {
+                ray_id = id;
+                r = make_ray(a.rays[2 * size_t(id)], a.rays[2 * size_t(id) + 1]);
+                isect = Isect(p);
+                st.reset();
+                res = miss_result();
+                cur = a.sc.root_ref;
+                active = root_step(a.sc, r, isect);
+                if (!active) finish();
+            }
+        }
+        if (__ballot(active) == 0) {
+            if (drained && next >= end) break;
+            continue;
+        }
+        if (active) {
+            while (ref_count(cur) == 0) {
+                if (!inner_step(a.sc, r, isect, st, cur)) {
+                    active = false;
+                    break;
                 }
             }
+            if (active) {
+                if (leaf_step<kAny>(a.sc, r, isect, cur, res))
+                    active = false;
+                else
+                    active = st.pop(r.tmax, cur);
+            }
+            if (!active) finish();
         }
-        if (!alive) break;
-        alive = stack.pop(r.tmax, cur);
     }
-    return res;
+}
+
+// Zeroes the work-queue heads before a kQueue launch (a kernel rather than a
+// memset, so that the pair can be captured in a graph).
+__global__ void reset_queue_kernel(uint32_t *queue)
+{
+    if (threadIdx.x < kQueueHeads) queue[threadIdx.x * kQueueStride] = 0;
 }
 
 }  // namespace rtx

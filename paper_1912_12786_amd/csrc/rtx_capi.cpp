@@ -83,8 +83,8 @@ rt_status check_params(const rt_scene *sc, rt_isect_kind kind, const void *param
 
 size_t workspace_for(const rt_bvh_info &info, uint32_t n_rays, const LaunchShape &s)
 {
-    const uint64_t stride = (uint64_t(n_rays) + s.block - 1) / s.block * s.block;
-    return size_t(spill_entries(info, s)) * stride * sizeof(uint64_t);
+    return (s.queue ? kQueueBytes : 0) +
+           size_t(spill_entries(info, s)) * size_t(launch_threads(n_rays, s)) * sizeof(uint64_t);
 }
 
 rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
@@ -122,7 +122,8 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     q.query = query;
     q.out = out;
     q.counters = count ? counters : nullptr;
-    q.spill = workspace;
+    q.queue = shape.queue ? workspace : nullptr;
+    q.spill = shape.queue ? static_cast<char *>(workspace) + kQueueBytes : workspace;
     q.shape = shape;
     q.stream = stream;
     const char *err = "";
@@ -196,11 +197,12 @@ rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
                         counters, workspace, workspace_bytes, stream);
 }
 
-rt_status rt_set_launch_shape(uint32_t block, uint32_t lds_stack)
+rt_status rt_set_launch_shape(uint32_t block, uint32_t lds_stack, uint32_t chunk, uint32_t queue)
 {
     g_last_error.clear();
     for (uint32_t i = 0; i < kNumShapes; ++i) {
-        if (kShapes[i].block == block && kShapes[i].lds_stack == lds_stack) {
+        if (kShapes[i].block == block && kShapes[i].lds_stack == lds_stack &&
+            kShapes[i].chunk == chunk && kShapes[i].queue == queue) {
             g_shape_index.store(i);
             return RT_OK;
         }
@@ -208,11 +210,14 @@ rt_status rt_set_launch_shape(uint32_t block, uint32_t lds_stack)
     return fail(RT_ERR_UNSUPPORTED, "launch shape not compiled into the library");
 }
 
-uint32_t rt_launch_shapes(uint32_t *blocks, uint32_t *lds_stacks, uint32_t cap)
+uint32_t rt_launch_shapes(uint32_t *blocks, uint32_t *lds_stacks, uint32_t *chunks,
+                          uint32_t *queues, uint32_t cap)
 {
     for (uint32_t i = 0; i < kNumShapes && i < cap; ++i) {
         if (blocks) blocks[i] = kShapes[i].block;
         if (lds_stacks) lds_stacks[i] = kShapes[i].lds_stack;
+        if (chunks) chunks[i] = kShapes[i].chunk;
+        if (queues) queues[i] = kShapes[i].queue;
     }
     return kNumShapes;
 }

@@ -12,58 +12,60 @@
 // workspace.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "rt_internal.hpp"
 #include "rt_traverse.hpp"
 
 namespace rtx {
 
-const LaunchShape kShapes[] = {{64, 8}, {64, 16}, {256, 8}, {256, 16}};
+// (block, LDS ring slots, rays per chunk, global queue); the first is the default
+const LaunchShape kShapes[] = {{64, 8, 64, 1}, {64, 8, 64, 0}, {64, 8, 32, 1}, {64, 8, 128, 1},
+                               {64, 16, 64, 1}, {256, 8, 64, 1}};
 const uint32_t kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-
-struct kernel_args {
-    scene_view sc;
-    const float4 *rays;  // 2 float4 per ray
-    uint32_t n_rays;
-    void *out;           // float4 hits (closest) or uint32 occluders (any)
-    uint4 *counters;
-    uint2 *spill;
-    uint32_t spill_stride;
-};
-
-template <class Isect, bool kAny, int kLds, int kBlock>
-__global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename Isect::params p)
-{
-    __shared__ uint2 lds[kLds][kBlock];
-    const uint32_t lane = threadIdx.x;
-    const uint32_t i = blockIdx.x * kBlock + lane;
-    if (i >= a.n_rays) return;
-
-    const float4 r0 = a.rays[2 * size_t(i)];
-    const float4 r1 = a.rays[2 * size_t(i) + 1];
-    const ray_state r = make_ray(r0, r1);
-    Isect isect(p);
-    trav_stack<kLds, kBlock> st{lds, a.spill, lane, i, a.spill_stride};
-    const trace_result res = traverse<kAny>(a.sc, r, isect, st);
-
-    if constexpr (kAny) {
-        static_cast<uint32_t *>(a.out)[i] = res.prim;
-    } else {
-        static_cast<float4 *>(a.out)[i] = make_float4(res.t, __uint_as_float(res.prim), res.u, res.v);
-    }
-    if constexpr (Isect::kCounts)
-        a.counters[i] = make_uint4(isect.num_boxes, isect.num_tris, isect.num_candidates,
-                                   isect.num_accepted);
-}
 
 namespace {
 
-template <class Isect, bool kAny, int kLds, int kBlock>
+// Resident blocks per CU x CUs of the current device for a kernel, cached per
+// device (queried once per kernel instantiation and device).
+template <class Kernel>
+uint32_t resident_blocks(Kernel kernel, uint32_t block, const char **err)
+{
+    static std::atomic<uint32_t> cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        *err = "hipGetDevice failed";
+        return 0;
+    }
+    if (cache[dev].load(std::memory_order_relaxed) == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, int(block), 0) != hipSuccess ||
+            cus <= 0 || per_cu <= 0) {
+            *err = "occupancy query failed";
+            return 0;
+        }
+        cache[dev].store(uint32_t(cus) * uint32_t(per_cu), std::memory_order_relaxed);
+    }
+    return cache[dev].load(std::memory_order_relaxed);
+}
+
+template <class Isect, bool kAny, int kSlots, int kBlock, int kChunk, bool kQueue>
 rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipStream_t s,
                      const char **err)
 {
-    const uint32_t grid = (a.n_rays + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL((trace_kernel<Isect, kAny, kLds, kBlock>), dim3(grid), dim3(kBlock), 0, s,
-                       a, p);
+    const LaunchShape sh{kBlock, kSlots, kChunk, kQueue};
+    auto kernel = trace_kernel<Isect, kAny, kSlots, kBlock, kChunk, kQueue>;
+    // the workspace is sized for launch_threads(); a queue grid is further
+    // trimmed to the waves that can be resident at once
+    uint32_t grid = uint32_t(launch_threads(a.n_rays, sh) / kBlock);
+    if constexpr (kQueue) {
+        const uint32_t resident = resident_blocks(kernel, kBlock, err);
+        if (resident == 0) return RT_ERR_HIP;
+        grid = grid < resident ? grid : resident;
+        hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, a.queue);
+    }
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, a, p);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         *err = hipGetErrorString(e);
@@ -72,30 +74,31 @@ rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipS
     return RT_OK;
 }
 
-template <class Isect, int kLds, int kBlock>
+template <class Isect, int kSlots, int kBlock, int kChunk, bool kQueue>
 rt_status dispatch_query(const TraceRequest &q, const kernel_args &a,
                          const typename Isect::params &p, const char **err)
 {
     hipStream_t s = static_cast<hipStream_t>(q.stream);
-    if (q.query == Query::Any) return launch_one<Isect, true, kLds, kBlock>(a, p, s, err);
-    return launch_one<Isect, false, kLds, kBlock>(a, p, s, err);
+    if (q.query == Query::Any) return launch_one<Isect, true, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
+    return launch_one<Isect, false, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
 }
 
-template <class Base, int kLds, int kBlock>
+template <class Base, int kSlots, int kBlock, int kChunk, bool kQueue>
 rt_status dispatch_count(const TraceRequest &q, const kernel_args &a,
                          const typename Base::params &p, const char **err)
 {
-    if (q.count) return dispatch_query<counting_intersector<Base>, kLds, kBlock>(q, a, p, err);
-    return dispatch_query<Base, kLds, kBlock>(q, a, p, err);
+    if (q.count)
+        return dispatch_query<counting_intersector<Base>, kSlots, kBlock, kChunk, kQueue>(q, a, p, err);
+    return dispatch_query<Base, kSlots, kBlock, kChunk, kQueue>(q, a, p, err);
 }
 
-template <int kLds, int kBlock>
+template <int kSlots, int kBlock, int kChunk, bool kQueue>
 rt_status dispatch_kind(const TraceRequest &q, const kernel_args &a, const char **err)
 {
     switch (q.kind) {
     case RT_ISECT_DEFAULT:
-        return dispatch_count<default_intersector, kLds, kBlock>(q, a, default_intersector::params{},
-                                                                 err);
+        return dispatch_count<default_intersector, kSlots, kBlock, kChunk, kQueue>(
+            q, a, default_intersector::params{}, err);
     case RT_ISECT_ALPHA: {
         alpha_intersector::params p;
         p.texcoords = reinterpret_cast<const float2 *>(q.alpha.texcoords);
@@ -103,12 +106,12 @@ rt_status dispatch_kind(const TraceRequest &q, const kernel_args &a, const char 
         p.width = q.alpha.width;
         p.height = q.alpha.height;
         p.alpha_min = q.alpha.alpha_min;
-        return dispatch_count<alpha_intersector, kLds, kBlock>(q, a, p, err);
+        return dispatch_count<alpha_intersector, kSlots, kBlock, kChunk, kQueue>(q, a, p, err);
     }
     case RT_ISECT_PROCEDURAL: {
         checker_intersector::params p;
         p.n = q.checker.checker_n;
-        return dispatch_count<checker_intersector, kLds, kBlock>(q, a, p, err);
+        return dispatch_count<checker_intersector, kSlots, kBlock, kChunk, kQueue>(q, a, p, err);
     }
     }
     *err = "unknown intersector kind";
@@ -133,14 +136,20 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
     a.n_rays = q.n_rays;
     a.out = q.out;
     a.counters = static_cast<uint4 *>(q.counters);
-    a.spill = static_cast<uint2 *>(q.spill);
-    a.spill_stride = (q.n_rays + q.shape.block - 1) / q.shape.block * q.shape.block;
+    a.spill = static_cast<uint64_t *>(q.spill);
+    a.queue = static_cast<uint32_t *>(q.queue);
 
-    const uint32_t b = q.shape.block, l = q.shape.lds_stack;
-    if (b == 64 && l == 8) return dispatch_kind<8, 64>(q, a, err);
-    if (b == 64 && l == 16) return dispatch_kind<16, 64>(q, a, err);
-    if (b == 256 && l == 8) return dispatch_kind<8, 256>(q, a, err);
-    if (b == 256 && l == 16) return dispatch_kind<16, 256>(q, a, err);
+    const LaunchShape &sh = q.shape;
+#define RTX_SHAPE(B, L, C, Q)                                                          \
+    if (sh.block == B && sh.lds_stack == L && sh.chunk == C && sh.queue == Q)          \
+        return dispatch_kind<L, B, C, Q>(q, a, err);
+    RTX_SHAPE(64, 8, 64, 1)
+    RTX_SHAPE(64, 8, 64, 0)
+    RTX_SHAPE(64, 8, 32, 1)
+    RTX_SHAPE(64, 8, 128, 1)
+    RTX_SHAPE(64, 16, 64, 1)
+    RTX_SHAPE(256, 8, 64, 1)
+#undef RTX_SHAPE
     *err = "launch shape not compiled into the library";
     return RT_ERR_UNSUPPORTED;
 }

@@ -66,8 +66,8 @@ SIGNATURES = [
                                    _SZ, _P]),
     ("rt_trace_any", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                _SZ, _P]),
-    ("rt_launch_shapes", C.c_uint32, [_P, _P, _U32]),
-    ("rt_set_launch_shape", C.c_int, [_U32, _U32]),
+    ("rt_launch_shapes", C.c_uint32, [_P, _P, _P, _P, _U32]),
+    ("rt_set_launch_shape", C.c_int, [_U32, _U32, _U32, _U32]),
     ("rt_status_string", C.c_char_p, [C.c_int]),
     ("rt_last_error", C.c_char_p, []),
 ]
@@ -165,16 +165,16 @@ def rt_trace_any(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params,
 
 
 def rt_launch_shapes():
+    """[(block, lds_stack, chunk, queue), ...]; the first is the default."""
     lib = load_library()
-    n = lib.rt_launch_shapes(None, None, 0)
-    b = (C.c_uint32 * n)()
-    l = (C.c_uint32 * n)()
-    lib.rt_launch_shapes(b, l, n)
-    return [(int(b[i]), int(l[i])) for i in range(n)]
+    n = lib.rt_launch_shapes(None, None, None, None, 0)
+    arr = [(C.c_uint32 * n)() for _ in range(4)]
+    lib.rt_launch_shapes(*arr, n)
+    return [tuple(int(a[i]) for a in arr) for i in range(n)]
 
 
-def rt_set_launch_shape(block: int, lds_stack: int):
-    _check(load_library().rt_set_launch_shape(block, lds_stack), "rt_set_launch_shape")
+def rt_set_launch_shape(block: int, lds_stack: int, chunk: int, queue: int):
+    _check(load_library().rt_set_launch_shape(block, lds_stack, chunk, queue), "rt_set_launch_shape")
 
 
 def rt_status_string(status: int) -> str:

@@ -268,7 +268,7 @@ def test_validation_errors(lib):
     sc_mis = _fake_scene()
     sc_mis.tris = 0x20008
     assert _closest(lib, sc_mis) == -2
-    # deep scene needs workspace
+    # a scene needs workspace (queue head and/or spill space)
     deep = _fake_scene(max_depth=60)
     assert _closest(lib, deep) == -4
     assert "workspace" in rtx.rt_last_error()
@@ -283,15 +283,24 @@ def test_zero_rays_is_a_no_op(lib):
 def test_workspace_bytes(lib):
     shapes = rtx.rt_launch_shapes()
     assert len(shapes) >= 1
-    sc = _fake_scene(max_depth=20)
-    for block, lds in shapes:
-        rtx.rt_set_launch_shape(block, lds)
-        b = rtx.rt_trace_workspace_bytes(sc, 1000)
-        padded = (1000 + block - 1) // block * block
-        assert b == max(0, 20 - lds) * padded * 8
-    rtx.rt_set_launch_shape(*shapes[0])
+    try:
+        for block, slots, chunk, queue in shapes:
+            rtx.rt_set_launch_shape(block, slots, chunk, queue)
+            for n in (1000, 3_000_000):
+                b = rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=20), n)
+                if queue:
+                    waves = min((n + 63) // 64, 256 * 32)
+                else:
+                    waves = (n + chunk - 1) // chunk
+                threads = (waves * 64 + block - 1) // block * block
+                assert b == (1024 if queue else 0) + max(0, 20 - (slots - 1)) * threads * 8
+                # shallow scenes need no spill space
+                shallow = rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=slots - 1), n)
+                assert shallow == (1024 if queue else 0)
+    finally:
+        rtx.rt_set_launch_shape(*shapes[0])
     with pytest.raises(rtx.RtxError):
-        rtx.rt_set_launch_shape(3, 3)
+        rtx.rt_set_launch_shape(3, 3, 3, 3)
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

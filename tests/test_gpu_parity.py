@@ -186,9 +186,9 @@ def test_tiny_all_launch_shapes_identical(torch_cuda, rtx_mod, tiny_setup):
     shapes = rtx.rt_launch_shapes()
     ref = None
     try:
-        for block, lds in shapes:
-            announce(f"tiny alpha count shape=({block},{lds})")
-            rtx.rt_set_launch_shape(block, lds)
+        for shape in shapes:
+            announce(f"tiny alpha count shape={shape}")
+            rtx.rt_set_launch_shape(*shape)
             hits, cnt = run(rtx, torch, scene, wl.rays, "alpha", count=True, alpha_min=128)
             if ref is None:
                 ref = (hits, cnt)
@@ -282,11 +282,11 @@ def test_deep_bvh_uses_spill_stack(torch_cuda, rtx_mod, oracle_lib):
     rays[:, 7] = np.inf
     shapes = rtx.rt_launch_shapes()
     try:
-        for block, lds in shapes:
-            rtx.rt_set_launch_shape(block, lds)
+        for shape in shapes:
+            rtx.rt_set_launch_shape(*shape)
             assert rtx.rt_trace_workspace_bytes(sc.view, 300) > 0
             for kind, kw in (("alpha", dict(alpha_min=1)), ("default", {})):
-                announce(f"deep bvh kind={kind} shape=({block},{lds})")
+                announce(f"deep bvh kind={kind} shape={shape}")
                 okw = dict(ai, alpha_min=1) if kind == "alpha" else {}
                 B = oracle_lib.traverse(verts, bvh, rays, kind, **okw)
                 hits, cnt = run(rtx, torch, sc, rays, kind, count=True, **kw)
