@@ -114,6 +114,80 @@ def cpu_baseline(wl, kind_kw, threads, budget_s=8.0):
     }
 
 
+def timed(fn, steps, warmup, stream):
+    """Mean wall time per call (ms) of fn over `steps` calls after `warmup`."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def bench_diff(args):
+    """Differentiable hit: 512x512 rays, perturbed 50k-triangle geodesic sphere
+    plus 5k alpha billboards; loss = sum w.(t, u, v).  Forward = one alpha
+    closest-hit launch; forward+backward adds the zeroing of the vertex
+    gradient and one rt_hit_backward launch; beside them the plain default
+    intersector on the same scene and rays."""
+    import torch
+    from paper_1912_12786_amd import diff, rtx
+    from paper_1912_12786_amd import workloads as W
+    if args.shape:
+        rtx.rt_set_launch_shape(*(int(x) for x in args.shape.split(",")))
+    dev = torch.device("cuda:0")
+    wl = W.diff_scene()
+    scene = rtx.upload_scene(wl.triangles, wl.geom_ids, wl.texcoords, wl.textures, device=dev)
+    rays = torch.from_numpy(wl.rays).to(dev)
+    n = wl.rays.shape[0]
+    hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    V = torch.from_numpy(wl.vertices).to(dev)
+    F = torch.from_numpy(wl.faces.astype(np.int32)).to(dev)
+    w = torch.from_numpy(wl.weights).to(dev)
+    gV = torch.zeros_like(V)
+    gR = torch.empty_like(rays)
+    ws = rtx.Workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def fwd():
+        rtx.trace(scene, rays, "alpha", alpha_min=128, out=hits, workspace=ws)
+
+    def fwd_bwd():
+        fwd()
+        gV.zero_()
+        rtx.rt_hit_backward(rays.data_ptr(), hits.data_ptr(), w.data_ptr(), n, V.data_ptr(),
+                            V.shape[0], F.data_ptr(), F.shape[0], gV.data_ptr(), gR.data_ptr(),
+                            stream.cuda_stream)
+
+    def plain():
+        rtx.trace(scene, rays, "default", out=hits, workspace=ws)
+
+    ms_f = timed(fwd, args.steps, args.warmup, stream)
+    ms_fb = timed(fwd_bwd, args.steps, args.warmup, stream)
+    ms_p = timed(plain, args.steps, args.warmup, stream)
+    print(json.dumps({
+        "metric": "Mrays/s differentiable closest hit (alpha mask): forward, forward+backward, "
+                  "plain default-intersector kernel on the same scene",
+        "value": round(n / ms_fb / 1e3, 2), "unit": "Mrays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n_tris": int(wl.faces.shape[0]),
+                   "n_vertices": int(wl.vertices.shape[0]), "n_rays": n},
+        "forward_mrays_s": round(n / ms_f / 1e3, 2),
+        "forward_backward_mrays_s": round(n / ms_fb / 1e3, 2),
+        "plain_default_mrays_s": round(n / ms_p / 1e3, 2),
+        "ms": {"forward": round(ms_f, 4), "forward_backward": round(ms_fb, 4),
+               "plain_default": round(ms_p, 4)},
+    }), flush=True)
+    del diff
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +199,9 @@ def main():
                     help="launch shape BLOCK,LDS_SLOTS,CHUNK,QUEUE (default: the library's default)")
     ap.add_argument("--intersector", default="alpha", choices=["alpha", "default"],
                     help="default = the same scene and rays with the accept-all intersector")
+    ap.add_argument("--workload", default="billboards", choices=["billboards", "diff"],
+                    help="diff = differentiable hit on the perturbed icosphere (forward, "
+                         "forward+backward and the plain kernel), reported on its own line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the traversal shards by rays with no exchange "
@@ -134,6 +211,9 @@ def main():
     import torch
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "diff":
+        bench_diff(args)
         return
     from paper_1912_12786_amd import rtx
     from paper_1912_12786_amd import workloads as W

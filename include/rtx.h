@@ -184,6 +184,33 @@ rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
                        uint32_t *occluder, rt_counters *counters,
                        void *workspace, size_t workspace_bytes, void *stream);
 
+/* Adjoint of the accepted closest hits (differentiable hit).  For every ray
+ * whose hit (from rt_trace_closest over the triangles vertices[faces]) is not
+ * a miss, the hit point o + t d = (1-u-v) v0 + u v1 + v v2 of triangle
+ * faces[prim_id] is differentiated implicitly with respect to the ray and the
+ * three vertex positions, holding the hit prim and the intersector's decision
+ * fixed (they are discrete).  With g = grad_tuv[i] = (dL/dt, dL/du, dL/dv),
+ * A = [d, -e1, -e2] (columns) and lam = -A^-T g:
+ *   grad_vertices[faces[prim][k]] += c_k lam, (c_0, c_1, c_2) = (-(1-u-v), -u, -v)
+ *   grad_rays[i] = (lam, 0, t lam, 0)   (dL/do, dL/dtmin, dL/dd, dL/dtmax)
+ *   rays          device, [n_rays] rt_ray (the traced rays)
+ *   hits          device, [n_rays] rt_hit (the forward result)
+ *   grad_tuv      device, [n_rays][3] float
+ *   vertices      device, [n_vertices][3] float
+ *   faces         device, [n_tris][3] uint32, the forward's triangles
+ *   grad_vertices device, [n_vertices][3] float, ACCUMULATED (caller zeroes);
+ *                 hipMalloc memory (float32 hardware atomics)
+ *   grad_rays     device, [n_rays][8] float, overwritten (zero for misses),
+ *                 or NULL
+ * Rays whose prim_id or face indices are out of range contribute nothing.
+ * The atomics' summation order is unspecified, so the last bits of
+ * grad_vertices vary between runs.  No paper counterpart: this is the
+ * differentiable extension of the closest-hit query of Section 3.1. */
+rt_status rt_hit_backward(const rt_ray *rays, const rt_hit *hits, const float *grad_tuv,
+                          uint32_t n_rays, const float *vertices, uint32_t n_vertices,
+                          const uint32_t *faces, uint32_t n_tris, float *grad_vertices,
+                          float *grad_rays, void *stream);
+
 /* Launch shapes compiled into the library:
  *   block      threads per block;
  *   lds_stack  LDS ring slots per lane for the top of the traversal stack

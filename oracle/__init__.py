@@ -74,6 +74,10 @@ def _load():
                                      P, C.c_int, P, P, P, P, P, C.c_int]
         lib.orc_traverse.restype = C.c_int
         lib.orc_node_size.restype = C.c_uint32
+        lib.orc_fixed_hit64.argtypes = [P, P, P, P, C.c_uint32, P]
+        lib.orc_fixed_hit64.restype = C.c_int
+        lib.orc_hit_grad64.argtypes = [P, C.c_uint32, P, P, P, P, C.c_uint32, P, P]
+        lib.orc_hit_grad64.restype = C.c_int
         assert lib.orc_node_size() == NODE_DTYPE.itemsize
         _lib = lib
     return _lib
@@ -200,3 +204,37 @@ def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, t
         out["counters"] = cnt
     del keep
     return out
+
+
+# ----------------------------------------------------------------------------
+# gradient of the accepted hit
+# ----------------------------------------------------------------------------
+def fixed_hit64(vertices64, faces, rays, prims):
+    """float64 (t, u, v) of each ray against its fixed triangle (NaN for
+    misses); ``vertices64`` float64 [nv, 3], ``faces`` uint32 [n, 3]."""
+    lib = _load()
+    v = np.ascontiguousarray(vertices64, np.float64)
+    f = np.ascontiguousarray(faces, np.uint32)
+    r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+    p = np.ascontiguousarray(prims, np.uint32)
+    out = np.empty((r.shape[0], 3), np.float64)
+    lib.orc_fixed_hit64(_ptr(v), _ptr(f), _ptr(r), _ptr(p), r.shape[0], _ptr(out))
+    return out
+
+
+def hit_grad64(vertices64, faces, rays, prims, grad_tuv):
+    """float64 closed-form gradient of sum(grad_tuv * (t, u, v)) with the hit
+    prims fixed.  Returns (grad_vertices [nv, 3], grad_rays [N, 6])."""
+    lib = _load()
+    v = np.ascontiguousarray(vertices64, np.float64)
+    f = np.ascontiguousarray(faces, np.uint32)
+    r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+    p = np.ascontiguousarray(prims, np.uint32)
+    g = np.ascontiguousarray(grad_tuv, np.float64)
+    gv = np.zeros_like(v)
+    gr = np.empty((r.shape[0], 6), np.float64)
+    rc = lib.orc_hit_grad64(_ptr(v), v.shape[0], _ptr(f), _ptr(r), _ptr(p), _ptr(g), r.shape[0],
+                            _ptr(gv), _ptr(gr))
+    if rc != 0:
+        raise ValueError("face index out of range")
+    return gv, gr

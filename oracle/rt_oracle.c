@@ -773,3 +773,94 @@ int orc_traverse(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
 }
 
 uint32_t orc_node_size(void) { return (uint32_t)sizeof(orc_node); }
+
+/* ======================================================================
+ * Gradient of the accepted hit (differentiable closest hit)
+ *
+ * For a ray that hit triangle (v0, v1, v2) at (t, u, v), the hit point
+ * satisfies F = o + t d - (1-u-v) v0 - u v1 - v v2 = 0.  With A = dF/d(t,u,v)
+ * = [d, -e1, -e2] (columns; e1 = v1 - v0, e2 = v2 - v0) the implicit function
+ * theorem gives d(t,u,v) = -A^-1 dF, so for an upstream gradient
+ * g = (dL/dt, dL/du, dL/dv):  dL/dtheta = lam . dF/dtheta with
+ * lam = -A^-T g, i.e.
+ *   dL/do = lam, dL/dd = t lam, dL/dv0 = -(1-u-v) lam, dL/dv1 = -u lam,
+ *   dL/dv2 = -v lam.
+ * A^T lam = -g reads d.lam = -g_t, e1.lam = g_u, e2.lam = g_v, solved here
+ * with the scalar triple product: lam = (-g_t (e1 x e2) + g_u (e2 x d)
+ * + g_v (d x e1)) / (d . (e1 x e2)).  The hit prim stays fixed and the
+ * intersector's decision is not differentiated (it is discrete).
+ * ====================================================================== */
+
+/* float64 (t, u, v) of ray i against the fixed triangle faces[prims[i]] of
+ * the float64 vertex array (plane formulation, no inside test); rays with
+ * prim = ORC_MISS or a parallel triangle get NaN. */
+int orc_fixed_hit64(const double *verts, const uint32_t *faces, const float *rays,
+                    const uint32_t *prims, uint32_t n_rays, double *tuv)
+{
+    for (uint32_t i = 0; i < n_rays; ++i) {
+        double *out = tuv + 3 * (size_t)i;
+        out[0] = out[1] = out[2] = NAN;
+        if (prims[i] == ORC_MISS) continue;
+        const float *r = rays + 8 * (size_t)i;
+        d3 o = {r[0], r[1], r[2]}, d = {r[4], r[5], r[6]};
+        const uint32_t *f = faces + 3 * (size_t)prims[i];
+        d3 v0 = {verts[3 * f[0]], verts[3 * f[0] + 1], verts[3 * f[0] + 2]};
+        d3 v1 = {verts[3 * f[1]], verts[3 * f[1] + 1], verts[3 * f[1] + 2]};
+        d3 v2 = {verts[3 * f[2]], verts[3 * f[2] + 1], verts[3 * f[2] + 2]};
+        d3 e1 = d3_sub(v1, v0), e2 = d3_sub(v2, v0);
+        d3 nrm = d3_cross(e1, e2);
+        double dn = d3_dot(d, nrm);
+        if (dn == 0.0) continue;
+        double t = d3_dot(d3_sub(v0, o), nrm) / dn;
+        d3 w = d3_sub(d3_add(o, d3_scale(d, t)), v0);
+        double nn = d3_dot(nrm, nrm);
+        out[0] = t;
+        out[1] = d3_dot(d3_cross(w, e2), nrm) / nn;
+        out[2] = d3_dot(d3_cross(e1, w), nrm) / nn;
+    }
+    return 0;
+}
+
+/* float64 closed-form gradient.  grad_verts [n_verts][3] is accumulated
+ * (caller zeroes it); grad_rays [n_rays][6] (dL/do, dL/dd) is overwritten
+ * (zero for misses).  (t, u, v) are recomputed in float64 for the fixed
+ * prim. */
+int orc_hit_grad64(const double *verts, uint32_t n_verts, const uint32_t *faces,
+                   const float *rays, const uint32_t *prims, const double *grad_tuv,
+                   uint32_t n_rays, double *grad_verts, double *grad_rays)
+{
+    for (uint32_t i = 0; i < n_rays; ++i) {
+        double *gr = grad_rays ? grad_rays + 6 * (size_t)i : NULL;
+        if (gr) for (int k = 0; k < 6; ++k) gr[k] = 0.0;
+        if (prims[i] == ORC_MISS) continue;
+        double tuv[3];
+        orc_fixed_hit64(verts, faces, rays + 8 * (size_t)i, prims + i, 1, tuv);
+        if (isnan(tuv[0])) continue;
+        const float *r = rays + 8 * (size_t)i;
+        d3 d = {r[4], r[5], r[6]};
+        const uint32_t *f = faces + 3 * (size_t)prims[i];
+        if (f[0] >= n_verts || f[1] >= n_verts || f[2] >= n_verts) return -1;
+        d3 v0 = {verts[3 * f[0]], verts[3 * f[0] + 1], verts[3 * f[0] + 2]};
+        d3 v1 = {verts[3 * f[1]], verts[3 * f[1] + 1], verts[3 * f[1] + 2]};
+        d3 v2 = {verts[3 * f[2]], verts[3 * f[2] + 1], verts[3 * f[2] + 2]};
+        d3 e1 = d3_sub(v1, v0), e2 = d3_sub(v2, v0);
+        double det = d3_dot(d, d3_cross(e1, e2));
+        const double *g = grad_tuv + 3 * (size_t)i;
+        d3 lam = d3_add(d3_add(d3_scale(d3_cross(e1, e2), -g[0]), d3_scale(d3_cross(e2, d), g[1])),
+                        d3_scale(d3_cross(d, e1), g[2]));
+        lam = d3_scale(lam, 1.0 / det);
+        double t = tuv[0], u = tuv[1], v = tuv[2], w0 = 1.0 - u - v;
+        double c[3] = {-w0, -u, -v};
+        for (int k = 0; k < 3; ++k) {
+            double *gv = grad_verts + 3 * (size_t)f[k];
+            gv[0] += c[k] * lam.x;
+            gv[1] += c[k] * lam.y;
+            gv[2] += c[k] * lam.z;
+        }
+        if (gr) {
+            gr[0] = lam.x; gr[1] = lam.y; gr[2] = lam.z;
+            gr[3] = t * lam.x; gr[4] = t * lam.y; gr[5] = t * lam.z;
+        }
+    }
+    return 0;
+}

@@ -91,4 +91,21 @@ inline uint64_t launch_threads(uint32_t n_rays, const LaunchShape &s)
 // Enqueues one traversal kernel; returns RT_OK or RT_ERR_HIP.
 rt_status launch_trace(const TraceRequest &req, const char **err);
 
+struct BackwardRequest {
+    const void *rays;
+    const void *hits;
+    const float *grad_tuv;
+    uint32_t n_rays;
+    const float *vertices;
+    uint32_t n_vertices;
+    const uint32_t *faces;
+    uint32_t n_tris;
+    float *grad_vertices;
+    void *grad_rays;
+    void *stream;
+};
+
+// Enqueues the adjoint of the accepted hits; returns RT_OK or RT_ERR_HIP.
+rt_status launch_hit_backward(const BackwardRequest &req, const char **err);
+
 }  // namespace rtx

@@ -197,6 +197,42 @@ rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
                         counters, workspace, workspace_bytes, stream);
 }
 
+rt_status rt_hit_backward(const rt_ray *rays, const rt_hit *hits, const float *grad_tuv,
+                          uint32_t n_rays, const float *vertices, uint32_t n_vertices,
+                          const uint32_t *faces, uint32_t n_tris, float *grad_vertices,
+                          float *grad_rays, void *stream)
+{
+    g_last_error.clear();
+    if (n_rays == 0) return RT_OK;
+    if (n_rays > RT_MAX_RAYS) return fail(RT_ERR_INVALID_ARG, "more than 2^31 rays in one call");
+    if (!rays || !hits || !grad_tuv) return fail(RT_ERR_INVALID_ARG, "rays/hits/grad_tuv are NULL");
+    if (!aligned(rays, 16) || !aligned(hits, 16))
+        return fail(RT_ERR_MISALIGNED, "rays and hits must be 16-byte aligned");
+    if (!aligned(grad_tuv, 4)) return fail(RT_ERR_MISALIGNED, "grad_tuv not 4-byte aligned");
+    if (n_tris > 0 && (!vertices || !faces || !grad_vertices))
+        return fail(RT_ERR_INVALID_ARG, "vertices/faces/grad_vertices are NULL");
+    if (!aligned(vertices, 4) || !aligned(faces, 4) || !aligned(grad_vertices, 4))
+        return fail(RT_ERR_MISALIGNED, "vertex, face and gradient arrays must be 4-byte aligned");
+    if (grad_rays && !aligned(grad_rays, 16))
+        return fail(RT_ERR_MISALIGNED, "grad_rays not 16-byte aligned");
+    BackwardRequest q;
+    q.rays = rays;
+    q.hits = hits;
+    q.grad_tuv = grad_tuv;
+    q.n_rays = n_rays;
+    q.vertices = vertices;
+    q.n_vertices = n_vertices;
+    q.faces = faces;
+    q.n_tris = n_tris;
+    q.grad_vertices = grad_vertices;
+    q.grad_rays = grad_rays;
+    q.stream = stream;
+    const char *err = "";
+    const rt_status st = launch_hit_backward(q, &err);
+    if (st != RT_OK) return fail(st, err);
+    return RT_OK;
+}
+
 rt_status rt_set_launch_shape(uint32_t block, uint32_t lds_stack, uint32_t chunk, uint32_t queue)
 {
     g_last_error.clear();

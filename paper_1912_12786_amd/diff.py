@@ -1,0 +1,78 @@
+"""Differentiable closest hit: ``(t, u, v)`` of the nearest accepted hit as a
+function of the rays and of the mesh's vertex positions.
+
+Forward: host BVH build over ``vertices[faces]`` (rt_bvh_build) and one
+rt_trace_closest launch with the chosen intersector.  Backward: one
+rt_hit_backward launch (implicit differentiation of o + t d = P(u, v) for the
+fixed hit triangle).  The hit triangle and the intersector's decision are
+discrete and are not differentiated; misses return zeros with zero gradient.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import rtx
+
+
+class DifferentiableHit(torch.autograd.Function):
+    """``tuv, prim, hit = DifferentiableHit.apply(rays, vertices, faces, geom_ids,
+    texcoords, textures, intersector, alpha_min, checker_n)``
+
+    rays float32 [N, 8] and vertices float32 [nv, 3] on the GPU (both may
+    require grad); faces uint32/int32 [n, 3]; geom_ids, texcoords, textures as
+    numpy arrays (alpha intersector) or None.  Returns tuv float32 [N, 3]
+    (zeros for misses), prim int32 [N] (-1 for misses) and hit bool [N]."""
+
+    @staticmethod
+    def forward(ctx, rays, vertices, faces, geom_ids, texcoords, textures, intersector="default",
+                alpha_min=128, checker_n=8):
+        v = vertices.detach()
+        f = faces.detach().to(torch.int64)
+        tris = v.cpu().numpy()[f.cpu().numpy()]
+        scene = rtx.upload_scene(tris, geom_ids, texcoords, textures, device=rays.device)
+        hits = rtx.trace(scene, rays.detach().contiguous(), intersector, alpha_min=alpha_min,
+                         checker_n=checker_n)
+        prim = hits[:, 1].view(torch.int32).clone()
+        hit = prim != -1
+        tuv = hits[:, [0, 2, 3]].clone()
+        tuv[~hit] = 0.0
+        faces_u32 = f.to(torch.int32).contiguous()
+        ctx.save_for_backward(rays.detach().contiguous(), hits, v.contiguous(), faces_u32)
+        ctx.mark_non_differentiable(prim, hit)
+        return tuv, prim, hit
+
+    @staticmethod
+    def backward(ctx, grad_tuv, grad_prim=None, grad_hit=None):
+        rays, hits, vertices, faces = ctx.saved_tensors
+        n = rays.shape[0]
+        g = grad_tuv.contiguous().to(torch.float32)
+        grad_vertices = torch.zeros_like(vertices)
+        grad_rays = torch.empty_like(rays)
+        stream = torch.cuda.current_stream(rays.device).cuda_stream
+        rtx.rt_hit_backward(rays.data_ptr(), hits.data_ptr(), g.data_ptr(), n,
+                            vertices.data_ptr(), vertices.shape[0], faces.data_ptr(),
+                            faces.shape[0], grad_vertices.data_ptr(), grad_rays.data_ptr(),
+                            stream)
+        return grad_rays, grad_vertices, None, None, None, None, None, None, None
+
+
+def hit_backward(rays, hits, grad_tuv, vertices, faces, grad_vertices=None, grad_rays=True):
+    """Direct call of rt_hit_backward on device tensors.  Returns
+    (grad_vertices, grad_rays or None); grad_vertices is zeroed here unless
+    given (then accumulated)."""
+    if grad_vertices is None:
+        grad_vertices = torch.zeros_like(vertices)
+    gr = torch.empty_like(rays) if grad_rays else None
+    faces_i = faces.to(torch.int32).contiguous()
+    g = grad_tuv.contiguous().to(torch.float32)
+    stream = torch.cuda.current_stream(rays.device).cuda_stream
+    rtx.rt_hit_backward(rays.data_ptr(), hits.data_ptr(), g.data_ptr(), rays.shape[0],
+                        vertices.data_ptr(), vertices.shape[0], faces_i.data_ptr(),
+                        faces_i.shape[0], grad_vertices.data_ptr(),
+                        None if gr is None else gr.data_ptr(), stream)
+    return grad_vertices, gr
+
+
+def as_numpy_u32(faces) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(faces), np.uint32)

@@ -66,6 +66,7 @@ SIGNATURES = [
                                    _SZ, _P]),
     ("rt_trace_any", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                _SZ, _P]),
+    ("rt_hit_backward", C.c_int, [_P, _P, _P, _U32, _P, _U32, _P, _U32, _P, _P, _P]),
     ("rt_launch_shapes", C.c_uint32, [_P, _P, _P, _P, _U32]),
     ("rt_set_launch_shape", C.c_int, [_U32, _U32, _U32, _U32]),
     ("rt_status_string", C.c_char_p, [C.c_int]),
@@ -162,6 +163,14 @@ def rt_trace_any(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params,
                             None if params is None else C.cast(C.pointer(params), C.c_void_p),
                             flags, occluder_ptr, counters_ptr, workspace_ptr, workspace_bytes,
                             stream), "rt_trace_any")
+
+
+def rt_hit_backward(rays_ptr: int, hits_ptr: int, grad_tuv_ptr: int, n_rays: int,
+                    vertices_ptr: int, n_vertices: int, faces_ptr: int, n_tris: int,
+                    grad_vertices_ptr: int, grad_rays_ptr: int | None, stream: int | None):
+    _check(load_library().rt_hit_backward(rays_ptr, hits_ptr, grad_tuv_ptr, n_rays, vertices_ptr,
+                                          n_vertices, faces_ptr, n_tris, grad_vertices_ptr,
+                                          grad_rays_ptr, stream), "rt_hit_backward")
 
 
 def rt_launch_shapes():

@@ -364,3 +364,110 @@ def subsample_indices(n_rays: int, width: int | None, height: int | None,
         idx.append((ys[:, None] * width + xs[None, :]).ravel())
     idx.append(rng.integers(0, n_rays, size=min(n_random, n_rays)))
     return np.unique(np.concatenate(idx)).astype(np.int64)
+
+
+# --------------------------------------------------------------------------
+# indexed meshes (for the differentiable hit)
+# --------------------------------------------------------------------------
+def geodesic_sphere(freq: int):
+    """Class-I geodesic sphere: each of the icosahedron's 20 faces is cut into
+    freq^2 triangles and every vertex is projected to the unit sphere.
+    Returns (vertices float64 [10 freq^2 + 2, 3], faces int64 [20 freq^2, 3])."""
+    p = (1.0 + math.sqrt(5.0)) / 2.0
+    ico_v = np.array([[-1, p, 0], [1, p, 0], [-1, -p, 0], [1, -p, 0],
+                      [0, -1, p], [0, 1, p], [0, -1, -p], [0, 1, -p],
+                      [p, 0, -1], [p, 0, 1], [-p, 0, -1], [-p, 0, 1]], np.float64)
+    ico_f = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+                      [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+                      [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+                      [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], np.int64)
+    key_to_id: dict = {}
+    verts = []
+
+    def vid(a, b, c, i, j):
+        # point i/freq along (a->b), j/freq along (a->c); keyed by its exact
+        # integer barycentric coordinates on the icosahedron's vertex set
+        k = freq - i - j
+        coords = {a: k, b: i, c: j}
+        key = tuple(sorted((v, w) for v, w in coords.items() if w))
+        if key not in key_to_id:
+            pt = (k * ico_v[a] + i * ico_v[b] + j * ico_v[c]) / freq
+            key_to_id[key] = len(verts)
+            verts.append(pt / np.linalg.norm(pt))
+        return key_to_id[key]
+
+    faces = []
+    for a, b, c in ico_f:
+        for i in range(freq):
+            for j in range(freq - i):
+                faces.append((vid(a, b, c, i, j), vid(a, b, c, i + 1, j), vid(a, b, c, i, j + 1)))
+                if i + j < freq - 1:
+                    faces.append((vid(a, b, c, i + 1, j), vid(a, b, c, i + 1, j + 1),
+                                  vid(a, b, c, i, j + 1)))
+    return np.asarray(verts, np.float64), np.asarray(faces, np.int64)
+
+
+DIFF_EYE = (0.0, 0.0, 4.0)
+
+
+@dataclass
+class MeshWorkload:
+    name: str
+    vertices: np.ndarray    # float32 [nv, 3]
+    faces: np.ndarray       # uint32 [n, 3]
+    rays: np.ndarray        # float32 [N, 8]
+    geom_ids: np.ndarray    # uint32 [n]
+    texcoords: np.ndarray   # float32 [n, 3, 2]
+    textures: np.ndarray    # uint32 [n_tex, H, W]
+    weights: np.ndarray     # float32 [N, 3] loss weights on (t, u, v)
+    opaque_tex: int         # texture id of the sphere (alpha 255 everywhere)
+
+    @property
+    def triangles(self) -> np.ndarray:
+        return self.vertices[self.faces]
+
+
+def diff_scene(freq: int = 50, n_billboards: int = 5000, width: int = 512, height: int = 512,
+               noise: float = 0.01, n_tex: int = 16, tex_size: int = 256) -> MeshWorkload:
+    """Perturbed geodesic sphere (20 freq^2 triangles, radius 1, vertex noise
+    N(0, noise^2) per coordinate) plus camera-facing alpha billboards (centres
+    in the shell 1.2 <= r <= 2, side U[0.05, 0.2], the billboard textures)
+    seen by a width x height pinhole camera at (0, 0, 4) with fov 40 degrees.
+    Loss weights on (t, u, v) are uniform in [-1, 1] per ray.  The sphere uses
+    an extra fully opaque texture so that one alpha-mask launch covers both."""
+    g = rng_for(CFG_DIFF, STREAM_GEOMETRY)
+    sv, sf = geodesic_sphere(freq)
+    sv = sv + g.normal(0.0, noise, size=sv.shape)
+    eye = np.asarray(DIFF_EYE, np.float64)
+    dirs = _random_unit(g, n_billboards)
+    rad = g.uniform(1.2, 2.0, size=n_billboards)
+    c = dirs * rad[:, None]
+    s = g.uniform(0.05, 0.2, size=n_billboards)
+    n = _normalize(eye[None, :] - c)
+    right = _normalize(np.cross(np.array([0.0, 1.0, 0.0])[None, :], n))
+    up = np.cross(n, right)
+    h = (s / 2.0)[:, None]
+    quad = np.stack([c - h * right - h * up, c + h * right - h * up,
+                     c + h * right + h * up, c - h * right + h * up], axis=1)   # [q, 4, 3]
+    bv = quad.reshape(-1, 3)
+    base = sv.shape[0] + 4 * np.arange(n_billboards)
+    bf = np.concatenate([np.stack([base, base + 1, base + 2], 1),
+                         np.stack([base, base + 2, base + 3], 1)], 0)
+    order = np.argsort(np.concatenate([2 * np.arange(n_billboards), 2 * np.arange(n_billboards) + 1]),
+                       kind="stable")
+    bf = bf[order]                                  # quad q -> faces 2q, 2q+1
+    verts = np.concatenate([sv, bv], 0).astype(np.float32)
+    faces = np.concatenate([sf, bf], 0).astype(np.uint32)
+    tex = alpha_textures(n_tex, tex_size, seed_for(CFG_BILLBOARDS, STREAM_TEXTURES))
+    opaque = np.full((1, tex_size, tex_size), np.uint32(0xFF808080), np.uint32)
+    textures = np.concatenate([tex, opaque], 0)
+    n_sphere = sf.shape[0]
+    tc = np.zeros((faces.shape[0], 3, 2), np.float32)
+    tc[n_sphere + 0::2] = np.array([[0, 0], [1, 0], [1, 1]], np.float32)
+    tc[n_sphere + 1::2] = np.array([[0, 0], [1, 1], [0, 1]], np.float32)
+    geom = np.full(faces.shape[0], n_tex, np.uint32)
+    geom[n_sphere:] = np.repeat(g.integers(0, n_tex, size=n_billboards), 2).astype(np.uint32)
+    rays = pinhole_rays(width, height, DIFF_EYE, (0.0, 0.0, 0.0), 40.0)
+    w = rng_for(CFG_DIFF, STREAM_WEIGHTS).uniform(-1.0, 1.0, size=(rays.shape[0], 3)).astype(np.float32)
+    return MeshWorkload(f"diff_icosphere_{n_sphere}_plus_{2 * n_billboards}_billboard_tris_{width}x{height}",
+                        verts, faces, rays, geom, tc, textures, w, n_tex)
