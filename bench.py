@@ -199,6 +199,8 @@ def main():
                     help="launch shape BLOCK,LDS_SLOTS,CHUNK,QUEUE (default: the library's default)")
     ap.add_argument("--intersector", default="alpha", choices=["alpha", "default"],
                     help="default = the same scene and rays with the accept-all intersector")
+    ap.add_argument("--query", default="closest", choices=["closest", "any", "multi"])
+    ap.add_argument("--k", type=int, default=4, help="hits kept per ray by --query multi")
     ap.add_argument("--workload", default="billboards", choices=["billboards", "diff"],
                     help="diff = differentiable hit on the perturbed icosphere (forward, "
                          "forward+backward and the plain kernel), reported on its own line")
@@ -235,12 +237,18 @@ def main():
     log(f"workload {wl.name}: gen {t_gen:.2f} s, host BVH build + upload {t_build:.2f} s, "
         f"{scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}")
     rays = torch.from_numpy(wl.rays).to(dev)
-    hits = torch.empty((wl.n_rays, 4), dtype=torch.float32, device=dev)
+    query = args.query
+    if query == "closest":
+        hits = torch.empty((wl.n_rays, 4), dtype=torch.float32, device=dev)
+    elif query == "any":
+        hits = torch.empty((wl.n_rays,), dtype=torch.int32, device=dev)
+    else:
+        hits = torch.empty((wl.n_rays, args.k, 4), dtype=torch.float32, device=dev)
     ws = rtx.Workspace(dev)
     stream = torch.cuda.current_stream(dev)
 
     def step():
-        rtx.trace(scene, rays, kind, alpha_min=128, out=hits, workspace=ws)
+        rtx.trace(scene, rays, kind, query=query, k=args.k, alpha_min=128, out=hits, workspace=ws)
 
     for _ in range(args.warmup):
         step()
@@ -262,10 +270,16 @@ def main():
     mrays = wl.n_rays * args.steps / wall / 1e6
 
     # exact per-ray counts from a separate (untimed) counting launch
-    _, cnt = rtx.trace(scene, rays, kind, alpha_min=128, count=True, workspace=ws)
+    _, cnt = rtx.trace(scene, rays, kind, query=query, k=args.k, alpha_min=128, count=True,
+                       workspace=ws)
     torch.cuda.synchronize()
     counters = cnt.cpu().numpy().view(np.uint32)
     alg_bytes = int(bytes_per_ray(counters, kind).sum())
+    # output records: 16-B hit (closest), 4-B occluder (any), k 16-B hits + 4-B count (multi)
+    if query == "any":
+        alg_bytes -= 12 * wl.n_rays
+    elif query == "multi":
+        alg_bytes += (16 * (args.k - 1) + 4) * wl.n_rays
     kernel_ms = float(per_launch_ms.mean())
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
 
@@ -274,11 +288,12 @@ def main():
         with open(TRAFFIC_FILE) as f:
             tf = json.load(f)
         if tf.get("kernel_source_sha") == kernel_source_sha() and kind == "alpha" \
+                and query == "closest" \
                 and list(rtx.rt_launch_shapes()[0]) == tf.get("launch_shape") and not args.shape:
             traffic = tf.get("traffic_bytes_per_launch")
 
     cpu = None
-    if not args.no_cpu_baseline and kind == "alpha":
+    if not args.no_cpu_baseline and kind == "alpha" and query == "closest":
         threads = len(os.sched_getaffinity(0))
         kind_kw = dict(geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures,
                        alpha_min=128)
@@ -304,7 +319,7 @@ def main():
             "n_rays": wl.n_rays,
             "intersector": kind,
             "alpha_threshold": "0.5 (alpha byte >= 128)" if kind == "alpha" else None,
-            "query": "closest",
+            "query": query if query != "multi" else f"multi (k={args.k})",
             "textures": "16 x 256x256 RGBA8",
             "bvh": f"binary SAH, {scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}",
             "launch_shape": ([int(x) for x in args.shape.split(",")] if args.shape
@@ -317,7 +332,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
-            "kernel": f"trace_kernel<{kind}_intersector, closest>",
+            "kernel": f"trace_kernel<{kind}_intersector, {query}>",
             "kernel_ms_mean": round(kernel_ms, 4),
             "kernel_ms_p10_p90": [round(float(np.percentile(per_launch_ms, 10)), 4),
                                   round(float(np.percentile(per_launch_ms, 90)), 4)],

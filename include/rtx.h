@@ -184,6 +184,22 @@ rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
                        uint32_t *occluder, rt_counters *counters,
                        void *workspace, size_t workspace_bytes, void *stream);
 
+/* Multi-hit query (Section 3.1: "the first N hit points", read as the k
+ * nearest hits the intersector accepts, in increasing t; a hit with the same
+ * t as a kept one goes after it).  Once k hits are kept, the k-th distance
+ * bounds the search.
+ *   k       1..RT_MAX_MULTI
+ *   hits    device output, [n_rays][k] rt_hit, nearest first, padded with
+ *           miss records
+ *   n_hits  device output, [n_rays] uint32, hits kept per ray (<= k)
+ * Other arguments as for rt_trace_closest; with k = 1 the result equals
+ * rt_trace_closest's. */
+#define RT_MAX_MULTI 8
+rt_status rt_trace_multi(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                         rt_isect_kind kind, const void *params, uint32_t flags, uint32_t k,
+                         rt_hit *hits, uint32_t *n_hits, rt_counters *counters, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
 /* Adjoint of the accepted closest hits (differentiable hit).  For every ray
  * whose hit (from rt_trace_closest over the triangles vertices[faces]) is not
  * a miss, the hit point o + t d = (1-u-v) v0 + u v1 + v v2 of triangle

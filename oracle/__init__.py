@@ -71,7 +71,10 @@ def _load():
         lib.orc_build.argtypes = [P, C.c_uint32, P, P, P, P]
         lib.orc_build.restype = C.c_int
         lib.orc_traverse.argtypes = [P, P, C.c_uint32, P, P, C.c_uint32, P, C.c_uint32, C.c_int,
-                                     P, C.c_int, P, P, P, P, P, C.c_int]
+                                     P, C.c_int, C.c_uint32, P, P, P, P, P, P, C.c_int]
+        lib.orc_brute_multi.argtypes = [P, P, C.c_uint32, P, C.c_uint32, C.c_int, P, C.c_uint32,
+                                        P, P, P, P, P, P, C.c_int]
+        lib.orc_brute_multi.restype = C.c_int
         lib.orc_traverse.restype = C.c_int
         lib.orc_node_size.restype = C.c_uint32
         lib.orc_fixed_hit64.argtypes = [P, P, P, P, C.c_uint32, P]
@@ -179,10 +182,13 @@ def build_bvh(vertices) -> OracleBVH:
 
 
 def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, texcoords=None,
-             textures=None, alpha_min=128, checker_n=8, any_hit=False, count=True, threads=None):
+             textures=None, alpha_min=128, checker_n=8, any_hit=False, count=True, multi_k=0,
+             threads=None):
     """Oracle B traversal.  Returns float32 ``t, u, v``, uint32 ``prim`` and,
     with ``count``, uint32 ``counters [N, 4]`` = (box tests, triangle tests,
-    candidates handed to the intersector, accepted candidates)."""
+    candidates handed to the intersector, accepted candidates).  With
+    ``multi_k > 0`` (multi-hit) ``t, u, v, prim`` are ``[N, multi_k]`` (nearest
+    first, padded with misses) and ``n_hits [N]`` counts the kept hits."""
     lib = _load()
     verts = np.ascontiguousarray(vertices, np.float32).reshape(-1, 9)
     r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
@@ -190,18 +196,48 @@ def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, t
     _check_kind(kind, geom_ids, texcoords, textures, n)
     g = None if geom_ids is None else np.ascontiguousarray(geom_ids, np.uint32)
     m = r.shape[0]
-    out = {k: np.empty(m, np.float32) for k in ("t", "u", "v")}
-    out["prim"] = np.empty(m, np.uint32)
+    shape = (m, multi_k) if multi_k else (m,)
+    out = {k: np.empty(shape, np.float32) for k in ("t", "u", "v")}
+    out["prim"] = np.empty(shape, np.uint32)
+    nh = np.empty(m, np.uint32) if multi_k else None
     cnt = np.empty((m, 4), np.uint32) if count else None
     is_, keep = _isect(texcoords, textures, alpha_min, checker_n)
     rc = lib.orc_traverse(_ptr(verts), _ptr(g), n, _ptr(bvh.nodes), _ptr(bvh.perm), bvh.n_nodes,
-                          _ptr(r), m, KINDS[kind], C.byref(is_), int(bool(any_hit)),
+                          _ptr(r), m, KINDS[kind], C.byref(is_), int(bool(any_hit)), int(multi_k),
                           _ptr(out["t"]), _ptr(out["prim"]), _ptr(out["u"]), _ptr(out["v"]),
-                          _ptr(cnt), _threads(threads))
+                          _ptr(nh), _ptr(cnt), _threads(threads))
     if rc != 0:
         raise RuntimeError(f"orc_traverse failed ({rc})")
     if count:
         out["counters"] = cnt
+    if multi_k:
+        out["n_hits"] = nh
+    del keep
+    return out
+
+
+def brute_multi(vertices, rays, k, kind="default", *, geom_ids=None, texcoords=None,
+                textures=None, alpha_min=128, checker_n=8):
+    """Oracle A for the multi-hit query: the k nearest accepted hits of every
+    ray in float64 ([N, k], ties by input index, padded with misses), their
+    number ``n_hits`` and exception ``flags``."""
+    lib = _load()
+    verts = np.ascontiguousarray(vertices, np.float32).reshape(-1, 9)
+    r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+    n = verts.shape[0]
+    _check_kind(kind, geom_ids, texcoords, textures, n)
+    g = None if geom_ids is None else np.ascontiguousarray(geom_ids, np.uint32)
+    m = r.shape[0]
+    out = {kk: np.empty((m, k), np.float64) for kk in ("t", "u", "v")}
+    out["prim"] = np.empty((m, k), np.uint32)
+    out["n_hits"] = np.empty(m, np.uint32)
+    out["flags"] = np.empty(m, np.uint8)
+    is_, keep = _isect(texcoords, textures, alpha_min, checker_n)
+    rc = lib.orc_brute_multi(_ptr(verts), _ptr(g), n, _ptr(r), m, KINDS[kind], C.byref(is_), k,
+                             _ptr(out["t"]), _ptr(out["prim"]), _ptr(out["u"]), _ptr(out["v"]),
+                             _ptr(out["n_hits"]), _ptr(out["flags"]), 1)
+    if rc != 0:
+        raise RuntimeError(f"orc_brute_multi failed ({rc})")
     del keep
     return out
 

@@ -41,6 +41,7 @@
 #include <string.h>
 
 #define ORC_MISS 0xFFFFFFFFu
+#define ORC_MAX_MULTI 8
 
 enum { ORC_DEFAULT = 0, ORC_ALPHA = 1, ORC_PROCEDURAL = 2 };
 
@@ -555,8 +556,10 @@ typedef struct {
     int kind;
     orc_isect is;
     int any_hit;
-    float *t, *u, *v;
+    uint32_t multi_k;   /* > 0: multi-hit query keeping the multi_k nearest */
+    float *t, *u, *v;   /* [n_rays] or, for multi-hit, [n_rays][multi_k] */
     uint32_t *prim;
+    uint32_t *n_hits;   /* multi-hit: hits found per ray */
     uint32_t *counters; /* [n_rays][4]: boxes, triangles, candidates, accepts */
     uint32_t next;
     pthread_mutex_t lock;
@@ -581,6 +584,11 @@ typedef struct {
     float t, u, v;
     uint32_t prim;
     int done;
+    /* multi-hit list, sorted by t (ties: earlier accepted first) */
+    uint32_t k, n;
+    float tmax0;
+    float lt[ORC_MAX_MULTI], lu[ORC_MAX_MULTI], lv[ORC_MAX_MULTI];
+    uint32_t lp[ORC_MAX_MULTI];
     uint32_t n_box, n_tri, n_cand, n_acc;
 } ray_state;
 
@@ -652,6 +660,22 @@ static void tri_test(const trav_job *job, ray_state *rs, uint32_t slot)
     rs->n_cand++;
     if (!accept32(job, prim, u, v)) return;
     rs->n_acc++;
+    if (rs->k > 0) {
+        /* multi-hit: insert after every kept hit with t' <= t; the k-th
+         * nearest distance, once k hits are kept, bounds the search */
+        uint32_t pos = rs->n;
+        while (pos > 0 && t < rs->lt[pos - 1]) --pos;
+        if (pos >= rs->k) return;
+        uint32_t last = rs->n < rs->k ? rs->n : rs->k - 1;
+        for (uint32_t i = last; i > pos; --i) {
+            rs->lt[i] = rs->lt[i - 1]; rs->lu[i] = rs->lu[i - 1];
+            rs->lv[i] = rs->lv[i - 1]; rs->lp[i] = rs->lp[i - 1];
+        }
+        rs->lt[pos] = t; rs->lu[pos] = u; rs->lv[pos] = v; rs->lp[pos] = prim;
+        if (rs->n < rs->k) rs->n++;
+        if (rs->n == rs->k) rs->tmax_cur = rs->lt[rs->k - 1] < rs->tmax0 ? rs->lt[rs->k - 1] : rs->tmax0;
+        return;
+    }
     rs->prim = prim;
     rs->t = t; rs->u = u; rs->v = v;
     if (job->any_hit) rs->done = 1;
@@ -674,8 +698,10 @@ static void trav_one(trav_job *job, uint32_t i)
     }
     rs.tmin = r[3];
     rs.tmax_cur = r[7];
+    rs.tmax0 = r[7];
     rs.prim = ORC_MISS;
     rs.t = INFINITY;
+    rs.k = job->multi_k;
 
     if (job->n_tris > 0) {
         uint32_t stack_node[128];
@@ -722,11 +748,23 @@ static void trav_one(trav_job *job, uint32_t i)
         }
     }
 
-    if (rs.prim == ORC_MISS) { rs.t = INFINITY; rs.u = 0.0f; rs.v = 0.0f; }
-    job->t[i] = rs.t;
-    job->u[i] = rs.u;
-    job->v[i] = rs.v;
-    job->prim[i] = rs.prim;
+    if (job->multi_k > 0) {
+        for (uint32_t j = 0; j < job->multi_k; ++j) {
+            size_t o = (size_t)i * job->multi_k + j;
+            int kept = j < rs.n;
+            job->t[o] = kept ? rs.lt[j] : INFINITY;
+            job->u[o] = kept ? rs.lu[j] : 0.0f;
+            job->v[o] = kept ? rs.lv[j] : 0.0f;
+            job->prim[o] = kept ? rs.lp[j] : ORC_MISS;
+        }
+        job->n_hits[i] = rs.n;
+    } else {
+        if (rs.prim == ORC_MISS) { rs.t = INFINITY; rs.u = 0.0f; rs.v = 0.0f; }
+        job->t[i] = rs.t;
+        job->u[i] = rs.u;
+        job->v[i] = rs.v;
+        job->prim[i] = rs.prim;
+    }
     if (job->counters) {
         uint32_t *c = job->counters + 4 * (size_t)i;
         c[0] = rs.n_box; c[1] = rs.n_tri; c[2] = rs.n_cand; c[3] = rs.n_acc;
@@ -750,14 +788,17 @@ static void *trav_worker(void *arg)
 
 /* Oracle B traversal over a BVH made by orc_build.  Outputs t/u/v/prim per
  * ray (misses: prim = ORC_MISS, t = +inf, u = v = 0; any-hit: the first
- * accepted hit) and, if counters != NULL, four uint32 counters per ray. */
+ * accepted hit; multi-hit (multi_k > 0): the multi_k nearest accepted hits in
+ * increasing t, ties in acceptance order, padded with misses, and their number
+ * in n_hits) and, if counters != NULL, four uint32 counters per ray. */
 int orc_traverse(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
                  const orc_node *nodes, const uint32_t *perm, uint32_t n_nodes,
                  const float *rays, uint32_t n_rays, int kind, const orc_isect *is,
-                 int any_hit, float *t, uint32_t *prim, float *u, float *v,
-                 uint32_t *counters, int n_threads)
+                 int any_hit, uint32_t multi_k, float *t, uint32_t *prim, float *u, float *v,
+                 uint32_t *n_hits, uint32_t *counters, int n_threads)
 {
     if (kind < ORC_DEFAULT || kind > ORC_PROCEDURAL) return -1;
+    if (multi_k > ORC_MAX_MULTI || (multi_k > 0 && (any_hit || !n_hits))) return -2;
     trav_job job;
     memset(&job, 0, sizeof job);
     job.verts = verts; job.geom = geom_ids; job.n_tris = n_tris;
@@ -765,7 +806,9 @@ int orc_traverse(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
     job.rays = rays; job.n_rays = n_rays; job.kind = kind;
     if (is) job.is = *is;
     job.any_hit = any_hit;
+    job.multi_k = multi_k;
     job.t = t; job.u = u; job.v = v; job.prim = prim; job.counters = counters;
+    job.n_hits = n_hits;
     pthread_mutex_init(&job.lock, NULL);
     run_threads(trav_worker, &job, n_threads);
     pthread_mutex_destroy(&job.lock);
@@ -862,5 +905,104 @@ int orc_hit_grad64(const double *verts, uint32_t n_verts, const uint32_t *faces,
             gr[3] = t * lam.x; gr[4] = t * lam.y; gr[5] = t * lam.z;
         }
     }
+    return 0;
+}
+
+
+/* ======================================================================
+ * Multi-hit query, float64 definition (Section 3.1: the first N hit points;
+ * read as the N nearest accepted hits in increasing distance).
+ * ====================================================================== */
+typedef struct {
+    double t, u, v;
+    uint32_t k;
+} acc_hit;
+
+static int acc_cmp(const void *a, const void *b)
+{
+    const acc_hit *x = (const acc_hit *)a, *y = (const acc_hit *)b;
+    if (x->t < y->t) return -1;
+    if (x->t > y->t) return 1;
+    return x->k < y->k ? -1 : (x->k > y->k);
+}
+
+/* For each ray: every accepted hit, sorted by (t, index); the first K are
+ * written ([n_rays][K], padded with misses) with their count.  flags marks
+ * rays whose kept set is ambiguous in float32: two accepted distances among
+ * the first K+1 within 1e-6 relative (or within their float32 bounds), or a
+ * candidate no farther than the K-th kept hit (all candidates when fewer than
+ * K were found) that is near an edge or near its filter decision. */
+int orc_brute_multi(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
+                    const float *rays, uint32_t n_rays, int kind, const orc_isect *is,
+                    uint32_t K, double *t, uint32_t *prim, double *u, double *v,
+                    uint32_t *n_hits, uint8_t *flags, int n_threads)
+{
+    (void)n_threads;
+    if (K == 0 || kind < ORC_DEFAULT || kind > ORC_PROCEDURAL) return -1;
+    acc_hit *buf = malloc(sizeof(acc_hit) * (n_tris ? n_tris : 1));
+    double *bt = malloc(sizeof(double) * (n_tris ? n_tris : 1));
+    if (!buf || !bt) { free(buf); free(bt); return -1; }
+    brute_job tmp;
+    memset(&tmp, 0, sizeof tmp);
+    if (is) tmp.is = *is;
+    for (uint32_t i = 0; i < n_rays; ++i) {
+        const float *r = rays + 8 * (size_t)i;
+        d3 o = {r[0], r[1], r[2]}, d = {r[4], r[5], r[6]};
+        double tmin = r[3], tmax = r[7];
+        uint32_t m = 0;
+        for (uint32_t k = 0; k < n_tris; ++k) {
+            double tt, uu, vv, mg, bu, btt;
+            if (!plane_hit64(o, d, verts + 9 * (size_t)k, &tt, &uu, &vv, &mg, &bu, &btt)) continue;
+            if (!(mg >= 0.0) || !(tt > tmin) || !(tt < tmax)) continue;
+            int acc = 1;
+            double fm;
+            uint32_t g = geom_ids ? geom_ids[k] : 0;
+            if (kind == ORC_ALPHA) acc = alpha_accept64(&tmp.is, k, g, uu, vv);
+            else if (kind == ORC_PROCEDURAL) acc = checker_accept64(&tmp.is, uu, vv, &fm);
+            if (!acc) continue;
+            buf[m].t = tt; buf[m].u = uu; buf[m].v = vv; buf[m].k = k;
+            bt[m] = btt;
+            ++m;
+        }
+        qsort(buf, m, sizeof(acc_hit), acc_cmp);
+        uint32_t keep = m < K ? m : K;
+        uint8_t fl = 0;
+        for (uint32_t j = 0; j < K; ++j) {
+            size_t o2 = (size_t)i * K + j;
+            t[o2] = j < keep ? buf[j].t : INFINITY;
+            u[o2] = j < keep ? buf[j].u : 0.0;
+            v[o2] = j < keep ? buf[j].v : 0.0;
+            prim[o2] = j < keep ? buf[j].k : ORC_MISS;
+        }
+        n_hits[i] = keep;
+        uint32_t lim = m < K + 1 ? m : K + 1;
+        for (uint32_t j = 1; j < lim; ++j)
+            if (buf[j].t - buf[j - 1].t < 1e-6 * fabs(buf[j].t)) fl |= ORC_E_NEAR_TIE;
+        double reach = (m >= K) ? buf[K - 1].t * (1.0 + 1e-6) : tmax;
+        for (uint32_t k = 0; k < n_tris; ++k) {
+            double tt, uu, vv, mg, bu, btt;
+            if (!plane_hit64(o, d, verts + 9 * (size_t)k, &tt, &uu, &vv, &mg, &bu, &btt)) continue;
+            if (!(tt > tmin - btt) || !(tt < tmax + btt) || !(tt <= reach + btt)) continue;
+            double delta = bu > 1e-6 ? bu : 1e-6;
+            if (fabs(mg) < delta) fl |= ORC_E_NEAR_EDGE;
+            if (mg > -delta && kind == ORC_ALPHA) {
+                double wh = tmp.is.width > tmp.is.height ? tmp.is.width : tmp.is.height;
+                if (alpha_decision_fragile(&tmp.is, k, geom_ids ? geom_ids[k] : 0, uu, vv,
+                                           (2.0 * delta + 0x1p-20) * wh))
+                    fl |= ORC_E_NEAR_FILTER;
+            } else if (mg > -delta && kind == ORC_PROCEDURAL) {
+                double fm;
+                checker_accept64(&tmp.is, uu, vv, &fm);
+                if (fm < 2.0 * delta * tmp.is.checker_n) fl |= ORC_E_NEAR_FILTER;
+            }
+            /* a near-equal distance to a kept hit makes the order ambiguous */
+            for (uint32_t j = 0; j < keep; ++j)
+                if (buf[j].k != k && mg > -delta && fabs(tt - buf[j].t) <= btt + bt[j])
+                    fl |= ORC_E_NEAR_TIE;
+        }
+        flags[i] = fl;
+    }
+    free(buf);
+    free(bt);
     return 0;
 }

@@ -29,7 +29,7 @@ uint32_t max_inner_nodes(uint32_t n_tris);
 rt_status build_bvh(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
                     NodeRecord *nodes, TriRecord *tris, rt_bvh_info *info);
 
-enum class Query { Closest, Any };
+enum class Query { Closest, Any, Multi };
 
 // Launch shape of the traversal kernels.
 struct LaunchShape {
@@ -61,7 +61,9 @@ struct TraceRequest {
     rt_procedural_params checker;
     bool count;
     Query query;
-    void *out;          // rt_hit* or uint32_t*
+    void *out;          // rt_hit* (multi: [n][multi_k]) or uint32_t*
+    void *n_hits;       // multi-hit: uint32_t* kept hits per ray
+    uint32_t multi_k;   // multi-hit: hits kept per ray (1..RT_MAX_MULTI)
     void *counters;     // rt_counters* or null
     void *spill;        // workspace past the queue head
     void *queue;        // queue head (queue shapes)

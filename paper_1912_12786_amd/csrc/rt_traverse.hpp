@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rtx {
 
 // -------------------------------------------------------------------------
@@ -277,11 +279,6 @@ struct scene_view {
     uint32_t n_tris;
 };
 
-struct trace_result {
-    float t, u, v;
-    uint32_t prim;
-};
-
 // One inner-node step: test both children's boxes; visit the nearer hit
 // child (ties -> child 0) and push the other if both are hit; with neither
 // hit, pop.  Returns false when the stack ran empty (ray finished).
@@ -309,11 +306,95 @@ __device__ __forceinline__ bool inner_step(const scene_view &sc, const ray_state
     return st.pop(r.tmax, cur);
 }
 
-// The triangles of one leaf, in stored order.  Returns true iff an any-hit
-// query accepted a hit (the ray is then finished).
-template <bool kAny, class Isect>
+// Result policies: what a query keeps of the accepted hits (Section 3.1).
+// commit() receives every accepted candidate in traversal order, may shrink
+// the search interval r.tmax, and returns true when the ray is finished.
+struct closest_result {  // the nearest accepted hit
+    float t, u, v;
+    uint32_t prim;
+    __device__ __forceinline__ void reset(const ray_state &, uint32_t)
+    {
+        t = __builtin_huge_valf();
+        u = v = 0.0f;
+        prim = kMissPrim;
+    }
+    __device__ __forceinline__ bool commit(ray_state &r, float tt, float uu, float vv, uint32_t p)
+    {
+        t = tt;
+        u = uu;
+        v = vv;
+        prim = p;
+        r.tmax = tt;
+        return false;
+    }
+};
+
+struct any_result {  // the first accepted hit met
+    uint32_t prim;
+    __device__ __forceinline__ void reset(const ray_state &, uint32_t) { prim = kMissPrim; }
+    __device__ __forceinline__ bool commit(ray_state &, float, float, float, uint32_t p)
+    {
+        prim = p;
+        return true;
+    }
+};
+
+// The k nearest accepted hits (k <= kMax, a run-time value), sorted by t;
+// a new hit goes after every kept hit with the same t.  Once k hits are kept,
+// the k-th distance bounds the search.  The list lives in registers: every
+// loop over it is unrolled, so no index is dynamic.
+template <int kMax>
+struct multi_result {
+    float t[kMax], u[kMax], v[kMax];
+    uint32_t prim[kMax];
+    uint32_t n, k;
+    float tmax0;
+    __device__ __forceinline__ void reset(const ray_state &r, uint32_t kk)
+    {
+#pragma unroll
+        for (int i = 0; i < kMax; ++i) {
+            t[i] = __builtin_huge_valf();
+            u[i] = v[i] = 0.0f;
+            prim[i] = kMissPrim;
+        }
+        n = 0;
+        k = kk;
+        tmax0 = r.tmax;
+    }
+    __device__ __forceinline__ bool commit(ray_state &r, float tt, float uu, float vv, uint32_t p)
+    {
+        // carry the new hit down the list, swapping it with every kept hit
+        // that is strictly farther; what falls off slot k-1 is dropped
+        float ct = tt, cu = uu, cv = vv;
+        uint32_t cp = p;
+        float tk = __builtin_huge_valf();
+#pragma unroll
+        for (int i = 0; i < kMax; ++i) {
+            const bool live = uint32_t(i) < k;
+            const bool take = live && ct < t[i];
+            const float st = t[i], su = u[i], sv = v[i];
+            const uint32_t sp = prim[i];
+            t[i] = take ? ct : st;
+            u[i] = take ? cu : su;
+            v[i] = take ? cv : sv;
+            prim[i] = take ? cp : sp;
+            ct = take ? st : ct;
+            cu = take ? su : cu;
+            cv = take ? sv : cv;
+            cp = take ? sp : cp;
+            if (uint32_t(i) + 1 == k) tk = t[i];
+        }
+        n = n < k ? n + 1 : k;
+        r.tmax = fminf(tmax0, tk);
+        return false;
+    }
+};
+
+// The triangles of one leaf, in stored order.  Returns true iff the result
+// policy finished the ray.
+template <class Result, class Isect>
 __device__ __forceinline__ bool leaf_step(const scene_view &sc, ray_state &r, Isect &isect,
-                                          uint32_t ref, trace_result &res)
+                                          uint32_t ref, Result &res)
 {
     const uint32_t first = ref_index(ref), count = ref_count(ref);
     for (uint32_t j = first; j < first + count; ++j) {
@@ -325,22 +406,10 @@ __device__ __forceinline__ bool leaf_step(const scene_view &sc, ray_state &r, Is
             bool ok = true;
             if constexpr (Isect::kFilters)
                 ok = isect.accept(hit_candidate{__float_as_uint(a.w), __float_as_uint(b.w), t, u, v});
-            if (ok) {
-                res.t = t;
-                res.u = u;
-                res.v = v;
-                res.prim = __float_as_uint(a.w);
-                if constexpr (kAny) return true;
-                r.tmax = t;
-            }
+            if (ok && res.commit(r, t, u, v, __float_as_uint(a.w))) return true;
         }
     }
     return false;
-}
-
-__device__ __forceinline__ trace_result miss_result()
-{
-    return trace_result{__builtin_huge_valf(), 0.0f, 0.0f, kMissPrim};
 }
 
 // Root test of a fresh ray: false if the ray misses the scene (or the scene
@@ -362,7 +431,9 @@ struct kernel_args {
     scene_view sc;
     const float4 *rays;  // 2 float4 per ray
     uint32_t n_rays;
-    void *out;           // float4 hits (closest) or uint32 occluders (any)
+    void *out;           // float4 hits (closest, [n][k] for multi) or uint32 occluders (any)
+    uint32_t *n_hits;    // multi-hit: kept hits per ray
+    uint32_t multi_k;    // multi-hit: hits kept per ray
     uint4 *counters;
     uint64_t *spill;     // [spill entries][gridDim.x * kBlock]
     uint32_t *queue;     // kQueueHeads work-queue heads, kQueueStride apart, zero at launch
@@ -381,7 +452,25 @@ constexpr uint32_t kQueueStride = 32;  // uint32 words
 // behind the slowest ray of the wave.  Each ray's own traversal (Algorithm 1:
 // descend inner nodes, then test the leaf's triangles, until the stack is
 // empty) is exactly what it would be alone.
-template <class Isect, bool kAny, int kSlots, int kBlock, int kChunk, bool kQueue>
+template <class Result>
+__device__ __forceinline__ void write_result(const kernel_args &a, uint32_t ray, const Result &res)
+{
+    if constexpr (std::is_same_v<Result, any_result>) {
+        static_cast<uint32_t *>(a.out)[ray] = res.prim;
+    } else if constexpr (std::is_same_v<Result, closest_result>) {
+        static_cast<float4 *>(a.out)[ray] =
+            make_float4(res.t, __uint_as_float(res.prim), res.u, res.v);
+    } else {
+        float4 *o = static_cast<float4 *>(a.out) + size_t(ray) * a.multi_k;
+#pragma unroll
+        for (int i = 0; i < int(sizeof(res.t) / sizeof(float)); ++i)
+            if (uint32_t(i) < a.multi_k)
+                o[i] = make_float4(res.t[i], __uint_as_float(res.prim[i]), res.u[i], res.v[i]);
+        a.n_hits[ray] = res.n;
+    }
+}
+
+template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue>
 __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename Isect::params p)
 {
     static_assert(kBlock % 64 == 0 && kChunk % 32 == 0, "wave64 shapes");
@@ -420,15 +509,11 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
     uint32_t ray_id = 0, cur = 0;
     ray_state r{};
     Isect isect(p);
-    trace_result res = miss_result();
+    Result res;
+    res.reset(r, a.multi_k);
 
     auto finish = [&]() {
-        if constexpr (kAny) {
-            static_cast<uint32_t *>(a.out)[ray_id] = res.prim;
-        } else {
-            static_cast<float4 *>(a.out)[ray_id] =
-                make_float4(res.t, __uint_as_float(res.prim), res.u, res.v);
-        }
+        write_result(a, ray_id, res);
         if constexpr (Isect::kCounts)
             a.counters[ray_id] = make_uint4(isect.num_boxes, isect.num_tris, isect.num_candidates,
                                             isect.num_accepted);
@@ -462,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
                 r = make_ray(a.rays[2 * size_t(id)], a.rays[2 * size_t(id) + 1]);
                 isect = Isect(p);
                 st.reset();
-                res = miss_result();
+                res.reset(r, a.multi_k);
                 cur = a.sc.root_ref;
                 active = root_step(a.sc, r, isect);
                 if (!active) finish();
@@ -480,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
                 }
             }
             if (active) {
-                if (leaf_step<kAny>(a.sc, r, isect, cur, res))
+                if (leaf_step(a.sc, r, isect, cur, res))
                     active = false;
                 else
                     active = st.pop(r.tmax, cur);

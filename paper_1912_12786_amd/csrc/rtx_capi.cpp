@@ -90,7 +90,8 @@ size_t workspace_for(const rt_bvh_info &info, uint32_t n_rays, const LaunchShape
 rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
                        rt_isect_kind kind, const void *params, uint32_t flags, void *out,
                        size_t out_align, rt_counters *counters, void *workspace,
-                       size_t workspace_bytes, void *stream)
+                       size_t workspace_bytes, void *stream, uint32_t multi_k = 0,
+                       uint32_t *n_hits = nullptr)
 {
     g_last_error.clear();
     rt_status st = check_scene(scene);
@@ -99,8 +100,12 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     TraceRequest q;
     st = check_params(scene, kind, params, q);
     if (st != RT_OK) return st;
+    if (query == Query::Multi && (multi_k < 1 || multi_k > RT_MAX_MULTI))
+        return fail(RT_ERR_INVALID_ARG, "multi-hit k must be within 1..RT_MAX_MULTI");
     if (n_rays == 0) return RT_OK;
     if (n_rays > RT_MAX_RAYS) return fail(RT_ERR_INVALID_ARG, "more than 2^31 rays in one call");
+    if (query == Query::Multi && (!n_hits || !aligned(n_hits, 4)))
+        return fail(RT_ERR_INVALID_ARG, "multi-hit needs a 4-byte aligned n_hits array");
     if (!rays) return fail(RT_ERR_INVALID_ARG, "rays are NULL");
     if (!aligned(rays, 16)) return fail(RT_ERR_MISALIGNED, "rays not 16-byte aligned");
     if (!out) return fail(RT_ERR_INVALID_ARG, "output array is NULL");
@@ -121,6 +126,8 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     q.count = count;
     q.query = query;
     q.out = out;
+    q.n_hits = n_hits;
+    q.multi_k = query == Query::Multi ? multi_k : 1;
     q.counters = count ? counters : nullptr;
     q.queue = shape.queue ? workspace : nullptr;
     q.spill = shape.queue ? static_cast<char *>(workspace) + kQueueBytes : workspace;
@@ -195,6 +202,15 @@ rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
 {
     return trace_common(Query::Any, scene, rays, n_rays, kind, params, flags, occluder, 4,
                         counters, workspace, workspace_bytes, stream);
+}
+
+rt_status rt_trace_multi(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                         rt_isect_kind kind, const void *params, uint32_t flags, uint32_t k,
+                         rt_hit *hits, uint32_t *n_hits, rt_counters *counters, void *workspace,
+                         size_t workspace_bytes, void *stream)
+{
+    return trace_common(Query::Multi, scene, rays, n_rays, kind, params, flags, hits, 16,
+                        counters, workspace, workspace_bytes, stream, k, n_hits);
 }
 
 rt_status rt_hit_backward(const rt_ray *rays, const rt_hit *hits, const float *grad_tuv,

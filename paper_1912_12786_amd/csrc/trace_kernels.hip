@@ -20,8 +20,7 @@
 namespace rtx {
 
 // (block, LDS ring slots, rays per chunk, global queue); the first is the default
-const LaunchShape kShapes[] = {{64, 8, 64, 1}, {64, 8, 64, 0}, {64, 8, 32, 1}, {64, 8, 128, 1},
-                               {64, 16, 64, 1}, {256, 8, 64, 1}};
+const LaunchShape kShapes[] = {{64, 8, 64, 1}, {64, 8, 64, 0}, {64, 16, 64, 1}, {256, 8, 64, 1}};
 const uint32_t kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 namespace {
@@ -50,12 +49,12 @@ uint32_t resident_blocks(Kernel kernel, uint32_t block, const char **err)
     return cache[dev].load(std::memory_order_relaxed);
 }
 
-template <class Isect, bool kAny, int kSlots, int kBlock, int kChunk, bool kQueue>
+template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue>
 rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipStream_t s,
                      const char **err)
 {
     const LaunchShape sh{kBlock, kSlots, kChunk, kQueue};
-    auto kernel = trace_kernel<Isect, kAny, kSlots, kBlock, kChunk, kQueue>;
+    auto kernel = trace_kernel<Isect, Result, kSlots, kBlock, kChunk, kQueue>;
     // the workspace is sized for launch_threads(); a queue grid is further
     // trimmed to the waves that can be resident at once
     uint32_t grid = uint32_t(launch_threads(a.n_rays, sh) / kBlock);
@@ -79,8 +78,16 @@ rt_status dispatch_query(const TraceRequest &q, const kernel_args &a,
                          const typename Isect::params &p, const char **err)
 {
     hipStream_t s = static_cast<hipStream_t>(q.stream);
-    if (q.query == Query::Any) return launch_one<Isect, true, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
-    return launch_one<Isect, false, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
+    switch (q.query) {
+    case Query::Any:
+        return launch_one<Isect, any_result, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
+    case Query::Multi:
+        return launch_one<Isect, multi_result<RT_MAX_MULTI>, kSlots, kBlock, kChunk, kQueue>(a, p, s,
+                                                                                              err);
+    case Query::Closest:
+        break;
+    }
+    return launch_one<Isect, closest_result, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
 }
 
 template <class Base, int kSlots, int kBlock, int kChunk, bool kQueue>
@@ -135,6 +142,8 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
     a.rays = static_cast<const float4 *>(q.rays);
     a.n_rays = q.n_rays;
     a.out = q.out;
+    a.n_hits = static_cast<uint32_t *>(q.n_hits);
+    a.multi_k = q.multi_k;
     a.counters = static_cast<uint4 *>(q.counters);
     a.spill = static_cast<uint64_t *>(q.spill);
     a.queue = static_cast<uint32_t *>(q.queue);
@@ -145,8 +154,6 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
         return dispatch_kind<L, B, C, Q>(q, a, err);
     RTX_SHAPE(64, 8, 64, 1)
     RTX_SHAPE(64, 8, 64, 0)
-    RTX_SHAPE(64, 8, 32, 1)
-    RTX_SHAPE(64, 8, 128, 1)
     RTX_SHAPE(64, 16, 64, 1)
     RTX_SHAPE(256, 8, 64, 1)
 #undef RTX_SHAPE

@@ -66,6 +66,8 @@ SIGNATURES = [
                                    _SZ, _P]),
     ("rt_trace_any", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                _SZ, _P]),
+    ("rt_trace_multi", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _U32, _P, _P,
+                                 _P, _P, _SZ, _P]),
     ("rt_hit_backward", C.c_int, [_P, _P, _P, _U32, _P, _U32, _P, _U32, _P, _P, _P]),
     ("rt_launch_shapes", C.c_uint32, [_P, _P, _P, _P, _U32]),
     ("rt_set_launch_shape", C.c_int, [_U32, _U32, _U32, _U32]),
@@ -163,6 +165,16 @@ def rt_trace_any(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params,
                             None if params is None else C.cast(C.pointer(params), C.c_void_p),
                             flags, occluder_ptr, counters_ptr, workspace_ptr, workspace_bytes,
                             stream), "rt_trace_any")
+
+
+def rt_trace_multi(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params, flags: int,
+                   k: int, hits_ptr: int, n_hits_ptr: int, counters_ptr: int | None,
+                   workspace_ptr: int | None, workspace_bytes: int, stream: int | None):
+    lib = load_library()
+    _check(lib.rt_trace_multi(C.byref(scene), rays_ptr, n_rays, kind,
+                              None if params is None else C.cast(C.pointer(params), C.c_void_p),
+                              flags, k, hits_ptr, n_hits_ptr, counters_ptr, workspace_ptr,
+                              workspace_bytes, stream), "rt_trace_multi")
 
 
 def rt_hit_backward(rays_ptr: int, hits_ptr: int, grad_tuv_ptr: int, n_rays: int,
@@ -273,14 +285,15 @@ class Workspace:
 
 
 def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "closest",
-          count: bool = False, alpha_min: int = 128, checker_n: int = 8, out=None,
+          count: bool = False, alpha_min: int = 128, checker_n: int = 8, k: int = 4, out=None,
           counters=None, workspace: Workspace | None = None, stream=None):
     """Traces device rays ``float32 [N, 8]``.
 
     closest: returns ``hits float32 [N, 4]`` = (t, prim_id bits, u, v); view
     column 1 as int32/uint32 for prim_id.  any: returns ``int32 [N]``
-    occluders (-1 = none).  With ``count`` also returns ``int32 [N, 4]``
-    counters (box tests, triangle tests, candidates, accepted)."""
+    occluders (-1 = none).  multi: returns ``(hits float32 [N, k, 4], n_hits
+    int32 [N])``.  With ``count`` also returns ``int32 [N, 4]`` counters (box
+    tests, triangle tests, candidates, accepted)."""
     torch = _torch()
     if rays.dtype != torch.float32 or rays.dim() != 2 or rays.shape[1] != 8 or not rays.is_contiguous():
         raise ValueError("rays must be a contiguous float32 [N, 8] tensor")
@@ -295,8 +308,12 @@ def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "clo
     elif query == "any":
         if out is None:
             out = torch.empty((n,), dtype=torch.int32, device=dev)
+    elif query == "multi":
+        if out is None:
+            out = torch.empty((n, k, 4), dtype=torch.float32, device=dev)
+        n_hits = torch.empty((n,), dtype=torch.int32, device=dev)
     else:
-        raise ValueError("query must be 'closest' or 'any'")
+        raise ValueError("query must be 'closest', 'any' or 'multi'")
     if count and counters is None:
         counters = torch.empty((n, 4), dtype=torch.int32, device=dev)
     ws = workspace or Workspace(dev)
@@ -306,7 +323,11 @@ def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "clo
     if query == "closest":
         rt_trace_closest(sc, rays.data_ptr(), n, KINDS[intersector], params, flags,
                          out.data_ptr(), cptr, wptr, wbytes, s)
-    else:
+    elif query == "any":
         rt_trace_any(sc, rays.data_ptr(), n, KINDS[intersector], params, flags,
                      out.data_ptr(), cptr, wptr, wbytes, s)
+    else:
+        rt_trace_multi(sc, rays.data_ptr(), n, KINDS[intersector], params, flags, k,
+                       out.data_ptr(), n_hits.data_ptr(), cptr, wptr, wbytes, s)
+        out = (out, n_hits)
     return (out, counters) if count else out

@@ -274,6 +274,16 @@ def test_validation_errors(lib):
     assert "workspace" in rtx.rt_last_error()
 
 
+def test_multi_validation(lib):
+    sc = _fake_scene()
+    for k in (0, 9):
+        assert lib.rt_trace_multi(C.byref(sc), 0x30000, 100, 0, None, 0, k, 0x40000, 0x50000,
+                                  None, None, 0, None) == -1
+    # n_hits is required
+    assert lib.rt_trace_multi(C.byref(sc), 0x30000, 100, 0, None, 0, 4, 0x40000, None,
+                              None, None, 0, None) == -1
+
+
 def test_zero_rays_is_a_no_op(lib):
     sc = _fake_scene()
     assert _closest(lib, sc, rays=None, n=0, hits=None) == 0

@@ -123,3 +123,29 @@ def test_diff_backward_matches_closed_form_and_fd(diff_setup, oracle_lib):
             assert abs(gV[vid, k] - fd) <= 1e-3 * scale, (vid, k, gV[vid, k], fd)
             # and the plain h = 1e-4 difference is within its own truncation estimate
             assert abs(gV[vid, k] - d1) <= 1e-3 * scale + 2.0 * abs(d1 - d2)
+
+
+def test_autograd_function(diff_setup):
+    import torch
+    from paper_1912_12786_amd import diff
+    wl, tris, scene, bvh = diff_setup
+    announce("DifferentiableHit autograd on the diff scene (every 16th ray)")
+    rays = torch.from_numpy(wl.rays[::16].copy()).cuda().requires_grad_(True)
+    V = torch.from_numpy(wl.vertices).cuda().requires_grad_(True)
+    F = torch.from_numpy(wl.faces.astype(np.int32)).cuda()
+    tuv, prim, hit = diff.DifferentiableHit.apply(rays, V, F, wl.geom_ids, wl.texcoords,
+                                                  wl.textures, "alpha", 128, 8)
+    w = torch.from_numpy(wl.weights[::16].copy()).cuda()
+    loss = (tuv * w).sum()
+    loss.backward()
+    assert V.grad is not None and rays.grad is not None
+    # the same numbers as a direct backward call with the same upstream weights
+    hits = torch.zeros((rays.shape[0], 4), device="cuda")
+    hits[:, 0], hits[:, 2], hits[:, 3] = tuv[:, 0].detach(), tuv[:, 1].detach(), tuv[:, 2].detach()
+    hits[:, 1] = prim.view(torch.float32)
+    gV, gR = diff.hit_backward(rays.detach(), hits, w, V.detach(), F)
+    torch.cuda.synchronize()
+    assert torch.allclose(V.grad, gV, rtol=1e-5, atol=1e-6)
+    assert torch.allclose(rays.grad, gR, rtol=1e-6, atol=1e-7)
+    assert torch.all(rays.grad[~hit] == 0)
+    assert torch.all(tuv[~hit] == 0)
