@@ -188,6 +188,118 @@ def bench_diff(args):
     del diff
 
 
+def bench_batched(args):
+    """64 scenes of uneven size (5.1M triangles, 19.9M rays in total), default
+    intersector, closest hit: one batched persistent launch (eager and replayed
+    from a captured graph) against 64 separate per-scene launches (eager and
+    graph-replayed).  The batched launch's shape is picked by the autotuner."""
+    import torch
+    from paper_1912_12786_amd import autotune, rtx
+    from paper_1912_12786_amd import workloads as W
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    scenes = W.batched()
+    sc_list = [rtx.upload_scene(s["vertices"], device=dev) for s in scenes]
+    counts = [s["rays"].shape[0] for s in scenes]
+    batch = rtx.Batch(sc_list, counts, "default", device=dev)
+    rays = torch.from_numpy(np.concatenate([s["rays"] for s in scenes])).to(dev)
+    torch.cuda.synchronize()
+    log(f"batched workload: {len(scenes)} scenes, {sum(s['vertices'].shape[0] for s in scenes)} "
+        f"tris, {rays.shape[0]} rays, prepared in {time.perf_counter() - t0:.1f} s")
+    n = rays.shape[0]
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    ws = rtx.Workspace(dev)
+    offs = batch.offsets
+    views = [rays[offs[i]:offs[i + 1]] for i in range(len(scenes))]
+    outs = [out[offs[i]:offs[i + 1]] for i in range(len(scenes))]
+    stream = torch.cuda.current_stream(dev)
+
+    def batched():
+        batch.trace(rays, out=out, workspace=ws)
+
+    def separate():
+        for sc, r, o in zip(sc_list, views, outs):
+            if r.shape[0]:
+                rtx.trace(sc, r, "default", out=o, workspace=ws)
+
+    best, tune_ms = autotune.tune("batched-64-scenes-default", batched, cache_path=None,
+                                  steps=3, warmup=1)
+    # grow the workspace to the largest need before any capture
+    ws.get(max(rtx.rt_trace_batch_workspace_bytes(batch.info),
+               max(rtx.rt_trace_workspace_bytes(sc.view, c) for sc, c in zip(sc_list, counts))))
+
+    def graph_of(fn):
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            fn()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        return g
+
+    g_batched = graph_of(batched)
+    g_separate = graph_of(separate)
+    ms = {
+        "batched_eager": timed(batched, args.steps, args.warmup, stream),
+        "batched_graph": timed(g_batched.replay, args.steps, args.warmup, stream),
+        "separate_eager": timed(separate, args.steps, args.warmup, stream),
+        "separate_graph": timed(g_separate.replay, args.steps, args.warmup, stream),
+    }
+    print(json.dumps({
+        "metric": "Mrays/s closest hit over a batch of 64 scenes (default intersector): one "
+                  "persistent launch vs 64 per-scene launches",
+        "value": round(n / ms["batched_graph"] / 1e3, 2), "unit": "Mrays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched_{len(scenes)}_scenes", "n_scenes": len(scenes),
+                   "n_tris": int(sum(s["vertices"].shape[0] for s in scenes)), "n_rays": int(n),
+                   "launch_shape": list(best)},
+        "mrays_s": {k: round(n / v / 1e3, 2) for k, v in ms.items()},
+        "ms": {k: round(v, 4) for k, v in ms.items()},
+        "autotune_ms": tune_ms,
+    }), flush=True)
+
+
+def bench_dispatch(args):
+    """Compile-time intersector vs the same decision dispatched at run time
+    (an inlined switch, or an indirect call through a function table) on the
+    billboard workload, for the default and the alpha-mask intersector."""
+    import torch
+    from paper_1912_12786_amd import rtx
+    from paper_1912_12786_amd import workloads as W
+    dev = torch.device("cuda:0")
+    wl = W.billboards()
+    scene = rtx.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures, device=dev)
+    rays = torch.from_numpy(wl.rays).to(dev)
+    n = wl.n_rays
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    ws = rtx.Workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+    sc = scene.view
+    res = {}
+    for kind in ("default", "alpha"):
+        params = rtx._params(scene, kind, 128, 8)
+        for name, flags in (("compile_time", 0), ("runtime_switch", rtx.RT_FLAG_RUNTIME_SWITCH),
+                            ("runtime_call", rtx.RT_FLAG_RUNTIME_CALL)):
+            wptr, wb = ws.get(rtx.rt_trace_workspace_bytes(sc, n, flags))
+
+            def fn():
+                rtx.rt_trace_closest(sc, rays.data_ptr(), n, rtx.KINDS[kind], params, flags,
+                                     out.data_ptr(), None, wptr, wb, stream.cuda_stream)
+            ms = timed(fn, args.steps, args.warmup, stream)
+            res[f"{kind}/{name}"] = {"ms": round(ms, 4), "mrays_s": round(n / ms / 1e3, 2)}
+    print(json.dumps({
+        "metric": "Mrays/s closest hit, compile-time intersector vs run-time dispatch "
+                  "(switch, indirect call) at 1080p billboards",
+        "value": res["alpha/compile_time"]["mrays_s"], "unit": "Mrays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic", "config": {"workload": wl.name, "n_rays": n},
+        "results": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,7 +313,7 @@ def main():
                     help="default = the same scene and rays with the accept-all intersector")
     ap.add_argument("--query", default="closest", choices=["closest", "any", "multi"])
     ap.add_argument("--k", type=int, default=4, help="hits kept per ray by --query multi")
-    ap.add_argument("--workload", default="billboards", choices=["billboards", "diff"],
+    ap.add_argument("--workload", default="billboards", choices=["billboards", "diff", "batched", "dispatch"],
                     help="diff = differentiable hit on the perturbed icosphere (forward, "
                          "forward+backward and the plain kernel), reported on its own line")
     args = ap.parse_args()
@@ -216,6 +328,12 @@ def main():
         return
     if args.workload == "diff":
         bench_diff(args)
+        return
+    if args.workload == "batched":
+        bench_batched(args)
+        return
+    if args.workload == "dispatch":
+        bench_dispatch(args)
         return
     from paper_1912_12786_amd import rtx
     from paper_1912_12786_amd import workloads as W

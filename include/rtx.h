@@ -86,8 +86,16 @@ typedef enum rt_isect_kind {
 } rt_isect_kind;
 
 /* Flags.  RT_FLAG_COUNT composes the counting intersector with the chosen
- * kind and requires a counters array. */
+ * kind and requires a counters array.
+ * RT_FLAG_RUNTIME_SWITCH / RT_FLAG_RUNTIME_CALL (closest-hit query, without
+ * counting) select the intersector per candidate at run time instead of at
+ * compile time -- an inlined switch over the kinds, or an indirect call
+ * through a table of filter functions, the way a library without templates
+ * must do it (Section 1).  Results are identical; they exist to measure the
+ * cost that compile-time injection avoids. */
 #define RT_FLAG_COUNT 0x1u
+#define RT_FLAG_RUNTIME_SWITCH 0x2u
+#define RT_FLAG_RUNTIME_CALL 0x4u
 
 /* Alpha-mask intersector (Listing 5).  For a candidate (prim, u, v):
  *   (s, t) = (1-u-v) tc[prim][0] + u tc[prim][1] + v tc[prim][2],
@@ -183,6 +191,51 @@ rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
                        rt_isect_kind kind, const void *params, uint32_t flags,
                        uint32_t *occluder, rt_counters *counters,
                        void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Batched launch: many scenes, each with its own consecutive range of rays,
+ * traced by one launch (one persistent grid draining one ray queue).
+ * The caller packs a scene table on the host (rt_batch_pack), copies it to
+ * device memory, and passes the device copy to rt_trace_batch; nothing is
+ * copied behind the caller's back, so the launch can be graph-captured.
+ * --------------------------------------------------------------------- */
+typedef struct rt_batch_entry {
+    rt_scene scene;          /* the scene's BVH (device), from rt_bvh_build */
+    uint32_t n_rays;         /* rays of this scene: the next n_rays of the batch */
+    rt_alpha_params alpha;   /* alpha-mask data of this scene (RT_ISECT_ALPHA only) */
+} rt_batch_entry;
+
+typedef struct rt_batch_info {
+    uint32_t n_scenes;
+    uint32_t n_rays;         /* sum of the entries' n_rays */
+    uint32_t max_depth;      /* deepest BVH of the batch */
+    uint32_t kind;           /* the intersector kind the table was packed for */
+} rt_batch_info;
+
+/* Bytes of the packed table for n_scenes scenes. */
+rt_status rt_batch_table_bytes(uint32_t n_scenes, size_t *bytes);
+
+/* Validates the entries (every scene as rt_trace_closest would, and for
+ * RT_ISECT_ALPHA every entry's alpha data against its scene) and writes the
+ * table into host_table (host, 16-byte aligned, table_bytes >= 
+ * rt_batch_table_bytes).  The device pointers inside are copied verbatim. */
+rt_status rt_batch_pack(const rt_batch_entry *entries, uint32_t n_scenes, rt_isect_kind kind,
+                        void *host_table, size_t table_bytes, rt_batch_info *info);
+
+/* Workspace of rt_trace_batch (as rt_trace_workspace_bytes). */
+rt_status rt_trace_batch_workspace_bytes(const rt_batch_info *info, uint32_t flags,
+                                         size_t *bytes);
+
+/* Closest-hit query over a batch (Section 3.1 per scene).  table: device copy
+ * of the packed table described by info; rays/hits/counters: device,
+ * [info->n_rays] in scene order (scene s owns the rays after those of scenes
+ * 0..s-1).  kind must be the kind the table was packed for; params: NULL, or
+ * rt_procedural_params for RT_ISECT_PROCEDURAL (the alpha data comes from the
+ * table).  Results are bit-identical to one rt_trace_closest call per scene. */
+rt_status rt_trace_batch(const void *table, const rt_batch_info *info, const rt_ray *rays,
+                         rt_isect_kind kind, const void *params, uint32_t flags, rt_hit *hits,
+                         rt_counters *counters, void *workspace, size_t workspace_bytes,
+                         void *stream);
 
 /* Multi-hit query (Section 3.1: "the first N hit points", read as the k
  * nearest hits the intersector accepts, in increasing t; a hit with the same

@@ -81,6 +81,12 @@ def _load():
         lib.orc_fixed_hit64.restype = C.c_int
         lib.orc_hit_grad64.argtypes = [P, C.c_uint32, P, P, P, P, C.c_uint32, P, P]
         lib.orc_hit_grad64.restype = C.c_int
+        lib.orc_brute_instanced.argtypes = [P, C.c_uint32, P, C.c_uint32, P, C.c_uint32, C.c_int, P,
+                                            P, P, P, P, P, P]
+        lib.orc_brute_instanced.restype = C.c_int
+        lib.orc_traverse_instanced.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, C.c_uint32,
+                                               C.c_int, P, C.c_int, P, P, P, P, P, P]
+        lib.orc_traverse_instanced.restype = C.c_int
         assert lib.orc_node_size() == NODE_DTYPE.itemsize
         _lib = lib
     return _lib
@@ -274,3 +280,89 @@ def hit_grad64(vertices64, faces, rays, prims, grad_tuv):
     if rc != 0:
         raise ValueError("face index out of range")
     return gv, gr
+
+
+# ----------------------------------------------------------------------------
+# instancing
+# ----------------------------------------------------------------------------
+class _Blas(C.Structure):
+    _fields_ = [("verts", C.c_void_p), ("n_tris", C.c_uint32), ("nodes", C.c_void_p),
+                ("perm", C.c_void_p)]
+
+
+class _Inst(C.Structure):
+    _fields_ = [("blas", C.c_uint32), ("m", C.c_float * 12)]
+
+
+def _instance_args(blas_vertices, blas_bvhs, inst_blas, inst_m):
+    keep = []
+    blas = (_Blas * len(blas_vertices))()
+    for i, (v, b) in enumerate(zip(blas_vertices, blas_bvhs)):
+        vv = np.ascontiguousarray(v, np.float32).reshape(-1, 9)
+        keep += [vv, b.nodes, b.perm]
+        blas[i].verts = vv.ctypes.data
+        blas[i].n_tris = vv.shape[0]
+        blas[i].nodes = b.nodes.ctypes.data
+        blas[i].perm = b.perm.ctypes.data
+    n = len(inst_blas)
+    inst = (_Inst * max(1, n))()
+    m = np.ascontiguousarray(inst_m, np.float32).reshape(-1, 12)
+    for j in range(n):
+        inst[j].blas = int(inst_blas[j])
+        inst[j].m[:] = m[j].tolist()
+    return blas, inst, keep
+
+
+def build_tlas(world_lo, world_hi) -> OracleBVH:
+    """Top-level BVH over instance world boxes (each as the degenerate
+    triangle lo, hi, hi)."""
+    lo = np.asarray(world_lo, np.float32)
+    hi = np.asarray(world_hi, np.float32)
+    return build_bvh(np.stack([lo, hi, hi], axis=1))
+
+
+def brute_instanced(blas_vertices, inst_blas, inst_m, rays, kind="default", checker_n=8):
+    """float64 definition over every instance and triangle."""
+    lib = _load()
+    bvhs = [OracleBVH(np.zeros(1, NODE_DTYPE), np.zeros(1, np.uint32), 0)] * len(blas_vertices)
+    blas, inst, keep = _instance_args(blas_vertices, bvhs, inst_blas, inst_m)
+    r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+    m = r.shape[0]
+    out = {k: np.empty(m, np.float64) for k in ("t", "u", "v")}
+    out["prim"] = np.empty(m, np.uint32)
+    out["inst"] = np.empty(m, np.uint32)
+    out["flags"] = np.empty(m, np.uint8)
+    is_, k2 = _isect(None, None, 128, checker_n)
+    rc = lib.orc_brute_instanced(blas, len(blas_vertices), inst, len(inst_blas), _ptr(r), m,
+                                 KINDS[kind], C.byref(is_), _ptr(out["t"]), _ptr(out["prim"]),
+                                 _ptr(out["inst"]), _ptr(out["u"]), _ptr(out["v"]),
+                                 _ptr(out["flags"]))
+    if rc != 0:
+        raise RuntimeError(f"orc_brute_instanced failed ({rc})")
+    del keep, k2
+    return out
+
+
+def traverse_instanced(blas_vertices, blas_bvhs, inst_blas, inst_m, tlas: OracleBVH, rays,
+                       kind="default", checker_n=8, any_hit=False, count=True):
+    """float32 two-level traversal (oracle B)."""
+    lib = _load()
+    blas, inst, keep = _instance_args(blas_vertices, blas_bvhs, inst_blas, inst_m)
+    r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+    m = r.shape[0]
+    out = {k: np.empty(m, np.float32) for k in ("t", "u", "v")}
+    out["prim"] = np.empty(m, np.uint32)
+    out["inst"] = np.empty(m, np.uint32)
+    cnt = np.empty((m, 4), np.uint32) if count else None
+    is_, k2 = _isect(None, None, 128, checker_n)
+    rc = lib.orc_traverse_instanced(blas, len(blas_vertices), inst, len(inst_blas),
+                                    _ptr(tlas.nodes), _ptr(tlas.perm), _ptr(r), m, KINDS[kind],
+                                    C.byref(is_), int(bool(any_hit)), _ptr(out["t"]),
+                                    _ptr(out["prim"]), _ptr(out["inst"]), _ptr(out["u"]),
+                                    _ptr(out["v"]), _ptr(cnt))
+    if rc != 0:
+        raise RuntimeError(f"orc_traverse_instanced failed ({rc})")
+    if count:
+        out["counters"] = cnt
+    del keep, k2
+    return out

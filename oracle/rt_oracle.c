@@ -1006,3 +1006,281 @@ int orc_brute_multi(const float *verts, const uint32_t *geom_ids, uint32_t n_tri
     free(bt);
     return 0;
 }
+
+/* ======================================================================
+ * Instancing (Section 3.2: a BVH may itself be a primitive of a BVH; object
+ * instancing stores BVHs as the primitives of a top-level BVH).
+ *
+ * An instance is a bottom-level BVH (blas) plus a row-major 3x4 affine map M
+ * from world to object space; a world ray o + t d becomes the object ray
+ * M(o) + t L(d) (L = linear part), so the distance t and the barycentrics of
+ * a hit are the same in both spaces.  Reading used for the float32 traversal:
+ *   o'_i = fma(m_i0, o_x, fma(m_i1, o_y, fma(m_i2, o_z, m_i3)))
+ *   d'_i = fma(m_i0, d_x, fma(m_i1, d_y, m_i2 * d_z))
+ * The top-level BVH is the binned-SAH BVH over the instances' world boxes
+ * (each box given as the degenerate triangle lo, hi, hi); at a top-level leaf
+ * the leaf's instances are entered in stored order, each by a full
+ * traversal of its bottom-level BVH (root box test in object space first)
+ * with the shared distance bound, before the top-level stack is popped.
+ * ====================================================================== */
+
+typedef struct {
+    const float *verts;       /* [n_tris][3][3] object space */
+    uint32_t n_tris;
+    const orc_node *nodes;
+    const uint32_t *perm;
+} orc_blas;
+
+typedef struct {
+    uint32_t blas;
+    float m[12];              /* object_from_world, row-major 3x4 */
+} orc_inst;
+
+/* float64 definition: every instance, every triangle (object-space test of
+ * the object-space ray, computed in float64 from the float32 inputs). */
+int orc_brute_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst *inst,
+                        uint32_t n_inst, const float *rays, uint32_t n_rays, int kind,
+                        const orc_isect *is, double *t_out, uint32_t *prim_out,
+                        uint32_t *inst_out, double *u_out, double *v_out, uint8_t *flags)
+{
+    if (kind == ORC_ALPHA) return -1;
+    for (uint32_t i = 0; i < n_rays; ++i) {
+        const float *r = rays + 8 * (size_t)i;
+        double tmin = r[3], tmax = r[7];
+        double t1 = INFINITY, t2 = INFINITY, u1 = 0, v1 = 0, bt1 = 0;
+        uint32_t p1 = ORC_MISS, q1 = ORC_MISS;
+        uint8_t fl = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            double reach = (p1 != ORC_MISS) ? t1 + 1e-6 * fabs(t1) + bt1 : tmax;
+            for (uint32_t j = 0; j < n_inst; ++j) {
+                const orc_inst *in = inst + j;
+                if (in->blas >= n_blas) return -2;
+                const orc_blas *b = blas + in->blas;
+                const float *m = in->m;
+                d3 o = {m[0] * (double)r[0] + m[1] * (double)r[1] + m[2] * (double)r[2] + m[3],
+                        m[4] * (double)r[0] + m[5] * (double)r[1] + m[6] * (double)r[2] + m[7],
+                        m[8] * (double)r[0] + m[9] * (double)r[1] + m[10] * (double)r[2] + m[11]};
+                d3 d = {m[0] * (double)r[4] + m[1] * (double)r[5] + m[2] * (double)r[6],
+                        m[4] * (double)r[4] + m[5] * (double)r[5] + m[6] * (double)r[6],
+                        m[8] * (double)r[4] + m[9] * (double)r[5] + m[10] * (double)r[6]};
+                for (uint32_t k = 0; k < b->n_tris; ++k) {
+                    double t, u, v, mg, bu, bt;
+                    if (!plane_hit64(o, d, b->verts + 9 * (size_t)k, &t, &u, &v, &mg, &bu, &bt)) continue;
+                    /* the object ray is a transformed float32 ray: widen the
+                     * float32 bounds by the transform's own rounding */
+                    bu = 2.0 * bu + 1e-6;
+                    bt = 2.0 * bt + 1e-6 * fabs(t);
+                    if (pass == 0) {
+                        if (!(mg >= 0.0) || !(t > tmin) || !(t < tmax)) continue;
+                        double fm;
+                        if (kind == ORC_PROCEDURAL && !checker_accept64(is, u, v, &fm)) continue;
+                        if (t < t1) { t2 = t1; t1 = t; u1 = u; v1 = v; p1 = k; q1 = j; bt1 = bt; }
+                        else if (t < t2) t2 = t;
+                    } else {
+                        if (!(t > tmin - bt) || !(t < tmax + bt) || !(t <= reach + bt)) continue;
+                        double delta = bu > 1e-6 ? bu : 1e-6;
+                        if (fabs(mg) < delta) fl |= ORC_E_NEAR_EDGE;
+                        if (mg > -delta && kind == ORC_PROCEDURAL) {
+                            double fm;
+                            checker_accept64(is, u, v, &fm);
+                            if (fm < 2.0 * delta * is->checker_n) fl |= ORC_E_NEAR_FILTER;
+                        }
+                        if (p1 != ORC_MISS && !(k == p1 && j == q1) && mg > -delta &&
+                            fabs(t - t1) <= bt + bt1)
+                            fl |= ORC_E_NEAR_TIE;
+                    }
+                }
+            }
+            if (pass == 0 && p1 != ORC_MISS && t2 - t1 < 1e-6 * fabs(t1)) fl |= ORC_E_NEAR_TIE;
+        }
+        t_out[i] = t1; u_out[i] = u1; v_out[i] = v1; prim_out[i] = p1; inst_out[i] = q1;
+        flags[i] = fl;
+    }
+    return 0;
+}
+
+/* float32 two-level traversal. */
+typedef struct {
+    const orc_blas *blas;
+    uint32_t n_blas;
+    const orc_inst *inst;
+    uint32_t n_inst;
+    const orc_node *tnodes;   /* top level, built over the instance boxes */
+    const uint32_t *tperm;    /* top-level leaf order -> instance index */
+    const float *rays;
+    uint32_t n_rays;
+    int kind;
+    orc_isect is;
+    int any_hit;
+    float *t, *u, *v;
+    uint32_t *prim, *inst_id;
+    uint32_t *counters;
+} inst_job;
+
+static void setup_ray(ray_state *rs, const float o[3], const float d[3])
+{
+    const float tiny = 0x1p-80f;
+    for (int a = 0; a < 3; ++a) {
+        rs->o[a] = o[a];
+        rs->d[a] = d[a];
+        float dd = d[a];
+        if (fabsf(dd) < tiny) dd = copysignf(tiny, dd);
+        rs->inv[a] = 1.0f / dd;
+        rs->ood[a] = o[a] * rs->inv[a];
+    }
+}
+
+/* One bottom-level traversal with the object ray in rs, on the stack above
+ * sp0 (left as found).  Returns 1 iff it accepted a hit. */
+static int blas_traverse(const inst_job *job, trav_job *tj, ray_state *rs, uint32_t inst_idx,
+                         uint32_t *stack_node, float *stack_tn, int sp0)
+{
+    const orc_blas *b = job->blas + job->inst[inst_idx].blas;
+    if (b->n_tris == 0) return 0;
+    tj->verts = b->verts;
+    tj->perm = b->perm;
+    tj->nodes = b->nodes;
+    float tn;
+    int sp = sp0;
+    uint32_t cur = 0;
+    int alive = box_test(rs, b->nodes[0].lo, b->nodes[0].hi, &tn);
+    const uint32_t acc_before = rs->n_acc;
+    while (alive && !rs->done) {
+        while (b->nodes[cur].count == 0) {
+            const orc_node *nd = &b->nodes[cur];
+            float tl, tr;
+            int hl = box_test(rs, b->nodes[nd->left].lo, b->nodes[nd->left].hi, &tl);
+            int hr = box_test(rs, b->nodes[nd->right].lo, b->nodes[nd->right].hi, &tr);
+            if (hl && hr) {
+                if (tr < tl) { cur = nd->right; stack_node[sp] = nd->left; stack_tn[sp] = tl; }
+                else { cur = nd->left; stack_node[sp] = nd->right; stack_tn[sp] = tr; }
+                ++sp;
+            } else if (hl) {
+                cur = nd->left;
+            } else if (hr) {
+                cur = nd->right;
+            } else {
+                alive = 0;
+                while (sp > sp0) {
+                    --sp;
+                    if (!(stack_tn[sp] > rs->tmax_cur)) { cur = stack_node[sp]; alive = 1; break; }
+                }
+                if (!alive) break;
+            }
+        }
+        if (!alive) break;
+        const orc_node *lf = &b->nodes[cur];
+        for (uint32_t j = lf->first; j < lf->first + lf->count && !rs->done; ++j)
+            tri_test(tj, rs, j);
+        if (rs->done) break;
+        alive = 0;
+        while (sp > sp0) {
+            --sp;
+            if (!(stack_tn[sp] > rs->tmax_cur)) { cur = stack_node[sp]; alive = 1; break; }
+        }
+    }
+    return rs->n_acc != acc_before;
+}
+
+static void inst_one(const inst_job *job, uint32_t i)
+{
+    const float *r = job->rays + (size_t)i * 8;
+    ray_state ws;   /* world ray */
+    memset(&ws, 0, sizeof ws);
+    setup_ray(&ws, r, r + 4);
+    ws.tmin = r[3];
+    ws.tmax_cur = r[7];
+    ws.prim = ORC_MISS;
+    ws.t = INFINITY;
+    trav_job tj;
+    memset(&tj, 0, sizeof tj);
+    tj.kind = job->kind;
+    tj.is = job->is;
+    tj.any_hit = job->any_hit;
+    uint32_t inst_hit = ORC_MISS;
+    uint32_t stack_node[256];
+    float stack_tn[256];
+    int sp = 0;
+    if (job->n_inst > 0) {
+        float tn;
+        uint32_t cur = 0;
+        int alive = box_test(&ws, job->tnodes[0].lo, job->tnodes[0].hi, &tn);
+        while (alive && !ws.done) {
+            while (job->tnodes[cur].count == 0) {
+                const orc_node *nd = &job->tnodes[cur];
+                float tl, tr;
+                int hl = box_test(&ws, job->tnodes[nd->left].lo, job->tnodes[nd->left].hi, &tl);
+                int hr = box_test(&ws, job->tnodes[nd->right].lo, job->tnodes[nd->right].hi, &tr);
+                if (hl && hr) {
+                    if (tr < tl) { cur = nd->right; stack_node[sp] = nd->left; stack_tn[sp] = tl; }
+                    else { cur = nd->left; stack_node[sp] = nd->right; stack_tn[sp] = tr; }
+                    ++sp;
+                } else if (hl) {
+                    cur = nd->left;
+                } else if (hr) {
+                    cur = nd->right;
+                } else {
+                    alive = 0;
+                    while (sp > 0) {
+                        --sp;
+                        if (!(stack_tn[sp] > ws.tmax_cur)) { cur = stack_node[sp]; alive = 1; break; }
+                    }
+                    if (!alive) break;
+                }
+            }
+            if (!alive) break;
+            const orc_node *lf = &job->tnodes[cur];
+            for (uint32_t j = lf->first; j < lf->first + lf->count && !ws.done; ++j) {
+                uint32_t q = job->tperm[j];
+                const float *m = job->inst[q].m;
+                float o[3], d[3];
+                for (int a = 0; a < 3; ++a) {
+                    o[a] = fmaf(m[4 * a + 0], r[0], fmaf(m[4 * a + 1], r[1], fmaf(m[4 * a + 2], r[2], m[4 * a + 3])));
+                    d[a] = fmaf(m[4 * a + 0], r[4], fmaf(m[4 * a + 1], r[5], m[4 * a + 2] * r[6]));
+                }
+                ray_state os = ws;      /* shares the distance bound and record */
+                setup_ray(&os, o, d);
+                if (blas_traverse(job, &tj, &os, q, stack_node, stack_tn, sp)) inst_hit = q;
+                /* carry back what the object ray changed */
+                ws.tmax_cur = os.tmax_cur; ws.prim = os.prim; ws.t = os.t; ws.u = os.u; ws.v = os.v;
+                ws.done = os.done;
+                ws.n_box = os.n_box; ws.n_tri = os.n_tri; ws.n_cand = os.n_cand; ws.n_acc = os.n_acc;
+            }
+            if (ws.done) break;
+            alive = 0;
+            while (sp > 0) {
+                --sp;
+                if (!(stack_tn[sp] > ws.tmax_cur)) { cur = stack_node[sp]; alive = 1; break; }
+            }
+        }
+    }
+    if (ws.prim == ORC_MISS) { ws.t = INFINITY; ws.u = 0.0f; ws.v = 0.0f; inst_hit = ORC_MISS; }
+    job->t[i] = ws.t; job->u[i] = ws.u; job->v[i] = ws.v;
+    job->prim[i] = ws.prim; job->inst_id[i] = inst_hit;
+    if (job->counters) {
+        uint32_t *c = job->counters + 4 * (size_t)i;
+        c[0] = ws.n_box; c[1] = ws.n_tri; c[2] = ws.n_cand; c[3] = ws.n_acc;
+    }
+}
+
+int orc_traverse_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst *inst,
+                           uint32_t n_inst, const orc_node *tnodes, const uint32_t *tperm,
+                           const float *rays, uint32_t n_rays, int kind, const orc_isect *is,
+                           int any_hit, float *t, uint32_t *prim, uint32_t *inst_id, float *u,
+                           float *v, uint32_t *counters)
+{
+    if (kind == ORC_ALPHA) return -1;
+    for (uint32_t q = 0; q < n_inst; ++q)
+        if (inst[q].blas >= n_blas) return -2;
+    inst_job job;
+    memset(&job, 0, sizeof job);
+    job.blas = blas; job.n_blas = n_blas; job.inst = inst; job.n_inst = n_inst;
+    job.tnodes = tnodes; job.tperm = tperm; job.rays = rays; job.n_rays = n_rays;
+    job.kind = kind;
+    if (is) job.is = *is;
+    job.any_hit = any_hit;
+    job.t = t; job.u = u; job.v = v; job.prim = prim; job.inst_id = inst_id;
+    job.counters = counters;
+    for (uint32_t i = 0; i < n_rays; ++i) inst_one(&job, i);
+    return 0;
+}

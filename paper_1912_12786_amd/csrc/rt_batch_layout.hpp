@@ -1,0 +1,36 @@
+// Layout of the scene table of a batched launch, shared by the host packer
+// (C ABI) and the traversal kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rtx {
+
+// -------------------------------------------------------------------------
+// batched launches: a device table of scenes, each owning a consecutive range
+// of the batch's rays
+//   [0, 64)                      header: n_scenes
+//   [64, 64 + 4 (n_scenes + 1))  ray_begin prefix (uint32), padded to 64 B
+//   then n_scenes records of 128 B (batch_scene below)
+// -------------------------------------------------------------------------
+struct alignas(16) batch_scene {
+    const float4 *nodes;
+    const float4 *tris;
+    const float2 *texcoords;    // alpha-mask data of this scene (may be null)
+    const uint32_t *textures;
+    float root_lo[3], root_hi[3];
+    uint32_t root_ref, n_tris;
+    uint32_t tex_width, tex_height, alpha_min;
+    uint32_t pad[11];
+};
+static_assert(sizeof(batch_scene) == 128, "batch scene record");
+
+__host__ __device__ constexpr size_t batch_prefix_offset() { return 64; }
+__host__ __device__ constexpr size_t batch_records_offset(uint32_t n_scenes)
+{
+    return 64 + (size_t(n_scenes + 1) * 4 + 63) / 64 * 64;
+}
+
+}  // namespace rtx

@@ -65,6 +65,8 @@ struct TraceRequest {
     void *n_hits;       // multi-hit: uint32_t* kept hits per ray
     uint32_t multi_k;   // multi-hit: hits kept per ray (1..RT_MAX_MULTI)
     void *counters;     // rt_counters* or null
+    const void *batch;  // batched launch: device scene table (closest query), else null
+    uint32_t runtime_dispatch;  // 0: compile-time intersector; 1: runtime switch; 2: indirect call
     void *spill;        // workspace past the queue head
     void *queue;        // queue head (queue shapes)
     LaunchShape shape;

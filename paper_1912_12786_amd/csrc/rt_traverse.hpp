@@ -29,6 +29,8 @@
 
 #include <type_traits>
 
+#include "rt_batch_layout.hpp"
+
 namespace rtx {
 
 // -------------------------------------------------------------------------
@@ -424,6 +426,22 @@ __device__ __forceinline__ bool root_step(const scene_view &sc, const ray_state 
                 sc.root_hi[2], tn);
 }
 
+// Index of the scene whose ray range holds ray `id` (binary search over the
+// ray_begin prefix; empty scenes are skipped naturally).
+__device__ __forceinline__ uint32_t batch_scene_of(const uint32_t *prefix, uint32_t n_scenes,
+                                                   uint32_t id)
+{
+    uint32_t lo = 0, hi = n_scenes;  // invariant: prefix[lo] <= id < prefix[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (prefix[mid] <= id)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // -------------------------------------------------------------------------
 // the traversal kernel
 // -------------------------------------------------------------------------
@@ -435,6 +453,7 @@ struct kernel_args {
     uint32_t *n_hits;    // multi-hit: kept hits per ray
     uint32_t multi_k;    // multi-hit: hits kept per ray
     uint4 *counters;
+    const unsigned char *batch;  // batched launch: the scene table (else null)
     uint64_t *spill;     // [spill entries][gridDim.x * kBlock]
     uint32_t *queue;     // kQueueHeads work-queue heads, kQueueStride apart, zero at launch
 };
@@ -470,7 +489,28 @@ __device__ __forceinline__ void write_result(const kernel_args &a, uint32_t ray,
     }
 }
 
-template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue>
+// Per-ray intersector parameters of a batched launch: the alpha mask takes
+// its texture data from the ray's scene record, other intersectors use the
+// launch's parameters.
+template <class Isect>
+__device__ __forceinline__ typename Isect::params batch_params(const typename Isect::params &p,
+                                                               const batch_scene &bs)
+{
+    if constexpr (std::is_base_of_v<alpha_intersector, Isect>) {
+        typename Isect::params q = p;
+        q.texcoords = bs.texcoords;
+        q.textures = bs.textures;
+        q.width = bs.tex_width;
+        q.height = bs.tex_height;
+        q.alpha_min = bs.alpha_min;
+        return q;
+    } else {
+        return p;
+    }
+}
+
+template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue,
+          bool kBatched = false>
 __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename Isect::params p)
 {
     static_assert(kBlock % 64 == 0 && kChunk % 32 == 0, "wave64 shapes");
@@ -508,6 +548,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
     bool active = false;
     uint32_t ray_id = 0, cur = 0;
     ray_state r{};
+    scene_view sc = a.sc;  // per lane in a batched launch
     Isect isect(p);
     Result res;
     res.reset(r, a.multi_k);
@@ -545,11 +586,30 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
             if (!active && id < end) {
                 ray_id = id;
                 r = make_ray(a.rays[2 * size_t(id)], a.rays[2 * size_t(id) + 1]);
-                isect = Isect(p);
+                if constexpr (kBatched) {
+                    const uint32_t n_scenes = *reinterpret_cast<const uint32_t *>(a.batch);
+                    const uint32_t *prefix =
+                        reinterpret_cast<const uint32_t *>(a.batch + batch_prefix_offset());
+                    const batch_scene &bs = reinterpret_cast<const batch_scene *>(
+                        a.batch + batch_records_offset(n_scenes))[batch_scene_of(prefix, n_scenes, id)];
+                    sc.nodes = bs.nodes;
+                    sc.tris = bs.tris;
+                    sc.root_lo[0] = bs.root_lo[0];
+                    sc.root_lo[1] = bs.root_lo[1];
+                    sc.root_lo[2] = bs.root_lo[2];
+                    sc.root_hi[0] = bs.root_hi[0];
+                    sc.root_hi[1] = bs.root_hi[1];
+                    sc.root_hi[2] = bs.root_hi[2];
+                    sc.root_ref = bs.root_ref;
+                    sc.n_tris = bs.n_tris;
+                    isect = Isect(batch_params<Isect>(p, bs));
+                } else {
+                    isect = Isect(p);
+                }
                 st.reset();
                 res.reset(r, a.multi_k);
-                cur = a.sc.root_ref;
-                active = root_step(a.sc, r, isect);
+                cur = sc.root_ref;
+                active = root_step(sc, r, isect);
                 if (!active) finish();
             }
         }
@@ -559,13 +619,13 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
         }
         if (active) {
             while (ref_count(cur) == 0) {
-                if (!inner_step(a.sc, r, isect, st, cur)) {
+                if (!inner_step(sc, r, isect, st, cur)) {
                     active = false;
                     break;
                 }
             }
             if (active) {
-                if (leaf_step(a.sc, r, isect, cur, res))
+                if (leaf_step(sc, r, isect, cur, res))
                     active = false;
                 else
                     active = st.pop(r.tmax, cur);
@@ -577,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
 
 // Zeroes the work-queue heads before a kQueue launch (a kernel rather than a
 // memset, so that the pair can be captured in a graph).
-__global__ void reset_queue_kernel(uint32_t *queue)
+static __global__ void reset_queue_kernel(uint32_t *queue)
 {
     if (threadIdx.x < kQueueHeads) queue[threadIdx.x * kQueueStride] = 0;
 }

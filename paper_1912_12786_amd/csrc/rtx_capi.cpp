@@ -6,6 +6,7 @@
 #include <string>
 
 #include "rt_internal.hpp"
+#include "rt_batch_layout.hpp"
 
 using namespace rtx;
 
@@ -45,6 +46,21 @@ rt_status check_scene(const rt_scene *sc)
     return RT_OK;
 }
 
+rt_status check_alpha(const rt_scene *sc, const rt_alpha_params &p)
+{
+    if (!p.texcoords || !p.textures) return fail(RT_ERR_INVALID_ARG, "alpha texcoords/textures are NULL");
+    if (!aligned(p.texcoords, 8)) return fail(RT_ERR_MISALIGNED, "alpha texcoords not 8-byte aligned");
+    if (!aligned(p.textures, 4)) return fail(RT_ERR_MISALIGNED, "alpha textures not 4-byte aligned");
+    if (p.n_texcoord_prims < sc->info.n_tris)
+        return fail(RT_ERR_INVALID_ARG, "alpha texcoords cover fewer triangles than the scene");
+    if (sc->info.n_tris > 0 && p.n_tex <= sc->info.max_geom_id)
+        return fail(RT_ERR_INVALID_ARG, "alpha n_tex must exceed the scene's max geom_id");
+    if (p.width < 1 || p.height < 1 || p.width > (1u << 24) || p.height > (1u << 24))
+        return fail(RT_ERR_INVALID_ARG, "alpha texture size must be within 1..2^24");
+    if (p.alpha_min > 255) return fail(RT_ERR_INVALID_ARG, "alpha_min must be 0..255");
+    return RT_OK;
+}
+
 rt_status check_params(const rt_scene *sc, rt_isect_kind kind, const void *params, TraceRequest &q)
 {
     q.kind = kind;
@@ -56,16 +72,8 @@ rt_status check_params(const rt_scene *sc, rt_isect_kind kind, const void *param
     case RT_ISECT_ALPHA: {
         if (!params) return fail(RT_ERR_INVALID_ARG, "alpha intersector needs rt_alpha_params");
         const rt_alpha_params &p = *static_cast<const rt_alpha_params *>(params);
-        if (!p.texcoords || !p.textures) return fail(RT_ERR_INVALID_ARG, "alpha texcoords/textures are NULL");
-        if (!aligned(p.texcoords, 8)) return fail(RT_ERR_MISALIGNED, "alpha texcoords not 8-byte aligned");
-        if (!aligned(p.textures, 4)) return fail(RT_ERR_MISALIGNED, "alpha textures not 4-byte aligned");
-        if (p.n_texcoord_prims < sc->info.n_tris)
-            return fail(RT_ERR_INVALID_ARG, "alpha texcoords cover fewer triangles than the scene");
-        if (sc->info.n_tris > 0 && p.n_tex <= sc->info.max_geom_id)
-            return fail(RT_ERR_INVALID_ARG, "alpha n_tex must exceed the scene's max geom_id");
-        if (p.width < 1 || p.height < 1 || p.width > (1u << 24) || p.height > (1u << 24))
-            return fail(RT_ERR_INVALID_ARG, "alpha texture size must be within 1..2^24");
-        if (p.alpha_min > 255) return fail(RT_ERR_INVALID_ARG, "alpha_min must be 0..255");
+        const rt_status st = check_alpha(sc, p);
+        if (st != RT_OK) return st;
         q.alpha = p;
         return RT_OK;
     }
@@ -91,15 +99,32 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
                        rt_isect_kind kind, const void *params, uint32_t flags, void *out,
                        size_t out_align, rt_counters *counters, void *workspace,
                        size_t workspace_bytes, void *stream, uint32_t multi_k = 0,
-                       uint32_t *n_hits = nullptr)
+                       uint32_t *n_hits = nullptr, const void *batch = nullptr)
 {
     g_last_error.clear();
     rt_status st = check_scene(scene);
     if (st != RT_OK) return st;
-    if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    if (flags & ~(RT_FLAG_COUNT | RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL))
+        return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    const uint32_t runtime = flags & (RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL);
+    if (runtime) {
+        if (runtime == (RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL))
+            return fail(RT_ERR_INVALID_ARG, "choose one runtime dispatch flag");
+        if (query != Query::Closest || batch || (flags & RT_FLAG_COUNT))
+            return fail(RT_ERR_UNSUPPORTED,
+                        "runtime dispatch is compiled for the plain closest-hit query only");
+    }
     TraceRequest q;
-    st = check_params(scene, kind, params, q);
-    if (st != RT_OK) return st;
+    q.runtime_dispatch = runtime == RT_FLAG_RUNTIME_SWITCH ? 1u : (runtime ? 2u : 0u);
+    if (batch) {  // per-scene data was validated by rt_batch_pack
+        q.kind = kind;
+        std::memset(&q.alpha, 0, sizeof q.alpha);
+        q.checker.checker_n =
+            kind == RT_ISECT_PROCEDURAL ? static_cast<const rt_procedural_params *>(params)->checker_n : 0;
+    } else {
+        st = check_params(scene, kind, params, q);
+        if (st != RT_OK) return st;
+    }
     if (query == Query::Multi && (multi_k < 1 || multi_k > RT_MAX_MULTI))
         return fail(RT_ERR_INVALID_ARG, "multi-hit k must be within 1..RT_MAX_MULTI");
     if (n_rays == 0) return RT_OK;
@@ -129,6 +154,7 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     q.n_hits = n_hits;
     q.multi_k = query == Query::Multi ? multi_k : 1;
     q.counters = count ? counters : nullptr;
+    q.batch = batch;
     q.queue = shape.queue ? workspace : nullptr;
     q.spill = shape.queue ? static_cast<char *>(workspace) + kQueueBytes : workspace;
     q.shape = shape;
@@ -202,6 +228,110 @@ rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
 {
     return trace_common(Query::Any, scene, rays, n_rays, kind, params, flags, occluder, 4,
                         counters, workspace, workspace_bytes, stream);
+}
+
+rt_status rt_batch_table_bytes(uint32_t n_scenes, size_t *bytes)
+{
+    g_last_error.clear();
+    if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
+    if (n_scenes == 0 || n_scenes > (1u << 24)) return fail(RT_ERR_INVALID_ARG, "n_scenes must be 1..2^24");
+    *bytes = batch_records_offset(n_scenes) + size_t(n_scenes) * sizeof(batch_scene);
+    return RT_OK;
+}
+
+rt_status rt_batch_pack(const rt_batch_entry *entries, uint32_t n_scenes, rt_isect_kind kind,
+                        void *host_table, size_t table_bytes, rt_batch_info *info)
+{
+    g_last_error.clear();
+    size_t need = 0;
+    rt_status st = rt_batch_table_bytes(n_scenes, &need);
+    if (st != RT_OK) return st;
+    if (!entries || !host_table || !info) return fail(RT_ERR_INVALID_ARG, "entries/table/info are NULL");
+    if (table_bytes < need) return fail(RT_ERR_INVALID_ARG, "table smaller than rt_batch_table_bytes");
+    if (!aligned(host_table, 16)) return fail(RT_ERR_MISALIGNED, "table not 16-byte aligned");
+    if (kind != RT_ISECT_DEFAULT && kind != RT_ISECT_ALPHA && kind != RT_ISECT_PROCEDURAL)
+        return fail(RT_ERR_UNSUPPORTED, "unknown intersector kind");
+    unsigned char *t = static_cast<unsigned char *>(host_table);
+    std::memset(t, 0, need);
+    uint32_t *header = reinterpret_cast<uint32_t *>(t);
+    uint32_t *prefix = reinterpret_cast<uint32_t *>(t + batch_prefix_offset());
+    batch_scene *rec = reinterpret_cast<batch_scene *>(t + batch_records_offset(n_scenes));
+    header[0] = n_scenes;
+    uint64_t total = 0;
+    uint32_t depth = 0;
+    for (uint32_t s = 0; s < n_scenes; ++s) {
+        const rt_batch_entry &e = entries[s];
+        st = check_scene(&e.scene);
+        if (st != RT_OK) return fail(st, "scene " + std::to_string(s) + ": " + g_last_error);
+        if (kind == RT_ISECT_ALPHA) {
+            st = check_alpha(&e.scene, e.alpha);
+            if (st != RT_OK) return fail(st, "scene " + std::to_string(s) + ": " + g_last_error);
+        }
+        prefix[s] = uint32_t(total);
+        total += e.n_rays;
+        if (total > RT_MAX_RAYS) return fail(RT_ERR_INVALID_ARG, "more than 2^31 rays in one batch");
+        const rt_bvh_info &in = e.scene.info;
+        batch_scene &r = rec[s];
+        r.nodes = static_cast<const float4 *>(e.scene.nodes);
+        r.tris = static_cast<const float4 *>(e.scene.tris);
+        r.texcoords = reinterpret_cast<const float2 *>(e.alpha.texcoords);
+        r.textures = e.alpha.textures;
+        for (int a = 0; a < 3; ++a) {
+            r.root_lo[a] = in.root_lo[a];
+            r.root_hi[a] = in.root_hi[a];
+        }
+        r.root_ref = in.root_ref;
+        r.n_tris = in.n_tris;
+        r.tex_width = e.alpha.width;
+        r.tex_height = e.alpha.height;
+        r.alpha_min = e.alpha.alpha_min;
+        depth = in.max_depth > depth ? in.max_depth : depth;
+    }
+    prefix[n_scenes] = uint32_t(total);
+    info->n_scenes = n_scenes;
+    info->n_rays = uint32_t(total);
+    info->max_depth = depth;
+    info->kind = uint32_t(kind);
+    return RT_OK;
+}
+
+rt_status rt_trace_batch_workspace_bytes(const rt_batch_info *info, uint32_t flags, size_t *bytes)
+{
+    g_last_error.clear();
+    if (!info || !bytes) return fail(RT_ERR_INVALID_ARG, "info/bytes are NULL");
+    if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    rt_bvh_info bi{};
+    bi.max_depth = info->max_depth;
+    *bytes = workspace_for(bi, info->n_rays, kShapes[g_shape_index.load()]);
+    return RT_OK;
+}
+
+rt_status rt_trace_batch(const void *table, const rt_batch_info *info, const rt_ray *rays,
+                         rt_isect_kind kind, const void *params, uint32_t flags, rt_hit *hits,
+                         rt_counters *counters, void *workspace, size_t workspace_bytes,
+                         void *stream)
+{
+    g_last_error.clear();
+    if (!info) return fail(RT_ERR_INVALID_ARG, "info is NULL");
+    if (!table) return fail(RT_ERR_INVALID_ARG, "table is NULL");
+    if (!aligned(table, 16)) return fail(RT_ERR_MISALIGNED, "table not 16-byte aligned");
+    if (uint32_t(kind) != info->kind)
+        return fail(RT_ERR_INVALID_ARG, "kind differs from the kind the table was packed for");
+    if (info->max_depth >= 128) return fail(RT_ERR_INVALID_ARG, "batch max_depth must be < 128");
+    if (kind == RT_ISECT_ALPHA && params)
+        return fail(RT_ERR_INVALID_ARG, "a batched alpha launch takes its data from the table");
+    if (kind == RT_ISECT_PROCEDURAL) {
+        if (!params) return fail(RT_ERR_INVALID_ARG, "procedural intersector needs rt_procedural_params");
+        const uint32_t n = static_cast<const rt_procedural_params *>(params)->checker_n;
+        if (n < 1 || n > 65536) return fail(RT_ERR_INVALID_ARG, "checker_n must be within 1..65536");
+    } else if (kind != RT_ISECT_DEFAULT && kind != RT_ISECT_ALPHA) {
+        return fail(RT_ERR_UNSUPPORTED, "unknown intersector kind");
+    }
+    // a stand-in scene carries the batch-wide sizes through the common checks
+    rt_scene proxy{};
+    proxy.info.max_depth = info->max_depth;
+    return trace_common(Query::Closest, &proxy, rays, info->n_rays, kind, params, flags, hits, 16,
+                        counters, workspace, workspace_bytes, stream, 0, nullptr, table);
 }
 
 rt_status rt_trace_multi(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,

@@ -19,6 +19,58 @@
 
 namespace rtx {
 
+// -------------------------------------------------------------------------
+// Runtime-dispatched intersectors: the same three decisions selected per
+// candidate at run time, as a library linked without templates must do
+// (Section 1: a runtime check whether a filter was registered, then a call).
+// They exist to measure what compile-time injection saves; results are
+// bit-identical to the compile-time intersectors.
+// -------------------------------------------------------------------------
+struct runtime_params {
+    alpha_intersector::params alpha;
+    uint32_t checker_n;
+    uint32_t kind;  // rt_isect_kind
+};
+
+// (a) a runtime switch over inlined filter code
+struct runtime_switch_intersector : intersector_base {
+    static constexpr bool kFilters = true;
+    using params = runtime_params;
+    runtime_params p;
+    __device__ explicit runtime_switch_intersector(const params &pp) : p(pp) {}
+    __device__ __forceinline__ bool accept(const hit_candidate &c)
+    {
+        if (p.kind == RT_ISECT_ALPHA) return alpha_intersector(p.alpha).accept(c);
+        if (p.kind == RT_ISECT_PROCEDURAL)
+            return checker_intersector(checker_intersector::params{p.checker_n}).accept(c);
+        return true;
+    }
+};
+
+// (b) an indirect call through a table of filter functions
+typedef bool (*accept_fn)(hit_candidate, runtime_params);
+__device__ __noinline__ bool accept_all_fn(hit_candidate, runtime_params) { return true; }
+__device__ __noinline__ bool accept_alpha_fn(hit_candidate c, runtime_params p)
+{
+    return alpha_intersector(p.alpha).accept(c);
+}
+__device__ __noinline__ bool accept_checker_fn(hit_candidate c, runtime_params p)
+{
+    return checker_intersector(checker_intersector::params{p.checker_n}).accept(c);
+}
+__device__ accept_fn g_accept_table[3] = {accept_all_fn, accept_alpha_fn, accept_checker_fn};
+
+struct runtime_call_intersector : intersector_base {
+    static constexpr bool kFilters = true;
+    using params = runtime_params;
+    runtime_params p;
+    __device__ explicit runtime_call_intersector(const params &pp) : p(pp) {}
+    __device__ __forceinline__ bool accept(const hit_candidate &c)
+    {
+        return g_accept_table[p.kind < 3 ? p.kind : 0](c, p);
+    }
+};
+
 // (block, LDS ring slots, rays per chunk, global queue); the first is the default
 const LaunchShape kShapes[] = {{64, 8, 64, 1}, {64, 8, 64, 0}, {64, 16, 64, 1}, {256, 8, 64, 1}};
 const uint32_t kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
@@ -49,12 +101,13 @@ uint32_t resident_blocks(Kernel kernel, uint32_t block, const char **err)
     return cache[dev].load(std::memory_order_relaxed);
 }
 
-template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue>
+template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue,
+          bool kBatched = false>
 rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipStream_t s,
                      const char **err)
 {
     const LaunchShape sh{kBlock, kSlots, kChunk, kQueue};
-    auto kernel = trace_kernel<Isect, Result, kSlots, kBlock, kChunk, kQueue>;
+    auto kernel = trace_kernel<Isect, Result, kSlots, kBlock, kChunk, kQueue, kBatched>;
     // the workspace is sized for launch_threads(); a queue grid is further
     // trimmed to the waves that can be resident at once
     uint32_t grid = uint32_t(launch_threads(a.n_rays, sh) / kBlock);
@@ -78,6 +131,13 @@ rt_status dispatch_query(const TraceRequest &q, const kernel_args &a,
                          const typename Isect::params &p, const char **err)
 {
     hipStream_t s = static_cast<hipStream_t>(q.stream);
+    if (q.batch) {
+        if (q.query != Query::Closest) {
+            *err = "batched launches support the closest-hit query only";
+            return RT_ERR_UNSUPPORTED;
+        }
+        return launch_one<Isect, closest_result, kSlots, kBlock, kChunk, kQueue, true>(a, p, s, err);
+    }
     switch (q.query) {
     case Query::Any:
         return launch_one<Isect, any_result, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
@@ -102,6 +162,22 @@ rt_status dispatch_count(const TraceRequest &q, const kernel_args &a,
 template <int kSlots, int kBlock, int kChunk, bool kQueue>
 rt_status dispatch_kind(const TraceRequest &q, const kernel_args &a, const char **err)
 {
+    if (q.runtime_dispatch) {
+        runtime_params rp;
+        rp.alpha.texcoords = reinterpret_cast<const float2 *>(q.alpha.texcoords);
+        rp.alpha.textures = q.alpha.textures;
+        rp.alpha.width = q.alpha.width;
+        rp.alpha.height = q.alpha.height;
+        rp.alpha.alpha_min = q.alpha.alpha_min;
+        rp.checker_n = q.checker.checker_n;
+        rp.kind = uint32_t(q.kind);
+        hipStream_t s = static_cast<hipStream_t>(q.stream);
+        if (q.runtime_dispatch == 1)
+            return launch_one<runtime_switch_intersector, closest_result, kSlots, kBlock, kChunk,
+                              kQueue>(a, rp, s, err);
+        return launch_one<runtime_call_intersector, closest_result, kSlots, kBlock, kChunk, kQueue>(
+            a, rp, s, err);
+    }
     switch (q.kind) {
     case RT_ISECT_DEFAULT:
         return dispatch_count<default_intersector, kSlots, kBlock, kChunk, kQueue>(
@@ -145,6 +221,7 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
     a.n_hits = static_cast<uint32_t *>(q.n_hits);
     a.multi_k = q.multi_k;
     a.counters = static_cast<uint4 *>(q.counters);
+    a.batch = static_cast<const unsigned char *>(q.batch);
     a.spill = static_cast<uint64_t *>(q.spill);
     a.queue = static_cast<uint32_t *>(q.queue);
 

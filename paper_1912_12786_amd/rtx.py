@@ -23,6 +23,8 @@ LIB_PATH = os.path.join(_HERE, "librtx.so")
 RT_OK = 0
 RT_MISS = 0xFFFFFFFF
 RT_FLAG_COUNT = 1
+RT_FLAG_RUNTIME_SWITCH = 2
+RT_FLAG_RUNTIME_CALL = 4
 RT_NODE_BYTES = 64
 RT_TRI_BYTES = 48
 KINDS = {"default": 0, "alpha": 1, "procedural": 2}
@@ -54,6 +56,15 @@ class rt_scene(C.Structure):
     _fields_ = [("nodes", C.c_void_p), ("tris", C.c_void_p), ("info", rt_bvh_info)]
 
 
+class rt_batch_entry(C.Structure):
+    _fields_ = [("scene", rt_scene), ("n_rays", C.c_uint32), ("alpha", rt_alpha_params)]
+
+
+class rt_batch_info(C.Structure):
+    _fields_ = [("n_scenes", C.c_uint32), ("n_rays", C.c_uint32), ("max_depth", C.c_uint32),
+                ("kind", C.c_uint32)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every entry point declared in include/rtx.h
@@ -66,6 +77,11 @@ SIGNATURES = [
                                    _SZ, _P]),
     ("rt_trace_any", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                _SZ, _P]),
+    ("rt_batch_table_bytes", C.c_int, [_U32, C.POINTER(_SZ)]),
+    ("rt_batch_pack", C.c_int, [_P, _U32, C.c_int, _P, _SZ, C.POINTER(rt_batch_info)]),
+    ("rt_trace_batch_workspace_bytes", C.c_int, [C.POINTER(rt_batch_info), _U32, C.POINTER(_SZ)]),
+    ("rt_trace_batch", C.c_int, [_P, C.POINTER(rt_batch_info), _P, C.c_int, _P, _U32, _P, _P, _P,
+                                 _SZ, _P]),
     ("rt_trace_multi", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _U32, _P, _P,
                                  _P, _P, _SZ, _P]),
     ("rt_hit_backward", C.c_int, [_P, _P, _P, _U32, _P, _U32, _P, _U32, _P, _P, _P]),
@@ -165,6 +181,41 @@ def rt_trace_any(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params,
                             None if params is None else C.cast(C.pointer(params), C.c_void_p),
                             flags, occluder_ptr, counters_ptr, workspace_ptr, workspace_bytes,
                             stream), "rt_trace_any")
+
+
+def rt_batch_table_bytes(n_scenes: int) -> int:
+    b = C.c_size_t()
+    _check(load_library().rt_batch_table_bytes(n_scenes, C.byref(b)), "rt_batch_table_bytes")
+    return b.value
+
+
+def rt_batch_pack(entries, kind: int):
+    """Packs rt_batch_entry structures into a host table.  Returns
+    (table uint8 array, rt_batch_info)."""
+    n = len(entries)
+    arr = (rt_batch_entry * n)(*entries)
+    nbytes = rt_batch_table_bytes(n)
+    table = np.zeros((nbytes + 15) // 16, dtype=np.dtype((np.void, 16)))
+    info = rt_batch_info()
+    _check(load_library().rt_batch_pack(C.cast(arr, C.c_void_p), n, kind, table.ctypes.data,
+                                        nbytes, C.byref(info)), "rt_batch_pack")
+    return table.view(np.uint8)[:nbytes], info
+
+
+def rt_trace_batch_workspace_bytes(info: rt_batch_info, flags: int = 0) -> int:
+    b = C.c_size_t()
+    _check(load_library().rt_trace_batch_workspace_bytes(C.byref(info), flags, C.byref(b)),
+           "rt_trace_batch_workspace_bytes")
+    return b.value
+
+
+def rt_trace_batch(table_ptr: int, info: rt_batch_info, rays_ptr: int, kind: int, params,
+                   flags: int, hits_ptr: int, counters_ptr: int | None, workspace_ptr: int | None,
+                   workspace_bytes: int, stream: int | None):
+    _check(load_library().rt_trace_batch(
+        table_ptr, C.byref(info), rays_ptr, kind,
+        None if params is None else C.cast(C.pointer(params), C.c_void_p), flags, hits_ptr,
+        counters_ptr, workspace_ptr, workspace_bytes, stream), "rt_trace_batch")
 
 
 def rt_trace_multi(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params, flags: int,
@@ -331,3 +382,50 @@ def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "clo
                        out.data_ptr(), n_hits.data_ptr(), cptr, wptr, wbytes, s)
         out = (out, n_hits)
     return (out, counters) if count else out
+
+
+class Batch:
+    """Scenes with their ray counts, packed into a device scene table
+    (rt_batch_pack + one host-to-device copy made here, by torch)."""
+
+    def __init__(self, scenes, n_rays, intersector: str = "default", alpha_min: int = 128,
+                 device="cuda"):
+        torch = _torch()
+        self.scenes = list(scenes)
+        self.kind = KINDS[intersector]
+        self.intersector = intersector
+        entries = []
+        for sc, n in zip(self.scenes, n_rays):
+            e = rt_batch_entry()
+            e.scene = sc.view
+            e.n_rays = int(n)
+            if intersector == "alpha":
+                e.alpha = sc.alpha_params(alpha_min)
+            entries.append(e)
+        table, self.info = rt_batch_pack(entries, self.kind)
+        self.table = torch.from_numpy(table.copy()).to(device)
+        self.offsets = np.concatenate([[0], np.cumsum(np.asarray(n_rays, np.int64))])
+
+    def trace(self, rays, *, count=False, checker_n: int = 8, out=None, counters=None,
+              workspace: Workspace | None = None, stream=None):
+        """Closest hits of all rays (scene order) in one launch."""
+        torch = _torch()
+        n = int(self.info.n_rays)
+        if rays.shape != (n, 8) or rays.dtype != torch.float32 or not rays.is_contiguous():
+            raise ValueError(f"rays must be a contiguous float32 [{n}, 8] tensor")
+        dev = rays.device
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        flags = RT_FLAG_COUNT if count else 0
+        if count and counters is None:
+            counters = torch.empty((n, 4), dtype=torch.int32, device=dev)
+        params = None
+        if self.intersector == "procedural":
+            params = rt_procedural_params()
+            params.checker_n = int(checker_n)
+        ws = workspace or Workspace(dev)
+        wptr, wbytes = ws.get(rt_trace_batch_workspace_bytes(self.info, flags))
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        rt_trace_batch(self.table.data_ptr(), self.info, rays.data_ptr(), self.kind, params, flags,
+                       out.data_ptr(), counters.data_ptr() if count else None, wptr, wbytes, s)
+        return (out, counters) if count else out

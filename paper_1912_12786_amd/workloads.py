@@ -471,3 +471,110 @@ def diff_scene(freq: int = 50, n_billboards: int = 5000, width: int = 512, heigh
     w = rng_for(CFG_DIFF, STREAM_WEIGHTS).uniform(-1.0, 1.0, size=(rays.shape[0], 3)).astype(np.float32)
     return MeshWorkload(f"diff_icosphere_{n_sphere}_plus_{2 * n_billboards}_billboard_tris_{width}x{height}",
                         verts, faces, rays, geom, tc, textures, w, n_tex)
+
+
+# --------------------------------------------------------------------------
+# batched multi-scene workload
+# --------------------------------------------------------------------------
+def incoherent_rays(n: int, seed: int, box=(0.0, 100.0)) -> np.ndarray:
+    """Bounce-like rays: origins uniform in the box, directions uniform on the
+    sphere (a stand-in for diffuse secondary rays of any scene type)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    o = rng.uniform(box[0], box[1], size=(n, 3))
+    d = _random_unit(rng, n)
+    rays = np.empty((n, 8), np.float32)
+    rays[:, 0:3] = o.astype(np.float32)
+    rays[:, 3] = 0.0
+    rays[:, 4:7] = d.astype(np.float32)
+    rays[:, 7] = np.inf
+    return rays
+
+
+def batched(n_scenes: int = 64, tri_range=(1_000, 500_000), ray_range=(4_000, 2_000_000),
+            width: int = 1920):
+    """Scenes of uneven size, each with its own ray batch.
+
+    Triangle and ray counts are log-uniform in the given ranges; the scene
+    type cycles through random triangles (rescaled to [0, 100]^3), camera
+    facing billboards and tessellated spheres.  Half of each ray batch is
+    primary rays of a 1920-wide camera (rows truncated to the count), half
+    incoherent rays.  Returns a list of dicts with ``vertices`` and ``rays``."""
+    g = rng_for(CFG_BATCHED, STREAM_GEOMETRY)
+    n_t = np.exp(g.uniform(math.log(tri_range[0]), math.log(tri_range[1]), size=n_scenes))
+    n_r = np.exp(g.uniform(math.log(ray_range[0]), math.log(ray_range[1]), size=n_scenes))
+    out = []
+    for s in range(n_scenes):
+        seed = seed_for(CFG_BATCHED, 100 + s)
+        kind = s % 3
+        nt = int(n_t[s])
+        if kind == 0:
+            v = random_triangles(nt, seed, side=5.0, box=(0.0, 100.0))
+        elif kind == 1:
+            v, _, _ = billboard_quads(max(1, nt // 2), seed, BILLBOARD_EYE)
+        else:
+            v, _, _ = sphere_scene(max(1, nt // 500), seed)
+        nr = int(n_r[s])
+        n_prim = nr // 2
+        height = max(1, -(-n_prim // width))
+        prim = pinhole_rays(width, height, BILLBOARD_EYE, BILLBOARD_CENTER, 60.0)[:n_prim]
+        rays = np.concatenate([prim, incoherent_rays(nr - n_prim, seed + 1)], 0)
+        out.append({"vertices": v, "rays": rays, "type": ("triangles", "billboards", "spheres")[kind]})
+    return out
+
+
+# --------------------------------------------------------------------------
+# instanced scenes
+# --------------------------------------------------------------------------
+def _rotation(rng: np.random.Generator) -> np.ndarray:
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def instance_transforms(world_from_object: np.ndarray, blas_lo: np.ndarray, blas_hi: np.ndarray):
+    """For row-major 3x4 world-from-object maps (float64 [n, 3, 4]) and each
+    instance's object-space box: the object-from-world maps rounded to float32
+    ([n, 12]) and world boxes (float32) that contain the instance under that
+    rounded map -- the 8 transformed corners, padded outward by 1e-5 of the
+    extent."""
+    n = world_from_object.shape[0]
+    L = world_from_object[:, :, :3]
+    T = world_from_object[:, :, 3]
+    Linv = np.linalg.inv(L)
+    ofw = np.concatenate([Linv, -np.einsum("nij,nj->ni", Linv, T)[..., None]], axis=2)
+    corners = np.stack(np.meshgrid([0, 1], [0, 1], [0, 1], indexing="ij"), -1).reshape(8, 3)
+    c = blas_lo[:, None, :] + corners[None] * (blas_hi - blas_lo)[:, None, :]      # [n, 8, 3]
+    w = np.einsum("nij,nkj->nki", L, c) + T[:, None, :]
+    lo, hi = w.min(1), w.max(1)
+    pad = 1e-5 * (hi - lo).max(1, keepdims=True) + 1e-6
+    lo32 = np.nextafter((lo - pad).astype(np.float32), np.float32(-np.inf))
+    hi32 = np.nextafter((hi + pad).astype(np.float32), np.float32(np.inf))
+    return ofw.reshape(n, 12).astype(np.float32), lo32, hi32
+
+
+def instanced(n_instances: int = 2000, width: int = 1920, height: int = 1080):
+    """Object instancing: three meshes (a 500-triangle sphere, 500 random
+    triangles, 50 billboard quads) instanced n_instances times with random
+    rotations, scales in [0.5, 3] and positions uniform in [0, 100]^3, seen by
+    the billboard camera.  Returns dict with blas vertex lists, per-instance
+    blas ids, object-from-world maps, world boxes and rays."""
+    g = rng_for(CFG_BATCHED, 900)
+    blas = [uv_sphere(np.zeros(3), 1.0).astype(np.float32),
+            random_triangles(500, seed_for(CFG_BATCHED, 901), side=0.3, box=(-1.0, 1.0)),
+            billboard_quads(50, seed_for(CFG_BATCHED, 902), (0.0, 0.0, -10.0),
+                            box=(-1.0, 1.0), side=(0.2, 0.6))[0]]
+    ids = g.integers(0, len(blas), size=n_instances).astype(np.uint32)
+    wfo = np.empty((n_instances, 3, 4))
+    for i in range(n_instances):
+        wfo[i, :, :3] = _rotation(g) * g.uniform(0.5, 3.0)
+        wfo[i, :, 3] = g.uniform(0.0, 100.0, size=3)
+    blo = np.stack([b.reshape(-1, 3).min(0) for b in blas]).astype(np.float64)[ids]
+    bhi = np.stack([b.reshape(-1, 3).max(0) for b in blas]).astype(np.float64)[ids]
+    m, lo, hi = instance_transforms(wfo, blo, bhi)
+    rays = pinhole_rays(width, height, BILLBOARD_EYE, BILLBOARD_CENTER, 60.0)
+    return {"blas": blas, "inst_blas": ids, "inst_m": m, "world_lo": lo, "world_hi": hi,
+            "rays": rays, "world_from_object": wfo,
+            "name": f"instanced_{n_instances}_x3_meshes_{width}x{height}"}

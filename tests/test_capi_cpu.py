@@ -63,7 +63,8 @@ def test_struct_layout_matches_header(tmp_path):
 #define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
 int main(void) {
   S(rt_ray) S(rt_hit) S(rt_counters) S(rt_alpha_params) S(rt_procedural_params)
-  S(rt_bvh_info) S(rt_scene)
+  S(rt_bvh_info) S(rt_scene) S(rt_batch_entry) S(rt_batch_info)
+  O(rt_batch_entry, n_rays) O(rt_batch_entry, alpha) O(rt_batch_info, max_depth)
   O(rt_alpha_params, textures) O(rt_alpha_params, n_texcoord_prims) O(rt_alpha_params, alpha_min)
   O(rt_bvh_info, root_ref) O(rt_bvh_info, root_lo) O(rt_bvh_info, root_hi)
   O(rt_scene, tris) O(rt_scene, info)
@@ -81,7 +82,8 @@ int main(void) {
     assert got["rt_hit.prim_id"] == 4 and got["rt_ray.dx"] == 16
     for name, cls in (("rt_alpha_params", rtx.rt_alpha_params),
                       ("rt_procedural_params", rtx.rt_procedural_params),
-                      ("rt_bvh_info", rtx.rt_bvh_info), ("rt_scene", rtx.rt_scene)):
+                      ("rt_bvh_info", rtx.rt_bvh_info), ("rt_scene", rtx.rt_scene),
+                      ("rt_batch_entry", rtx.rt_batch_entry), ("rt_batch_info", rtx.rt_batch_info)):
         assert got[name] == C.sizeof(cls), name
         for field, *_ in cls._fields_:
             key = f"{name}.{field}"
@@ -244,7 +246,11 @@ def test_validation_errors(lib):
     assert _closest(lib, sc, hits=None) == -1
     assert _closest(lib, sc, hits=0x40008) == -2
     assert _closest(lib, sc, kind=7) == -3
-    assert _closest(lib, sc, flags=2) == -3
+    assert _closest(lib, sc, flags=8) == -3                          # unknown flag
+    assert _closest(lib, sc, flags=6) == -1                          # two runtime modes
+    assert _closest(lib, sc, flags=3, counters=0x50000) == -3        # runtime + counting
+    assert lib.rt_trace_any(C.byref(sc), 0x30000, 100, 0, None, 2, 0x40000, None, None, 0,
+                            None) == -3                              # runtime + any-hit
     assert _closest(lib, sc, flags=rtx.RT_FLAG_COUNT) == -1          # counters missing
     assert _closest(lib, sc, flags=rtx.RT_FLAG_COUNT, counters=0x50004) == -2
     assert _closest(lib, sc, kind=1) == -1                           # alpha params missing
@@ -282,6 +288,48 @@ def test_multi_validation(lib):
     # n_hits is required
     assert lib.rt_trace_multi(C.byref(sc), 0x30000, 100, 0, None, 0, 4, 0x40000, None,
                               None, None, 0, None) == -1
+
+
+def test_batch_pack_layout_and_validation(lib):
+    scenes = [_fake_scene(n_tris=10, max_depth=3), _fake_scene(n_tris=0, n_nodes=0),
+              _fake_scene(n_tris=20, n_nodes=5, max_depth=7)]
+    counts = [100, 0, 37]
+    entries = []
+    for i, (sc, n) in enumerate(zip(scenes, counts)):
+        e = rtx.rt_batch_entry()
+        e.scene = sc
+        e.scene.nodes = 0x10000 * (i + 1)
+        e.scene.info.root_lo[:] = [i, i, i]
+        e.n_rays = n
+        entries.append(e)
+    table, info = rtx.rt_batch_pack(entries, 0)
+    assert (info.n_scenes, info.n_rays, info.max_depth, info.kind) == (3, 137, 7, 0)
+    assert len(table) == rtx.rt_batch_table_bytes(3)
+    u32 = table.view(np.uint32)
+    assert u32[0] == 3
+    assert u32[16:20].tolist() == [0, 100, 100, 137]          # ray prefix at byte 64
+    rec = table[128:].view(np.uint64).reshape(3, 16)            # 128-B records at byte 128
+    assert rec[:, 0].tolist() == [0x10000, 0x20000, 0x30000]
+    recf = table[128:].view(np.float32).reshape(3, 32)
+    assert recf[2, 8:11].tolist() == [2, 2, 2]                  # root_lo
+    # an invalid scene is reported with its index
+    bad = rtx.rt_batch_entry()
+    bad.scene = _fake_scene(n_nodes=0)
+    with pytest.raises(rtx.RtxError, match="scene 1"):
+        rtx.rt_batch_pack([entries[0], bad], 0)
+    # alpha batches validate every entry's alpha data
+    with pytest.raises(rtx.RtxError, match="scene 0"):
+        rtx.rt_batch_pack([entries[0]], 1)
+    ok = rtx.rt_batch_entry()
+    ok.scene = _fake_scene()
+    ok.alpha = rtx.rt_alpha_params(0x60000, 0x70000, 10, 1, 4, 4, 128)
+    t2, i2 = rtx.rt_batch_pack([ok], 1)
+    assert i2.kind == 1
+    # trace_batch checks the kind against the packed table
+    assert lib.rt_trace_batch(0x1000, C.byref(i2), 0x30000, 0, None, 0, 0x40000, None, None, 0,
+                              None) == -1
+    assert lib.rt_trace_batch(None, C.byref(i2), 0x30000, 1, None, 0, 0x40000, None, None, 0,
+                              None) == -1
 
 
 def test_zero_rays_is_a_no_op(lib):
