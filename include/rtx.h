@@ -237,6 +237,54 @@ rt_status rt_trace_batch(const void *table, const rt_batch_info *info, const rt_
                          rt_counters *counters, void *workspace, size_t workspace_bytes,
                          void *stream);
 
+/* ---------------------------------------------------------------------
+ * Instancing (Section 3.2: a BVH may be a primitive of another BVH; object
+ * instancing).  A top-level BVH is built over instances; an instance is a
+ * bottom-level scene (from rt_bvh_build) seen through an affine map.  At a
+ * top-level leaf every instance in stored order is entered with the object
+ * ray o' = M o + m, d' = M d (float32: o'_i = fma(M_i0, o_x, fma(M_i1, o_y,
+ * fma(M_i2, o_z, m_i))), d'_i = fma(M_i0, d_x, fma(M_i1, d_y, M_i2 d_z))),
+ * which leaves t and the barycentrics of a hit unchanged.
+ * --------------------------------------------------------------------- */
+typedef struct rt_instance {
+    uint32_t blas;                 /* index of the bottom-level scene */
+    float object_from_world[12];   /* row-major 3x4 [M | m] */
+    float world_lo[3], world_hi[3];/* a world box containing the instance under
+                                      that map (the caller's responsibility) */
+} rt_instance;
+
+/* Host build of the top-level BVH over the instances' world boxes (same
+ * construction as rt_bvh_build; buffer sizes from rt_bvh_buffer_bytes(n_inst));
+ * its leaf records carry instance indices as prim_id. */
+rt_status rt_tlas_build(const rt_instance *instances, uint32_t n_inst, void *nodes,
+                        size_t node_cap, void *tris, size_t tri_cap, rt_bvh_info *info);
+
+/* Bytes of the packed instance table. */
+rt_status rt_instance_table_bytes(uint32_t n_blas, uint32_t n_inst, size_t *bytes);
+
+/* Validates the bottom-level scenes and instances and writes the table into
+ * host_table (host, 16-byte aligned); *max_blas_depth receives the deepest
+ * bottom-level BVH.  The caller copies the table to device memory. */
+rt_status rt_instance_pack(const rt_scene *blas, uint32_t n_blas, const rt_instance *instances,
+                           uint32_t n_inst, void *host_table, size_t table_bytes,
+                           uint32_t *max_blas_depth);
+
+/* Workspace of rt_trace_instanced. */
+rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, uint32_t max_blas_depth,
+                                             uint32_t n_rays, uint32_t flags, size_t *bytes);
+
+/* Closest-hit (any_hit = 0: out is rt_hit[n_rays], prim_id relative to the
+ * hit instance's scene) or any-hit (any_hit = 1: out is uint32[n_rays])
+ * query over an instanced scene.  tlas: from rt_tlas_build over the same
+ * instances as the device table; inst_ids (device, may be NULL) receives the
+ * hit instance or RT_MISS.  RT_ISECT_DEFAULT or RT_ISECT_PROCEDURAL;
+ * RT_FLAG_COUNT counts the box tests of both levels and the triangle tests. */
+rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, uint32_t max_blas_depth,
+                             const rt_ray *rays, uint32_t n_rays, rt_isect_kind kind,
+                             const void *params, uint32_t flags, int any_hit, void *out,
+                             uint32_t *inst_ids, rt_counters *counters, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
 /* Multi-hit query (Section 3.1: "the first N hit points", read as the k
  * nearest hits the intersector accepts, in increasing t; a hit with the same
  * t as a kept one goes after it).  Once k hits are kept, the k-th distance

@@ -33,4 +33,32 @@ __host__ __device__ constexpr size_t batch_records_offset(uint32_t n_scenes)
     return 64 + (size_t(n_scenes + 1) * 4 + 63) / 64 * 64;
 }
 
+// -------------------------------------------------------------------------
+// instanced launches: a device table of bottom-level BVHs and instances
+//   [0, 64)                        header: n_blas, n_inst
+//   [64, 64 + 64 n_blas)           blas records (64 B)
+//   then n_inst instance records (64 B)
+// -------------------------------------------------------------------------
+struct alignas(16) blas_record {
+    const float4 *nodes;
+    const float4 *tris;
+    float root_lo[3], root_hi[3];
+    uint32_t root_ref, n_tris;
+    uint32_t pad[2];
+};
+static_assert(sizeof(blas_record) == 64, "blas record");
+
+struct alignas(16) instance_record {
+    uint32_t blas;
+    uint32_t pad[3];
+    float m[12];  // object_from_world, row-major 3x4
+};
+static_assert(sizeof(instance_record) == 64, "instance record");
+
+__host__ __device__ constexpr size_t instance_blas_offset() { return 64; }
+__host__ __device__ constexpr size_t instance_records_offset(uint32_t n_blas)
+{
+    return 64 + size_t(n_blas) * sizeof(blas_record);
+}
+
 }  // namespace rtx

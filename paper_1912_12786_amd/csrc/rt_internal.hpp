@@ -95,6 +95,25 @@ inline uint64_t launch_threads(uint32_t n_rays, const LaunchShape &s)
 // Enqueues one traversal kernel; returns RT_OK or RT_ERR_HIP.
 rt_status launch_trace(const TraceRequest &req, const char **err);
 
+struct InstancedRequest {
+    const rt_scene *tlas;
+    const void *table;     // device instance table
+    const void *rays;
+    uint32_t n_rays;
+    rt_isect_kind kind;
+    rt_procedural_params checker;
+    bool count, any;
+    void *out;             // rt_hit* or uint32_t* (any)
+    uint32_t *inst_ids;    // may be null
+    void *counters;
+    void *spill;
+    void *stream;
+};
+
+// Instanced traversal: one ray per lane, LDS ring of kInstancedSlots.
+constexpr uint32_t kInstancedSlots = 8;
+rt_status launch_instanced(const InstancedRequest &req, const char **err);
+
 struct BackwardRequest {
     const void *rays;
     const void *hits;

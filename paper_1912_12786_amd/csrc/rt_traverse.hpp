@@ -226,8 +226,14 @@ struct ring_stack {
     global_ptr<uint64_t> spill;  // this lane's column: entry i at spill[i * stride]
     uint32_t tid, stride;
     uint32_t sp = 0, base = 0;
+    uint32_t floor = 0;  // pops stop here (a nested traversal owns [floor, sp))
 
-    __device__ __forceinline__ void reset() { sp = 0; base = 0; }
+    __device__ __forceinline__ void reset()
+    {
+        sp = 0;
+        base = 0;
+        floor = 0;
+    }
 
     // Writes e into the free slot; keeps it iff `keep`.
     __device__ __forceinline__ void push_if(bool keep, uint2 e)
@@ -245,7 +251,7 @@ struct ring_stack {
     // Pops until an entry with tn <= tmax appears; false when empty.
     __device__ __forceinline__ bool pop(float tmax, uint32_t &ref)
     {
-        while (sp > 0) {
+        while (sp > floor) {
             --sp;
             uint2 e;
             if (sp >= base) {
@@ -471,6 +477,12 @@ constexpr uint32_t kQueueStride = 32;  // uint32 words
 // behind the slowest ray of the wave.  Each ray's own traversal (Algorithm 1:
 // descend inner nodes, then test the leaf's triangles, until the stack is
 // empty) is exactly what it would be alone.
+template <class Result>  // closest_result or any_result
+__device__ __forceinline__ bool res_hit(const Result &res)
+{
+    return res.prim != kMissPrim;
+}
+
 template <class Result>
 __device__ __forceinline__ void write_result(const kernel_args &a, uint32_t ray, const Result &res)
 {
@@ -633,6 +645,119 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
             if (!active) finish();
         }
     }
+}
+
+// -------------------------------------------------------------------------
+// instancing (Section 3.2: BVHs as primitives of a top-level BVH)
+// -------------------------------------------------------------------------
+// World ray -> object ray of an instance with object_from_world map m
+// (row-major 3x4); t and the barycentrics of a hit are unchanged.
+__device__ __forceinline__ ray_state object_ray(const ray_state &w, const float m[12])
+{
+    float4 o, d;
+    o.x = fmaf(m[0], w.ox, fmaf(m[1], w.oy, fmaf(m[2], w.oz, m[3])));
+    o.y = fmaf(m[4], w.ox, fmaf(m[5], w.oy, fmaf(m[6], w.oz, m[7])));
+    o.z = fmaf(m[8], w.ox, fmaf(m[9], w.oy, fmaf(m[10], w.oz, m[11])));
+    o.w = w.tmin;
+    d.x = fmaf(m[0], w.dx, fmaf(m[1], w.dy, m[2] * w.dz));
+    d.y = fmaf(m[4], w.dx, fmaf(m[5], w.dy, m[6] * w.dz));
+    d.z = fmaf(m[8], w.dx, fmaf(m[9], w.dy, m[10] * w.dz));
+    d.w = w.tmax;
+    return make_ray(o, d);
+}
+
+// One ray per lane.  The top-level BVH (built over the instances' world
+// boxes; its leaf records carry instance indices) is walked like any BVH; at
+// a top-level leaf each instance in stored order is entered by a full
+// traversal of its bottom-level BVH with the object ray, on the same stack
+// above a floor, sharing the distance bound; then the top level resumes.
+template <class Isect, class Result, int kSlots>
+__global__ __launch_bounds__(64) void trace_instanced_kernel(kernel_args a, const unsigned char *table,
+                                                             uint32_t *inst_out,
+                                                             typename Isect::params p)
+{
+    __shared__ uint2 ring[kSlots][64];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t i = blockIdx.x * 64 + tid;
+    if (i >= a.n_rays) return;
+    ring_stack<kSlots, 64> st{ring, (global_ptr<uint64_t>)(a.spill + i), tid, gridDim.x * 64u};
+    ray_state rw = make_ray(a.rays[2 * size_t(i)], a.rays[2 * size_t(i) + 1]);
+    Isect isect(p);
+    Result res;
+    res.reset(rw, 1);
+    uint32_t inst_hit = kMissPrim;
+    const uint32_t n_blas = reinterpret_cast<const uint32_t *>(table)[0];
+    const uint32_t n_inst = reinterpret_cast<const uint32_t *>(table)[1];
+    const blas_record *blas = reinterpret_cast<const blas_record *>(table + instance_blas_offset());
+    const instance_record *inst =
+        reinterpret_cast<const instance_record *>(table + instance_records_offset(n_blas));
+    const scene_view &tl = a.sc;
+    bool done = false;
+    uint32_t cur = tl.root_ref;
+    bool alive = root_step(tl, rw, isect);
+    while (alive && !done) {
+        while (ref_count(cur) == 0) {
+            if (!inner_step(tl, rw, isect, st, cur)) {
+                alive = false;
+                break;
+            }
+        }
+        if (!alive) break;
+        const uint32_t first = ref_index(cur), count = ref_count(cur);
+        for (uint32_t j = first; j < first + count && !done; ++j) {
+            const uint32_t q = __float_as_uint(tl.tris[3 * size_t(j)].w);
+            if (q >= n_inst) continue;
+            const instance_record &ir = inst[q];
+            const uint32_t b = ir.blas;
+            if (b >= n_blas) continue;
+            float m[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) m[k] = ir.m[k];
+            ray_state ro = object_ray(rw, m);
+            const blas_record &br = blas[b];
+            scene_view bv;
+            bv.nodes = br.nodes;
+            bv.tris = br.tris;
+            bv.root_lo[0] = br.root_lo[0];
+            bv.root_lo[1] = br.root_lo[1];
+            bv.root_lo[2] = br.root_lo[2];
+            bv.root_hi[0] = br.root_hi[0];
+            bv.root_hi[1] = br.root_hi[1];
+            bv.root_hi[2] = br.root_hi[2];
+            bv.root_ref = br.root_ref;
+            bv.n_tris = br.n_tris;
+            const float t_before = ro.tmax;
+            st.floor = st.sp;
+            if (root_step(bv, ro, isect)) {
+                uint32_t c2 = bv.root_ref;
+                bool alive2 = true;
+                while (alive2) {
+                    while (ref_count(c2) == 0) {
+                        if (!inner_step(bv, ro, isect, st, c2)) {
+                            alive2 = false;
+                            break;
+                        }
+                    }
+                    if (!alive2) break;
+                    if (leaf_step(bv, ro, isect, c2, res)) {
+                        done = true;
+                        break;
+                    }
+                    alive2 = st.pop(ro.tmax, c2);
+                }
+            }
+            st.floor = 0;
+            if (done || ro.tmax != t_before) inst_hit = q;
+            rw.tmax = ro.tmax;
+        }
+        if (done) break;
+        alive = st.pop(rw.tmax, cur);
+    }
+    write_result(a, i, res);
+    if (inst_out) inst_out[i] = res_hit(res) ? inst_hit : kMissPrim;
+    if constexpr (Isect::kCounts)
+        a.counters[i] = make_uint4(isect.num_boxes, isect.num_tris, isect.num_candidates,
+                                   isect.num_accepted);
 }
 
 // Zeroes the work-queue heads before a kQueue launch (a kernel rather than a

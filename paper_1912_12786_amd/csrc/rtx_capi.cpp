@@ -1,6 +1,8 @@
 // C ABI of librtx: argument validation, workspace sizing and the single
 // host-side selection of the kernel instantiation per call.
 #include <atomic>
+#include <cmath>
+#include <vector>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -332,6 +334,162 @@ rt_status rt_trace_batch(const void *table, const rt_batch_info *info, const rt_
     proxy.info.max_depth = info->max_depth;
     return trace_common(Query::Closest, &proxy, rays, info->n_rays, kind, params, flags, hits, 16,
                         counters, workspace, workspace_bytes, stream, 0, nullptr, table);
+}
+
+rt_status rt_tlas_build(const rt_instance *instances, uint32_t n_inst, void *nodes,
+                        size_t node_cap, void *tris, size_t tri_cap, rt_bvh_info *info)
+{
+    g_last_error.clear();
+    if (n_inst > 0 && !instances) return fail(RT_ERR_INVALID_ARG, "instances are NULL");
+    if (n_inst > RT_MAX_TRIS) return fail(RT_ERR_INVALID_ARG, "more than 2^29-1 instances");
+    std::vector<float> boxes;
+    try {
+        boxes.resize(size_t(n_inst) * 9);
+    } catch (const std::bad_alloc &) {
+        return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+    for (uint32_t q = 0; q < n_inst; ++q) {
+        const rt_instance &in = instances[q];
+        for (int a = 0; a < 3; ++a) {
+            const float lo = in.world_lo[a], hi = in.world_hi[a];
+            if (!std::isfinite(lo) || !std::isfinite(hi) || lo > hi)
+                return fail(RT_ERR_INVALID_ARG, "instance " + std::to_string(q) + ": bad world box");
+            // the box as the degenerate triangle (lo, hi, hi)
+            boxes[9 * size_t(q) + a] = lo;
+            boxes[9 * size_t(q) + 3 + a] = hi;
+            boxes[9 * size_t(q) + 6 + a] = hi;
+        }
+    }
+    return rt_bvh_build(boxes.data(), nullptr, n_inst, nodes, node_cap, tris, tri_cap, info);
+}
+
+rt_status rt_instance_table_bytes(uint32_t n_blas, uint32_t n_inst, size_t *bytes)
+{
+    g_last_error.clear();
+    if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
+    if (n_blas > (1u << 24) || n_inst > RT_MAX_TRIS)
+        return fail(RT_ERR_INVALID_ARG, "too many bottom-level scenes or instances");
+    *bytes = instance_records_offset(n_blas) + size_t(n_inst) * sizeof(instance_record);
+    return RT_OK;
+}
+
+rt_status rt_instance_pack(const rt_scene *blas, uint32_t n_blas, const rt_instance *instances,
+                           uint32_t n_inst, void *host_table, size_t table_bytes,
+                           uint32_t *max_blas_depth)
+{
+    size_t need = 0;
+    rt_status st = rt_instance_table_bytes(n_blas, n_inst, &need);
+    if (st != RT_OK) return st;
+    if ((n_blas && !blas) || (n_inst && !instances) || !host_table || !max_blas_depth)
+        return fail(RT_ERR_INVALID_ARG, "blas/instances/table/max_blas_depth are NULL");
+    if (table_bytes < need) return fail(RT_ERR_INVALID_ARG, "table smaller than rt_instance_table_bytes");
+    if (!aligned(host_table, 16)) return fail(RT_ERR_MISALIGNED, "table not 16-byte aligned");
+    unsigned char *t = static_cast<unsigned char *>(host_table);
+    std::memset(t, 0, need);
+    uint32_t *hdr = reinterpret_cast<uint32_t *>(t);
+    hdr[0] = n_blas;
+    hdr[1] = n_inst;
+    blas_record *br = reinterpret_cast<blas_record *>(t + instance_blas_offset());
+    instance_record *ir = reinterpret_cast<instance_record *>(t + instance_records_offset(n_blas));
+    uint32_t depth = 0;
+    for (uint32_t b = 0; b < n_blas; ++b) {
+        st = check_scene(&blas[b]);
+        if (st != RT_OK) return fail(st, "bottom-level scene " + std::to_string(b) + ": " + g_last_error);
+        const rt_bvh_info &in = blas[b].info;
+        br[b].nodes = static_cast<const float4 *>(blas[b].nodes);
+        br[b].tris = static_cast<const float4 *>(blas[b].tris);
+        for (int a = 0; a < 3; ++a) {
+            br[b].root_lo[a] = in.root_lo[a];
+            br[b].root_hi[a] = in.root_hi[a];
+        }
+        br[b].root_ref = in.root_ref;
+        br[b].n_tris = in.n_tris;
+        depth = in.max_depth > depth ? in.max_depth : depth;
+    }
+    for (uint32_t q = 0; q < n_inst; ++q) {
+        if (instances[q].blas >= n_blas)
+            return fail(RT_ERR_INVALID_ARG, "instance " + std::to_string(q) + ": blas out of range");
+        ir[q].blas = instances[q].blas;
+        for (int k = 0; k < 12; ++k) {
+            if (!std::isfinite(instances[q].object_from_world[k]))
+                return fail(RT_ERR_INVALID_ARG, "instance " + std::to_string(q) + ": non-finite map");
+            ir[q].m[k] = instances[q].object_from_world[k];
+        }
+    }
+    *max_blas_depth = depth;
+    g_last_error.clear();
+    return RT_OK;
+}
+
+static size_t instanced_workspace(const rt_bvh_info &tlas, uint32_t max_blas_depth, uint32_t n_rays)
+{
+    const uint32_t depth = tlas.max_depth + max_blas_depth;
+    const uint32_t cap = kInstancedSlots - 1;
+    const size_t threads = (size_t(n_rays) + 63) / 64 * 64;
+    return size_t(depth > cap ? depth - cap : 0) * threads * sizeof(uint64_t);
+}
+
+rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, uint32_t max_blas_depth,
+                                             uint32_t n_rays, uint32_t flags, size_t *bytes)
+{
+    g_last_error.clear();
+    if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
+    rt_status st = check_scene(tlas);
+    if (st != RT_OK) return st;
+    if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    if (max_blas_depth >= 128) return fail(RT_ERR_INVALID_ARG, "max_blas_depth must be < 128");
+    *bytes = instanced_workspace(tlas->info, max_blas_depth, n_rays);
+    return RT_OK;
+}
+
+rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, uint32_t max_blas_depth,
+                             const rt_ray *rays, uint32_t n_rays, rt_isect_kind kind,
+                             const void *params, uint32_t flags, int any_hit, void *out,
+                             uint32_t *inst_ids, rt_counters *counters, void *workspace,
+                             size_t workspace_bytes, void *stream)
+{
+    g_last_error.clear();
+    rt_status st = check_scene(tlas);
+    if (st != RT_OK) return st;
+    if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    if (max_blas_depth >= 128) return fail(RT_ERR_INVALID_ARG, "max_blas_depth must be < 128");
+    InstancedRequest q{};
+    q.kind = kind;
+    if (kind == RT_ISECT_PROCEDURAL) {
+        if (!params) return fail(RT_ERR_INVALID_ARG, "procedural intersector needs rt_procedural_params");
+        q.checker = *static_cast<const rt_procedural_params *>(params);
+        if (q.checker.checker_n < 1 || q.checker.checker_n > 65536)
+            return fail(RT_ERR_INVALID_ARG, "checker_n must be within 1..65536");
+    } else if (kind != RT_ISECT_DEFAULT) {
+        return fail(RT_ERR_UNSUPPORTED, "instanced traversal supports the default and procedural intersectors");
+    }
+    if (n_rays == 0) return RT_OK;
+    if (n_rays > RT_MAX_RAYS) return fail(RT_ERR_INVALID_ARG, "more than 2^31 rays in one call");
+    if (!table || !aligned(table, 16)) return fail(RT_ERR_INVALID_ARG, "table NULL or not 16-byte aligned");
+    if (!rays || !aligned(rays, 16)) return fail(RT_ERR_INVALID_ARG, "rays NULL or not 16-byte aligned");
+    if (!out || !aligned(out, any_hit ? 4 : 16)) return fail(RT_ERR_INVALID_ARG, "output NULL or misaligned");
+    if (inst_ids && !aligned(inst_ids, 4)) return fail(RT_ERR_MISALIGNED, "inst_ids not 4-byte aligned");
+    const bool count = (flags & RT_FLAG_COUNT) != 0;
+    if (count && (!counters || !aligned(counters, 16)))
+        return fail(RT_ERR_INVALID_ARG, "RT_FLAG_COUNT needs a 16-byte aligned counters array");
+    const size_t need = instanced_workspace(tlas->info, max_blas_depth, n_rays);
+    if (need > 0 && (!workspace || workspace_bytes < need || !aligned(workspace, 16)))
+        return fail(RT_ERR_WORKSPACE, "workspace smaller than rt_trace_instanced_workspace_bytes");
+    q.tlas = tlas;
+    q.table = table;
+    q.rays = rays;
+    q.n_rays = n_rays;
+    q.count = count;
+    q.any = any_hit != 0;
+    q.out = out;
+    q.inst_ids = inst_ids;
+    q.counters = count ? counters : nullptr;
+    q.spill = workspace;
+    q.stream = stream;
+    const char *err = "";
+    st = launch_instanced(q, &err);
+    if (st != RT_OK) return fail(st, err);
+    return RT_OK;
 }
 
 rt_status rt_trace_multi(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,

@@ -203,6 +203,73 @@ rt_status dispatch_kind(const TraceRequest &q, const kernel_args &a, const char 
 
 }  // namespace
 
+namespace {
+
+template <class Isect, class Result>
+rt_status launch_inst(const InstancedRequest &q, const kernel_args &a,
+                      const typename Isect::params &p, const char **err)
+{
+    const uint32_t grid = (q.n_rays + 63) / 64;
+    hipLaunchKernelGGL((trace_instanced_kernel<Isect, Result, kInstancedSlots>), dim3(grid), dim3(64),
+                       0, static_cast<hipStream_t>(q.stream), a,
+                       static_cast<const unsigned char *>(q.table), q.inst_ids, p);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        *err = hipGetErrorString(e);
+        return RT_ERR_HIP;
+    }
+    return RT_OK;
+}
+
+template <class Isect>
+rt_status launch_inst_query(const InstancedRequest &q, const kernel_args &a,
+                            const typename Isect::params &p, const char **err)
+{
+    if (q.any) return launch_inst<Isect, any_result>(q, a, p, err);
+    return launch_inst<Isect, closest_result>(q, a, p, err);
+}
+
+template <class Base>
+rt_status launch_inst_count(const InstancedRequest &q, const kernel_args &a,
+                            const typename Base::params &p, const char **err)
+{
+    if (q.count) return launch_inst_query<counting_intersector<Base>>(q, a, p, err);
+    return launch_inst_query<Base>(q, a, p, err);
+}
+
+}  // namespace
+
+rt_status launch_instanced(const InstancedRequest &q, const char **err)
+{
+    kernel_args a{};
+    const rt_bvh_info &info = q.tlas->info;
+    a.sc.nodes = static_cast<const float4 *>(q.tlas->nodes);
+    a.sc.tris = static_cast<const float4 *>(q.tlas->tris);
+    for (int k = 0; k < 3; ++k) {
+        a.sc.root_lo[k] = info.root_lo[k];
+        a.sc.root_hi[k] = info.root_hi[k];
+    }
+    a.sc.root_ref = info.root_ref;
+    a.sc.n_tris = info.n_tris;
+    a.rays = static_cast<const float4 *>(q.rays);
+    a.n_rays = q.n_rays;
+    a.out = q.out;
+    a.multi_k = 1;
+    a.counters = static_cast<uint4 *>(q.counters);
+    a.spill = static_cast<uint64_t *>(q.spill);
+    switch (q.kind) {
+    case RT_ISECT_DEFAULT:
+        return launch_inst_count<default_intersector>(q, a, default_intersector::params{}, err);
+    case RT_ISECT_PROCEDURAL:
+        return launch_inst_count<checker_intersector>(q, a, checker_intersector::params{q.checker.checker_n},
+                                                      err);
+    default:
+        break;
+    }
+    *err = "instanced traversal supports the default and procedural intersectors";
+    return RT_ERR_UNSUPPORTED;
+}
+
 rt_status launch_trace(const TraceRequest &q, const char **err)
 {
     kernel_args a;

@@ -56,6 +56,11 @@ class rt_scene(C.Structure):
     _fields_ = [("nodes", C.c_void_p), ("tris", C.c_void_p), ("info", rt_bvh_info)]
 
 
+class rt_instance(C.Structure):
+    _fields_ = [("blas", C.c_uint32), ("object_from_world", C.c_float * 12),
+                ("world_lo", C.c_float * 3), ("world_hi", C.c_float * 3)]
+
+
 class rt_batch_entry(C.Structure):
     _fields_ = [("scene", rt_scene), ("n_rays", C.c_uint32), ("alpha", rt_alpha_params)]
 
@@ -82,6 +87,13 @@ SIGNATURES = [
     ("rt_trace_batch_workspace_bytes", C.c_int, [C.POINTER(rt_batch_info), _U32, C.POINTER(_SZ)]),
     ("rt_trace_batch", C.c_int, [_P, C.POINTER(rt_batch_info), _P, C.c_int, _P, _U32, _P, _P, _P,
                                  _SZ, _P]),
+    ("rt_tlas_build", C.c_int, [_P, _U32, _P, _SZ, _P, _SZ, C.POINTER(rt_bvh_info)]),
+    ("rt_instance_table_bytes", C.c_int, [_U32, _U32, C.POINTER(_SZ)]),
+    ("rt_instance_pack", C.c_int, [_P, _U32, _P, _U32, _P, _SZ, C.POINTER(_U32)]),
+    ("rt_trace_instanced_workspace_bytes", C.c_int, [C.POINTER(rt_scene), _U32, _U32, _U32,
+                                                     C.POINTER(_SZ)]),
+    ("rt_trace_instanced", C.c_int, [C.POINTER(rt_scene), _P, _U32, _P, _U32, C.c_int, _P, _U32,
+                                     C.c_int, _P, _P, _P, _P, _SZ, _P]),
     ("rt_trace_multi", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _U32, _P, _P,
                                  _P, _P, _SZ, _P]),
     ("rt_hit_backward", C.c_int, [_P, _P, _P, _U32, _P, _U32, _P, _U32, _P, _P, _P]),
@@ -216,6 +228,106 @@ def rt_trace_batch(table_ptr: int, info: rt_batch_info, rays_ptr: int, kind: int
         table_ptr, C.byref(info), rays_ptr, kind,
         None if params is None else C.cast(C.pointer(params), C.c_void_p), flags, hits_ptr,
         counters_ptr, workspace_ptr, workspace_bytes, stream), "rt_trace_batch")
+
+
+def _instances(inst_blas, inst_m, world_lo, world_hi):
+    n = len(inst_blas)
+    arr = (rt_instance * max(1, n))()
+    m = np.ascontiguousarray(inst_m, np.float32).reshape(-1, 12)
+    lo = np.ascontiguousarray(world_lo, np.float32).reshape(-1, 3)
+    hi = np.ascontiguousarray(world_hi, np.float32).reshape(-1, 3)
+    for q in range(n):
+        arr[q].blas = int(inst_blas[q])
+        arr[q].object_from_world[:] = m[q].tolist()
+        arr[q].world_lo[:] = lo[q].tolist()
+        arr[q].world_hi[:] = hi[q].tolist()
+    return arr, n
+
+
+def rt_tlas_build(inst_blas, inst_m, world_lo, world_hi):
+    """Host build of the top-level BVH; returns (nodes, tris, info) like rt_bvh_build."""
+    arr, n = _instances(inst_blas, inst_m, world_lo, world_hi)
+    nb, tb = rt_bvh_buffer_bytes(n)
+    nodes = np.zeros(max(nb, 16) // 16, dtype=np.dtype((np.void, 16)))
+    tris = np.zeros(max(tb, 16) // 16, dtype=np.dtype((np.void, 16)))
+    info = rt_bvh_info()
+    _check(load_library().rt_tlas_build(C.cast(arr, C.c_void_p), n,
+                                        nodes.ctypes.data if nb else None, nb,
+                                        tris.ctypes.data if tb else None, tb, C.byref(info)),
+           "rt_tlas_build")
+    return nodes.view(np.uint8)[: info.n_nodes * RT_NODE_BYTES], tris.view(np.uint8)[: n * RT_TRI_BYTES], info
+
+
+def rt_instance_pack(blas_views, inst_blas, inst_m, world_lo, world_hi):
+    """Packs the instance table on the host; returns (table uint8, max_blas_depth)."""
+    lib = load_library()
+    arr, n = _instances(inst_blas, inst_m, world_lo, world_hi)
+    nb = len(blas_views)
+    scenes = (rt_scene * max(1, nb))(*blas_views)
+    b = C.c_size_t()
+    _check(lib.rt_instance_table_bytes(nb, n, C.byref(b)), "rt_instance_table_bytes")
+    table = np.zeros((b.value + 15) // 16, dtype=np.dtype((np.void, 16)))
+    depth = C.c_uint32()
+    _check(lib.rt_instance_pack(C.cast(scenes, C.c_void_p), nb, C.cast(arr, C.c_void_p), n,
+                                table.ctypes.data, b.value, C.byref(depth)), "rt_instance_pack")
+    return table.view(np.uint8)[: b.value], int(depth.value)
+
+
+class InstancedScene:
+    """Bottom-level scenes + instances: a device top-level BVH and table."""
+
+    def __init__(self, blas_vertices, inst_blas, inst_m, world_lo, world_hi, device="cuda"):
+        torch = _torch()
+        self.blas = [upload_scene(v, device=device) for v in blas_vertices]
+        nodes, tris, self.tlas_info = rt_tlas_build(inst_blas, inst_m, world_lo, world_hi)
+        self.tlas_nodes = torch.from_numpy(nodes.copy()).to(device) if nodes.size else None
+        self.tlas_tris = torch.from_numpy(tris.copy()).to(device)
+        table, self.max_blas_depth = rt_instance_pack([b.view for b in self.blas], inst_blas,
+                                                      inst_m, world_lo, world_hi)
+        self.table = torch.from_numpy(table.copy()).to(device)
+
+    @property
+    def tlas(self) -> rt_scene:
+        sc = rt_scene()
+        sc.nodes = self.tlas_nodes.data_ptr() if self.tlas_nodes is not None else None
+        sc.tris = self.tlas_tris.data_ptr() if self.tlas_tris.numel() else None
+        sc.info = self.tlas_info
+        return sc
+
+    def trace(self, rays, intersector="default", *, any_hit=False, count=False, checker_n=8,
+              out=None, inst_ids=None, workspace=None, stream=None):
+        """Returns (hits [N,4] float32 or occluders [N] int32, inst_ids [N] int32[,
+        counters])."""
+        torch = _torch()
+        n = int(rays.shape[0])
+        dev = rays.device
+        if out is None:
+            out = (torch.empty((n,), dtype=torch.int32, device=dev) if any_hit
+                   else torch.empty((n, 4), dtype=torch.float32, device=dev))
+        if inst_ids is None:
+            inst_ids = torch.empty((n,), dtype=torch.int32, device=dev)
+        counters = torch.empty((n, 4), dtype=torch.int32, device=dev) if count else None
+        params = None
+        if intersector == "procedural":
+            params = rt_procedural_params()
+            params.checker_n = int(checker_n)
+        elif intersector != "default":
+            raise ValueError("instancing supports the default and procedural intersectors")
+        flags = RT_FLAG_COUNT if count else 0
+        tl = self.tlas
+        lib = load_library()
+        b = C.c_size_t()
+        _check(lib.rt_trace_instanced_workspace_bytes(C.byref(tl), self.max_blas_depth, n, flags,
+                                                      C.byref(b)), "rt_trace_instanced_workspace_bytes")
+        ws = workspace or Workspace(dev)
+        wptr, wbytes = ws.get(b.value)
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        _check(lib.rt_trace_instanced(
+            C.byref(tl), self.table.data_ptr(), self.max_blas_depth, rays.data_ptr(), n,
+            KINDS[intersector], None if params is None else C.cast(C.pointer(params), C.c_void_p),
+            flags, int(bool(any_hit)), out.data_ptr(), inst_ids.data_ptr(),
+            counters.data_ptr() if count else None, wptr, wbytes, s), "rt_trace_instanced")
+        return (out, inst_ids, counters) if count else (out, inst_ids)
 
 
 def rt_trace_multi(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params, flags: int,

@@ -63,7 +63,8 @@ def test_struct_layout_matches_header(tmp_path):
 #define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
 int main(void) {
   S(rt_ray) S(rt_hit) S(rt_counters) S(rt_alpha_params) S(rt_procedural_params)
-  S(rt_bvh_info) S(rt_scene) S(rt_batch_entry) S(rt_batch_info)
+  S(rt_bvh_info) S(rt_scene) S(rt_batch_entry) S(rt_batch_info) S(rt_instance)
+  O(rt_instance, object_from_world) O(rt_instance, world_lo) O(rt_instance, world_hi)
   O(rt_batch_entry, n_rays) O(rt_batch_entry, alpha) O(rt_batch_info, max_depth)
   O(rt_alpha_params, textures) O(rt_alpha_params, n_texcoord_prims) O(rt_alpha_params, alpha_min)
   O(rt_bvh_info, root_ref) O(rt_bvh_info, root_lo) O(rt_bvh_info, root_hi)
@@ -83,7 +84,8 @@ int main(void) {
     for name, cls in (("rt_alpha_params", rtx.rt_alpha_params),
                       ("rt_procedural_params", rtx.rt_procedural_params),
                       ("rt_bvh_info", rtx.rt_bvh_info), ("rt_scene", rtx.rt_scene),
-                      ("rt_batch_entry", rtx.rt_batch_entry), ("rt_batch_info", rtx.rt_batch_info)):
+                      ("rt_batch_entry", rtx.rt_batch_entry), ("rt_batch_info", rtx.rt_batch_info),
+                      ("rt_instance", rtx.rt_instance)):
         assert got[name] == C.sizeof(cls), name
         for field, *_ in cls._fields_:
             key = f"{name}.{field}"
@@ -330,6 +332,40 @@ def test_batch_pack_layout_and_validation(lib):
                               None) == -1
     assert lib.rt_trace_batch(None, C.byref(i2), 0x30000, 1, None, 0, 0x40000, None, None, 0,
                               None) == -1
+
+
+def test_tlas_build_matches_oracle_box_tree(oracle_lib):
+    from paper_1912_12786_amd import workloads as W
+    wl = W.instanced(300, 8, 8)
+    nodes, tris, info = rtx.rt_tlas_build(wl["inst_blas"], wl["inst_m"], wl["world_lo"],
+                                          wl["world_hi"])
+    ob = oracle_lib.build_tlas(wl["world_lo"], wl["world_hi"])
+    prod = decode_product_bvh(nodes, tris, info)
+    orc = decode_oracle_bvh(ob)
+    assert len(prod) == len(orc)
+    for a, b in zip(prod, orc):
+        assert a[0] == b[0] and a[1] == b[1] and a[2:] == b[2:]
+    assert np.array_equal(tris.view(np.uint32).reshape(-1, 12)[:, 3], ob.perm)
+
+
+def test_instance_pack_validation(lib):
+    from paper_1912_12786_amd import workloads as W
+    wl = W.instanced(5, 8, 8)
+    blas = [_fake_scene(), _fake_scene(max_depth=9), _fake_scene(max_depth=4)]
+    table, depth = rtx.rt_instance_pack(blas, wl["inst_blas"], wl["inst_m"], wl["world_lo"],
+                                        wl["world_hi"])
+    assert depth == 9
+    u32 = table.view(np.uint32)
+    assert u32[0] == 3 and u32[1] == 5
+    rec = table[64 + 3 * 64:].view(np.float32).reshape(5, 16)
+    assert np.array_equal(rec[:, 4:], wl["inst_m"])
+    assert np.array_equal(table[64 + 3 * 64:].view(np.uint32).reshape(5, 16)[:, 0], wl["inst_blas"])
+    with pytest.raises(rtx.RtxError, match="blas out of range"):
+        rtx.rt_instance_pack(blas[:1], np.array([0, 1], np.uint32), wl["inst_m"][:2],
+                             wl["world_lo"][:2], wl["world_hi"][:2])
+    with pytest.raises(rtx.RtxError, match="bad world box"):
+        rtx.rt_tlas_build(np.zeros(1, np.uint32), wl["inst_m"][:1], wl["world_hi"][:1],
+                          wl["world_lo"][:1])
 
 
 def test_zero_rays_is_a_no_op(lib):
