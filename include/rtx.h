@@ -285,8 +285,8 @@ rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, uint32_t m
                              uint32_t *inst_ids, rt_counters *counters, void *workspace,
                              size_t workspace_bytes, void *stream);
 
-/* Multi-hit query (Section 3.1: "the first N hit points", read as the k
- * nearest hits the intersector accepts, in increasing t; a hit with the same
+/* Multi-hit query (Section 3.1 names a query returning several hit
+ * points; read here as the k nearest hits the intersector accepts, in increasing t; a hit with the same
  * t as a kept one goes after it).  Once k hits are kept, the k-th distance
  * bounds the search.
  *   k       1..RT_MAX_MULTI

@@ -910,8 +910,8 @@ int orc_hit_grad64(const double *verts, uint32_t n_verts, const uint32_t *faces,
 
 
 /* ======================================================================
- * Multi-hit query, float64 definition (Section 3.1: the first N hit points;
- * read as the N nearest accepted hits in increasing distance).
+ * Multi-hit query, float64 definition (Section 3.1: a query returning several hit
+ * points, read as the N nearest accepted hits in increasing distance).
  * ====================================================================== */
 typedef struct {
     double t, u, v;

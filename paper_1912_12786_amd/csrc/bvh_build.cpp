@@ -1,6 +1,6 @@
 // Host BVH builder of librtx.
 //
-// The paper traverses a BVH "built over some primitives" (Section 3.1) but
+// The paper traverses a BVH over the scene primitives (Section 3.1) but
 // does not describe the construction, so this library fixes one:
 //   * triangle box = exact float min/max of its three vertices; centroid =
 //     0.5 * (lo + hi) evaluated in double;

@@ -106,12 +106,13 @@ struct InstancedRequest {
     void *out;             // rt_hit* or uint32_t* (any)
     uint32_t *inst_ids;    // may be null
     void *counters;
-    void *spill;
+    void *spill;           // workspace past the queue heads
+    void *queue;           // queue heads
     void *stream;
 };
 
-// Instanced traversal: one ray per lane, LDS ring of kInstancedSlots.
-constexpr uint32_t kInstancedSlots = 8;
+// Instanced traversal: the library's default launch shape (persistent grid,
+// lane refill, LDS ring of kShapes[0].lds_stack slots).
 rt_status launch_instanced(const InstancedRequest &req, const char **err);
 
 struct BackwardRequest {

@@ -13,8 +13,9 @@
 //                                      current interval; the result is AND-ed
 //                                      into the hit (Listing 3: hr.hit &= ...)
 //   static constexpr bool kFilters     false lets the traversal skip the
-//                                      accept call entirely (zero cost when no
-//                                      custom code is supplied, Section 1)
+//                                      accept call entirely (an intersector
+//                                      without a decision adds no work,
+//                                      Section 1)
 //
 // The intersector object lives in registers for one ray, so per-ray state such
 // as the heat-map counters of Listing 6 is plain member data.
@@ -521,6 +522,78 @@ __device__ __forceinline__ typename Isect::params batch_params(const typename Is
     }
 }
 
+// The wave's supply of rays: its current chunk [next, end) and, in a queue
+// launch, the queue state.  Chunks past the static first ones are dealt
+// round-robin to kQueueHeads heads; a wave draws from the head of its block's
+// XCD (blocks are dispatched to the XCDs round-robin) and, once that head is
+// exhausted, from the others in turn.
+template <int kBlock, int kChunk, bool kQueue>
+struct ray_feed {
+    uint32_t next, end;
+    bool drained;  // no further chunk will come
+    uint32_t head, dead_heads;
+
+    __device__ __forceinline__ ray_feed(uint32_t n_rays, uint32_t gtid)
+    {
+        // every wave's first chunk is static (chunk index = wave index), so a
+        // queue launch does not start with every wave on an atomic
+        next = (gtid / 64) * uint32_t(kChunk);
+        end = min(next + uint32_t(kChunk), n_rays);
+        drained = !kQueue;
+        head = blockIdx.x % kQueueHeads;
+        dead_heads = 0;
+    }
+
+    // Wave-wide, with the wave's idle-lane mask: makes sure the chunk holds
+    // rays (drawing a new chunk from the queue if needed); false if none are
+    // left for now.
+    __device__ __forceinline__ bool refill(uint64_t idle, uint32_t n_rays, uint32_t *queue)
+    {
+        if constexpr (kQueue) {
+            if (idle != 0 && next >= end && !drained) {
+                const uint32_t n_chunks = (n_rays + uint32_t(kChunk) - 1) / uint32_t(kChunk);
+                const uint32_t first_dynamic = gridDim.x * (uint32_t(kBlock) / 64);
+                while (dead_heads != (1u << kQueueHeads) - 1) {
+                    uint32_t k = 0;
+                    if (__lane_id() == 0) k = atomicAdd(queue + head * kQueueStride, 1u);
+                    k = __builtin_amdgcn_readfirstlane(k);
+                    const uint64_t chunk = uint64_t(first_dynamic) + head + uint64_t(kQueueHeads) * k;
+                    if (chunk < n_chunks) {
+                        next = uint32_t(chunk) * uint32_t(kChunk);
+                        end = min(next + uint32_t(kChunk), n_rays);
+                        break;
+                    }
+                    dead_heads |= 1u << head;
+                    head = (head + 1) % kQueueHeads;
+                }
+                drained = dead_heads == (1u << kQueueHeads) - 1;
+            }
+        }
+        return idle != 0 && next < end;
+    }
+
+    // Wave-wide after a successful refill: the idle lanes take the next rays
+    // in lane order; a lane's ray id is valid iff it is below `end` (read
+    // before the call).
+    __device__ __forceinline__ uint32_t take(uint64_t idle, uint64_t lanes_below)
+    {
+        const uint32_t id = next + uint32_t(__popcll(idle & lanes_below));
+        next = min(next + uint32_t(__popcll(idle)), end);
+        return id;
+    }
+
+    __device__ __forceinline__ bool exhausted() const { return drained && next >= end; }
+};
+
+// A wave leaves its inner-node phase for the leaf phase once fewer than
+// kLeafBreak/16 of its busy lanes are still at inner nodes: waiting for the
+// last lane to reach a leaf would issue every node fetch for a few lanes.
+constexpr uint32_t kLeafBreak = 8;
+__device__ __forceinline__ bool leave_inner_phase(uint32_t n_inner, uint32_t n_leaf)
+{
+    return 16u * n_inner < kLeafBreak * (n_inner + n_leaf);
+}
+
 template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue,
           bool kBatched = false>
 __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename Isect::params p)
@@ -532,28 +605,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
     const uint32_t lane = __lane_id();
     const uint64_t lanes_below = (uint64_t(1) << lane) - 1;
 
-    // the wave's current chunk [next, end) (wave-uniform)
-    uint32_t next, end;
-    bool drained;  // no further chunk will come
-    // queue state (kQueue): chunks past the static ones are dealt round-robin
-    // to kQueueHeads heads; a wave draws from the head of its block's XCD
-    // (blocks are dispatched to the XCDs round-robin) and, once that head is
-    // exhausted, from the others in turn
-    const uint32_t n_chunks = (a.n_rays + uint32_t(kChunk) - 1) / uint32_t(kChunk);
-    const uint32_t first_dynamic = gridDim.x * (uint32_t(kBlock) / 64);
-    uint32_t head = blockIdx.x % kQueueHeads, dead_heads = 0;
-    if constexpr (kQueue) {
-        // every wave's first chunk is static (chunk index = wave index), so
-        // the launch does not start with every wave on an atomic
-        next = (gtid / 64) * uint32_t(kChunk);
-        end = min(next + uint32_t(kChunk), a.n_rays);
-        drained = false;
-    } else {
-        next = (gtid / 64) * uint32_t(kChunk);
-        end = min(next + uint32_t(kChunk), a.n_rays);
-        drained = true;
-        if (next >= a.n_rays) return;
-    }
+    ray_feed<kBlock, kChunk, kQueue> feed(a.n_rays, gtid);
 
     ring_stack<kSlots, kBlock> st{ring, (global_ptr<uint64_t>)(a.spill + gtid), tid,
                                   gridDim.x * uint32_t(kBlock)};
@@ -574,28 +626,9 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
 
     for (;;) {
         const uint64_t idle = __ballot(!active);
-        if constexpr (kQueue) {
-            if (idle != 0 && next >= end && !drained) {
-                while (dead_heads != (1u << kQueueHeads) - 1) {
-                    uint32_t k = 0;
-                    if (lane == 0) k = atomicAdd(a.queue + head * kQueueStride, 1u);
-                    k = __builtin_amdgcn_readfirstlane(k);
-                    const uint64_t chunk = uint64_t(first_dynamic) + head + uint64_t(kQueueHeads) * k;
-                    if (chunk < n_chunks) {
-                        next = uint32_t(chunk) * uint32_t(kChunk);
-                        end = min(next + uint32_t(kChunk), a.n_rays);
-                        break;
-                    }
-                    dead_heads |= 1u << head;
-                    head = (head + 1) % kQueueHeads;
-                }
-                drained = dead_heads == (1u << kQueueHeads) - 1;
-            }
-        }
-        if (idle != 0 && next < end) {
-            const uint32_t id = next + uint32_t(__popcll(idle & lanes_below));
-            next = min(next + uint32_t(__popcll(idle)), end);
-            if (!active && id < end) {
+        if (feed.refill(idle, a.n_rays, a.queue)) {
+            const uint32_t id = feed.take(idle, lanes_below);
+            if (!active && id < feed.end) {
                 ray_id = id;
                 r = make_ray(a.rays[2 * size_t(id)], a.rays[2 * size_t(id) + 1]);
                 if constexpr (kBatched) {
@@ -626,17 +659,24 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
             }
         }
         if (__ballot(active) == 0) {
-            if (drained && next >= end) break;
+            if (feed.exhausted()) break;
             continue;
         }
         if (active) {
-            while (ref_count(cur) == 0) {
-                if (!inner_step(sc, r, isect, st, cur)) {
-                    active = false;
+            // inner phase: lanes at inner nodes step on while enough of them
+            // remain; lanes already at a leaf wait (their ray's order is
+            // unchanged -- a lane that leaves this phase at an inner node
+            // simply continues from it in the next round)
+            for (;;) {
+                const bool in_inner = active && ref_count(cur) == 0;
+                const uint64_t mi = __ballot(in_inner);
+                if (mi == 0) break;
+                const uint64_t ml = __ballot(active && !in_inner);
+                if (ml != 0 && leave_inner_phase(uint32_t(__popcll(mi)), uint32_t(__popcll(ml))))
                     break;
-                }
+                if (in_inner && !inner_step(sc, r, isect, st, cur)) active = false;
             }
-            if (active) {
+            if (active && ref_count(cur) != 0) {
                 if (leaf_step(sc, r, isect, cur, res))
                     active = false;
                 else
@@ -666,98 +706,182 @@ __device__ __forceinline__ ray_state object_ray(const ray_state &w, const float 
     return make_ray(o, d);
 }
 
-// One ray per lane.  The top-level BVH (built over the instances' world
-// boxes; its leaf records carry instance indices) is walked like any BVH; at
-// a top-level leaf each instance in stored order is entered by a full
-// traversal of its bottom-level BVH with the object ray, on the same stack
-// above a floor, sharing the distance bound; then the top level resumes.
-template <class Isect, class Result, int kSlots>
-__global__ __launch_bounds__(64) void trace_instanced_kernel(kernel_args a, const unsigned char *table,
-                                                             uint32_t *inst_out,
-                                                             typename Isect::params p)
+// State of a lane that has entered an instance but not yet tested its
+// bottom-level root box (a leaf reference with the impossible count 7).
+constexpr uint32_t kPendingRoot = 0xFFFFFFFFu;
+
+// Two-level traversal, one ray per lane with the single-level kernel's lane
+// refill, ray queue and inner/leaf phases.  The top-level BVH (built over the
+// instances' world boxes; its leaf records carry instance indices) is walked
+// like any BVH; at a top-level leaf each instance in stored order is entered
+// by a full traversal of its bottom-level BVH with the object ray, on the same
+// stack above a floor, sharing the distance bound; then the top level
+// resumes.  A lane is at one level at a time: `r` is its ray at that level;
+// when a bottom-level traversal ends, the world ray is rebuilt from the input
+// ray (1/d recomputed exactly as at the start) with the current bound.
+// Entering an instance takes two rounds (object ray, then its root box test)
+// so that no round holds both records' registers.
+
+template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue>
+__global__ __launch_bounds__(kBlock) void trace_instanced_kernel(kernel_args a, const unsigned char *table,
+                                                                 uint32_t *inst_out,
+                                                                 typename Isect::params p)
 {
-    __shared__ uint2 ring[kSlots][64];
+    static_assert(kBlock % 64 == 0 && kChunk % 32 == 0, "wave64 shapes");
+    __shared__ uint2 ring[kSlots][kBlock];
     const uint32_t tid = threadIdx.x;
-    const uint32_t i = blockIdx.x * 64 + tid;
-    if (i >= a.n_rays) return;
-    ring_stack<kSlots, 64> st{ring, (global_ptr<uint64_t>)(a.spill + i), tid, gridDim.x * 64u};
-    ray_state rw = make_ray(a.rays[2 * size_t(i)], a.rays[2 * size_t(i) + 1]);
-    Isect isect(p);
-    Result res;
-    res.reset(rw, 1);
-    uint32_t inst_hit = kMissPrim;
+    const uint32_t gtid = blockIdx.x * kBlock + tid;
+    const uint64_t lanes_below = (uint64_t(1) << __lane_id()) - 1;
     const uint32_t n_blas = reinterpret_cast<const uint32_t *>(table)[0];
     const uint32_t n_inst = reinterpret_cast<const uint32_t *>(table)[1];
     const blas_record *blas = reinterpret_cast<const blas_record *>(table + instance_blas_offset());
     const instance_record *inst =
         reinterpret_cast<const instance_record *>(table + instance_records_offset(n_blas));
     const scene_view &tl = a.sc;
-    bool done = false;
-    uint32_t cur = tl.root_ref;
-    bool alive = root_step(tl, rw, isect);
-    while (alive && !done) {
-        while (ref_count(cur) == 0) {
-            if (!inner_step(tl, rw, isect, st, cur)) {
-                alive = false;
-                break;
+
+    ray_feed<kBlock, kChunk, kQueue> feed(a.n_rays, gtid);
+    ring_stack<kSlots, kBlock> st{ring, (global_ptr<uint64_t>)(a.spill + gtid), tid,
+                                  gridDim.x * uint32_t(kBlock)};
+    bool active = false;
+    uint32_t ray_id = 0, cur = 0;
+    ray_state r{};         // the ray at the lane's current level
+    bool bottom = false;   // in a bottom-level traversal
+    uint32_t leaf = 0;     // top-level leaf being entered
+    uint32_t next_inst = 0;  // its next instance slot
+    uint32_t q = 0;        // instance of the bottom-level traversal
+    float t_enter = 0.0f;  // distance bound when it was entered
+    const float4 *bnodes = nullptr, *btris = nullptr;  // its bottom-level BVH
+    uint32_t inst_hit = kMissPrim;
+    Isect isect(p);
+    Result res;
+    res.reset(r, 1);
+
+    auto finish = [&]() {
+        write_result(a, ray_id, res);
+        if (inst_out) inst_out[ray_id] = res_hit(res) ? inst_hit : kMissPrim;
+        if constexpr (Isect::kCounts)
+            a.counters[ray_id] = make_uint4(isect.num_boxes, isect.num_tris, isect.num_candidates,
+                                            isect.num_accepted);
+    };
+    // end of a bottom-level traversal: back to the top-level leaf; the world
+    // ray (with the current bound) is rebuilt from the input before the
+    // lane's next leaf phase
+    bool restore = false;
+    auto leave_instance = [&]() {
+        if (r.tmax != t_enter) inst_hit = q;  // a hit was accepted in it
+        restore = true;
+        st.floor = 0;
+        bottom = false;
+        cur = leaf;
+    };
+
+    for (;;) {
+        const uint64_t idle = __ballot(!active);
+        if (feed.refill(idle, a.n_rays, a.queue)) {
+            const uint32_t id = feed.take(idle, lanes_below);
+            if (!active && id < feed.end) {
+                ray_id = id;
+                r = make_ray(a.rays[2 * size_t(id)], a.rays[2 * size_t(id) + 1]);
+                isect = Isect(p);
+                st.reset();
+                res.reset(r, 1);
+                inst_hit = kMissPrim;
+                bottom = false;
+                cur = tl.root_ref;
+                next_inst = 0;
+                active = root_step(tl, r, isect);
+                if (!active) finish();
             }
         }
-        if (!alive) break;
-        const uint32_t first = ref_index(cur), count = ref_count(cur);
-        for (uint32_t j = first; j < first + count && !done; ++j) {
-            const uint32_t q = __float_as_uint(tl.tris[3 * size_t(j)].w);
-            if (q >= n_inst) continue;
-            const instance_record &ir = inst[q];
-            const uint32_t b = ir.blas;
-            if (b >= n_blas) continue;
-            float m[12];
-#pragma unroll
-            for (int k = 0; k < 12; ++k) m[k] = ir.m[k];
-            ray_state ro = object_ray(rw, m);
-            const blas_record &br = blas[b];
-            scene_view bv;
-            bv.nodes = br.nodes;
-            bv.tris = br.tris;
-            bv.root_lo[0] = br.root_lo[0];
-            bv.root_lo[1] = br.root_lo[1];
-            bv.root_lo[2] = br.root_lo[2];
-            bv.root_hi[0] = br.root_hi[0];
-            bv.root_hi[1] = br.root_hi[1];
-            bv.root_hi[2] = br.root_hi[2];
-            bv.root_ref = br.root_ref;
-            bv.n_tris = br.n_tris;
-            const float t_before = ro.tmax;
-            st.floor = st.sp;
-            if (root_step(bv, ro, isect)) {
-                uint32_t c2 = bv.root_ref;
-                bool alive2 = true;
-                while (alive2) {
-                    while (ref_count(c2) == 0) {
-                        if (!inner_step(bv, ro, isect, st, c2)) {
-                            alive2 = false;
-                            break;
-                        }
+        if (__ballot(active) == 0) {
+            if (feed.exhausted()) break;
+            continue;
+        }
+        if (active) {
+            for (;;) {
+                const bool in_inner = active && ref_count(cur) == 0;
+                const uint64_t mi = __ballot(in_inner);
+                if (mi == 0) break;
+                const uint64_t ml = __ballot(active && !in_inner);
+                if (ml != 0 && leave_inner_phase(uint32_t(__popcll(mi)), uint32_t(__popcll(ml))))
+                    break;
+                if (in_inner) {
+                    scene_view v = tl;
+                    if (bottom) v.nodes = bnodes;
+                    if (!inner_step(v, r, isect, st, cur)) {
+                        if (bottom)
+                            leave_instance();
+                        else
+                            active = false;
+                    } else if (!bottom) {
+                        next_inst = 0;
                     }
-                    if (!alive2) break;
-                    if (leaf_step(bv, ro, isect, c2, res)) {
-                        done = true;
-                        break;
-                    }
-                    alive2 = st.pop(ro.tmax, c2);
                 }
             }
-            st.floor = 0;
-            if (done || ro.tmax != t_before) inst_hit = q;
-            rw.tmax = ro.tmax;
+            if (restore) {
+                float4 d = a.rays[2 * size_t(ray_id) + 1];
+                d.w = r.tmax;
+                r = make_ray(a.rays[2 * size_t(ray_id)], d);
+                restore = false;
+            }
+            if (active && ref_count(cur) != 0) {
+                if (bottom && cur == kPendingRoot) {
+                    // root box of the entered instance's bottom-level BVH
+                    const blas_record &br = blas[inst[q].blas];
+                    scene_view b;
+                    b.nodes = br.nodes;
+                    b.tris = br.tris;
+                    b.root_lo[0] = br.root_lo[0];
+                    b.root_lo[1] = br.root_lo[1];
+                    b.root_lo[2] = br.root_lo[2];
+                    b.root_hi[0] = br.root_hi[0];
+                    b.root_hi[1] = br.root_hi[1];
+                    b.root_hi[2] = br.root_hi[2];
+                    b.root_ref = br.root_ref;
+                    b.n_tris = br.n_tris;
+                    if (root_step(b, r, isect)) {
+                        t_enter = r.tmax;
+                        bnodes = b.nodes;
+                        btris = b.tris;
+                        st.floor = st.sp;
+                        cur = b.root_ref;
+                    } else {
+                        leave_instance();
+                    }
+                } else if (bottom) {
+                    scene_view v = tl;
+                    v.tris = btris;
+                    if (leaf_step(v, r, isect, cur, res)) {
+                        inst_hit = q;
+                        active = false;
+                    } else if (!st.pop(r.tmax, cur)) {
+                        leave_instance();
+                    }
+                } else if (next_inst < ref_count(cur)) {
+                    // enter the leaf's next instance: the object ray now, its
+                    // root box test in the next round
+                    const uint32_t qq = __float_as_uint(tl.tris[3 * size_t(ref_index(cur) + next_inst)].w);
+                    ++next_inst;
+                    if (qq < n_inst && inst[qq].blas < n_blas) {
+                        float m[12];
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) m[k] = inst[qq].m[k];
+                        r = object_ray(r, m);
+                        q = qq;
+                        leaf = cur;
+                        t_enter = r.tmax;
+                        bottom = true;
+                        cur = kPendingRoot;
+                    }
+                } else if (st.pop(r.tmax, cur)) {  // leaf done: next top-level node
+                    next_inst = 0;
+                } else {
+                    active = false;
+                }
+            }
+            if (!active) finish();
         }
-        if (done) break;
-        alive = st.pop(rw.tmax, cur);
     }
-    write_result(a, i, res);
-    if (inst_out) inst_out[i] = res_hit(res) ? inst_hit : kMissPrim;
-    if constexpr (Isect::kCounts)
-        a.counters[i] = make_uint4(isect.num_boxes, isect.num_tris, isect.num_candidates,
-                                   isect.num_accepted);
 }
 
 // Zeroes the work-queue heads before a kQueue launch (a kernel rather than a

@@ -209,7 +209,9 @@ rt_status rt_trace_workspace_bytes(const rt_scene *scene, uint32_t n_rays, uint3
     if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
     rt_status st = check_scene(scene);
     if (st != RT_OK) return st;
-    if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    // the runtime-dispatch flags select kernels with the same workspace
+    if (flags & ~(RT_FLAG_COUNT | RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL))
+        return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
     if (n_rays > RT_MAX_RAYS) return fail(RT_ERR_INVALID_ARG, "more than 2^31 rays in one call");
     *bytes = workspace_for(scene->info, n_rays, kShapes[g_shape_index.load()]);
     return RT_OK;
@@ -421,12 +423,14 @@ rt_status rt_instance_pack(const rt_scene *blas, uint32_t n_blas, const rt_insta
     return RT_OK;
 }
 
+// Queue heads, then spill columns for the two-level stack (at most the
+// top-level depth plus the deepest bottom-level BVH) of every launched thread.
 static size_t instanced_workspace(const rt_bvh_info &tlas, uint32_t max_blas_depth, uint32_t n_rays)
 {
-    const uint32_t depth = tlas.max_depth + max_blas_depth;
-    const uint32_t cap = kInstancedSlots - 1;
-    const size_t threads = (size_t(n_rays) + 63) / 64 * 64;
-    return size_t(depth > cap ? depth - cap : 0) * threads * sizeof(uint64_t);
+    const LaunchShape &sh = kShapes[0];
+    rt_bvh_info both = tlas;
+    both.max_depth = tlas.max_depth + max_blas_depth;
+    return kQueueBytes + size_t(spill_entries(both, sh)) * launch_threads(n_rays, sh) * sizeof(uint64_t);
 }
 
 rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, uint32_t max_blas_depth,
@@ -484,7 +488,8 @@ rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, uint32_t m
     q.out = out;
     q.inst_ids = inst_ids;
     q.counters = count ? counters : nullptr;
-    q.spill = workspace;
+    q.queue = workspace;
+    q.spill = static_cast<unsigned char *>(workspace) + kQueueBytes;
     q.stream = stream;
     const char *err = "";
     st = launch_instanced(q, &err);

@@ -142,6 +142,10 @@ rt_status dispatch_query(const TraceRequest &q, const kernel_args &a,
     case Query::Any:
         return launch_one<Isect, any_result, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
     case Query::Multi:
+        // the kept list lives in registers: a short list for small k keeps
+        // the kernel's register use (and so its occupancy) closer to closest-hit
+        if (q.multi_k <= 4)
+            return launch_one<Isect, multi_result<4>, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
         return launch_one<Isect, multi_result<RT_MAX_MULTI>, kSlots, kBlock, kChunk, kQueue>(a, p, s,
                                                                                               err);
     case Query::Closest:
@@ -209,9 +213,17 @@ template <class Isect, class Result>
 rt_status launch_inst(const InstancedRequest &q, const kernel_args &a,
                       const typename Isect::params &p, const char **err)
 {
-    const uint32_t grid = (q.n_rays + 63) / 64;
-    hipLaunchKernelGGL((trace_instanced_kernel<Isect, Result, kInstancedSlots>), dim3(grid), dim3(64),
-                       0, static_cast<hipStream_t>(q.stream), a,
+    constexpr int kSlots = 8, kBlock = 64, kChunk = 64;
+    static_assert(kSlots == 8 && kBlock == 64 && kChunk == 64, "kShapes[0]");
+    const LaunchShape sh{kBlock, kSlots, kChunk, 1};
+    auto kernel = trace_instanced_kernel<Isect, Result, kSlots, kBlock, kChunk, true>;
+    hipStream_t s = static_cast<hipStream_t>(q.stream);
+    uint32_t grid = uint32_t(launch_threads(a.n_rays, sh) / kBlock);
+    const uint32_t resident = resident_blocks(kernel, kBlock, err);
+    if (resident == 0) return RT_ERR_HIP;
+    grid = grid < resident ? grid : resident;
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, a.queue);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, a,
                        static_cast<const unsigned char *>(q.table), q.inst_ids, p);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -257,6 +269,7 @@ rt_status launch_instanced(const InstancedRequest &q, const char **err)
     a.multi_k = 1;
     a.counters = static_cast<uint4 *>(q.counters);
     a.spill = static_cast<uint64_t *>(q.spill);
+    a.queue = static_cast<uint32_t *>(q.queue);
     switch (q.kind) {
     case RT_ISECT_DEFAULT:
         return launch_inst_count<default_intersector>(q, a, default_intersector::params{}, err);

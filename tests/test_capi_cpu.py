@@ -395,6 +395,13 @@ def test_workspace_bytes(lib):
         rtx.rt_set_launch_shape(*shapes[0])
     with pytest.raises(rtx.RtxError):
         rtx.rt_set_launch_shape(3, 3, 3, 3)
+    # every flag a trace call accepts is accepted here, with the same size
+    sc = _fake_scene(max_depth=20)
+    base = rtx.rt_trace_workspace_bytes(sc, 5000)
+    for flags in (rtx.RT_FLAG_COUNT, rtx.RT_FLAG_RUNTIME_SWITCH, rtx.RT_FLAG_RUNTIME_CALL):
+        assert rtx.rt_trace_workspace_bytes(sc, 5000, flags) == base
+    with pytest.raises(rtx.RtxError):
+        rtx.rt_trace_workspace_bytes(sc, 5000, 1 << 7)
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

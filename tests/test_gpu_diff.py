@@ -145,7 +145,13 @@ def test_autograd_function(diff_setup):
     hits[:, 1] = prim.view(torch.float32)
     gV, gR = diff.hit_backward(rays.detach(), hits, w, V.detach(), F)
     torch.cuda.synchronize()
-    assert torch.allclose(V.grad, gV, rtol=1e-5, atol=1e-6)
+    # vertex gradients are float32 atomic sums, so two launches may add the
+    # same contributions in another order: per vertex, agree to 1e-4 of the
+    # vertex's gradient norm (the float64 comparison above allows 1e-3)
+    d = (V.grad - gV).norm(dim=1)
+    n = gV.norm(dim=1)
+    assert torch.all(d <= 1e-4 * n + 1e-7 * n.max()), float((d / n.clamp_min(1e-30)).max())
+    assert torch.all(V.grad[n == 0] == 0)
     assert torch.allclose(rays.grad, gR, rtol=1e-6, atol=1e-7)
     assert torch.all(rays.grad[~hit] == 0)
     assert torch.all(tuv[~hit] == 0)
