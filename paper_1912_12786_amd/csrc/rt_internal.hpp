@@ -106,13 +106,14 @@ struct InstancedRequest {
     void *out;             // rt_hit* or uint32_t* (any)
     uint32_t *inst_ids;    // may be null
     void *counters;
-    void *spill;           // workspace past the queue heads
-    void *queue;           // queue heads
+    void *spill;
     void *stream;
 };
 
-// Instanced traversal: the library's default launch shape (persistent grid,
-// lane refill, LDS ring of kShapes[0].lds_stack slots).
+// Instanced traversal: one ray per lane, one wave per 64 consecutive rays (no
+// refill: rays of a wave stay coherent, so its lanes tend to enter the same
+// instances together), LDS ring of kInstancedSlots.
+constexpr uint32_t kInstancedSlots = 8;
 rt_status launch_instanced(const InstancedRequest &req, const char **err);
 
 struct BackwardRequest {

@@ -706,182 +706,98 @@ __device__ __forceinline__ ray_state object_ray(const ray_state &w, const float 
     return make_ray(o, d);
 }
 
-// State of a lane that has entered an instance but not yet tested its
-// bottom-level root box (a leaf reference with the impossible count 7).
-constexpr uint32_t kPendingRoot = 0xFFFFFFFFu;
-
-// Two-level traversal, one ray per lane with the single-level kernel's lane
-// refill, ray queue and inner/leaf phases.  The top-level BVH (built over the
-// instances' world boxes; its leaf records carry instance indices) is walked
-// like any BVH; at a top-level leaf each instance in stored order is entered
-// by a full traversal of its bottom-level BVH with the object ray, on the same
-// stack above a floor, sharing the distance bound; then the top level
-// resumes.  A lane is at one level at a time: `r` is its ray at that level;
-// when a bottom-level traversal ends, the world ray is rebuilt from the input
-// ray (1/d recomputed exactly as at the start) with the current bound.
-// Entering an instance takes two rounds (object ray, then its root box test)
-// so that no round holds both records' registers.
-
-template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue>
-__global__ __launch_bounds__(kBlock) void trace_instanced_kernel(kernel_args a, const unsigned char *table,
-                                                                 uint32_t *inst_out,
-                                                                 typename Isect::params p)
+// One ray per lane.  The top-level BVH (built over the instances' world
+// boxes; its leaf records carry instance indices) is walked like any BVH; at
+// a top-level leaf each instance in stored order is entered by a full
+// traversal of its bottom-level BVH with the object ray, on the same stack
+// above a floor, sharing the distance bound; then the top level resumes.
+template <class Isect, class Result, int kSlots>
+__global__ __launch_bounds__(64) void trace_instanced_kernel(kernel_args a, const unsigned char *table,
+                                                             uint32_t *inst_out,
+                                                             typename Isect::params p)
 {
-    static_assert(kBlock % 64 == 0 && kChunk % 32 == 0, "wave64 shapes");
-    __shared__ uint2 ring[kSlots][kBlock];
+    __shared__ uint2 ring[kSlots][64];
     const uint32_t tid = threadIdx.x;
-    const uint32_t gtid = blockIdx.x * kBlock + tid;
-    const uint64_t lanes_below = (uint64_t(1) << __lane_id()) - 1;
+    const uint32_t i = blockIdx.x * 64 + tid;
+    if (i >= a.n_rays) return;
+    ring_stack<kSlots, 64> st{ring, (global_ptr<uint64_t>)(a.spill + i), tid, gridDim.x * 64u};
+    ray_state rw = make_ray(a.rays[2 * size_t(i)], a.rays[2 * size_t(i) + 1]);
+    Isect isect(p);
+    Result res;
+    res.reset(rw, 1);
+    uint32_t inst_hit = kMissPrim;
     const uint32_t n_blas = reinterpret_cast<const uint32_t *>(table)[0];
     const uint32_t n_inst = reinterpret_cast<const uint32_t *>(table)[1];
     const blas_record *blas = reinterpret_cast<const blas_record *>(table + instance_blas_offset());
     const instance_record *inst =
         reinterpret_cast<const instance_record *>(table + instance_records_offset(n_blas));
     const scene_view &tl = a.sc;
-
-    ray_feed<kBlock, kChunk, kQueue> feed(a.n_rays, gtid);
-    ring_stack<kSlots, kBlock> st{ring, (global_ptr<uint64_t>)(a.spill + gtid), tid,
-                                  gridDim.x * uint32_t(kBlock)};
-    bool active = false;
-    uint32_t ray_id = 0, cur = 0;
-    ray_state r{};         // the ray at the lane's current level
-    bool bottom = false;   // in a bottom-level traversal
-    uint32_t leaf = 0;     // top-level leaf being entered
-    uint32_t next_inst = 0;  // its next instance slot
-    uint32_t q = 0;        // instance of the bottom-level traversal
-    float t_enter = 0.0f;  // distance bound when it was entered
-    const float4 *bnodes = nullptr, *btris = nullptr;  // its bottom-level BVH
-    uint32_t inst_hit = kMissPrim;
-    Isect isect(p);
-    Result res;
-    res.reset(r, 1);
-
-    auto finish = [&]() {
-        write_result(a, ray_id, res);
-        if (inst_out) inst_out[ray_id] = res_hit(res) ? inst_hit : kMissPrim;
-        if constexpr (Isect::kCounts)
-            a.counters[ray_id] = make_uint4(isect.num_boxes, isect.num_tris, isect.num_candidates,
-                                            isect.num_accepted);
-    };
-    // end of a bottom-level traversal: back to the top-level leaf; the world
-    // ray (with the current bound) is rebuilt from the input before the
-    // lane's next leaf phase
-    bool restore = false;
-    auto leave_instance = [&]() {
-        if (r.tmax != t_enter) inst_hit = q;  // a hit was accepted in it
-        restore = true;
-        st.floor = 0;
-        bottom = false;
-        cur = leaf;
-    };
-
-    for (;;) {
-        const uint64_t idle = __ballot(!active);
-        if (feed.refill(idle, a.n_rays, a.queue)) {
-            const uint32_t id = feed.take(idle, lanes_below);
-            if (!active && id < feed.end) {
-                ray_id = id;
-                r = make_ray(a.rays[2 * size_t(id)], a.rays[2 * size_t(id) + 1]);
-                isect = Isect(p);
-                st.reset();
-                res.reset(r, 1);
-                inst_hit = kMissPrim;
-                bottom = false;
-                cur = tl.root_ref;
-                next_inst = 0;
-                active = root_step(tl, r, isect);
-                if (!active) finish();
+    bool done = false;
+    uint32_t cur = tl.root_ref;
+    bool alive = root_step(tl, rw, isect);
+    while (alive && !done) {
+        while (ref_count(cur) == 0) {
+            if (!inner_step(tl, rw, isect, st, cur)) {
+                alive = false;
+                break;
             }
         }
-        if (__ballot(active) == 0) {
-            if (feed.exhausted()) break;
-            continue;
-        }
-        if (active) {
-            for (;;) {
-                const bool in_inner = active && ref_count(cur) == 0;
-                const uint64_t mi = __ballot(in_inner);
-                if (mi == 0) break;
-                const uint64_t ml = __ballot(active && !in_inner);
-                if (ml != 0 && leave_inner_phase(uint32_t(__popcll(mi)), uint32_t(__popcll(ml))))
-                    break;
-                if (in_inner) {
-                    scene_view v = tl;
-                    if (bottom) v.nodes = bnodes;
-                    if (!inner_step(v, r, isect, st, cur)) {
-                        if (bottom)
-                            leave_instance();
-                        else
-                            active = false;
-                    } else if (!bottom) {
-                        next_inst = 0;
-                    }
-                }
-            }
-            if (restore) {
-                float4 d = a.rays[2 * size_t(ray_id) + 1];
-                d.w = r.tmax;
-                r = make_ray(a.rays[2 * size_t(ray_id)], d);
-                restore = false;
-            }
-            if (active && ref_count(cur) != 0) {
-                if (bottom && cur == kPendingRoot) {
-                    // root box of the entered instance's bottom-level BVH
-                    const blas_record &br = blas[inst[q].blas];
-                    scene_view b;
-                    b.nodes = br.nodes;
-                    b.tris = br.tris;
-                    b.root_lo[0] = br.root_lo[0];
-                    b.root_lo[1] = br.root_lo[1];
-                    b.root_lo[2] = br.root_lo[2];
-                    b.root_hi[0] = br.root_hi[0];
-                    b.root_hi[1] = br.root_hi[1];
-                    b.root_hi[2] = br.root_hi[2];
-                    b.root_ref = br.root_ref;
-                    b.n_tris = br.n_tris;
-                    if (root_step(b, r, isect)) {
-                        t_enter = r.tmax;
-                        bnodes = b.nodes;
-                        btris = b.tris;
-                        st.floor = st.sp;
-                        cur = b.root_ref;
-                    } else {
-                        leave_instance();
-                    }
-                } else if (bottom) {
-                    scene_view v = tl;
-                    v.tris = btris;
-                    if (leaf_step(v, r, isect, cur, res)) {
-                        inst_hit = q;
-                        active = false;
-                    } else if (!st.pop(r.tmax, cur)) {
-                        leave_instance();
-                    }
-                } else if (next_inst < ref_count(cur)) {
-                    // enter the leaf's next instance: the object ray now, its
-                    // root box test in the next round
-                    const uint32_t qq = __float_as_uint(tl.tris[3 * size_t(ref_index(cur) + next_inst)].w);
-                    ++next_inst;
-                    if (qq < n_inst && inst[qq].blas < n_blas) {
-                        float m[12];
+        if (!alive) break;
+        const uint32_t first = ref_index(cur), count = ref_count(cur);
+        for (uint32_t j = first; j < first + count && !done; ++j) {
+            const uint32_t q = __float_as_uint(tl.tris[3 * size_t(j)].w);
+            if (q >= n_inst) continue;
+            const instance_record &ir = inst[q];
+            const uint32_t b = ir.blas;
+            if (b >= n_blas) continue;
+            float m[12];
 #pragma unroll
-                        for (int k = 0; k < 12; ++k) m[k] = inst[qq].m[k];
-                        r = object_ray(r, m);
-                        q = qq;
-                        leaf = cur;
-                        t_enter = r.tmax;
-                        bottom = true;
-                        cur = kPendingRoot;
+            for (int k = 0; k < 12; ++k) m[k] = ir.m[k];
+            ray_state ro = object_ray(rw, m);
+            const blas_record &br = blas[b];
+            scene_view bv;
+            bv.nodes = br.nodes;
+            bv.tris = br.tris;
+            bv.root_lo[0] = br.root_lo[0];
+            bv.root_lo[1] = br.root_lo[1];
+            bv.root_lo[2] = br.root_lo[2];
+            bv.root_hi[0] = br.root_hi[0];
+            bv.root_hi[1] = br.root_hi[1];
+            bv.root_hi[2] = br.root_hi[2];
+            bv.root_ref = br.root_ref;
+            bv.n_tris = br.n_tris;
+            const float t_before = ro.tmax;
+            st.floor = st.sp;
+            if (root_step(bv, ro, isect)) {
+                uint32_t c2 = bv.root_ref;
+                bool alive2 = true;
+                while (alive2) {
+                    while (ref_count(c2) == 0) {
+                        if (!inner_step(bv, ro, isect, st, c2)) {
+                            alive2 = false;
+                            break;
+                        }
                     }
-                } else if (st.pop(r.tmax, cur)) {  // leaf done: next top-level node
-                    next_inst = 0;
-                } else {
-                    active = false;
+                    if (!alive2) break;
+                    if (leaf_step(bv, ro, isect, c2, res)) {
+                        done = true;
+                        break;
+                    }
+                    alive2 = st.pop(ro.tmax, c2);
                 }
             }
-            if (!active) finish();
+            st.floor = 0;
+            if (done || ro.tmax != t_before) inst_hit = q;
+            rw.tmax = ro.tmax;
         }
+        if (done) break;
+        alive = st.pop(rw.tmax, cur);
     }
+    write_result(a, i, res);
+    if (inst_out) inst_out[i] = res_hit(res) ? inst_hit : kMissPrim;
+    if constexpr (Isect::kCounts)
+        a.counters[i] = make_uint4(isect.num_boxes, isect.num_tris, isect.num_candidates,
+                                   isect.num_accepted);
 }
 
 // Zeroes the work-queue heads before a kQueue launch (a kernel rather than a

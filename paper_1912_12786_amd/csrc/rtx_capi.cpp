@@ -423,14 +423,14 @@ rt_status rt_instance_pack(const rt_scene *blas, uint32_t n_blas, const rt_insta
     return RT_OK;
 }
 
-// Queue heads, then spill columns for the two-level stack (at most the
-// top-level depth plus the deepest bottom-level BVH) of every launched thread.
+// Spill columns for the two-level stack (at most the top-level depth plus the
+// deepest bottom-level BVH), one per ray.
 static size_t instanced_workspace(const rt_bvh_info &tlas, uint32_t max_blas_depth, uint32_t n_rays)
 {
-    const LaunchShape &sh = kShapes[0];
-    rt_bvh_info both = tlas;
-    both.max_depth = tlas.max_depth + max_blas_depth;
-    return kQueueBytes + size_t(spill_entries(both, sh)) * launch_threads(n_rays, sh) * sizeof(uint64_t);
+    const uint32_t depth = tlas.max_depth + max_blas_depth;
+    const uint32_t cap = kInstancedSlots - 1;
+    const size_t threads = (size_t(n_rays) + 63) / 64 * 64;
+    return size_t(depth > cap ? depth - cap : 0) * threads * sizeof(uint64_t);
 }
 
 rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, uint32_t max_blas_depth,
@@ -488,8 +488,7 @@ rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, uint32_t m
     q.out = out;
     q.inst_ids = inst_ids;
     q.counters = count ? counters : nullptr;
-    q.queue = workspace;
-    q.spill = static_cast<unsigned char *>(workspace) + kQueueBytes;
+    q.spill = workspace;
     q.stream = stream;
     const char *err = "";
     st = launch_instanced(q, &err);

@@ -213,17 +213,9 @@ template <class Isect, class Result>
 rt_status launch_inst(const InstancedRequest &q, const kernel_args &a,
                       const typename Isect::params &p, const char **err)
 {
-    constexpr int kSlots = 8, kBlock = 64, kChunk = 64;
-    static_assert(kSlots == 8 && kBlock == 64 && kChunk == 64, "kShapes[0]");
-    const LaunchShape sh{kBlock, kSlots, kChunk, 1};
-    auto kernel = trace_instanced_kernel<Isect, Result, kSlots, kBlock, kChunk, true>;
-    hipStream_t s = static_cast<hipStream_t>(q.stream);
-    uint32_t grid = uint32_t(launch_threads(a.n_rays, sh) / kBlock);
-    const uint32_t resident = resident_blocks(kernel, kBlock, err);
-    if (resident == 0) return RT_ERR_HIP;
-    grid = grid < resident ? grid : resident;
-    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, a.queue);
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, a,
+    const uint32_t grid = (q.n_rays + 63) / 64;
+    hipLaunchKernelGGL((trace_instanced_kernel<Isect, Result, kInstancedSlots>), dim3(grid), dim3(64),
+                       0, static_cast<hipStream_t>(q.stream), a,
                        static_cast<const unsigned char *>(q.table), q.inst_ids, p);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -269,7 +261,6 @@ rt_status launch_instanced(const InstancedRequest &q, const char **err)
     a.multi_k = 1;
     a.counters = static_cast<uint4 *>(q.counters);
     a.spill = static_cast<uint64_t *>(q.spill);
-    a.queue = static_cast<uint32_t *>(q.queue);
     switch (q.kind) {
     case RT_ISECT_DEFAULT:
         return launch_inst_count<default_intersector>(q, a, default_intersector::params{}, err);
