@@ -73,12 +73,36 @@ def copy_calibration():
                       "launches": 3}), flush=True)
 
 
-def cpu_baseline(wl, kind_kw, threads, budget_s=8.0):
+def tile_order(wl, tile: int = 8) -> np.ndarray:
+    """Permutation of a pinhole workload's primary rays (scanline order, width
+    from its name) into tile x tile pixel blocks; other rays keep their place."""
+    import re
+    m = re.search(r"_(\d+)x(\d+)", wl.name)
+    w, h = int(m.group(1)), int(m.group(2))
+    y, x = np.divmod(np.arange(w * h), w)
+    key = ((y // tile) * ((w + tile - 1) // tile) + x // tile) * tile * tile + (y % tile) * tile + x % tile
+    order = np.argsort(key, kind="stable")
+    return np.concatenate([order, np.arange(w * h, wl.n_rays)])
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, kind, kind_kw, threads, budget_s=8.0):
     """The oracle as it stands, on this host's cores, on the same workload:
     oracle B (float32 BVH traversal of its own BVH) over every ray, repeated
-    until about ``budget_s`` seconds have passed (median pass reported), and
-    oracle A (float64 brute force over every triangle) on a ray sample sized
-    to about ``budget_s / 2`` seconds."""
+    until about ``budget_s`` seconds have passed (median pass reported), the
+    same on one thread over every 16th ray, and oracle A (float64 brute force
+    over every triangle) on a ray sample sized to about ``budget_s / 2``
+    seconds."""
     import oracle
     from paper_1912_12786_amd import workloads as W
     oracle.build(force=False)
@@ -88,18 +112,22 @@ def cpu_baseline(wl, kind_kw, threads, budget_s=8.0):
     passes = []
     while not passes or (sum(passes) < budget_s and len(passes) < 50):
         t0 = time.perf_counter()
-        oracle.traverse(wl.vertices, bvh, wl.rays, "alpha", count=False, threads=threads, **kind_kw)
+        oracle.traverse(wl.vertices, bvh, wl.rays, kind, count=False, threads=threads, **kind_kw)
         passes.append(time.perf_counter() - t0)
     t_b = float(np.median(passes))
+    sub = wl.rays[::16]
+    t0 = time.perf_counter()
+    oracle.traverse(wl.vertices, bvh, sub, kind, count=False, threads=1, **kind_kw)
+    t_b1 = time.perf_counter() - t0
     # size the brute-force sample from a short probe
     probe = W.subsample_indices(wl.n_rays, None, None, seed=7, n_random=256)
     t0 = time.perf_counter()
-    oracle.brute(wl.vertices, wl.rays, "alpha", ray_index=probe, threads=threads, **kind_kw)
+    oracle.brute(wl.vertices, wl.rays, kind, ray_index=probe, threads=threads, **kind_kw)
     t_probe = time.perf_counter() - t0
     n_a = int(min(wl.n_rays, max(256, len(probe) * (budget_s / 2) / max(t_probe, 1e-3))))
     idx = W.subsample_indices(wl.n_rays, None, None, seed=8, n_random=n_a)
     t0 = time.perf_counter()
-    oracle.brute(wl.vertices, wl.rays, "alpha", ray_index=idx, threads=threads, **kind_kw)
+    oracle.brute(wl.vertices, wl.rays, kind, ray_index=idx, threads=threads, **kind_kw)
     t_a = time.perf_counter() - t0
     return {
         "value": round(wl.n_rays / t_b / 1e6, 3),
@@ -110,7 +138,9 @@ def cpu_baseline(wl, kind_kw, threads, budget_s=8.0):
                    f"all {wl.n_rays} rays, {len(passes)} passes, median {t_b:.3f} s; oracle A "
                    f"(float64 brute force over all {wl.n_tris} triangles) on {len(idx)} sampled "
                    f"rays in {t_a:.2f} s"),
+        "single_thread_mrays_s": round(sub.shape[0] / t_b1 / 1e6, 3),
         "bruteforce_mrays_s": round(len(idx) / t_a / 1e6, 6),
+        "cpu_model": cpu_model(),
     }
 
 
@@ -350,11 +380,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--shape", default=None,
                     help="launch shape BLOCK,LDS_SLOTS,CHUNK,QUEUE (default: the library's default)")
-    ap.add_argument("--intersector", default="alpha", choices=["alpha", "default"],
-                    help="default = the same scene and rays with the accept-all intersector")
+    ap.add_argument("--intersector", default=None, choices=["alpha", "default", "procedural"],
+                    help="default: alpha on billboards, accept-all on tiny, procedural checker "
+                         "on spheres")
+    ap.add_argument("--ray-order", default="scanline", choices=["scanline", "tiled"],
+                    help="tiled: primary rays reordered into 8x8 pixel tiles before upload "
+                         "(hits come back in that order)")
     ap.add_argument("--query", default="closest", choices=["closest", "any", "multi"])
     ap.add_argument("--k", type=int, default=4, help="hits kept per ray by --query multi")
-    ap.add_argument("--workload", default="billboards", choices=["billboards", "diff", "batched", "dispatch", "instanced"],
+    ap.add_argument("--workload", default="billboards",
+                    choices=["billboards", "tiny", "spheres", "diff", "batched", "dispatch",
+                             "instanced"],
                     help="diff = differentiable hit on the perturbed icosphere (forward, "
                          "forward+backward and the plain kernel), reported on its own line")
     args = ap.parse_args()
@@ -384,13 +420,18 @@ def main():
 
     if args.shape:
         rtx.rt_set_launch_shape(*(int(x) for x in args.shape.split(",")))
-    kind = args.intersector
+    kind = args.intersector or {"billboards": "alpha", "tiny": "default",
+                                "spheres": "procedural"}[args.workload]
+    if kind == "alpha" and args.workload != "billboards":
+        raise SystemExit("the alpha intersector needs the billboard workload's textures")
     dev = torch.device("cuda:0")
     props = torch.cuda.get_device_properties(dev)
     log(f"device {props.name} CUs={props.multi_processor_count} "
         f"gcn={getattr(props, 'gcnArchName', '?')}")
     t0 = time.perf_counter()
-    wl = W.billboards()
+    wl = {"billboards": W.billboards, "tiny": W.tiny, "spheres": W.spheres}[args.workload]()
+    if args.ray_order == "tiled":
+        wl.rays = wl.rays[tile_order(wl)]
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     scene = rtx.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures, device=dev)
@@ -409,27 +450,38 @@ def main():
     ws = rtx.Workspace(dev)
     stream = torch.cuda.current_stream(dev)
 
-    def step():
-        rtx.trace(scene, rays, kind, query=query, k=args.k, alpha_min=128, out=hits, workspace=ws)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    def time_launches(r, o):
+        """(per-launch ms from HIP events on the launch stream, wall s) of
+        args.steps launches over rays r into o, after args.warmup."""
+        def step():
+            rtx.trace(scene, r, kind, query=query, k=args.k, alpha_min=128, out=o, workspace=ws)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            starts[i].record(stream)
+            step()
+            ends[i].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return np.array([s.elapsed_time(e) for s, e in zip(starts, ends)]), wall
 
     # timed region: K launches on the current stream, HIP events around each
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record(stream)
-        step()
-        ends[i].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per_launch_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    per_launch_ms, wall = time_launches(rays, hits)
     ms_per_step = wall * 1e3 / args.steps
     mrays = wl.n_rays * args.steps / wall / 1e6
+    split = None
+    if args.workload == "spheres":  # primary and bounce rays on their own
+        n_p = int(wl.extra["n_primary"])
+        split = {}
+        for name, sl in (("primary", slice(0, n_p)), ("bounce", slice(n_p, wl.n_rays))):
+            ms, _ = time_launches(rays[sl], hits[sl])
+            split[name] = {"n_rays": sl.stop - sl.start, "kernel_ms_median": round(float(np.median(ms)), 4),
+                           "mrays_s": round((sl.stop - sl.start) / float(np.median(ms)) / 1e3, 2)}
 
     # exact per-ray counts from a separate (untimed) counting launch
     _, cnt = rtx.trace(scene, rays, kind, query=query, k=args.k, alpha_min=128, count=True,
@@ -450,20 +502,22 @@ def main():
         with open(TRAFFIC_FILE) as f:
             tf = json.load(f)
         if tf.get("kernel_source_sha") == kernel_source_sha() and kind == "alpha" \
-                and query == "closest" \
+                and query == "closest" and args.ray_order == "scanline" \
                 and list(rtx.rt_launch_shapes()[0]) == tf.get("launch_shape") and not args.shape:
             traffic = tf.get("traffic_bytes_per_launch")
 
     cpu = None
-    if not args.no_cpu_baseline and kind == "alpha" and query == "closest":
+    if not args.no_cpu_baseline and query == "closest":
         threads = len(os.sched_getaffinity(0))
         kind_kw = dict(geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures,
-                       alpha_min=128)
-        cpu = cpu_baseline(wl, kind_kw, threads)
+                       alpha_min=128) if kind == "alpha" else {}
+        cpu = cpu_baseline(wl, kind, kind_kw, threads)
 
     mean_c = counters.mean(axis=0)
     result = {
-        "metric": "Mrays/s closest-hit w/ alpha-mask intersector at 1080p; HBM GB/s % of peak",
+        "metric": ("Mrays/s closest-hit w/ alpha-mask intersector at 1080p; HBM GB/s % of peak"
+                   if args.workload == "billboards" else
+                   f"Mrays/s {query} hit, {kind} intersector, {wl.name}; HBM GB/s % of peak"),
         "value": round(mrays, 2),
         "unit": "Mrays/s",
         "n_gpus": 1,
@@ -482,7 +536,8 @@ def main():
             "intersector": kind,
             "alpha_threshold": "0.5 (alpha byte >= 128)" if kind == "alpha" else None,
             "query": query if query != "multi" else f"multi (k={args.k})",
-            "textures": "16 x 256x256 RGBA8",
+            "textures": "16 x 256x256 RGBA8" if wl.textures is not None else None,
+            "ray_order": "8x8 tiles" if args.ray_order == "tiled" else "scanline",
             "bvh": f"binary SAH, {scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}",
             "launch_shape": ([int(x) for x in args.shape.split(",")] if args.shape
                              else list(rtx.rt_launch_shapes()[0])),
@@ -496,6 +551,7 @@ def main():
             "traffic": traffic,
             "kernel": f"trace_kernel<{kind}_intersector, {query}>",
             "kernel_ms_mean": round(kernel_ms, 4),
+            "kernel_ms_median": round(float(np.median(per_launch_ms)), 4),
             "kernel_ms_p10_p90": [round(float(np.percentile(per_launch_ms, 10)), 4),
                                   round(float(np.percentile(per_launch_ms, 90)), 4)],
             "algorithmic_bytes_per_launch": alg_bytes,
@@ -506,6 +562,8 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if split:
+        result["primary_bounce"] = split
     print(json.dumps(result), flush=True)
 
 
