@@ -335,9 +335,10 @@ rt_status rt_hit_backward(const rt_ray *rays, const rt_hit *hits, const float *g
  *              workspace);
  *   chunk      rays a wave takes at a time; the wave hands the next ray of
  *              its chunk to a lane as soon as the lane's ray is finished;
- *   queue      1: a persistent grid (256 CUs x 32 wave slots) takes chunks
- *              from a global atomic queue kept in the workspace; 0: wave w
- *              owns the static chunk w.
+ *   queue      1: a persistent grid (the blocks that can be resident at
+ *              once, from the occupancy query; the workspace is sized for at
+ *              most 256 CUs x 32 wave slots) takes chunks from atomic queues
+ *              kept in the workspace; 0: wave w owns the static chunk w.
  * Writes up to cap entries per array (any array may be NULL) and returns the
  * number of shapes; the first shape is the default. */
 uint32_t rt_launch_shapes(uint32_t *blocks, uint32_t *lds_stacks, uint32_t *chunks,
