@@ -140,6 +140,7 @@ def cpu_baseline(wl, kind, kind_kw, threads, budget_s=8.0):
                    f"rays in {t_a:.2f} s"),
         "single_thread_mrays_s": round(sub.shape[0] / t_b1 / 1e6, 3),
         "bruteforce_mrays_s": round(len(idx) / t_a / 1e6, 6),
+        "bruteforce_full_set_s": round(wl.n_rays * t_a / len(idx), 1),
         "cpu_model": cpu_model(),
     }
 

@@ -87,6 +87,12 @@ def test_small_batch_matches_per_scene_and_oracle(env, oracle_lib, kind):
         sl = slice(off[i], off[i + 1])
         P.assert_exact_vs_b({k: v[sl] for k, v in g.items()}, B, f"batch scene {i}")
         assert np.array_equal(c[sl].view(np.uint32), B["counters"])
+        # and the float64 definition on up to 512 rays of the scene
+        rng = np.random.default_rng(100 + i)
+        idx = np.sort(rng.choice(s["rays"].shape[0], size=min(512, s["rays"].shape[0]),
+                                 replace=False))
+        A = oracle_lib.brute(s["vertices"], s["rays"], kind, ray_index=idx, **okw)
+        P.compare_vs_a({k: v[sl] for k, v in g.items()}, A, idx, f"batch scene {i} vs A")
 
 
 def test_full_batch_matches_per_scene(env, oracle_lib):
