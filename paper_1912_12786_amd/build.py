@@ -69,5 +69,33 @@ def build(verbose: bool = False) -> str:
     return LIB_PATH
 
 
+def build_user_library(sources, out_path: str, verbose: bool = False) -> str:
+    """Compiles HIP sources that instantiate the traversal template with their
+    own intersector (they include ``csrc/rt_launch.hpp``) into a shared
+    library at ``out_path``, with the same flags as librtx."""
+    cc = hipcc()
+    objs = []
+    for src in sources:
+        obj = os.path.splitext(out_path)[0] + "_" + os.path.splitext(os.path.basename(src))[0] + ".o"
+        cmd = [cc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-x", "hip", "-c", src,
+               "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
+                        if "packed-fp32-ops' is not a recognized feature" not in l)
+        if msg.strip():
+            print(msg, file=sys.stderr)
+        if r.returncode != 0:
+            raise subprocess.CalledProcessError(r.returncode, cmd)
+        objs.append(obj)
+    tmp = out_path + ".tmp"
+    subprocess.run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], check=True)
+    os.replace(tmp, out_path)
+    for o in objs:
+        os.remove(o)
+    return out_path
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv[1:]))

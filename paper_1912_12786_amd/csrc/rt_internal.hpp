@@ -49,6 +49,7 @@ constexpr uint64_t kPersistentWaves = 256 * 32;
 constexpr size_t kQueueBytes = 1024;
 
 // The shapes compiled into the library; the first one is the default.
+constexpr LaunchShape kDefaultShape{64, 8, 64, 1};
 extern const LaunchShape kShapes[];
 extern const uint32_t kNumShapes;
 
@@ -90,6 +91,13 @@ inline uint64_t launch_threads(uint32_t n_rays, const LaunchShape &s)
         if (waves > kPersistentWaves) waves = kPersistentWaves;
     }
     return (waves * 64 + s.block - 1) / s.block * s.block;
+}
+
+// Workspace bytes of a single-scene launch of n_rays rays in shape s.
+inline size_t workspace_for(const rt_bvh_info &info, uint32_t n_rays, const LaunchShape &s)
+{
+    return (s.queue ? kQueueBytes : 0) +
+           size_t(spill_entries(info, s)) * size_t(launch_threads(n_rays, s)) * sizeof(uint64_t);
 }
 
 // Enqueues one traversal kernel; returns RT_OK or RT_ERR_HIP.

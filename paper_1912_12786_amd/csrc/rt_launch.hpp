@@ -1,0 +1,151 @@
+// Host-side launching of the traversal kernel template, shared by librtx and
+// by C++/HIP code that compiles its own intersector into the traversal
+// (Section 3.2: the intersector is a compile-time parameter of the traversal,
+// so user code that includes this header gets its accept decision inlined
+// into its own kernel instantiation).
+//
+// A user intersector derives from intersector_base and provides
+//   struct params { ... };                       (passed by value to the kernel)
+//   __device__ explicit T(const params &);
+//   static constexpr bool kFilters = true;       (when it can reject hits)
+//   __device__ bool accept(const hit_candidate &);
+// and may be wrapped in counting_intersector<T> for the per-ray counters.
+// trace_custom<T>() then runs the closest-hit query with it, using the
+// library's default launch shape and the scene layout of rt_bvh_build.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+
+#include "rt_internal.hpp"
+#include "rt_traverse.hpp"
+
+namespace rtx {
+
+// Resident blocks per CU x CUs of the current device for a kernel, cached per
+// device (queried once per kernel instantiation and device).
+template <class Kernel>
+uint32_t resident_blocks(Kernel kernel, uint32_t block, const char **err)
+{
+    static std::atomic<uint32_t> cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        *err = "hipGetDevice failed";
+        return 0;
+    }
+    if (cache[dev].load(std::memory_order_relaxed) == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, int(block), 0) != hipSuccess ||
+            cus <= 0 || per_cu <= 0) {
+            *err = "occupancy query failed";
+            return 0;
+        }
+        cache[dev].store(uint32_t(cus) * uint32_t(per_cu), std::memory_order_relaxed);
+    }
+    return cache[dev].load(std::memory_order_relaxed);
+}
+
+// Kernel arguments for one scene; the workspace holds the queue heads (queue
+// shapes) and then the stack spill columns.
+inline kernel_args scene_args(const rt_scene &scene, const void *rays, uint32_t n_rays, void *out,
+                              void *counters, void *workspace, const LaunchShape &shape)
+{
+    kernel_args a{};
+    const rt_bvh_info &info = scene.info;
+    a.sc.nodes = static_cast<const float4 *>(scene.nodes);
+    a.sc.tris = static_cast<const float4 *>(scene.tris);
+    for (int k = 0; k < 3; ++k) {
+        a.sc.root_lo[k] = info.root_lo[k];
+        a.sc.root_hi[k] = info.root_hi[k];
+    }
+    a.sc.root_ref = info.root_ref;
+    a.sc.n_tris = info.n_tris;
+    a.rays = static_cast<const float4 *>(rays);
+    a.n_rays = n_rays;
+    a.out = out;
+    a.multi_k = 1;
+    a.counters = static_cast<uint4 *>(counters);
+    unsigned char *ws = static_cast<unsigned char *>(workspace);
+    a.queue = shape.queue ? reinterpret_cast<uint32_t *>(ws) : nullptr;
+    a.spill = reinterpret_cast<uint64_t *>(shape.queue && ws ? ws + kQueueBytes : ws);
+    return a;
+}
+
+// Enqueues one traversal kernel (and, for a queue shape, the reset of the
+// queue heads before it); returns RT_OK or RT_ERR_HIP.
+template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue,
+          bool kBatched = false>
+rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipStream_t s,
+                     const char **err)
+{
+    const LaunchShape sh{kBlock, kSlots, kChunk, kQueue};
+    auto kernel = trace_kernel<Isect, Result, kSlots, kBlock, kChunk, kQueue, kBatched>;
+    // the workspace is sized for launch_threads(); a queue grid is further
+    // trimmed to the waves that can be resident at once
+    uint32_t grid = uint32_t(launch_threads(a.n_rays, sh) / kBlock);
+    if constexpr (kQueue) {
+        const uint32_t resident = resident_blocks(kernel, kBlock, err);
+        if (resident == 0) return RT_ERR_HIP;
+        grid = grid < resident ? grid : resident;
+        hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, a.queue);
+    }
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, a, p);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        *err = hipGetErrorString(e);
+        return RT_ERR_HIP;
+    }
+    return RT_OK;
+}
+
+// Closest-hit query with a user intersector Isect (wrap it in
+// counting_intersector<> and pass counters for the per-ray counts).
+//   scene      built by rt_bvh_build, device buffers (not validated here
+//              beyond null pointers, alignment and the stack bound)
+//   rays, out  device, n_rays rt_ray / rt_hit, 16-byte aligned
+//   counters   device rt_counters[n_rays] iff Isect counts, else NULL
+//   workspace  device, at least custom_workspace_bytes(scene, n_rays) bytes
+// Returns RT_OK, RT_ERR_INVALID_ARG / RT_ERR_MISALIGNED / RT_ERR_WORKSPACE
+// (nothing launched; *err says why) or RT_ERR_HIP.
+inline size_t custom_workspace_bytes(const rt_scene &scene, uint32_t n_rays)
+{
+    return workspace_for(scene.info, n_rays, kDefaultShape);
+}
+
+template <class Isect>
+rt_status trace_custom(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                       const typename Isect::params &p, rt_hit *out, rt_counters *counters,
+                       void *workspace, size_t workspace_bytes, hipStream_t stream,
+                       const char **err)
+{
+    auto is16 = [](const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    if (!scene) {
+        *err = "scene is NULL";
+        return RT_ERR_INVALID_ARG;
+    }
+    if (n_rays == 0) return RT_OK;
+    if (n_rays > RT_MAX_RAYS || !rays || !out || (Isect::kCounts != (counters != nullptr))) {
+        *err = "rays/out NULL, too many rays, or counters given iff the intersector counts";
+        return RT_ERR_INVALID_ARG;
+    }
+    if (scene->info.n_tris > 0 && (!scene->tris || scene->info.max_depth >= 128)) {
+        *err = "scene triangle records NULL or stack bound exceeded";
+        return RT_ERR_INVALID_ARG;
+    }
+    if (!is16(rays) || !is16(out) || (counters && !is16(counters)) || !is16(workspace)) {
+        *err = "rays, out, counters and workspace must be 16-byte aligned";
+        return RT_ERR_MISALIGNED;
+    }
+    if (!workspace || workspace_bytes < custom_workspace_bytes(*scene, n_rays)) {
+        *err = "workspace smaller than custom_workspace_bytes";
+        return RT_ERR_WORKSPACE;
+    }
+    constexpr LaunchShape s = kDefaultShape;
+    const kernel_args a = scene_args(*scene, rays, n_rays, out, counters, workspace, s);
+    return launch_one<Isect, closest_result, int(s.lds_stack), int(s.block), int(s.chunk),
+                      s.queue != 0>(a, p, stream, err);
+}
+
+}  // namespace rtx

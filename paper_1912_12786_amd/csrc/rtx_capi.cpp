@@ -91,12 +91,6 @@ rt_status check_params(const rt_scene *sc, rt_isect_kind kind, const void *param
     return fail(RT_ERR_UNSUPPORTED, "unknown intersector kind");
 }
 
-size_t workspace_for(const rt_bvh_info &info, uint32_t n_rays, const LaunchShape &s)
-{
-    return (s.queue ? kQueueBytes : 0) +
-           size_t(spill_entries(info, s)) * size_t(launch_threads(n_rays, s)) * sizeof(uint64_t);
-}
-
 rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
                        rt_isect_kind kind, const void *params, uint32_t flags, void *out,
                        size_t out_align, rt_counters *counters, void *workspace,

@@ -12,10 +12,7 @@
 // workspace.
 #include <hip/hip_runtime.h>
 
-#include <atomic>
-
-#include "rt_internal.hpp"
-#include "rt_traverse.hpp"
+#include "rt_launch.hpp"
 
 namespace rtx {
 
@@ -72,60 +69,11 @@ struct runtime_call_intersector : intersector_base {
 };
 
 // (block, LDS ring slots, rays per chunk, global queue); the first is the default
-const LaunchShape kShapes[] = {{64, 8, 64, 1},  {64, 8, 64, 0},   {64, 16, 64, 1}, {256, 8, 64, 1},
+const LaunchShape kShapes[] = {kDefaultShape,   {64, 8, 64, 0},   {64, 16, 64, 1}, {256, 8, 64, 1},
                                {128, 8, 64, 1}, {64, 8, 128, 1}, {256, 16, 64, 1}};
 const uint32_t kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 namespace {
-
-// Resident blocks per CU x CUs of the current device for a kernel, cached per
-// device (queried once per kernel instantiation and device).
-template <class Kernel>
-uint32_t resident_blocks(Kernel kernel, uint32_t block, const char **err)
-{
-    static std::atomic<uint32_t> cache[64] = {};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
-        *err = "hipGetDevice failed";
-        return 0;
-    }
-    if (cache[dev].load(std::memory_order_relaxed) == 0) {
-        int cus = 0, per_cu = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, int(block), 0) != hipSuccess ||
-            cus <= 0 || per_cu <= 0) {
-            *err = "occupancy query failed";
-            return 0;
-        }
-        cache[dev].store(uint32_t(cus) * uint32_t(per_cu), std::memory_order_relaxed);
-    }
-    return cache[dev].load(std::memory_order_relaxed);
-}
-
-template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue,
-          bool kBatched = false>
-rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipStream_t s,
-                     const char **err)
-{
-    const LaunchShape sh{kBlock, kSlots, kChunk, kQueue};
-    auto kernel = trace_kernel<Isect, Result, kSlots, kBlock, kChunk, kQueue, kBatched>;
-    // the workspace is sized for launch_threads(); a queue grid is further
-    // trimmed to the waves that can be resident at once
-    uint32_t grid = uint32_t(launch_threads(a.n_rays, sh) / kBlock);
-    if constexpr (kQueue) {
-        const uint32_t resident = resident_blocks(kernel, kBlock, err);
-        if (resident == 0) return RT_ERR_HIP;
-        grid = grid < resident ? grid : resident;
-        hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, a.queue);
-    }
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, a, p);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        *err = hipGetErrorString(e);
-        return RT_ERR_HIP;
-    }
-    return RT_OK;
-}
 
 template <class Isect, int kSlots, int kBlock, int kChunk, bool kQueue>
 rt_status dispatch_query(const TraceRequest &q, const kernel_args &a,
@@ -277,22 +225,9 @@ rt_status launch_instanced(const InstancedRequest &q, const char **err)
 
 rt_status launch_trace(const TraceRequest &q, const char **err)
 {
-    kernel_args a;
-    const rt_bvh_info &info = q.scene->info;
-    a.sc.nodes = static_cast<const float4 *>(q.scene->nodes);
-    a.sc.tris = static_cast<const float4 *>(q.scene->tris);
-    for (int k = 0; k < 3; ++k) {
-        a.sc.root_lo[k] = info.root_lo[k];
-        a.sc.root_hi[k] = info.root_hi[k];
-    }
-    a.sc.root_ref = info.root_ref;
-    a.sc.n_tris = info.n_tris;
-    a.rays = static_cast<const float4 *>(q.rays);
-    a.n_rays = q.n_rays;
-    a.out = q.out;
+    kernel_args a = scene_args(*q.scene, q.rays, q.n_rays, q.out, q.counters, nullptr, q.shape);
     a.n_hits = static_cast<uint32_t *>(q.n_hits);
     a.multi_k = q.multi_k;
-    a.counters = static_cast<uint4 *>(q.counters);
     a.batch = static_cast<const unsigned char *>(q.batch);
     a.spill = static_cast<uint64_t *>(q.spill);
     a.queue = static_cast<uint32_t *>(q.queue);

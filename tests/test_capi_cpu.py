@@ -415,3 +415,25 @@ def test_binding_fails_loudly_without_library(tmp_path):
         finally:
             rtx._lib = saved
     importlib.invalidate_caches()
+
+
+def test_custom_intersector_library_loads_and_validates(lib):
+    """The user-defined intersector library (compiled against the traversal
+    template) loads, exports its entry points, sizes its workspace like the
+    library's default shape, and validates arguments without a GPU."""
+    from tests.custom import binding
+    cl = binding.load()
+    sc = _fake_scene(max_depth=20)
+    rtx.rt_set_launch_shape(*rtx.rt_launch_shapes()[0])
+    assert cl.prim_mask_workspace_bytes(C.byref(sc), 5000) == rtx.rt_trace_workspace_bytes(sc, 5000)
+    # zero rays: nothing to do
+    assert cl.prim_mask_trace(C.byref(sc), None, 0, 0x10, None, None, None, 0, None) == 0
+    # status codes of include/rtx.h: -1 invalid argument, -2 misaligned, -4 workspace
+    # no mask for a non-empty scene
+    assert cl.prim_mask_trace(C.byref(sc), 0x30000, 10, None, 0x40000, None, 0x50000, 1 << 20,
+                              None) == -1
+    # misaligned output, too-small workspace
+    assert cl.prim_mask_trace(C.byref(sc), 0x30000, 10, 0x10, 0x40008, None, 0x50000, 1 << 20,
+                              None) == -2
+    assert cl.prim_mask_trace(C.byref(sc), 0x30000, 10, 0x10, 0x40000, None, 0x50000, 16,
+                              None) == -4
