@@ -74,11 +74,10 @@ def copy_calibration():
 
 
 def tile_order(wl, tile: int = 8) -> np.ndarray:
-    """Permutation of a pinhole workload's primary rays (scanline order, width
-    from its name) into tile x tile pixel blocks; other rays keep their place."""
-    import re
-    m = re.search(r"_(\d+)x(\d+)", wl.name)
-    w, h = int(m.group(1)), int(m.group(2))
+    """Permutation of a pinhole workload's primary rays (scanline order, the
+    first width x height rays) into tile x tile pixel blocks; other rays keep
+    their place."""
+    w, h = int(wl.extra["width"]), int(wl.extra["height"])
     y, x = np.divmod(np.arange(w * h), w)
     key = ((y // tile) * ((w + tile - 1) // tile) + x // tile) * tile * tile + (y % tile) * tile + x % tile
     order = np.argsort(key, kind="stable")

@@ -319,8 +319,9 @@ def tiny(width: int = 64, height: int = 64) -> Workload:
     from distance 2, vertical fov 40 degrees."""
     v = random_triangles(1024, seed_for(CFG_TINY, STREAM_GEOMETRY))
     rays = pinhole_rays(width, height, (0.5, 0.5, 2.5), (0.5, 0.5, 0.5), 40.0)
-    return Workload("tiny_1k_tris_64x64", v, rays,
-                    geom_ids=np.zeros(v.shape[0], np.uint32))
+    return Workload(f"tiny_1k_tris_{width}x{height}", v, rays,
+                    geom_ids=np.zeros(v.shape[0], np.uint32),
+                    extra={"width": width, "height": height})
 
 
 def billboards(n_quads: int = 100_000, width: int = 1920, height: int = 1080,
@@ -331,7 +332,8 @@ def billboards(n_quads: int = 100_000, width: int = 1920, height: int = 1080,
     tex = alpha_textures(n_tex, tex_size, seed_for(CFG_BILLBOARDS, STREAM_TEXTURES))
     rays = pinhole_rays(width, height, BILLBOARD_EYE, BILLBOARD_CENTER, 60.0)
     return Workload(f"billboards_{2 * n_quads}_tris_{width}x{height}", v, rays,
-                    geom_ids=geom, texcoords=tc, textures=tex)
+                    geom_ids=geom, texcoords=tc, textures=tex,
+                    extra={"width": width, "height": height})
 
 
 def spheres(n_spheres: int = 2000, width: int = 1920, height: int = 1080,
@@ -348,7 +350,8 @@ def spheres(n_spheres: int = 2000, width: int = 1920, height: int = 1080,
     rays = np.concatenate([prim, bounce], 0)
     return Workload(f"spheres_{v.shape[0]}_tris_{width}x{height}_plus_bounce", v, rays,
                     geom_ids=np.zeros(v.shape[0], np.uint32),
-                    extra={"n_primary": prim.shape[0], "centres": c, "radii": r})
+                    extra={"n_primary": prim.shape[0], "centres": c, "radii": r,
+                           "width": width, "height": height})
 
 
 def subsample_indices(n_rays: int, width: int | None, height: int | None,
