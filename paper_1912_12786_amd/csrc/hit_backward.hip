@@ -10,15 +10,21 @@
 // solved with scalar triple products.  The hit prim and the intersector's
 // accept decision are discrete and held fixed.
 //
-// One lane per ray; the per-ray algebra runs in float64 (full vector rate on
-// this GPU) from the float32 inputs, and vertex gradients are scattered with
-// float32 hardware atomics (coarse-grained device memory), so their summation
-// order -- and the last bits of the sums -- vary from run to run.
+// One lane per ray; the per-ray algebra runs in float64 (half the float32
+// vector rate on gfx950, ample for ~150 operations per ray) from the float32
+// inputs.  Vertex gradients are scattered with float32 hardware atomics
+// (coarse-grained device memory): neighbouring rays of a wave usually hit the
+// same triangle, so each run of consecutive lanes with the same triangle first
+// sums its contributions (a segmented suffix scan over the wave) and only the
+// run's first lane issues the nine atomics.  The summation order -- and the
+// last bits of the sums -- still vary from run to run.
 #include <hip/hip_runtime.h>
 
 #include "rt_internal.hpp"
 
 namespace rtx {
+
+constexpr uint32_t kNoPrim = 0xFFFFFFFFu;
 
 struct backward_args {
     const float4 *rays;      // 2 float4 per ray
@@ -33,15 +39,28 @@ struct backward_args {
     float4 *grad_rays;       // [n][2] float4 or null
 };
 
+// Sums v over the lanes [lane, run_end] of the caller's run (run_end: last
+// lane of the run, >= lane).  Every lane of the wave must call it.
+__device__ __forceinline__ float run_suffix_sum(float v, uint32_t lane, uint32_t run_end)
+{
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const float w = __shfl_down(v, off, 64);
+        if (lane + off <= run_end) v += w;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(256) void hit_backward_kernel(backward_args a)
 {
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.n_rays) return;
-    const float4 h = a.hits[i];
-    const uint32_t prim = __float_as_uint(h.y);
+    const bool in_range = i < a.n_rays;  // no early exit: the wave scans together
+    uint32_t prim = kNoPrim;
+    if (in_range) prim = __float_as_uint(a.hits[i].y);
     float lx = 0.0f, ly = 0.0f, lz = 0.0f;
     float tl[3] = {0.0f, 0.0f, 0.0f};  // t * lam
-    bool ok = prim < a.n_tris;
+    float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};  // dL/dv0, dv1, dv2
+    bool ok = in_range && prim < a.n_tris;
     uint32_t f0 = 0, f1 = 0, f2 = 0;
     if (ok) {
         f0 = a.faces[3 * size_t(prim)];
@@ -85,18 +104,15 @@ __global__ __launch_bounds__(256) void hit_backward_kernel(backward_args a)
         const double lyd = (-gt * ny + gu * c1y + gv * c2y) * inv;
         const double lzd = (-gt * nz + gu * c1z + gv * c2z) * inv;
         const double w0 = (1.0 - u) - v;
-        float *g0 = a.grad_vertices + 3 * size_t(f0);
-        float *g1 = a.grad_vertices + 3 * size_t(f1);
-        float *g2 = a.grad_vertices + 3 * size_t(f2);
-        unsafeAtomicAdd(g0 + 0, float(-w0 * lxd));
-        unsafeAtomicAdd(g0 + 1, float(-w0 * lyd));
-        unsafeAtomicAdd(g0 + 2, float(-w0 * lzd));
-        unsafeAtomicAdd(g1 + 0, float(-u * lxd));
-        unsafeAtomicAdd(g1 + 1, float(-u * lyd));
-        unsafeAtomicAdd(g1 + 2, float(-u * lzd));
-        unsafeAtomicAdd(g2 + 0, float(-v * lxd));
-        unsafeAtomicAdd(g2 + 1, float(-v * lyd));
-        unsafeAtomicAdd(g2 + 2, float(-v * lzd));
+        g[0] = float(-w0 * lxd);
+        g[1] = float(-w0 * lyd);
+        g[2] = float(-w0 * lzd);
+        g[3] = float(-u * lxd);
+        g[4] = float(-u * lyd);
+        g[5] = float(-u * lzd);
+        g[6] = float(-v * lxd);
+        g[7] = float(-v * lyd);
+        g[8] = float(-v * lzd);
         lx = float(lxd);
         ly = float(lyd);
         lz = float(lzd);
@@ -104,7 +120,32 @@ __global__ __launch_bounds__(256) void hit_backward_kernel(backward_args a)
         tl[1] = float(td * lyd);
         tl[2] = float(td * lzd);
     }
-    if (a.grad_rays) {
+    // runs of consecutive lanes with the same triangle (lanes without a valid
+    // hit form runs of their own key and add nothing)
+    const uint32_t lane = __lane_id();
+    const uint32_t key = ok ? prim : kNoPrim;
+    const uint32_t next_key = __shfl_down(key, 1, 64);
+    const uint64_t tails = __ballot(lane == 63 || next_key != key);
+    const uint32_t run_end = uint32_t(__ffsll((long long)(tails >> lane << lane)) - 1);
+    const uint32_t prev_key = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || prev_key != key;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g[k] = run_suffix_sum(g[k], lane, run_end);
+    if (ok && head) {
+        float *g0 = a.grad_vertices + 3 * size_t(f0);
+        float *g1 = a.grad_vertices + 3 * size_t(f1);
+        float *g2 = a.grad_vertices + 3 * size_t(f2);
+        unsafeAtomicAdd(g0 + 0, g[0]);
+        unsafeAtomicAdd(g0 + 1, g[1]);
+        unsafeAtomicAdd(g0 + 2, g[2]);
+        unsafeAtomicAdd(g1 + 0, g[3]);
+        unsafeAtomicAdd(g1 + 1, g[4]);
+        unsafeAtomicAdd(g1 + 2, g[5]);
+        unsafeAtomicAdd(g2 + 0, g[6]);
+        unsafeAtomicAdd(g2 + 1, g[7]);
+        unsafeAtomicAdd(g2 + 2, g[8]);
+    }
+    if (in_range && a.grad_rays) {
         a.grad_rays[2 * size_t(i)] = make_float4(lx, ly, lz, 0.0f);
         a.grad_rays[2 * size_t(i) + 1] = make_float4(tl[0], tl[1], tl[2], 0.0f);
     }
