@@ -1,0 +1,42 @@
+"""Host logic of bench.py (no GPU): the one-GPU contract, the algorithmic
+bytes model against hand counts, and the tiled ray order."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import bench
+from paper_1912_12786_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_bytes_per_ray_hand_counts():
+    # boxes, tris, candidates, accepted
+    c = np.array([[1, 0, 0, 0],      # missed the root: ray + hit only
+                  [7, 4, 1, 1],      # 3 inner nodes, 4 triangles, 1 alpha lookup
+                  [73, 12, 2, 1]], np.uint32)
+    alpha = bench.bytes_per_ray(c, "alpha")
+    plain = bench.bytes_per_ray(c, "default")
+    assert alpha.tolist() == [48, 48 + 3 * 64 + 4 * 48 + 28, 48 + 36 * 64 + 12 * 48 + 2 * 28]
+    assert plain.tolist() == [48, 48 + 3 * 64 + 4 * 48, 48 + 36 * 64 + 12 * 48]
+
+
+def test_tile_order_is_a_tiled_permutation():
+    wl = W.tiny(24, 16)
+    o = bench.tile_order(wl, tile=8)
+    assert np.array_equal(np.sort(o), np.arange(wl.n_rays))
+    # the first 64 entries are the top-left 8x8 pixel block, row by row
+    first = o[:64]
+    y, x = np.divmod(first, 24)
+    assert y.max() < 8 and x.max() < 8
+    assert np.array_equal(first[:8], np.arange(8))
+    assert first[8] == 24
