@@ -327,7 +327,8 @@ struct closest_result {  // the nearest accepted hit
         u = v = 0.0f;
         prim = kMissPrim;
     }
-    __device__ __forceinline__ bool commit(ray_state &r, float tt, float uu, float vv, uint32_t p)
+    __device__ __forceinline__ bool commit(ray_state &r, float tt, float uu, float vv, uint32_t p,
+                                           uint32_t)
     {
         t = tt;
         u = uu;
@@ -341,7 +342,7 @@ struct closest_result {  // the nearest accepted hit
 struct any_result {  // the first accepted hit met
     uint32_t prim;
     __device__ __forceinline__ void reset(const ray_state &, uint32_t) { prim = kMissPrim; }
-    __device__ __forceinline__ bool commit(ray_state &, float, float, float, uint32_t p)
+    __device__ __forceinline__ bool commit(ray_state &, float, float, float, uint32_t p, uint32_t)
     {
         prim = p;
         return true;
@@ -350,12 +351,15 @@ struct any_result {  // the first accepted hit met
 
 // The k nearest accepted hits (k <= kMax, a run-time value), sorted by t;
 // a new hit goes after every kept hit with the same t.  Once k hits are kept,
-// the k-th distance bounds the search.  The list lives in registers: every
-// loop over it is unrolled, so no index is dynamic.
+// the k-th distance bounds the search.  The list lives in registers as
+// (t, triangle record index) pairs only -- every loop over it is unrolled, so
+// no index is dynamic -- and the barycentrics of the kept hits are recomputed
+// from their records when the ray is written (the same float32 operations on
+// the same ray give the same u, v), which halves the list's registers.
 template <int kMax>
 struct multi_result {
-    float t[kMax], u[kMax], v[kMax];
-    uint32_t prim[kMax];
+    float t[kMax];
+    uint32_t rec[kMax];
     uint32_t n, k;
     float tmax0;
     __device__ __forceinline__ void reset(const ray_state &r, uint32_t kk)
@@ -363,34 +367,30 @@ struct multi_result {
 #pragma unroll
         for (int i = 0; i < kMax; ++i) {
             t[i] = __builtin_huge_valf();
-            u[i] = v[i] = 0.0f;
-            prim[i] = kMissPrim;
+            rec[i] = kMissPrim;
         }
         n = 0;
         k = kk;
         tmax0 = r.tmax;
     }
-    __device__ __forceinline__ bool commit(ray_state &r, float tt, float uu, float vv, uint32_t p)
+    __device__ __forceinline__ bool commit(ray_state &r, float tt, float, float, uint32_t,
+                                           uint32_t j)
     {
         // carry the new hit down the list, swapping it with every kept hit
         // that is strictly farther; what falls off slot k-1 is dropped
-        float ct = tt, cu = uu, cv = vv;
-        uint32_t cp = p;
+        float ct = tt;
+        uint32_t cj = j;
         float tk = __builtin_huge_valf();
 #pragma unroll
         for (int i = 0; i < kMax; ++i) {
             const bool live = uint32_t(i) < k;
             const bool take = live && ct < t[i];
-            const float st = t[i], su = u[i], sv = v[i];
-            const uint32_t sp = prim[i];
+            const float st = t[i];
+            const uint32_t sj = rec[i];
             t[i] = take ? ct : st;
-            u[i] = take ? cu : su;
-            v[i] = take ? cv : sv;
-            prim[i] = take ? cp : sp;
+            rec[i] = take ? cj : sj;
             ct = take ? st : ct;
-            cu = take ? su : cu;
-            cv = take ? sv : cv;
-            cp = take ? sp : cp;
+            cj = take ? sj : cj;
             if (uint32_t(i) + 1 == k) tk = t[i];
         }
         n = n < k ? n + 1 : k;
@@ -415,7 +415,7 @@ __device__ __forceinline__ bool leaf_step(const scene_view &sc, ray_state &r, Is
             bool ok = true;
             if constexpr (Isect::kFilters)
                 ok = isect.accept(hit_candidate{__float_as_uint(a.w), __float_as_uint(b.w), t, u, v});
-            if (ok && res.commit(r, t, u, v, __float_as_uint(a.w))) return true;
+            if (ok && res.commit(r, t, u, v, __float_as_uint(a.w), j)) return true;
         }
     }
     return false;
@@ -484,8 +484,11 @@ __device__ __forceinline__ bool res_hit(const Result &res)
     return res.prim != kMissPrim;
 }
 
+// Writes ray `ray`'s record(s); sc and r are the lane's scene and ray state
+// (the multi-hit list recomputes its barycentrics from them).
 template <class Result>
-__device__ __forceinline__ void write_result(const kernel_args &a, uint32_t ray, const Result &res)
+__device__ __forceinline__ void write_result(const kernel_args &a, const scene_view &sc,
+                                             const ray_state &r, uint32_t ray, const Result &res)
 {
     if constexpr (std::is_same_v<Result, any_result>) {
         static_cast<uint32_t *>(a.out)[ray] = res.prim;
@@ -495,9 +498,18 @@ __device__ __forceinline__ void write_result(const kernel_args &a, uint32_t ray,
     } else {
         float4 *o = static_cast<float4 *>(a.out) + size_t(ray) * a.multi_k;
 #pragma unroll
-        for (int i = 0; i < int(sizeof(res.t) / sizeof(float)); ++i)
-            if (uint32_t(i) < a.multi_k)
-                o[i] = make_float4(res.t[i], __uint_as_float(res.prim[i]), res.u[i], res.v[i]);
+        for (int i = 0; i < int(sizeof(res.t) / sizeof(float)); ++i) {
+            if (uint32_t(i) >= a.multi_k) continue;
+            float4 h = make_float4(__builtin_huge_valf(), __uint_as_float(kMissPrim), 0.0f, 0.0f);
+            if (uint32_t(i) < res.n) {
+                const float4 *tp = sc.tris + 3 * size_t(res.rec[i]);
+                const float4 ta = tp[0], tb = tp[1], tc = tp[2];
+                float tt, uu, vv;
+                triangle(r, ta, tb, tc, tt, uu, vv);
+                h = make_float4(res.t[i], ta.w, uu, vv);
+            }
+            o[i] = h;
+        }
         a.n_hits[ray] = res.n;
     }
 }
@@ -618,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
     res.reset(r, a.multi_k);
 
     auto finish = [&]() {
-        write_result(a, ray_id, res);
+        write_result(a, sc, r, ray_id, res);
         if constexpr (Isect::kCounts)
             a.counters[ray_id] = make_uint4(isect.num_boxes, isect.num_tris, isect.num_candidates,
                                             isect.num_accepted);
@@ -793,7 +805,7 @@ __global__ __launch_bounds__(64) void trace_instanced_kernel(kernel_args a, cons
         if (done) break;
         alive = st.pop(rw.tmax, cur);
     }
-    write_result(a, i, res);
+    write_result(a, tl, rw, i, res);
     if (inst_out) inst_out[i] = res_hit(res) ? inst_hit : kMissPrim;
     if constexpr (Isect::kCounts)
         a.counters[i] = make_uint4(isect.num_boxes, isect.num_tris, isect.num_candidates,
