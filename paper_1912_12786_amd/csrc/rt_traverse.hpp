@@ -376,15 +376,19 @@ struct multi_result {
     __device__ __forceinline__ bool commit(ray_state &r, float tt, float, float, uint32_t,
                                            uint32_t j)
     {
-        // carry the new hit down the list, swapping it with every kept hit
-        // that is strictly farther; what falls off slot k-1 is dropped
+        // the new hit goes into the first slot whose kept hit is strictly
+        // farther; from there on every kept hit moves down one slot (a plain
+        // shift, so kept hits of equal t keep their order); what falls off
+        // slot k-1 is dropped
         float ct = tt;
         uint32_t cj = j;
         float tk = __builtin_huge_valf();
+        bool shifting = false;
 #pragma unroll
         for (int i = 0; i < kMax; ++i) {
             const bool live = uint32_t(i) < k;
-            const bool take = live && ct < t[i];
+            const bool take = live && (shifting || ct < t[i]);
+            shifting = take;
             const float st = t[i];
             const uint32_t sj = rec[i];
             t[i] = take ? ct : st;
