@@ -500,19 +500,21 @@ class Batch:
     """Scenes with their ray counts, packed into a device scene table
     (rt_batch_pack + one host-to-device copy made here, by torch)."""
 
-    def __init__(self, scenes, n_rays, intersector: str = "default", alpha_min: int = 128,
+    def __init__(self, scenes, n_rays, intersector: str = "default", alpha_min=128,
                  device="cuda"):
         torch = _torch()
         self.scenes = list(scenes)
         self.kind = KINDS[intersector]
         self.intersector = intersector
         entries = []
-        for sc, n in zip(self.scenes, n_rays):
+        mins = ([int(alpha_min)] * len(self.scenes) if np.ndim(alpha_min) == 0
+                else [int(a) for a in alpha_min])   # one threshold, or one per scene
+        for sc, n, amin in zip(self.scenes, n_rays, mins):
             e = rt_batch_entry()
             e.scene = sc.view
             e.n_rays = int(n)
             if intersector == "alpha":
-                e.alpha = sc.alpha_params(alpha_min)
+                e.alpha = sc.alpha_params(amin)
             entries.append(e)
         table, self.info = rt_batch_pack(entries, self.kind)
         self.table = torch.from_numpy(table.copy()).to(device)
