@@ -558,12 +558,34 @@ def instance_transforms(world_from_object: np.ndarray, blas_lo: np.ndarray, blas
     return ofw.reshape(n, 12).astype(np.float32), lo32, hi32
 
 
+def tight_world_boxes(world_from_object: np.ndarray, meshes, ids: np.ndarray):
+    """World boxes of instances from their transformed vertices (tighter than
+    the transformed object box of a rotated instance), padded outward by
+    1e-5 of the extent and rounded outward to float32, like
+    instance_transforms()."""
+    n = world_from_object.shape[0]
+    lo = np.zeros((n, 3))
+    hi = np.zeros((n, 3))
+    for q in range(n):
+        v = np.asarray(meshes[ids[q]], np.float64).reshape(-1, 3)
+        if v.size == 0:
+            lo[q] = hi[q] = world_from_object[q, :, 3]
+            continue
+        w = v @ world_from_object[q, :, :3].T + world_from_object[q, :, 3]
+        lo[q], hi[q] = w.min(0), w.max(0)
+    pad = 1e-5 * (hi - lo).max(1, keepdims=True) + 1e-6
+    lo32 = np.nextafter((lo - pad).astype(np.float32), np.float32(-np.inf))
+    hi32 = np.nextafter((hi + pad).astype(np.float32), np.float32(np.inf))
+    return lo32, hi32
+
+
 def instanced(n_instances: int = 2000, width: int = 1920, height: int = 1080):
     """Object instancing: three meshes (a 500-triangle sphere, 500 random
     triangles, 50 billboard quads) instanced n_instances times with random
     rotations, scales in [0.5, 3] and positions uniform in [0, 100]^3, seen by
     the billboard camera.  Returns dict with blas vertex lists, per-instance
-    blas ids, object-from-world maps, world boxes and rays."""
+    blas ids, object-from-world maps, world boxes (from the transformed
+    vertices) and rays."""
     g = rng_for(CFG_BATCHED, 900)
     blas = [uv_sphere(np.zeros(3), 1.0).astype(np.float32),
             random_triangles(500, seed_for(CFG_BATCHED, 901), side=0.3, box=(-1.0, 1.0)),
@@ -576,7 +598,8 @@ def instanced(n_instances: int = 2000, width: int = 1920, height: int = 1080):
         wfo[i, :, 3] = g.uniform(0.0, 100.0, size=3)
     blo = np.stack([b.reshape(-1, 3).min(0) for b in blas]).astype(np.float64)[ids]
     bhi = np.stack([b.reshape(-1, 3).max(0) for b in blas]).astype(np.float64)[ids]
-    m, lo, hi = instance_transforms(wfo, blo, bhi)
+    m, _, _ = instance_transforms(wfo, blo, bhi)
+    lo, hi = tight_world_boxes(wfo, blas, ids)
     rays = pinhole_rays(width, height, BILLBOARD_EYE, BILLBOARD_CENTER, 60.0)
     return {"blas": blas, "inst_blas": ids, "inst_m": m, "world_lo": lo, "world_hi": hi,
             "rays": rays, "world_from_object": wfo,
