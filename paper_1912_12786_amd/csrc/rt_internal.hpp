@@ -85,11 +85,9 @@ inline uint32_t spill_entries(const rt_bvh_info &info, const LaunchShape &s)
 // Threads launched for n_rays rays (one column of spill space each).
 inline uint64_t launch_threads(uint32_t n_rays, const LaunchShape &s)
 {
+    // one wave per chunk; a queue grid at most fills the chip
     uint64_t waves = (uint64_t(n_rays) + s.chunk - 1) / s.chunk;
-    if (s.queue) {
-        waves = (uint64_t(n_rays) + 63) / 64;
-        if (waves > kPersistentWaves) waves = kPersistentWaves;
-    }
+    if (s.queue && waves > kPersistentWaves) waves = kPersistentWaves;
     return (waves * 64 + s.block - 1) / s.block * s.block;
 }
 

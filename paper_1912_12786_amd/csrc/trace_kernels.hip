@@ -70,7 +70,8 @@ struct runtime_call_intersector : intersector_base {
 
 // (block, LDS ring slots, rays per chunk, global queue); the first is the default
 const LaunchShape kShapes[] = {kDefaultShape,   {64, 8, 64, 0},   {64, 16, 64, 1}, {256, 8, 64, 1},
-                               {128, 8, 64, 1}, {64, 8, 128, 1}, {256, 16, 64, 1}};
+                               {128, 8, 64, 1}, {64, 8, 128, 1}, {256, 16, 64, 1},
+                               {64, 8, 32, 1}};
 const uint32_t kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 namespace {
@@ -243,6 +244,7 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
     RTX_SHAPE(128, 8, 64, 1)
     RTX_SHAPE(64, 8, 128, 1)
     RTX_SHAPE(256, 16, 64, 1)
+    RTX_SHAPE(64, 8, 32, 1)
 #undef RTX_SHAPE
     *err = "launch shape not compiled into the library";
     return RT_ERR_UNSUPPORTED;

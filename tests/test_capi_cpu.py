@@ -382,10 +382,9 @@ def test_workspace_bytes(lib):
             rtx.rt_set_launch_shape(block, slots, chunk, queue)
             for n in (1000, 3_000_000):
                 b = rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=20), n)
+                waves = (n + chunk - 1) // chunk
                 if queue:
-                    waves = min((n + 63) // 64, 256 * 32)
-                else:
-                    waves = (n + chunk - 1) // chunk
+                    waves = min(waves, 256 * 32)
                 threads = (waves * 64 + block - 1) // block * block
                 assert b == (1024 if queue else 0) + max(0, 20 - (slots - 1)) * threads * 8
                 # shallow scenes need no spill space
