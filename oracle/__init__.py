@@ -287,14 +287,15 @@ def hit_grad64(vertices64, faces, rays, prims, grad_tuv):
 # ----------------------------------------------------------------------------
 class _Blas(C.Structure):
     _fields_ = [("verts", C.c_void_p), ("n_tris", C.c_uint32), ("nodes", C.c_void_p),
-                ("perm", C.c_void_p)]
+                ("perm", C.c_void_p), ("geom", C.c_void_p), ("texcoords", C.c_void_p)]
 
 
 class _Inst(C.Structure):
     _fields_ = [("blas", C.c_uint32), ("m", C.c_float * 12)]
 
 
-def _instance_args(blas_vertices, blas_bvhs, inst_blas, inst_m):
+def _instance_args(blas_vertices, blas_bvhs, inst_blas, inst_m, geom_ids=None, texcoords=None):
+    """geom_ids / texcoords: per-mesh lists (alpha intersector) or None."""
     keep = []
     blas = (_Blas * len(blas_vertices))()
     for i, (v, b) in enumerate(zip(blas_vertices, blas_bvhs)):
@@ -304,6 +305,18 @@ def _instance_args(blas_vertices, blas_bvhs, inst_blas, inst_m):
         blas[i].n_tris = vv.shape[0]
         blas[i].nodes = b.nodes.ctypes.data
         blas[i].perm = b.perm.ctypes.data
+        if geom_ids is not None and geom_ids[i] is not None:
+            g = np.ascontiguousarray(geom_ids[i], np.uint32)
+            if g.shape[0] < vv.shape[0]:
+                raise ValueError("geom_ids must cover every triangle of the mesh")
+            keep.append(g)
+            blas[i].geom = g.ctypes.data
+        if texcoords is not None and texcoords[i] is not None:
+            tc = np.ascontiguousarray(texcoords[i], np.float32)
+            if tc.shape[0] < vv.shape[0]:
+                raise ValueError("texcoords must cover every triangle of the mesh")
+            keep.append(tc)
+            blas[i].texcoords = tc.ctypes.data
     n = len(inst_blas)
     inst = (_Inst * max(1, n))()
     m = np.ascontiguousarray(inst_m, np.float32).reshape(-1, 12)
@@ -321,18 +334,22 @@ def build_tlas(world_lo, world_hi) -> OracleBVH:
     return build_bvh(np.stack([lo, hi, hi], axis=1))
 
 
-def brute_instanced(blas_vertices, inst_blas, inst_m, rays, kind="default", checker_n=8):
-    """float64 definition over every instance and triangle."""
+def brute_instanced(blas_vertices, inst_blas, inst_m, rays, kind="default", checker_n=8, *,
+                    geom_ids=None, texcoords=None, textures=None, alpha_min=128):
+    """float64 definition over every instance and triangle.  Alpha: per-mesh
+    geom_ids and texcoords lists, one shared texture array."""
     lib = _load()
     bvhs = [OracleBVH(np.zeros(1, NODE_DTYPE), np.zeros(1, np.uint32), 0)] * len(blas_vertices)
-    blas, inst, keep = _instance_args(blas_vertices, bvhs, inst_blas, inst_m)
+    blas, inst, keep = _instance_args(blas_vertices, bvhs, inst_blas, inst_m, geom_ids, texcoords)
     r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
     m = r.shape[0]
     out = {k: np.empty(m, np.float64) for k in ("t", "u", "v")}
     out["prim"] = np.empty(m, np.uint32)
     out["inst"] = np.empty(m, np.uint32)
     out["flags"] = np.empty(m, np.uint8)
-    is_, k2 = _isect(None, None, 128, checker_n)
+    if kind == "alpha" and (textures is None or texcoords is None):
+        raise ValueError("alpha intersector needs per-mesh texcoords and a texture array")
+    is_, k2 = _isect(None, textures, alpha_min, checker_n)
     rc = lib.orc_brute_instanced(blas, len(blas_vertices), inst, len(inst_blas), _ptr(r), m,
                                  KINDS[kind], C.byref(is_), _ptr(out["t"]), _ptr(out["prim"]),
                                  _ptr(out["inst"]), _ptr(out["u"]), _ptr(out["v"]),
@@ -344,17 +361,22 @@ def brute_instanced(blas_vertices, inst_blas, inst_m, rays, kind="default", chec
 
 
 def traverse_instanced(blas_vertices, blas_bvhs, inst_blas, inst_m, tlas: OracleBVH, rays,
-                       kind="default", checker_n=8, any_hit=False, count=True):
-    """float32 two-level traversal (oracle B)."""
+                       kind="default", checker_n=8, any_hit=False, count=True, *,
+                       geom_ids=None, texcoords=None, textures=None, alpha_min=128):
+    """float32 two-level traversal (oracle B).  Alpha: per-mesh geom_ids and
+    texcoords lists, one shared texture array."""
     lib = _load()
-    blas, inst, keep = _instance_args(blas_vertices, blas_bvhs, inst_blas, inst_m)
+    blas, inst, keep = _instance_args(blas_vertices, blas_bvhs, inst_blas, inst_m, geom_ids,
+                                      texcoords)
     r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
     m = r.shape[0]
     out = {k: np.empty(m, np.float32) for k in ("t", "u", "v")}
     out["prim"] = np.empty(m, np.uint32)
     out["inst"] = np.empty(m, np.uint32)
     cnt = np.empty((m, 4), np.uint32) if count else None
-    is_, k2 = _isect(None, None, 128, checker_n)
+    if kind == "alpha" and (textures is None or texcoords is None):
+        raise ValueError("alpha intersector needs per-mesh texcoords and a texture array")
+    is_, k2 = _isect(None, textures, alpha_min, checker_n)
     rc = lib.orc_traverse_instanced(blas, len(blas_vertices), inst, len(inst_blas),
                                     _ptr(tlas.nodes), _ptr(tlas.perm), _ptr(r), m, KINDS[kind],
                                     C.byref(is_), int(bool(any_hit)), _ptr(out["t"]),

@@ -1022,6 +1022,9 @@ int orc_brute_multi(const float *verts, const uint32_t *geom_ids, uint32_t n_tri
  * the leaf's instances are entered in stored order, each by a full
  * traversal of its bottom-level BVH (root box test in object space first)
  * with the shared distance bound, before the top-level stack is popped.
+ * The intersector decides per mesh: the alpha mask (Section 4, Listing 5)
+ * reads the hit mesh's own texture coordinates and texture ids, from one
+ * texture array shared by all meshes.
  * ====================================================================== */
 
 typedef struct {
@@ -1029,6 +1032,8 @@ typedef struct {
     uint32_t n_tris;
     const orc_node *nodes;
     const uint32_t *perm;
+    const uint32_t *geom;     /* alpha: texture id per triangle (NULL: 0) */
+    const float *texcoords;   /* alpha: [n_tris][3][2] of this mesh */
 } orc_blas;
 
 typedef struct {
@@ -1043,7 +1048,9 @@ int orc_brute_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst *i
                         const orc_isect *is, double *t_out, uint32_t *prim_out,
                         uint32_t *inst_out, double *u_out, double *v_out, uint8_t *flags)
 {
-    if (kind == ORC_ALPHA) return -1;
+    if (kind == ORC_ALPHA)
+        for (uint32_t b = 0; b < n_blas; ++b)
+            if (blas[b].n_tris > 0 && !blas[b].texcoords) return -3;
     for (uint32_t i = 0; i < n_rays; ++i) {
         const float *r = rays + 8 * (size_t)i;
         double tmin = r[3], tmax = r[7];
@@ -1056,6 +1063,9 @@ int orc_brute_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst *i
                 const orc_inst *in = inst + j;
                 if (in->blas >= n_blas) return -2;
                 const orc_blas *b = blas + in->blas;
+                /* the alpha mask reads this mesh's texture coordinates */
+                orc_isect bis = *is;
+                bis.texcoords = b->texcoords;
                 const float *m = in->m;
                 d3 o = {m[0] * (double)r[0] + m[1] * (double)r[1] + m[2] * (double)r[2] + m[3],
                         m[4] * (double)r[0] + m[5] * (double)r[1] + m[6] * (double)r[2] + m[7],
@@ -1070,10 +1080,12 @@ int orc_brute_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst *i
                      * float32 bounds by the transform's own rounding */
                     bu = 2.0 * bu + 1e-6;
                     bt = 2.0 * bt + 1e-6 * fabs(t);
+                    const uint32_t g = b->geom ? b->geom[k] : 0;
                     if (pass == 0) {
                         if (!(mg >= 0.0) || !(t > tmin) || !(t < tmax)) continue;
                         double fm;
                         if (kind == ORC_PROCEDURAL && !checker_accept64(is, u, v, &fm)) continue;
+                        if (kind == ORC_ALPHA && !alpha_accept64(&bis, k, g, u, v)) continue;
                         if (t < t1) { t2 = t1; t1 = t; u1 = u; v1 = v; p1 = k; q1 = j; bt1 = bt; }
                         else if (t < t2) t2 = t;
                     } else {
@@ -1084,6 +1096,14 @@ int orc_brute_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst *i
                             double fm;
                             checker_accept64(is, u, v, &fm);
                             if (fm < 2.0 * delta * is->checker_n) fl |= ORC_E_NEAR_FILTER;
+                        }
+                        if (mg > -delta && kind == ORC_ALPHA) {
+                            /* as for a single scene: a texel within reach of
+                             * the texture coordinates' error deciding otherwise */
+                            double wh = is->width > is->height ? is->width : is->height;
+                            double reach_tex = (2.0 * delta + 0x1p-20) * wh;
+                            if (alpha_decision_fragile(&bis, k, g, u, v, reach_tex))
+                                fl |= ORC_E_NEAR_FILTER;
                         }
                         if (p1 != ORC_MISS && !(k == p1 && j == q1) && mg > -delta &&
                             fabs(t - t1) <= bt + bt1)
@@ -1140,6 +1160,8 @@ static int blas_traverse(const inst_job *job, trav_job *tj, ray_state *rs, uint3
     tj->verts = b->verts;
     tj->perm = b->perm;
     tj->nodes = b->nodes;
+    tj->geom = b->geom;
+    tj->is.texcoords = b->texcoords;
     float tn;
     int sp = sp0;
     uint32_t cur = 0;
@@ -1269,7 +1291,9 @@ int orc_traverse_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst
                            int any_hit, float *t, uint32_t *prim, uint32_t *inst_id, float *u,
                            float *v, uint32_t *counters)
 {
-    if (kind == ORC_ALPHA) return -1;
+    if (kind == ORC_ALPHA)
+        for (uint32_t b = 0; b < n_blas; ++b)
+            if (blas[b].n_tris > 0 && !blas[b].texcoords) return -3;
     for (uint32_t q = 0; q < n_inst; ++q)
         if (inst[q].blas >= n_blas) return -2;
     inst_job job;
