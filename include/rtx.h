@@ -262,24 +262,48 @@ rt_status rt_tlas_build(const rt_instance *instances, uint32_t n_inst, void *nod
 /* Bytes of the packed instance table. */
 rt_status rt_instance_table_bytes(uint32_t n_blas, uint32_t n_inst, size_t *bytes);
 
-/* Validates the bottom-level scenes and instances and writes the table into
- * host_table (host, 16-byte aligned); *max_blas_depth receives the deepest
- * bottom-level BVH.  The caller copies the table to device memory. */
-rt_status rt_instance_pack(const rt_scene *blas, uint32_t n_blas, const rt_instance *instances,
-                           uint32_t n_inst, void *host_table, size_t table_bytes,
-                           uint32_t *max_blas_depth);
+/* Texture coordinates of one mesh, for the alpha mask of an instanced scene
+ * (every mesh has its own; the texture array is shared). */
+typedef struct rt_mesh_texcoords {
+    const float *texcoords;   /* device, [n_prims][3][2] by the mesh's input
+                                 triangle index, 8-byte aligned */
+    uint32_t n_prims;         /* must be >= the mesh's n_tris */
+} rt_mesh_texcoords;
+
+/* What rt_instance_pack found out about the meshes; the trace calls take it
+ * with the table. */
+typedef struct rt_instance_info {
+    uint32_t n_blas, n_inst;
+    uint32_t max_blas_depth;  /* deepest bottom-level BVH */
+    uint32_t max_geom_id;     /* largest texture id over the meshes */
+    uint32_t has_texcoords;   /* 1 iff texture coordinates were given for
+                                 every mesh with triangles */
+} rt_instance_info;
+
+/* Validates the bottom-level scenes, their texture coordinates (texcoords:
+ * host array [n_blas], or NULL when no alpha mask will be used; an entry may
+ * be {NULL, 0} for a mesh without triangles) and the instances, writes the
+ * table into host_table (host, 16-byte aligned) and fills *info.  The caller
+ * copies the table to device memory. */
+rt_status rt_instance_pack(const rt_scene *blas, const rt_mesh_texcoords *texcoords,
+                           uint32_t n_blas, const rt_instance *instances, uint32_t n_inst,
+                           void *host_table, size_t table_bytes, rt_instance_info *info);
 
 /* Workspace of rt_trace_instanced. */
-rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, uint32_t max_blas_depth,
+rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, const rt_instance_info *info,
                                              uint32_t n_rays, uint32_t flags, size_t *bytes);
 
 /* Closest-hit (any_hit = 0: out is rt_hit[n_rays], prim_id relative to the
  * hit instance's scene) or any-hit (any_hit = 1: out is uint32[n_rays])
  * query over an instanced scene.  tlas: from rt_tlas_build over the same
- * instances as the device table; inst_ids (device, may be NULL) receives the
- * hit instance or RT_MISS.  RT_ISECT_DEFAULT or RT_ISECT_PROCEDURAL;
+ * instances as the device table; info: from rt_instance_pack of that table;
+ * inst_ids (device, may be NULL) receives the hit instance or RT_MISS.
+ * RT_ISECT_DEFAULT, RT_ISECT_PROCEDURAL, or RT_ISECT_ALPHA with an
+ * rt_alpha_params whose texture array serves every mesh (its texcoords and
+ * n_texcoord_prims are ignored: each mesh uses the texture coordinates given
+ * to rt_instance_pack, and texture ids come from each mesh's rt_bvh_build).
  * RT_FLAG_COUNT counts the box tests of both levels and the triangle tests. */
-rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, uint32_t max_blas_depth,
+rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, const rt_instance_info *info,
                              const rt_ray *rays, uint32_t n_rays, rt_isect_kind kind,
                              const void *params, uint32_t flags, int any_hit, void *out,
                              uint32_t *inst_ids, rt_counters *counters, void *workspace,

@@ -44,6 +44,7 @@ struct alignas(16) blas_record {
     const float4 *tris;
     float root_lo[3], root_hi[3];
     uint32_t root_ref, n_tris;
+    const float2 *texcoords;  // alpha mask: this mesh's texture coordinates
     uint32_t pad[2];
 };
 static_assert(sizeof(blas_record) == 64, "blas record");

@@ -108,6 +108,7 @@ struct InstancedRequest {
     uint32_t n_rays;
     rt_isect_kind kind;
     rt_procedural_params checker;
+    rt_alpha_params alpha;  // textures for every mesh (texcoords per mesh)
     bool count, any;
     void *out;             // rt_hit* or uint32_t* (any)
     uint32_t *inst_ids;    // may be null

@@ -782,6 +782,8 @@ __global__ __launch_bounds__(64) void trace_instanced_kernel(kernel_args a, cons
             bv.root_hi[2] = br.root_hi[2];
             bv.root_ref = br.root_ref;
             bv.n_tris = br.n_tris;
+            // the alpha mask reads the texture coordinates of the entered mesh
+            if constexpr (std::is_base_of_v<alpha_intersector, Isect>) isect.p.texcoords = br.texcoords;
             const float t_before = ro.tmax;
             st.floor = st.sp;
             if (root_step(bv, ro, isect)) {

@@ -369,15 +369,15 @@ rt_status rt_instance_table_bytes(uint32_t n_blas, uint32_t n_inst, size_t *byte
     return RT_OK;
 }
 
-rt_status rt_instance_pack(const rt_scene *blas, uint32_t n_blas, const rt_instance *instances,
-                           uint32_t n_inst, void *host_table, size_t table_bytes,
-                           uint32_t *max_blas_depth)
+rt_status rt_instance_pack(const rt_scene *blas, const rt_mesh_texcoords *texcoords,
+                           uint32_t n_blas, const rt_instance *instances, uint32_t n_inst,
+                           void *host_table, size_t table_bytes, rt_instance_info *info)
 {
     size_t need = 0;
     rt_status st = rt_instance_table_bytes(n_blas, n_inst, &need);
     if (st != RT_OK) return st;
-    if ((n_blas && !blas) || (n_inst && !instances) || !host_table || !max_blas_depth)
-        return fail(RT_ERR_INVALID_ARG, "blas/instances/table/max_blas_depth are NULL");
+    if ((n_blas && !blas) || (n_inst && !instances) || !host_table || !info)
+        return fail(RT_ERR_INVALID_ARG, "blas/instances/table/info are NULL");
     if (table_bytes < need) return fail(RT_ERR_INVALID_ARG, "table smaller than rt_instance_table_bytes");
     if (!aligned(host_table, 16)) return fail(RT_ERR_MISALIGNED, "table not 16-byte aligned");
     unsigned char *t = static_cast<unsigned char *>(host_table);
@@ -387,10 +387,14 @@ rt_status rt_instance_pack(const rt_scene *blas, uint32_t n_blas, const rt_insta
     hdr[1] = n_inst;
     blas_record *br = reinterpret_cast<blas_record *>(t + instance_blas_offset());
     instance_record *ir = reinterpret_cast<instance_record *>(t + instance_records_offset(n_blas));
-    uint32_t depth = 0;
+    rt_instance_info out{};
+    out.n_blas = n_blas;
+    out.n_inst = n_inst;
+    out.has_texcoords = texcoords ? 1u : 0u;
     for (uint32_t b = 0; b < n_blas; ++b) {
+        const std::string which = "bottom-level scene " + std::to_string(b);
         st = check_scene(&blas[b]);
-        if (st != RT_OK) return fail(st, "bottom-level scene " + std::to_string(b) + ": " + g_last_error);
+        if (st != RT_OK) return fail(st, which + ": " + g_last_error);
         const rt_bvh_info &in = blas[b].info;
         br[b].nodes = static_cast<const float4 *>(blas[b].nodes);
         br[b].tris = static_cast<const float4 *>(blas[b].tris);
@@ -400,7 +404,16 @@ rt_status rt_instance_pack(const rt_scene *blas, uint32_t n_blas, const rt_insta
         }
         br[b].root_ref = in.root_ref;
         br[b].n_tris = in.n_tris;
-        depth = in.max_depth > depth ? in.max_depth : depth;
+        if (texcoords && in.n_tris > 0) {
+            const rt_mesh_texcoords &tc = texcoords[b];
+            if (!tc.texcoords || tc.n_prims < in.n_tris)
+                return fail(RT_ERR_INVALID_ARG, which + ": texcoords NULL or covering fewer triangles");
+            if (!aligned(tc.texcoords, 8))
+                return fail(RT_ERR_MISALIGNED, which + ": texcoords not 8-byte aligned");
+            br[b].texcoords = reinterpret_cast<const float2 *>(tc.texcoords);
+        }
+        out.max_blas_depth = in.max_depth > out.max_blas_depth ? in.max_depth : out.max_blas_depth;
+        if (in.n_tris > 0 && in.max_geom_id > out.max_geom_id) out.max_geom_id = in.max_geom_id;
     }
     for (uint32_t q = 0; q < n_inst; ++q) {
         if (instances[q].blas >= n_blas)
@@ -412,7 +425,7 @@ rt_status rt_instance_pack(const rt_scene *blas, uint32_t n_blas, const rt_insta
             ir[q].m[k] = instances[q].object_from_world[k];
         }
     }
-    *max_blas_depth = depth;
+    *info = out;
     g_last_error.clear();
     return RT_OK;
 }
@@ -427,7 +440,14 @@ static size_t instanced_workspace(const rt_bvh_info &tlas, uint32_t max_blas_dep
     return size_t(depth > cap ? depth - cap : 0) * threads * sizeof(uint64_t);
 }
 
-rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, uint32_t max_blas_depth,
+static rt_status check_instance_info(const rt_instance_info *info)
+{
+    if (!info) return fail(RT_ERR_INVALID_ARG, "info is NULL");
+    if (info->max_blas_depth >= 128) return fail(RT_ERR_INVALID_ARG, "max_blas_depth must be < 128");
+    return RT_OK;
+}
+
+rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, const rt_instance_info *info,
                                              uint32_t n_rays, uint32_t flags, size_t *bytes)
 {
     g_last_error.clear();
@@ -435,12 +455,13 @@ rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, uint32_t max_
     rt_status st = check_scene(tlas);
     if (st != RT_OK) return st;
     if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
-    if (max_blas_depth >= 128) return fail(RT_ERR_INVALID_ARG, "max_blas_depth must be < 128");
-    *bytes = instanced_workspace(tlas->info, max_blas_depth, n_rays);
+    st = check_instance_info(info);
+    if (st != RT_OK) return st;
+    *bytes = instanced_workspace(tlas->info, info->max_blas_depth, n_rays);
     return RT_OK;
 }
 
-rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, uint32_t max_blas_depth,
+rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, const rt_instance_info *info,
                              const rt_ray *rays, uint32_t n_rays, rt_isect_kind kind,
                              const void *params, uint32_t flags, int any_hit, void *out,
                              uint32_t *inst_ids, rt_counters *counters, void *workspace,
@@ -450,7 +471,8 @@ rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, uint32_t m
     rt_status st = check_scene(tlas);
     if (st != RT_OK) return st;
     if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
-    if (max_blas_depth >= 128) return fail(RT_ERR_INVALID_ARG, "max_blas_depth must be < 128");
+    st = check_instance_info(info);
+    if (st != RT_OK) return st;
     InstancedRequest q{};
     q.kind = kind;
     if (kind == RT_ISECT_PROCEDURAL) {
@@ -458,8 +480,20 @@ rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, uint32_t m
         q.checker = *static_cast<const rt_procedural_params *>(params);
         if (q.checker.checker_n < 1 || q.checker.checker_n > 65536)
             return fail(RT_ERR_INVALID_ARG, "checker_n must be within 1..65536");
+    } else if (kind == RT_ISECT_ALPHA) {
+        if (!params) return fail(RT_ERR_INVALID_ARG, "alpha intersector needs rt_alpha_params");
+        q.alpha = *static_cast<const rt_alpha_params *>(params);
+        if (!info->has_texcoords)
+            return fail(RT_ERR_INVALID_ARG, "the table was packed without texture coordinates");
+        if (!q.alpha.textures || !aligned(q.alpha.textures, 4))
+            return fail(RT_ERR_INVALID_ARG, "alpha textures NULL or misaligned");
+        if (q.alpha.width < 1 || q.alpha.height < 1 || q.alpha.alpha_min > 255)
+            return fail(RT_ERR_INVALID_ARG, "alpha texture size or alpha_min out of range");
+        if (q.alpha.n_tex <= info->max_geom_id)
+            return fail(RT_ERR_INVALID_ARG, "a mesh's geom_id exceeds the texture count");
+        q.alpha.texcoords = nullptr;  // per mesh, from the table
     } else if (kind != RT_ISECT_DEFAULT) {
-        return fail(RT_ERR_UNSUPPORTED, "instanced traversal supports the default and procedural intersectors");
+        return fail(RT_ERR_UNSUPPORTED, "unknown intersector kind");
     }
     if (n_rays == 0) return RT_OK;
     if (n_rays > RT_MAX_RAYS) return fail(RT_ERR_INVALID_ARG, "more than 2^31 rays in one call");
@@ -470,7 +504,7 @@ rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, uint32_t m
     const bool count = (flags & RT_FLAG_COUNT) != 0;
     if (count && (!counters || !aligned(counters, 16)))
         return fail(RT_ERR_INVALID_ARG, "RT_FLAG_COUNT needs a 16-byte aligned counters array");
-    const size_t need = instanced_workspace(tlas->info, max_blas_depth, n_rays);
+    const size_t need = instanced_workspace(tlas->info, info->max_blas_depth, n_rays);
     if (need > 0 && (!workspace || workspace_bytes < need || !aligned(workspace, 16)))
         return fail(RT_ERR_WORKSPACE, "workspace smaller than rt_trace_instanced_workspace_bytes");
     q.tlas = tlas;

@@ -217,10 +217,19 @@ rt_status launch_instanced(const InstancedRequest &q, const char **err)
     case RT_ISECT_PROCEDURAL:
         return launch_inst_count<checker_intersector>(q, a, checker_intersector::params{q.checker.checker_n},
                                                       err);
+    case RT_ISECT_ALPHA: {
+        alpha_intersector::params p;
+        p.texcoords = nullptr;  // set per bottom-level scene at instance entry
+        p.textures = q.alpha.textures;
+        p.width = q.alpha.width;
+        p.height = q.alpha.height;
+        p.alpha_min = q.alpha.alpha_min;
+        return launch_inst_count<alpha_intersector>(q, a, p, err);
+    }
     default:
         break;
     }
-    *err = "instanced traversal supports the default and procedural intersectors";
+    *err = "unknown intersector kind";
     return RT_ERR_UNSUPPORTED;
 }
 

@@ -61,6 +61,15 @@ class rt_instance(C.Structure):
                 ("world_lo", C.c_float * 3), ("world_hi", C.c_float * 3)]
 
 
+class rt_mesh_texcoords(C.Structure):
+    _fields_ = [("texcoords", C.c_void_p), ("n_prims", C.c_uint32)]
+
+
+class rt_instance_info(C.Structure):
+    _fields_ = [("n_blas", C.c_uint32), ("n_inst", C.c_uint32), ("max_blas_depth", C.c_uint32),
+                ("max_geom_id", C.c_uint32), ("has_texcoords", C.c_uint32)]
+
+
 class rt_batch_entry(C.Structure):
     _fields_ = [("scene", rt_scene), ("n_rays", C.c_uint32), ("alpha", rt_alpha_params)]
 
@@ -89,11 +98,12 @@ SIGNATURES = [
                                  _SZ, _P]),
     ("rt_tlas_build", C.c_int, [_P, _U32, _P, _SZ, _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_instance_table_bytes", C.c_int, [_U32, _U32, C.POINTER(_SZ)]),
-    ("rt_instance_pack", C.c_int, [_P, _U32, _P, _U32, _P, _SZ, C.POINTER(_U32)]),
-    ("rt_trace_instanced_workspace_bytes", C.c_int, [C.POINTER(rt_scene), _U32, _U32, _U32,
+    ("rt_instance_pack", C.c_int, [_P, _P, _U32, _P, _U32, _P, _SZ, C.POINTER(rt_instance_info)]),
+    ("rt_trace_instanced_workspace_bytes", C.c_int, [C.POINTER(rt_scene),
+                                                     C.POINTER(rt_instance_info), _U32, _U32,
                                                      C.POINTER(_SZ)]),
-    ("rt_trace_instanced", C.c_int, [C.POINTER(rt_scene), _P, _U32, _P, _U32, C.c_int, _P, _U32,
-                                     C.c_int, _P, _P, _P, _P, _SZ, _P]),
+    ("rt_trace_instanced", C.c_int, [C.POINTER(rt_scene), _P, C.POINTER(rt_instance_info), _P,
+                                     _U32, C.c_int, _P, _U32, C.c_int, _P, _P, _P, _P, _SZ, _P]),
     ("rt_trace_multi", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _U32, _P, _P,
                                  _P, _P, _SZ, _P]),
     ("rt_hit_backward", C.c_int, [_P, _P, _P, _U32, _P, _U32, _P, _U32, _P, _P, _P]),
@@ -258,33 +268,64 @@ def rt_tlas_build(inst_blas, inst_m, world_lo, world_hi):
     return nodes.view(np.uint8)[: info.n_nodes * RT_NODE_BYTES], tris.view(np.uint8)[: n * RT_TRI_BYTES], info
 
 
-def rt_instance_pack(blas_views, inst_blas, inst_m, world_lo, world_hi):
-    """Packs the instance table on the host; returns (table uint8, max_blas_depth)."""
+def rt_instance_pack(blas_views, inst_blas, inst_m, world_lo, world_hi, texcoords=None):
+    """Packs the instance table on the host; returns (table uint8, rt_instance_info).
+
+    ``texcoords``: None, or one (device pointer or None, n_prims) pair per
+    bottom-level scene, for the alpha mask."""
     lib = load_library()
     arr, n = _instances(inst_blas, inst_m, world_lo, world_hi)
     nb = len(blas_views)
     scenes = (rt_scene * max(1, nb))(*blas_views)
+    tcs = None
+    if texcoords is not None:
+        if len(texcoords) != nb:
+            raise ValueError("one texcoords entry per bottom-level scene")
+        tcs = (rt_mesh_texcoords * max(1, nb))(
+            *[rt_mesh_texcoords(p, int(m)) for p, m in texcoords])
     b = C.c_size_t()
     _check(lib.rt_instance_table_bytes(nb, n, C.byref(b)), "rt_instance_table_bytes")
     table = np.zeros((b.value + 15) // 16, dtype=np.dtype((np.void, 16)))
-    depth = C.c_uint32()
-    _check(lib.rt_instance_pack(C.cast(scenes, C.c_void_p), nb, C.cast(arr, C.c_void_p), n,
-                                table.ctypes.data, b.value, C.byref(depth)), "rt_instance_pack")
-    return table.view(np.uint8)[: b.value], int(depth.value)
+    info = rt_instance_info()
+    _check(lib.rt_instance_pack(C.cast(scenes, C.c_void_p),
+                                None if tcs is None else C.cast(tcs, C.c_void_p), nb,
+                                C.cast(arr, C.c_void_p), n, table.ctypes.data, b.value,
+                                C.byref(info)), "rt_instance_pack")
+    return table.view(np.uint8)[: b.value], info
 
 
 class InstancedScene:
-    """Bottom-level scenes + instances: a device top-level BVH and table."""
+    """Bottom-level scenes + instances: a device top-level BVH and table.
 
-    def __init__(self, blas_vertices, inst_blas, inst_m, world_lo, world_hi, device="cuda"):
+    For the alpha mask give every mesh its texture ids (``geom_ids``, one
+    list entry per mesh, as in ``upload_scene``) and texture coordinates
+    (``texcoords``, [n_tris, 3, 2] per mesh), and ``textures`` shared by all
+    meshes ([n_tex, H, W] RGBA8 packed in uint32)."""
+
+    def __init__(self, blas_vertices, inst_blas, inst_m, world_lo, world_hi, device="cuda", *,
+                 geom_ids=None, texcoords=None, textures=None):
         torch = _torch()
-        self.blas = [upload_scene(v, device=device) for v in blas_vertices]
+        nb = len(blas_vertices)
+        gids = geom_ids if geom_ids is not None else [None] * nb
+        tcs = texcoords if texcoords is not None else [None] * nb
+        if len(gids) != nb or len(tcs) != nb:
+            raise ValueError("geom_ids/texcoords need one entry per bottom-level scene")
+        self.blas = [upload_scene(v, g, t, device=device)
+                     for v, g, t in zip(blas_vertices, gids, tcs)]
         nodes, tris, self.tlas_info = rt_tlas_build(inst_blas, inst_m, world_lo, world_hi)
         self.tlas_nodes = torch.from_numpy(nodes.copy()).to(device) if nodes.size else None
         self.tlas_tris = torch.from_numpy(tris.copy()).to(device)
-        table, self.max_blas_depth = rt_instance_pack([b.view for b in self.blas], inst_blas,
-                                                      inst_m, world_lo, world_hi)
+        mesh_tc = None
+        if texcoords is not None:
+            mesh_tc = [(b.texcoords.data_ptr() if b.texcoords is not None and b.texcoords.numel()
+                        else None, 0 if b.texcoords is None else b.texcoords.numel() // 6)
+                       for b in self.blas]
+        table, self.info = rt_instance_pack([b.view for b in self.blas], inst_blas, inst_m,
+                                            world_lo, world_hi, mesh_tc)
+        self.max_blas_depth = int(self.info.max_blas_depth)
         self.table = torch.from_numpy(table.copy()).to(device)
+        self.textures = None if textures is None else torch.from_numpy(
+            np.ascontiguousarray(textures, np.uint32).view(np.int32)).to(device)
 
     @property
     def tlas(self) -> rt_scene:
@@ -294,8 +335,21 @@ class InstancedScene:
         sc.info = self.tlas_info
         return sc
 
+    def _alpha_params(self, alpha_min: int) -> rt_alpha_params:
+        if self.textures is None:
+            raise ValueError("the alpha mask needs textures")
+        p = rt_alpha_params()
+        p.texcoords = None
+        p.n_texcoord_prims = 0
+        p.textures = self.textures.data_ptr()
+        p.n_tex = int(self.textures.shape[0])
+        p.height = int(self.textures.shape[1])
+        p.width = int(self.textures.shape[2])
+        p.alpha_min = int(alpha_min)
+        return p
+
     def trace(self, rays, intersector="default", *, any_hit=False, count=False, checker_n=8,
-              out=None, inst_ids=None, workspace=None, stream=None):
+              alpha_min=128, out=None, inst_ids=None, workspace=None, stream=None):
         """Returns (hits [N,4] float32 or occluders [N] int32, inst_ids [N] int32[,
         counters])."""
         torch = _torch()
@@ -311,19 +365,21 @@ class InstancedScene:
         if intersector == "procedural":
             params = rt_procedural_params()
             params.checker_n = int(checker_n)
+        elif intersector == "alpha":
+            params = self._alpha_params(alpha_min)
         elif intersector != "default":
-            raise ValueError("instancing supports the default and procedural intersectors")
+            raise ValueError(f"unknown intersector {intersector!r}")
         flags = RT_FLAG_COUNT if count else 0
         tl = self.tlas
         lib = load_library()
         b = C.c_size_t()
-        _check(lib.rt_trace_instanced_workspace_bytes(C.byref(tl), self.max_blas_depth, n, flags,
+        _check(lib.rt_trace_instanced_workspace_bytes(C.byref(tl), C.byref(self.info), n, flags,
                                                       C.byref(b)), "rt_trace_instanced_workspace_bytes")
         ws = workspace or Workspace(dev)
         wptr, wbytes = ws.get(b.value)
         s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
         _check(lib.rt_trace_instanced(
-            C.byref(tl), self.table.data_ptr(), self.max_blas_depth, rays.data_ptr(), n,
+            C.byref(tl), self.table.data_ptr(), C.byref(self.info), rays.data_ptr(), n,
             KINDS[intersector], None if params is None else C.cast(C.pointer(params), C.c_void_p),
             flags, int(bool(any_hit)), out.data_ptr(), inst_ids.data_ptr(),
             counters.data_ptr() if count else None, wptr, wbytes, s), "rt_trace_instanced")

@@ -351,10 +351,11 @@ def test_tlas_build_matches_oracle_box_tree(oracle_lib):
 def test_instance_pack_validation(lib):
     from paper_1912_12786_amd import workloads as W
     wl = W.instanced(5, 8, 8)
-    blas = [_fake_scene(), _fake_scene(max_depth=9), _fake_scene(max_depth=4)]
-    table, depth = rtx.rt_instance_pack(blas, wl["inst_blas"], wl["inst_m"], wl["world_lo"],
-                                        wl["world_hi"])
-    assert depth == 9
+    blas = [_fake_scene(), _fake_scene(max_depth=9, max_geom=6), _fake_scene(max_depth=4)]
+    table, info = rtx.rt_instance_pack(blas, wl["inst_blas"], wl["inst_m"], wl["world_lo"],
+                                       wl["world_hi"])
+    assert (info.n_blas, info.n_inst, info.max_blas_depth, info.max_geom_id,
+            info.has_texcoords) == (3, 5, 9, 6, 0)
     u32 = table.view(np.uint32)
     assert u32[0] == 3 and u32[1] == 5
     rec = table[64 + 3 * 64:].view(np.float32).reshape(5, 16)
@@ -366,6 +367,54 @@ def test_instance_pack_validation(lib):
     with pytest.raises(rtx.RtxError, match="bad world box"):
         rtx.rt_tlas_build(np.zeros(1, np.uint32), wl["inst_m"][:1], wl["world_hi"][:1],
                           wl["world_lo"][:1])
+
+
+def test_instance_pack_texcoords(lib):
+    from paper_1912_12786_amd import workloads as W
+    wl = W.instanced(5, 8, 8)
+    blas = [_fake_scene(), _fake_scene(max_geom=3), _fake_scene(n_tris=0, max_geom=99)]
+    tcs = [(0x50000, 10), (0x60000, 12), (None, 0)]
+    table, info = rtx.rt_instance_pack(blas, wl["inst_blas"], wl["inst_m"], wl["world_lo"],
+                                       wl["world_hi"], tcs)
+    # the empty mesh's geom id does not count
+    assert info.has_texcoords == 1 and info.max_geom_id == 3
+    # blas_record: nodes, tris, root box, root_ref, n_tris, texcoords
+    rec = table[64:64 + 3 * 64].view(np.uint64).reshape(3, 8)
+    assert list(rec[:, 6]) == [0x50000, 0x60000, 0]
+    with pytest.raises(rtx.RtxError, match="bottom-level scene 1: texcoords NULL or covering fewer"):
+        rtx.rt_instance_pack(blas, wl["inst_blas"], wl["inst_m"], wl["world_lo"], wl["world_hi"],
+                             [(0x50000, 10), (0x60000, 9), (None, 0)])
+    with pytest.raises(rtx.RtxError, match="bottom-level scene 0: texcoords NULL"):
+        rtx.rt_instance_pack(blas, wl["inst_blas"], wl["inst_m"], wl["world_lo"], wl["world_hi"],
+                             [(None, 10), (0x60000, 12), (None, 0)])
+    with pytest.raises(rtx.RtxError, match="not 8-byte aligned"):
+        rtx.rt_instance_pack(blas, wl["inst_blas"], wl["inst_m"], wl["world_lo"], wl["world_hi"],
+                             [(0x50004, 10), (0x60000, 12), (None, 0)])
+
+    # argument checks of the alpha query run before any launch (zero rays)
+    tl = _fake_scene()
+    ap = rtx.rt_alpha_params()
+    ap.textures, ap.n_tex, ap.width, ap.height, ap.alpha_min = 0x70000, 4, 8, 8, 128
+
+    def call(inf, params, kind=rtx.KINDS["alpha"]):
+        p = None if params is None else C.cast(C.pointer(params), C.c_void_p)
+        return lib.rt_trace_instanced(C.byref(tl), 0x80000, C.byref(inf), None, 0, kind, p, 0, 0,
+                                      None, None, None, None, 0, None)
+
+    assert call(info, ap) == 0
+    _, bare = rtx.rt_instance_pack(blas, wl["inst_blas"], wl["inst_m"], wl["world_lo"],
+                                   wl["world_hi"])
+    assert call(bare, ap) == -1
+    assert b"without texture coordinates" in lib.rt_last_error()
+    ap.n_tex = 3
+    assert call(info, ap) == -1
+    assert b"exceeds the texture count" in lib.rt_last_error()
+    ap.n_tex = 4
+    assert call(info, None) == -1
+    ap.alpha_min = 256
+    assert call(info, ap) == -1
+    assert lib.rt_trace_instanced(C.byref(tl), 0x80000, None, None, 0, 0, None, 0, 0, None, None,
+                                  None, None, 0, None) == -1
 
 
 def test_zero_rays_is_a_no_op(lib):

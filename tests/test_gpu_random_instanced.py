@@ -1,7 +1,8 @@
 """Seeded random instanced scenes on the GPU against oracle B's two-level
 traversal, bit for bit (hits, instance ids, counters): several meshes,
 duplicated instances (exact ties between instances), mirrored and strongly
-scaled maps, empty meshes, rays aimed at instances and stray rays."""
+scaled maps, empty meshes, rays aimed at instances and stray rays; the three
+built-in masks (alpha with per-mesh texture ids and coordinates)."""
 import numpy as np
 import pytest
 
@@ -65,16 +66,25 @@ def random_instances(seed):
 def test_random_instanced_bit_exact(env, oracle_lib, seed):
     torch, rtx = env
     meshes, ids, maps, lo, hi, rays = random_instances(seed)
-    kind = ["default", "procedural"][seed % 2]
-    any_hit = bool((seed // 2) % 2)
+    kind = ["default", "procedural", "alpha"][seed % 3]
+    any_hit = bool((seed // 3) % 2)
+    akw = {}
+    if kind == "alpha":
+        rng = np.random.default_rng(6000 + seed)
+        n_tex = int(rng.integers(1, 5))
+        akw = dict(geom_ids=[rng.integers(0, n_tex, size=m.shape[0]).astype(np.uint32)
+                             for m in meshes],
+                   texcoords=[rng.uniform(-0.2, 1.2, size=(m.shape[0], 3, 2)).astype(np.float32)
+                              for m in meshes],
+                   textures=W.alpha_textures(n_tex, int(rng.integers(16, 65)), 6100 + seed))
     announce(f"random instanced seed={seed} meshes={len(meshes)} instances={len(ids)} "
              f"rays={rays.shape[0]} kind={kind} any={any_hit}")
-    sc = rtx.InstancedScene(meshes, ids, maps, lo, hi)
+    sc = rtx.InstancedScene(meshes, ids, maps, lo, hi, **akw)
     out, inst, cnt = sc.trace(torch.from_numpy(rays).cuda(), kind, any_hit=any_hit, count=True)
     torch.cuda.synchronize()
     bvhs = [oracle_lib.build_bvh(b) for b in meshes]
     tl = oracle_lib.build_tlas(lo, hi)
-    B = oracle_lib.traverse_instanced(meshes, bvhs, ids, maps, tl, rays, kind, any_hit=any_hit)
+    B = oracle_lib.traverse_instanced(meshes, bvhs, ids, maps, tl, rays, kind, any_hit=any_hit, **akw)
     P.assert_counters_vs_b(cnt, B, f"random instanced {seed}")
     assert np.array_equal(inst.cpu().numpy().view(np.uint32), B["inst"])
     if any_hit:
