@@ -73,13 +73,22 @@ def copy_calibration():
                       "launches": 3}), flush=True)
 
 
-def tile_order(wl, tile: int = 8) -> np.ndarray:
+def _morton2(x: np.ndarray, y: np.ndarray, bits: int) -> np.ndarray:
+    """Interleaves the low ``bits`` bits of x (even positions) and y (odd)."""
+    k = np.zeros_like(x)
+    for b in range(bits):
+        k |= ((x >> b) & 1) << (2 * b) | ((y >> b) & 1) << (2 * b + 1)
+    return k
+
+
+def tile_order(wl, tile: int = 8, morton: bool = False) -> np.ndarray:
     """Permutation of a pinhole workload's primary rays (scanline order, the
-    first width x height rays) into tile x tile pixel blocks; other rays keep
-    their place."""
+    first width x height rays) into tile x tile pixel blocks (row-major inside
+    a block, or Z-order with ``morton``); other rays keep their place."""
     w, h = int(wl.extra["width"]), int(wl.extra["height"])
     y, x = np.divmod(np.arange(w * h), w)
-    key = ((y // tile) * ((w + tile - 1) // tile) + x // tile) * tile * tile + (y % tile) * tile + x % tile
+    inner = _morton2(x % tile, y % tile, int(tile).bit_length() - 1) if morton else (y % tile) * tile + x % tile
+    key = ((y // tile) * ((w + tile - 1) // tile) + x // tile) * tile * tile + inner
     order = np.argsort(key, kind="stable")
     return np.concatenate([order, np.arange(w * h, wl.n_rays)])
 
@@ -332,40 +341,50 @@ def bench_dispatch(args):
 
 def bench_instanced(args):
     """Object instancing: 2000 instances of three meshes at 1080p, closest hit
-    with the default intersector, against the same scene flattened into one
-    BVH of world-space triangles."""
+    (accept-all, or the alpha mask with per-mesh texture data), against the
+    same scene flattened into one BVH of world-space triangles."""
     import torch
     from paper_1912_12786_amd import rtx
     from paper_1912_12786_amd import workloads as W
     dev = torch.device("cuda:0")
+    kind = args.intersector or "default"
     wl = W.instanced(2000)
+    akw = W.instanced_alpha(wl) if kind == "alpha" else {}
     isc = rtx.InstancedScene(wl["blas"], wl["inst_blas"], wl["inst_m"], wl["world_lo"],
-                             wl["world_hi"], device=dev)
+                             wl["world_hi"], device=dev, **akw)
     wfo = wl["world_from_object"]
     flat = np.concatenate([np.einsum("ij,tkj->tki", wfo[q, :, :3],
                                      wl["blas"][b].astype(np.float64)) + wfo[q, :, 3]
                            for q, b in enumerate(wl["inst_blas"])]).astype(np.float32)
-    fsc = rtx.upload_scene(flat, device=dev)
+    if akw:
+        fsc = rtx.upload_scene(flat, np.concatenate([akw["geom_ids"][b] for b in wl["inst_blas"]]),
+                               np.concatenate([akw["texcoords"][b] for b in wl["inst_blas"]]),
+                               akw["textures"], device=dev)
+    else:
+        fsc = rtx.upload_scene(flat, device=dev)
     rays = torch.from_numpy(wl["rays"]).to(dev)
     n = rays.shape[0]
     out = torch.empty((n, 4), dtype=torch.float32, device=dev)
     ids = torch.empty((n,), dtype=torch.int32, device=dev)
     ws = rtx.Workspace(dev)
     stream = torch.cuda.current_stream(dev)
-    ms_i = timed(lambda: isc.trace(rays, out=out, inst_ids=ids, workspace=ws), args.steps,
+    ms_i = timed(lambda: isc.trace(rays, kind, out=out, inst_ids=ids, workspace=ws), args.steps,
                  args.warmup, stream)
-    ms_f = timed(lambda: rtx.trace(fsc, rays, out=out, workspace=ws), args.steps, args.warmup,
-                 stream)
+    ms_f = timed(lambda: rtx.trace(fsc, rays, kind, out=out, workspace=ws), args.steps,
+                 args.warmup, stream)
     bytes_i = sum(int(b.tris.numel()) + (int(b.nodes.numel()) if b.nodes is not None else 0)
                   for b in isc.blas) + int(isc.tlas_tris.numel()) + int(isc.tlas_nodes.numel()) \
         + int(isc.table.numel())
     bytes_f = int(fsc.tris.numel()) + int(fsc.nodes.numel())
+    if akw:  # texture coordinates (the shared textures are the same on both sides)
+        bytes_i += sum(int(b.texcoords.numel()) * 4 for b in isc.blas)
+        bytes_f += int(fsc.texcoords.numel()) * 4
     print(json.dumps({
-        "metric": "Mrays/s closest hit, instanced two-level BVH vs the flattened scene",
+        "metric": f"Mrays/s closest hit ({kind}), instanced two-level BVH vs the flattened scene",
         "value": round(n / ms_i / 1e3, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl["name"], "n_instances": 2000, "n_rays": n,
-                   "world_tris": int(flat.shape[0])},
+                   "world_tris": int(flat.shape[0]), "intersector": kind},
         "instanced_mrays_s": round(n / ms_i / 1e3, 2), "flattened_mrays_s": round(n / ms_f / 1e3, 2),
         "ms": {"instanced": round(ms_i, 4), "flattened": round(ms_f, 4)},
         "scene_bytes": {"instanced": bytes_i, "flattened": bytes_f}}), flush=True)
@@ -383,9 +402,9 @@ def main():
     ap.add_argument("--intersector", default=None, choices=["alpha", "default", "procedural"],
                     help="default: alpha on billboards, accept-all on tiny, procedural checker "
                          "on spheres")
-    ap.add_argument("--ray-order", default="scanline", choices=["scanline", "tiled"],
+    ap.add_argument("--ray-order", default="scanline", choices=["scanline", "tiled", "morton"],
                     help="tiled: primary rays reordered into 8x8 pixel tiles before upload "
-                         "(hits come back in that order)")
+                         "(hits come back in that order); morton: the same tiles in Z-order")
     ap.add_argument("--query", default="closest", choices=["closest", "any", "multi"])
     ap.add_argument("--k", type=int, default=4, help="hits kept per ray by --query multi")
     ap.add_argument("--workload", default="billboards",
@@ -430,8 +449,8 @@ def main():
         f"gcn={getattr(props, 'gcnArchName', '?')}")
     t0 = time.perf_counter()
     wl = {"billboards": W.billboards, "tiny": W.tiny, "spheres": W.spheres}[args.workload]()
-    if args.ray_order == "tiled":
-        wl.rays = wl.rays[tile_order(wl)]
+    if args.ray_order != "scanline":
+        wl.rays = wl.rays[tile_order(wl, morton=args.ray_order == "morton")]
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     scene = rtx.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures, device=dev)
@@ -537,7 +556,8 @@ def main():
             "alpha_threshold": "0.5 (alpha byte >= 128)" if kind == "alpha" else None,
             "query": query if query != "multi" else f"multi (k={args.k})",
             "textures": "16 x 256x256 RGBA8" if wl.textures is not None else None,
-            "ray_order": "8x8 tiles" if args.ray_order == "tiled" else "scanline",
+            "ray_order": {"tiled": "8x8 tiles", "morton": "8x8 tiles, Z-order inside"}.get(
+                args.ray_order, "scanline"),
             "bvh": f"binary SAH, {scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}",
             "launch_shape": ([int(x) for x in args.shape.split(",")] if args.shape
                              else list(rtx.rt_launch_shapes()[0])),

@@ -604,3 +604,22 @@ def instanced(n_instances: int = 2000, width: int = 1920, height: int = 1080):
     return {"blas": blas, "inst_blas": ids, "inst_m": m, "world_lo": lo, "world_hi": hi,
             "rays": rays, "world_from_object": wfo,
             "name": f"instanced_{n_instances}_x3_meshes_{width}x{height}"}
+
+
+def instanced_alpha(wl, n_tex: int = 16, tex_size: int = 256) -> dict:
+    """Alpha-mask inputs for an ``instanced`` workload: in every mesh each pair
+    of consecutive triangles gets one texture id in U{0..n_tex-1} and the
+    billboard texture coordinates ``(0,0),(1,0),(1,1)`` / ``(0,0),(1,1),(0,1)``;
+    the textures are the billboard workload's.  Returns the keyword arguments
+    of ``InstancedScene`` (``geom_ids``, ``texcoords``, ``textures``)."""
+    g = rng_for(CFG_BATCHED, 903)
+    geoms, tcs = [], []
+    for mesh in wl["blas"]:
+        n = int(mesh.shape[0])
+        geoms.append(np.repeat(g.integers(0, n_tex, size=(n + 1) // 2), 2)[:n].astype(np.uint32))
+        tc = np.empty((n, 3, 2), np.float32)
+        tc[0::2] = np.array([[0, 0], [1, 0], [1, 1]], np.float32)
+        tc[1::2] = np.array([[0, 0], [1, 1], [0, 1]], np.float32)
+        tcs.append(tc)
+    tex = alpha_textures(n_tex, tex_size, seed_for(CFG_BILLBOARDS, STREAM_TEXTURES))
+    return {"geom_ids": geoms, "texcoords": tcs, "textures": tex}

@@ -134,3 +134,35 @@ def test_identity_instance_equals_plain_trace(env):
     plain = rtx.trace(rtx.upload_scene(wl.vertices), rays)
     torch.cuda.synchronize()
     assert torch.equal(hits.view(torch.int32), plain.view(torch.int32))
+
+
+@pytest.mark.parametrize("kind", ["default", "alpha"])
+def test_instanced_bench_config_sampled(env, oracle_lib, kind):
+    """The benchmark's instanced launch (2,000 instances, 1920x1080 rays, one
+    call over all rays) against oracle B's two-level traversal on every 61st
+    ray: hits, instance ids and counters bit for bit."""
+    torch, rtx = env
+    wl = W.instanced(2000)
+    akw = W.instanced_alpha(wl) if kind == "alpha" else {}
+    announce(f"instanced bench config kind={kind} rays={wl['rays'].shape[0]}")
+    sc = rtx.InstancedScene(wl["blas"], wl["inst_blas"], wl["inst_m"], wl["world_lo"], wl["world_hi"],
+                            **akw)
+    rays = wl["rays"]
+    out, inst, cnt = sc.trace(torch.from_numpy(rays).cuda(), kind, count=True)
+    plain, plain_inst = sc.trace(torch.from_numpy(rays).cuda(), kind)
+    torch.cuda.synchronize()
+    # the counting launch and the timed (non-counting) launch agree everywhere
+    assert torch.equal(out.view(torch.int32), plain.view(torch.int32))
+    assert torch.equal(inst, plain_inst)
+    idx = np.arange(5, rays.shape[0], 61)
+    bvhs = [oracle_lib.build_bvh(b) for b in wl["blas"]]
+    tl = oracle_lib.build_tlas(wl["world_lo"], wl["world_hi"])
+    B = oracle_lib.traverse_instanced(wl["blas"], bvhs, wl["inst_blas"], wl["inst_m"], tl, rays[idx],
+                                      kind, **akw)
+    g = P.hits_to_numpy(out[torch.from_numpy(idx).cuda()])
+    P.assert_exact_vs_b(g, B, f"instanced bench config {kind}")
+    assert np.array_equal(inst.cpu().numpy().view(np.uint32)[idx], B["inst"])
+    P.assert_counters_vs_b(cnt[torch.from_numpy(idx).cuda()], B, f"instanced bench config {kind}")
+    assert (g["prim"] != MISS).mean() > 0.05
+    if kind == "alpha":
+        assert (B["counters"][:, 2] > B["counters"][:, 3]).sum() > 100
