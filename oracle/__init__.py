@@ -9,7 +9,9 @@ alpha-mask and procedural intersectors of Section 4 evaluated in float64.
 
 Oracle B (:func:`build_bvh`, :func:`traverse`): its own binned-SAH BVH and a
 float32 while-while traversal (Algorithm 1) that counts ray/box and
-ray/triangle tests the way the heat-map intersector of Section 4 does.
+ray/triangle tests the way the heat-map intersector of Section 4 does; with
+``layout="q8"`` the inner nodes' child boxes are the 8-bit quantized boxes of
+the 32-byte node layout (:func:`quantize`), which the paper does not cover.
 
 The C source is ``rt_oracle.c``; :func:`build` compiles it with gcc.
 """
@@ -76,6 +78,12 @@ def _load():
                                         P, P, P, P, P, P, C.c_int]
         lib.orc_brute_multi.restype = C.c_int
         lib.orc_traverse.restype = C.c_int
+        lib.orc_traverse_layout.argtypes = [P, P, C.c_uint32, P, P, C.c_uint32, P, P, C.c_uint32,
+                                            C.c_int, P, C.c_int, C.c_uint32, P, P, P, P, P, P,
+                                            C.c_int]
+        lib.orc_traverse_layout.restype = C.c_int
+        lib.orc_quantize.argtypes = [P, C.c_uint32, P, P, P]
+        lib.orc_quantize.restype = C.c_int
         lib.orc_node_size.restype = C.c_uint32
         lib.orc_fixed_hit64.argtypes = [P, P, P, P, C.c_uint32, P]
         lib.orc_fixed_hit64.restype = C.c_int
@@ -187,14 +195,32 @@ def build_bvh(vertices) -> OracleBVH:
     return OracleBVH(nodes[: nn.value].copy(), perm[:n].copy(), int(md.value))
 
 
+def quantize(bvh: OracleBVH) -> dict:
+    """The 32-byte node layout of every inner node of an oracle BVH:
+    ``frames [n_nodes, 3]`` uint32 (origin bits | scale exponent), ``q
+    [n_nodes, 12]`` uint8 (qlo0.xyz, qhi0.xyz, qlo1.xyz, qhi1.xyz) and the
+    decoded child boxes ``qbox [n_nodes, 12]`` float32 (lo0, hi0, lo1, hi1);
+    leaf entries are zero."""
+    lib = _load()
+    n = bvh.n_nodes
+    frames = np.zeros((n, 3), np.uint32)
+    q = np.zeros((n, 12), np.uint8)
+    qbox = np.zeros((n, 12), np.float32)
+    if lib.orc_quantize(_ptr(bvh.nodes), n, _ptr(frames), _ptr(q), _ptr(qbox)) != 0:
+        raise ValueError("orc_quantize: a box has no valid scale (non-finite coordinates)")
+    return {"frames": frames, "q": q, "qbox": qbox}
+
+
 def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, texcoords=None,
              textures=None, alpha_min=128, checker_n=8, any_hit=False, count=True, multi_k=0,
-             threads=None):
+             layout="f32", threads=None):
     """Oracle B traversal.  Returns float32 ``t, u, v``, uint32 ``prim`` and,
     with ``count``, uint32 ``counters [N, 4]`` = (box tests, triangle tests,
     candidates handed to the intersector, accepted candidates).  With
     ``multi_k > 0`` (multi-hit) ``t, u, v, prim`` are ``[N, multi_k]`` (nearest
-    first, padded with misses) and ``n_hits [N]`` counts the kept hits."""
+    first, padded with misses) and ``n_hits [N]`` counts the kept hits.
+    ``layout``: "f32" (float32 child boxes) or "q8" (the 32-byte layout's
+    quantized child boxes)."""
     lib = _load()
     verts = np.ascontiguousarray(vertices, np.float32).reshape(-1, 9)
     r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
@@ -208,10 +234,14 @@ def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, t
     nh = np.empty(m, np.uint32) if multi_k else None
     cnt = np.empty((m, 4), np.uint32) if count else None
     is_, keep = _isect(texcoords, textures, alpha_min, checker_n)
-    rc = lib.orc_traverse(_ptr(verts), _ptr(g), n, _ptr(bvh.nodes), _ptr(bvh.perm), bvh.n_nodes,
-                          _ptr(r), m, KINDS[kind], C.byref(is_), int(bool(any_hit)), int(multi_k),
-                          _ptr(out["t"]), _ptr(out["prim"]), _ptr(out["u"]), _ptr(out["v"]),
-                          _ptr(nh), _ptr(cnt), _threads(threads))
+    if layout not in ("f32", "q8"):
+        raise ValueError(f"unknown layout {layout!r}")
+    qbox = quantize(bvh)["qbox"] if layout == "q8" else None
+    rc = lib.orc_traverse_layout(_ptr(verts), _ptr(g), n, _ptr(bvh.nodes), _ptr(bvh.perm),
+                                 bvh.n_nodes, _ptr(qbox), _ptr(r), m, KINDS[kind], C.byref(is_),
+                                 int(bool(any_hit)), int(multi_k), _ptr(out["t"]),
+                                 _ptr(out["prim"]), _ptr(out["u"]), _ptr(out["v"]), _ptr(nh),
+                                 _ptr(cnt), _threads(threads))
     if rc != 0:
         raise RuntimeError(f"orc_traverse failed ({rc})")
     if count:

@@ -514,6 +514,100 @@ int orc_build(const float *verts, uint32_t n_tris, orc_node *nodes, uint32_t *pe
 }
 
 /* ======================================================================
+ * Oracle B part 1b: the 32-byte node layout (8-bit child boxes)
+ *
+ * Not in the paper (its BVH format is open); the layout is defined in words:
+ * for an inner node with child boxes B0, B1, per axis a
+ *   L = min(lo0, lo1), H = max(hi0, hi1);
+ *   org = the largest float <= L whose bit pattern has its low 8 bits clear;
+ *   E   = the smallest integer in [1, 254] with fma(255, 2^(E-127), org) >= H;
+ *   frame word F = bits(org) | E;
+ *   decode(q) = fma(q, 2^(E-127), org) for q in 0..255;
+ *   qlo = the largest q with decode(q) <= lo, qhi = the smallest q with
+ *   decode(q) >= hi, for each child coordinate.
+ * Byte order of the twelve q: qlo0.xyz, qhi0.xyz, qlo1.xyz, qhi1.xyz.
+ * The traversal decodes the child boxes from F and q and runs the same slab
+ * test on them; the root keeps its float32 box.
+ * ====================================================================== */
+
+static uint32_t bits_of(float f)
+{
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    return b;
+}
+
+static float float_of(uint32_t b)
+{
+    float f;
+    memcpy(&f, &b, 4);
+    return f;
+}
+
+/* The largest float <= L whose pattern has its low 8 bits clear: for L >= 0
+ * clearing the bits lowers the value; for L < 0 it would raise it, so the
+ * magnitude goes up to the next pattern with clear low bits instead. */
+static float frame_origin(float L)
+{
+    uint32_t b = bits_of(L);
+    if (!(b & 0x80000000u) || (b & 0xFFu) == 0) return float_of(b & ~0xFFu);
+    return float_of((b | 0xFFu) + 1u);
+}
+
+static float q8_decode(uint32_t q, uint32_t frame)
+{
+    float org = float_of(frame & ~0xFFu);
+    float s = float_of((frame & 0xFFu) << 23);
+    return fmaf((float)q, s, org);
+}
+
+/* Quantizes every inner node of an oracle BVH: frames [n_nodes][3] words,
+ * q [n_nodes][12] bytes and the decoded child boxes qbox [n_nodes][12]
+ * floats (lo0, hi0, lo1, hi1); leaf entries are zero.  Returns -1 if some
+ * axis has no valid exponent (non-finite boxes). */
+int orc_quantize(const orc_node *nodes, uint32_t n_nodes, uint32_t *frames, uint8_t *q,
+                 float *qbox)
+{
+    memset(frames, 0, sizeof(uint32_t) * 3 * (size_t)n_nodes);
+    memset(q, 0, 12 * (size_t)n_nodes);
+    memset(qbox, 0, sizeof(float) * 12 * (size_t)n_nodes);
+    for (uint32_t n = 0; n < n_nodes; ++n) {
+        const orc_node *nd = &nodes[n];
+        if (nd->count > 0) continue;
+        const orc_node *ch[2] = {&nodes[nd->left], &nodes[nd->right]};
+        for (int a = 0; a < 3; ++a) {
+            float L = fminf(ch[0]->lo[a], ch[1]->lo[a]);
+            float H = fmaxf(ch[0]->hi[a], ch[1]->hi[a]);
+            float org = frame_origin(L);
+            uint32_t E = 0;
+            for (uint32_t e = 1; e <= 254; ++e) {
+                if (fmaf(255.0f, float_of(e << 23), org) >= H) { E = e; break; }
+            }
+            if (E == 0) return -1;
+            uint32_t F = bits_of(org) | E;
+            frames[3 * (size_t)n + a] = F;
+            for (int c = 0; c < 2; ++c) {
+                uint32_t qlo = 0, qhi = 255;
+                for (uint32_t k = 256; k-- > 0;)
+                    if (q8_decode(k, F) <= ch[c]->lo[a]) { qlo = k; break; }
+                for (uint32_t k = 0; k < 256; ++k)
+                    if (q8_decode(k, F) >= ch[c]->hi[a]) { qhi = k; break; }
+                q[12 * (size_t)n + 6 * c + a] = (uint8_t)qlo;
+                q[12 * (size_t)n + 6 * c + 3 + a] = (uint8_t)qhi;
+            }
+        }
+        /* the traversal's boxes come from the stored words alone */
+        for (int c = 0; c < 2; ++c)
+            for (int a = 0; a < 3; ++a) {
+                uint32_t F = frames[3 * (size_t)n + a];
+                qbox[12 * (size_t)n + 6 * c + a] = q8_decode(q[12 * (size_t)n + 6 * c + a], F);
+                qbox[12 * (size_t)n + 6 * c + 3 + a] = q8_decode(q[12 * (size_t)n + 6 * c + 3 + a], F);
+            }
+    }
+    return 0;
+}
+
+/* ======================================================================
  * Oracle B part 2: float32 while-while traversal (Algorithm 1)
  *
  * Per ray:
@@ -561,6 +655,7 @@ typedef struct {
     uint32_t *prim;
     uint32_t *n_hits;   /* multi-hit: hits found per ray */
     uint32_t *counters; /* [n_rays][4]: boxes, triangles, candidates, accepts */
+    const float *qbox;  /* 32-byte layout: decoded child boxes per node, or NULL */
     uint32_t next;
     pthread_mutex_t lock;
 } trav_job;
@@ -715,8 +810,15 @@ static void trav_one(trav_job *job, uint32_t i)
             while (job->nodes[cur].count == 0) {
                 const orc_node *nd = &job->nodes[cur];
                 float tl, tr;
-                int hl = box_test(&rs, job->nodes[nd->left].lo, job->nodes[nd->left].hi, &tl);
-                int hr = box_test(&rs, job->nodes[nd->right].lo, job->nodes[nd->right].hi, &tr);
+                int hl, hr;
+                if (job->qbox) {
+                    const float *qb = job->qbox + 12 * (size_t)cur;
+                    hl = box_test(&rs, qb, qb + 3, &tl);
+                    hr = box_test(&rs, qb + 6, qb + 9, &tr);
+                } else {
+                    hl = box_test(&rs, job->nodes[nd->left].lo, job->nodes[nd->left].hi, &tl);
+                    hr = box_test(&rs, job->nodes[nd->right].lo, job->nodes[nd->right].hi, &tr);
+                }
                 if (hl && hr) {
                     if (tr < tl) { cur = nd->right; stack_node[sp] = nd->left; stack_tn[sp] = tl; }
                     else { cur = nd->left; stack_node[sp] = nd->right; stack_tn[sp] = tr; }
@@ -791,11 +893,32 @@ static void *trav_worker(void *arg)
  * accepted hit; multi-hit (multi_k > 0): the multi_k nearest accepted hits in
  * increasing t, ties in acceptance order, padded with misses, and their number
  * in n_hits) and, if counters != NULL, four uint32 counters per ray. */
+int orc_traverse_layout(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
+                        const orc_node *nodes, const uint32_t *perm, uint32_t n_nodes,
+                        const float *qbox, const float *rays, uint32_t n_rays, int kind,
+                        const orc_isect *is, int any_hit, uint32_t multi_k, float *t,
+                        uint32_t *prim, float *u, float *v, uint32_t *n_hits, uint32_t *counters,
+                        int n_threads);
+
 int orc_traverse(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
                  const orc_node *nodes, const uint32_t *perm, uint32_t n_nodes,
                  const float *rays, uint32_t n_rays, int kind, const orc_isect *is,
                  int any_hit, uint32_t multi_k, float *t, uint32_t *prim, float *u, float *v,
                  uint32_t *n_hits, uint32_t *counters, int n_threads)
+{
+    return orc_traverse_layout(verts, geom_ids, n_tris, nodes, perm, n_nodes, NULL, rays, n_rays,
+                               kind, is, any_hit, multi_k, t, prim, u, v, n_hits, counters,
+                               n_threads);
+}
+
+/* The same traversal; with qbox (orc_quantize's decoded child boxes) the
+ * inner nodes' box tests use the 32-byte layout's boxes. */
+int orc_traverse_layout(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
+                        const orc_node *nodes, const uint32_t *perm, uint32_t n_nodes,
+                        const float *qbox, const float *rays, uint32_t n_rays, int kind,
+                        const orc_isect *is, int any_hit, uint32_t multi_k, float *t,
+                        uint32_t *prim, float *u, float *v, uint32_t *n_hits, uint32_t *counters,
+                        int n_threads)
 {
     if (kind < ORC_DEFAULT || kind > ORC_PROCEDURAL) return -1;
     if (multi_k > ORC_MAX_MULTI || (multi_k > 0 && (any_hit || !n_hits))) return -2;
@@ -809,6 +932,7 @@ int orc_traverse(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
     job.multi_k = multi_k;
     job.t = t; job.u = u; job.v = v; job.prim = prim; job.counters = counters;
     job.n_hits = n_hits;
+    job.qbox = qbox;
     pthread_mutex_init(&job.lock, NULL);
     run_threads(trav_worker, &job, n_threads);
     pthread_mutex_destroy(&job.lock);
