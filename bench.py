@@ -48,14 +48,14 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def bytes_per_ray(counters: np.ndarray, kind: str) -> np.ndarray:
+def bytes_per_ray(counters: np.ndarray, kind: str, node_bytes: int = 64) -> np.ndarray:
     """Algorithmic bytes of one ray: its 32-byte ray record and 16-byte hit
-    record, one 64-byte node record per inner node entered (box tests are the
-    root's plus two per inner node), one 48-byte triangle record per triangle
-    test, and per alpha decision the 24 bytes of texture coordinates plus the
-    4-byte texel."""
+    record, one node record (64 bytes, or 32 in the compressed layout) per
+    inner node entered (box tests are the root's plus two per inner node),
+    one 48-byte triangle record per triangle test, and per alpha decision the
+    24 bytes of texture coordinates plus the 4-byte texel."""
     c = counters.astype(np.int64)
-    b = 32 + 16 + 64 * ((c[:, 0] - 1).clip(min=0) // 2) + 48 * c[:, 1]
+    b = 32 + 16 + node_bytes * ((c[:, 0] - 1).clip(min=0) // 2) + 48 * c[:, 1]
     if kind == "alpha":
         b = b + 28 * c[:, 2]
     return b
@@ -104,28 +104,31 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(wl, kind, kind_kw, threads, budget_s=8.0):
+def cpu_baseline(wl, kind, kind_kw, threads, budget_s=8.0, layout="f32"):
     """The oracle as it stands, on this host's cores, on the same workload:
-    oracle B (float32 BVH traversal of its own BVH) over every ray, repeated
-    until about ``budget_s`` seconds have passed (median pass reported), the
-    same on one thread over every 16th ray, and oracle A (float64 brute force
-    over every triangle) on a ray sample sized to about ``budget_s / 2``
-    seconds."""
+    oracle B (float32 BVH traversal of its own BVH, in the node layout the
+    GPU run used) over every ray, repeated until about ``budget_s`` seconds
+    have passed (median pass reported), the same on one thread over every
+    16th ray, and oracle A (float64 brute force over every triangle) on a ray
+    sample sized to about ``budget_s / 2`` seconds."""
     import oracle
     from paper_1912_12786_amd import workloads as W
     oracle.build(force=False)
     t0 = time.perf_counter()
     bvh = oracle.build_bvh(wl.vertices)
+    if layout == "q8":
+        bvh.qbox = oracle.quantize(bvh)["qbox"]
     t_build = time.perf_counter() - t0
     passes = []
     while not passes or (sum(passes) < budget_s and len(passes) < 50):
         t0 = time.perf_counter()
-        oracle.traverse(wl.vertices, bvh, wl.rays, kind, count=False, threads=threads, **kind_kw)
+        oracle.traverse(wl.vertices, bvh, wl.rays, kind, count=False, threads=threads,
+                        layout=layout, **kind_kw)
         passes.append(time.perf_counter() - t0)
     t_b = float(np.median(passes))
     sub = wl.rays[::16]
     t0 = time.perf_counter()
-    oracle.traverse(wl.vertices, bvh, sub, kind, count=False, threads=1, **kind_kw)
+    oracle.traverse(wl.vertices, bvh, sub, kind, count=False, threads=1, layout=layout, **kind_kw)
     t_b1 = time.perf_counter() - t0
     # size the brute-force sample from a short probe
     probe = W.subsample_indices(wl.n_rays, None, None, seed=7, n_random=256)
@@ -142,7 +145,8 @@ def cpu_baseline(wl, kind, kind_kw, threads, budget_s=8.0):
         "unit": "Mrays/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"oracle B (float32 BVH traversal; its own BVH built in {t_build:.2f} s) over "
+        "sample": (f"oracle B (float32 BVH traversal, {layout} nodes; its own BVH built in "
+                   f"{t_build:.2f} s) over "
                    f"all {wl.n_rays} rays, {len(passes)} passes, median {t_b:.3f} s; oracle A "
                    f"(float64 brute force over all {wl.n_tris} triangles) on {len(idx)} sampled "
                    f"rays in {t_a:.2f} s"),
@@ -405,6 +409,9 @@ def main():
     ap.add_argument("--ray-order", default="scanline", choices=["scanline", "tiled", "morton"],
                     help="tiled: primary rays reordered into 8x8 pixel tiles before upload "
                          "(hits come back in that order); morton: the same tiles in Z-order")
+    ap.add_argument("--layout", default="f32", choices=["f32", "q8"],
+                    help="inner-node layout: f32 = 64-B nodes with float32 boxes, q8 = 32-B "
+                         "nodes with 8-bit boxes (rt_bvh_compress)")
     ap.add_argument("--query", default="closest", choices=["closest", "any", "multi"])
     ap.add_argument("--k", type=int, default=4, help="hits kept per ray by --query multi")
     ap.add_argument("--workload", default="billboards",
@@ -453,7 +460,8 @@ def main():
         wl.rays = wl.rays[tile_order(wl, morton=args.ray_order == "morton")]
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    scene = rtx.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures, device=dev)
+    scene = rtx.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures, device=dev,
+                             layout=args.layout)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     log(f"workload {wl.name}: gen {t_gen:.2f} s, host BVH build + upload {t_build:.2f} s, "
@@ -507,7 +515,8 @@ def main():
                        workspace=ws)
     torch.cuda.synchronize()
     counters = cnt.cpu().numpy().view(np.uint32)
-    alg_bytes = int(bytes_per_ray(counters, kind).sum())
+    node_bytes = 32 if args.layout == "q8" else 64
+    alg_bytes = int(bytes_per_ray(counters, kind, node_bytes).sum())
     # output records: 16-B hit (closest), 4-B occluder (any), k 16-B hits + 4-B count (multi)
     if query == "any":
         alg_bytes -= 12 * wl.n_rays
@@ -522,6 +531,7 @@ def main():
             tf = json.load(f)
         if tf.get("kernel_source_sha") == kernel_source_sha() and kind == "alpha" \
                 and query == "closest" and args.ray_order == "scanline" \
+                and tf.get("layout", "f32") == args.layout \
                 and list(rtx.rt_launch_shapes()[0]) == tf.get("launch_shape") and not args.shape:
             traffic = tf.get("traffic_bytes_per_launch")
 
@@ -530,7 +540,7 @@ def main():
         threads = len(os.sched_getaffinity(0))
         kind_kw = dict(geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures,
                        alpha_min=128) if kind == "alpha" else {}
-        cpu = cpu_baseline(wl, kind, kind_kw, threads)
+        cpu = cpu_baseline(wl, kind, kind_kw, threads, layout=args.layout)
 
     mean_c = counters.mean(axis=0)
     result = {
@@ -559,6 +569,8 @@ def main():
             "ray_order": {"tiled": "8x8 tiles", "morton": "8x8 tiles, Z-order inside"}.get(
                 args.ray_order, "scanline"),
             "bvh": f"binary SAH, {scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}",
+            "node_layout": ("32-B nodes, 8-bit child boxes" if args.layout == "q8"
+                            else "64-B nodes, float32 child boxes"),
             "launch_shape": ([int(x) for x in args.shape.split(",")] if args.shape
                              else list(rtx.rt_launch_shapes()[0])),
         },

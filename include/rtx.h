@@ -116,6 +116,10 @@ typedef struct rt_procedural_params {
     uint32_t checker_n;         /* >= 1 */
 } rt_procedural_params;
 
+/* Inner-node layouts (rt_bvh_info.layout). */
+#define RT_LAYOUT_F32 0u  /* 64-B nodes with float32 child boxes (rt_bvh_build) */
+#define RT_LAYOUT_Q8 1u   /* 32-B nodes with 8-bit child boxes (rt_bvh_compress) */
+
 /* Description of a built BVH (filled by rt_bvh_build). */
 typedef struct rt_bvh_info {
     uint32_t n_tris;
@@ -124,18 +128,21 @@ typedef struct rt_bvh_info {
     uint32_t max_geom_id;
     uint32_t root_ref;       /* packed reference of the root item */
     float root_lo[3], root_hi[3];
+    uint32_t layout;         /* RT_LAYOUT_F32 or RT_LAYOUT_Q8 */
 } rt_bvh_info;
 
 /* A built BVH resident in device memory: a non-owning view.  nodes and tris
- * must be copies of what rt_bvh_build wrote (the kernels follow the child
- * references without bounds checks; only the root is validated). */
+ * must be copies of what rt_bvh_build (and rt_bvh_compress for
+ * RT_LAYOUT_Q8) wrote (the kernels follow the child references without
+ * bounds checks; only the root is validated). */
 typedef struct rt_scene {
-    const void *nodes;       /* device, n_nodes records of RT_NODE_BYTES */
+    const void *nodes;       /* device, n_nodes records of RT_NODE_BYTES or RT_NODE_BYTES_Q8 */
     const void *tris;        /* device, n_tris records of RT_TRI_BYTES */
     rt_bvh_info info;
 } rt_scene;
 
 #define RT_NODE_BYTES 64u
+#define RT_NODE_BYTES_Q8 32u
 #define RT_TRI_BYTES 48u
 #define RT_MAX_TRIS 0x1FFFFFFFu  /* 2^29 - 1 */
 #define RT_MAX_RAYS 0x80000000u  /* rays per trace call */
@@ -161,6 +168,26 @@ rt_status rt_bvh_buffer_bytes(uint32_t n_tris, size_t *node_bytes, size_t *tri_b
 rt_status rt_bvh_build(const float *vertices, const uint32_t *geom_ids, uint32_t n_tris,
                        void *nodes, size_t node_cap, void *tris, size_t tri_cap,
                        rt_bvh_info *info);
+
+/* Converts the inner nodes of a built BVH (host, from rt_bvh_build) to the
+ * 32-byte layout: per node and axis a frame word -- the largest float32
+ * <= the node's lower bound whose low 8 pattern bits are clear, carrying in
+ * those bits an exponent E such that the scale 2^(E-127) is the smallest
+ * with fma(255, scale, origin) >= the node's upper bound -- then each child
+ * coordinate as the tightest 8-bit q whose decoded value
+ * fma(q, scale, origin) lies on the outside of the exact bound (lower bounds
+ * round down, upper bounds up), in the order qlo0.xyz qhi0.xyz qlo1.xyz
+ * qhi1.xyz, then the two child references unchanged.  The traversal decodes
+ * the boxes and box-tests them like float32 boxes; a decoded box contains
+ * its exact box, so closest and any-hit answers equal the float32 layout's
+ * except among hits of exactly equal t, while the counters are the
+ * compressed traversal's own.  (The paper leaves the BVH format open.)
+ *   nodes     host, info->n_nodes records of RT_NODE_BYTES
+ *   out       host output, capacity out_cap >= n_nodes * RT_NODE_BYTES_Q8, 16-byte aligned
+ *   out_info  host output: *info with layout = RT_LAYOUT_Q8 (may alias info)
+ * Fails if info->layout is not RT_LAYOUT_F32 or a box is not finite. */
+rt_status rt_bvh_compress(const void *nodes, const rt_bvh_info *info, void *out, size_t out_cap,
+                          rt_bvh_info *out_info);
 
 /* Device workspace a trace call needs (bytes, possibly 0): the ray queue
  * head of persistent launch shapes and overflow space for traversal stacks
@@ -210,15 +237,17 @@ typedef struct rt_batch_info {
     uint32_t n_rays;         /* sum of the entries' n_rays */
     uint32_t max_depth;      /* deepest BVH of the batch */
     uint32_t kind;           /* the intersector kind the table was packed for */
+    uint32_t layout;         /* node layout shared by every scene of the batch */
 } rt_batch_info;
 
 /* Bytes of the packed table for n_scenes scenes. */
 rt_status rt_batch_table_bytes(uint32_t n_scenes, size_t *bytes);
 
 /* Validates the entries (every scene as rt_trace_closest would, and for
- * RT_ISECT_ALPHA every entry's alpha data against its scene) and writes the
- * table into host_table (host, 16-byte aligned, table_bytes >= 
- * rt_batch_table_bytes).  The device pointers inside are copied verbatim. */
+ * RT_ISECT_ALPHA every entry's alpha data against its scene; all scenes must
+ * share one node layout) and writes the table into host_table (host,
+ * 16-byte aligned, table_bytes >= rt_batch_table_bytes).  The device
+ * pointers inside are copied verbatim. */
 rt_status rt_batch_pack(const rt_batch_entry *entries, uint32_t n_scenes, rt_isect_kind kind,
                         void *host_table, size_t table_bytes, rt_batch_info *info);
 
@@ -280,7 +309,9 @@ typedef struct rt_instance_info {
                                  every mesh with triangles */
 } rt_instance_info;
 
-/* Validates the bottom-level scenes, their texture coordinates (texcoords:
+/* Instancing takes scenes of layout RT_LAYOUT_F32 only (bottom and top level).
+ *
+ * Validates the bottom-level scenes, their texture coordinates (texcoords:
  * host array [n_blas], or NULL when no alpha mask will be used; an entry may
  * be {NULL, 0} for a mesh without triangles) and the instances, writes the
  * table into host_table (host, 16-byte aligned) and fills *info.  The caller
@@ -364,7 +395,9 @@ rt_status rt_hit_backward(const rt_ray *rays, const rt_hit *hits, const float *g
  *              most 256 CUs x 32 wave slots) takes chunks from atomic queues
  *              kept in the workspace; 0: wave w owns the static chunk w.
  * Writes up to cap entries per array (any array may be NULL) and returns the
- * number of shapes; the first shape is the default. */
+ * number of shapes; the first shape is the default.  Scenes of layout
+ * RT_LAYOUT_Q8 run with the default shape only (other shapes return
+ * RT_ERR_UNSUPPORTED), and not with the run-time dispatch flags. */
 uint32_t rt_launch_shapes(uint32_t *blocks, uint32_t *lds_stacks, uint32_t *chunks,
                           uint32_t *queues, uint32_t cap);
 

@@ -20,7 +20,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import numpy as np
 
@@ -174,6 +174,7 @@ class OracleBVH:
     nodes: np.ndarray    # NODE_DTYPE, preorder, node 0 = root
     perm: np.ndarray     # uint32, leaf order -> input triangle index
     max_depth: int
+    qbox: np.ndarray | None = field(default=None, repr=False)  # quantize()'s boxes, once computed
 
     @property
     def n_nodes(self) -> int:
@@ -236,7 +237,11 @@ def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, t
     is_, keep = _isect(texcoords, textures, alpha_min, checker_n)
     if layout not in ("f32", "q8"):
         raise ValueError(f"unknown layout {layout!r}")
-    qbox = quantize(bvh)["qbox"] if layout == "q8" else None
+    qbox = None
+    if layout == "q8":
+        if bvh.qbox is None:
+            bvh.qbox = quantize(bvh)["qbox"]
+        qbox = bvh.qbox
     rc = lib.orc_traverse_layout(_ptr(verts), _ptr(g), n, _ptr(bvh.nodes), _ptr(bvh.perm),
                                  bvh.n_nodes, _ptr(qbox), _ptr(r), m, KINDS[kind], C.byref(is_),
                                  int(bool(any_hit)), int(multi_k), _ptr(out["t"]),

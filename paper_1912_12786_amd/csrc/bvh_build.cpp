@@ -24,6 +24,8 @@
 //     its first triangle record).
 //   triangle record, 48 B: {v0.xyz, prim_id} {e1.xyz, geom_id} {e2.xyz, 0}
 //     with e1 = v1 - v0 and e2 = v2 - v0 rounded to float.
+//   compressed inner node, 32 B (compress_nodes): {F.x F.y F.z Q0} {Q1 Q2 ref0 ref1}
+//     with frame words F and twelve 8-bit child coordinates Q (see below).
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -278,6 +280,107 @@ rt_status build_bvh(const float *verts, const uint32_t *geom_ids, uint32_t n_tri
         info->max_geom_id = gmax;
     } catch (const std::bad_alloc &) {
         return RT_ERR_OUT_OF_MEMORY;
+    }
+    return RT_OK;
+}
+
+// -------------------------------------------------------------------------
+// 32-byte nodes.  Per axis the frame is the union of the two child boxes
+// [L, H]; its origin is the largest float <= L whose pattern has a zero low
+// byte, and the low byte holds the exponent E of the scale s = 2^(E - 127),
+// the smallest with fma(255, s, origin) >= H.  A coordinate is stored as the
+// q in 0..255 whose decoded value fma(q, s, origin) is the tightest one on
+// the outside of the exact bound.  decode() is monotone in q and in s (one
+// correctly rounded fma of non-negative increments), so each choice is a
+// binary search.
+// -------------------------------------------------------------------------
+namespace {
+
+uint32_t pattern(float f)
+{
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    return b;
+}
+
+float from_pattern(uint32_t b)
+{
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+
+float frame_origin_of(float lo)
+{
+    const uint32_t b = pattern(lo);
+    if ((b & 0xFFu) == 0) return lo;
+    // positive: drop the low byte (smaller value); negative: round the
+    // magnitude up to the next pattern with a zero low byte
+    return from_pattern((b >> 31) ? (b & ~0xFFu) + 0x100u : (b & ~0xFFu));
+}
+
+float decode_q(uint32_t q, float scale, float origin)
+{
+    return std::fmaf(float(q), scale, origin);
+}
+
+}  // namespace
+
+rt_status compress_nodes(const NodeRecord *in, uint32_t n_nodes, NodeQ8Record *out)
+{
+    for (uint32_t n = 0; n < n_nodes; ++n) {
+        const NodeRecord &nd = in[n];
+        NodeQ8Record &o = out[n];
+        uint8_t q[12];
+        for (int a = 0; a < 3; ++a) {
+            const float c_lo[2] = {nd.f[a], nd.f[6 + a]};
+            const float c_hi[2] = {nd.f[3 + a], nd.f[9 + a]};
+            for (int c = 0; c < 2; ++c)
+                if (!std::isfinite(c_lo[c]) || !std::isfinite(c_hi[c])) return RT_ERR_INVALID_ARG;
+            const float L = c_lo[0] < c_lo[1] ? c_lo[0] : c_lo[1];
+            const float H = c_hi[0] > c_hi[1] ? c_hi[0] : c_hi[1];
+            const float org = frame_origin_of(L);
+            // smallest E in [1, 254] with decode(255) >= H (E = 254 always
+            // qualifies: 255 * 2^127 overflows to +inf)
+            uint32_t e_lo = 1, e_hi = 254;
+            while (e_lo < e_hi) {
+                const uint32_t mid = (e_lo + e_hi) / 2;
+                if (decode_q(255, from_pattern(mid << 23), org) >= H)
+                    e_hi = mid;
+                else
+                    e_lo = mid + 1;
+            }
+            const float scale = from_pattern(e_lo << 23);
+            o.u[a] = pattern(org) | e_lo;
+            for (int c = 0; c < 2; ++c) {
+                // largest q with decode(q) <= lo (q = 0 qualifies: origin <= L)
+                uint32_t lo_q = 0, hi_q = 255;
+                while (lo_q < hi_q) {
+                    const uint32_t mid = (lo_q + hi_q + 1) / 2;
+                    if (decode_q(mid, scale, org) <= c_lo[c])
+                        lo_q = mid;
+                    else
+                        hi_q = mid - 1;
+                }
+                q[6 * c + a] = uint8_t(lo_q);
+                // smallest q with decode(q) >= hi (q = 255 qualifies)
+                lo_q = 0;
+                hi_q = 255;
+                while (lo_q < hi_q) {
+                    const uint32_t mid = (lo_q + hi_q) / 2;
+                    if (decode_q(mid, scale, org) >= c_hi[c])
+                        hi_q = mid;
+                    else
+                        lo_q = mid + 1;
+                }
+                q[6 * c + 3 + a] = uint8_t(lo_q);
+            }
+        }
+        for (int w = 0; w < 3; ++w)
+            o.u[3 + w] = uint32_t(q[4 * w]) | uint32_t(q[4 * w + 1]) << 8 |
+                         uint32_t(q[4 * w + 2]) << 16 | uint32_t(q[4 * w + 3]) << 24;
+        o.u[6] = nd.u[12];
+        o.u[7] = nd.u[13];
     }
     return RT_OK;
 }

@@ -23,7 +23,8 @@ struct alignas(16) batch_scene {
     float root_lo[3], root_hi[3];
     uint32_t root_ref, n_tris;
     uint32_t tex_width, tex_height, alpha_min;
-    uint32_t pad[11];
+    uint32_t layout;            // RT_LAYOUT_F32 or RT_LAYOUT_Q8
+    uint32_t pad[10];
 };
 static_assert(sizeof(batch_scene) == 128, "batch scene record");
 
@@ -45,7 +46,8 @@ struct alignas(16) blas_record {
     float root_lo[3], root_hi[3];
     uint32_t root_ref, n_tris;
     const float2 *texcoords;  // alpha mask: this mesh's texture coordinates
-    uint32_t pad[2];
+    uint32_t layout;          // RT_LAYOUT_F32 or RT_LAYOUT_Q8
+    uint32_t pad;
 };
 static_assert(sizeof(blas_record) == 64, "blas record");
 

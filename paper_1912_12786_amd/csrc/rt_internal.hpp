@@ -25,9 +25,16 @@ struct alignas(16) TriRecord {
 };
 static_assert(sizeof(TriRecord) == RT_TRI_BYTES, "triangle record size");
 
+struct alignas(16) NodeQ8Record {
+    uint32_t u[8];
+};
+static_assert(sizeof(NodeQ8Record) == RT_NODE_BYTES_Q8, "compressed node record size");
+
 uint32_t max_inner_nodes(uint32_t n_tris);
 rt_status build_bvh(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
                     NodeRecord *nodes, TriRecord *tris, rt_bvh_info *info);
+// 64-B nodes -> 32-B nodes (RT_ERR_INVALID_ARG if a box is not finite).
+rt_status compress_nodes(const NodeRecord *in, uint32_t n_nodes, NodeQ8Record *out);
 
 enum class Query { Closest, Any, Multi };
 

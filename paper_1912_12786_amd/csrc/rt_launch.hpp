@@ -11,7 +11,8 @@
 //   __device__ bool accept(const hit_candidate &);
 // and may be wrapped in counting_intersector<T> for the per-ray counters.
 // trace_custom<T>() then runs the closest-hit query with it, using the
-// library's default launch shape and the scene layout of rt_bvh_build.
+// library's default launch shape and the scene's node layout (rt_bvh_build,
+// or rt_bvh_compress).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -62,6 +63,7 @@ inline kernel_args scene_args(const rt_scene &scene, const void *rays, uint32_t 
     }
     a.sc.root_ref = info.root_ref;
     a.sc.n_tris = info.n_tris;
+    a.sc.layout = info.layout;
     a.rays = static_cast<const float4 *>(rays);
     a.n_rays = n_rays;
     a.out = out;
@@ -76,12 +78,12 @@ inline kernel_args scene_args(const rt_scene &scene, const void *rays, uint32_t 
 // Enqueues one traversal kernel (and, for a queue shape, the reset of the
 // queue heads before it); returns RT_OK or RT_ERR_HIP.
 template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue,
-          bool kBatched = false>
+          bool kBatched = false, uint32_t kLayout = RT_LAYOUT_F32>
 rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipStream_t s,
                      const char **err)
 {
     const LaunchShape sh{kBlock, kSlots, kChunk, kQueue};
-    auto kernel = trace_kernel<Isect, Result, kSlots, kBlock, kChunk, kQueue, kBatched>;
+    auto kernel = trace_kernel<Isect, Result, kSlots, kBlock, kChunk, kQueue, kBatched, kLayout>;
     // the workspace is sized for launch_threads(); a queue grid is further
     // trimmed to the waves that can be resident at once
     uint32_t grid = uint32_t(launch_threads(a.n_rays, sh) / kBlock);
@@ -134,6 +136,10 @@ rt_status trace_custom(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
         *err = "scene triangle records NULL or stack bound exceeded";
         return RT_ERR_INVALID_ARG;
     }
+    if (scene->info.layout != RT_LAYOUT_F32 && scene->info.layout != RT_LAYOUT_Q8) {
+        *err = "unknown scene node layout";
+        return RT_ERR_INVALID_ARG;
+    }
     if (!is16(rays) || !is16(out) || (counters && !is16(counters)) || !is16(workspace)) {
         *err = "rays, out, counters and workspace must be 16-byte aligned";
         return RT_ERR_MISALIGNED;
@@ -144,6 +150,9 @@ rt_status trace_custom(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
     }
     constexpr LaunchShape s = kDefaultShape;
     const kernel_args a = scene_args(*scene, rays, n_rays, out, counters, workspace, s);
+    if (scene->info.layout == RT_LAYOUT_Q8)
+        return launch_one<Isect, closest_result, int(s.lds_stack), int(s.block), int(s.chunk),
+                          s.queue != 0, false, RT_LAYOUT_Q8>(a, p, stream, err);
     return launch_one<Isect, closest_result, int(s.lds_stack), int(s.block), int(s.chunk),
                       s.queue != 0>(a, p, stream, err);
 }

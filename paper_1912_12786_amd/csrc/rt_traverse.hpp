@@ -281,31 +281,67 @@ struct ring_stack {
 };
 
 struct scene_view {
-    const float4 *nodes;  // 4 float4 per inner node
+    const float4 *nodes;  // 4 float4 per inner node (2 with RT_LAYOUT_Q8)
     const float4 *tris;   // 3 float4 per triangle record
     float root_lo[3], root_hi[3];
     uint32_t root_ref;
     uint32_t n_tris;
+    uint32_t layout;      // RT_LAYOUT_F32 or RT_LAYOUT_Q8
 };
+
+// The two child boxes (lo0, hi0, lo1, hi1) and references of inner node
+// `cur`.  RT_LAYOUT_Q8: per axis a, origin = frame word with its low byte
+// cleared and scale = 2^(low byte - 127) (both as bit patterns), and each
+// 8-bit coordinate q decodes to fma(q, scale, origin).  The layout is a
+// compile-time choice: a run-time branch here merges the two paths' loads
+// and costs the float32 layout 6-13 %.
+template <uint32_t kLayout>
+__device__ __forceinline__ void node_children(const scene_view &sc, uint32_t cur, float (&b)[12],
+                                              uint32_t &ref0, uint32_t &ref1)
+{
+    if constexpr (kLayout == RT_LAYOUT_Q8) {
+        const uint4 *nd = reinterpret_cast<const uint4 *>(sc.nodes) + 2 * size_t(cur);
+        const uint4 w0 = nd[0], w1 = nd[1];
+        const uint32_t frame[3] = {w0.x, w0.y, w0.z};
+        const uint32_t qw[3] = {w0.w, w1.x, w1.y};
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const uint32_t f = frame[k % 3];
+            const float q = float((qw[k / 4] >> (8 * (k % 4))) & 0xFFu);
+            b[k] = fmaf(q, __uint_as_float((f & 0xFFu) << 23), __uint_as_float(f & ~0xFFu));
+        }
+        ref0 = w1.z;
+        ref1 = w1.w;
+    } else {
+        const float4 *nd = sc.nodes + 4 * size_t(cur);
+        const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2];
+        const uint4 n3 = *reinterpret_cast<const uint4 *>(nd + 3);
+        b[0] = n0.x; b[1] = n0.y; b[2] = n0.z; b[3] = n0.w;
+        b[4] = n1.x; b[5] = n1.y; b[6] = n1.z; b[7] = n1.w;
+        b[8] = n2.x; b[9] = n2.y; b[10] = n2.z; b[11] = n2.w;
+        ref0 = n3.x;
+        ref1 = n3.y;
+    }
+}
 
 // One inner-node step: test both children's boxes; visit the nearer hit
 // child (ties -> child 0) and push the other if both are hit; with neither
 // hit, pop.  Returns false when the stack ran empty (ray finished).
-template <class Isect, class Stack>
+template <uint32_t kLayout = RT_LAYOUT_F32, class Isect, class Stack>
 __device__ __forceinline__ bool inner_step(const scene_view &sc, const ray_state &r, Isect &isect,
                                            Stack &st, uint32_t &cur)
 {
-    const float4 *nd = sc.nodes + 4 * size_t(cur);
-    const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2];
-    const uint4 n3 = *reinterpret_cast<const uint4 *>(nd + 3);
+    float b[12];
+    uint32_t ref0, ref1;
+    node_children<kLayout>(sc, cur, b, ref0, ref1);
     float tl, tr;
     isect.on_box_test();
     isect.on_box_test();
-    const bool hl = slab(r, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tl);
-    const bool hr = slab(r, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tr);
+    const bool hl = slab(r, b[0], b[1], b[2], b[3], b[4], b[5], tl);
+    const bool hr = slab(r, b[6], b[7], b[8], b[9], b[10], b[11], tr);
     const bool right_first = tr < tl;
-    const uint32_t near = (hl && !(hr && right_first)) ? n3.x : n3.y;
-    const uint32_t far = right_first ? n3.x : n3.y;
+    const uint32_t near = (hl && !(hr && right_first)) ? ref0 : ref1;
+    const uint32_t far = right_first ? ref0 : ref1;
     const float far_tn = right_first ? tl : tr;
     st.push_if(hl && hr, make_uint2(far, __float_as_uint(far_tn)));
     if (hl || hr) {
@@ -611,7 +647,7 @@ __device__ __forceinline__ bool leave_inner_phase(uint32_t n_inner, uint32_t n_l
 }
 
 template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue,
-          bool kBatched = false>
+          bool kBatched = false, uint32_t kLayout = RT_LAYOUT_F32>
 __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename Isect::params p)
 {
     static_assert(kBlock % 64 == 0 && kChunk % 32 == 0, "wave64 shapes");
@@ -663,6 +699,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
                     sc.root_hi[2] = bs.root_hi[2];
                     sc.root_ref = bs.root_ref;
                     sc.n_tris = bs.n_tris;
+                    sc.layout = bs.layout;
                     isect = Isect(batch_params<Isect>(p, bs));
                 } else {
                     isect = Isect(p);
@@ -690,7 +727,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename I
                 const uint64_t ml = __ballot(active && !in_inner);
                 if (ml != 0 && leave_inner_phase(uint32_t(__popcll(mi)), uint32_t(__popcll(ml))))
                     break;
-                if (in_inner && !inner_step(sc, r, isect, st, cur)) active = false;
+                if (in_inner && !inner_step<kLayout>(sc, r, isect, st, cur)) active = false;
             }
             if (active && ref_count(cur) != 0) {
                 if (leaf_step(sc, r, isect, cur, res))
@@ -782,6 +819,7 @@ __global__ __launch_bounds__(64) void trace_instanced_kernel(kernel_args a, cons
             bv.root_hi[2] = br.root_hi[2];
             bv.root_ref = br.root_ref;
             bv.n_tris = br.n_tris;
+            bv.layout = br.layout;
             // the alpha mask reads the texture coordinates of the entered mesh
             if constexpr (std::is_base_of_v<alpha_intersector, Isect>) isect.p.texcoords = br.texcoords;
             const float t_before = ro.tmax;

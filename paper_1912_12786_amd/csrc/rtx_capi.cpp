@@ -34,6 +34,8 @@ rt_status check_scene(const rt_scene *sc)
     if (!sc->tris) return fail(RT_ERR_INVALID_ARG, "scene triangle records are NULL");
     if (!aligned(sc->tris, 16)) return fail(RT_ERR_MISALIGNED, "scene triangle records not 16-byte aligned");
     if (in.max_depth >= 128) return fail(RT_ERR_INVALID_ARG, "scene max_depth must be < 128");
+    if (in.layout != RT_LAYOUT_F32 && in.layout != RT_LAYOUT_Q8)
+        return fail(RT_ERR_INVALID_ARG, "unknown scene node layout");
     const uint32_t cnt = in.root_ref >> 29, idx = in.root_ref & 0x1FFFFFFFu;
     if (cnt == 0) {
         if (in.n_nodes == 0 || idx >= in.n_nodes)
@@ -196,6 +198,28 @@ rt_status rt_bvh_build(const float *vertices, const uint32_t *geom_ids, uint32_t
     return RT_OK;
 }
 
+rt_status rt_bvh_compress(const void *nodes, const rt_bvh_info *info, void *out, size_t out_cap,
+                          rt_bvh_info *out_info)
+{
+    g_last_error.clear();
+    if (!info || !out_info) return fail(RT_ERR_INVALID_ARG, "info/out_info are NULL");
+    if (info->layout != RT_LAYOUT_F32) return fail(RT_ERR_INVALID_ARG, "input nodes are not RT_LAYOUT_F32");
+    const size_t need = size_t(info->n_nodes) * RT_NODE_BYTES_Q8;
+    if (info->n_nodes > 0) {
+        if (!nodes || !out) return fail(RT_ERR_INVALID_ARG, "nodes/out are NULL");
+        if (out_cap < need) return fail(RT_ERR_INVALID_ARG, "out smaller than n_nodes * RT_NODE_BYTES_Q8");
+        if (!aligned(nodes, 16) || !aligned(out, 16))
+            return fail(RT_ERR_MISALIGNED, "nodes/out must be 16-byte aligned");
+        const rt_status st = compress_nodes(static_cast<const NodeRecord *>(nodes), info->n_nodes,
+                                            static_cast<NodeQ8Record *>(out));
+        if (st != RT_OK) return fail(st, "a node box is not finite");
+    }
+    rt_bvh_info o = *info;
+    o.layout = RT_LAYOUT_Q8;
+    *out_info = o;
+    return RT_OK;
+}
+
 rt_status rt_trace_workspace_bytes(const rt_scene *scene, uint32_t n_rays, uint32_t flags,
                                    size_t *bytes)
 {
@@ -257,10 +281,14 @@ rt_status rt_batch_pack(const rt_batch_entry *entries, uint32_t n_scenes, rt_ise
     header[0] = n_scenes;
     uint64_t total = 0;
     uint32_t depth = 0;
+    const uint32_t layout = n_scenes ? entries[0].scene.info.layout : RT_LAYOUT_F32;
     for (uint32_t s = 0; s < n_scenes; ++s) {
         const rt_batch_entry &e = entries[s];
         st = check_scene(&e.scene);
         if (st != RT_OK) return fail(st, "scene " + std::to_string(s) + ": " + g_last_error);
+        if (e.scene.info.layout != layout)
+            return fail(RT_ERR_UNSUPPORTED, "scene " + std::to_string(s) +
+                                                ": the scenes of a batch must share one node layout");
         if (kind == RT_ISECT_ALPHA) {
             st = check_alpha(&e.scene, e.alpha);
             if (st != RT_OK) return fail(st, "scene " + std::to_string(s) + ": " + g_last_error);
@@ -280,6 +308,7 @@ rt_status rt_batch_pack(const rt_batch_entry *entries, uint32_t n_scenes, rt_ise
         }
         r.root_ref = in.root_ref;
         r.n_tris = in.n_tris;
+        r.layout = in.layout;
         r.tex_width = e.alpha.width;
         r.tex_height = e.alpha.height;
         r.alpha_min = e.alpha.alpha_min;
@@ -290,6 +319,7 @@ rt_status rt_batch_pack(const rt_batch_entry *entries, uint32_t n_scenes, rt_ise
     info->n_rays = uint32_t(total);
     info->max_depth = depth;
     info->kind = uint32_t(kind);
+    info->layout = layout;
     return RT_OK;
 }
 
@@ -326,8 +356,11 @@ rt_status rt_trace_batch(const void *table, const rt_batch_info *info, const rt_
         return fail(RT_ERR_UNSUPPORTED, "unknown intersector kind");
     }
     // a stand-in scene carries the batch-wide sizes through the common checks
+    if (info->layout != RT_LAYOUT_F32 && info->layout != RT_LAYOUT_Q8)
+        return fail(RT_ERR_INVALID_ARG, "unknown batch node layout");
     rt_scene proxy{};
     proxy.info.max_depth = info->max_depth;
+    proxy.info.layout = info->layout;
     return trace_common(Query::Closest, &proxy, rays, info->n_rays, kind, params, flags, hits, 16,
                         counters, workspace, workspace_bytes, stream, 0, nullptr, table);
 }
@@ -395,6 +428,8 @@ rt_status rt_instance_pack(const rt_scene *blas, const rt_mesh_texcoords *texcoo
         const std::string which = "bottom-level scene " + std::to_string(b);
         st = check_scene(&blas[b]);
         if (st != RT_OK) return fail(st, which + ": " + g_last_error);
+        if (blas[b].info.layout != RT_LAYOUT_F32)
+            return fail(RT_ERR_UNSUPPORTED, which + ": instancing takes RT_LAYOUT_F32 scenes");
         const rt_bvh_info &in = blas[b].info;
         br[b].nodes = static_cast<const float4 *>(blas[b].nodes);
         br[b].tris = static_cast<const float4 *>(blas[b].tris);
@@ -404,6 +439,7 @@ rt_status rt_instance_pack(const rt_scene *blas, const rt_mesh_texcoords *texcoo
         }
         br[b].root_ref = in.root_ref;
         br[b].n_tris = in.n_tris;
+        br[b].layout = in.layout;
         if (texcoords && in.n_tris > 0) {
             const rt_mesh_texcoords &tc = texcoords[b];
             if (!tc.texcoords || tc.n_prims < in.n_tris)
@@ -454,6 +490,8 @@ rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, const rt_inst
     if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
     rt_status st = check_scene(tlas);
     if (st != RT_OK) return st;
+    if (tlas->info.layout != RT_LAYOUT_F32)
+        return fail(RT_ERR_UNSUPPORTED, "instancing takes an RT_LAYOUT_F32 top-level scene");
     if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
     st = check_instance_info(info);
     if (st != RT_OK) return st;
@@ -470,6 +508,8 @@ rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, const rt_i
     g_last_error.clear();
     rt_status st = check_scene(tlas);
     if (st != RT_OK) return st;
+    if (tlas->info.layout != RT_LAYOUT_F32)
+        return fail(RT_ERR_UNSUPPORTED, "instancing takes an RT_LAYOUT_F32 top-level scene");
     if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
     st = check_instance_info(info);
     if (st != RT_OK) return st;

@@ -76,7 +76,7 @@ const uint32_t kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 namespace {
 
-template <class Isect, int kSlots, int kBlock, int kChunk, bool kQueue>
+template <class Isect, int kSlots, int kBlock, int kChunk, bool kQueue, uint32_t kLayout>
 rt_status dispatch_query(const TraceRequest &q, const kernel_args &a,
                          const typename Isect::params &p, const char **err)
 {
@@ -86,55 +86,68 @@ rt_status dispatch_query(const TraceRequest &q, const kernel_args &a,
             *err = "batched launches support the closest-hit query only";
             return RT_ERR_UNSUPPORTED;
         }
-        return launch_one<Isect, closest_result, kSlots, kBlock, kChunk, kQueue, true>(a, p, s, err);
+        return launch_one<Isect, closest_result, kSlots, kBlock, kChunk, kQueue, true, kLayout>(a, p, s,
+                                                                                               err);
     }
     switch (q.query) {
     case Query::Any:
-        return launch_one<Isect, any_result, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
+        return launch_one<Isect, any_result, kSlots, kBlock, kChunk, kQueue, false, kLayout>(a, p, s,
+                                                                                            err);
     case Query::Multi:
         // the kept list lives in registers: a short list for small k keeps
         // the kernel's register use (and so its occupancy) closer to closest-hit
         if (q.multi_k <= 4)
-            return launch_one<Isect, multi_result<4>, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
-        return launch_one<Isect, multi_result<RT_MAX_MULTI>, kSlots, kBlock, kChunk, kQueue>(a, p, s,
-                                                                                              err);
+            return launch_one<Isect, multi_result<4>, kSlots, kBlock, kChunk, kQueue, false, kLayout>(
+                a, p, s, err);
+        return launch_one<Isect, multi_result<RT_MAX_MULTI>, kSlots, kBlock, kChunk, kQueue, false,
+                          kLayout>(a, p, s, err);
     case Query::Closest:
         break;
     }
-    return launch_one<Isect, closest_result, kSlots, kBlock, kChunk, kQueue>(a, p, s, err);
+    return launch_one<Isect, closest_result, kSlots, kBlock, kChunk, kQueue, false, kLayout>(a, p, s,
+                                                                                            err);
 }
 
-template <class Base, int kSlots, int kBlock, int kChunk, bool kQueue>
+template <class Base, int kSlots, int kBlock, int kChunk, bool kQueue, uint32_t kLayout>
 rt_status dispatch_count(const TraceRequest &q, const kernel_args &a,
                          const typename Base::params &p, const char **err)
 {
     if (q.count)
-        return dispatch_query<counting_intersector<Base>, kSlots, kBlock, kChunk, kQueue>(q, a, p, err);
-    return dispatch_query<Base, kSlots, kBlock, kChunk, kQueue>(q, a, p, err);
+        return dispatch_query<counting_intersector<Base>, kSlots, kBlock, kChunk, kQueue, kLayout>(
+            q, a, p, err);
+    return dispatch_query<Base, kSlots, kBlock, kChunk, kQueue, kLayout>(q, a, p, err);
 }
 
 template <int kSlots, int kBlock, int kChunk, bool kQueue>
+rt_status dispatch_runtime(const TraceRequest &q, const kernel_args &a, const char **err)
+{
+    runtime_params rp;
+    rp.alpha.texcoords = reinterpret_cast<const float2 *>(q.alpha.texcoords);
+    rp.alpha.textures = q.alpha.textures;
+    rp.alpha.width = q.alpha.width;
+    rp.alpha.height = q.alpha.height;
+    rp.alpha.alpha_min = q.alpha.alpha_min;
+    rp.checker_n = q.checker.checker_n;
+    rp.kind = uint32_t(q.kind);
+    hipStream_t s = static_cast<hipStream_t>(q.stream);
+    if (q.runtime_dispatch == 1)
+        return launch_one<runtime_switch_intersector, closest_result, kSlots, kBlock, kChunk, kQueue>(
+            a, rp, s, err);
+    return launch_one<runtime_call_intersector, closest_result, kSlots, kBlock, kChunk, kQueue>(
+        a, rp, s, err);
+}
+
+template <int kSlots, int kBlock, int kChunk, bool kQueue, uint32_t kLayout = RT_LAYOUT_F32>
 rt_status dispatch_kind(const TraceRequest &q, const kernel_args &a, const char **err)
 {
-    if (q.runtime_dispatch) {
-        runtime_params rp;
-        rp.alpha.texcoords = reinterpret_cast<const float2 *>(q.alpha.texcoords);
-        rp.alpha.textures = q.alpha.textures;
-        rp.alpha.width = q.alpha.width;
-        rp.alpha.height = q.alpha.height;
-        rp.alpha.alpha_min = q.alpha.alpha_min;
-        rp.checker_n = q.checker.checker_n;
-        rp.kind = uint32_t(q.kind);
-        hipStream_t s = static_cast<hipStream_t>(q.stream);
-        if (q.runtime_dispatch == 1)
-            return launch_one<runtime_switch_intersector, closest_result, kSlots, kBlock, kChunk,
-                              kQueue>(a, rp, s, err);
-        return launch_one<runtime_call_intersector, closest_result, kSlots, kBlock, kChunk, kQueue>(
-            a, rp, s, err);
+    // the run-time dispatch variants exist for the float32 layout only
+    // (launch_trace rejects them otherwise)
+    if constexpr (kLayout == RT_LAYOUT_F32) {
+        if (q.runtime_dispatch) return dispatch_runtime<kSlots, kBlock, kChunk, kQueue>(q, a, err);
     }
     switch (q.kind) {
     case RT_ISECT_DEFAULT:
-        return dispatch_count<default_intersector, kSlots, kBlock, kChunk, kQueue>(
+        return dispatch_count<default_intersector, kSlots, kBlock, kChunk, kQueue, kLayout>(
             q, a, default_intersector::params{}, err);
     case RT_ISECT_ALPHA: {
         alpha_intersector::params p;
@@ -143,12 +156,13 @@ rt_status dispatch_kind(const TraceRequest &q, const kernel_args &a, const char 
         p.width = q.alpha.width;
         p.height = q.alpha.height;
         p.alpha_min = q.alpha.alpha_min;
-        return dispatch_count<alpha_intersector, kSlots, kBlock, kChunk, kQueue>(q, a, p, err);
+        return dispatch_count<alpha_intersector, kSlots, kBlock, kChunk, kQueue, kLayout>(q, a, p, err);
     }
     case RT_ISECT_PROCEDURAL: {
         checker_intersector::params p;
         p.n = q.checker.checker_n;
-        return dispatch_count<checker_intersector, kSlots, kBlock, kChunk, kQueue>(q, a, p, err);
+        return dispatch_count<checker_intersector, kSlots, kBlock, kChunk, kQueue, kLayout>(q, a, p,
+                                                                                          err);
     }
     }
     *err = "unknown intersector kind";
@@ -205,6 +219,7 @@ rt_status launch_instanced(const InstancedRequest &q, const char **err)
     }
     a.sc.root_ref = info.root_ref;
     a.sc.n_tris = info.n_tris;
+    a.sc.layout = info.layout;
     a.rays = static_cast<const float4 *>(q.rays);
     a.n_rays = q.n_rays;
     a.out = q.out;
@@ -243,6 +258,18 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
     a.queue = static_cast<uint32_t *>(q.queue);
 
     const LaunchShape &sh = q.shape;
+    // 32-byte nodes: compiled for the default launch shape only
+    if (q.scene->info.layout == RT_LAYOUT_Q8) {
+        constexpr LaunchShape d = kDefaultShape;
+        if (sh.block != d.block || sh.lds_stack != d.lds_stack || sh.chunk != d.chunk ||
+            sh.queue != d.queue || q.runtime_dispatch) {
+            *err = "the compressed node layout is compiled for the default launch shape and the "
+                   "compile-time intersectors only";
+            return RT_ERR_UNSUPPORTED;
+        }
+        return dispatch_kind<int(d.lds_stack), int(d.block), int(d.chunk), d.queue != 0,
+                             RT_LAYOUT_Q8>(q, a, err);
+    }
 #define RTX_SHAPE(B, L, C, Q)                                                          \
     if (sh.block == B && sh.lds_stack == L && sh.chunk == C && sh.queue == Q)          \
         return dispatch_kind<L, B, C, Q>(q, a, err);

@@ -26,7 +26,9 @@ RT_FLAG_COUNT = 1
 RT_FLAG_RUNTIME_SWITCH = 2
 RT_FLAG_RUNTIME_CALL = 4
 RT_NODE_BYTES = 64
+RT_NODE_BYTES_Q8 = 32
 RT_TRI_BYTES = 48
+LAYOUTS = {"f32": 0, "q8": 1}
 KINDS = {"default": 0, "alpha": 1, "procedural": 2}
 
 
@@ -49,7 +51,7 @@ class rt_procedural_params(C.Structure):
 class rt_bvh_info(C.Structure):
     _fields_ = [("n_tris", C.c_uint32), ("n_nodes", C.c_uint32), ("max_depth", C.c_uint32),
                 ("max_geom_id", C.c_uint32), ("root_ref", C.c_uint32),
-                ("root_lo", C.c_float * 3), ("root_hi", C.c_float * 3)]
+                ("root_lo", C.c_float * 3), ("root_hi", C.c_float * 3), ("layout", C.c_uint32)]
 
 
 class rt_scene(C.Structure):
@@ -76,7 +78,7 @@ class rt_batch_entry(C.Structure):
 
 class rt_batch_info(C.Structure):
     _fields_ = [("n_scenes", C.c_uint32), ("n_rays", C.c_uint32), ("max_depth", C.c_uint32),
-                ("kind", C.c_uint32)]
+                ("kind", C.c_uint32), ("layout", C.c_uint32)]
 
 
 _lib = None
@@ -86,6 +88,7 @@ _P, _U32, _SZ = C.c_void_p, C.c_uint32, C.c_size_t
 SIGNATURES = [
     ("rt_bvh_buffer_bytes", C.c_int, [_U32, C.POINTER(_SZ), C.POINTER(_SZ)]),
     ("rt_bvh_build", C.c_int, [_P, _P, _U32, _P, _SZ, _P, _SZ, C.POINTER(rt_bvh_info)]),
+    ("rt_bvh_compress", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_trace_workspace_bytes", C.c_int, [C.POINTER(rt_scene), _U32, _U32, C.POINTER(_SZ)]),
     ("rt_trace_closest", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                    _SZ, _P]),
@@ -462,10 +465,31 @@ class Scene:
         return p
 
 
-def upload_scene(vertices, geom_ids=None, texcoords=None, textures=None, device="cuda") -> Scene:
-    """Builds the BVH on the host (rt_bvh_build) and copies it to ``device``."""
+def rt_bvh_compress(nodes: np.ndarray, info: rt_bvh_info):
+    """64-byte nodes (from rt_bvh_build) -> 32-byte nodes with 8-bit child
+    boxes.  Returns ``(nodes uint8, info)`` with ``info.layout = 1``."""
+    n = int(info.n_nodes)
+    src = np.ascontiguousarray(nodes, np.uint8)
+    src16 = np.zeros(max(1, n * RT_NODE_BYTES // 16), dtype=np.dtype((np.void, 16)))
+    src16.view(np.uint8)[: n * RT_NODE_BYTES] = src[: n * RT_NODE_BYTES]
+    out = np.zeros(max(1, n * RT_NODE_BYTES_Q8 // 16), dtype=np.dtype((np.void, 16)))
+    oinfo = rt_bvh_info()
+    _check(load_library().rt_bvh_compress(src16.ctypes.data if n else None, C.byref(info),
+                                           out.ctypes.data if n else None, n * RT_NODE_BYTES_Q8,
+                                           C.byref(oinfo)), "rt_bvh_compress")
+    return out.view(np.uint8)[: n * RT_NODE_BYTES_Q8], oinfo
+
+
+def upload_scene(vertices, geom_ids=None, texcoords=None, textures=None, device="cuda",
+                 layout: str = "f32") -> Scene:
+    """Builds the BVH on the host (rt_bvh_build, then rt_bvh_compress for
+    ``layout="q8"``) and copies it to ``device``."""
     torch = _torch()
+    if layout not in LAYOUTS:
+        raise ValueError(f"unknown layout {layout!r}")
     nodes, tris, info = rt_bvh_build(vertices, geom_ids)
+    if layout == "q8":
+        nodes, info = rt_bvh_compress(nodes, info)
     dn = torch.from_numpy(nodes.copy()).to(device) if nodes.size else None
     dt = torch.from_numpy(tris.copy()).to(device)
     tc = None if texcoords is None else torch.from_numpy(

@@ -485,3 +485,62 @@ def test_custom_intersector_library_loads_and_validates(lib):
                               None) == -2
     assert cl.prim_mask_trace(C.byref(sc), 0x30000, 10, 0x10, 0x40000, None, 0x50000, 16,
                               None) == -4
+
+
+# ----------------------------------------------------------------------------
+# 32-byte node layout
+# ----------------------------------------------------------------------------
+def _q8_scenes():
+    from paper_1912_12786_amd import workloads as W
+    rng = np.random.default_rng(11)
+    flat = W.random_triangles(300, 12, side=0.2, box=(-3.0, 3.0)).copy()
+    flat[::3, :, 1] = flat[::3, :1, 1]                      # zero extent on y
+    return {"tiny": W.tiny().vertices,
+            "billboards": W.billboards(3000).vertices,
+            "negative_flat": flat,
+            "far": (rng.uniform(-1, 1, size=(500, 3, 3)) * 0.01 + 5e3).astype(np.float32)}
+
+
+@pytest.mark.parametrize("name", ["tiny", "billboards", "negative_flat", "far"])
+def test_compress_matches_oracle_quantizer(lib, oracle_lib, name):
+    """The product's 32-byte nodes equal the oracle's quantization of its own
+    (identical) BVH word for word: frames, 8-bit coordinates, references."""
+    v = _q8_scenes()[name]
+    nodes, tris, info = rtx.rt_bvh_build(v)
+    q, qi = rtx.rt_bvh_compress(nodes, info)
+    assert qi.layout == 1 and qi.n_nodes == info.n_nodes and qi.root_ref == info.root_ref
+    b = oracle_lib.build_bvh(v)
+    Q = oracle_lib.quantize(b)
+    inner = np.nonzero(b.nodes["count"] == 0)[0]
+    assert inner.size == info.n_nodes
+    w = q.view(np.uint32).reshape(-1, 8)
+    assert np.array_equal(w[:, :3], Q["frames"][inner])
+    assert np.array_equal(w[:, 3:6].copy().view(np.uint8).reshape(-1, 12), Q["q"][inner])
+    assert np.array_equal(w[:, 6:8], nodes.view(np.uint32).reshape(-1, 16)[:, 12:14])
+
+
+def test_compress_validation(lib):
+    v = _q8_scenes()["tiny"]
+    nodes, tris, info = rtx.rt_bvh_build(v)
+    q, qi = rtx.rt_bvh_compress(nodes, info)
+    with pytest.raises(rtx.RtxError, match="not RT_LAYOUT_F32"):
+        rtx.rt_bvh_compress(nodes, qi)
+    bad = nodes.copy()
+    bad.view(np.float32)[3] = np.inf                         # hi0.x of node 0
+    with pytest.raises(rtx.RtxError, match="not finite"):
+        rtx.rt_bvh_compress(bad, info)
+    empty = rtx.rt_bvh_info()
+    _, ei = rtx.rt_bvh_compress(np.zeros(0, np.uint8), empty)
+    assert ei.layout == 1 and ei.n_nodes == 0
+    sc = _fake_scene()
+    sc.info.layout = 2
+    assert _closest(lib, sc) == -1
+    assert b"unknown scene node layout" in lib.rt_last_error()
+    sc.info.layout = 1
+    assert _closest(lib, sc, n=0) == 0
+    # instancing takes float32-box scenes only
+    from paper_1912_12786_amd import workloads as W
+    wl = W.instanced(3, 8, 8)
+    with pytest.raises(rtx.RtxError, match="RT_LAYOUT_F32"):
+        rtx.rt_instance_pack([_fake_scene(), sc], np.zeros(3, np.uint32), wl["inst_m"][:3],
+                             wl["world_lo"][:3], wl["world_hi"][:3])
