@@ -242,7 +242,7 @@ def bench_batched(args):
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     scenes = W.batched()
-    sc_list = [rtx.upload_scene(s["vertices"], device=dev) for s in scenes]
+    sc_list = [rtx.upload_scene(s["vertices"], device=dev, layout=args.layout) for s in scenes]
     counts = [s["rays"].shape[0] for s in scenes]
     batch = rtx.Batch(sc_list, counts, "default", device=dev)
     rays = torch.from_numpy(np.concatenate([s["rays"] for s in scenes])).to(dev)
@@ -298,6 +298,7 @@ def bench_batched(args):
         "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"batched_{len(scenes)}_scenes", "n_scenes": len(scenes),
+                   "node_layout": args.layout,
                    "n_tris": int(sum(s["vertices"].shape[0] for s in scenes)), "n_rays": int(n),
                    "launch_shape": list(best)},
         "mrays_s": {k: round(n / v / 1e3, 2) for k, v in ms.items()},

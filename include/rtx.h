@@ -45,7 +45,7 @@ typedef enum rt_status {
     RT_OK = 0,
     RT_ERR_INVALID_ARG = -1,  /* null pointer, bad size, inconsistent scene */
     RT_ERR_MISALIGNED = -2,   /* a device array is not 16-byte aligned */
-    RT_ERR_UNSUPPORTED = -3,  /* unknown intersector kind or flag */
+    RT_ERR_UNSUPPORTED = -3,  /* unknown intersector kind or flag; combination not compiled in */
     RT_ERR_WORKSPACE = -4,    /* workspace missing or smaller than required */
     RT_ERR_HIP = -5,          /* a HIP runtime call failed */
     RT_ERR_OUT_OF_MEMORY = -6 /* host scratch allocation in the builder failed */

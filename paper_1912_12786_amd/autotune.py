@@ -22,7 +22,9 @@ def _device_name(torch) -> str:
 
 
 def time_shapes(run, steps: int = 10, warmup: int = 2, shapes=None) -> dict:
-    """Mean milliseconds per call of ``run()`` for each launch shape."""
+    """Mean milliseconds per call of ``run()`` for each launch shape that the
+    traced scenes can use (compressed-node scenes run with the default shape
+    only: the library refuses the others before launching anything)."""
     import torch
     shapes = shapes or rtx.rt_launch_shapes()
     saved = rtx.rt_launch_shapes()[0]
@@ -31,6 +33,12 @@ def time_shapes(run, steps: int = 10, warmup: int = 2, shapes=None) -> dict:
     try:
         for sh in shapes:
             rtx.rt_set_launch_shape(*sh)
+            try:
+                run()
+            except rtx.RtxError as e:
+                if e.status != rtx.RT_ERR_UNSUPPORTED:
+                    raise
+                continue
             for _ in range(warmup):
                 run()
             torch.cuda.synchronize()

@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtx.so")
 
 RT_OK = 0
+RT_ERR_UNSUPPORTED = -3
 RT_MISS = 0xFFFFFFFF
 RT_FLAG_COUNT = 1
 RT_FLAG_RUNTIME_SWITCH = 2
