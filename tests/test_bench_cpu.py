@@ -40,3 +40,22 @@ def test_tile_order_is_a_tiled_permutation():
     assert y.max() < 8 and x.max() < 8
     assert np.array_equal(first[:8], np.arange(8))
     assert first[8] == 24
+
+
+def test_bytes_per_ray_compressed_nodes():
+    c = np.array([[7, 4, 1, 1]], np.uint32)
+    assert bench.bytes_per_ray(c, "alpha", node_bytes=32).tolist() == [48 + 3 * 32 + 4 * 48 + 28]
+
+
+def test_morton_tile_order():
+    wl = W.tiny(24, 16)
+    o = bench.tile_order(wl, tile=8, morton=True)
+    assert np.array_equal(np.sort(o), np.arange(wl.n_rays))
+    first = o[:64]
+    y, x = np.divmod(first, 24)
+    assert y.max() < 8 and x.max() < 8
+    # Z-order: each aligned group of 4 is a 2x2 pixel quad, each group of 16 a 4x4 block
+    assert (y[:4].tolist(), x[:4].tolist()) == ([0, 0, 1, 1], [0, 1, 0, 1])
+    for g in range(0, 64, 16):
+        assert y[g:g + 16].max() - y[g:g + 16].min() == 3 and x[g:g + 16].max() - x[g:g + 16].min() == 3
+    assert (y[4], x[4]) == (0, 2)
