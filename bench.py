@@ -104,7 +104,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(wl, kind, kind_kw, threads, budget_s=8.0, layout="f32"):
+def cpu_baseline(wl, kind, kind_kw, threads, budget_s=8.0, layout="f32", max_leaf=4):
     """The oracle as it stands, on this host's cores, on the same workload:
     oracle B (float32 BVH traversal of its own BVH, in the node layout the
     GPU run used) over every ray, repeated until about ``budget_s`` seconds
@@ -115,7 +115,7 @@ def cpu_baseline(wl, kind, kind_kw, threads, budget_s=8.0, layout="f32"):
     from paper_1912_12786_amd import workloads as W
     oracle.build(force=False)
     t0 = time.perf_counter()
-    bvh = oracle.build_bvh(wl.vertices)
+    bvh = oracle.build_bvh(wl.vertices, max_leaf=max_leaf)
     if layout == "q8":
         bvh.qbox = oracle.quantize(bvh)["qbox"]
     t_build = time.perf_counter() - t0
@@ -145,7 +145,8 @@ def cpu_baseline(wl, kind, kind_kw, threads, budget_s=8.0, layout="f32"):
         "unit": "Mrays/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"oracle B (float32 BVH traversal, {layout} nodes; its own BVH built in "
+        "sample": (f"oracle B (float32 BVH traversal, {layout} nodes, leaves of <= {max_leaf}; "
+                   f"its own BVH built in "
                    f"{t_build:.2f} s) over "
                    f"all {wl.n_rays} rays, {len(passes)} passes, median {t_b:.3f} s; oracle A "
                    f"(float64 brute force over all {wl.n_tris} triangles) on {len(idx)} sampled "
@@ -242,7 +243,8 @@ def bench_batched(args):
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     scenes = W.batched()
-    sc_list = [rtx.upload_scene(s["vertices"], device=dev, layout=args.layout) for s in scenes]
+    sc_list = [rtx.upload_scene(s["vertices"], device=dev, layout=args.layout,
+                                max_leaf=args.max_leaf) for s in scenes]
     counts = [s["rays"].shape[0] for s in scenes]
     batch = rtx.Batch(sc_list, counts, "default", device=dev)
     rays = torch.from_numpy(np.concatenate([s["rays"] for s in scenes])).to(dev)
@@ -298,7 +300,7 @@ def bench_batched(args):
         "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"batched_{len(scenes)}_scenes", "n_scenes": len(scenes),
-                   "node_layout": args.layout,
+                   "node_layout": args.layout, "max_leaf": args.max_leaf,
                    "n_tris": int(sum(s["vertices"].shape[0] for s in scenes)), "n_rays": int(n),
                    "launch_shape": list(best)},
         "mrays_s": {k: round(n / v / 1e3, 2) for k, v in ms.items()},
@@ -410,6 +412,10 @@ def main():
     ap.add_argument("--ray-order", default="scanline", choices=["scanline", "tiled", "morton"],
                     help="tiled: primary rays reordered into 8x8 pixel tiles before upload "
                          "(hits come back in that order); morton: the same tiles in Z-order")
+    ap.add_argument("--max-leaf", type=int, default=2,
+                    help="leaf size limit of the BVH build (1..7; the library's default is 4; "
+                         "2 measured fastest on the billboards). Used by the billboards, tiny, "
+                         "spheres and batched workloads")
     ap.add_argument("--layout", default="f32", choices=["f32", "q8"],
                     help="inner-node layout: f32 = 64-B nodes with float32 boxes, q8 = 32-B "
                          "nodes with 8-bit boxes (rt_bvh_compress)")
@@ -462,7 +468,7 @@ def main():
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     scene = rtx.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures, device=dev,
-                             layout=args.layout)
+                             layout=args.layout, max_leaf=args.max_leaf)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     log(f"workload {wl.name}: gen {t_gen:.2f} s, host BVH build + upload {t_build:.2f} s, "
@@ -533,6 +539,7 @@ def main():
         if tf.get("kernel_source_sha") == kernel_source_sha() and kind == "alpha" \
                 and query == "closest" and args.ray_order == "scanline" \
                 and tf.get("layout", "f32") == args.layout \
+                and tf.get("max_leaf", 4) == args.max_leaf \
                 and list(rtx.rt_launch_shapes()[0]) == tf.get("launch_shape") and not args.shape:
             traffic = tf.get("traffic_bytes_per_launch")
 
@@ -541,7 +548,7 @@ def main():
         threads = len(os.sched_getaffinity(0))
         kind_kw = dict(geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures,
                        alpha_min=128) if kind == "alpha" else {}
-        cpu = cpu_baseline(wl, kind, kind_kw, threads, layout=args.layout)
+        cpu = cpu_baseline(wl, kind, kind_kw, threads, layout=args.layout, max_leaf=args.max_leaf)
 
     mean_c = counters.mean(axis=0)
     result = {
@@ -569,7 +576,9 @@ def main():
             "textures": "16 x 256x256 RGBA8" if wl.textures is not None else None,
             "ray_order": {"tiled": "8x8 tiles", "morton": "8x8 tiles, Z-order inside"}.get(
                 args.ray_order, "scanline"),
-            "bvh": f"binary SAH, {scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}",
+            "bvh": (f"binary SAH, leaves of <= {args.max_leaf} triangles, {scene.info.n_nodes} "
+                    f"inner nodes, depth {scene.info.max_depth}"),
+            "max_leaf": args.max_leaf,
             "node_layout": ("32-B nodes, 8-bit child boxes" if args.layout == "q8"
                             else "64-B nodes, float32 child boxes"),
             "launch_shape": ([int(x) for x in args.shape.split(",")] if args.shape

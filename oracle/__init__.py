@@ -72,6 +72,8 @@ def _load():
         lib.orc_brute.restype = C.c_int
         lib.orc_build.argtypes = [P, C.c_uint32, P, P, P, P]
         lib.orc_build.restype = C.c_int
+        lib.orc_build_leaf.argtypes = [P, C.c_uint32, C.c_uint32, P, P, P, P]
+        lib.orc_build_leaf.restype = C.c_int
         lib.orc_traverse.argtypes = [P, P, C.c_uint32, P, P, C.c_uint32, P, C.c_uint32, C.c_int,
                                      P, C.c_int, C.c_uint32, P, P, P, P, P, P, C.c_int]
         lib.orc_brute_multi.argtypes = [P, P, C.c_uint32, P, C.c_uint32, C.c_int, P, C.c_uint32,
@@ -181,8 +183,9 @@ class OracleBVH:
         return int(self.nodes.shape[0])
 
 
-def build_bvh(vertices) -> OracleBVH:
-    """Oracle B's own BVH build (binned SAH, leaves of at most 4 triangles)."""
+def build_bvh(vertices, max_leaf: int = 4) -> OracleBVH:
+    """Oracle B's own BVH build (binned SAH, leaves of at most ``max_leaf``
+    triangles, 1..7)."""
     lib = _load()
     verts = np.ascontiguousarray(vertices, np.float32).reshape(-1, 9)
     n = verts.shape[0]
@@ -190,7 +193,10 @@ def build_bvh(vertices) -> OracleBVH:
     perm = np.zeros(max(1, n), np.uint32)
     nn = C.c_uint32()
     md = C.c_uint32()
-    rc = lib.orc_build(_ptr(verts), n, _ptr(nodes), _ptr(perm), C.byref(nn), C.byref(md))
+    rc = lib.orc_build_leaf(_ptr(verts), n, int(max_leaf), _ptr(nodes), _ptr(perm), C.byref(nn),
+                            C.byref(md))
+    if rc == -2:
+        raise ValueError("max_leaf must be within 1..7")
     if rc != 0:
         raise MemoryError("orc_build failed")
     return OracleBVH(nodes[: nn.value].copy(), perm[:n].copy(), int(md.value))

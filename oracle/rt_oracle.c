@@ -333,7 +333,8 @@ int orc_brute(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
  * here (and by the product builder, which is a separate implementation):
  *   - triangle box = exact float min/max of its vertices; centroid (float64)
  *     = 0.5 * (lo + hi);
- *   - a node with at most 4 triangles is a leaf;
+ *   - a node with at most max_leaf triangles is a leaf (max_leaf in 1..7,
+ *     4 by default);
  *   - otherwise, per axis with non-zero centroid extent, 32 equal-width bins
  *     over the centroid range, bin = min(31, (int)((c - cmin) * (32 / ext)));
  *     every plane between bins is a candidate with cost
@@ -360,6 +361,7 @@ typedef struct {
     orc_node *nodes;
     uint32_t n_nodes, cap;
     uint32_t max_depth;
+    uint32_t max_leaf;
 } build_ctx;
 
 static double box_area(const float lo[3], const float hi[3])
@@ -403,7 +405,7 @@ static uint32_t build_rec(build_ctx *ctx, uint32_t first, uint32_t count, uint32
         uint32_t k = ctx->perm[i];
         box_grow(nd->lo, nd->hi, ctx->tri_lo + 3 * (size_t)k, ctx->tri_hi + 3 * (size_t)k);
     }
-    if (count <= 4) {
+    if (count <= ctx->max_leaf) {
         nd->first = first;
         nd->count = count;
         return id;
@@ -476,9 +478,20 @@ static uint32_t build_rec(build_ctx *ctx, uint32_t first, uint32_t count, uint32
 /* Builds the oracle's BVH.  nodes must hold 2*n_tris (at least 1) entries.
  * Outputs: node array (preorder, node 0 = root), perm (leaf order -> input
  * triangle index), node count and maximum node depth. */
+int orc_build_leaf(const float *verts, uint32_t n_tris, uint32_t max_leaf, orc_node *nodes,
+                   uint32_t *perm, uint32_t *n_nodes_out, uint32_t *max_depth_out);
+
 int orc_build(const float *verts, uint32_t n_tris, orc_node *nodes, uint32_t *perm,
               uint32_t *n_nodes_out, uint32_t *max_depth_out)
 {
+    return orc_build_leaf(verts, n_tris, 4, nodes, perm, n_nodes_out, max_depth_out);
+}
+
+/* The same build with leaves of at most max_leaf (1..7) triangles. */
+int orc_build_leaf(const float *verts, uint32_t n_tris, uint32_t max_leaf, orc_node *nodes,
+                   uint32_t *perm, uint32_t *n_nodes_out, uint32_t *max_depth_out)
+{
+    if (max_leaf < 1 || max_leaf > 7) return -2;
     if (n_tris == 0) {
         memset(&nodes[0], 0, sizeof nodes[0]);
         box_empty(nodes[0].lo, nodes[0].hi);
@@ -505,7 +518,7 @@ int orc_build(const float *verts, uint32_t n_tris, orc_node *nodes, uint32_t *pe
         }
         perm[k] = k;
     }
-    build_ctx ctx = {tlo, thi, cen, perm, tmp, nodes, 0, 2 * n_tris, 0};
+    build_ctx ctx = {tlo, thi, cen, perm, tmp, nodes, 0, 2 * n_tris, 0, max_leaf};
     build_rec(&ctx, 0, n_tris, 0);
     *n_nodes_out = ctx.n_nodes;
     *max_depth_out = ctx.max_depth;

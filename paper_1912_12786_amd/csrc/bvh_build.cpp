@@ -4,7 +4,8 @@
 // does not describe the construction, so this library fixes one:
 //   * triangle box = exact float min/max of its three vertices; centroid =
 //     0.5 * (lo + hi) evaluated in double;
-//   * a node with <= 4 triangles becomes a leaf;
+//   * a node with <= max_leaf triangles becomes a leaf (max_leaf in 1..7,
+//     4 unless the caller chooses otherwise);
 //   * otherwise each axis with a non-zero centroid extent is cut into 32
 //     equal-width bins, bin = min(31, int((c - cmin) * (32 / extent))); every
 //     plane between two bins is costed as area(L) |L| + area(R) |R| (box
@@ -39,7 +40,6 @@ namespace rtx {
 namespace {
 
 constexpr int kBins = 32;
-constexpr uint32_t kMaxLeaf = 4;
 constexpr uint32_t kMedianDepth = 40;
 
 struct Box {
@@ -73,6 +73,7 @@ struct Builder {
     std::vector<double> cen;   // [n][3]
     std::vector<uint32_t> order, scratch;
     NodeRecord *nodes;
+    uint32_t max_leaf = 4;
     uint32_t n_inner = 0;
     uint32_t max_depth = 0;
 
@@ -192,7 +193,7 @@ struct Builder {
     uint32_t build(uint32_t first, uint32_t count, uint32_t depth)
     {
         if (depth > max_depth) max_depth = depth;
-        if (count <= kMaxLeaf) return leaf_ref(first, count);
+        if (count <= max_leaf) return leaf_ref(first, count);
         const uint32_t id = n_inner++;
         const Split sp = find_split(first, count, depth);
         const uint32_t nl = partition(first, count, sp);
@@ -212,13 +213,17 @@ struct Builder {
 
 }  // namespace
 
-uint32_t max_inner_nodes(uint32_t n_tris) { return n_tris > kMaxLeaf ? n_tris - 1 : 0; }
+uint32_t max_inner_nodes(uint32_t n_tris, uint32_t max_leaf)
+{
+    return n_tris > max_leaf ? n_tris - 1 : 0;
+}
 
 rt_status build_bvh(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
-                    NodeRecord *nodes, TriRecord *tris, rt_bvh_info *info)
+                    uint32_t max_leaf, NodeRecord *nodes, TriRecord *tris, rt_bvh_info *info)
 {
     std::memset(info, 0, sizeof *info);
     info->n_tris = n_tris;
+    info->max_leaf = max_leaf;
     if (n_tris == 0) {
         for (int a = 0; a < 3; ++a) {
             info->root_lo[a] = std::numeric_limits<float>::infinity();
@@ -229,6 +234,7 @@ rt_status build_bvh(const float *verts, const uint32_t *geom_ids, uint32_t n_tri
     try {
         Builder b;
         b.verts = verts;
+        b.max_leaf = max_leaf;
         b.tbox.resize(n_tris);
         b.cen.resize(3 * size_t(n_tris));
         b.order.resize(n_tris);

@@ -30,9 +30,10 @@ struct alignas(16) NodeQ8Record {
 };
 static_assert(sizeof(NodeQ8Record) == RT_NODE_BYTES_Q8, "compressed node record size");
 
-uint32_t max_inner_nodes(uint32_t n_tris);
+// Inner nodes of a BVH over n_tris triangles with leaves of at most max_leaf.
+uint32_t max_inner_nodes(uint32_t n_tris, uint32_t max_leaf);
 rt_status build_bvh(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
-                    NodeRecord *nodes, TriRecord *tris, rt_bvh_info *info);
+                    uint32_t max_leaf, NodeRecord *nodes, TriRecord *tris, rt_bvh_info *info);
 // 64-B nodes -> 32-B nodes (RT_ERR_INVALID_ARG if a box is not finite).
 rt_status compress_nodes(const NodeRecord *in, uint32_t n_nodes, NodeQ8Record *out);
 

@@ -44,7 +44,9 @@ rt_status check_scene(const rt_scene *sc)
         if (!aligned(sc->nodes, 16)) return fail(RT_ERR_MISALIGNED, "scene nodes not 16-byte aligned");
         if (in.n_nodes >= in.n_tris) return fail(RT_ERR_INVALID_ARG, "scene has more inner nodes than triangles");
     } else {
-        if (cnt > 4 || uint64_t(idx) + cnt > in.n_tris)
+        // rt_bvh_build_ex records its leaf limit; 0 (a hand-made info) means 4
+        const uint32_t leaf_cap = in.max_leaf ? in.max_leaf : 4u;
+        if (in.max_leaf > 7 || cnt > leaf_cap || uint64_t(idx) + cnt > in.n_tris)
             return fail(RT_ERR_INVALID_ARG, "scene root leaf out of range");
     }
     return RT_OK;
@@ -172,7 +174,7 @@ rt_status rt_bvh_buffer_bytes(uint32_t n_tris, size_t *node_bytes, size_t *tri_b
     g_last_error.clear();
     if (!node_bytes || !tri_bytes) return fail(RT_ERR_INVALID_ARG, "output pointers are NULL");
     if (n_tris > RT_MAX_TRIS) return fail(RT_ERR_INVALID_ARG, "more than 2^29-1 triangles");
-    *node_bytes = size_t(max_inner_nodes(n_tris)) * RT_NODE_BYTES;
+    *node_bytes = size_t(max_inner_nodes(n_tris, 1)) * RT_NODE_BYTES;
     *tri_bytes = size_t(n_tris) * RT_TRI_BYTES;
     return RT_OK;
 }
@@ -180,11 +182,20 @@ rt_status rt_bvh_buffer_bytes(uint32_t n_tris, size_t *node_bytes, size_t *tri_b
 rt_status rt_bvh_build(const float *vertices, const uint32_t *geom_ids, uint32_t n_tris,
                        void *nodes, size_t node_cap, void *tris, size_t tri_cap, rt_bvh_info *info)
 {
+    return rt_bvh_build_ex(vertices, geom_ids, n_tris, nullptr, nodes, node_cap, tris, tri_cap, info);
+}
+
+rt_status rt_bvh_build_ex(const float *vertices, const uint32_t *geom_ids, uint32_t n_tris,
+                          const rt_build_params *params, void *nodes, size_t node_cap, void *tris,
+                          size_t tri_cap, rt_bvh_info *info)
+{
     g_last_error.clear();
     if (!info) return fail(RT_ERR_INVALID_ARG, "info is NULL");
+    const uint32_t max_leaf = params ? params->max_leaf : 4u;
+    if (max_leaf < 1 || max_leaf > 7) return fail(RT_ERR_INVALID_ARG, "max_leaf must be within 1..7");
     if (n_tris > RT_MAX_TRIS) return fail(RT_ERR_INVALID_ARG, "more than 2^29-1 triangles");
     if (n_tris > 0 && !vertices) return fail(RT_ERR_INVALID_ARG, "vertices are NULL");
-    const size_t need_nodes = size_t(max_inner_nodes(n_tris)) * RT_NODE_BYTES;
+    const size_t need_nodes = size_t(max_inner_nodes(n_tris, max_leaf)) * RT_NODE_BYTES;
     const size_t need_tris = size_t(n_tris) * RT_TRI_BYTES;
     if (need_nodes > 0 && (!nodes || node_cap < need_nodes))
         return fail(RT_ERR_INVALID_ARG, "node buffer smaller than rt_bvh_buffer_bytes");
@@ -192,7 +203,7 @@ rt_status rt_bvh_build(const float *vertices, const uint32_t *geom_ids, uint32_t
         return fail(RT_ERR_INVALID_ARG, "triangle buffer smaller than rt_bvh_buffer_bytes");
     if ((nodes && !aligned(nodes, 16)) || (tris && !aligned(tris, 16)))
         return fail(RT_ERR_MISALIGNED, "host output buffers must be 16-byte aligned");
-    rt_status st = build_bvh(vertices, geom_ids, n_tris, static_cast<NodeRecord *>(nodes),
+    rt_status st = build_bvh(vertices, geom_ids, n_tris, max_leaf, static_cast<NodeRecord *>(nodes),
                              static_cast<TriRecord *>(tris), info);
     if (st != RT_OK) return fail(st, "host allocation failed during BVH build");
     return RT_OK;

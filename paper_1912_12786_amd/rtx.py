@@ -52,7 +52,12 @@ class rt_procedural_params(C.Structure):
 class rt_bvh_info(C.Structure):
     _fields_ = [("n_tris", C.c_uint32), ("n_nodes", C.c_uint32), ("max_depth", C.c_uint32),
                 ("max_geom_id", C.c_uint32), ("root_ref", C.c_uint32),
-                ("root_lo", C.c_float * 3), ("root_hi", C.c_float * 3), ("layout", C.c_uint32)]
+                ("root_lo", C.c_float * 3), ("root_hi", C.c_float * 3), ("layout", C.c_uint32),
+                ("max_leaf", C.c_uint32)]
+
+
+class rt_build_params(C.Structure):
+    _fields_ = [("max_leaf", C.c_uint32)]
 
 
 class rt_scene(C.Structure):
@@ -89,6 +94,8 @@ _P, _U32, _SZ = C.c_void_p, C.c_uint32, C.c_size_t
 SIGNATURES = [
     ("rt_bvh_buffer_bytes", C.c_int, [_U32, C.POINTER(_SZ), C.POINTER(_SZ)]),
     ("rt_bvh_build", C.c_int, [_P, _P, _U32, _P, _SZ, _P, _SZ, C.POINTER(rt_bvh_info)]),
+    ("rt_bvh_build_ex", C.c_int, [_P, _P, _U32, C.POINTER(rt_build_params), _P, _SZ, _P, _SZ,
+                                  C.POINTER(rt_bvh_info)]),
     ("rt_bvh_compress", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_trace_workspace_bytes", C.c_int, [C.POINTER(rt_scene), _U32, _U32, C.POINTER(_SZ)]),
     ("rt_trace_closest", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
@@ -157,8 +164,9 @@ def rt_bvh_buffer_bytes(n_tris: int):
     return nb.value, tb.value
 
 
-def rt_bvh_build(vertices: np.ndarray, geom_ids: np.ndarray | None = None):
-    """Host BVH build.  Returns ``(nodes, tris, info)``: uint8 arrays holding
+def rt_bvh_build(vertices: np.ndarray, geom_ids: np.ndarray | None = None, max_leaf: int = 4):
+    """Host BVH build (rt_bvh_build_ex; leaves of at most ``max_leaf``
+    triangles).  Returns ``(nodes, tris, info)``: uint8 arrays holding
     ``info.n_nodes`` 64-byte node records and ``n_tris`` 48-byte triangle
     records, and the filled ``rt_bvh_info``."""
     lib = load_library()
@@ -172,10 +180,11 @@ def rt_bvh_build(vertices: np.ndarray, geom_ids: np.ndarray | None = None):
     nodes = np.zeros(max(nb, 16) // 16, dtype=np.dtype((np.void, 16)))
     tris = np.zeros(max(tb, 16) // 16, dtype=np.dtype((np.void, 16)))
     info = rt_bvh_info()
-    _check(lib.rt_bvh_build(v.ctypes.data if n else None, None if g is None else g.ctypes.data, n,
-                            nodes.ctypes.data if nb else None, nb,
-                            tris.ctypes.data if tb else None, tb, C.byref(info)),
-           "rt_bvh_build")
+    params = rt_build_params(int(max_leaf))
+    _check(lib.rt_bvh_build_ex(v.ctypes.data if n else None, None if g is None else g.ctypes.data,
+                               n, C.byref(params), nodes.ctypes.data if nb else None, nb,
+                               tris.ctypes.data if tb else None, tb, C.byref(info)),
+           "rt_bvh_build_ex")
     nodes_u8 = nodes.view(np.uint8)[: info.n_nodes * RT_NODE_BYTES]
     tris_u8 = tris.view(np.uint8)[: n * RT_TRI_BYTES]
     return nodes_u8, tris_u8, info
@@ -482,13 +491,14 @@ def rt_bvh_compress(nodes: np.ndarray, info: rt_bvh_info):
 
 
 def upload_scene(vertices, geom_ids=None, texcoords=None, textures=None, device="cuda",
-                 layout: str = "f32") -> Scene:
-    """Builds the BVH on the host (rt_bvh_build, then rt_bvh_compress for
-    ``layout="q8"``) and copies it to ``device``."""
+                 layout: str = "f32", max_leaf: int = 4) -> Scene:
+    """Builds the BVH on the host (rt_bvh_build_ex with leaves of at most
+    ``max_leaf`` triangles, then rt_bvh_compress for ``layout="q8"``) and
+    copies it to ``device``."""
     torch = _torch()
     if layout not in LAYOUTS:
         raise ValueError(f"unknown layout {layout!r}")
-    nodes, tris, info = rt_bvh_build(vertices, geom_ids)
+    nodes, tris, info = rt_bvh_build(vertices, geom_ids, max_leaf)
     if layout == "q8":
         nodes, info = rt_bvh_compress(nodes, info)
     dn = torch.from_numpy(nodes.copy()).to(device) if nodes.size else None

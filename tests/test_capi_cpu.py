@@ -201,8 +201,10 @@ def test_builder_deterministic():
 
 
 def test_buffer_bytes():
+    # bounds for any leaf size: n - 1 inner nodes (leaves of one triangle)
     assert rtx.rt_bvh_buffer_bytes(0) == (0, 0)
-    assert rtx.rt_bvh_buffer_bytes(4) == (0, 4 * 48)
+    assert rtx.rt_bvh_buffer_bytes(1) == (0, 48)
+    assert rtx.rt_bvh_buffer_bytes(4) == (3 * 64, 4 * 48)
     assert rtx.rt_bvh_buffer_bytes(5) == (4 * 64, 5 * 48)
     with pytest.raises(rtx.RtxError):
         rtx.rt_bvh_buffer_bytes(1 << 29)
@@ -544,3 +546,43 @@ def test_compress_validation(lib):
     with pytest.raises(rtx.RtxError, match="RT_LAYOUT_F32"):
         rtx.rt_instance_pack([_fake_scene(), sc], np.zeros(3, np.uint32), wl["inst_m"][:3],
                              wl["world_lo"][:3], wl["world_hi"][:3])
+
+
+# ----------------------------------------------------------------------------
+# leaf size (rt_bvh_build_ex)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("max_leaf", [1, 2, 3, 7])
+@pytest.mark.parametrize("name", ["tiny", "negative_flat"])
+def test_leaf_size_builds_match_oracle(lib, oracle_lib, name, max_leaf):
+    """The product's BVH with leaves of at most max_leaf triangles equals the
+    oracle's independent build with the same limit, node for node."""
+    v = _q8_scenes()[name]
+    nodes, tris, info = rtx.rt_bvh_build(v, max_leaf=max_leaf)
+    assert info.max_leaf == max_leaf
+    ob = oracle_lib.build_bvh(v, max_leaf=max_leaf)
+    prod = decode_product_bvh(nodes, tris, info)
+    orc = decode_oracle_bvh(ob)
+    assert len(prod) == len(orc)
+    for a, b in zip(prod, orc):
+        for k in (0, 1):
+            assert np.array_equal(np.array(a[k], np.float32).view(np.uint32),
+                                  np.array(b[k], np.float32).view(np.uint32))
+        assert a[2:] == b[2:]
+    assert np.array_equal(tris.view(np.uint32).reshape(-1, 12)[:, 3], ob.perm)
+    counts = ob.nodes["count"]
+    assert counts.max() <= max_leaf and (counts > 0).sum() >= v.shape[0] / max_leaf
+
+
+def test_leaf_size_validation(lib):
+    v = np.zeros((3, 3, 3), np.float32)
+    for bad in (0, 8):
+        with pytest.raises(rtx.RtxError, match="max_leaf"):
+            rtx.rt_bvh_build(v, max_leaf=bad)
+    # a root leaf of 7 triangles is a valid scene
+    v7 = np.random.default_rng(1).uniform(0, 1, size=(7, 3, 3)).astype(np.float32)
+    nodes, tris, info = rtx.rt_bvh_build(v7, max_leaf=7)
+    assert info.n_nodes == 0 and info.root_ref >> 29 == 7
+    sc = _fake_scene(n_tris=7, n_nodes=0, root_ref=(7 << 29))
+    assert _closest(lib, sc, n=0) == -1              # hand-made info: limit 4
+    sc.info.max_leaf = 7
+    assert _closest(lib, sc, n=0) == 0

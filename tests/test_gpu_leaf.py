@@ -1,0 +1,84 @@
+"""GPU parity for BVHs built with other leaf size limits (rt_bvh_build_ex):
+every compiled kernel against oracle B built with the same limit, bit for
+bit (hits, occluders, counters), including the benchmark's configuration
+(billboards, leaves of at most 2 triangles, both node layouts)."""
+import numpy as np
+import pytest
+
+from paper_1912_12786_amd import workloads as W
+from tests import parity as P
+from tests.test_gpu_parity import kind_kwargs, tiny_alpha_inputs, trace_kwargs
+
+pytestmark = pytest.mark.gpu
+MISS = 0xFFFFFFFF
+
+
+def announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1912_12786_amd import rtx
+    rtx.load_library()
+    return torch, rtx
+
+
+@pytest.mark.parametrize("max_leaf", [1, 2, 7])
+@pytest.mark.parametrize("kind", ["alpha", "procedural"])
+@pytest.mark.parametrize("query", ["closest", "any"])
+def test_tiny_leaf_sizes(env, oracle_lib, max_leaf, kind, query):
+    torch, rtx = env
+    wl = W.tiny()
+    ai = tiny_alpha_inputs(wl.n_tris)
+    announce(f"tiny max_leaf={max_leaf} kind={kind} query={query}")
+    sc = rtx.upload_scene(wl.vertices, ai["geom_ids"], ai["texcoords"], ai["textures"],
+                          max_leaf=max_leaf)
+    assert sc.info.max_leaf == max_leaf
+    out, cnt = rtx.trace(sc, torch.from_numpy(wl.rays).cuda(), kind, query=query, count=True,
+                         **trace_kwargs(kind))
+    torch.cuda.synchronize()
+    bvh = oracle_lib.build_bvh(wl.vertices, max_leaf=max_leaf)
+    B = oracle_lib.traverse(wl.vertices, bvh, wl.rays, kind, any_hit=(query == "any"),
+                            **kind_kwargs(kind, ai))
+    P.assert_counters_vs_b(cnt, B, f"tiny leaf {max_leaf}")
+    if query == "closest":
+        P.assert_exact_vs_b(P.hits_to_numpy(out), B, f"tiny leaf {max_leaf} {kind}")
+    else:
+        assert np.array_equal(P.occluders_to_numpy(out), B["prim"])
+
+
+@pytest.mark.parametrize("layout", ["f32", "q8"])
+def test_billboards_bench_config(env, oracle_lib, layout):
+    """The benchmark's launch (alpha, billboards, 1920x1080, leaves of at
+    most 2 triangles): all rays against oracle B with hits and counters, the
+    float64 definition on a subsample."""
+    torch, rtx = env
+    wl = W.billboards()
+    announce(f"billboards alpha max_leaf=2 layout={layout}")
+    sc = rtx.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures, max_leaf=2,
+                          layout=layout)
+    rays = torch.from_numpy(wl.rays).cuda()
+    hits, cnt = rtx.trace(sc, rays, "alpha", count=True, alpha_min=128)
+    plain = rtx.trace(sc, rays, "alpha", alpha_min=128)
+    torch.cuda.synchronize()
+    assert torch.equal(plain.view(torch.int32), hits.view(torch.int32))
+    okw = dict(geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures, alpha_min=128)
+    bvh = oracle_lib.build_bvh(wl.vertices, max_leaf=2)
+    B = oracle_lib.traverse(wl.vertices, bvh, wl.rays, "alpha", layout=layout, **okw)
+    g = P.hits_to_numpy(hits)
+    P.assert_exact_vs_b(g, B, f"billboards leaf 2 {layout}")
+    P.assert_counters_vs_b(cnt, B, f"billboards leaf 2 {layout}")
+    idx = W.subsample_indices(wl.n_rays, 1920, 1080, seed=W.seed_for(W.CFG_BILLBOARDS, 9),
+                              stride=16, n_random=2048)
+    A = oracle_lib.brute(wl.vertices, wl.rays, "alpha", ray_index=idx, **okw)
+    s = P.compare_vs_a(g, A, idx, f"billboards leaf 2 {layout}")
+    assert s["excluded"] < 0.05 * len(idx)
+    announce(f"billboards alpha any max_leaf=2 layout={layout}")
+    occ = rtx.trace(sc, rays, "alpha", query="any", alpha_min=128)
+    torch.cuda.synchronize()
+    Ba = oracle_lib.traverse(wl.vertices, bvh, wl.rays, "alpha", any_hit=True, layout=layout,
+                             count=False, **okw)
+    assert np.array_equal(P.occluders_to_numpy(occ), Ba["prim"])

@@ -491,3 +491,53 @@ def test_bvh_deterministic(oracle_lib):
     v = W.tiny().vertices
     a, b = oracle_lib.build_bvh(v), oracle_lib.build_bvh(v)
     assert a.nodes.tobytes() == b.nodes.tobytes() and np.array_equal(a.perm, b.perm)
+
+
+# ----------------------------------------------------------------------------
+# leaf size limit of the build
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("max_leaf", [1, 2, 3, 5, 7])
+def test_bvh_leaf_limit(oracle_lib, max_leaf):
+    """Leaves hold at most max_leaf triangles, inner nodes more; leaves
+    partition the triangles; and the traversal still answers the float64
+    definition (outside the exception set)."""
+    rng = np.random.default_rng(20 + max_leaf)
+    verts, rays = _random_scene(rng, 60, 300)
+    bvh = oracle_lib.build_bvh(verts, max_leaf=max_leaf)
+    nd = bvh.nodes
+    leaves = nd[nd["count"] > 0]
+    inner = nd[nd["count"] == 0]
+    assert leaves["count"].max() <= max_leaf
+    assert np.all(leaves["count"] >= 1)
+    covered = np.zeros(60, int)
+    for lf in leaves:
+        covered[lf["first"]:lf["first"] + lf["count"]] += 1
+    assert np.all(covered == 1)
+    # an inner node's subtree holds more than max_leaf triangles
+    def size(i):
+        return int(nd[i]["count"]) if nd[i]["count"] else size(int(nd[i]["left"])) + size(int(nd[i]["right"]))
+    assert all(size(i) > max_leaf for i in np.nonzero(nd["count"] == 0)[0])
+    assert len(inner) == len(leaves) - 1
+    for kind in ("default", "alpha"):
+        kw = _scene_params(rng, kind, 60)
+        A = oracle_lib.brute(verts, rays, kind, **kw)
+        B = oracle_lib.traverse(verts, bvh, rays, kind, **kw)
+        ok = A["flags"] == 0
+        assert np.array_equal(A["prim"][ok], B["prim"][ok])
+
+
+def test_root_leaf_counts_up_to_seven(oracle_lib):
+    """A scene of N <= max_leaf triangles is one root leaf: every ray that
+    hits the root box makes exactly 1 box test and N triangle tests (closest
+    hit, accept-all), every other ray 1 box test and none."""
+    rng = np.random.default_rng(8)
+    for n in (5, 6, 7):
+        verts, rays = _random_scene(rng, n, 400)
+        bvh = oracle_lib.build_bvh(verts, max_leaf=7)
+        assert bvh.n_nodes == 1 and bvh.nodes[0]["count"] == n
+        B = oracle_lib.traverse(verts, bvh, rays)
+        c = B["counters"]
+        assert np.all(c[:, 0] == 1)
+        assert set(np.unique(c[:, 1])) <= {0, n} and (c[:, 1] == n).sum() > 50
+    with pytest.raises(ValueError):
+        oracle_lib.build_bvh(verts, max_leaf=8)
