@@ -416,6 +416,10 @@ def main():
                     help="leaf size limit of the BVH build (1..7; the library's default is 4; "
                          "2 measured fastest on the billboards). Used by the billboards, tiny, "
                          "spheres and batched workloads")
+    ap.add_argument("--tune-build", action="store_true",
+                    help="let the autotuner choose leaf size (2, 3, 4), node layout and launch "
+                         "shape for the billboards/tiny/spheres workload (overrides --max-leaf, "
+                         "--layout and --shape)")
     ap.add_argument("--layout", default="f32", choices=["f32", "q8"],
                     help="inner-node layout: f32 = 64-B nodes with float32 boxes, q8 = 32-B "
                          "nodes with 8-bit boxes (rt_bvh_compress)")
@@ -471,6 +475,17 @@ def main():
                              layout=args.layout, max_leaf=args.max_leaf)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
+    tuned = None
+    if args.tune_build:
+        from paper_1912_12786_amd import autotune
+        del scene
+        scene, tuned = autotune.tune_scene(
+            f"bench-{wl.name}-{kind}", wl.vertices, torch.from_numpy(wl.rays).to(dev), kind,
+            geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures, cache_path=None,
+            device=dev)
+        args.max_leaf, args.layout = tuned["max_leaf"], tuned["layout"]
+        args.shape = ",".join(map(str, tuned["shape"]))
+        log(f"autotuner: leaves <= {args.max_leaf}, {args.layout} nodes, shape {args.shape}")
     log(f"workload {wl.name}: gen {t_gen:.2f} s, host BVH build + upload {t_build:.2f} s, "
         f"{scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}")
     rays = torch.from_numpy(wl.rays).to(dev)
@@ -606,6 +621,8 @@ def main():
     }
     if split:
         result["primary_bounce"] = split
+    if tuned:
+        result["autotuned_build"] = tuned
     print(json.dumps(result), flush=True)
 
 

@@ -1,10 +1,14 @@
-"""Launch-shape autotuner.
+"""Autotuner for launch shapes and scene builds.
 
-Times every launch shape compiled into librtx (threads per block, LDS ring
-slots, rays per chunk, persistent queue on/off) on a caller-supplied workload
-and selects the fastest with rt_set_launch_shape.  Results do not depend on
-the shape, only speed does.  Choices are cached per device and workload key
-in a JSON file.
+:func:`tune` times every launch shape compiled into librtx (threads per
+block, LDS ring slots, rays per chunk, persistent queue on/off) on a
+caller-supplied workload and selects the fastest with rt_set_launch_shape;
+results do not depend on the shape, only speed does.  :func:`tune_scene`
+also chooses how a scene is built: the BVH leaf size limit and the node
+layout (float32 or compressed 8-bit child boxes).  Those change the per-ray
+box and triangle counts, and among hits of exactly equal t possibly which one
+is reported, but not the closest or any-hit answer otherwise.  Choices are
+cached per device and key in a JSON file.
 """
 from __future__ import annotations
 
@@ -85,3 +89,66 @@ def tune(key: str, run, cache_path: str | None = DEFAULT_CACHE, steps: int = 10,
             os.replace(tmp, cache_path)
     rtx.rt_set_launch_shape(*best)
     return best, times
+
+
+def _load_cache(cache_path):
+    if cache_path and os.path.exists(cache_path):
+        try:
+            with open(cache_path) as f:
+                return json.load(f)
+        except (OSError, ValueError):
+            return {}
+    return {}
+
+
+def _store(cache_path, cache):
+    os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
+    tmp = cache_path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1)
+    os.replace(tmp, cache_path)
+
+
+def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_ids=None,
+               texcoords=None, textures=None, alpha_min: int = 128, checker_n: int = 8,
+               leaf_sizes=(2, 3, 4), layouts=("f32", "q8"), cache_path: str | None = DEFAULT_CACHE,
+               steps: int = 5, warmup: int = 1, retune: bool = False, device="cuda"):
+    """Chooses the BVH leaf size, node layout and launch shape that trace
+    ``rays`` (device float32 [N, 8], closest hit) fastest through the scene,
+    and returns ``(scene, choice)``: the scene built that way and
+    ``{"max_leaf", "layout", "shape", "ms"}``.  The launch shape is also
+    selected with rt_set_launch_shape.  A cached choice for this device and
+    key is reused unless ``retune``."""
+    import torch
+    dev_name = _device_name(torch)
+    cache = _load_cache(cache_path)
+    valid = {tuple(s) for s in rtx.rt_launch_shapes()}
+    entry = cache.get(dev_name, {}).get(key)
+    kw = dict(alpha_min=alpha_min, checker_n=checker_n)
+
+    def build(max_leaf, layout):
+        return rtx.upload_scene(vertices, geom_ids, texcoords, textures, device=device,
+                                layout=layout, max_leaf=max_leaf)
+
+    if entry and not retune and tuple(entry["shape"]) in valid:
+        choice = entry
+    else:
+        ws = rtx.Workspace(device)
+        out = torch.empty((rays.shape[0], 4), dtype=torch.float32, device=rays.device)
+        timings = {}
+        for max_leaf in leaf_sizes:
+            for layout in layouts:
+                scene = build(max_leaf, layout)
+                t = time_shapes(lambda: rtx.trace(scene, rays, intersector, out=out, workspace=ws, **kw),
+                                steps, warmup)
+                for shape, ms in t.items():
+                    timings[(int(max_leaf), layout, shape)] = ms
+                del scene
+        best = min(timings, key=timings.get)
+        choice = {"max_leaf": best[0], "layout": best[1], "shape": list(best[2]),
+                  "ms": {f"{k[0]}/{k[1]}/{','.join(map(str, k[2]))}": v for k, v in timings.items()}}
+        if cache_path:
+            cache.setdefault(dev_name, {})[key] = choice
+            _store(cache_path, cache)
+    rtx.rt_set_launch_shape(*choice["shape"])
+    return build(choice["max_leaf"], choice["layout"]), choice
