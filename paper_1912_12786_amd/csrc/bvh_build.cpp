@@ -21,7 +21,7 @@
 //   inner node, 64 B:  {lo0.x lo0.y lo0.z hi0.x} {hi0.y hi0.z lo1.x lo1.y}
 //                      {lo1.z hi1.x hi1.y hi1.z} {ref0 ref1 0 0}
 //     child c's box is (loc, hic); refc = (count << 29) | index with count = 0
-//     for an inner node (index = its node number) and 1..4 for a leaf (index =
+//     for an inner node (index = its node number) and 1..max_leaf for a leaf (index =
 //     its first triangle record).
 //   triangle record, 48 B: {v0.xyz, prim_id} {e1.xyz, geom_id} {e2.xyz, 0}
 //     with e1 = v1 - v0 and e2 = v2 - v0 rounded to float.
