@@ -115,3 +115,44 @@ def test_tune_scene_chooses_a_build_and_shape(env, oracle_lib, tmp_path):
         assert again == choice
     finally:
         rtx.rt_set_launch_shape(*rtx.rt_launch_shapes()[0])
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_builds_bit_exact(env, oracle_lib, seed):
+    """The random sweep's scenes and rays with a random leaf size limit and
+    node layout, every intersector and query, against oracle B built and
+    laid out the same way."""
+    from tests.test_gpu_random import random_case
+    from tests.test_oracle_pins import _scene_params
+    torch, rtx = env
+    rng, verts, rays = random_case(200 + seed)
+    max_leaf = int(rng.integers(1, 8))
+    layout = ["f32", "q8"][seed % 2]
+    kind = ["default", "alpha", "procedural"][seed % 3]
+    query = ["closest", "any", "multi"][(seed // 2) % 3]
+    k = int(rng.integers(1, 9))
+    kw = _scene_params(rng, kind, verts.shape[0])
+    announce(f"random build seed={seed} tris={verts.shape[0]} rays={rays.shape[0]} "
+             f"max_leaf={max_leaf} layout={layout} kind={kind} query={query} k={k}")
+    sc = rtx.upload_scene(verts, kw.get("geom_ids"), kw.get("texcoords"), kw.get("textures"),
+                          layout=layout, max_leaf=max_leaf)
+    tkw = {kk: kw[kk] for kk in ("alpha_min", "checker_n") if kk in kw}
+    res, cnt = rtx.trace(sc, torch.from_numpy(rays).cuda(), kind, query=query, k=k, count=True, **tkw)
+    torch.cuda.synchronize()
+    bvh = oracle_lib.build_bvh(verts, max_leaf=max_leaf)
+    B = oracle_lib.traverse(verts, bvh, rays, kind, any_hit=(query == "any"),
+                            multi_k=(k if query == "multi" else 0), layout=layout, **kw)
+    P.assert_counters_vs_b(cnt, B, f"random build {seed}")
+    if query == "closest":
+        P.assert_exact_vs_b(P.hits_to_numpy(res), B, f"random build {seed}")
+    elif query == "any":
+        assert np.array_equal(P.occluders_to_numpy(res), B["prim"])
+    else:
+        hits, nh = res
+        h = hits.cpu().numpy()
+        assert np.array_equal(nh.cpu().numpy().view(np.uint32), B["n_hits"])
+        assert np.array_equal(np.ascontiguousarray(h[..., 1]).view(np.uint32),
+                              np.asarray(B["prim"], np.uint32).reshape(-1, k))
+        for col, key in ((0, "t"), (2, "u"), (3, "v")):
+            assert np.array_equal(h[..., col].view(np.uint32),
+                                  np.ascontiguousarray(B[key], np.float32).reshape(-1, k).view(np.uint32))
