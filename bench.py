@@ -187,7 +187,8 @@ def bench_diff(args):
         rtx.rt_set_launch_shape(*(int(x) for x in args.shape.split(",")))
     dev = torch.device("cuda:0")
     wl = W.diff_scene()
-    scene = rtx.upload_scene(wl.triangles, wl.geom_ids, wl.texcoords, wl.textures, device=dev)
+    scene = rtx.upload_scene(wl.triangles, wl.geom_ids, wl.texcoords, wl.textures, device=dev,
+                             max_leaf=args.max_leaf)
     rays = torch.from_numpy(wl.rays).to(dev)
     n = wl.rays.shape[0]
     hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
@@ -221,7 +222,7 @@ def bench_diff(args):
         "value": round(n / ms_fb / 1e3, 2), "unit": "Mrays/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n_tris": int(wl.faces.shape[0]),
+        "config": {"workload": wl.name, "n_tris": int(wl.faces.shape[0]), "max_leaf": args.max_leaf,
                    "n_vertices": int(wl.vertices.shape[0]), "n_rays": n},
         "forward_mrays_s": round(n / ms_f / 1e3, 2),
         "forward_backward_mrays_s": round(n / ms_fb / 1e3, 2),
@@ -358,7 +359,7 @@ def bench_instanced(args):
     wl = W.instanced(2000)
     akw = W.instanced_alpha(wl) if kind == "alpha" else {}
     isc = rtx.InstancedScene(wl["blas"], wl["inst_blas"], wl["inst_m"], wl["world_lo"],
-                             wl["world_hi"], device=dev, **akw)
+                             wl["world_hi"], device=dev, max_leaf=args.max_leaf, **akw)
     wfo = wl["world_from_object"]
     flat = np.concatenate([np.einsum("ij,tkj->tki", wfo[q, :, :3],
                                      wl["blas"][b].astype(np.float64)) + wfo[q, :, 3]
@@ -366,9 +367,9 @@ def bench_instanced(args):
     if akw:
         fsc = rtx.upload_scene(flat, np.concatenate([akw["geom_ids"][b] for b in wl["inst_blas"]]),
                                np.concatenate([akw["texcoords"][b] for b in wl["inst_blas"]]),
-                               akw["textures"], device=dev)
+                               akw["textures"], device=dev, max_leaf=args.max_leaf)
     else:
-        fsc = rtx.upload_scene(flat, device=dev)
+        fsc = rtx.upload_scene(flat, device=dev, max_leaf=args.max_leaf)
     rays = torch.from_numpy(wl["rays"]).to(dev)
     n = rays.shape[0]
     out = torch.empty((n, 4), dtype=torch.float32, device=dev)
@@ -391,6 +392,7 @@ def bench_instanced(args):
         "value": round(n / ms_i / 1e3, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl["name"], "n_instances": 2000, "n_rays": n,
+                   "max_leaf": args.max_leaf,
                    "world_tris": int(flat.shape[0]), "intersector": kind},
         "instanced_mrays_s": round(n / ms_i / 1e3, 2), "flattened_mrays_s": round(n / ms_f / 1e3, 2),
         "ms": {"instanced": round(ms_i, 4), "flattened": round(ms_f, 4)},
@@ -412,10 +414,11 @@ def main():
     ap.add_argument("--ray-order", default="scanline", choices=["scanline", "tiled", "morton"],
                     help="tiled: primary rays reordered into 8x8 pixel tiles before upload "
                          "(hits come back in that order); morton: the same tiles in Z-order")
-    ap.add_argument("--max-leaf", type=int, default=2,
-                    help="leaf size limit of the BVH build (1..7; the library's default is 4; "
-                         "2 measured fastest on the billboards). Used by the billboards, tiny, "
-                         "spheres and batched workloads")
+    ap.add_argument("--max-leaf", type=int, default=None,
+                    help="leaf size limit of the BVH build (1..7; the library's default is 4). "
+                         "Default: 2 (measured fastest on the billboards, spheres, diff and "
+                         "batched scenes), 4 for instanced (its bottom-level meshes; 2 is 1 %% "
+                         "slower there). Not used by the dispatch ablation")
     ap.add_argument("--tune-build", action="store_true",
                     help="let the autotuner choose leaf size (2, 3, 4), node layout and launch "
                          "shape for the billboards/tiny/spheres workload (overrides --max-leaf, "
@@ -431,6 +434,8 @@ def main():
                     help="diff = differentiable hit on the perturbed icosphere (forward, "
                          "forward+backward and the plain kernel), reported on its own line")
     args = ap.parse_args()
+    if args.max_leaf is None:
+        args.max_leaf = 4 if args.workload == "instanced" else 2
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the traversal shards by rays with no exchange "
               "step, so multi-GPU runs are not part of this benchmark", file=sys.stderr)

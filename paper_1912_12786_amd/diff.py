@@ -17,20 +17,22 @@ from . import rtx
 
 class DifferentiableHit(torch.autograd.Function):
     """``tuv, prim, hit = DifferentiableHit.apply(rays, vertices, faces, geom_ids,
-    texcoords, textures, intersector, alpha_min, checker_n)``
+    texcoords, textures, intersector, alpha_min, checker_n, max_leaf)``
 
     rays float32 [N, 8] and vertices float32 [nv, 3] on the GPU (both may
     require grad); faces uint32/int32 [n, 3]; geom_ids, texcoords, textures as
-    numpy arrays (alpha intersector) or None.  Returns tuv float32 [N, 3]
+    numpy arrays (alpha intersector) or None; max_leaf: leaf size limit of the
+    forward's BVH build (1..7).  Returns tuv float32 [N, 3]
     (zeros for misses), prim int32 [N] (-1 for misses) and hit bool [N]."""
 
     @staticmethod
     def forward(ctx, rays, vertices, faces, geom_ids, texcoords, textures, intersector="default",
-                alpha_min=128, checker_n=8):
+                alpha_min=128, checker_n=8, max_leaf=4):
         v = vertices.detach()
         f = faces.detach().to(torch.int64)
         tris = v.cpu().numpy()[f.cpu().numpy()]
-        scene = rtx.upload_scene(tris, geom_ids, texcoords, textures, device=rays.device)
+        scene = rtx.upload_scene(tris, geom_ids, texcoords, textures, device=rays.device,
+                                 max_leaf=max_leaf)
         hits = rtx.trace(scene, rays.detach().contiguous(), intersector, alpha_min=alpha_min,
                          checker_n=checker_n)
         prim = hits[:, 1].view(torch.int32).clone()
@@ -54,7 +56,7 @@ class DifferentiableHit(torch.autograd.Function):
                             vertices.data_ptr(), vertices.shape[0], faces.data_ptr(),
                             faces.shape[0], grad_vertices.data_ptr(), grad_rays.data_ptr(),
                             stream)
-        return grad_rays, grad_vertices, None, None, None, None, None, None, None
+        return grad_rays, grad_vertices, None, None, None, None, None, None, None, None
 
 
 def hit_backward(rays, hits, grad_tuv, vertices, faces, grad_vertices=None, grad_rays=True):

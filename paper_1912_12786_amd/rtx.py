@@ -316,14 +316,14 @@ class InstancedScene:
     meshes ([n_tex, H, W] RGBA8 packed in uint32)."""
 
     def __init__(self, blas_vertices, inst_blas, inst_m, world_lo, world_hi, device="cuda", *,
-                 geom_ids=None, texcoords=None, textures=None):
+                 geom_ids=None, texcoords=None, textures=None, max_leaf: int = 4):
         torch = _torch()
         nb = len(blas_vertices)
         gids = geom_ids if geom_ids is not None else [None] * nb
         tcs = texcoords if texcoords is not None else [None] * nb
         if len(gids) != nb or len(tcs) != nb:
             raise ValueError("geom_ids/texcoords need one entry per bottom-level scene")
-        self.blas = [upload_scene(v, g, t, device=device)
+        self.blas = [upload_scene(v, g, t, device=device, max_leaf=max_leaf)
                      for v, g, t in zip(blas_vertices, gids, tcs)]
         nodes, tris, self.tlas_info = rt_tlas_build(inst_blas, inst_m, world_lo, world_hi)
         self.tlas_nodes = torch.from_numpy(nodes.copy()).to(device) if nodes.size else None
