@@ -103,10 +103,12 @@ rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipS
 }
 
 // Closest-hit query with a user intersector Isect (wrap it in
-// counting_intersector<> and pass counters for the per-ray counts).
+// counting_intersector<> and pass counters for the per-ray counts); with
+// Result = any_result (trace_custom_any) the any-hit query.
 //   scene      built by rt_bvh_build, device buffers (not validated here
 //              beyond null pointers, alignment and the stack bound)
-//   rays, out  device, n_rays rt_ray / rt_hit, 16-byte aligned
+//   rays, out  device, n_rays rt_ray / rt_hit (any-hit: uint32), 16-byte
+//              aligned
 //   counters   device rt_counters[n_rays] iff Isect counts, else NULL
 //   workspace  device, at least custom_workspace_bytes(scene, n_rays) bytes
 // Returns RT_OK, RT_ERR_INVALID_ARG / RT_ERR_MISALIGNED / RT_ERR_WORKSPACE
@@ -116,9 +118,9 @@ inline size_t custom_workspace_bytes(const rt_scene &scene, uint32_t n_rays)
     return workspace_for(scene.info, n_rays, kDefaultShape);
 }
 
-template <class Isect>
+template <class Isect, class Result = closest_result>
 rt_status trace_custom(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
-                       const typename Isect::params &p, rt_hit *out, rt_counters *counters,
+                       const typename Isect::params &p, void *out, rt_counters *counters,
                        void *workspace, size_t workspace_bytes, hipStream_t stream,
                        const char **err)
 {
@@ -151,10 +153,22 @@ rt_status trace_custom(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
     constexpr LaunchShape s = kDefaultShape;
     const kernel_args a = scene_args(*scene, rays, n_rays, out, counters, workspace, s);
     if (scene->info.layout == RT_LAYOUT_Q8)
-        return launch_one<Isect, closest_result, int(s.lds_stack), int(s.block), int(s.chunk),
+        return launch_one<Isect, Result, int(s.lds_stack), int(s.block), int(s.chunk),
                           s.queue != 0, false, RT_LAYOUT_Q8>(a, p, stream, err);
-    return launch_one<Isect, closest_result, int(s.lds_stack), int(s.block), int(s.chunk),
-                      s.queue != 0>(a, p, stream, err);
+    return launch_one<Isect, Result, int(s.lds_stack), int(s.block), int(s.chunk), s.queue != 0>(
+        a, p, stream, err);
+}
+
+// Any-hit query with a user intersector: occluders[i] = the first accepted
+// hit's triangle (input index) or RT_MISS (uint32, device, 4-byte aligned).
+template <class Isect>
+rt_status trace_custom_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                           const typename Isect::params &p, uint32_t *occluders,
+                           rt_counters *counters, void *workspace, size_t workspace_bytes,
+                           hipStream_t stream, const char **err)
+{
+    return trace_custom<Isect, any_result>(scene, rays, n_rays, p, occluders, counters, workspace,
+                                           workspace_bytes, stream, err);
 }
 
 }  // namespace rtx

@@ -114,6 +114,14 @@ def test_python_defined_checker_and_alpha_equal_builtins(env, workload):
         assert torch.equal(ah.view(torch.int32), rah.view(torch.int32)) and torch.equal(ac, rac)
         assert torch.equal(plain.view(torch.int32), ah.view(torch.int32))
         assert (c[:, 2] > c[:, 3]).any() and (ac[:, 2] > ac[:, 3]).any()   # both masks reject
+        # the any-hit query (shadow rays through the masks)
+        ao, aoc = alpha.trace(sc, rays, ap, query="any", count=True)
+        rao, raoc = rtx.trace(sc, rays, "alpha", query="any", alpha_min=128, count=True)
+        co = checker.trace(sc, rays, checker.params(n=8.0), query="any")
+        rco = rtx.trace(sc, rays, "procedural", query="any", checker_n=8)
+        torch.cuda.synchronize()
+        assert torch.equal(ao, rao) and torch.equal(aoc, raoc) and torch.equal(co, rco)
+        assert torch.equal(ao != -1, rah[:, 1].view(torch.int32) != -1)
 
 
 def test_python_defined_wireframe(env, oracle_lib):
