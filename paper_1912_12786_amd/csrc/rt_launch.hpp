@@ -91,7 +91,14 @@ rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipS
         const uint32_t resident = resident_blocks(kernel, kBlock, err);
         if (resident == 0) return RT_ERR_HIP;
         grid = grid < resident ? grid : resident;
-        hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, a.queue);
+        // A wave draws from the queue only after its static first chunk, and
+        // a drawn chunk is first_dynamic (= the grid's waves) + head + 8 k.
+        // When the grid has a wave for every chunk, no draw can name a chunk,
+        // whatever the heads hold, so the heads need no reset (one launch
+        // less for small ray counts).
+        const uint64_t n_chunks = (uint64_t(a.n_rays) + kChunk - 1) / kChunk;
+        if (uint64_t(grid) * (kBlock / 64) < n_chunks)
+            hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, a.queue);
     }
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, a, p);
     const hipError_t e = hipGetLastError();
