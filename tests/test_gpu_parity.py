@@ -322,7 +322,7 @@ def billboards_setup(torch_cuda, rtx_mod, oracle_lib):
     scene = rtx_mod.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures)
     bvh = oracle_lib.build_bvh(wl.vertices)
     idx = W.subsample_indices(wl.n_rays, 1920, 1080, seed=W.seed_for(W.CFG_BILLBOARDS, 9),
-                              stride=16, n_random=2048)
+                              stride=8, n_random=8192)
     return wl, scene, bvh, idx
 
 
@@ -379,7 +379,7 @@ def test_spheres_full_procedural_counts(torch_cuda, rtx_mod, oracle_lib, spheres
     P.assert_exact_vs_b(g, B, "spheres procedural")
     P.assert_counters_vs_b(cnt, B, "spheres procedural")
     idx = W.subsample_indices(wl.n_rays, None, None, seed=W.seed_for(W.CFG_SPHERES, 9),
-                              n_random=1024)
+                              n_random=8192)
     A = oracle_lib.brute(wl.vertices, wl.rays, "procedural", ray_index=idx, checker_n=8)
     s = P.compare_vs_a(g, A, idx, "spheres procedural")
     print("oracle A summary spheres", s, flush=True)
