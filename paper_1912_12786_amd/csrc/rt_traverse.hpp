@@ -646,9 +646,23 @@ __device__ __forceinline__ bool leave_inner_phase(uint32_t n_inner, uint32_t n_l
     return 16u * n_inner < kLeafBreak * (n_inner + n_leaf);
 }
 
+// Waves per SIMD a traversal kernel must fit.  The k <= 4 multi-hit list fits
+// 6 (80 VGPRs) without spilling, which measured +2 % (alpha) to +11 %
+// (accept-all) over the compiler's 5; the other kernels keep the compiler's
+// choice (6 waves spill the k <= 8 list: -15 %).
+template <class Result>
+struct min_waves_per_simd {
+    static constexpr int value = 1;
+};
+template <>
+struct min_waves_per_simd<multi_result<4>> {
+    static constexpr int value = 6;
+};
+
 template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue,
           bool kBatched = false, uint32_t kLayout = RT_LAYOUT_F32>
-__global__ __launch_bounds__(kBlock) void trace_kernel(kernel_args a, typename Isect::params p)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<Result>::value)))
+void trace_kernel(kernel_args a, typename Isect::params p)
 {
     static_assert(kBlock % 64 == 0 && kChunk % 32 == 0, "wave64 shapes");
     __shared__ uint2 ring[kSlots][kBlock];
