@@ -131,6 +131,10 @@ rt_status trace_custom(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
                        void *workspace, size_t workspace_bytes, hipStream_t stream,
                        const char **err)
 {
+    // the multi-hit policy needs the per-ray hit counts and k, which this
+    // entry point does not take
+    static_assert(std::is_same_v<Result, closest_result> || std::is_same_v<Result, any_result>,
+                  "trace_custom runs the closest-hit or the any-hit query");
     auto is16 = [](const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
     if (!scene) {
         *err = "scene is NULL";
