@@ -423,9 +423,11 @@ def main():
                     help="let the autotuner choose leaf size (2, 3, 4), node layout and launch "
                          "shape for the billboards/tiny/spheres workload (overrides --max-leaf, "
                          "--layout and --shape)")
-    ap.add_argument("--layout", default="f32", choices=["f32", "q8"],
+    ap.add_argument("--layout", default=None, choices=["f32", "q8"],
                     help="inner-node layout: f32 = 64-B nodes with float32 boxes, q8 = 32-B "
-                         "nodes with 8-bit boxes (rt_bvh_compress)")
+                         "nodes with 8-bit boxes (rt_bvh_compress). Default: q8 for the spheres "
+                         "and batched workloads (measured faster: BVHs beyond the caches), f32 "
+                         "otherwise")
     ap.add_argument("--query", default="closest", choices=["closest", "any", "multi"])
     ap.add_argument("--k", type=int, default=4, help="hits kept per ray by --query multi")
     ap.add_argument("--workload", default="billboards",
@@ -436,6 +438,8 @@ def main():
     args = ap.parse_args()
     if args.max_leaf is None:
         args.max_leaf = 4 if args.workload == "instanced" else 2
+    if args.layout is None:
+        args.layout = "q8" if args.workload in ("spheres", "batched") else "f32"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the traversal shards by rays with no exchange "
               "step, so multi-GPU runs are not part of this benchmark", file=sys.stderr)
