@@ -24,7 +24,7 @@ struct prim_mask_intersector : rtx::intersector_base {
     }
 };
 
-const char *g_error = "";
+thread_local const char *g_error = "";
 
 }  // namespace
 
