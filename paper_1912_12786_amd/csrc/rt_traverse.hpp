@@ -733,7 +733,12 @@ void trace_kernel(kernel_args a, typename Isect::params p)
             // inner phase: lanes at inner nodes step on while enough of them
             // remain; lanes already at a leaf wait (their ray's order is
             // unchanged -- a lane that leaves this phase at an inner node
-            // simply continues from it in the next round)
+            // simply continues from it in the next round).  The wave runs
+            // this phase at raised issue priority and its leaf phase at the
+            // lowest: on a SIMD shared by waves in both phases, node fetches
+            // then issue ahead of the longer dependent leaf chains (measured
+            // +2.6 % alpha billboards, +1.8 % spheres, default unchanged)
+            __builtin_amdgcn_s_setprio(1);
             for (;;) {
                 const bool in_inner = active && ref_count(cur) == 0;
                 const uint64_t mi = __ballot(in_inner);
@@ -743,6 +748,7 @@ void trace_kernel(kernel_args a, typename Isect::params p)
                     break;
                 if (in_inner && !inner_step<kLayout>(sc, r, isect, st, cur)) active = false;
             }
+            __builtin_amdgcn_s_setprio(0);
             if (active && ref_count(cur) != 0) {
                 if (leaf_step(sc, r, isect, cur, res))
                     active = false;
