@@ -24,12 +24,15 @@
 
 namespace rtx {
 
-// Resident blocks per CU x CUs of the current device for a kernel, cached per
-// device (queried once per kernel instantiation and device).
+// Resident blocks per CU x CUs of the current device for `kernel` launched
+// with `block` threads, cached per device in `cache`.  Each kernel
+// instantiation passes its own cache: instantiations share a function-pointer
+// type whenever their intersectors share a parameter type, yet differ in
+// registers and block size, hence in occupancy.
 template <class Kernel>
-uint32_t resident_blocks(Kernel kernel, uint32_t block, const char **err)
+uint32_t resident_blocks(Kernel kernel, uint32_t block, std::atomic<uint32_t> (&cache)[64],
+                         const char **err)
 {
-    static std::atomic<uint32_t> cache[64] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
         *err = "hipGetDevice failed";
@@ -88,7 +91,8 @@ rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipS
     // trimmed to the waves that can be resident at once
     uint32_t grid = uint32_t(launch_threads(a.n_rays, sh) / kBlock);
     if constexpr (kQueue) {
-        const uint32_t resident = resident_blocks(kernel, kBlock, err);
+        static std::atomic<uint32_t> occupancy_cache[64] = {};  // this instantiation's
+        const uint32_t resident = resident_blocks(kernel, kBlock, occupancy_cache, err);
         if (resident == 0) return RT_ERR_HIP;
         grid = grid < resident ? grid : resident;
         // A wave draws from the queue only after its static first chunk, and
