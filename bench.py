@@ -507,6 +507,19 @@ def main():
         hits = torch.empty((wl.n_rays, args.k, 4), dtype=torch.float32, device=dev)
     ws = rtx.Workspace(dev)
     stream = torch.cuda.current_stream(dev)
+    shape_ms = None
+    if query == "multi" and not args.shape:
+        # the k-hit lists favour another launch shape than the closest hit
+        # (lanes refilled from the queue lose more coherence over their longer
+        # traversals), so the autotuner picks it here, untimed
+        from paper_1912_12786_amd import autotune
+        best, shape_ms = autotune.tune(
+            f"bench-{wl.name}-{kind}-multi{args.k}",
+            lambda: rtx.trace(scene, rays, kind, query="multi", k=args.k, alpha_min=128, out=hits,
+                              workspace=ws),
+            cache_path=None, steps=10, warmup=2)
+        args.shape = ",".join(map(str, best))
+        log(f"autotuner: multi-hit launch shape {args.shape}")
 
     def time_launches(r, o):
         """(per-launch ms from HIP events on the launch stream, wall s) of
@@ -577,7 +590,7 @@ def main():
     mean_c = counters.mean(axis=0)
     result = {
         "metric": ("Mrays/s closest-hit w/ alpha-mask intersector at 1080p; HBM GB/s % of peak"
-                   if args.workload == "billboards" else
+                   if args.workload == "billboards" and kind == "alpha" and query == "closest" else
                    f"Mrays/s {query} hit, {kind} intersector, {wl.name}; HBM GB/s % of peak"),
         "value": round(mrays, 2),
         "unit": "Mrays/s",
@@ -632,6 +645,8 @@ def main():
         result["primary_bounce"] = split
     if tuned:
         result["autotuned_build"] = tuned
+    if shape_ms:
+        result["autotuned_shape_ms"] = shape_ms
     print(json.dumps(result), flush=True)
 
 
