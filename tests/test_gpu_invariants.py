@@ -7,7 +7,9 @@ benchmark's size (billboards, 200k triangles, 1920x1080, alpha >= 128):
 * filtering never brings a hit nearer: t(alpha) >= t(accept-all) per ray;
 * ray order: the same rays in 8x8 tiles or Z-order give the same per-ray
   hits and counters;
-* repeated launches give identical hits and counters."""
+* repeated launches give identical hits and counters;
+* every compiled launch shape gives the same bits (closest with counters,
+  4 nearest hits)."""
 import numpy as np
 import pytest
 
@@ -97,3 +99,28 @@ def test_repeated_launches_identical(setup):
         h, c = rtx.trace(scene, rays, "alpha", alpha_min=128, count=True)
         torch.cuda.synchronize()
         assert torch.equal(h.view(torch.int32), ref_h.view(torch.int32)) and torch.equal(c, ref_c)
+
+
+def test_all_launch_shapes_identical_full_size(setup):
+    """Every compiled launch shape, in one process and in turn, gives the
+    same bits for the closest hit with its counters and for the 4 nearest
+    hits: the per-ray visit order does not depend on the shape, the grid or
+    how many waves are resident."""
+    torch, rtx, wl, scene = setup
+    rays = torch.from_numpy(wl.rays).cuda()
+    shapes = rtx.rt_launch_shapes()
+    ref = None
+    try:
+        for shape in shapes:
+            announce(f"billboards alpha closest+count and multi k=4, shape={shape}")
+            rtx.rt_set_launch_shape(*shape)
+            h, c = rtx.trace(scene, rays, "alpha", alpha_min=128, count=True)
+            m, n = rtx.trace(scene, rays, "alpha", query="multi", k=4, alpha_min=128)
+            torch.cuda.synchronize()
+            got = (h.view(torch.int32), c, m.view(torch.int32), n)
+            if ref is None:
+                ref = got
+            else:
+                assert all(torch.equal(x, y) for x, y in zip(got, ref)), shape
+    finally:
+        rtx.rt_set_launch_shape(*shapes[0])
