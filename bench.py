@@ -7,10 +7,12 @@ threshold 0.5 (alpha byte >= 128).  One step = one rt_trace_closest launch
 over all 2,073,600 rays (ray setup, traversal, triangle tests, alpha lookups,
 hit output), inputs and BVH resident in device memory.
 
-Prints ONE JSON line: Mrays/s, the algorithmic-bandwidth roofline of the
-traversal kernel (bytes the method must read and write per ray, from exact
-per-ray counts of a separate counting launch), and the CPU oracle timed on
-this host's cores on the same workload.
+Prints ONE JSON line: Mrays/s, the roofline of the traversal kernel (HBM
+bytes per launch measured by rocprofv3 over the launch time measured here,
+against the 8 TB/s peak; the texture-addresser busy fraction, the roof the
+counters show binding; and the bytes the method touches per ray, from exact
+per-ray counts of a separate counting launch, as a request rate), and the CPU
+oracle timed on this host's cores on the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
     python bench.py --copy-calibration   # plain copy kernel for counter scaling
@@ -31,13 +33,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_trace_alpha_billboards.json")
+N_CUS, CLOCK_GHZ = 256, 2.4    # MI355X compute units and peak engine clock
+# one texture addresser per CU, busy at most every cycle
+PEAK_TA_GCYCLES = N_CUS * CLOCK_GHZ
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1912_12786_amd", "csrc", f)
-                  for f in ("rt_traverse.hpp", "trace_kernels.hip")]
+                  for f in ("rt_traverse.hpp", "trace_kernels.hip", "rt_launch.hpp",
+                            "rt_batch_layout.hpp")]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def emit(line: dict):
+    """Prints one JSON result line, tagged with the kernel sources it ran."""
+    line.setdefault("kernel_source_sha", kernel_source_sha())
+    print(json.dumps(line), flush=True)
 
 
 def kernel_source_sha() -> str:
@@ -46,6 +58,61 @@ def kernel_source_sha() -> str:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def find_counters(sha, workload, kind, query, layout, max_leaf, shape, ray_order):
+    """The rocprofv3 counter record (``profiles/counters_*.json``) taken on
+    exactly this kernel source and configuration, or None."""
+    if not os.path.isdir(PROFILES):
+        return None
+    for name in sorted(os.listdir(PROFILES)):
+        if not (name.startswith("counters_") and name.endswith(".json")):
+            continue
+        with open(os.path.join(PROFILES, name)) as f:
+            rec = json.load(f)
+        cfg = rec.get("config", {})
+        if (rec.get("kernel_source_sha") == sha and cfg.get("workload") == workload
+                and cfg.get("intersector") == kind and cfg.get("query") == query
+                and cfg.get("layout") == layout and cfg.get("max_leaf") == max_leaf
+                and cfg.get("launch_shape") == list(shape)
+                and cfg.get("ray_order", "scanline") == ray_order):
+            rec["file"] = os.path.join("profiles", name)
+            return rec
+    return None
+
+
+def roofline(kernel_ms: float, alg_bytes: int, rec) -> dict:
+    """The roofline object of the dominant kernel.
+
+    ``achieved``/``frac``: HBM bytes per launch measured by rocprofv3
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading of the same
+    counters; ``traffic``) over the mean launch time measured here, against
+    the 8 TB/s HBM peak.  They are null when no counter record matches the
+    current kernel source and configuration.  ``issue``: the texture
+    addresser's busy fraction from the same record (every vector memory
+    instruction passes through it), the roof the counters show binding.
+    ``algorithmic_gbs``: the bytes the method touches per launch (per-ray
+    counts x record sizes, cache hits included) over the same time; it is a
+    request rate, not DRAM traffic, and may exceed the HBM peak."""
+    sec = kernel_ms * 1e-3
+    out = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
+           "traffic": None}
+    if rec is not None:
+        traffic = int(rec["traffic_bytes_per_launch"])
+        gbs = traffic / sec / 1e9
+        out.update(achieved=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4), traffic=traffic)
+        if rec.get("ta_busy_frac") is not None:
+            ta = float(rec["ta_busy_frac"])
+            out["limiter"] = rec.get("limiter", "vmem_issue")
+            out["issue"] = {"bound": "vmem_issue", "unit": "G TA-cycles/s",
+                            "achieved": round(ta * PEAK_TA_GCYCLES, 1), "peak": PEAK_TA_GCYCLES,
+                            "frac": round(ta, 4),
+                            "vmem_rd_wave_instr_per_launch": rec.get("vmem_rd_wave_instr"),
+                            "valu_lane_utilisation": rec.get("valu_lane_utilisation")}
+        out["counters_file"] = rec["file"]
+    out["algorithmic_gbs"] = round(alg_bytes / sec / 1e9, 1)
+    out["algorithmic_frac_of_hbm_peak"] = round(alg_bytes / sec / 1e9 / PEAK_HBM_GBS, 4)
+    return out
 
 
 def bytes_per_ray(counters: np.ndarray, kind: str, node_bytes: int = 64) -> np.ndarray:
@@ -69,8 +136,8 @@ def copy_calibration():
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4,
-                      "launches": 3}), flush=True)
+    emit({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4,
+                      "launches": 3})
 
 
 def _morton2(x: np.ndarray, y: np.ndarray, bits: int) -> np.ndarray:
@@ -91,6 +158,11 @@ def tile_order(wl, tile: int = 8, morton: bool = False) -> np.ndarray:
     key = ((y // tile) * ((w + tile - 1) // tile) + x // tile) * tile * tile + inner
     order = np.argsort(key, kind="stable")
     return np.concatenate([order, np.arange(w * h, wl.n_rays)])
+
+
+def parse_shape(text):
+    """--shape BLOCK,LDS_SLOTS,CHUNK,QUEUE -> tuple, or None for the default."""
+    return tuple(int(x) for x in text.split(",")) if text else None
 
 
 def cpu_model() -> str:
@@ -183,8 +255,7 @@ def bench_diff(args):
     import torch
     from paper_1912_12786_amd import diff, rtx
     from paper_1912_12786_amd import workloads as W
-    if args.shape:
-        rtx.rt_set_launch_shape(*(int(x) for x in args.shape.split(",")))
+    shape = parse_shape(args.shape)
     dev = torch.device("cuda:0")
     wl = W.diff_scene()
     scene = rtx.upload_scene(wl.triangles, wl.geom_ids, wl.texcoords, wl.textures, device=dev,
@@ -201,7 +272,7 @@ def bench_diff(args):
     stream = torch.cuda.current_stream(dev)
 
     def fwd():
-        rtx.trace(scene, rays, "alpha", alpha_min=128, out=hits, workspace=ws)
+        rtx.trace(scene, rays, "alpha", alpha_min=128, out=hits, workspace=ws, shape=shape)
 
     def fwd_bwd():
         fwd()
@@ -211,12 +282,12 @@ def bench_diff(args):
                             stream.cuda_stream)
 
     def plain():
-        rtx.trace(scene, rays, "default", out=hits, workspace=ws)
+        rtx.trace(scene, rays, "default", out=hits, workspace=ws, shape=shape)
 
     ms_f = timed(fwd, args.steps, args.warmup, stream)
     ms_fb = timed(fwd_bwd, args.steps, args.warmup, stream)
     ms_p = timed(plain, args.steps, args.warmup, stream)
-    print(json.dumps({
+    emit({
         "metric": "Mrays/s differentiable closest hit (alpha mask): forward, forward+backward, "
                   "plain default-intersector kernel on the same scene",
         "value": round(n / ms_fb / 1e3, 2), "unit": "Mrays/s", "n_gpus": 1,
@@ -229,7 +300,7 @@ def bench_diff(args):
         "plain_default_mrays_s": round(n / ms_p / 1e3, 2),
         "ms": {"forward": round(ms_f, 4), "forward_backward": round(ms_fb, 4),
                "plain_default": round(ms_p, 4)},
-    }), flush=True)
+    })
     del diff
 
 
@@ -260,8 +331,10 @@ def bench_batched(args):
     outs = [out[offs[i]:offs[i + 1]] for i in range(len(scenes))]
     stream = torch.cuda.current_stream(dev)
 
-    def batched():
-        batch.trace(rays, out=out, workspace=ws)
+    best = None
+
+    def batched(shape=None):
+        batch.trace(rays, out=out, workspace=ws, shape=shape or best)
 
     def separate():
         for sc, r, o in zip(sc_list, views, outs):
@@ -271,7 +344,7 @@ def bench_batched(args):
     best, tune_ms = autotune.tune("batched-64-scenes-default", batched, cache_path=None,
                                   steps=3, warmup=1)
     # grow the workspace to the largest need before any capture
-    ws.get(max(rtx.rt_trace_batch_workspace_bytes(batch.info),
+    ws.get(max(rtx.rt_trace_batch_workspace_bytes(batch.info, rtx.shape_flag(best)),
                max(rtx.rt_trace_workspace_bytes(sc.view, c) for sc, c in zip(sc_list, counts))))
 
     def graph_of(fn):
@@ -294,7 +367,7 @@ def bench_batched(args):
         "separate_eager": timed(separate, args.steps, args.warmup, stream),
         "separate_graph": timed(g_separate.replay, args.steps, args.warmup, stream),
     }
-    print(json.dumps({
+    emit({
         "metric": "Mrays/s closest hit over a batch of 64 scenes (default intersector): one "
                   "persistent launch vs 64 per-scene launches",
         "value": round(n / ms["batched_graph"] / 1e3, 2), "unit": "Mrays/s", "n_gpus": 1,
@@ -307,7 +380,7 @@ def bench_batched(args):
         "mrays_s": {k: round(n / v / 1e3, 2) for k, v in ms.items()},
         "ms": {k: round(v, 4) for k, v in ms.items()},
         "autotune_ms": tune_ms,
-    }), flush=True)
+    })
 
 
 def bench_dispatch(args):
@@ -338,13 +411,13 @@ def bench_dispatch(args):
                                      out.data_ptr(), None, wptr, wb, stream.cuda_stream)
             ms = timed(fn, args.steps, args.warmup, stream)
             res[f"{kind}/{name}"] = {"ms": round(ms, 4), "mrays_s": round(n / ms / 1e3, 2)}
-    print(json.dumps({
+    emit({
         "metric": "Mrays/s closest hit, compile-time intersector vs run-time dispatch "
                   "(switch, indirect call) at 1080p billboards",
         "value": res["alpha/compile_time"]["mrays_s"], "unit": "Mrays/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
         "data": "synthetic", "config": {"workload": wl.name, "n_rays": n},
-        "results": res}), flush=True)
+        "results": res})
 
 
 def bench_instanced(args):
@@ -387,7 +460,7 @@ def bench_instanced(args):
     if akw:  # texture coordinates (the shared textures are the same on both sides)
         bytes_i += sum(int(b.texcoords.numel()) * 4 for b in isc.blas)
         bytes_f += int(fsc.texcoords.numel()) * 4
-    print(json.dumps({
+    emit({
         "metric": f"Mrays/s closest hit ({kind}), instanced two-level BVH vs the flattened scene",
         "value": round(n / ms_i / 1e3, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
@@ -396,7 +469,7 @@ def bench_instanced(args):
                    "world_tris": int(flat.shape[0]), "intersector": kind},
         "instanced_mrays_s": round(n / ms_i / 1e3, 2), "flattened_mrays_s": round(n / ms_f / 1e3, 2),
         "ms": {"instanced": round(ms_i, 4), "flattened": round(ms_f, 4)},
-        "scene_bytes": {"instanced": bytes_i, "flattened": bytes_f}}), flush=True)
+        "scene_bytes": {"instanced": bytes_i, "flattened": bytes_f}})
 
 
 def main():
@@ -464,8 +537,6 @@ def main():
     from paper_1912_12786_amd import rtx
     from paper_1912_12786_amd import workloads as W
 
-    if args.shape:
-        rtx.rt_set_launch_shape(*(int(x) for x in args.shape.split(",")))
     kind = args.intersector or {"billboards": "alpha", "tiny": "default",
                                 "spheres": "procedural"}[args.workload]
     if kind == "alpha" and args.workload != "billboards":
@@ -515,17 +586,20 @@ def main():
         from paper_1912_12786_amd import autotune
         best, shape_ms = autotune.tune(
             f"bench-{wl.name}-{kind}-multi{args.k}",
-            lambda: rtx.trace(scene, rays, kind, query="multi", k=args.k, alpha_min=128, out=hits,
-                              workspace=ws),
+            lambda sh: rtx.trace(scene, rays, kind, query="multi", k=args.k, alpha_min=128, out=hits,
+                                 workspace=ws, shape=sh),
             cache_path=None, steps=10, warmup=2)
         args.shape = ",".join(map(str, best))
         log(f"autotuner: multi-hit launch shape {args.shape}")
+
+    shape = parse_shape(args.shape)
 
     def time_launches(r, o):
         """(per-launch ms from HIP events on the launch stream, wall s) of
         args.steps launches over rays r into o, after args.warmup."""
         def step():
-            rtx.trace(scene, r, kind, query=query, k=args.k, alpha_min=128, out=o, workspace=ws)
+            rtx.trace(scene, r, kind, query=query, k=args.k, alpha_min=128, out=o, workspace=ws,
+                      shape=shape)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -556,7 +630,7 @@ def main():
 
     # exact per-ray counts from a separate (untimed) counting launch
     _, cnt = rtx.trace(scene, rays, kind, query=query, k=args.k, alpha_min=128, count=True,
-                       workspace=ws)
+                       workspace=ws, shape=shape)
     torch.cuda.synchronize()
     counters = cnt.cpu().numpy().view(np.uint32)
     node_bytes = 32 if args.layout == "q8" else 64
@@ -567,18 +641,10 @@ def main():
     elif query == "multi":
         alg_bytes += (16 * (args.k - 1) + 4) * wl.n_rays
     kernel_ms = float(per_launch_ms.mean())
-    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
 
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tf = json.load(f)
-        if tf.get("kernel_source_sha") == kernel_source_sha() and kind == "alpha" \
-                and query == "closest" and args.ray_order == "scanline" \
-                and tf.get("layout", "f32") == args.layout \
-                and tf.get("max_leaf", 4) == args.max_leaf \
-                and list(rtx.rt_launch_shapes()[0]) == tf.get("launch_shape") and not args.shape:
-            traffic = tf.get("traffic_bytes_per_launch")
+    counters_rec = find_counters(kernel_source_sha(), wl.name, kind, query, args.layout,
+                                 args.max_leaf, list(shape or rtx.rt_launch_shapes()[0]),
+                                 args.ray_order)
 
     cpu = None
     if not args.no_cpu_baseline and query == "closest":
@@ -621,13 +687,7 @@ def main():
             "launch_shape": ([int(x) for x in args.shape.split(",")] if args.shape
                              else list(rtx.rt_launch_shapes()[0])),
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": traffic,
+        "roofline": roofline(kernel_ms, alg_bytes, counters_rec) | {
             "kernel": f"trace_kernel<{kind}_intersector, {query}>",
             "kernel_ms_mean": round(kernel_ms, 4),
             "kernel_ms_median": round(float(np.median(per_launch_ms)), 4),
@@ -647,7 +707,7 @@ def main():
         result["autotuned_build"] = tuned
     if shape_ms:
         result["autotuned_shape_ms"] = shape_ms
-    print(json.dumps(result), flush=True)
+    emit(result)
 
 
 if __name__ == "__main__":

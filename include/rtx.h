@@ -97,6 +97,16 @@ typedef enum rt_isect_kind {
 #define RT_FLAG_RUNTIME_SWITCH 0x2u
 #define RT_FLAG_RUNTIME_CALL 0x4u
 
+/* Launch shape of one call: bits 8..15 of flags hold an index into the table
+ * that rt_launch_shapes lists (0, the default, when the field is clear).  The
+ * shape is chosen per call, so calls on different threads or streams may use
+ * different shapes; the workspace queries take the same flags, because the
+ * workspace size depends on the shape.  Results never depend on the shape.
+ * An index past the table is RT_ERR_UNSUPPORTED. */
+#define RT_FLAG_SHAPE_SHIFT 8u
+#define RT_FLAG_SHAPE_MASK 0xFF00u
+#define RT_FLAG_SHAPE(index) ((((uint32_t)(index)) << RT_FLAG_SHAPE_SHIFT) & RT_FLAG_SHAPE_MASK)
+
 /* Alpha-mask intersector (Listing 5).  For a candidate (prim, u, v):
  *   (s, t) = (1-u-v) tc[prim][0] + u tc[prim][1] + v tc[prim][2],
  *   texel  = nearest texel (clamp to edge) of texture geom_id(prim),
@@ -399,7 +409,8 @@ rt_status rt_hit_backward(const rt_ray *rays, const rt_hit *hits, const float *g
                           const uint32_t *faces, uint32_t n_tris, float *grad_vertices,
                           float *grad_rays, void *stream);
 
-/* Launch shapes compiled into the library:
+/* Launch shapes compiled into the library (the index a call selects with
+ * RT_FLAG_SHAPE is the position in this list):
  *   block      threads per block;
  *   lds_stack  LDS ring slots per lane for the top of the traversal stack
  *              (lds_stack - 1 entries stay on chip, older ones move to the
@@ -416,13 +427,6 @@ rt_status rt_hit_backward(const rt_ray *rays, const rt_hit *hits, const float *g
  * RT_ERR_UNSUPPORTED), and not with the run-time dispatch flags. */
 uint32_t rt_launch_shapes(uint32_t *blocks, uint32_t *lds_stacks, uint32_t *chunks,
                           uint32_t *queues, uint32_t cap);
-
-/* Selects the launch shape of later trace calls in this process (a tuning
- * hook; not synchronised with trace calls running on other threads).
- * Results never depend on the shape; speed and the workspace size do, so
- * query rt_trace_workspace_bytes again after changing it.
- * RT_ERR_UNSUPPORTED if the shape is not compiled in. */
-rt_status rt_set_launch_shape(uint32_t block, uint32_t lds_stack, uint32_t chunk, uint32_t queue);
 
 /* Static description of a status code. */
 const char *rt_status_string(rt_status status);

@@ -2,8 +2,9 @@
 
 :func:`tune` times every launch shape compiled into librtx (threads per
 block, LDS ring slots, rays per chunk, persistent queue on/off) on a
-caller-supplied workload and selects the fastest with rt_set_launch_shape;
-results do not depend on the shape, only speed does.  :func:`tune_scene`
+caller-supplied workload and returns the fastest; the caller passes it to its
+trace calls (``shape=``), which select it per call.  Results do not depend on
+the shape, only speed does.  :func:`tune_scene`
 also chooses how a scene is built: the BVH leaf size limit and the node
 layout (float32 or compressed 8-bit child boxes).  Those change the per-ray
 box and triangle counts, and among hits of exactly equal t possibly which one
@@ -26,43 +27,41 @@ def _device_name(torch) -> str:
 
 
 def time_shapes(run, steps: int = 10, warmup: int = 2, shapes=None) -> dict:
-    """Mean milliseconds per call of ``run()`` for each launch shape that the
-    traced scenes can use (compressed-node scenes run with the default shape
-    only: the library refuses the others before launching anything)."""
+    """Mean milliseconds per call of ``run(shape)`` for each launch shape that
+    the traced scenes can use (compressed-node scenes run with the default
+    shape only: the library refuses the others before launching anything).
+    ``run`` receives the shape tuple and passes it to its trace calls."""
     import torch
     shapes = shapes or rtx.rt_launch_shapes()
-    saved = rtx.rt_launch_shapes()[0]
     times = {}
     stream = torch.cuda.current_stream()
-    try:
-        for sh in shapes:
-            rtx.rt_set_launch_shape(*sh)
-            try:
-                run()
-            except rtx.RtxError as e:
-                if e.status != rtx.RT_ERR_UNSUPPORTED:
-                    raise
-                continue
-            for _ in range(warmup):
-                run()
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(steps):
-                run()
-            b.record(stream)
-            torch.cuda.synchronize()
-            times[tuple(sh)] = a.elapsed_time(b) / steps
-    finally:
-        rtx.rt_set_launch_shape(*saved)
+    for sh in shapes:
+        sh = tuple(sh)
+        try:
+            run(sh)
+        except rtx.RtxError as e:
+            if e.status != rtx.RT_ERR_UNSUPPORTED:
+                raise
+            continue
+        for _ in range(warmup):
+            run(sh)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            run(sh)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times[sh] = a.elapsed_time(b) / steps
     return times
 
 
 def tune(key: str, run, cache_path: str | None = DEFAULT_CACHE, steps: int = 10,
          warmup: int = 2, retune: bool = False):
-    """Selects (and returns) the fastest shape for ``run`` under ``key``,
-    reusing a cached choice for this device unless ``retune``."""
+    """Returns ``(shape, times)``: the fastest shape for ``run(shape)`` under
+    ``key``, reusing a cached choice for this device unless ``retune``.
+    Nothing global changes: the caller passes the shape to its trace calls."""
     import torch
     dev = _device_name(torch)
     cache = {}
@@ -87,7 +86,6 @@ def tune(key: str, run, cache_path: str | None = DEFAULT_CACHE, steps: int = 10,
             with open(tmp, "w") as f:
                 json.dump(cache, f, indent=1)
             os.replace(tmp, cache_path)
-    rtx.rt_set_launch_shape(*best)
     return best, times
 
 
@@ -116,9 +114,9 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
     """Chooses the BVH leaf size, node layout and launch shape that trace
     ``rays`` (device float32 [N, 8], closest hit) fastest through the scene,
     and returns ``(scene, choice)``: the scene built that way and
-    ``{"max_leaf", "layout", "shape", "ms"}``.  The launch shape is also
-    selected with rt_set_launch_shape.  A cached choice for this device and
-    key is reused unless ``retune``."""
+    ``{"max_leaf", "layout", "shape", "ms"}``; pass ``choice["shape"]`` to the
+    trace calls.  A cached choice for this device and key is reused unless
+    ``retune``."""
     import torch
     dev_name = _device_name(torch)
     cache = _load_cache(cache_path)
@@ -139,8 +137,8 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
         for max_leaf in leaf_sizes:
             for layout in layouts:
                 scene = build(max_leaf, layout)
-                t = time_shapes(lambda: rtx.trace(scene, rays, intersector, out=out, workspace=ws, **kw),
-                                steps, warmup)
+                t = time_shapes(lambda sh: rtx.trace(scene, rays, intersector, out=out, workspace=ws,
+                                                     shape=sh, **kw), steps, warmup)
                 for shape, ms in t.items():
                     timings[(int(max_leaf), layout, shape)] = ms
                 del scene
@@ -150,5 +148,4 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
         if cache_path:
             cache.setdefault(dev_name, {})[key] = choice
             _store(cache_path, cache)
-    rtx.rt_set_launch_shape(*choice["shape"])
     return build(choice["max_leaf"], choice["layout"]), choice

@@ -15,12 +15,26 @@ using namespace rtx;
 namespace {
 
 thread_local std::string g_last_error;
-std::atomic<uint32_t> g_shape_index{0};
+
+// Flag bits every single-scene trace call knows: the intersector options and
+// the launch-shape field.
+constexpr uint32_t kKnownFlags = RT_FLAG_COUNT | RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL |
+                                 RT_FLAG_SHAPE_MASK;
 
 rt_status fail(rt_status s, const std::string &msg)
 {
     g_last_error = msg;
     return s;
+}
+
+// The launch shape a call's flags select (RT_FLAG_SHAPE); false if the index
+// names no compiled shape.
+bool shape_of(uint32_t flags, LaunchShape &out)
+{
+    const uint32_t i = (flags & RT_FLAG_SHAPE_MASK) >> RT_FLAG_SHAPE_SHIFT;
+    if (i >= kNumShapes) return false;
+    out = kShapes[i];
+    return true;
 }
 
 bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
@@ -104,8 +118,9 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     g_last_error.clear();
     rt_status st = check_scene(scene);
     if (st != RT_OK) return st;
-    if (flags & ~(RT_FLAG_COUNT | RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL))
-        return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    if (flags & ~kKnownFlags) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    LaunchShape shape;
+    if (!shape_of(flags, shape)) return fail(RT_ERR_UNSUPPORTED, "launch shape index not compiled in");
     const uint32_t runtime = flags & (RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL);
     if (runtime) {
         if (runtime == (RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL))
@@ -138,7 +153,6 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     const bool count = (flags & RT_FLAG_COUNT) != 0;
     if (count && !counters) return fail(RT_ERR_INVALID_ARG, "RT_FLAG_COUNT needs a counters array");
     if (count && !aligned(counters, 16)) return fail(RT_ERR_MISALIGNED, "counters not 16-byte aligned");
-    const LaunchShape shape = kShapes[g_shape_index.load(std::memory_order_relaxed)];
     const size_t need = workspace_for(scene->info, n_rays, shape);
     if (need > 0) {
         if (!workspace || workspace_bytes < need)
@@ -239,10 +253,11 @@ rt_status rt_trace_workspace_bytes(const rt_scene *scene, uint32_t n_rays, uint3
     rt_status st = check_scene(scene);
     if (st != RT_OK) return st;
     // the runtime-dispatch flags select kernels with the same workspace
-    if (flags & ~(RT_FLAG_COUNT | RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL))
-        return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    if (flags & ~kKnownFlags) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    LaunchShape shape;
+    if (!shape_of(flags, shape)) return fail(RT_ERR_UNSUPPORTED, "launch shape index not compiled in");
     if (n_rays > RT_MAX_RAYS) return fail(RT_ERR_INVALID_ARG, "more than 2^31 rays in one call");
-    *bytes = workspace_for(scene->info, n_rays, kShapes[g_shape_index.load()]);
+    *bytes = workspace_for(scene->info, n_rays, shape);
     return RT_OK;
 }
 
@@ -338,10 +353,12 @@ rt_status rt_trace_batch_workspace_bytes(const rt_batch_info *info, uint32_t fla
 {
     g_last_error.clear();
     if (!info || !bytes) return fail(RT_ERR_INVALID_ARG, "info/bytes are NULL");
-    if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    if (flags & ~(RT_FLAG_COUNT | RT_FLAG_SHAPE_MASK)) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    LaunchShape shape;
+    if (!shape_of(flags, shape)) return fail(RT_ERR_UNSUPPORTED, "launch shape index not compiled in");
     rt_bvh_info bi{};
     bi.max_depth = info->max_depth;
-    *bytes = workspace_for(bi, info->n_rays, kShapes[g_shape_index.load()]);
+    *bytes = workspace_for(bi, info->n_rays, shape);
     return RT_OK;
 }
 
@@ -618,19 +635,6 @@ rt_status rt_hit_backward(const rt_ray *rays, const rt_hit *hits, const float *g
     const rt_status st = launch_hit_backward(q, &err);
     if (st != RT_OK) return fail(st, err);
     return RT_OK;
-}
-
-rt_status rt_set_launch_shape(uint32_t block, uint32_t lds_stack, uint32_t chunk, uint32_t queue)
-{
-    g_last_error.clear();
-    for (uint32_t i = 0; i < kNumShapes; ++i) {
-        if (kShapes[i].block == block && kShapes[i].lds_stack == lds_stack &&
-            kShapes[i].chunk == chunk && kShapes[i].queue == queue) {
-            g_shape_index.store(i);
-            return RT_OK;
-        }
-    }
-    return fail(RT_ERR_UNSUPPORTED, "launch shape not compiled into the library");
 }
 
 uint32_t rt_launch_shapes(uint32_t *blocks, uint32_t *lds_stacks, uint32_t *chunks,

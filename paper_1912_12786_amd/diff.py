@@ -15,12 +15,25 @@ import torch
 from . import rtx
 
 
+def _same_cuda_device(**tensors):
+    """Raises ValueError unless every tensor lives on one CUDA device: the
+    backward kernel dereferences their data pointers on that device."""
+    devs = {name: t.device for name, t in tensors.items() if t is not None}
+    bad = [name for name, d in devs.items() if d.type != "cuda"]
+    if bad:
+        raise ValueError(f"{', '.join(bad)} must be CUDA tensors (got {[str(devs[b]) for b in bad]})")
+    if len(set(devs.values())) > 1:
+        raise ValueError(f"tensors on different devices: { {k: str(v) for k, v in devs.items()} }")
+
+
 class DifferentiableHit(torch.autograd.Function):
     """``tuv, prim, hit = DifferentiableHit.apply(rays, vertices, faces, geom_ids,
     texcoords, textures, intersector, alpha_min, checker_n, max_leaf)``
 
-    rays float32 [N, 8] and vertices float32 [nv, 3] on the GPU (both may
-    require grad); faces uint32/int32 [n, 3]; geom_ids, texcoords, textures as
+    rays float32 [N, 8] and vertices float32 [nv, 3] on one GPU (both may
+    require grad; anything else raises ValueError before a launch); faces
+    uint32/int32 [n, 3] on any device (copied to the vertices' device);
+    geom_ids, texcoords, textures as
     numpy arrays (alpha intersector) or None; max_leaf: leaf size limit of the
     forward's BVH build (1..7).  Returns tuv float32 [N, 3]
     (zeros for misses), prim int32 [N] (-1 for misses) and hit bool [N]."""
@@ -28,6 +41,7 @@ class DifferentiableHit(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rays, vertices, faces, geom_ids, texcoords, textures, intersector="default",
                 alpha_min=128, checker_n=8, max_leaf=4):
+        _same_cuda_device(rays=rays, vertices=vertices)
         v = vertices.detach()
         f = faces.detach().to(torch.int64)
         tris = v.cpu().numpy()[f.cpu().numpy()]
@@ -39,7 +53,8 @@ class DifferentiableHit(torch.autograd.Function):
         hit = prim != -1
         tuv = hits[:, [0, 2, 3]].clone()
         tuv[~hit] = 0.0
-        faces_u32 = f.to(torch.int32).contiguous()
+        # the backward kernel reads the faces on the vertices' device
+        faces_u32 = f.to(device=v.device, dtype=torch.int32).contiguous()
         ctx.save_for_backward(rays.detach().contiguous(), hits, v.contiguous(), faces_u32)
         ctx.mark_non_differentiable(prim, hit)
         return tuv, prim, hit
@@ -49,6 +64,7 @@ class DifferentiableHit(torch.autograd.Function):
         rays, hits, vertices, faces = ctx.saved_tensors
         n = rays.shape[0]
         g = grad_tuv.contiguous().to(torch.float32)
+        _same_cuda_device(rays=rays, hits=hits, vertices=vertices, faces=faces, grad_tuv=g)
         grad_vertices = torch.zeros_like(vertices)
         grad_rays = torch.empty_like(rays)
         stream = torch.cuda.current_stream(rays.device).cuda_stream
@@ -63,10 +79,13 @@ def hit_backward(rays, hits, grad_tuv, vertices, faces, grad_vertices=None, grad
     """Direct call of rt_hit_backward on device tensors.  Returns
     (grad_vertices, grad_rays or None); grad_vertices is zeroed here unless
     given (then accumulated)."""
+    _same_cuda_device(rays=rays, hits=hits, vertices=vertices, grad_tuv=grad_tuv,
+                      grad_vertices=grad_vertices)
     if grad_vertices is None:
         grad_vertices = torch.zeros_like(vertices)
     gr = torch.empty_like(rays) if grad_rays else None
-    faces_i = faces.to(torch.int32).contiguous()
+    # faces given on the host are copied to the vertices' device
+    faces_i = faces.to(device=vertices.device, dtype=torch.int32).contiguous()
     g = grad_tuv.contiguous().to(torch.float32)
     stream = torch.cuda.current_stream(rays.device).cuda_stream
     rtx.rt_hit_backward(rays.data_ptr(), hits.data_ptr(), g.data_ptr(), rays.shape[0],

@@ -26,6 +26,8 @@ RT_MISS = 0xFFFFFFFF
 RT_FLAG_COUNT = 1
 RT_FLAG_RUNTIME_SWITCH = 2
 RT_FLAG_RUNTIME_CALL = 4
+RT_FLAG_SHAPE_SHIFT = 8
+RT_FLAG_SHAPE_MASK = 0xFF00
 RT_NODE_BYTES = 64
 RT_NODE_BYTES_Q8 = 32
 RT_TRI_BYTES = 48
@@ -119,7 +121,6 @@ SIGNATURES = [
                                  _P, _P, _SZ, _P]),
     ("rt_hit_backward", C.c_int, [_P, _P, _P, _U32, _P, _U32, _P, _U32, _P, _P, _P]),
     ("rt_launch_shapes", C.c_uint32, [_P, _P, _P, _P, _U32]),
-    ("rt_set_launch_shape", C.c_int, [_U32, _U32, _U32, _U32]),
     ("rt_status_string", C.c_char_p, [C.c_int]),
     ("rt_last_error", C.c_char_p, []),
 ]
@@ -364,7 +365,13 @@ class InstancedScene:
     def trace(self, rays, intersector="default", *, any_hit=False, count=False, checker_n=8,
               alpha_min=128, out=None, inst_ids=None, workspace=None, stream=None):
         """Returns (hits [N,4] float32 or occluders [N] int32, inst_ids [N] int32[,
-        counters])."""
+        counters]).  ``stream``: as for :func:`trace`."""
+        with _on_stream(rays.device, stream) as s:
+            return self._trace_on(rays, intersector, any_hit, count, checker_n, alpha_min, out,
+                                  inst_ids, workspace, s)
+
+    def _trace_on(self, rays, intersector, any_hit, count, checker_n, alpha_min, out, inst_ids,
+                  workspace, s):
         torch = _torch()
         n = int(rays.shape[0])
         dev = rays.device
@@ -390,7 +397,6 @@ class InstancedScene:
                                                       C.byref(b)), "rt_trace_instanced_workspace_bytes")
         ws = workspace or Workspace(dev)
         wptr, wbytes = ws.get(b.value)
-        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
         _check(lib.rt_trace_instanced(
             C.byref(tl), self.table.data_ptr(), C.byref(self.info), rays.data_ptr(), n,
             KINDS[intersector], None if params is None else C.cast(C.pointer(params), C.c_void_p),
@@ -426,8 +432,23 @@ def rt_launch_shapes():
     return [tuple(int(a[i]) for a in arr) for i in range(n)]
 
 
-def rt_set_launch_shape(block: int, lds_stack: int, chunk: int, queue: int):
-    _check(load_library().rt_set_launch_shape(block, lds_stack, chunk, queue), "rt_set_launch_shape")
+def RT_FLAG_SHAPE(index: int) -> int:
+    """The flags field that selects launch shape ``index`` of rt_launch_shapes()."""
+    return (int(index) << RT_FLAG_SHAPE_SHIFT) & RT_FLAG_SHAPE_MASK
+
+
+def shape_flag(shape) -> int:
+    """Flags bits for a launch shape given as None (the default), an index into
+    rt_launch_shapes(), or a (block, lds_stack, chunk, queue) tuple."""
+    if shape is None:
+        return 0
+    if isinstance(shape, (int, np.integer)):
+        return RT_FLAG_SHAPE(int(shape))
+    shapes = rt_launch_shapes()
+    key = tuple(int(x) for x in shape)
+    if key not in shapes:
+        raise RtxError(RT_ERR_UNSUPPORTED, "shape_flag", f"launch shape {key} not compiled in")
+    return RT_FLAG_SHAPE(shapes.index(key))
 
 
 def rt_status_string(status: int) -> str:
@@ -522,6 +543,33 @@ def _params(scene: Scene, intersector: str, alpha_min: int, checker_n: int):
     return None
 
 
+class _on_stream:
+    """Context for one trace call: yields the raw stream to launch on.  When
+    the caller names a stream other than torch's current one, torch's current
+    stream is switched to it for the call, so that the outputs and any
+    temporary workspace allocated here belong to the stream the kernel runs
+    on (the caching allocator then never hands their memory to other work
+    while the kernel may still use it)."""
+
+    def __init__(self, device, stream):
+        self.device, self.stream, self.ctx = device, stream, None
+
+    def __enter__(self):
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        if self.stream is None or int(self.stream) == int(cur.cuda_stream):
+            return cur.cuda_stream
+        ext = torch.cuda.ExternalStream(int(self.stream), device=self.device)
+        self.ctx = torch.cuda.stream(ext)
+        self.ctx.__enter__()
+        return int(self.stream)
+
+    def __exit__(self, *exc):
+        if self.ctx is not None:
+            self.ctx.__exit__(*exc)
+        return False
+
+
 class Workspace:
     """Caller-owned device workspace reused across trace calls."""
 
@@ -540,21 +588,32 @@ class Workspace:
 
 def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "closest",
           count: bool = False, alpha_min: int = 128, checker_n: int = 8, k: int = 4, out=None,
-          counters=None, workspace: Workspace | None = None, stream=None):
+          counters=None, workspace: Workspace | None = None, stream=None, shape=None):
     """Traces device rays ``float32 [N, 8]``.
 
     closest: returns ``hits float32 [N, 4]`` = (t, prim_id bits, u, v); view
     column 1 as int32/uint32 for prim_id.  any: returns ``int32 [N]``
     occluders (-1 = none).  multi: returns ``(hits float32 [N, k, 4], n_hits
     int32 [N])``.  With ``count`` also returns ``int32 [N, 4]`` counters (box
-    tests, triangle tests, candidates, accepted)."""
+    tests, triangle tests, candidates, accepted).  ``shape``: launch shape of
+    this call (see :func:`shape_flag`; None = the library's default).
+    ``stream``: a raw hipStream_t to launch on instead of torch's current
+    stream; the tensors allocated here are then allocated on that stream."""
     torch = _torch()
     if rays.dtype != torch.float32 or rays.dim() != 2 or rays.shape[1] != 8 or not rays.is_contiguous():
         raise ValueError("rays must be a contiguous float32 [N, 8] tensor")
+    with _on_stream(rays.device, stream) as s:
+        return _trace_on(scene, rays, intersector, query, count, alpha_min, checker_n, k, out,
+                         counters, workspace, s, shape)
+
+
+def _trace_on(scene, rays, intersector, query, count, alpha_min, checker_n, k, out, counters,
+              workspace, s, shape):
+    torch = _torch()
     n = int(rays.shape[0])
     dev = rays.device
     params = _params(scene, intersector, alpha_min, checker_n)
-    flags = RT_FLAG_COUNT if count else 0
+    flags = (RT_FLAG_COUNT if count else 0) | shape_flag(shape)
     sc = scene.view
     if query == "closest":
         if out is None:
@@ -572,7 +631,6 @@ def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "clo
         counters = torch.empty((n, 4), dtype=torch.int32, device=dev)
     ws = workspace or Workspace(dev)
     wptr, wbytes = ws.get(rt_trace_workspace_bytes(sc, n, flags))
-    s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
     cptr = counters.data_ptr() if count else None
     if query == "closest":
         rt_trace_closest(sc, rays.data_ptr(), n, KINDS[intersector], params, flags,
@@ -612,16 +670,23 @@ class Batch:
         self.offsets = np.concatenate([[0], np.cumsum(np.asarray(n_rays, np.int64))])
 
     def trace(self, rays, *, count=False, checker_n: int = 8, out=None, counters=None,
-              workspace: Workspace | None = None, stream=None):
-        """Closest hits of all rays (scene order) in one launch."""
+              workspace: Workspace | None = None, stream=None, shape=None):
+        """Closest hits of all rays (scene order) in one launch (``shape``,
+        ``stream``: as for :func:`trace`)."""
         torch = _torch()
         n = int(self.info.n_rays)
         if rays.shape != (n, 8) or rays.dtype != torch.float32 or not rays.is_contiguous():
             raise ValueError(f"rays must be a contiguous float32 [{n}, 8] tensor")
+        with _on_stream(rays.device, stream) as s:
+            return self._trace_on(rays, count, checker_n, out, counters, workspace, s, shape)
+
+    def _trace_on(self, rays, count, checker_n, out, counters, workspace, s, shape):
+        torch = _torch()
+        n = int(self.info.n_rays)
         dev = rays.device
         if out is None:
             out = torch.empty((n, 4), dtype=torch.float32, device=dev)
-        flags = RT_FLAG_COUNT if count else 0
+        flags = (RT_FLAG_COUNT if count else 0) | shape_flag(shape)
         if count and counters is None:
             counters = torch.empty((n, 4), dtype=torch.int32, device=dev)
         params = None
@@ -630,7 +695,6 @@ class Batch:
             params.checker_n = int(checker_n)
         ws = workspace or Workspace(dev)
         wptr, wbytes = ws.get(rt_trace_batch_workspace_bytes(self.info, flags))
-        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
         rt_trace_batch(self.table.data_ptr(), self.info, rays.data_ptr(), self.kind, params, flags,
                        out.data_ptr(), counters.data_ptr() if count else None, wptr, wbytes, s)
         return (out, counters) if count else out

@@ -428,23 +428,27 @@ def test_zero_rays_is_a_no_op(lib):
 def test_workspace_bytes(lib):
     shapes = rtx.rt_launch_shapes()
     assert len(shapes) >= 1
-    try:
-        for block, slots, chunk, queue in shapes:
-            rtx.rt_set_launch_shape(block, slots, chunk, queue)
-            for n in (1000, 3_000_000):
-                b = rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=20), n)
-                waves = (n + chunk - 1) // chunk
-                if queue:
-                    waves = min(waves, 256 * 32)
-                threads = (waves * 64 + block - 1) // block * block
-                assert b == (1024 if queue else 0) + max(0, 20 - (slots - 1)) * threads * 8
-                # shallow scenes need no spill space
-                shallow = rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=slots - 1), n)
-                assert shallow == (1024 if queue else 0)
-    finally:
-        rtx.rt_set_launch_shape(*shapes[0])
-    with pytest.raises(rtx.RtxError):
-        rtx.rt_set_launch_shape(3, 3, 3, 3)
+    for i, (block, slots, chunk, queue) in enumerate(shapes):
+        f = rtx.RT_FLAG_SHAPE(i)
+        assert rtx.shape_flag((block, slots, chunk, queue)) == f
+        for n in (1000, 3_000_000):
+            b = rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=20), n, f)
+            waves = (n + chunk - 1) // chunk
+            if queue:
+                waves = min(waves, 256 * 32)
+            threads = (waves * 64 + block - 1) // block * block
+            assert b == (1024 if queue else 0) + max(0, 20 - (slots - 1)) * threads * 8
+            # shallow scenes need no spill space
+            shallow = rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=slots - 1), n, f)
+            assert shallow == (1024 if queue else 0)
+    # the default field (0) is the first shape
+    assert rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=20), 5000) == \
+        rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=20), 5000, rtx.RT_FLAG_SHAPE(0))
+    # an index past the table is refused, here and by the trace calls
+    with pytest.raises(rtx.RtxError, match="launch shape"):
+        rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=20), 5000, rtx.RT_FLAG_SHAPE(len(shapes)))
+    with pytest.raises(rtx.RtxError, match="not compiled in"):
+        rtx.shape_flag((3, 3, 3, 3))
     # every flag a trace call accepts is accepted here, with the same size
     sc = _fake_scene(max_depth=20)
     base = rtx.rt_trace_workspace_bytes(sc, 5000)
@@ -474,7 +478,6 @@ def test_custom_intersector_library_loads_and_validates(lib):
     from tests.custom import binding
     cl = binding.load()
     sc = _fake_scene(max_depth=20)
-    rtx.rt_set_launch_shape(*rtx.rt_launch_shapes()[0])
     assert cl.prim_mask_workspace_bytes(C.byref(sc), 5000) == rtx.rt_trace_workspace_bytes(sc, 5000)
     # zero rays: nothing to do
     assert cl.prim_mask_trace(C.byref(sc), None, 0, 0x10, None, None, None, 0, None) == 0

@@ -154,14 +154,11 @@ def test_autotuner_picks_a_compiled_shape(env, tmp_path):
     rays = torch.from_numpy(np.concatenate([s["rays"] for s in scenes])).cuda()
     ws = rtx.Workspace("cuda")
     ref = batch.trace(rays, workspace=ws).clone()
-    default = rtx.rt_launch_shapes()[0]
-    try:
-        best, times = autotune.tune("small-batch", lambda: batch.trace(rays, workspace=ws),
-                                    cache_path=str(tmp_path / "tune.json"), steps=3, warmup=1)
-        assert tuple(best) in {tuple(s) for s in rtx.rt_launch_shapes()}
-        assert len(times) == len(rtx.rt_launch_shapes())
-        assert same_bits(batch.trace(rays, workspace=ws), ref)
-        again, _ = autotune.tune("small-batch", lambda: None, cache_path=str(tmp_path / "tune.json"))
-        assert tuple(again) == tuple(best)      # served from the cache
-    finally:
-        rtx.rt_set_launch_shape(*default)
+    best, times = autotune.tune("small-batch",
+                                lambda sh: batch.trace(rays, workspace=ws, shape=sh),
+                                cache_path=str(tmp_path / "tune.json"), steps=3, warmup=1)
+    assert tuple(best) in {tuple(s) for s in rtx.rt_launch_shapes()}
+    assert len(times) == len(rtx.rt_launch_shapes())
+    assert same_bits(batch.trace(rays, workspace=ws, shape=best), ref)
+    again, _ = autotune.tune("small-batch", lambda sh: None, cache_path=str(tmp_path / "tune.json"))
+    assert tuple(again) == tuple(best)      # served from the cache

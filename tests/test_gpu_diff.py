@@ -155,3 +155,24 @@ def test_autograd_function(diff_setup):
     assert torch.allclose(rays.grad, gR, rtol=1e-6, atol=1e-7)
     assert torch.all(rays.grad[~hit] == 0)
     assert torch.all(tuv[~hit] == 0)
+
+
+def test_host_faces_are_moved_to_the_vertices_device(diff_setup):
+    """Faces given as a host tensor reach the backward kernel on the GPU
+    (forward keeps a device copy); the gradients equal those of device faces."""
+    import torch
+    from paper_1912_12786_amd import diff
+    wl, tris, scene, bvh = diff_setup
+    announce("DifferentiableHit with host faces (every 64th ray)")
+    rays = torch.from_numpy(wl.rays[::64].copy()).cuda()
+    w = torch.from_numpy(wl.weights[::64].copy()).cuda()
+    grads = []
+    for F in (torch.from_numpy(wl.faces.astype(np.int32)),
+              torch.from_numpy(wl.faces.astype(np.int32)).cuda()):
+        V = torch.from_numpy(wl.vertices).cuda().requires_grad_(True)
+        tuv, prim, hit = diff.DifferentiableHit.apply(rays, V, F, None, None, None, "default")
+        (tuv * w).sum().backward()
+        torch.cuda.synchronize()
+        grads.append(V.grad.clone())
+    n = grads[1].norm(dim=1)
+    assert torch.all((grads[0] - grads[1]).norm(dim=1) <= 1e-4 * n + 1e-7 * n.max())

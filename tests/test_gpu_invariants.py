@@ -110,17 +110,13 @@ def test_all_launch_shapes_identical_full_size(setup):
     rays = torch.from_numpy(wl.rays).cuda()
     shapes = rtx.rt_launch_shapes()
     ref = None
-    try:
-        for shape in shapes:
-            announce(f"billboards alpha closest+count and multi k=4, shape={shape}")
-            rtx.rt_set_launch_shape(*shape)
-            h, c = rtx.trace(scene, rays, "alpha", alpha_min=128, count=True)
-            m, n = rtx.trace(scene, rays, "alpha", query="multi", k=4, alpha_min=128)
-            torch.cuda.synchronize()
-            got = (h.view(torch.int32), c, m.view(torch.int32), n)
-            if ref is None:
-                ref = got
-            else:
-                assert all(torch.equal(x, y) for x, y in zip(got, ref)), shape
-    finally:
-        rtx.rt_set_launch_shape(*shapes[0])
+    for shape in shapes:
+        announce(f"billboards alpha closest+count and multi k=4, shape={shape}")
+        h, c = rtx.trace(scene, rays, "alpha", alpha_min=128, count=True, shape=shape)
+        m, n = rtx.trace(scene, rays, "alpha", query="multi", k=4, alpha_min=128, shape=shape)
+        torch.cuda.synchronize()
+        got = (h.view(torch.int32), c, m.view(torch.int32), n)
+        if ref is None:
+            ref = got
+        else:
+            assert all(torch.equal(x, y) for x, y in zip(got, ref)), shape

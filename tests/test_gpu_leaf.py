@@ -95,26 +95,24 @@ def test_tune_scene_chooses_a_build_and_shape(env, oracle_lib, tmp_path):
     rays = torch.from_numpy(wl.rays).cuda()
     cache = str(tmp_path / "tune.json")
     announce("tune_scene over the tiny scene")
-    try:
-        sc, choice = autotune.tune_scene("tiny-alpha", wl.vertices, rays, "alpha", cache_path=cache,
-                                         leaf_sizes=(2, 4), steps=2, warmup=1, **ai)
-        n_shapes = len(rtx.rt_launch_shapes())
-        # f32 builds time every shape, compressed ones the default shape only
-        assert len(choice["ms"]) == 2 * (n_shapes + 1)
-        assert sc.info.max_leaf == choice["max_leaf"]
-        assert sc.info.layout == (1 if choice["layout"] == "q8" else 0)
-        hits, cnt = rtx.trace(sc, rays, "alpha", count=True, alpha_min=128)
-        torch.cuda.synchronize()
-        bvh = oracle_lib.build_bvh(wl.vertices, max_leaf=choice["max_leaf"])
-        B = oracle_lib.traverse(wl.vertices, bvh, wl.rays, "alpha", layout=choice["layout"],
-                                alpha_min=128, **ai)
-        P.assert_exact_vs_b(P.hits_to_numpy(hits), B, "tuned tiny")
-        P.assert_counters_vs_b(cnt, B, "tuned tiny")
-        _, again = autotune.tune_scene("tiny-alpha", wl.vertices, rays, "alpha", cache_path=cache,
-                                       leaf_sizes=(2, 4), **ai)
-        assert again == choice
-    finally:
-        rtx.rt_set_launch_shape(*rtx.rt_launch_shapes()[0])
+    sc, choice = autotune.tune_scene("tiny-alpha", wl.vertices, rays, "alpha", cache_path=cache,
+                                     leaf_sizes=(2, 4), steps=2, warmup=1, **ai)
+    n_shapes = len(rtx.rt_launch_shapes())
+    # f32 builds time every shape, compressed ones the default shape only
+    assert len(choice["ms"]) == 2 * (n_shapes + 1)
+    assert sc.info.max_leaf == choice["max_leaf"]
+    assert sc.info.layout == (1 if choice["layout"] == "q8" else 0)
+    hits, cnt = rtx.trace(sc, rays, "alpha", count=True, alpha_min=128,
+                          shape=tuple(choice["shape"]))
+    torch.cuda.synchronize()
+    bvh = oracle_lib.build_bvh(wl.vertices, max_leaf=choice["max_leaf"])
+    B = oracle_lib.traverse(wl.vertices, bvh, wl.rays, "alpha", layout=choice["layout"],
+                            alpha_min=128, **ai)
+    P.assert_exact_vs_b(P.hits_to_numpy(hits), B, "tuned tiny")
+    P.assert_counters_vs_b(cnt, B, "tuned tiny")
+    _, again = autotune.tune_scene("tiny-alpha", wl.vertices, rays, "alpha", cache_path=cache,
+                                   leaf_sizes=(2, 4), **ai)
+    assert again == choice
 
 
 @pytest.mark.parametrize("seed", range(8))

@@ -185,17 +185,13 @@ def test_tiny_all_launch_shapes_identical(torch_cuda, rtx_mod, tiny_setup):
     wl, ai, scene, _ = tiny_setup
     shapes = rtx.rt_launch_shapes()
     ref = None
-    try:
-        for shape in shapes:
-            announce(f"tiny alpha count shape={shape}")
-            rtx.rt_set_launch_shape(*shape)
-            hits, cnt = run(rtx, torch, scene, wl.rays, "alpha", count=True, alpha_min=128)
-            if ref is None:
-                ref = (hits, cnt)
-            else:
-                assert same_bits(hits, ref[0]) and same_bits(cnt, ref[1])
-    finally:
-        rtx.rt_set_launch_shape(*shapes[0])
+    for shape in shapes:
+        announce(f"tiny alpha count shape={shape}")
+        hits, cnt = run(rtx, torch, scene, wl.rays, "alpha", count=True, alpha_min=128, shape=shape)
+        if ref is None:
+            ref = (hits, cnt)
+        else:
+            assert same_bits(hits, ref[0]) and same_bits(cnt, ref[1])
 
 
 # ----------------------------------------------------------------------------
@@ -281,21 +277,17 @@ def test_deep_bvh_uses_spill_stack(torch_cuda, rtx_mod, oracle_lib):
     rays[150:, 5:7] = rng.normal(0, 1e-3, size=(150, 2))
     rays[:, 7] = np.inf
     shapes = rtx.rt_launch_shapes()
-    try:
-        for shape in shapes:
-            rtx.rt_set_launch_shape(*shape)
-            assert rtx.rt_trace_workspace_bytes(sc.view, 300) > 0
-            for kind, kw in (("alpha", dict(alpha_min=1)), ("default", {})):
-                announce(f"deep bvh kind={kind} shape={shape}")
-                okw = dict(ai, alpha_min=1) if kind == "alpha" else {}
-                B = oracle_lib.traverse(verts, bvh, rays, kind, **okw)
-                hits, cnt = run(rtx, torch, sc, rays, kind, count=True, **kw)
-                P.assert_exact_vs_b(P.hits_to_numpy(hits), B, f"deep {kind}")
-                P.assert_counters_vs_b(cnt, B, f"deep {kind}")
-                if kind == "alpha":   # every box along the ray visited
-                    assert B["counters"][:, 1].max() == n
-    finally:
-        rtx.rt_set_launch_shape(*shapes[0])
+    for i, shape in enumerate(shapes):
+        assert rtx.rt_trace_workspace_bytes(sc.view, 300, rtx.RT_FLAG_SHAPE(i)) > 0
+        for kind, kw in (("alpha", dict(alpha_min=1)), ("default", {})):
+            announce(f"deep bvh kind={kind} shape={shape}")
+            okw = dict(ai, alpha_min=1) if kind == "alpha" else {}
+            B = oracle_lib.traverse(verts, bvh, rays, kind, **okw)
+            hits, cnt = run(rtx, torch, sc, rays, kind, count=True, shape=shape, **kw)
+            P.assert_exact_vs_b(P.hits_to_numpy(hits), B, f"deep {kind}")
+            P.assert_counters_vs_b(cnt, B, f"deep {kind}")
+            if kind == "alpha":   # every box along the ray visited
+                assert B["counters"][:, 1].max() == n
 
 
 def test_nondefault_stream_and_determinism(torch_cuda, rtx_mod, tiny_setup):

@@ -1,10 +1,11 @@
 """Performance smoke test: the benchmark's launch (alpha mask, billboards
 200k triangles, 1920x1080, leaves of at most 2 triangles) must keep at least
-half of its recorded throughput (3197 Mrays/s, 0.643 ms per launch on MI355X)
-and of its algorithmic-bandwidth fraction (1.11 of the 8 TB/s HBM peak).  The
-bounds are loose on purpose: they catch a broken schedule or a lost
-optimisation, not run-to-run noise."""
-import numpy as np
+half of its recorded throughput (3069 Mrays/s on MI355X, 0.676 ms per launch).
+The bound is loose on purpose: it catches a broken schedule or a lost
+optimisation, not run-to-run noise.  The roofline object bench.py builds from
+the same launch time must describe a physically possible point: measured HBM
+traffic over the launch time at most the 8 TB/s peak, the texture addresser
+busy at most all of the time."""
 import pytest
 
 from paper_1912_12786_amd import workloads as W
@@ -28,10 +29,12 @@ def test_headline_throughput_floor():
     ms = bench.timed(lambda: rtx.trace(scene, rays, "alpha", alpha_min=128, out=out, workspace=ws),
                      20, 3, stream)
     mrays = wl.n_rays / ms / 1e3
-    _, cnt = rtx.trace(scene, rays, "alpha", alpha_min=128, count=True, workspace=ws)
-    torch.cuda.synchronize()
-    alg = int(bench.bytes_per_ray(cnt.cpu().numpy().view(np.uint32), "alpha").sum())
-    frac = alg / (ms * 1e-3) / (bench.PEAK_HBM_GBS * 1e9)
-    print(f"[gpu-case] {mrays:.0f} Mrays/s, {ms:.4f} ms, roofline fraction {frac:.3f}", flush=True)
-    assert mrays > 1550, mrays
-    assert frac > 0.55, frac
+    rec = bench.find_counters(bench.kernel_source_sha(), wl.name, "alpha", "closest", "f32", 2,
+                              list(rtx.rt_launch_shapes()[0]), "scanline")
+    roof = bench.roofline(ms, 0, rec)
+    print(f"[gpu-case] {mrays:.0f} Mrays/s, {ms:.4f} ms, HBM fraction {roof['frac']}, "
+          f"counters {None if rec is None else rec['file']}", flush=True)
+    assert mrays > 1530, mrays
+    if rec is not None:
+        assert 0 < roof["frac"] <= 1.0, roof
+        assert 0 < roof["issue"]["frac"] <= 1.0, roof

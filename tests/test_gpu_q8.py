@@ -88,13 +88,9 @@ def test_tiny_q8_launch_shapes(env, tiny_q8):
     wl, ai, sc, _ = tiny_q8
     shapes = rtx.rt_launch_shapes()
     rays = torch.from_numpy(wl.rays).cuda()
-    try:
-        for shape in shapes[1:]:
-            rtx.rt_set_launch_shape(*shape)
-            with pytest.raises(rtx.RtxError, match="default launch shape"):
-                rtx.trace(sc, rays, "alpha", alpha_min=128)
-    finally:
-        rtx.rt_set_launch_shape(*shapes[0])
+    for shape in shapes[1:]:
+        with pytest.raises(rtx.RtxError, match="default launch shape"):
+            rtx.trace(sc, rays, "alpha", alpha_min=128, shape=shape)
     from tests.test_gpu_dispatch import trace_flags
     for flags in (rtx.RT_FLAG_RUNTIME_SWITCH, rtx.RT_FLAG_RUNTIME_CALL):
         with pytest.raises(rtx.RtxError, match="compile-time intersectors"):

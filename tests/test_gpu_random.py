@@ -79,13 +79,9 @@ def test_random_scene_bit_exact(env, oracle_lib, seed):
     sc = rtx.upload_scene(verts, kw.get("geom_ids"), kw.get("texcoords"), kw.get("textures"))
     tkw = {kk: kw[kk] for kk in ("alpha_min", "checker_n") if kk in kw}
     bvh = oracle_lib.build_bvh(verts)
-    try:
-        rtx.rt_set_launch_shape(*shape)
-        out = rtx.trace(sc, torch.from_numpy(rays).cuda(), kind, query=query, k=k, count=True,
-                        **tkw)
-        torch.cuda.synchronize()
-    finally:
-        rtx.rt_set_launch_shape(*shapes[0])
+    out = rtx.trace(sc, torch.from_numpy(rays).cuda(), kind, query=query, k=k, count=True,
+                    shape=shape, **tkw)
+    torch.cuda.synchronize()
     res, cnt = out
     B = oracle_lib.traverse(verts, bvh, rays, kind, any_hit=(query == "any"),
                             multi_k=(k if query == "multi" else 0), **kw)
