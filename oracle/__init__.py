@@ -92,7 +92,7 @@ def _load():
         lib.orc_hit_grad64.argtypes = [P, C.c_uint32, P, P, P, P, C.c_uint32, P, P]
         lib.orc_hit_grad64.restype = C.c_int
         lib.orc_brute_instanced.argtypes = [P, C.c_uint32, P, C.c_uint32, P, C.c_uint32, C.c_int, P,
-                                            P, P, P, P, P, P]
+                                            P, P, P, P, P, P, P, P]
         lib.orc_brute_instanced.restype = C.c_int
         lib.orc_traverse_instanced.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, C.c_uint32,
                                                C.c_int, P, C.c_int, P, P, P, P, P, P]
@@ -378,13 +378,16 @@ def build_tlas(world_lo, world_hi) -> OracleBVH:
 def brute_instanced(blas_vertices, inst_blas, inst_m, rays, kind="default", checker_n=8, *,
                     geom_ids=None, texcoords=None, textures=None, alpha_min=128):
     """float64 definition over every instance and triangle.  Alpha: per-mesh
-    geom_ids and texcoords lists, one shared texture array."""
+    geom_ids and texcoords lists, one shared texture array.  Returns ``t, u,
+    v, prim, inst, flags`` and the float32 error bounds ``bound_uv, bound_t``
+    of the nearest hit (the single-scene bound plus the object-ray
+    transform's rounding)."""
     lib = _load()
     bvhs = [OracleBVH(np.zeros(1, NODE_DTYPE), np.zeros(1, np.uint32), 0)] * len(blas_vertices)
     blas, inst, keep = _instance_args(blas_vertices, bvhs, inst_blas, inst_m, geom_ids, texcoords)
     r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
     m = r.shape[0]
-    out = {k: np.empty(m, np.float64) for k in ("t", "u", "v")}
+    out = {k: np.empty(m, np.float64) for k in ("t", "u", "v", "bound_uv", "bound_t")}
     out["prim"] = np.empty(m, np.uint32)
     out["inst"] = np.empty(m, np.uint32)
     out["flags"] = np.empty(m, np.uint8)
@@ -394,7 +397,8 @@ def brute_instanced(blas_vertices, inst_blas, inst_m, rays, kind="default", chec
     rc = lib.orc_brute_instanced(blas, len(blas_vertices), inst, len(inst_blas), _ptr(r), m,
                                  KINDS[kind], C.byref(is_), _ptr(out["t"]), _ptr(out["prim"]),
                                  _ptr(out["inst"]), _ptr(out["u"]), _ptr(out["v"]),
-                                 _ptr(out["flags"]))
+                                 _ptr(out["flags"]), _ptr(out["bound_uv"]),
+                                 _ptr(out["bound_t"]))
     if rc != 0:
         raise RuntimeError(f"orc_brute_instanced failed ({rc})")
     del keep, k2

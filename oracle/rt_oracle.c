@@ -1180,10 +1180,45 @@ typedef struct {
 
 /* float64 definition: every instance, every triangle (object-space test of
  * the object-space ray, computed in float64 from the float32 inputs). */
+/* Extra float32 error of a hit reached through a float32 object ray.  The
+ * traversal forms o' and d' with three roundings per component, so
+ * |o'_i - o_i| <= c (|m_i0 o_x| + |m_i1 o_y| + |m_i2 o_z| + |m_i3|) and
+ * |d'_i - d_i| <= c (|m_i0 d_x| + |m_i1 d_y| + |m_i2 d_z|), c = 4 eps (above
+ * the 3 eps + O(eps^2) of three roundings).  A hit solves
+ * o + t d = v0 + u e1 + v e2; perturbing o by do and d by dd moves the
+ * solution by [d, -e1, -e2]^-1 (-(do + t dd)), so by Cramer's rule, with
+ * w = do + t dd and det = d.(e1 x e2):
+ *   |dt| <= |w| |e1 x e2| / |det|,  |du| <= |w| |d x e2| / |det|,
+ *   |dv| <= |w| |d x e1| / |det|.
+ * The float32 test's own rounding on the perturbed ray is the single-scene
+ * bound; first-order terms only, with a factor 2 on the sum for the
+ * second-order remainder. */
+static void transform_error(const float *m, const float *r, d3 d, const float *tri, double t,
+                            double *x_uv, double *x_t)
+{
+    const double c = 4.0 * 0x1p-24;
+    d3 ao, ad;
+    double *pao = &ao.x, *pad = &ad.x;
+    for (int a = 0; a < 3; ++a) {
+        const float *row = m + 4 * a;
+        pao[a] = c * (fabs((double)row[0] * r[0]) + fabs((double)row[1] * r[1]) +
+                      fabs((double)row[2] * r[2]) + fabs((double)row[3]));
+        pad[a] = c * (fabs((double)row[0] * r[4]) + fabs((double)row[1] * r[5]) +
+                      fabs((double)row[2] * r[6]));
+    }
+    double w = d3_norm(ao) + fabs(t) * d3_norm(ad);
+    d3 v0 = d3_load(tri), e1 = d3_sub(d3_load(tri + 3), v0), e2 = d3_sub(d3_load(tri + 6), v0);
+    double adet = fabs(d3_dot(d, d3_cross(e1, e2)));
+    double cu = d3_norm(d3_cross(d, e2)), cv = d3_norm(d3_cross(d, e1));
+    *x_uv = w * (cu > cv ? cu : cv) / adet;
+    *x_t = w * d3_norm(d3_cross(e1, e2)) / adet;
+}
+
 int orc_brute_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst *inst,
                         uint32_t n_inst, const float *rays, uint32_t n_rays, int kind,
                         const orc_isect *is, double *t_out, uint32_t *prim_out,
-                        uint32_t *inst_out, double *u_out, double *v_out, uint8_t *flags)
+                        uint32_t *inst_out, double *u_out, double *v_out, uint8_t *flags,
+                        double *bound_uv, double *bound_t)
 {
     if (kind == ORC_ALPHA)
         for (uint32_t b = 0; b < n_blas; ++b)
@@ -1191,7 +1226,7 @@ int orc_brute_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst *i
     for (uint32_t i = 0; i < n_rays; ++i) {
         const float *r = rays + 8 * (size_t)i;
         double tmin = r[3], tmax = r[7];
-        double t1 = INFINITY, t2 = INFINITY, u1 = 0, v1 = 0, bt1 = 0;
+        double t1 = INFINITY, t2 = INFINITY, u1 = 0, v1 = 0, bt1 = 0, bu1 = 0;
         uint32_t p1 = ORC_MISS, q1 = ORC_MISS;
         uint8_t fl = 0;
         for (int pass = 0; pass < 2; ++pass) {
@@ -1213,17 +1248,19 @@ int orc_brute_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst *i
                 for (uint32_t k = 0; k < b->n_tris; ++k) {
                     double t, u, v, mg, bu, bt;
                     if (!plane_hit64(o, d, b->verts + 9 * (size_t)k, &t, &u, &v, &mg, &bu, &bt)) continue;
-                    /* the object ray is a transformed float32 ray: widen the
-                     * float32 bounds by the transform's own rounding */
-                    bu = 2.0 * bu + 1e-6;
-                    bt = 2.0 * bt + 1e-6 * fabs(t);
+                    /* the object ray is a transformed float32 ray: add the
+                     * transform's own rounding, carried through the hit */
+                    double xu, xt;
+                    transform_error(m, r, d, b->verts + 9 * (size_t)k, t, &xu, &xt);
+                    bu += 2.0 * xu;
+                    bt += 2.0 * xt;
                     const uint32_t g = b->geom ? b->geom[k] : 0;
                     if (pass == 0) {
                         if (!(mg >= 0.0) || !(t > tmin) || !(t < tmax)) continue;
                         double fm;
                         if (kind == ORC_PROCEDURAL && !checker_accept64(is, u, v, &fm)) continue;
                         if (kind == ORC_ALPHA && !alpha_accept64(&bis, k, g, u, v)) continue;
-                        if (t < t1) { t2 = t1; t1 = t; u1 = u; v1 = v; p1 = k; q1 = j; bt1 = bt; }
+                        if (t < t1) { t2 = t1; t1 = t; u1 = u; v1 = v; p1 = k; q1 = j; bt1 = bt; bu1 = bu; }
                         else if (t < t2) t2 = t;
                     } else {
                         if (!(t > tmin - bt) || !(t < tmax + bt) || !(t <= reach + bt)) continue;
@@ -1252,6 +1289,8 @@ int orc_brute_instanced(const orc_blas *blas, uint32_t n_blas, const orc_inst *i
         }
         t_out[i] = t1; u_out[i] = u1; v_out[i] = v1; prim_out[i] = p1; inst_out[i] = q1;
         flags[i] = fl;
+        if (bound_uv) bound_uv[i] = bu1;
+        if (bound_t) bound_t[i] = bt1;
     }
     return 0;
 }
