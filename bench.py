@@ -140,6 +140,128 @@ def copy_calibration():
                       "launches": 3})
 
 
+COPY_BYTES = 1 << 30   # the calibration copy reads and writes 1 GiB
+
+
+def _counter_rows(directory: str) -> list:
+    """Every row of the rocprofv3 counter CSVs under ``directory``."""
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"),
+                                 recursive=True)):
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    if not rows:
+        raise SystemExit(f"no rocprofv3 counter CSV under {directory}")
+    return rows
+
+
+def _per_dispatch(rows, match, first_n=None) -> dict:
+    """Mean value per dispatch of each counter over the dispatches of the
+    kernels whose name ``match`` accepts (the first ``first_n`` of them, in
+    dispatch order, when given), and the number of dispatches used."""
+    by_dispatch = {}
+    for r in rows:
+        if not match(r["Kernel_Name"]):
+            continue
+        d = by_dispatch.setdefault(int(r["Dispatch_Id"]), {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    ids = sorted(by_dispatch)[:first_n] if first_n else sorted(by_dispatch)
+    if not ids:
+        raise SystemExit("no dispatch of the selected kernel in the counter CSV")
+    names = set().union(*(by_dispatch[i] for i in ids))
+    return {"n": len(ids), **{k: sum(by_dispatch[i].get(k, 0.0) for i in ids) / len(ids)
+                              for k in names}}
+
+
+def ingest_counters(args, directory: str):
+    """Writes ``profiles/counters_<config>.json`` from the rocprofv3 passes
+    under ``directory``: ``fetch/`` (FETCH_SIZE), ``write/`` (WRITE_SIZE) and
+    ``issue/`` (texture-addresser and SQ counters) of ``bench.py --steps S
+    --warmup W --no-cpu-baseline`` with this run's configuration flags, and
+    ``copy_fetch/``, ``copy_write/`` of ``bench.py --copy-calibration``.  Only
+    the first W + S dispatches of the timed (non-counting) trace kernel are
+    used; the copy calibration scales the two HBM counters."""
+    from paper_1912_12786_amd import rtx
+    kind = args.intersector or {"billboards": "alpha", "tiny": "default",
+                                "spheres": "procedural"}[args.workload]
+    isect = {"alpha": "alpha_intersector", "default": "default_intersector",
+             "procedural": "checker_intersector"}[kind]
+    res = {"closest": "closest_result", "any": "any_result",
+           "multi": f"multi_result<{args.k}>"}[args.query]
+
+    def trace_kernel(name):
+        return ("trace_kernel<" in name and f"rtx::{isect}," in name and "counting" not in name
+                and f"rtx::{res}" in name)
+
+    def copy_kernel(name):
+        return "copy" in name.lower()
+
+    n = args.warmup + args.steps
+    fetch = _per_dispatch(_counter_rows(os.path.join(directory, "fetch")), trace_kernel, n)
+    write = _per_dispatch(_counter_rows(os.path.join(directory, "write")), trace_kernel, n)
+    issue = _per_dispatch(_counter_rows(os.path.join(directory, "issue")), trace_kernel, n)
+    cf = _per_dispatch(_counter_rows(os.path.join(directory, "copy_fetch")), copy_kernel)
+    cw = _per_dispatch(_counter_rows(os.path.join(directory, "copy_write")), copy_kernel)
+    f_fac = COPY_BYTES / (cf["FETCH_SIZE"] * 1024)
+    w_fac = COPY_BYTES / (cw["WRITE_SIZE"] * 1024)
+    traffic = fetch["FETCH_SIZE"] * 1024 * f_fac + write["WRITE_SIZE"] * 1024 * w_fac
+    grbm = issue["GRBM_GUI_ACTIVE"]          # summed over the 8 XCDs
+    ta_busy = issue["TA_TA_BUSY_sum"] / N_CUS / (grbm / 8)
+    lane_util = issue["SQ_THREAD_CYCLES_VALU"] / (64 * issue["SQ_ACTIVE_INST_VALU"])
+    shape = list(parse_shape(args.shape) or rtx.rt_launch_shapes()[0])
+    wl_name = {"billboards": "billboards_200000_tris_1920x1080"}.get(args.workload)
+    if wl_name is None:
+        from paper_1912_12786_amd import workloads as W
+        wl_name = {"tiny": W.tiny, "spheres": W.spheres}[args.workload]().name
+    base = (f"python3 bench.py --workload {args.workload} --intersector {kind} --query "
+            f"{args.query} --layout {args.layout} --max-leaf {args.max_leaf} --ray-order "
+            f"{args.ray_order}" + (f" --shape {args.shape}" if args.shape else "")
+            + f" --steps {args.steps} --warmup {args.warmup} --no-cpu-baseline")
+    pmc = "rocprofv3 --pmc {} --output-format csv -d <out>/{} -o bench -- "
+    rec = {
+        "kernel_source_sha": kernel_source_sha(),
+        "config": {"workload": wl_name, "intersector": kind, "query": args.query,
+                   "layout": args.layout, "max_leaf": args.max_leaf, "launch_shape": shape,
+                   "ray_order": args.ray_order},
+        "dispatches": {"fetch": fetch["n"], "write": write["n"], "issue": issue["n"]},
+        "fetch_kib_per_dispatch": round(fetch["FETCH_SIZE"], 2),
+        "write_kib_per_dispatch": round(write["WRITE_SIZE"], 2),
+        "copy_calibration": {"bytes_copied": COPY_BYTES, "fetch_kib": round(cf["FETCH_SIZE"], 2),
+                             "write_kib": round(cw["WRITE_SIZE"], 2),
+                             "fetch_factor": round(f_fac, 5), "write_factor": round(w_fac, 5)},
+        "traffic_bytes_per_launch": int(round(traffic)),
+        "ta_busy_frac": round(ta_busy, 4),
+        "limiter": "vmem_issue",
+        "vmem_rd_wave_instr": int(round(issue["SQ_INSTS_VMEM_RD"])),
+        "valu_wave_instr": int(round(issue["SQ_INSTS_VALU"])),
+        "valu_lane_utilisation": round(lane_util, 4),
+        "waves": int(round(issue["SQ_WAVES"])),
+        "gpu_active_cycles_per_xcd": int(round(grbm / 8)),
+        "commands": {
+            "fetch": pmc.format("FETCH_SIZE", "fetch") + base,
+            "write": pmc.format("WRITE_SIZE", "write") + base,
+            "issue": pmc.format(" ".join(ISSUE_COUNTERS), "issue") + base,
+            "copy_fetch": pmc.format("FETCH_SIZE", "copy_fetch") + "python3 bench.py --copy-calibration",
+            "copy_write": pmc.format("WRITE_SIZE", "copy_write") + "python3 bench.py --copy-calibration",
+            "ingest": f"python3 bench.py --ingest-counters <out> " + base.split(" ", 2)[2],
+        },
+    }
+    name = (f"counters_{args.workload}_{kind}_{args.query}_{args.layout}_leaf{args.max_leaf}_"
+            f"{'x'.join(map(str, shape))}_{args.ray_order}.json")
+    with open(os.path.join(PROFILES, name), "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps({"written": os.path.join("profiles", name), **rec}))
+
+
+# one pass of texture-addresser and SQ counters (within one pass's limits:
+# 6 SQ, 1 TA, 1 GRBM)
+ISSUE_COUNTERS = ("TA_TA_BUSY_sum", "GRBM_GUI_ACTIVE", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VALU",
+                  "SQ_THREAD_CYCLES_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVES")
+
+
 def _morton2(x: np.ndarray, y: np.ndarray, bits: int) -> np.ndarray:
     """Interleaves the low ``bits`` bits of x (even positions) and y (odd)."""
     k = np.zeros_like(x)
@@ -479,6 +601,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--ingest-counters", metavar="DIR", default=None,
+                    help="write profiles/counters_<config>.json from rocprofv3 counter passes "
+                         "under DIR (fetch/, write/, issue/, copy_fetch/, copy_write/) taken "
+                         "with the same configuration flags; no GPU needed")
     ap.add_argument("--shape", default=None,
                     help="launch shape BLOCK,LDS_SLOTS,CHUNK,QUEUE (default: the library's default)")
     ap.add_argument("--intersector", default=None, choices=["alpha", "default", "procedural"],
@@ -518,6 +644,9 @@ def main():
               "step, so multi-GPU runs are not part of this benchmark", file=sys.stderr)
         sys.exit(2)
 
+    if args.ingest_counters:
+        ingest_counters(args, args.ingest_counters)
+        return
     import torch
     if args.copy_calibration:
         copy_calibration()
