@@ -237,6 +237,30 @@ rt_status rt_trace_closest(const rt_scene *scene, const rt_ray *rays, uint32_t n
                            rt_hit *hits, rt_counters *counters,
                            void *workspace, size_t workspace_bytes, void *stream);
 
+/* Bytes of the library's own fixed device scratch (64 MiB per GPU) that
+ * rt_trace_closest_noalloc uses in place of a caller workspace. */
+#define RT_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* rt_trace_closest without a workspace argument and without any allocation,
+ * for callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation).  The workspace
+ * rt_trace_closest would take (ray-queue heads and stack overflow space) is
+ * a fixed RT_NOALLOC_SCRATCH_BYTES array in device memory that the library
+ * holds on every GPU it runs on until the process ends.  Arguments, results
+ * and errors as for rt_trace_closest (hits and counters are bit-identical),
+ * plus: a call whose rt_trace_workspace_bytes exceeds
+ * RT_NOALLOC_SCRATCH_BYTES fails with RT_ERR_WORKSPACE before any device
+ * work (the default launch shape fits scenes of max_depth <= 22 at any ray
+ * count; more LDS stack slots or fewer rays per call fit deeper ones).  The
+ * stream must belong to the current device.  All calls on one GPU share
+ * that GPU's scratch: calls that overlap in time on one GPU (two streams,
+ * two threads) race and give undefined results; calls ordered on one stream
+ * do not.  The first call on a device looks up the scratch's address there
+ * (RT_ERR_HIP if that fails). */
+rt_status rt_trace_closest_noalloc(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                                   rt_isect_kind kind, const void *params, uint32_t flags,
+                                   rt_hit *hits, rt_counters *counters, void *stream);
+
 /* Any-hit query (Section 3.1): occluder[i] = input index of the first hit
  * the intersector accepted in traversal order, or RT_MISS.  Arguments as for
  * rt_trace_closest. */

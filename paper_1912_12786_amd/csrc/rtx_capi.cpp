@@ -2,15 +2,23 @@
 // host-side selection of the kernel instantiation per call.
 #include <atomic>
 #include <cmath>
+#include <mutex>
 #include <vector>
 #include <cstdint>
 #include <cstring>
 #include <string>
 
+#include <hip/hip_runtime.h>
+
 #include "rt_internal.hpp"
 #include "rt_batch_layout.hpp"
 
 using namespace rtx;
+
+// Fixed device scratch of rt_trace_closest_noalloc: one copy per GPU, at
+// each GPU's own address.  In host code this name is only a handle for
+// hipGetSymbolAddress, never a device pointer.
+static __device__ __align__(256) unsigned char scratch[RT_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -109,11 +117,36 @@ rt_status check_params(const rt_scene *sc, rt_isect_kind kind, const void *param
     return fail(RT_ERR_UNSUPPORTED, "unknown intersector kind");
 }
 
+// Device address of `scratch` on each device, looked up once per device
+// with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+rt_status scratch_on_current_device(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(RT_ERR_HIP, "no current HIP device for the fixed scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RT_ERR_HIP, std::string("hipGetSymbolAddress of the fixed scratch: ") +
+                                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RT_OK;
+}
+
 rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
                        rt_isect_kind kind, const void *params, uint32_t flags, void *out,
                        size_t out_align, rt_counters *counters, void *workspace,
                        size_t workspace_bytes, void *stream, uint32_t multi_k = 0,
-                       uint32_t *n_hits = nullptr, const void *batch = nullptr)
+                       uint32_t *n_hits = nullptr, const void *batch = nullptr,
+                       bool fixed_scratch = false)
 {
     g_last_error.clear();
     rt_status st = check_scene(scene);
@@ -154,7 +187,22 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     if (count && !counters) return fail(RT_ERR_INVALID_ARG, "RT_FLAG_COUNT needs a counters array");
     if (count && !aligned(counters, 16)) return fail(RT_ERR_MISALIGNED, "counters not 16-byte aligned");
     const size_t need = workspace_for(scene->info, n_rays, shape);
-    if (need > 0) {
+    if (fixed_scratch) {  // the library's own scratch replaces the workspace
+        if (need > RT_NOALLOC_SCRATCH_BYTES)
+            return fail(RT_ERR_WORKSPACE,
+                        "call needs " + std::to_string(need) + " bytes of workspace, more than "
+                        "the fixed scratch of rt_trace_closest_noalloc (" +
+                        std::to_string(RT_NOALLOC_SCRATCH_BYTES) + "): use rt_trace_closest "
+                        "with a workspace, a launch shape with more LDS stack slots, or fewer "
+                        "rays per call");
+        workspace = nullptr;
+        workspace_bytes = 0;
+        if (need > 0) {
+            st = scratch_on_current_device(&workspace);
+            if (st != RT_OK) return st;
+            workspace_bytes = RT_NOALLOC_SCRATCH_BYTES;
+        }
+    } else if (need > 0) {
         if (!workspace || workspace_bytes < need)
             return fail(RT_ERR_WORKSPACE, "workspace smaller than rt_trace_workspace_bytes");
         if (!aligned(workspace, 16)) return fail(RT_ERR_MISALIGNED, "workspace not 16-byte aligned");
@@ -268,6 +316,14 @@ rt_status rt_trace_closest(const rt_scene *scene, const rt_ray *rays, uint32_t n
 {
     return trace_common(Query::Closest, scene, rays, n_rays, kind, params, flags, hits, 16,
                         counters, workspace, workspace_bytes, stream);
+}
+
+rt_status rt_trace_closest_noalloc(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,
+                                   rt_isect_kind kind, const void *params, uint32_t flags,
+                                   rt_hit *hits, rt_counters *counters, void *stream)
+{
+    return trace_common(Query::Closest, scene, rays, n_rays, kind, params, flags, hits, 16,
+                        counters, nullptr, 0, stream, 0, nullptr, nullptr, true);
 }
 
 rt_status rt_trace_any(const rt_scene *scene, const rt_ray *rays, uint32_t n_rays,

@@ -31,6 +31,7 @@ RT_FLAG_SHAPE_MASK = 0xFF00
 RT_NODE_BYTES = 64
 RT_NODE_BYTES_Q8 = 32
 RT_TRI_BYTES = 48
+RT_NOALLOC_SCRATCH_BYTES = 64 << 20
 LAYOUTS = {"f32": 0, "q8": 1}
 KINDS = {"default": 0, "alpha": 1, "procedural": 2}
 
@@ -102,6 +103,8 @@ SIGNATURES = [
     ("rt_trace_workspace_bytes", C.c_int, [C.POINTER(rt_scene), _U32, _U32, C.POINTER(_SZ)]),
     ("rt_trace_closest", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                    _SZ, _P]),
+    ("rt_trace_closest_noalloc", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32,
+                                           _P, _P, _P]),
     ("rt_trace_any", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                _SZ, _P]),
     ("rt_batch_table_bytes", C.c_int, [_U32, C.POINTER(_SZ)]),
@@ -207,6 +210,17 @@ def rt_trace_closest(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, par
                                 None if params is None else C.cast(C.pointer(params), C.c_void_p),
                                 flags, hits_ptr, counters_ptr, workspace_ptr, workspace_bytes,
                                 stream), "rt_trace_closest")
+
+
+def rt_trace_closest_noalloc(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params,
+                             flags: int, hits_ptr: int, counters_ptr: int | None,
+                             stream: int | None):
+    lib = load_library()
+    _check(lib.rt_trace_closest_noalloc(C.byref(scene), rays_ptr, n_rays, kind,
+                                        None if params is None else
+                                        C.cast(C.pointer(params), C.c_void_p),
+                                        flags, hits_ptr, counters_ptr, stream),
+           "rt_trace_closest_noalloc")
 
 
 def rt_trace_any(scene: rt_scene, rays_ptr: int, n_rays: int, kind: int, params, flags: int,

@@ -589,3 +589,30 @@ def test_leaf_size_validation(lib):
     assert _closest(lib, sc, n=0) == -1              # hand-made info: limit 4
     sc.info.max_leaf = 7
     assert _closest(lib, sc, n=0) == 0
+
+
+def test_noalloc_rejects_before_any_device_work(lib):
+    """rt_trace_closest_noalloc validates like rt_trace_closest and refuses a
+    call whose workspace exceeds its fixed scratch, all before a HIP call."""
+    def call(sc, n=100, flags=0, rays=0x30000, hits=0x40000, counters=None):
+        return lib.rt_trace_closest_noalloc(C.byref(sc) if sc is not None else None, rays, n, 0,
+                                            None, flags, hits, counters, None)
+    sc = _fake_scene()
+    assert call(None) == -1
+    assert call(sc, rays=None) == -1
+    assert call(sc, hits=0x40008) == -2
+    assert call(sc, flags=rtx.RT_FLAG_COUNT) == -1
+    assert call(sc, n=(1 << 31) + 1) == -1
+    assert call(sc, n=0) == 0                      # no rays: no launch, no scratch lookup
+    assert call(sc, flags=rtx.RT_FLAG_SHAPE(len(rtx.rt_launch_shapes()))) == -3
+    # the default shape's spill space at the full persistent grid: 4 MiB per
+    # stack level beyond the 7 in LDS, so max_depth 22 fits and 23 does not
+    full = 3_000_000
+    for depth, ok in ((22, True), (23, False), (100, False)):
+        need = rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=depth), full)
+        assert (need <= rtx.RT_NOALLOC_SCRATCH_BYTES) == ok, (depth, need)
+    assert call(_fake_scene(max_depth=23), n=full) == -4
+    assert "fixed scratch" in rtx.rt_last_error()
+    # a deep scene still fits with fewer rays per call
+    need = rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=100), 20_000)
+    assert need <= rtx.RT_NOALLOC_SCRATCH_BYTES
