@@ -84,6 +84,12 @@ def _load():
                                             C.c_int, P, C.c_int, C.c_uint32, P, P, P, P, P, P,
                                             C.c_int]
         lib.orc_traverse_layout.restype = C.c_int
+        lib.orc_traverse_wide.argtypes = [P, P, C.c_uint32, P, P, C.c_uint32, P, P, C.c_uint32,
+                                          C.c_int, P, C.c_int, C.c_uint32, P, P, P, P, P, P,
+                                          C.c_int]
+        lib.orc_traverse_wide.restype = C.c_int
+        lib.orc_widen.argtypes = [P, C.c_uint32, P, P, P, P]
+        lib.orc_widen.restype = C.c_int
         lib.orc_quantize.argtypes = [P, C.c_uint32, P, P, P]
         lib.orc_quantize.restype = C.c_int
         lib.orc_node_size.restype = C.c_uint32
@@ -177,6 +183,7 @@ class OracleBVH:
     perm: np.ndarray     # uint32, leaf order -> input triangle index
     max_depth: int
     qbox: np.ndarray | None = field(default=None, repr=False)  # quantize()'s boxes, once computed
+    wide: dict | None = field(default=None, repr=False)        # widen()'s layout, once computed
 
     @property
     def n_nodes(self) -> int:
@@ -218,6 +225,26 @@ def quantize(bvh: OracleBVH) -> dict:
     return {"frames": frames, "q": q, "qbox": qbox}
 
 
+WIDE_DTYPE = np.dtype([("n", "<u4"), ("child", "<u4", 4)])
+WIDE_STACK = 128  # entries of oracle B's traversal stack
+
+
+def widen(bvh: OracleBVH) -> dict:
+    """The four-wide layout of an oracle BVH: ``wide`` (one WIDE_DTYPE entry
+    per binary node: child count and binary child indices of the wide node it
+    heads, n = 0 for the others), ``order`` (the heads of the wide nodes in
+    depth-first preorder), and ``stack_bound`` (the largest sum of k - 1 over
+    the wide nodes of a root-to-leaf path)."""
+    lib = _load()
+    n = bvh.n_nodes
+    wide = np.zeros(max(1, n), WIDE_DTYPE)
+    order = np.zeros(max(1, n), np.uint32)
+    nw, sb = C.c_uint32(), C.c_uint32()
+    if lib.orc_widen(_ptr(bvh.nodes), n, _ptr(wide), _ptr(order), C.byref(nw), C.byref(sb)) != 0:
+        raise RuntimeError("orc_widen failed")
+    return {"wide": wide[:n], "order": order[: nw.value].copy(), "stack_bound": int(sb.value)}
+
+
 def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, texcoords=None,
              textures=None, alpha_min=128, checker_n=8, any_hit=False, count=True, multi_k=0,
              layout="f32", threads=None):
@@ -226,8 +253,8 @@ def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, t
     candidates handed to the intersector, accepted candidates).  With
     ``multi_k > 0`` (multi-hit) ``t, u, v, prim`` are ``[N, multi_k]`` (nearest
     first, padded with misses) and ``n_hits [N]`` counts the kept hits.
-    ``layout``: "f32" (float32 child boxes) or "q8" (the 32-byte layout's
-    quantized child boxes)."""
+    ``layout``: "f32" (float32 child boxes), "q8" (the 32-byte layout's
+    quantized child boxes) or "wide4" (the four-wide layout of the same BVH)."""
     lib = _load()
     verts = np.ascontiguousarray(vertices, np.float32).reshape(-1, 9)
     r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
@@ -241,18 +268,29 @@ def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, t
     nh = np.empty(m, np.uint32) if multi_k else None
     cnt = np.empty((m, 4), np.uint32) if count else None
     is_, keep = _isect(texcoords, textures, alpha_min, checker_n)
-    if layout not in ("f32", "q8"):
+    if layout not in ("f32", "q8", "wide4"):
         raise ValueError(f"unknown layout {layout!r}")
     qbox = None
     if layout == "q8":
         if bvh.qbox is None:
             bvh.qbox = quantize(bvh)["qbox"]
         qbox = bvh.qbox
-    rc = lib.orc_traverse_layout(_ptr(verts), _ptr(g), n, _ptr(bvh.nodes), _ptr(bvh.perm),
-                                 bvh.n_nodes, _ptr(qbox), _ptr(r), m, KINDS[kind], C.byref(is_),
-                                 int(bool(any_hit)), int(multi_k), _ptr(out["t"]),
-                                 _ptr(out["prim"]), _ptr(out["u"]), _ptr(out["v"]), _ptr(nh),
-                                 _ptr(cnt), _threads(threads))
+    if layout == "wide4":
+        if bvh.wide is None:
+            bvh.wide = widen(bvh)
+        if bvh.wide["stack_bound"] > WIDE_STACK:
+            raise ValueError("four-wide stack bound exceeds the oracle's stack")
+        rc = lib.orc_traverse_wide(_ptr(verts), _ptr(g), n, _ptr(bvh.nodes), _ptr(bvh.perm),
+                                   bvh.n_nodes, _ptr(bvh.wide["wide"]), _ptr(r), m, KINDS[kind],
+                                   C.byref(is_), int(bool(any_hit)), int(multi_k), _ptr(out["t"]),
+                                   _ptr(out["prim"]), _ptr(out["u"]), _ptr(out["v"]), _ptr(nh),
+                                   _ptr(cnt), _threads(threads))
+    else:
+        rc = lib.orc_traverse_layout(_ptr(verts), _ptr(g), n, _ptr(bvh.nodes), _ptr(bvh.perm),
+                                     bvh.n_nodes, _ptr(qbox), _ptr(r), m, KINDS[kind],
+                                     C.byref(is_), int(bool(any_hit)), int(multi_k),
+                                     _ptr(out["t"]), _ptr(out["prim"]), _ptr(out["u"]),
+                                     _ptr(out["v"]), _ptr(nh), _ptr(cnt), _threads(threads))
     if rc != 0:
         raise RuntimeError(f"orc_traverse failed ({rc})")
     if count:

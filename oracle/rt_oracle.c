@@ -621,6 +621,84 @@ int orc_quantize(const orc_node *nodes, uint32_t n_nodes, uint32_t *frames, uint
 }
 
 /* ======================================================================
+ * Oracle B part 1c: the four-wide layout
+ *
+ * Not in the paper (it leaves the BVH's arity open); defined in words:
+ *   collapse  for a binary inner node X the child list starts [X.left,
+ *             X.right]; while it has fewer than 4 entries and one of them is
+ *             a binary inner node, the inner entry with the largest box
+ *             surface area (float64; ties -> the earliest in the list) is
+ *             replaced at its place by its left child followed by its right
+ *             child.  Inner entries of the final list head wide nodes of
+ *             their own; leaf entries are the binary leaves.
+ *   traverse at a wide node with k children, box-test children 0..k-1 in
+ *             order (each counted); order the hit ones by (tn, child index)
+ *             ascending, visit the first and push the others from the last to
+ *             the second (the second ends on top); none hit -> pop.  Pops,
+ *             leaves and counting as in the binary traversal.
+ *   bound     the stack never holds more than the largest sum of (k - 1)
+ *             over the wide nodes of a root-to-leaf path.
+ * The oracle keys each wide node by the index of the binary node heading it.
+ * ====================================================================== */
+
+typedef struct {
+    uint32_t n;         /* children (2..4); 0 if this binary node heads no wide node */
+    uint32_t child[4];  /* binary node indices, in list order */
+} orc_wide;
+
+static uint32_t widen_rec(const orc_node *nodes, uint32_t x, orc_wide *wide, uint32_t *order,
+                          uint32_t *n_order, uint32_t *bound)
+{
+    uint32_t list[4] = {nodes[x].left, nodes[x].right, 0, 0};
+    uint32_t n = 2;
+    while (n < 4) {
+        int best = -1;
+        double best_area = -1.0;
+        for (uint32_t i = 0; i < n; ++i) {
+            const orc_node *c = &nodes[list[i]];
+            if (c->count != 0) continue;
+            double a = box_area(c->lo, c->hi);
+            if (a > best_area) { best_area = a; best = (int)i; }
+        }
+        if (best < 0) break;
+        uint32_t y = list[best];
+        for (uint32_t i = n; i > (uint32_t)best + 1; --i) list[i] = list[i - 1];
+        list[best] = nodes[y].left;
+        list[best + 1] = nodes[y].right;
+        ++n;
+    }
+    wide[x].n = n;
+    for (uint32_t i = 0; i < 4; ++i) wide[x].child[i] = i < n ? list[i] : 0;
+    order[(*n_order)++] = x;
+    uint32_t count = 1, deepest = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (nodes[list[i]].count != 0) continue;
+        uint32_t b = 0;
+        count += widen_rec(nodes, list[i], wide, order, n_order, &b);
+        if (b > deepest) deepest = b;
+    }
+    *bound = (n - 1) + deepest;
+    return count;
+}
+
+/* Collapses an oracle BVH (n_nodes binary nodes, node 0 the root) into the
+ * four-wide layout.  wide[] has n_nodes entries (keyed by binary index);
+ * order[] receives the heads of the wide nodes in depth-first preorder
+ * (children in list order).  Outputs the wide node count and the stack
+ * bound; a root that is a leaf (or an empty scene) gives none. */
+int orc_widen(const orc_node *nodes, uint32_t n_nodes, orc_wide *wide, uint32_t *order,
+              uint32_t *n_wide, uint32_t *stack_bound)
+{
+    for (uint32_t i = 0; i < n_nodes; ++i) memset(&wide[i], 0, sizeof wide[i]);
+    *n_wide = 0;
+    *stack_bound = 0;
+    if (n_nodes == 0 || nodes[0].count != 0 || n_nodes == 1) return 0;
+    uint32_t n_order = 0;
+    *n_wide = widen_rec(nodes, 0, wide, order, &n_order, stack_bound);
+    return n_order == *n_wide ? 0 : -1;
+}
+
+/* ======================================================================
  * Oracle B part 2: float32 while-while traversal (Algorithm 1)
  *
  * Per ray:
@@ -669,6 +747,7 @@ typedef struct {
     uint32_t *n_hits;   /* multi-hit: hits found per ray */
     uint32_t *counters; /* [n_rays][4]: boxes, triangles, candidates, accepts */
     const float *qbox;  /* 32-byte layout: decoded child boxes per node, or NULL */
+    const orc_wide *wide; /* four-wide layout (by binary head index), or NULL */
     uint32_t next;
     pthread_mutex_t lock;
 } trav_job;
@@ -820,7 +899,36 @@ static void trav_one(trav_job *job, uint32_t i)
         int alive = box_test(&rs, job->nodes[0].lo, job->nodes[0].hi, &tn);
         while (alive && !rs.done) {
             /* descend through inner nodes */
-            while (job->nodes[cur].count == 0) {
+            while (job->wide && job->nodes[cur].count == 0) {
+                const orc_wide *w = &job->wide[cur];
+                float tn4[4];
+                uint32_t hits[4], m = 0;
+                for (uint32_t c = 0; c < w->n; ++c) {
+                    const orc_node *ch = &job->nodes[w->child[c]];
+                    if (!box_test(&rs, ch->lo, ch->hi, &tn4[c])) continue;
+                    /* insert c after every hit child with tn <= tn4[c] */
+                    uint32_t pos = m;
+                    while (pos > 0 && tn4[c] < tn4[hits[pos - 1]]) { hits[pos] = hits[pos - 1]; --pos; }
+                    hits[pos] = c;
+                    ++m;
+                }
+                if (m > 0) {
+                    for (uint32_t j = m - 1; j >= 1; --j) {
+                        stack_node[sp] = w->child[hits[j]];
+                        stack_tn[sp] = tn4[hits[j]];
+                        ++sp;
+                    }
+                    cur = w->child[hits[0]];
+                } else {
+                    alive = 0;
+                    while (sp > 0) {
+                        --sp;
+                        if (!(stack_tn[sp] > rs.tmax_cur)) { cur = stack_node[sp]; alive = 1; break; }
+                    }
+                    if (!alive) break;
+                }
+            }
+            while (!job->wide && job->nodes[cur].count == 0) {
                 const orc_node *nd = &job->nodes[cur];
                 float tl, tr;
                 int hl, hr;
@@ -913,6 +1021,15 @@ int orc_traverse_layout(const float *verts, const uint32_t *geom_ids, uint32_t n
                         uint32_t *prim, float *u, float *v, uint32_t *n_hits, uint32_t *counters,
                         int n_threads);
 
+/* The traversal over the four-wide layout of the same BVH (wide from
+ * orc_widen; the binary nodes supply the boxes and the leaves). */
+int orc_traverse_wide(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
+                      const orc_node *nodes, const uint32_t *perm, uint32_t n_nodes,
+                      const orc_wide *wide, const float *rays, uint32_t n_rays, int kind,
+                      const orc_isect *is, int any_hit, uint32_t multi_k, float *t,
+                      uint32_t *prim, float *u, float *v, uint32_t *n_hits, uint32_t *counters,
+                      int n_threads);
+
 int orc_traverse(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
                  const orc_node *nodes, const uint32_t *perm, uint32_t n_nodes,
                  const float *rays, uint32_t n_rays, int kind, const orc_isect *is,
@@ -946,6 +1063,33 @@ int orc_traverse_layout(const float *verts, const uint32_t *geom_ids, uint32_t n
     job.t = t; job.u = u; job.v = v; job.prim = prim; job.counters = counters;
     job.n_hits = n_hits;
     job.qbox = qbox;
+    pthread_mutex_init(&job.lock, NULL);
+    run_threads(trav_worker, &job, n_threads);
+    pthread_mutex_destroy(&job.lock);
+    return 0;
+}
+
+int orc_traverse_wide(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
+                      const orc_node *nodes, const uint32_t *perm, uint32_t n_nodes,
+                      const orc_wide *wide, const float *rays, uint32_t n_rays, int kind,
+                      const orc_isect *is, int any_hit, uint32_t multi_k, float *t,
+                      uint32_t *prim, float *u, float *v, uint32_t *n_hits, uint32_t *counters,
+                      int n_threads)
+{
+    if (kind < ORC_DEFAULT || kind > ORC_PROCEDURAL) return -1;
+    if (multi_k > ORC_MAX_MULTI || (multi_k > 0 && (any_hit || !n_hits))) return -2;
+    if (!wide) return -3;
+    trav_job job;
+    memset(&job, 0, sizeof job);
+    job.verts = verts; job.geom = geom_ids; job.n_tris = n_tris;
+    job.nodes = nodes; job.perm = perm; job.n_nodes = n_nodes;
+    job.rays = rays; job.n_rays = n_rays; job.kind = kind;
+    if (is) job.is = *is;
+    job.any_hit = any_hit;
+    job.multi_k = multi_k;
+    job.t = t; job.u = u; job.v = v; job.prim = prim; job.counters = counters;
+    job.n_hits = n_hits;
+    job.wide = wide;
     pthread_mutex_init(&job.lock, NULL);
     run_threads(trav_worker, &job, n_threads);
     pthread_mutex_destroy(&job.lock);

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 def load(name: str) -> dict:
     with open(os.path.join(HERE, name)) as f:
         fx = json.load(f)
-    fx["vertices"] = np.asarray(fx["vertices"], np.float32)
+    if "vertices" in fx:
+        fx["vertices"] = np.asarray(fx["vertices"], np.float32)
     if "rays" in fx:
         fx["rays"] = np.asarray([[np.inf if x == "inf" else x for x in r] for r in fx["rays"]],
                                 np.float32)
