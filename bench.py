@@ -115,14 +115,18 @@ def roofline(kernel_ms: float, alg_bytes: int, rec) -> dict:
     return out
 
 
-def bytes_per_ray(counters: np.ndarray, kind: str, node_bytes: int = 64) -> np.ndarray:
+def bytes_per_ray(counters: np.ndarray, kind: str, node_bytes: int = 64,
+                  children: int = 2) -> np.ndarray:
     """Algorithmic bytes of one ray: its 32-byte ray record and 16-byte hit
-    record, one node record (64 bytes, or 32 in the compressed layout) per
-    inner node entered (box tests are the root's plus two per inner node),
-    one 48-byte triangle record per triangle test, and per alpha decision the
-    24 bytes of texture coordinates plus the 4-byte texel."""
+    record, one node record (64 bytes, 32 in the compressed layout, 128 in the
+    four-wide one) per inner node entered (box tests are the root's plus one
+    per child of every inner node entered: two, or up to four in the wide
+    layout, where bytes are counted per box test as a quarter record, exact
+    for full nodes), one 48-byte triangle record per triangle test, and per
+    alpha decision the 24 bytes of texture coordinates plus the 4-byte
+    texel."""
     c = counters.astype(np.int64)
-    b = 32 + 16 + node_bytes * ((c[:, 0] - 1).clip(min=0) // 2) + 48 * c[:, 1]
+    b = (32 + 16 + node_bytes * (c[:, 0] - 1).clip(min=0) // children + 48 * c[:, 1])
     if kind == "alpha":
         b = b + 28 * c[:, 2]
     return b
@@ -622,11 +626,12 @@ def main():
                     help="let the autotuner choose leaf size (2, 3, 4), node layout and launch "
                          "shape for the billboards/tiny/spheres workload (overrides --max-leaf, "
                          "--layout and --shape)")
-    ap.add_argument("--layout", default=None, choices=["f32", "q8"],
-                    help="inner-node layout: f32 = 64-B nodes with float32 boxes, q8 = 32-B "
-                         "nodes with 8-bit boxes (rt_bvh_compress). Default: q8 for the spheres "
-                         "and batched workloads (measured faster: BVHs beyond the caches), f32 "
-                         "otherwise")
+    ap.add_argument("--layout", default=None, choices=["f32", "q8", "wide4"],
+                    help="inner-node layout: f32 = 64-B binary nodes with float32 boxes, q8 = "
+                         "32-B binary nodes with 8-bit boxes (rt_bvh_compress), wide4 = 128-B "
+                         "four-wide nodes with float32 boxes (rt_bvh_widen). Default: q8 for the "
+                         "spheres and batched workloads (measured faster: BVHs beyond the "
+                         "caches), f32 otherwise")
     ap.add_argument("--query", default="closest", choices=["closest", "any", "multi"])
     ap.add_argument("--k", type=int, default=4, help="hits kept per ray by --query multi")
     ap.add_argument("--workload", default="billboards",
@@ -762,8 +767,9 @@ def main():
                        workspace=ws, shape=shape)
     torch.cuda.synchronize()
     counters = cnt.cpu().numpy().view(np.uint32)
-    node_bytes = 32 if args.layout == "q8" else 64
-    alg_bytes = int(bytes_per_ray(counters, kind, node_bytes).sum())
+    node_bytes = {"q8": 32, "wide4": 128}.get(args.layout, 64)
+    alg_bytes = int(bytes_per_ray(counters, kind, node_bytes,
+                                  4 if args.layout == "wide4" else 2).sum())
     # output records: 16-B hit (closest), 4-B occluder (any), k 16-B hits + 4-B count (multi)
     if query == "any":
         alg_bytes -= 12 * wl.n_rays
@@ -811,8 +817,9 @@ def main():
             "bvh": (f"binary SAH, leaves of <= {args.max_leaf} triangles, {scene.info.n_nodes} "
                     f"inner nodes, depth {scene.info.max_depth}"),
             "max_leaf": args.max_leaf,
-            "node_layout": ("32-B nodes, 8-bit child boxes" if args.layout == "q8"
-                            else "64-B nodes, float32 child boxes"),
+            "node_layout": {"q8": "32-B nodes, 8-bit child boxes",
+                            "wide4": "128-B four-wide nodes, float32 child boxes"}.get(
+                                args.layout, "64-B nodes, float32 child boxes"),
             "launch_shape": ([int(x) for x in args.shape.split(",")] if args.shape
                              else list(rtx.rt_launch_shapes()[0])),
         },

@@ -129,6 +129,7 @@ typedef struct rt_procedural_params {
 /* Inner-node layouts (rt_bvh_info.layout). */
 #define RT_LAYOUT_F32 0u  /* 64-B nodes with float32 child boxes (rt_bvh_build) */
 #define RT_LAYOUT_Q8 1u   /* 32-B nodes with 8-bit child boxes (rt_bvh_compress) */
+#define RT_LAYOUT_WIDE4 2u /* 128-B nodes with up to four float32 child boxes (rt_bvh_widen) */
 
 /* Description of a built BVH (filled by rt_bvh_build). */
 typedef struct rt_bvh_info {
@@ -138,7 +139,7 @@ typedef struct rt_bvh_info {
     uint32_t max_geom_id;
     uint32_t root_ref;       /* packed reference of the root item */
     float root_lo[3], root_hi[3];
-    uint32_t layout;         /* RT_LAYOUT_F32 or RT_LAYOUT_Q8 */
+    uint32_t layout;         /* RT_LAYOUT_F32, RT_LAYOUT_Q8 or RT_LAYOUT_WIDE4 */
     uint32_t max_leaf;       /* leaf size limit the BVH was built with (0 is read as 4) */
 } rt_bvh_info;
 
@@ -154,6 +155,8 @@ typedef struct rt_scene {
 
 #define RT_NODE_BYTES 64u
 #define RT_NODE_BYTES_Q8 32u
+#define RT_NODE_BYTES_WIDE4 128u
+#define RT_WIDE_EMPTY_REF 0xFFFFFFFFu  /* reference of an unused four-wide child slot */
 #define RT_TRI_BYTES 48u
 #define RT_MAX_TRIS 0x1FFFFFFFu  /* 2^29 - 1 */
 #define RT_MAX_RAYS 0x80000000u  /* rays per trace call */
@@ -214,6 +217,37 @@ rt_status rt_bvh_build_ex(const float *vertices, const uint32_t *geom_ids, uint3
  * Fails if info->layout is not RT_LAYOUT_F32 or a box is not finite. */
 rt_status rt_bvh_compress(const void *nodes, const rt_bvh_info *info, void *out, size_t out_cap,
                           rt_bvh_info *out_info);
+
+/* Converts the inner nodes of a built BVH (host, from rt_bvh_build) to the
+ * four-wide layout: 128-byte nodes of up to four children, so that a ray
+ * visits about half as many nodes and each node fetch brings four child
+ * boxes (the paper leaves the BVH's arity open; Section 3.2's traversal only
+ * needs child boxes).  For a binary inner node the child list starts as its
+ * two children; while it has fewer than four entries and one of them is an
+ * inner node, the inner entry with the largest box surface area (in double,
+ * 2(dx dy + dy dz + dz dx); ties -> the earliest in the list) is replaced at
+ * its place by its two children (first, second).  Each inner entry of the
+ * final list becomes a four-wide node of its own; wide nodes are numbered in
+ * depth-first preorder (children in list order, node 0 the root); leaf
+ * entries keep their references.  Words of a node: lo.x[4], hi.x[4],
+ * lo.y[4], hi.y[4], lo.z[4], hi.z[4] (child c in lane c, boxes bit-identical
+ * to the binary child boxes), ref[4] (RT_WIDE_EMPTY_REF and a zero box in the
+ * unused last slots), a zero word.  The traversal box-tests every child of a
+ * node (counted), visits the hit ones in (entry distance, child index) order
+ * and pushes all but the first, the second nearest on top; closest and
+ * any-hit answers equal the binary layout's except among hits of exactly
+ * equal t, and the counters are the wide traversal's own.
+ *   nodes     host, info->n_nodes records of RT_NODE_BYTES (RT_LAYOUT_F32)
+ *   out       host output, capacity out_cap >= info->n_nodes * RT_NODE_BYTES_WIDE4
+ *             (an upper bound: the wide node count is returned), 16-byte aligned
+ *   out_info  host output: *info with layout = RT_LAYOUT_WIDE4, n_nodes = the
+ *             wide node count, max_depth = the stack bound (the largest sum of
+ *             k - 1 over the wide nodes of a root-to-leaf path), root_ref 0 for
+ *             an inner root (a root leaf stays as it is); may alias info.
+ * Fails if info->layout is not RT_LAYOUT_F32 or a child reference is out of
+ * range. */
+rt_status rt_bvh_widen(const void *nodes, const rt_bvh_info *info, void *out, size_t out_cap,
+                       rt_bvh_info *out_info);
 
 /* Device workspace a trace call needs (bytes, possibly 0): the ray queue
  * head of persistent launch shapes and overflow space for traversal stacks

@@ -27,6 +27,9 @@
 //     with e1 = v1 - v0 and e2 = v2 - v0 rounded to float.
 //   compressed inner node, 32 B (compress_nodes): {F.x F.y F.z Q0} {Q1 Q2 ref0 ref1}
 //     with frame words F and twelve 8-bit child coordinates Q (see below).
+//   four-wide inner node, 128 B (widen_nodes): {lo.x[4]} {hi.x[4]} {lo.y[4]}
+//     {hi.y[4]} {lo.z[4]} {hi.z[4]} {ref[4]} {0 0 0 0}, child c in lane c,
+//     unused slots (the last ones) with ref 0xFFFFFFFF and a zero box.
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -388,6 +391,128 @@ rt_status compress_nodes(const NodeRecord *in, uint32_t n_nodes, NodeQ8Record *o
         o.u[6] = nd.u[12];
         o.u[7] = nd.u[13];
     }
+    return RT_OK;
+}
+
+// -------------------------------------------------------------------------
+// Four-wide nodes.  A binary node's child list [left, right] grows, while it
+// has fewer than four entries and one of them is inner, by replacing the
+// inner entry of largest box surface area (double; ties -> the earliest) by
+// its two children in place.  The inner entries of the final list are
+// collapsed the same way into wide nodes of their own, numbered in
+// depth-first preorder; leaf entries keep their binary references.  A wide
+// node pushes at most k - 1 stack entries, so the stack bound is the largest
+// sum of k - 1 along a root-to-leaf path.
+// -------------------------------------------------------------------------
+namespace {
+
+struct WideEntry {
+    uint32_t ref;
+    float lo[3], hi[3];
+};
+
+double surface(const WideEntry &e)
+{
+    const double dx = double(e.hi[0]) - double(e.lo[0]);
+    const double dy = double(e.hi[1]) - double(e.lo[1]);
+    const double dz = double(e.hi[2]) - double(e.lo[2]);
+    return 2.0 * (dx * dy + dy * dz + dz * dx);
+}
+
+// The two child slots of binary inner node idx.
+void binary_children(const NodeRecord *in, uint32_t idx, WideEntry (&c)[2])
+{
+    const NodeRecord &nd = in[idx];
+    for (int k = 0; k < 2; ++k) {
+        for (int a = 0; a < 3; ++a) {
+            c[k].lo[a] = nd.f[6 * k + a];
+            c[k].hi[a] = nd.f[6 * k + 3 + a];
+        }
+        c[k].ref = nd.u[12 + k];
+    }
+}
+
+struct Widener {
+    const NodeRecord *in;
+    uint32_t n_in;
+    NodeW4Record *out;
+    uint32_t n_out = 0;
+
+    // Collapses binary inner node idx into wide node n_out; returns the
+    // largest sum of k - 1 below and including it, or UINT32_MAX if a child
+    // reference is out of range.
+    uint32_t collapse(uint32_t idx)
+    {
+        WideEntry list[4];
+        WideEntry two[2];
+        binary_children(in, idx, two);
+        list[0] = two[0];
+        list[1] = two[1];
+        uint32_t n = 2;
+        while (n < 4) {
+            int best = -1;
+            double best_area = -1.0;
+            for (uint32_t i = 0; i < n; ++i) {
+                if ((list[i].ref >> 29) != 0) continue;
+                const double a = surface(list[i]);
+                if (a > best_area) {
+                    best_area = a;
+                    best = int(i);
+                }
+            }
+            if (best < 0) break;
+            const uint32_t x = list[best].ref & kRefIndexMaskHost;
+            if (x >= n_in) return UINT32_MAX;
+            binary_children(in, x, two);
+            for (uint32_t i = n; i > uint32_t(best) + 1; --i) list[i] = list[i - 1];
+            list[best] = two[0];
+            list[best + 1] = two[1];
+            ++n;
+        }
+        const uint32_t self = n_out++;
+        NodeW4Record &o = out[self];
+        std::memset(&o, 0, sizeof o);
+        uint32_t deepest = 0;
+        for (uint32_t c = 0; c < 4; ++c) {
+            if (c >= n) {
+                o.u[24 + c] = RT_WIDE_EMPTY_REF;
+                continue;
+            }
+            for (int a = 0; a < 3; ++a) {
+                o.f[8 * a + c] = list[c].lo[a];
+                o.f[8 * a + 4 + c] = list[c].hi[a];
+            }
+            uint32_t ref = list[c].ref;
+            if ((ref >> 29) == 0) {
+                const uint32_t x = ref & kRefIndexMaskHost;
+                if (x >= n_in) return UINT32_MAX;
+                const uint32_t child = n_out;
+                const uint32_t b = collapse(x);
+                if (b == UINT32_MAX) return b;
+                deepest = b > deepest ? b : deepest;
+                ref = child;
+            }
+            out[self].u[24 + c] = ref;
+        }
+        return (n - 1) + deepest;
+    }
+};
+
+}  // namespace
+
+rt_status widen_nodes(const NodeRecord *in, const rt_bvh_info &info, NodeW4Record *out,
+                      uint32_t *n_out, uint32_t *stack_bound)
+{
+    *n_out = 0;
+    *stack_bound = 0;
+    if ((info.root_ref >> 29) != 0 || info.n_nodes == 0) return RT_OK;  // the root is a leaf
+    Widener w{in, info.n_nodes, out};
+    const uint32_t root = info.root_ref & kRefIndexMaskHost;
+    if (root >= info.n_nodes) return RT_ERR_INVALID_ARG;
+    const uint32_t b = w.collapse(root);
+    if (b == UINT32_MAX) return RT_ERR_INVALID_ARG;
+    *n_out = w.n_out;
+    *stack_bound = b;
     return RT_OK;
 }
 

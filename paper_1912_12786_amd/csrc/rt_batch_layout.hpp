@@ -23,7 +23,7 @@ struct alignas(16) batch_scene {
     float root_lo[3], root_hi[3];
     uint32_t root_ref, n_tris;
     uint32_t tex_width, tex_height, alpha_min;
-    uint32_t layout;            // RT_LAYOUT_F32 or RT_LAYOUT_Q8
+    uint32_t layout;            // RT_LAYOUT_F32, RT_LAYOUT_Q8 or RT_LAYOUT_WIDE4
     uint32_t pad[10];
 };
 static_assert(sizeof(batch_scene) == 128, "batch scene record");

@@ -30,12 +30,26 @@ struct alignas(16) NodeQ8Record {
 };
 static_assert(sizeof(NodeQ8Record) == RT_NODE_BYTES_Q8, "compressed node record size");
 
+struct alignas(16) NodeW4Record {
+    union {
+        float f[32];
+        uint32_t u[32];
+    };
+};
+static_assert(sizeof(NodeW4Record) == RT_NODE_BYTES_WIDE4, "four-wide node record size");
+
+constexpr uint32_t kRefIndexMaskHost = 0x1FFFFFFFu;
+
 // Inner nodes of a BVH over n_tris triangles with leaves of at most max_leaf.
 uint32_t max_inner_nodes(uint32_t n_tris, uint32_t max_leaf);
 rt_status build_bvh(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
                     uint32_t max_leaf, NodeRecord *nodes, TriRecord *tris, rt_bvh_info *info);
 // 64-B nodes -> 32-B nodes (RT_ERR_INVALID_ARG if a box is not finite).
 rt_status compress_nodes(const NodeRecord *in, uint32_t n_nodes, NodeQ8Record *out);
+// 64-B binary nodes -> 128-B four-wide nodes (at most info.n_nodes of them);
+// RT_ERR_INVALID_ARG if a child reference is out of range.
+rt_status widen_nodes(const NodeRecord *in, const rt_bvh_info &info, NodeW4Record *out,
+                      uint32_t *n_out, uint32_t *stack_bound);
 
 enum class Query { Closest, Any, Multi };
 

@@ -12,7 +12,7 @@
 // and may be wrapped in counting_intersector<T> for the per-ray counters.
 // trace_custom<T>() then runs the closest-hit query with it, using the
 // library's default launch shape and the scene's node layout (rt_bvh_build,
-// or rt_bvh_compress).
+// rt_bvh_compress or rt_bvh_widen).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -153,7 +153,8 @@ rt_status trace_custom(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
         *err = "scene triangle records NULL or stack bound exceeded";
         return RT_ERR_INVALID_ARG;
     }
-    if (scene->info.layout != RT_LAYOUT_F32 && scene->info.layout != RT_LAYOUT_Q8) {
+    if (scene->info.layout != RT_LAYOUT_F32 && scene->info.layout != RT_LAYOUT_Q8 &&
+        scene->info.layout != RT_LAYOUT_WIDE4) {
         *err = "unknown scene node layout";
         return RT_ERR_INVALID_ARG;
     }
@@ -170,6 +171,9 @@ rt_status trace_custom(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
     if (scene->info.layout == RT_LAYOUT_Q8)
         return launch_one<Isect, Result, int(s.lds_stack), int(s.block), int(s.chunk),
                           s.queue != 0, false, RT_LAYOUT_Q8>(a, p, stream, err);
+    if (scene->info.layout == RT_LAYOUT_WIDE4)
+        return launch_one<Isect, Result, int(s.lds_stack), int(s.block), int(s.chunk),
+                          s.queue != 0, false, RT_LAYOUT_WIDE4>(a, p, stream, err);
     return launch_one<Isect, Result, int(s.lds_stack), int(s.block), int(s.chunk), s.queue != 0>(
         a, p, stream, err);
 }

@@ -281,12 +281,12 @@ struct ring_stack {
 };
 
 struct scene_view {
-    const float4 *nodes;  // 4 float4 per inner node (2 with RT_LAYOUT_Q8)
+    const float4 *nodes;  // 4 float4 per inner node (2 with RT_LAYOUT_Q8, 8 with RT_LAYOUT_WIDE4)
     const float4 *tris;   // 3 float4 per triangle record
     float root_lo[3], root_hi[3];
     uint32_t root_ref;
     uint32_t n_tris;
-    uint32_t layout;      // RT_LAYOUT_F32 or RT_LAYOUT_Q8
+    uint32_t layout;      // RT_LAYOUT_F32, RT_LAYOUT_Q8 or RT_LAYOUT_WIDE4
 };
 
 // The two child boxes (lo0, hi0, lo1, hi1) and references of inner node
@@ -324,6 +324,75 @@ __device__ __forceinline__ void node_children(const scene_view &sc, uint32_t cur
     }
 }
 
+// Order key of a four-wide child: hit children by (tn, child index), every
+// missed child after them.  The float's bit pattern is mapped to an unsigned
+// integer of the same order (negative values reversed), so one 64-bit
+// compare orders the pair.
+__device__ __forceinline__ uint64_t wide_key(bool hit, float tn, uint32_t c)
+{
+    const uint32_t b = __float_as_uint(tn);
+    const uint32_t ord = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return hit ? (uint64_t(ord) << 2 | c) : ~uint64_t(0);
+}
+
+__device__ __forceinline__ float wide_key_tn(uint64_t k)
+{
+    const uint32_t ord = uint32_t(k >> 2);
+    return __uint_as_float((ord & 0x80000000u) ? (ord & 0x7FFFFFFFu) : ~ord);
+}
+
+__device__ __forceinline__ void order2(uint64_t &a, uint64_t &b)
+{
+    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+// One step at a four-wide node (RT_LAYOUT_WIDE4, 128-B record: lo.x[4],
+// hi.x[4], lo.y[4], hi.y[4], lo.z[4], hi.z[4], ref[4]): box-test every used
+// child slot, visit the nearest hit child (ties -> the lower slot) and push
+// the other hit ones from the farthest to the second nearest; with none hit,
+// pop.  The four keys are ordered by a five-comparator sorting network.
+template <class Isect, class Stack>
+__device__ __forceinline__ bool inner_step_wide(const scene_view &sc, const ray_state &r,
+                                                Isect &isect, Stack &st, uint32_t &cur)
+{
+    const float4 *nd = sc.nodes + 8 * size_t(cur);
+    const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5];
+    const uint4 rf = *reinterpret_cast<const uint4 *>(nd + 6);
+    const float alx[4] = {lx.x, lx.y, lx.z, lx.w}, ahx[4] = {hx.x, hx.y, hx.z, hx.w};
+    const float aly[4] = {ly.x, ly.y, ly.z, ly.w}, ahy[4] = {hy.x, hy.y, hy.z, hy.w};
+    const float alz[4] = {lz.x, lz.y, lz.z, lz.w}, ahz[4] = {hz.x, hz.y, hz.z, hz.w};
+    const uint32_t ref[4] = {rf.x, rf.y, rf.z, rf.w};
+    uint64_t k[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bool used = ref[c] != RT_WIDE_EMPTY_REF;
+        if (used) isect.on_box_test();
+        float tn;
+        const bool hit = slab(r, alx[c], aly[c], alz[c], ahx[c], ahy[c], ahz[c], tn);
+        k[c] = wide_key(used && hit, tn, uint32_t(c));
+    }
+    order2(k[0], k[1]);
+    order2(k[2], k[3]);
+    order2(k[0], k[2]);
+    order2(k[1], k[3]);
+    order2(k[1], k[2]);
+    const uint64_t none = ~uint64_t(0);
+    auto ref_of = [&](uint64_t key) {
+        const uint32_t c = uint32_t(key) & 3u;
+        return c == 0 ? ref[0] : c == 1 ? ref[1] : c == 2 ? ref[2] : ref[3];
+    };
+    st.push_if(k[3] != none, make_uint2(ref_of(k[3]), __float_as_uint(wide_key_tn(k[3]))));
+    st.push_if(k[2] != none, make_uint2(ref_of(k[2]), __float_as_uint(wide_key_tn(k[2]))));
+    st.push_if(k[1] != none, make_uint2(ref_of(k[1]), __float_as_uint(wide_key_tn(k[1]))));
+    if (k[0] != none) {
+        cur = ref_of(k[0]);
+        return true;
+    }
+    return st.pop(r.tmax, cur);
+}
+
 // One inner-node step: test both children's boxes; visit the nearer hit
 // child (ties -> child 0) and push the other if both are hit; with neither
 // hit, pop.  Returns false when the stack ran empty (ray finished).
@@ -331,6 +400,7 @@ template <uint32_t kLayout = RT_LAYOUT_F32, class Isect, class Stack>
 __device__ __forceinline__ bool inner_step(const scene_view &sc, const ray_state &r, Isect &isect,
                                            Stack &st, uint32_t &cur)
 {
+    if constexpr (kLayout == RT_LAYOUT_WIDE4) return inner_step_wide(sc, r, isect, st, cur);
     float b[12];
     uint32_t ref0, ref1;
     node_children<kLayout>(sc, cur, b, ref0, ref1);

@@ -270,6 +270,21 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
         return dispatch_kind<int(d.lds_stack), int(d.block), int(d.chunk), d.queue != 0,
                              RT_LAYOUT_Q8>(q, a, err);
     }
+    // four-wide nodes: the default launch shape and its 16-slot variant (a
+    // wide node pushes up to three entries)
+    if (q.scene->info.layout == RT_LAYOUT_WIDE4) {
+        if (q.runtime_dispatch) {
+            *err = "the four-wide node layout is compiled for the compile-time intersectors only";
+            return RT_ERR_UNSUPPORTED;
+        }
+        if (sh.block == 64 && sh.lds_stack == 8 && sh.chunk == 64 && sh.queue == 1)
+            return dispatch_kind<8, 64, 64, true, RT_LAYOUT_WIDE4>(q, a, err);
+        if (sh.block == 64 && sh.lds_stack == 16 && sh.chunk == 64 && sh.queue == 1)
+            return dispatch_kind<16, 64, 64, true, RT_LAYOUT_WIDE4>(q, a, err);
+        *err = "the four-wide node layout is compiled for launch shapes (64, 8, 64, 1) and "
+               "(64, 16, 64, 1) only";
+        return RT_ERR_UNSUPPORTED;
+    }
 #define RTX_SHAPE(B, L, C, Q)                                                          \
     if (sh.block == B && sh.lds_stack == L && sh.chunk == C && sh.queue == Q)          \
         return dispatch_kind<L, B, C, Q>(q, a, err);

@@ -59,3 +59,11 @@ def test_morton_tile_order():
     for g in range(0, 64, 16):
         assert y[g:g + 16].max() - y[g:g + 16].min() == 3 and x[g:g + 16].max() - x[g:g + 16].min() == 3
     assert (y[4], x[4]) == (0, 2)
+
+
+def test_bytes_per_ray_wide_nodes():
+    # root + one full wide node (4 box tests) + one wide node of 3 children:
+    # 8 box tests after the root, 2 nodes, 256 B (counted per box test: 8 x 32)
+    c = np.array([[9, 2, 1, 1]], np.uint32)
+    assert bench.bytes_per_ray(c, "default", node_bytes=128, children=4).tolist() == \
+        [48 + 8 * 32 + 2 * 48]

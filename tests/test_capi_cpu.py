@@ -538,7 +538,7 @@ def test_compress_validation(lib):
     _, ei = rtx.rt_bvh_compress(np.zeros(0, np.uint8), empty)
     assert ei.layout == 1 and ei.n_nodes == 0
     sc = _fake_scene()
-    sc.info.layout = 2
+    sc.info.layout = 3
     assert _closest(lib, sc) == -1
     assert b"unknown scene node layout" in lib.rt_last_error()
     sc.info.layout = 1
@@ -616,3 +616,109 @@ def test_noalloc_rejects_before_any_device_work(lib):
     # a deep scene still fits with fewer rays per call
     need = rtx.rt_trace_workspace_bytes(_fake_scene(max_depth=100), 20_000)
     assert need <= rtx.RT_NOALLOC_SCRATCH_BYTES
+
+
+# ----------------------------------------------------------------------------
+# four-wide nodes (rt_bvh_widen) against the oracle's collapse
+# ----------------------------------------------------------------------------
+def decode_product_wide(nodes_u8, info):
+    """Preorder list of (child count, [(lo, hi, leaf count, leaf first)]) of
+    the wide nodes, leaf firsts as triangle-record positions."""
+    nf = nodes_u8.view(np.float32).reshape(-1, 32)
+    nu = nodes_u8.view(np.uint32).reshape(-1, 32)
+    out = []
+
+    def rec(w):
+        refs = [int(x) for x in nu[w, 24:28]]
+        k = sum(1 for r in refs if r != rtx.RT_WIDE_EMPTY_REF)
+        assert all(r == rtx.RT_WIDE_EMPTY_REF for r in refs[k:]), "unused slots must be last"
+        assert np.all(nu[w, 28:32] == 0)
+        kids = []
+        for c in range(k):
+            lo = nf[w, [c, 8 + c, 16 + c]]
+            hi = nf[w, [4 + c, 12 + c, 20 + c]]
+            cnt, idx = refs[c] >> 29, refs[c] & 0x1FFFFFFF
+            kids.append((lo.view(np.uint32).tolist(), hi.view(np.uint32).tolist(), cnt,
+                         idx if cnt else None))
+        for c in range(k, 4):
+            assert np.all(nu[w, [c, 4 + c, 8 + c, 12 + c, 16 + c, 20 + c]] == 0)
+        out.append((k, kids))
+        for c in range(k):
+            if refs[c] >> 29 == 0:
+                assert refs[c] > w, "wide nodes must be numbered in preorder"
+                rec(refs[c])
+
+    if info.n_nodes:
+        rec(0)
+    return out
+
+
+def decode_oracle_wide(bvh, w):
+    nodes = bvh.nodes
+    out = []
+    for h in w["order"]:
+        e = w["wide"][h]
+        kids = []
+        for c in e["child"][: e["n"]]:
+            nd = nodes[int(c)]
+            cnt = int(nd["count"])
+            kids.append((nd["lo"].astype(np.float32).view(np.uint32).tolist(),
+                         nd["hi"].astype(np.float32).view(np.uint32).tolist(), cnt,
+                         int(nd["first"]) if cnt else None))
+        out.append((int(e["n"]), kids))
+    return out
+
+
+def assert_same_wide(oracle_lib, verts, max_leaf):
+    nodes, tris, info = rtx.rt_bvh_build(verts, max_leaf=max_leaf)
+    wn, winfo = rtx.rt_bvh_widen(nodes, info)
+    ob = oracle_lib.build_bvh(verts, max_leaf=max_leaf)
+    ow = oracle_lib.widen(ob)
+    assert winfo.layout == rtx.LAYOUTS["wide4"]
+    assert winfo.n_nodes == len(ow["order"])
+    assert winfo.max_depth == ow["stack_bound"]
+    assert decode_product_wide(wn, winfo) == decode_oracle_wide(ob, ow)
+    if info.root_ref >> 29:
+        assert winfo.root_ref == info.root_ref and winfo.n_nodes == 0
+    else:
+        assert winfo.root_ref == 0
+    for f in ("n_tris", "max_geom_id", "max_leaf"):
+        assert getattr(winfo, f) == getattr(info, f)
+    assert list(winfo.root_lo) == list(info.root_lo) and list(winfo.root_hi) == list(info.root_hi)
+    return winfo
+
+
+def test_widen_matches_oracle(oracle_lib):
+    rng = np.random.default_rng(9)
+    for n in (1, 3, 5, 8, 9, 17, 100, 1000):
+        for ml in (1, 2, 4):
+            v = rng.uniform(0, 1, size=(n, 3, 3)).astype(np.float32)
+            assert_same_wide(oracle_lib, v, ml)
+    assert_same_wide(oracle_lib, W.tiny().vertices, 4)
+
+
+def test_widen_matches_oracle_billboards(oracle_lib):
+    wl = W.billboards()
+    info = assert_same_wide(oracle_lib, wl.vertices, 2)
+    assert 0 < info.max_depth < 128
+
+
+def test_widen_validation(lib):
+    info = rtx.rt_bvh_info()
+    info.layout = 1
+    out = rtx.rt_bvh_info()
+    assert lib.rt_bvh_widen(None, C.byref(info), None, 0, C.byref(out)) == -1   # not float32 nodes
+    nodes, tris, binfo = rtx.rt_bvh_build(W.tiny().vertices)
+    buf = np.zeros(16, np.uint8)
+    assert lib.rt_bvh_widen(nodes.ctypes.data, C.byref(binfo), buf.ctypes.data, 16,
+                            C.byref(out)) == -1                                  # out too small
+    assert "smaller" in rtx.rt_last_error()
+    assert lib.rt_bvh_widen(None, None, None, 0, None) == -1
+    # a wide scene is accepted by the trace calls' validation (it fails later on
+    # the fake device pointers only when launched, which the CPU never does)
+    sc = _fake_scene(max_depth=30)
+    sc.info.layout = rtx.LAYOUTS["wide4"]
+    need = rtx.rt_trace_workspace_bytes(sc, 1000)
+    assert need > 1024
+    # runtime dispatch is compiled for binary float32 nodes only
+    assert _closest(lib, sc, flags=rtx.RT_FLAG_RUNTIME_SWITCH, ws=0x80000, wsb=need) == -3
