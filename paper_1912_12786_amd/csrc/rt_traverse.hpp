@@ -358,8 +358,12 @@ __device__ __forceinline__ bool inner_step_wide(const scene_view &sc, const ray_
                                                 Isect &isect, Stack &st, uint32_t &cur)
 {
     const float4 *nd = sc.nodes + 8 * size_t(cur);
-    const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5];
     const uint4 rf = *reinterpret_cast<const uint4 *>(nd + 6);
+    const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5];
+    // all seven fetches in flight before any use: without this fence the
+    // scheduler issues the reference word only after the six box words have
+    // arrived, a second memory round trip per node
+    __builtin_amdgcn_sched_barrier(0);
     const float alx[4] = {lx.x, lx.y, lx.z, lx.w}, ahx[4] = {hx.x, hx.y, hx.z, hx.w};
     const float aly[4] = {ly.x, ly.y, ly.z, ly.w}, ahy[4] = {hy.x, hy.y, hy.z, hy.w};
     const float alz[4] = {lz.x, lz.y, lz.z, lz.w}, ahz[4] = {hz.x, hz.y, hz.z, hz.w};
@@ -379,9 +383,12 @@ __device__ __forceinline__ bool inner_step_wide(const scene_view &sc, const ray_
     order2(k[1], k[3]);
     order2(k[1], k[2]);
     const uint64_t none = ~uint64_t(0);
+    // the reference of the key's child slot, by selects rather than branches
     auto ref_of = [&](uint64_t key) {
-        const uint32_t c = uint32_t(key) & 3u;
-        return c == 0 ? ref[0] : c == 1 ? ref[1] : c == 2 ? ref[2] : ref[3];
+        const uint32_t c = uint32_t(key);
+        const uint32_t r01 = (c & 1u) ? ref[1] : ref[0];
+        const uint32_t r23 = (c & 1u) ? ref[3] : ref[2];
+        return (c & 2u) ? r23 : r01;
     };
     st.push_if(k[3] != none, make_uint2(ref_of(k[3]), __float_as_uint(wide_key_tn(k[3]))));
     st.push_if(k[2] != none, make_uint2(ref_of(k[2]), __float_as_uint(wide_key_tn(k[2]))));

@@ -1,6 +1,6 @@
 """The runtime-dispatched intersectors (an inlined run-time switch, and an
 indirect call through a table of filter functions) must give bit-identical
-results to the compile-time intersectors."""
+results to the compile-time intersectors, and all three equal oracle B."""
 import numpy as np
 import pytest
 
@@ -29,7 +29,7 @@ def trace_flags(torch, rtx, scene, rays, kind, flags, **kw):
 
 @pytest.mark.parametrize("workload", ["tiny", "billboards"])
 @pytest.mark.parametrize("kind", ["default", "alpha", "procedural"])
-def test_runtime_dispatch_is_bit_identical(workload, kind):
+def test_runtime_dispatch_is_bit_identical(oracle_lib, workload, kind):
     import torch
     from paper_1912_12786_amd import rtx
     print(f"[gpu-case] runtime dispatch {workload} {kind}", flush=True)
@@ -48,3 +48,15 @@ def test_runtime_dispatch_is_bit_identical(workload, kind):
     for flags in (rtx.RT_FLAG_RUNTIME_SWITCH, rtx.RT_FLAG_RUNTIME_CALL):
         got = trace_flags(torch, rtx, scene, rays, kind, flags)
         assert same_bits(got, ref), flags
+    # and all three against oracle B (the same BVH, leaves of at most 4)
+    okw = {}
+    if kind == "alpha":
+        okw = dict(geom_ids=geom, texcoords=tc, textures=tex, alpha_min=128) if workload == "tiny" \
+            else dict(geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures,
+                      alpha_min=128)
+    elif kind == "procedural":
+        okw = dict(checker_n=8)
+    B = oracle_lib.traverse(wl.vertices, oracle_lib.build_bvh(wl.vertices), wl.rays, kind,
+                            count=False, **okw)
+    from tests import parity as P
+    P.assert_exact_vs_b(P.hits_to_numpy(ref), B, f"dispatch {workload} {kind}")
