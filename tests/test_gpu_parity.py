@@ -332,7 +332,11 @@ def test_billboards_full_closest(torch_cuda, rtx_mod, oracle_lib, billboards_set
     A = oracle_lib.brute(wl.vertices, wl.rays, kind, ray_index=idx, **okw)
     s = P.compare_vs_a(g, A, idx, f"billboards {kind}")
     print("oracle A summary", kind, s, flush=True)
-    assert s["excluded"] < 0.05 * len(idx)
+    # measured on these rays: 267 (alpha) and 25 (default) of 40,450 in the
+    # exception set; 12 and 7 rays with a u/v error above 1e-5 that pass only
+    # through the widened float32 bound
+    assert s["excluded"] <= 0.01 * len(idx)
+    assert s["n_uv_over_1e-5"] <= 0.001 * s["checked"]
 
 
 def test_billboards_full_counts_and_any(torch_cuda, rtx_mod, oracle_lib, billboards_setup):
@@ -375,6 +379,12 @@ def test_spheres_full_procedural_counts(torch_cuda, rtx_mod, oracle_lib, spheres
     A = oracle_lib.brute(wl.vertices, wl.rays, "procedural", ray_index=idx, checker_n=8)
     s = P.compare_vs_a(g, A, idx, "spheres procedural")
     print("oracle A summary spheres", s, flush=True)
+    # measured: 133 of 8,183 in the exception set (131 near a checker line:
+    # small far triangles widen the float32 bound and so the band), and 240
+    # rays with a u/v error above 1e-5 within their bound (triangles about
+    # 1/1000 of their distance wide)
+    assert s["excluded"] <= 0.025 * len(idx)
+    assert s["n_uv_over_1e-5"] <= 0.05 * s["checked"]
     announce("spheres default closest count")
     hits, cnt = run(rtx, torch, scene, wl.rays, "default", count=True)
     B = oracle_lib.traverse(wl.vertices, bvh, wl.rays, "default")
