@@ -98,9 +98,10 @@ def roofline(kernel_ms: float, alg_bytes: int, rec) -> dict:
     out = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
            "traffic": None}
     if rec is not None:
-        traffic = int(rec["traffic_bytes_per_launch"])
-        gbs = traffic / sec / 1e9
-        out.update(achieved=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4), traffic=traffic)
+        if rec.get("traffic_bytes_per_launch") is not None:
+            traffic = int(rec["traffic_bytes_per_launch"])
+            gbs = traffic / sec / 1e9
+            out.update(achieved=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4), traffic=traffic)
         if rec.get("ta_busy_frac") is not None:
             ta = float(rec["ta_busy_frac"])
             out["limiter"] = rec.get("limiter", "vmem_issue")
@@ -179,63 +180,89 @@ def _per_dispatch(rows, match, first_n=None) -> dict:
                               for k in names}}
 
 
+def kernel_tail(shape, batched: bool, layout: str) -> str:
+    """The end of the traversal kernel's demangled name for one launch shape,
+    batched flag and node layout (its last template arguments)."""
+    block, slots, chunk, queue = shape
+    code = {"f32": 0, "q8": 1, "wide4": 2}[layout]
+    return (f", {slots}, {block}, {chunk}, {'true' if queue else 'false'}, "
+            f"{'true' if batched else 'false'}, {code}u>")
+
+
 def ingest_counters(args, directory: str):
     """Writes ``profiles/counters_<config>.json`` from the rocprofv3 passes
-    under ``directory``: ``fetch/`` (FETCH_SIZE), ``write/`` (WRITE_SIZE) and
-    ``issue/`` (texture-addresser and SQ counters) of ``bench.py --steps S
-    --warmup W --no-cpu-baseline`` with this run's configuration flags, and
-    ``copy_fetch/``, ``copy_write/`` of ``bench.py --copy-calibration``.  Only
-    the first W + S dispatches of the timed (non-counting) trace kernel are
-    used; the copy calibration scales the two HBM counters."""
+    under ``directory``: ``issue/`` (texture-addresser and SQ counters) of
+    ``bench.py --steps S --warmup W --no-cpu-baseline`` with this run's
+    configuration flags, its stdout in ``issue.log`` (whose JSON line names
+    the kernel sources measured) and, when present, ``fetch/`` (FETCH_SIZE) and
+    ``write/`` (WRITE_SIZE) of the same command with ``copy_fetch/``,
+    ``copy_write/`` of ``bench.py --copy-calibration``, which scale the two
+    HBM counters.  Only the timed (non-counting) trace kernel of exactly this
+    launch shape, batched flag and node layout is read; single-scene runs use
+    their first W + S dispatches of it, the batched run every one (each
+    traces the whole batch)."""
     from paper_1912_12786_amd import rtx
-    kind = args.intersector or {"billboards": "alpha", "tiny": "default",
-                                "spheres": "procedural"}[args.workload]
+    batched = args.workload == "batched"
+    kind = "default" if batched else (args.intersector or {
+        "billboards": "alpha", "tiny": "default", "spheres": "procedural"}[args.workload])
     isect = {"alpha": "alpha_intersector", "default": "default_intersector",
              "procedural": "checker_intersector"}[kind]
     res = {"closest": "closest_result", "any": "any_result",
            "multi": f"multi_result<{args.k}>"}[args.query]
+    shape = list(parse_shape(args.shape) or rtx.rt_launch_shapes()[0])
+    tail = kernel_tail(shape, batched, args.layout)
 
     def trace_kernel(name):
         return ("trace_kernel<" in name and f"rtx::{isect}," in name and "counting" not in name
-                and f"rtx::{res}" in name)
+                and f"rtx::{res}" in name and tail in name)
 
     def copy_kernel(name):
         return "copy" in name.lower()
 
-    n = args.warmup + args.steps
-    fetch = _per_dispatch(_counter_rows(os.path.join(directory, "fetch")), trace_kernel, n)
-    write = _per_dispatch(_counter_rows(os.path.join(directory, "write")), trace_kernel, n)
+    def have(sub):
+        return os.path.isdir(os.path.join(directory, sub))
+
+    # the kernel sources the profiled runs were built from: the sha each run
+    # printed in its JSON line (stdout of the profiled command, saved as
+    # <pass>.log beside the pass's folder)
+    shas = set()
+    for sub in ("issue", "fetch", "write"):
+        log_path = os.path.join(directory, sub + ".log")
+        if not os.path.exists(log_path):
+            continue
+        with open(log_path, errors="replace") as f:
+            for line in f:
+                if line.startswith("{") and "kernel_source_sha" in line:
+                    shas.add(json.loads(line)["kernel_source_sha"])
+    if len(shas) != 1:
+        raise SystemExit(f"expected one kernel_source_sha in the passes' logs, found {shas}")
+    sha = shas.pop()
+
+    n = None if batched else args.warmup + args.steps
     issue = _per_dispatch(_counter_rows(os.path.join(directory, "issue")), trace_kernel, n)
-    cf = _per_dispatch(_counter_rows(os.path.join(directory, "copy_fetch")), copy_kernel)
-    cw = _per_dispatch(_counter_rows(os.path.join(directory, "copy_write")), copy_kernel)
-    f_fac = COPY_BYTES / (cf["FETCH_SIZE"] * 1024)
-    w_fac = COPY_BYTES / (cw["WRITE_SIZE"] * 1024)
-    traffic = fetch["FETCH_SIZE"] * 1024 * f_fac + write["WRITE_SIZE"] * 1024 * w_fac
     grbm = issue["GRBM_GUI_ACTIVE"]          # summed over the 8 XCDs
     ta_busy = issue["TA_TA_BUSY_sum"] / N_CUS / (grbm / 8)
     lane_util = issue["SQ_THREAD_CYCLES_VALU"] / (64 * issue["SQ_ACTIVE_INST_VALU"])
-    shape = list(parse_shape(args.shape) or rtx.rt_launch_shapes()[0])
-    wl_name = {"billboards": "billboards_200000_tris_1920x1080"}.get(args.workload)
-    if wl_name is None:
-        from paper_1912_12786_amd import workloads as W
-        wl_name = {"tiny": W.tiny, "spheres": W.spheres}[args.workload]().name
-    base = (f"python3 bench.py --workload {args.workload} --intersector {kind} --query "
-            f"{args.query} --layout {args.layout} --max-leaf {args.max_leaf} --ray-order "
-            f"{args.ray_order}" + (f" --shape {args.shape}" if args.shape else "")
-            + f" --steps {args.steps} --warmup {args.warmup} --no-cpu-baseline")
+    if batched:
+        wl_name = "batched_64_scenes"
+    else:
+        wl_name = {"billboards": "billboards_200000_tris_1920x1080"}.get(args.workload)
+        if wl_name is None:
+            from paper_1912_12786_amd import workloads as W
+            wl_name = {"tiny": W.tiny, "spheres": W.spheres}[args.workload]().name
+    flags = (f"--workload {args.workload}" + ("" if batched else f" --intersector {kind} "
+             f"--query {args.query} --ray-order {args.ray_order}")
+             + f" --layout {args.layout} --max-leaf {args.max_leaf}"
+             + (f" --shape {args.shape}" if args.shape else ""))
+    base = f"python3 bench.py {flags} --steps {args.steps} --warmup {args.warmup} --no-cpu-baseline"
     pmc = "rocprofv3 --pmc {} --output-format csv -d <out>/{} -o bench -- "
     rec = {
-        "kernel_source_sha": kernel_source_sha(),
+        "kernel_source_sha": sha,
         "config": {"workload": wl_name, "intersector": kind, "query": args.query,
                    "layout": args.layout, "max_leaf": args.max_leaf, "launch_shape": shape,
                    "ray_order": args.ray_order},
-        "dispatches": {"fetch": fetch["n"], "write": write["n"], "issue": issue["n"]},
-        "fetch_kib_per_dispatch": round(fetch["FETCH_SIZE"], 2),
-        "write_kib_per_dispatch": round(write["WRITE_SIZE"], 2),
-        "copy_calibration": {"bytes_copied": COPY_BYTES, "fetch_kib": round(cf["FETCH_SIZE"], 2),
-                             "write_kib": round(cw["WRITE_SIZE"], 2),
-                             "fetch_factor": round(f_fac, 5), "write_factor": round(w_fac, 5)},
-        "traffic_bytes_per_launch": int(round(traffic)),
+        "kernel": f"trace_kernel<{isect}, {res}{tail}",
+        "dispatches": {"issue": issue["n"]},
         "ta_busy_frac": round(ta_busy, 4),
         "limiter": "vmem_issue",
         "vmem_rd_wave_instr": int(round(issue["SQ_INSTS_VMEM_RD"])),
@@ -243,15 +270,33 @@ def ingest_counters(args, directory: str):
         "valu_lane_utilisation": round(lane_util, 4),
         "waves": int(round(issue["SQ_WAVES"])),
         "gpu_active_cycles_per_xcd": int(round(grbm / 8)),
-        "commands": {
+        "commands": {"issue": pmc.format(" ".join(ISSUE_COUNTERS), "issue") + base},
+    }
+    if have("fetch") and have("write") and have("copy_fetch") and have("copy_write"):
+        fetch = _per_dispatch(_counter_rows(os.path.join(directory, "fetch")), trace_kernel, n)
+        write = _per_dispatch(_counter_rows(os.path.join(directory, "write")), trace_kernel, n)
+        cf = _per_dispatch(_counter_rows(os.path.join(directory, "copy_fetch")), copy_kernel)
+        cw = _per_dispatch(_counter_rows(os.path.join(directory, "copy_write")), copy_kernel)
+        f_fac = COPY_BYTES / (cf["FETCH_SIZE"] * 1024)
+        w_fac = COPY_BYTES / (cw["WRITE_SIZE"] * 1024)
+        traffic = fetch["FETCH_SIZE"] * 1024 * f_fac + write["WRITE_SIZE"] * 1024 * w_fac
+        rec["dispatches"].update(fetch=fetch["n"], write=write["n"])
+        rec.update({
+            "fetch_kib_per_dispatch": round(fetch["FETCH_SIZE"], 2),
+            "write_kib_per_dispatch": round(write["WRITE_SIZE"], 2),
+            "copy_calibration": {"bytes_copied": COPY_BYTES, "fetch_kib": round(cf["FETCH_SIZE"], 2),
+                                 "write_kib": round(cw["WRITE_SIZE"], 2),
+                                 "fetch_factor": round(f_fac, 5), "write_factor": round(w_fac, 5)},
+            "traffic_bytes_per_launch": int(round(traffic)),
+        })
+        rec["commands"].update({
             "fetch": pmc.format("FETCH_SIZE", "fetch") + base,
             "write": pmc.format("WRITE_SIZE", "write") + base,
-            "issue": pmc.format(" ".join(ISSUE_COUNTERS), "issue") + base,
             "copy_fetch": pmc.format("FETCH_SIZE", "copy_fetch") + "python3 bench.py --copy-calibration",
             "copy_write": pmc.format("WRITE_SIZE", "copy_write") + "python3 bench.py --copy-calibration",
-            "ingest": f"python3 bench.py --ingest-counters <out> " + base.split(" ", 2)[2],
-        },
-    }
+        })
+    rec["commands"]["ingest"] = (f"python3 bench.py --ingest-counters <out> {flags} "
+                                 f"--steps {args.steps} --warmup {args.warmup}")
     name = (f"counters_{args.workload}_{kind}_{args.query}_{args.layout}_leaf{args.max_leaf}_"
             f"{'x'.join(map(str, shape))}_{args.ray_order}.json")
     with open(os.path.join(PROFILES, name), "w") as f:
@@ -434,7 +479,8 @@ def bench_batched(args):
     """64 scenes of uneven size (5.1M triangles, 19.9M rays in total), default
     intersector, closest hit: one batched persistent launch (eager and replayed
     from a captured graph) against 64 separate per-scene launches (eager and
-    graph-replayed).  The batched launch's shape is picked by the autotuner."""
+    graph-replayed).  The batched launch's shape is picked by the autotuner
+    unless --shape names one."""
     import torch
     from paper_1912_12786_amd import autotune, rtx
     from paper_1912_12786_amd import workloads as W
@@ -467,8 +513,11 @@ def bench_batched(args):
             if r.shape[0]:
                 rtx.trace(sc, r, "default", out=o, workspace=ws)
 
-    best, tune_ms = autotune.tune("batched-64-scenes-default", batched, cache_path=None,
-                                  steps=3, warmup=1)
+    if args.shape:   # a given shape skips the autotuner
+        best, tune_ms = parse_shape(args.shape), None
+    else:
+        best, tune_ms = autotune.tune("batched-64-scenes-default", batched, cache_path=None,
+                                      steps=3, warmup=1)
     # grow the workspace to the largest need before any capture
     ws.get(max(rtx.rt_trace_batch_workspace_bytes(batch.info, rtx.shape_flag(best)),
                max(rtx.rt_trace_workspace_bytes(sc.view, c) for sc, c in zip(sc_list, counts))))
@@ -829,6 +878,11 @@ def main():
             "kernel_ms_median": round(float(np.median(per_launch_ms)), 4),
             "kernel_ms_p10_p90": [round(float(np.percentile(per_launch_ms, 10)), 4),
                                   round(float(np.percentile(per_launch_ms, 90)), 4)],
+            # launches that took over 1.5x the median (position in the timed
+            # run, ms): HIP events bracket each launch, so a host-side delay
+            # before the launch is enqueued shows here
+            "slow_launches": [[int(i), round(float(per_launch_ms[i]), 3)] for i in
+                              np.nonzero(per_launch_ms > 1.5 * np.median(per_launch_ms))[0]],
             "algorithmic_bytes_per_launch": alg_bytes,
             "bytes_per_ray_mean": round(alg_bytes / wl.n_rays, 1),
             "mean_counts_per_ray": {"box_tests": round(float(mean_c[0]), 2),
