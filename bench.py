@@ -681,6 +681,11 @@ def main():
                          "four-wide nodes with float32 boxes (rt_bvh_widen). Default: q8 for the "
                          "spheres and batched workloads (measured faster: BVHs beyond the "
                          "caches), f32 otherwise")
+    ap.add_argument("--schedule", default="tiles", choices=["tiles", "index"],
+                    help="tiles: the image's rays are handed to lanes in 8x8 pixel tiles "
+                         "(RT_FLAG_TILE_WIDTH; results and their order unchanged); index: in "
+                         "ray-index order. Applies to the billboards, tiny and spheres "
+                         "workloads (the spheres' primary rays)")
     ap.add_argument("--query", default="closest", choices=["closest", "any", "multi"])
     ap.add_argument("--k", type=int, default=4, help="hits kept per ray by --query multi")
     ap.add_argument("--workload", default="billboards",
@@ -776,13 +781,16 @@ def main():
         log(f"autotuner: multi-hit launch shape {args.shape}")
 
     shape = parse_shape(args.shape)
+    # rays in scanline order over an image: lanes may take them in tiles
+    width = int(wl.extra["width"]) if (args.schedule == "tiles" and args.ray_order == "scanline"
+                                       and "width" in wl.extra) else None
 
-    def time_launches(r, o):
+    def time_launches(r, o, image_width=width):
         """(per-launch ms from HIP events on the launch stream, wall s) of
         args.steps launches over rays r into o, after args.warmup."""
         def step():
             rtx.trace(scene, r, kind, query=query, k=args.k, alpha_min=128, out=o, workspace=ws,
-                      shape=shape)
+                      shape=shape, image_width=image_width)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -807,7 +815,7 @@ def main():
         n_p = int(wl.extra["n_primary"])
         split = {}
         for name, sl in (("primary", slice(0, n_p)), ("bounce", slice(n_p, wl.n_rays))):
-            ms, _ = time_launches(rays[sl], hits[sl])
+            ms, _ = time_launches(rays[sl], hits[sl], width if name == "primary" else None)
             split[name] = {"n_rays": sl.stop - sl.start, "kernel_ms_median": round(float(np.median(ms)), 4),
                            "mrays_s": round((sl.stop - sl.start) / float(np.median(ms)) / 1e3, 2)}
 
@@ -863,6 +871,8 @@ def main():
             "textures": "16 x 256x256 RGBA8" if wl.textures is not None else None,
             "ray_order": {"tiled": "8x8 tiles", "morton": "8x8 tiles, Z-order inside"}.get(
                 args.ray_order, "scanline"),
+            "schedule": (f"lanes take the rays in 8x8 pixel tiles of the {width}-wide image"
+                         if width else "lanes take the rays in index order"),
             "bvh": (f"binary SAH, leaves of <= {args.max_leaf} triangles, {scene.info.n_nodes} "
                     f"inner nodes, depth {scene.info.max_depth}"),
             "max_leaf": args.max_leaf,

@@ -107,6 +107,20 @@ typedef enum rt_isect_kind {
 #define RT_FLAG_SHAPE_MASK 0xFF00u
 #define RT_FLAG_SHAPE(index) ((((uint32_t)(index)) << RT_FLAG_SHAPE_SHIFT) & RT_FLAG_SHAPE_MASK)
 
+/* Tiled schedule (a hint for rays that form an image in scanline order, such
+ * as a camera's primary rays): bits 16..27 of flags hold W/8 for an image W
+ * pixels wide (W a multiple of 8, at most 32760).  Rays are then handed to the
+ * GPU's lanes in 8 x 8 pixel tiles instead of in index order: the first
+ * 8 * W * floor(n_rays / (8 W)) rays (whole rows of tiles) are taken tile by
+ * tile, the rest in index order.  Only which lanes trace which rays, and
+ * when, changes: every ray's result and counters, and where they are written
+ * (at the ray's index), are those of the untiled call.  Single-scene calls
+ * (rt_trace_closest, rt_trace_closest_noalloc, rt_trace_any, rt_trace_multi)
+ * take it; an image wider than 32760 is RT_ERR_INVALID_ARG. */
+#define RT_FLAG_TILE_SHIFT 16u
+#define RT_FLAG_TILE_MASK 0x0FFF0000u
+#define RT_FLAG_TILE_WIDTH(width) ((((uint32_t)(width) / 8u) << RT_FLAG_TILE_SHIFT) & RT_FLAG_TILE_MASK)
+
 /* Alpha-mask intersector (Listing 5).  For a candidate (prim, u, v):
  *   (s, t) = (1-u-v) tc[prim][0] + u tc[prim][1] + v tc[prim][2],
  *   texel  = nearest texel (clamp to edge) of texture geom_id(prim),

@@ -93,6 +93,7 @@ struct TraceRequest {
     void *spill;        // workspace past the queue head
     void *queue;        // queue head (queue shapes)
     LaunchShape shape;
+    uint32_t tile_w8;   // tiled schedule: image width / 8 (0: index order)
     void *stream;
 };
 

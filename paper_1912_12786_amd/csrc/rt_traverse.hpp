@@ -580,7 +580,20 @@ struct kernel_args {
     const unsigned char *batch;  // batched launch: the scene table (else null)
     uint64_t *spill;     // [spill entries][gridDim.x * kBlock]
     uint32_t *queue;     // kQueueHeads work-queue heads, kQueueStride apart, zero at launch
+    uint32_t tile_w8;    // tiled schedule: image width / 8 (0: rays in index order)
+    uint32_t tiled;      // rays [0, tiled) are whole rows of 8 x 8 tiles
 };
+
+// The ray a lane takes for schedule position `pos`: in a tiled schedule,
+// position 64 c + j of the first `tiled` rays is pixel j (row-major) of
+// tile c, tiles numbered row-major over an image a.tile_w8 tiles wide.
+__device__ __forceinline__ uint32_t scheduled_ray(const kernel_args &a, uint32_t pos)
+{
+    if (a.tile_w8 == 0 || pos >= a.tiled) return pos;
+    const uint32_t c = pos >> 6, j = pos & 63u;
+    const uint32_t ty = c / a.tile_w8, tx = c - ty * a.tile_w8;
+    return ((ty << 3) + (j >> 3)) * (a.tile_w8 << 3) + (tx << 3) + (j & 7u);
+}
 
 // Work-queue heads of a persistent launch: one per XCD (MI355X has 8), each
 // in its own 128-byte cache line.
@@ -772,8 +785,8 @@ void trace_kernel(kernel_args a, typename Isect::params p)
         if (feed.refill(idle, a.n_rays, a.queue)) {
             const uint32_t id = feed.take(idle, lanes_below);
             if (!active && id < feed.end) {
-                ray_id = id;
-                r = make_ray(a.rays[2 * size_t(id)], a.rays[2 * size_t(id) + 1]);
+                ray_id = scheduled_ray(a, id);
+                r = make_ray(a.rays[2 * size_t(ray_id)], a.rays[2 * size_t(ray_id) + 1]);
                 if constexpr (kBatched) {
                     const uint32_t n_scenes = *reinterpret_cast<const uint32_t *>(a.batch);
                     const uint32_t *prefix =

@@ -27,7 +27,7 @@ thread_local std::string g_last_error;
 // Flag bits every single-scene trace call knows: the intersector options and
 // the launch-shape field.
 constexpr uint32_t kKnownFlags = RT_FLAG_COUNT | RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL |
-                                 RT_FLAG_SHAPE_MASK;
+                                 RT_FLAG_SHAPE_MASK | RT_FLAG_TILE_MASK;
 
 rt_status fail(rt_status s, const std::string &msg)
 {
@@ -164,6 +164,9 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     }
     TraceRequest q;
     q.runtime_dispatch = runtime == RT_FLAG_RUNTIME_SWITCH ? 1u : (runtime ? 2u : 0u);
+    q.tile_w8 = (flags & RT_FLAG_TILE_MASK) >> RT_FLAG_TILE_SHIFT;
+    if (q.tile_w8 && batch)
+        return fail(RT_ERR_UNSUPPORTED, "the tiled schedule is for single-scene calls");
     if (batch) {  // per-scene data was validated by rt_batch_pack
         q.kind = kind;
         std::memset(&q.alpha, 0, sizeof q.alpha);

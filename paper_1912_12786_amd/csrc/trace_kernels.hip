@@ -256,6 +256,11 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
     a.batch = static_cast<const unsigned char *>(q.batch);
     a.spill = static_cast<uint64_t *>(q.spill);
     a.queue = static_cast<uint32_t *>(q.queue);
+    if (q.tile_w8) {  // whole rows of 8 x 8 tiles of an image 8 tile_w8 wide
+        const uint64_t per_row = 64ull * q.tile_w8;
+        a.tile_w8 = q.tile_w8;
+        a.tiled = uint32_t(uint64_t(q.n_rays) / per_row * per_row);
+    }
 
     const LaunchShape &sh = q.shape;
     // 32-byte nodes: compiled for the default launch shape only

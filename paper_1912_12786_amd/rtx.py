@@ -28,6 +28,8 @@ RT_FLAG_RUNTIME_SWITCH = 2
 RT_FLAG_RUNTIME_CALL = 4
 RT_FLAG_SHAPE_SHIFT = 8
 RT_FLAG_SHAPE_MASK = 0xFF00
+RT_FLAG_TILE_SHIFT = 16
+RT_FLAG_TILE_MASK = 0x0FFF0000
 RT_NODE_BYTES = 64
 RT_NODE_BYTES_Q8 = 32
 RT_NODE_BYTES_WIDE4 = 128
@@ -621,9 +623,20 @@ class Workspace:
         return self.buf.data_ptr(), int(self.buf.numel())
 
 
+def tile_flag(image_width: int | None) -> int:
+    """Flag bits of the tiled schedule for rays forming an image of this
+    width in scanline order (None or 0: index order)."""
+    if not image_width:
+        return 0
+    if image_width % 8 or not 0 < image_width <= 8 * 0xFFF:
+        raise ValueError("tiled schedule: image width must be a multiple of 8, at most 32760")
+    return (image_width // 8) << RT_FLAG_TILE_SHIFT
+
+
 def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "closest",
           count: bool = False, alpha_min: int = 128, checker_n: int = 8, k: int = 4, out=None,
-          counters=None, workspace: Workspace | None = None, stream=None, shape=None):
+          counters=None, workspace: Workspace | None = None, stream=None, shape=None,
+          image_width: int | None = None):
     """Traces device rays ``float32 [N, 8]``.
 
     closest: returns ``hits float32 [N, 4]`` = (t, prim_id bits, u, v); view
@@ -633,22 +646,25 @@ def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "clo
     tests, triangle tests, candidates, accepted).  ``shape``: launch shape of
     this call (see :func:`shape_flag`; None = the library's default).
     ``stream``: a raw hipStream_t to launch on instead of torch's current
-    stream; the tensors allocated here are then allocated on that stream."""
+    stream; the tensors allocated here are then allocated on that stream.
+    ``image_width``: the rays are an image of this width in scanline order;
+    lanes then take them in 8 x 8 tiles (same results, see
+    ``RT_FLAG_TILE_WIDTH``)."""
     torch = _torch()
     if rays.dtype != torch.float32 or rays.dim() != 2 or rays.shape[1] != 8 or not rays.is_contiguous():
         raise ValueError("rays must be a contiguous float32 [N, 8] tensor")
     with _on_stream(rays.device, stream) as s:
         return _trace_on(scene, rays, intersector, query, count, alpha_min, checker_n, k, out,
-                         counters, workspace, s, shape)
+                         counters, workspace, s, shape, image_width)
 
 
 def _trace_on(scene, rays, intersector, query, count, alpha_min, checker_n, k, out, counters,
-              workspace, s, shape):
+              workspace, s, shape, image_width=None):
     torch = _torch()
     n = int(rays.shape[0])
     dev = rays.device
     params = _params(scene, intersector, alpha_min, checker_n)
-    flags = (RT_FLAG_COUNT if count else 0) | shape_flag(shape)
+    flags = (RT_FLAG_COUNT if count else 0) | shape_flag(shape) | tile_flag(image_width)
     sc = scene.view
     if query == "closest":
         if out is None:

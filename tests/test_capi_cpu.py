@@ -722,3 +722,17 @@ def test_widen_validation(lib):
     assert need > 1024
     # runtime dispatch is compiled for binary float32 nodes only
     assert _closest(lib, sc, flags=rtx.RT_FLAG_RUNTIME_SWITCH, ws=0x80000, wsb=need) == -3
+
+
+def test_tile_flag(lib):
+    assert rtx.tile_flag(None) == 0 and rtx.tile_flag(1920) == 240 << 16
+    for bad in (12, 32768, -8):
+        with pytest.raises(ValueError):
+            rtx.tile_flag(bad)
+    # accepted by the single-scene calls' validation, refused by the batched
+    # and instanced launches
+    sc = _fake_scene()
+    assert _closest(lib, sc, n=0, flags=rtx.tile_flag(1920)) == 0
+    info = rtx.rt_batch_info()
+    assert lib.rt_trace_batch(0x10000, C.byref(info), 0x30000, 0, None, rtx.tile_flag(1920),
+                              0x40000, None, None, 0, None) == -3

@@ -1,0 +1,113 @@
+"""The tiled schedule (RT_FLAG_TILE_WIDTH: lanes take the rays of an image in
+8 x 8 pixel tiles) changes only which lanes trace which rays: every result
+and counter, at its ray's index, equals the call in index order, for every
+query, node layout and entry point, including ray counts that end inside a
+row of tiles; a sentinel-filled output shows that every ray is traced once."""
+import numpy as np
+import pytest
+
+from paper_1912_12786_amd import workloads as W
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1912_12786_amd import rtx
+    rtx.load_library()
+    return torch, rtx
+
+
+def same_bits(a, b):
+    import torch
+    return a.shape == b.shape and torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+@pytest.fixture(scope="module")
+def billboards(env):
+    torch, rtx = env
+    wl = W.billboards()
+    scenes = {layout: rtx.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures,
+                                       max_leaf=2, layout=layout)
+              for layout in ("f32", "q8", "wide4")}
+    return wl, scenes, torch.from_numpy(wl.rays).cuda()
+
+
+@pytest.mark.parametrize("layout", ["f32", "q8", "wide4"])
+def test_tiled_schedule_matches_index_order(env, billboards, layout):
+    torch, rtx = env
+    wl, scenes, rays = billboards
+    sc = scenes[layout]
+    for query in ("closest", "any", "multi"):
+        announce(f"billboards alpha {layout} {query}: tiles of the 1920-wide image vs index order")
+        ref, rc = rtx.trace(sc, rays, "alpha", query=query, k=2, count=True, alpha_min=128)
+        if query == "closest":
+            out = torch.full((wl.n_rays, 4), 7.0, device="cuda")
+            got, gc = rtx.trace(sc, rays, "alpha", query=query, count=True, alpha_min=128,
+                                out=out, image_width=1920)
+        else:
+            got, gc = rtx.trace(sc, rays, "alpha", query=query, k=2, count=True, alpha_min=128,
+                                image_width=1920)
+        torch.cuda.synchronize()
+        if query == "multi":
+            assert same_bits(got[0], ref[0]) and same_bits(got[1], ref[1])
+        else:
+            assert same_bits(got, ref)
+        assert same_bits(gc, rc)
+
+
+@pytest.mark.parametrize("n,width", [(2_073_600 - 1234, 1920), (2_073_600, 1912), (200, 8),
+                                     (100, 24), (64 * 64, 64)])
+def test_tiled_schedule_partial_rows(env, oracle_lib, billboards, n, width):
+    """Ray counts that end inside a row of tiles, widths that do not divide
+    the count, and fewer rays than one row of tiles: the tiled part is the
+    whole rows of tiles, the rest keeps index order; the result equals index
+    order and oracle B."""
+    torch, rtx = env
+    wl, scenes, rays = billboards
+    announce(f"tiled schedule n={n} width={width}")
+    r = rays[:n].contiguous()
+    out = torch.full((n, 4), 7.0, device="cuda")
+    got, gc = rtx.trace(scenes["f32"], r, "alpha", count=True, alpha_min=128, out=out,
+                        image_width=width)
+    ref, rc = rtx.trace(scenes["f32"], r, "alpha", count=True, alpha_min=128)
+    torch.cuda.synchronize()
+    assert same_bits(got, ref) and same_bits(gc, rc)
+    if n <= 5000:
+        okw = dict(geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures,
+                   alpha_min=128)
+        B = oracle_lib.traverse(wl.vertices, oracle_lib.build_bvh(wl.vertices, max_leaf=2),
+                                wl.rays[:n], "alpha", **okw)
+        P.assert_exact_vs_b(P.hits_to_numpy(got), B, f"tiled n={n}")
+        P.assert_counters_vs_b(gc, B, f"tiled n={n}")
+
+
+def test_tiled_schedule_noalloc_and_spheres(env):
+    """The allocation-free entry point with the tile flag, and the spheres'
+    primary rays tiled while their bounce rays keep index order."""
+    torch, rtx = env
+    wl = W.spheres()
+    sc = rtx.upload_scene(wl.vertices, layout="q8", max_leaf=2)
+    rays = torch.from_numpy(wl.rays).cuda()
+    announce("spheres procedural, tiled primary rays")
+    ref = rtx.trace(sc, rays, "procedural", checker_n=8)
+    got = rtx.trace(sc, rays, "procedural", checker_n=8, image_width=1920)
+    torch.cuda.synchronize()
+    assert same_bits(got, ref)
+    tw = W.tiny()
+    tsc = rtx.upload_scene(tw.vertices)
+    trays = torch.from_numpy(tw.rays).cuda()
+    announce("noalloc tiny, tiled 64-wide image")
+    h = torch.full((tw.n_rays, 4), 7.0, device="cuda")
+    rtx.rt_trace_closest_noalloc(tsc.view, trays.data_ptr(), tw.n_rays, 0, None,
+                                 rtx.tile_flag(64), h.data_ptr(), None,
+                                 torch.cuda.current_stream().cuda_stream)
+    ref = rtx.trace(tsc, trays)
+    torch.cuda.synchronize()
+    assert same_bits(h, ref)
