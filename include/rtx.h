@@ -97,6 +97,21 @@ typedef enum rt_isect_kind {
 #define RT_FLAG_RUNTIME_SWITCH 0x2u
 #define RT_FLAG_RUNTIME_CALL 0x4u
 
+/* Longest-path-first schedule: before the traversal, the rays are grouped in
+ * the chunks that lanes take (64 rays in the default launch shape: tiles of
+ * the tiled schedule, or runs of consecutive rays), each chunk is keyed by
+ * the longest stretch inside the scene box of the intervals [tmin, tmax] of
+ * four of its rays, the ends of its first and last runs of 8 (the corners of
+ * an 8 x 8 tile), in 64 steps of the box diagonal, and the chunks are handed
+ * out in decreasing key order.  A ray's work grows with the length of scene it crosses, and the
+ * launch ends when its last and longest rays do, so starting the long ones
+ * first shortens the tail.  Only the schedule changes: every ray's result,
+ * counters and output position are those of the call without it.  The
+ * workspace grows by 8 bytes per chunk plus 512 (rt_trace_workspace_bytes
+ * with the same flags); single-scene calls only (RT_ERR_UNSUPPORTED for
+ * batches). */
+#define RT_FLAG_LONGEST_FIRST 0x8u
+
 /* Launch shape of one call: bits 8..15 of flags hold an index into the table
  * that rt_launch_shapes lists (0, the default, when the field is clear).  The
  * shape is chosen per call, so calls on different threads or streams may use

@@ -112,12 +112,15 @@ def _store(cache_path, cache):
 def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_ids=None,
                texcoords=None, textures=None, alpha_min: int = 128, checker_n: int = 8,
                leaf_sizes=(2, 3, 4), layouts=("f32", "q8", "wide4"),
-               cache_path: str | None = DEFAULT_CACHE,
+               cache_path: str | None = DEFAULT_CACHE, longest_first=(False, True),
+               image_width: int | None = None,
                steps: int = 5, warmup: int = 1, retune: bool = False, device="cuda"):
-    """Chooses the BVH leaf size, node layout and launch shape that trace
-    ``rays`` (device float32 [N, 8], closest hit) fastest through the scene,
-    and returns ``(scene, choice)``: the scene built that way and
-    ``{"max_leaf", "layout", "shape", "ms"}``; pass ``choice["shape"]`` to the
+    """Chooses the BVH leaf size, node layout, launch shape and chunk order
+    (index or longest-path-first) that trace ``rays`` (device float32 [N, 8],
+    closest hit; an image of ``image_width`` in scanline order when given)
+    fastest through the scene, and returns ``(scene, choice)``: the scene
+    built that way and ``{"max_leaf", "layout", "shape", "longest_first",
+    "ms"}``; pass ``choice["shape"]`` and ``choice["longest_first"]`` to the
     trace calls.  A cached choice for this device and key is reused unless
     ``retune``."""
     import torch
@@ -140,14 +143,19 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
         for max_leaf in leaf_sizes:
             for layout in layouts:
                 scene = build(max_leaf, layout)
-                t = time_shapes(lambda sh: rtx.trace(scene, rays, intersector, out=out, workspace=ws,
-                                                     shape=sh, **kw), steps, warmup)
-                for shape, ms in t.items():
-                    timings[(int(max_leaf), layout, shape)] = ms
+                for lf in longest_first:
+                    t = time_shapes(lambda sh: rtx.trace(scene, rays, intersector, out=out,
+                                                         workspace=ws, shape=sh,
+                                                         image_width=image_width,
+                                                         longest_first=lf, **kw), steps, warmup)
+                    for shape, ms in t.items():
+                        timings[(int(max_leaf), layout, shape, bool(lf))] = ms
                 del scene
         best = min(timings, key=timings.get)
         choice = {"max_leaf": best[0], "layout": best[1], "shape": list(best[2]),
-                  "ms": {f"{k[0]}/{k[1]}/{','.join(map(str, k[2]))}": v for k, v in timings.items()}}
+                  "longest_first": best[3],
+                  "ms": {f"{k[0]}/{k[1]}/{','.join(map(str, k[2]))}/{'lf' if k[3] else 'index'}": v
+                         for k, v in timings.items()}}
         if cache_path:
             cache.setdefault(dev_name, {})[key] = choice
             _store(cache_path, cache)

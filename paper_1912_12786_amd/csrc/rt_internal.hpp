@@ -94,6 +94,7 @@ struct TraceRequest {
     void *queue;        // queue head (queue shapes)
     LaunchShape shape;
     uint32_t tile_w8;   // tiled schedule: image width / 8 (0: index order)
+    void *order;        // longest-path-first: the chunk-order area (else null)
     void *stream;
 };
 
@@ -115,9 +116,18 @@ inline uint64_t launch_threads(uint32_t n_rays, const LaunchShape &s)
 }
 
 // Workspace bytes of a single-scene launch of n_rays rays in shape s.
-inline size_t workspace_for(const rt_bvh_info &info, uint32_t n_rays, const LaunchShape &s)
+// Chunk-order area of a longest-path-first launch: a key and an order entry
+// per chunk (chunks of s.chunk rays), then 64 bucket counts and 64 cursors.
+inline size_t order_bytes(uint32_t n_rays, const LaunchShape &s)
 {
-    return (s.queue ? kQueueBytes : 0) +
+    const size_t n_chunks = (size_t(n_rays) + s.chunk - 1) / s.chunk;
+    return (8 * n_chunks + 512 + 15) / 16 * 16;
+}
+
+inline size_t workspace_for(const rt_bvh_info &info, uint32_t n_rays, const LaunchShape &s,
+                            bool longest_first = false)
+{
+    return (s.queue ? kQueueBytes : 0) + (longest_first ? order_bytes(n_rays, s) : 0) +
            size_t(spill_entries(info, s)) * size_t(launch_threads(n_rays, s)) * sizeof(uint64_t);
 }
 

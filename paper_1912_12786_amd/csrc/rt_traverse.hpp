@@ -582,6 +582,7 @@ struct kernel_args {
     uint32_t *queue;     // kQueueHeads work-queue heads, kQueueStride apart, zero at launch
     uint32_t tile_w8;    // tiled schedule: image width / 8 (0: rays in index order)
     uint32_t tiled;      // rays [0, tiled) are whole rows of 8 x 8 tiles
+    const uint32_t *order;  // longest-path-first: chunk to take at each position (else null)
 };
 
 // The ray a lane takes for schedule position `pos`: in a tiled schedule,
@@ -675,12 +676,25 @@ struct ray_feed {
     bool drained;  // no further chunk will come
     uint32_t head, dead_heads;
 
-    __device__ __forceinline__ ray_feed(uint32_t n_rays, uint32_t gtid)
+    // The rays of the chunk at schedule position c (the chunk itself, or the
+    // one a longest-path-first order puts there).
+    __device__ __forceinline__ void set_chunk(uint32_t c, uint32_t n_rays, const uint32_t *order)
     {
-        // every wave's first chunk is static (chunk index = wave index), so a
-        // queue launch does not start with every wave on an atomic
-        next = (gtid / 64) * uint32_t(kChunk);
+        if (order) c = order[c];
+        next = c * uint32_t(kChunk);
         end = min(next + uint32_t(kChunk), n_rays);
+    }
+
+    __device__ __forceinline__ ray_feed(uint32_t n_rays, uint32_t gtid, const uint32_t *order)
+    {
+        // every wave's first chunk is static (position = wave index), so a
+        // queue launch does not start with every wave on an atomic
+        const uint32_t c = gtid / 64;
+        if (c * uint64_t(kChunk) < n_rays) {
+            set_chunk(c, n_rays, order);
+        } else {
+            next = end = 0;
+        }
         drained = !kQueue;
         head = blockIdx.x % kQueueHeads;
         dead_heads = 0;
@@ -689,7 +703,8 @@ struct ray_feed {
     // Wave-wide, with the wave's idle-lane mask: makes sure the chunk holds
     // rays (drawing a new chunk from the queue if needed); false if none are
     // left for now.
-    __device__ __forceinline__ bool refill(uint64_t idle, uint32_t n_rays, uint32_t *queue)
+    __device__ __forceinline__ bool refill(uint64_t idle, uint32_t n_rays, uint32_t *queue,
+                                          const uint32_t *order)
     {
         if constexpr (kQueue) {
             if (idle != 0 && next >= end && !drained) {
@@ -701,8 +716,7 @@ struct ray_feed {
                     k = __builtin_amdgcn_readfirstlane(k);
                     const uint64_t chunk = uint64_t(first_dynamic) + head + uint64_t(kQueueHeads) * k;
                     if (chunk < n_chunks) {
-                        next = uint32_t(chunk) * uint32_t(kChunk);
-                        end = min(next + uint32_t(kChunk), n_rays);
+                        set_chunk(uint32_t(chunk), n_rays, order);
                         break;
                     }
                     dead_heads |= 1u << head;
@@ -761,7 +775,7 @@ void trace_kernel(kernel_args a, typename Isect::params p)
     const uint32_t lane = __lane_id();
     const uint64_t lanes_below = (uint64_t(1) << lane) - 1;
 
-    ray_feed<kBlock, kChunk, kQueue> feed(a.n_rays, gtid);
+    ray_feed<kBlock, kChunk, kQueue> feed(a.n_rays, gtid, a.order);
 
     ring_stack<kSlots, kBlock> st{ring, (global_ptr<uint64_t>)(a.spill + gtid), tid,
                                   gridDim.x * uint32_t(kBlock)};
@@ -782,7 +796,7 @@ void trace_kernel(kernel_args a, typename Isect::params p)
 
     for (;;) {
         const uint64_t idle = __ballot(!active);
-        if (feed.refill(idle, a.n_rays, a.queue)) {
+        if (feed.refill(idle, a.n_rays, a.queue, a.order)) {
             const uint32_t id = feed.take(idle, lanes_below);
             if (!active && id < feed.end) {
                 ray_id = scheduled_ray(a, id);
@@ -971,6 +985,101 @@ __global__ __launch_bounds__(64) void trace_instanced_kernel(kernel_args a, cons
 static __global__ void reset_queue_kernel(uint32_t *queue)
 {
     if (threadIdx.x < kQueueHeads) queue[threadIdx.x * kQueueStride] = 0;
+}
+
+// -------------------------------------------------------------------------
+// longest-path-first chunk order (three small kernels before the traversal)
+// area: keys[n_chunks], order[n_chunks], counts[64], cursors[64]
+// -------------------------------------------------------------------------
+constexpr uint32_t kOrderBuckets = 64;
+
+// Zeroes the bucket counts and cursors.
+static __global__ void order_clear_kernel(uint32_t *counts)
+{
+    if (threadIdx.x < 2 * kOrderBuckets) counts[threadIdx.x] = 0;
+}
+
+// Four lanes per chunk (blocks of kOrderKeysBlock threads): the chunk's key
+// is 63 minus the bucket (64 steps of the scene box's diagonal) of the
+// longest interval stretch inside the box among four of its rays, the ends
+// of its first and last runs of 8 (the corners of an 8 x 8 tile), so that
+// sorting keys ascending puts long chunks first.  counts[key] tallies the
+// chunks per key through a block-level tally in LDS (one global atomic per
+// key and block: same-address atomics from every chunk serialize at the
+// L2).
+constexpr uint32_t kOrderKeysBlock = 1024;
+constexpr uint32_t kOrderSamples = 4;
+static __global__ __launch_bounds__(kOrderKeysBlock) void order_keys_kernel(
+    kernel_args a, uint32_t chunk, uint32_t n_chunks, float buckets_per_length, uint32_t *keys,
+    uint32_t *counts)
+{
+    __shared__ uint32_t tally[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) tally[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t c = (blockIdx.x * blockDim.x + threadIdx.x) / kOrderSamples;
+    const uint32_t sample = threadIdx.x % kOrderSamples;
+    // 0, 7, chunk - 8, chunk - 1 (chunks are multiples of 32 rays)
+    const uint32_t j = (sample & 2u ? chunk - 8u : 0u) + (sample & 1u ? 7u : 0u);
+    float len = 0.0f;
+    const uint32_t pos = c * chunk + j;
+    if (c < n_chunks && pos < a.n_rays) {
+        const uint32_t id = scheduled_ray(a, pos);
+        const ray_state r = make_ray(a.rays[2 * size_t(id)], a.rays[2 * size_t(id) + 1]);
+        float tn;
+        if (slab(r, a.sc.root_lo[0], a.sc.root_lo[1], a.sc.root_lo[2], a.sc.root_hi[0],
+                 a.sc.root_hi[1], a.sc.root_hi[2], tn)) {
+            const float tf = fminf(fminf(fminf(fmaxf(fmaf(a.sc.root_lo[0], r.ix, -r.bx),
+                                                     fmaf(a.sc.root_hi[0], r.ix, -r.bx)),
+                                               fmaxf(fmaf(a.sc.root_lo[1], r.iy, -r.by),
+                                                     fmaf(a.sc.root_hi[1], r.iy, -r.by))),
+                                         fmaxf(fmaf(a.sc.root_lo[2], r.iz, -r.bz),
+                                               fmaf(a.sc.root_hi[2], r.iz, -r.bz))),
+                                   r.tmax);
+            len = tf - tn;
+        }
+    }
+    for (uint32_t off = kOrderSamples / 2; off > 0; off >>= 1)
+        len = fmaxf(len, __shfl_xor(len, int(off)));
+    if (sample == 0 && c < n_chunks) {
+        const float q = fminf(len * buckets_per_length, float(kOrderBuckets - 1));
+        const uint32_t key = kOrderBuckets - 1 - (q >= 0.0f ? uint32_t(q) : 0u);
+        keys[c] = key;
+        atomicAdd(tally + key, 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets && tally[threadIdx.x] != 0)
+        atomicAdd(counts + threadIdx.x, tally[threadIdx.x]);
+}
+
+// Scatters the chunk indices into ascending key order: bucket bases from an
+// exclusive scan of the counts, per-block offsets from LDS tallies and one
+// global cursor reservation per bucket and block.
+static __global__ void order_scatter_kernel(uint32_t n_chunks, const uint32_t *keys,
+                                            uint32_t *order, uint32_t *counts)
+{
+    __shared__ uint32_t base[kOrderBuckets], tally[kOrderBuckets], reserved[kOrderBuckets];
+    const uint32_t t = threadIdx.x;
+    if (t < kOrderBuckets) {
+        uint32_t v = counts[t];
+        for (uint32_t off = 1; off < kOrderBuckets; off <<= 1) {
+            const uint32_t u = __shfl_up(v, off);
+            if (t >= off) v += u;
+        }
+        base[t] = v - counts[t];
+        tally[t] = 0;
+    }
+    __syncthreads();
+    const uint32_t c = blockIdx.x * blockDim.x + t;
+    uint32_t key = 0, mine = 0;
+    if (c < n_chunks) {
+        key = keys[c];
+        mine = atomicAdd(tally + key, 1u);
+    }
+    __syncthreads();
+    if (t < kOrderBuckets && tally[t] != 0)
+        reserved[t] = atomicAdd(counts + kOrderBuckets + t, tally[t]);
+    __syncthreads();
+    if (c < n_chunks) order[base[key] + reserved[key] + mine] = c;
 }
 
 }  // namespace rtx

@@ -27,7 +27,7 @@ thread_local std::string g_last_error;
 // Flag bits every single-scene trace call knows: the intersector options and
 // the launch-shape field.
 constexpr uint32_t kKnownFlags = RT_FLAG_COUNT | RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL |
-                                 RT_FLAG_SHAPE_MASK | RT_FLAG_TILE_MASK;
+                                 RT_FLAG_SHAPE_MASK | RT_FLAG_TILE_MASK | RT_FLAG_LONGEST_FIRST;
 
 rt_status fail(rt_status s, const std::string &msg)
 {
@@ -167,6 +167,9 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     q.tile_w8 = (flags & RT_FLAG_TILE_MASK) >> RT_FLAG_TILE_SHIFT;
     if (q.tile_w8 && batch)
         return fail(RT_ERR_UNSUPPORTED, "the tiled schedule is for single-scene calls");
+    const bool longest_first = (flags & RT_FLAG_LONGEST_FIRST) != 0;
+    if (longest_first && batch)
+        return fail(RT_ERR_UNSUPPORTED, "the longest-path-first schedule is for single-scene calls");
     if (batch) {  // per-scene data was validated by rt_batch_pack
         q.kind = kind;
         std::memset(&q.alpha, 0, sizeof q.alpha);
@@ -189,7 +192,7 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     const bool count = (flags & RT_FLAG_COUNT) != 0;
     if (count && !counters) return fail(RT_ERR_INVALID_ARG, "RT_FLAG_COUNT needs a counters array");
     if (count && !aligned(counters, 16)) return fail(RT_ERR_MISALIGNED, "counters not 16-byte aligned");
-    const size_t need = workspace_for(scene->info, n_rays, shape);
+    const size_t need = workspace_for(scene->info, n_rays, shape, longest_first);
     if (fixed_scratch) {  // the library's own scratch replaces the workspace
         if (need > RT_NOALLOC_SCRATCH_BYTES)
             return fail(RT_ERR_WORKSPACE,
@@ -220,8 +223,13 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     q.multi_k = query == Query::Multi ? multi_k : 1;
     q.counters = count ? counters : nullptr;
     q.batch = batch;
-    q.queue = shape.queue ? workspace : nullptr;
-    q.spill = shape.queue ? static_cast<char *>(workspace) + kQueueBytes : workspace;
+    // workspace: [queue heads][chunk-order area][spill columns]
+    char *w = static_cast<char *>(workspace);
+    q.queue = shape.queue ? w : nullptr;
+    w += shape.queue ? kQueueBytes : 0;
+    q.order = longest_first ? w : nullptr;
+    w += longest_first ? order_bytes(n_rays, shape) : 0;
+    q.spill = w;
     q.shape = shape;
     q.stream = stream;
     const char *err = "";
@@ -337,7 +345,7 @@ rt_status rt_trace_workspace_bytes(const rt_scene *scene, uint32_t n_rays, uint3
     LaunchShape shape;
     if (!shape_of(flags, shape)) return fail(RT_ERR_UNSUPPORTED, "launch shape index not compiled in");
     if (n_rays > RT_MAX_RAYS) return fail(RT_ERR_INVALID_ARG, "more than 2^31 rays in one call");
-    *bytes = workspace_for(scene->info, n_rays, shape);
+    *bytes = workspace_for(scene->info, n_rays, shape, (flags & RT_FLAG_LONGEST_FIRST) != 0);
     return RT_OK;
 }
 

@@ -26,6 +26,7 @@ RT_MISS = 0xFFFFFFFF
 RT_FLAG_COUNT = 1
 RT_FLAG_RUNTIME_SWITCH = 2
 RT_FLAG_RUNTIME_CALL = 4
+RT_FLAG_LONGEST_FIRST = 8
 RT_FLAG_SHAPE_SHIFT = 8
 RT_FLAG_SHAPE_MASK = 0xFF00
 RT_FLAG_TILE_SHIFT = 16
@@ -636,7 +637,7 @@ def tile_flag(image_width: int | None) -> int:
 def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "closest",
           count: bool = False, alpha_min: int = 128, checker_n: int = 8, k: int = 4, out=None,
           counters=None, workspace: Workspace | None = None, stream=None, shape=None,
-          image_width: int | None = None):
+          image_width: int | None = None, longest_first: bool = False):
     """Traces device rays ``float32 [N, 8]``.
 
     closest: returns ``hits float32 [N, 4]`` = (t, prim_id bits, u, v); view
@@ -649,22 +650,25 @@ def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "clo
     stream; the tensors allocated here are then allocated on that stream.
     ``image_width``: the rays are an image of this width in scanline order;
     lanes then take them in 8 x 8 tiles (same results, see
-    ``RT_FLAG_TILE_WIDTH``)."""
+    ``RT_FLAG_TILE_WIDTH``).  ``longest_first``: hand out the chunks of rays
+    that cross the most scene first (same results, see
+    ``RT_FLAG_LONGEST_FIRST``)."""
     torch = _torch()
     if rays.dtype != torch.float32 or rays.dim() != 2 or rays.shape[1] != 8 or not rays.is_contiguous():
         raise ValueError("rays must be a contiguous float32 [N, 8] tensor")
     with _on_stream(rays.device, stream) as s:
         return _trace_on(scene, rays, intersector, query, count, alpha_min, checker_n, k, out,
-                         counters, workspace, s, shape, image_width)
+                         counters, workspace, s, shape, image_width, longest_first)
 
 
 def _trace_on(scene, rays, intersector, query, count, alpha_min, checker_n, k, out, counters,
-              workspace, s, shape, image_width=None):
+              workspace, s, shape, image_width=None, longest_first=False):
     torch = _torch()
     n = int(rays.shape[0])
     dev = rays.device
     params = _params(scene, intersector, alpha_min, checker_n)
-    flags = (RT_FLAG_COUNT if count else 0) | shape_flag(shape) | tile_flag(image_width)
+    flags = ((RT_FLAG_COUNT if count else 0) | shape_flag(shape) | tile_flag(image_width)
+             | (RT_FLAG_LONGEST_FIRST if longest_first else 0))
     sc = scene.view
     if query == "closest":
         if out is None:

@@ -250,7 +250,8 @@ def test_validation_errors(lib):
     assert _closest(lib, sc, hits=None) == -1
     assert _closest(lib, sc, hits=0x40008) == -2
     assert _closest(lib, sc, kind=7) == -3
-    assert _closest(lib, sc, flags=8) == -3                          # unknown flag
+    assert _closest(lib, sc, flags=0x10) == -3                       # unknown flag
+    assert _closest(lib, sc, flags=rtx.RT_FLAG_LONGEST_FIRST) == -4  # needs its workspace
     assert _closest(lib, sc, flags=6) == -1                          # two runtime modes
     assert _closest(lib, sc, flags=3, counters=0x50000) == -3        # runtime + counting
     assert lib.rt_trace_any(C.byref(sc), 0x30000, 100, 0, None, 2, 0x40000, None, None, 0,
@@ -735,4 +736,20 @@ def test_tile_flag(lib):
     assert _closest(lib, sc, n=0, flags=rtx.tile_flag(1920)) == 0
     info = rtx.rt_batch_info()
     assert lib.rt_trace_batch(0x10000, C.byref(info), 0x30000, 0, None, rtx.tile_flag(1920),
+                              0x40000, None, None, 0, None) == -3
+
+
+def test_longest_first_workspace(lib):
+    """The longest-path-first schedule adds a key and an order entry per
+    chunk plus 512 bytes (bucket counts and cursors), rounded to 16."""
+    sc = _fake_scene(max_depth=3)
+    for shape in rtx.rt_launch_shapes():
+        f = rtx.shape_flag(tuple(shape))
+        for n in (1, 64, 65, 2_073_600):
+            plain = rtx.rt_trace_workspace_bytes(sc, n, f)
+            lf = rtx.rt_trace_workspace_bytes(sc, n, f | rtx.RT_FLAG_LONGEST_FIRST)
+            chunks = -(-n // shape[2])
+            assert lf - plain == (8 * chunks + 512 + 15) // 16 * 16
+    info = rtx.rt_batch_info()
+    assert lib.rt_trace_batch(0x10000, C.byref(info), 0x30000, 0, None, rtx.RT_FLAG_LONGEST_FIRST,
                               0x40000, None, None, 0, None) == -3

@@ -100,12 +100,13 @@ def test_tune_scene_chooses_a_build_and_shape(env, oracle_lib, tmp_path):
                                      leaf_sizes=(2, 4), steps=2, warmup=1, **ai)
     n_shapes = len(rtx.rt_launch_shapes())
     # f32 builds time every shape, compressed ones the default shape only,
-    # four-wide ones the default shape and its 16-slot variant
-    assert len(choice["ms"]) == 2 * (n_shapes + 1 + 2)
+    # four-wide ones the default shape and its 16-slot variant; each in index
+    # and longest-path-first chunk order
+    assert len(choice["ms"]) == 2 * 2 * (n_shapes + 1 + 2)
     assert sc.info.max_leaf == choice["max_leaf"]
     assert sc.info.layout == rtx.LAYOUTS[choice["layout"]]
     hits, cnt = rtx.trace(sc, rays, "alpha", count=True, alpha_min=128,
-                          shape=tuple(choice["shape"]))
+                          shape=tuple(choice["shape"]), longest_first=choice["longest_first"])
     torch.cuda.synchronize()
     bvh = oracle_lib.build_bvh(wl.vertices, max_leaf=choice["max_leaf"])
     B = oracle_lib.traverse(wl.vertices, bvh, wl.rays, "alpha", layout=choice["layout"],

@@ -111,3 +111,74 @@ def test_tiled_schedule_noalloc_and_spheres(env):
     ref = rtx.trace(tsc, trays)
     torch.cuda.synchronize()
     assert same_bits(h, ref)
+
+
+@pytest.mark.parametrize("layout", ["f32", "q8", "wide4"])
+def test_longest_first_matches_index_order(env, billboards, layout):
+    """Longest-path-first chunk order (with and without tiles) equals index
+    order for every query and node layout."""
+    torch, rtx = env
+    wl, scenes, rays = billboards
+    sc = scenes[layout]
+    for query in ("closest", "any", "multi"):
+        ref, rc = rtx.trace(sc, rays, "alpha", query=query, k=2, count=True, alpha_min=128)
+        for width in (None, 1920):
+            announce(f"billboards alpha {layout} {query} longest-first tiles={width}")
+            if query == "closest":
+                out = torch.full((wl.n_rays, 4), 7.0, device="cuda")
+                got, gc = rtx.trace(sc, rays, "alpha", count=True, alpha_min=128, out=out,
+                                    image_width=width, longest_first=True)
+            else:
+                got, gc = rtx.trace(sc, rays, "alpha", query=query, k=2, count=True,
+                                    alpha_min=128, image_width=width, longest_first=True)
+            torch.cuda.synchronize()
+            if query == "multi":
+                assert same_bits(got[0], ref[0]) and same_bits(got[1], ref[1])
+            else:
+                assert same_bits(got, ref)
+            assert same_bits(gc, rc)
+
+
+def test_longest_first_every_shape_and_size(env, oracle_lib, billboards):
+    """Every compiled launch shape (static and persistent grids, chunks of 32,
+    64 and 128), ray counts that end inside a chunk, one ray, and the
+    allocation-free entry point; sentinel-filled outputs."""
+    torch, rtx = env
+    wl, scenes, rays = billboards
+    sc = scenes["f32"]
+    for shape in rtx.rt_launch_shapes():
+        for n in (1, 63, 100_001, wl.n_rays):
+            announce(f"longest-first shape={tuple(shape)} n={n}")
+            r = rays[:n].contiguous()
+            out = torch.full((n, 4), 7.0, device="cuda")
+            got = rtx.trace(sc, r, "alpha", alpha_min=128, out=out, shape=tuple(shape),
+                            longest_first=True, image_width=1920 if n == wl.n_rays else None)
+            ref = rtx.trace(sc, r, "alpha", alpha_min=128, shape=tuple(shape))
+            torch.cuda.synchronize()
+            assert same_bits(got, ref), (tuple(shape), n)
+    announce("longest-first through rt_trace_closest_noalloc")
+    h = torch.full((wl.n_rays, 4), 7.0, device="cuda")
+    flags = rtx.RT_FLAG_LONGEST_FIRST | rtx.tile_flag(1920)
+    rtx.rt_trace_closest_noalloc(sc.view, rays.data_ptr(), wl.n_rays, rtx.KINDS["alpha"],
+                                 rtx._params(sc, "alpha", 128, 8), flags, h.data_ptr(), None,
+                                 torch.cuda.current_stream().cuda_stream)
+    ref = rtx.trace(sc, rays, "alpha", alpha_min=128)
+    torch.cuda.synchronize()
+    assert same_bits(h, ref)
+
+
+def test_longest_first_spheres_and_empty(env):
+    torch, rtx = env
+    wl = W.spheres()
+    sc = rtx.upload_scene(wl.vertices, layout="q8", max_leaf=2)
+    rays = torch.from_numpy(wl.rays).cuda()
+    announce("spheres procedural longest-first with counters")
+    ref, rc = rtx.trace(sc, rays, "procedural", checker_n=8, count=True)
+    got, gc = rtx.trace(sc, rays, "procedural", checker_n=8, count=True, longest_first=True)
+    torch.cuda.synchronize()
+    assert same_bits(got, ref) and same_bits(gc, rc)
+    announce("longest-first on an empty scene")
+    empty = rtx.upload_scene(np.zeros((0, 3, 3), np.float32))
+    h = rtx.trace(empty, rays[:1000].contiguous(), longest_first=True)
+    torch.cuda.synchronize()
+    assert np.all(P.hits_to_numpy(h)["prim"] == 0xFFFFFFFF)
