@@ -60,7 +60,15 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def find_counters(sha, workload, kind, query, layout, max_leaf, shape, ray_order):
+def default_order(workload: str, kind: str, query: str) -> str:
+    """The chunk order bench.py uses unless ``--order`` names one: longest
+    path first for the alpha-mask closest hit on the billboards, where it was
+    measured faster, ray-index order elsewhere, where it was measured slower."""
+    return "longest-first" if (workload, kind, query) == ("billboards", "alpha", "closest") else "index"
+
+
+def find_counters(sha, workload, kind, query, layout, max_leaf, shape, ray_order,
+                  schedule="index", order="index"):
     """The rocprofv3 counter record (``profiles/counters_*.json``) taken on
     exactly this kernel source and configuration, or None."""
     if not os.path.isdir(PROFILES):
@@ -75,7 +83,9 @@ def find_counters(sha, workload, kind, query, layout, max_leaf, shape, ray_order
                 and cfg.get("intersector") == kind and cfg.get("query") == query
                 and cfg.get("layout") == layout and cfg.get("max_leaf") == max_leaf
                 and cfg.get("launch_shape") == list(shape)
-                and cfg.get("ray_order", "scanline") == ray_order):
+                and cfg.get("ray_order", "scanline") == ray_order
+                and cfg.get("schedule", "index") == schedule
+                and cfg.get("order", "index") == order):
             rec["file"] = os.path.join("profiles", name)
             return rec
     return None
@@ -250,8 +260,12 @@ def ingest_counters(args, directory: str):
         if wl_name is None:
             from paper_1912_12786_amd import workloads as W
             wl_name = {"tiny": W.tiny, "spheres": W.spheres}[args.workload]().name
+    # tiles apply to scanline rays of an image (every single-scene workload is one)
+    schedule = "index" if (batched or args.ray_order != "scanline") else args.schedule
+    order = "index" if batched else (args.order or default_order(args.workload, kind, args.query))
     flags = (f"--workload {args.workload}" + ("" if batched else f" --intersector {kind} "
-             f"--query {args.query} --ray-order {args.ray_order}")
+             f"--query {args.query} --ray-order {args.ray_order} --schedule {schedule} "
+             f"--order {order}")
              + f" --layout {args.layout} --max-leaf {args.max_leaf}"
              + (f" --shape {args.shape}" if args.shape else ""))
     base = f"python3 bench.py {flags} --steps {args.steps} --warmup {args.warmup} --no-cpu-baseline"
@@ -260,7 +274,7 @@ def ingest_counters(args, directory: str):
         "kernel_source_sha": sha,
         "config": {"workload": wl_name, "intersector": kind, "query": args.query,
                    "layout": args.layout, "max_leaf": args.max_leaf, "launch_shape": shape,
-                   "ray_order": args.ray_order},
+                   "ray_order": args.ray_order, "schedule": schedule, "order": order},
         "kernel": f"trace_kernel<{isect}, {res}{tail}",
         "dispatches": {"issue": issue["n"]},
         "ta_busy_frac": round(ta_busy, 4),
@@ -298,7 +312,7 @@ def ingest_counters(args, directory: str):
     rec["commands"]["ingest"] = (f"python3 bench.py --ingest-counters <out> {flags} "
                                  f"--steps {args.steps} --warmup {args.warmup}")
     name = (f"counters_{args.workload}_{kind}_{args.query}_{args.layout}_leaf{args.max_leaf}_"
-            f"{'x'.join(map(str, shape))}_{args.ray_order}.json")
+            f"{'x'.join(map(str, shape))}_{args.ray_order}_{schedule}_{order}.json")
     with open(os.path.join(PROFILES, name), "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
@@ -795,9 +809,7 @@ def main():
     width = int(wl.extra["width"]) if (args.schedule == "tiles" and args.ray_order == "scanline"
                                        and "width" in wl.extra) else None
     if args.order is None:
-        args.order = ("longest-first" if (args.workload, kind, query) == ("billboards", "alpha",
-                                                                           "closest")
-                      else "index")
+        args.order = default_order(args.workload, kind, query)
     lf = args.order == "longest-first"
 
     def time_launches(r, o, image_width=width):
@@ -851,7 +863,7 @@ def main():
 
     counters_rec = find_counters(kernel_source_sha(), wl.name, kind, query, args.layout,
                                  args.max_leaf, list(shape or rtx.rt_launch_shapes()[0]),
-                                 args.ray_order)
+                                 args.ray_order, "tiles" if width else "index", args.order)
 
     cpu = None
     if not args.no_cpu_baseline and query == "closest":
