@@ -107,9 +107,9 @@ typedef enum rt_isect_kind {
  * launch ends when its last and longest rays do, so starting the long ones
  * first shortens the tail.  Only the schedule changes: every ray's result,
  * counters and output position are those of the call without it.  The
- * workspace grows by 8 bytes per chunk plus 512 (rt_trace_workspace_bytes
- * with the same flags); single-scene calls only (RT_ERR_UNSUPPORTED for
- * batches). */
+ * workspace grows by 8 bytes per chunk plus 256 bytes per 256 chunks (or
+ * part), rounded up to 16 (rt_trace_workspace_bytes with the same flags);
+ * single-scene calls only (RT_ERR_UNSUPPORTED for batches). */
 #define RT_FLAG_LONGEST_FIRST 0x8u
 
 /* Launch shape of one call: bits 8..15 of flags hold an index into the table

@@ -117,11 +117,16 @@ inline uint64_t launch_threads(uint32_t n_rays, const LaunchShape &s)
 
 // Workspace bytes of a single-scene launch of n_rays rays in shape s.
 // Chunk-order area of a longest-path-first launch: a key and an order entry
-// per chunk (chunks of s.chunk rays), then 64 bucket counts and 64 cursors.
+// per chunk (chunks of s.chunk rays), then one row of kOrderAreaBuckets
+// counts for each kOrderAreaRowChunks chunks (the keying kernel's per-block
+// tallies; the kernels assert the same two numbers).
+constexpr size_t kOrderAreaBuckets = 64;
+constexpr size_t kOrderAreaRowChunks = 256;
 inline size_t order_bytes(uint32_t n_rays, const LaunchShape &s)
 {
     const size_t n_chunks = (size_t(n_rays) + s.chunk - 1) / s.chunk;
-    return (8 * n_chunks + 512 + 15) / 16 * 16;
+    const size_t n_rows = (n_chunks + kOrderAreaRowChunks - 1) / kOrderAreaRowChunks;
+    return (8 * n_chunks + 4 * kOrderAreaBuckets * n_rows + 15) / 16 * 16;
 }
 
 inline size_t workspace_for(const rt_bvh_info &info, uint32_t n_rays, const LaunchShape &s,

@@ -99,9 +99,10 @@ rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipS
         // a drawn chunk is first_dynamic (= the grid's waves) + head + 8 k.
         // When the grid has a wave for every chunk, no draw can name a chunk,
         // whatever the heads hold, so the heads need no reset (one launch
-        // less for small ray counts).
+        // less for small ray counts).  A longest-path-first order's scatter
+        // kernel has zeroed them already.
         const uint64_t n_chunks = (uint64_t(a.n_rays) + kChunk - 1) / kChunk;
-        if (uint64_t(grid) * (kBlock / 64) < n_chunks)
+        if (uint64_t(grid) * (kBlock / 64) < n_chunks && a.order == nullptr)
             hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, a.queue);
     }
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, a, p);

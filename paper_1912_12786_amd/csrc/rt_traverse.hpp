@@ -988,30 +988,25 @@ static __global__ void reset_queue_kernel(uint32_t *queue)
 }
 
 // -------------------------------------------------------------------------
-// longest-path-first chunk order (three small kernels before the traversal)
-// area: keys[n_chunks], order[n_chunks], counts[64], cursors[64]
+// longest-path-first chunk order (two small kernels before the traversal)
+// area: keys[n_chunks], order[n_chunks], then one row of kOrderBuckets
+// per-block tallies for each block of the keying kernel
 // -------------------------------------------------------------------------
-constexpr uint32_t kOrderBuckets = 64;
-
-// Zeroes the bucket counts and cursors.
-static __global__ void order_clear_kernel(uint32_t *counts)
-{
-    if (threadIdx.x < 2 * kOrderBuckets) counts[threadIdx.x] = 0;
-}
-
-// Four lanes per chunk (blocks of kOrderKeysBlock threads): the chunk's key
-// is 63 minus the bucket (64 steps of the scene box's diagonal) of the
-// longest interval stretch inside the box among four of its rays, the ends
-// of its first and last runs of 8 (the corners of an 8 x 8 tile), so that
-// sorting keys ascending puts long chunks first.  counts[key] tallies the
-// chunks per key through a block-level tally in LDS (one global atomic per
-// key and block: same-address atomics from every chunk serialize at the
-// L2).
 constexpr uint32_t kOrderKeysBlock = 1024;
 constexpr uint32_t kOrderSamples = 4;
+constexpr uint32_t kOrderRowChunks = kOrderKeysBlock / kOrderSamples;  // chunks per block
+constexpr uint32_t kOrderBuckets = 64;
+
+// Four lanes per chunk: the chunk's key is 63 minus the bucket (64 steps of
+// the scene box's diagonal) of the longest interval stretch inside the box
+// among four of its rays, the ends of its first and last runs of 8 (the
+// corners of an 8 x 8 tile), so that sorting keys ascending puts long chunks
+// first.  Block b writes its chunks' keys and, in row b of the tallies, how
+// many of them fall in each bucket (every row is written whole, so the area
+// needs no clearing beforehand).
 static __global__ __launch_bounds__(kOrderKeysBlock) void order_keys_kernel(
     kernel_args a, uint32_t chunk, uint32_t n_chunks, float buckets_per_length, uint32_t *keys,
-    uint32_t *counts)
+    uint32_t *tallies)
 {
     __shared__ uint32_t tally[kOrderBuckets];
     if (threadIdx.x < kOrderBuckets) tally[threadIdx.x] = 0;
@@ -1047,39 +1042,56 @@ static __global__ __launch_bounds__(kOrderKeysBlock) void order_keys_kernel(
         atomicAdd(tally + key, 1u);
     }
     __syncthreads();
-    if (threadIdx.x < kOrderBuckets && tally[threadIdx.x] != 0)
-        atomicAdd(counts + threadIdx.x, tally[threadIdx.x]);
+    if (threadIdx.x < kOrderBuckets)
+        tallies[blockIdx.x * kOrderBuckets + threadIdx.x] = tally[threadIdx.x];
 }
 
-// Scatters the chunk indices into ascending key order: bucket bases from an
-// exclusive scan of the counts, per-block offsets from LDS tallies and one
-// global cursor reservation per bucket and block.
-static __global__ void order_scatter_kernel(uint32_t n_chunks, const uint32_t *keys,
-                                            uint32_t *order, uint32_t *counts)
+// Scatters the chunk indices into ascending key order; block b takes the
+// keying kernel's block b's chunks.  Wave w sums the tally rows w, w + 4, ...
+// per bucket (over all rows, and over the rows before b); a bucket's base is
+// the exclusive scan of the totals plus the counts of earlier blocks, and a
+// chunk's place within its block and bucket comes from an LDS tally.  Block 0
+// also zeroes the work-queue heads for the traversal that follows.
+constexpr uint32_t kOrderScatterBlock = kOrderRowChunks;
+static __global__ __launch_bounds__(kOrderScatterBlock) void order_scatter_kernel(
+    uint32_t n_chunks, uint32_t n_rows, const uint32_t *keys, const uint32_t *tallies,
+    uint32_t *order, uint32_t *queue)
 {
-    __shared__ uint32_t base[kOrderBuckets], tally[kOrderBuckets], reserved[kOrderBuckets];
-    const uint32_t t = threadIdx.x;
+    constexpr uint32_t kWaves = kOrderScatterBlock / 64;
+    __shared__ uint32_t total[kWaves][kOrderBuckets], before[kWaves][kOrderBuckets];
+    __shared__ uint32_t base[kOrderBuckets], tally[kOrderBuckets];
+    const uint32_t t = threadIdx.x, w = t / 64, bucket = t % 64;
+    if (blockIdx.x == 0 && queue != nullptr && t < kQueueHeads) queue[t * kQueueStride] = 0;
+    uint32_t sum = 0, sum_before = 0;
+#pragma unroll 8
+    for (uint32_t row = w; row < n_rows; row += kWaves) {
+        const uint32_t v = tallies[row * kOrderBuckets + bucket];
+        sum += v;
+        sum_before += row < blockIdx.x ? v : 0u;
+    }
+    total[w][bucket] = sum;
+    before[w][bucket] = sum_before;
+    if (t < kOrderBuckets) tally[t] = 0;
+    __syncthreads();
     if (t < kOrderBuckets) {
-        uint32_t v = counts[t];
-        for (uint32_t off = 1; off < kOrderBuckets; off <<= 1) {
-            const uint32_t u = __shfl_up(v, off);
-            if (t >= off) v += u;
+        uint32_t all = 0, mine = 0;
+        for (uint32_t k = 0; k < kWaves; ++k) {
+            all += total[k][t];
+            mine += before[k][t];
         }
-        base[t] = v - counts[t];
-        tally[t] = 0;
+        uint32_t incl = all;  // inclusive scan over the 64 buckets (one wave)
+        for (uint32_t off = 1; off < kOrderBuckets; off <<= 1) {
+            const uint32_t u = __shfl_up(incl, off);
+            if (t >= off) incl += u;
+        }
+        base[t] = incl - all + mine;
     }
     __syncthreads();
-    const uint32_t c = blockIdx.x * blockDim.x + t;
-    uint32_t key = 0, mine = 0;
+    const uint32_t c = blockIdx.x * kOrderScatterBlock + t;
     if (c < n_chunks) {
-        key = keys[c];
-        mine = atomicAdd(tally + key, 1u);
+        const uint32_t key = keys[c];
+        order[base[key] + atomicAdd(tally + key, 1u)] = c;
     }
-    __syncthreads();
-    if (t < kOrderBuckets && tally[t] != 0)
-        reserved[t] = atomicAdd(counts + kOrderBuckets + t, tally[t]);
-    __syncthreads();
-    if (c < n_chunks) order[base[key] + reserved[key] + mine] = c;
 }
 
 }  // namespace rtx

@@ -263,25 +263,25 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
         a.tile_w8 = q.tile_w8;
         a.tiled = uint32_t(uint64_t(q.n_rays) / per_row * per_row);
     }
-    if (q.order) {  // longest-path-first: key, count and order the chunks first
+    if (q.order) {  // longest-path-first: key and tally the chunks, then order them
+        static_assert(kOrderAreaBuckets == kOrderBuckets && kOrderAreaRowChunks == kOrderRowChunks,
+                      "the chunk-order area's sizing and its kernels agree");
         const uint32_t chunk = q.shape.chunk;
         const uint32_t n_chunks = uint32_t((uint64_t(q.n_rays) + chunk - 1) / chunk);
+        const uint32_t n_rows = (n_chunks + kOrderRowChunks - 1) / kOrderRowChunks;
         uint32_t *keys = static_cast<uint32_t *>(q.order);
         uint32_t *order = keys + n_chunks;
-        uint32_t *counts = order + n_chunks;
+        uint32_t *tallies = order + n_chunks;
         const rt_bvh_info &in = q.scene->info;
         const float dx = in.root_hi[0] - in.root_lo[0], dy = in.root_hi[1] - in.root_lo[1],
                     dz = in.root_hi[2] - in.root_lo[2];
         const float diag = std::sqrt(dx * dx + dy * dy + dz * dz);
         const float per_length = diag > 0.0f && std::isfinite(diag) ? float(kOrderBuckets) / diag : 0.0f;
         hipStream_t st = static_cast<hipStream_t>(q.stream);
-        hipLaunchKernelGGL(order_clear_kernel, dim3(1), dim3(2 * kOrderBuckets), 0, st, counts);
-        constexpr uint32_t per_block = kOrderKeysBlock / kOrderSamples;  // chunks per block
-        hipLaunchKernelGGL(order_keys_kernel, dim3((n_chunks + per_block - 1) / per_block),
-                           dim3(kOrderKeysBlock), 0, st, a, chunk, n_chunks, per_length, keys,
-                           counts);
-        hipLaunchKernelGGL(order_scatter_kernel, dim3((n_chunks + 255) / 256), dim3(256), 0, st,
-                           n_chunks, keys, order, counts);
+        hipLaunchKernelGGL(order_keys_kernel, dim3(n_rows), dim3(kOrderKeysBlock), 0, st, a, chunk,
+                           n_chunks, per_length, keys, tallies);
+        hipLaunchKernelGGL(order_scatter_kernel, dim3(n_rows), dim3(kOrderScatterBlock), 0, st,
+                           n_chunks, n_rows, keys, tallies, order, a.queue);
         a.order = order;
     }
 

@@ -741,15 +741,16 @@ def test_tile_flag(lib):
 
 def test_longest_first_workspace(lib):
     """The longest-path-first schedule adds a key and an order entry per
-    chunk plus 512 bytes (bucket counts and cursors), rounded to 16."""
+    chunk plus a row of 64 bucket counts per 256 chunks, rounded to 16."""
     sc = _fake_scene(max_depth=3)
     for shape in rtx.rt_launch_shapes():
         f = rtx.shape_flag(tuple(shape))
-        for n in (1, 64, 65, 2_073_600):
+        for n in (1, 64, 65, 256 * 64, 256 * 64 + 1, 2_073_600):
             plain = rtx.rt_trace_workspace_bytes(sc, n, f)
             lf = rtx.rt_trace_workspace_bytes(sc, n, f | rtx.RT_FLAG_LONGEST_FIRST)
             chunks = -(-n // shape[2])
-            assert lf - plain == (8 * chunks + 512 + 15) // 16 * 16
+            rows = -(-chunks // 256)
+            assert lf - plain == (8 * chunks + 256 * rows + 15) // 16 * 16
     info = rtx.rt_batch_info()
     assert lib.rt_trace_batch(0x10000, C.byref(info), 0x30000, 0, None, rtx.RT_FLAG_LONGEST_FIRST,
                               0x40000, None, None, 0, None) == -3
