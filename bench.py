@@ -68,7 +68,7 @@ def default_order(workload: str, kind: str, query: str) -> str:
 
 
 def find_counters(sha, workload, kind, query, layout, max_leaf, shape, ray_order,
-                  schedule="index", order="index"):
+                  schedule="index", order="index", waves=7):
     """The rocprofv3 counter record (``profiles/counters_*.json``) taken on
     exactly this kernel source and configuration, or None."""
     if not os.path.isdir(PROFILES):
@@ -85,7 +85,8 @@ def find_counters(sha, workload, kind, query, layout, max_leaf, shape, ray_order
                 and cfg.get("launch_shape") == list(shape)
                 and cfg.get("ray_order", "scanline") == ray_order
                 and cfg.get("schedule", "index") == schedule
-                and cfg.get("order", "index") == order):
+                and cfg.get("order", "index") == order
+                and cfg.get("waves_per_simd") == waves):
             rec["file"] = os.path.join("profiles", name)
             return rec
     return None
@@ -267,14 +268,17 @@ def ingest_counters(args, directory: str):
              f"--query {args.query} --ray-order {args.ray_order} --schedule {schedule} "
              f"--order {order}")
              + f" --layout {args.layout} --max-leaf {args.max_leaf}"
-             + (f" --shape {args.shape}" if args.shape else ""))
+             + (f" --shape {args.shape}" if args.shape else "")
+             + (f" --waves-per-simd {args.waves_per_simd}" if args.waves_per_simd else ""))
+    waves = args.waves_per_simd or rtx.RT_DEFAULT_WAVES_PER_SIMD
     base = f"python3 bench.py {flags} --steps {args.steps} --warmup {args.warmup} --no-cpu-baseline"
     pmc = "rocprofv3 --pmc {} --output-format csv -d <out>/{} -o bench -- "
     rec = {
         "kernel_source_sha": sha,
         "config": {"workload": wl_name, "intersector": kind, "query": args.query,
                    "layout": args.layout, "max_leaf": args.max_leaf, "launch_shape": shape,
-                   "ray_order": args.ray_order, "schedule": schedule, "order": order},
+                   "ray_order": args.ray_order, "schedule": schedule, "order": order,
+                   "waves_per_simd": waves},
         "kernel": f"trace_kernel<{isect}, {res}{tail}",
         "dispatches": {"issue": issue["n"]},
         "ta_busy_frac": round(ta_busy, 4),
@@ -312,7 +316,7 @@ def ingest_counters(args, directory: str):
     rec["commands"]["ingest"] = (f"python3 bench.py --ingest-counters <out> {flags} "
                                  f"--steps {args.steps} --warmup {args.warmup}")
     name = (f"counters_{args.workload}_{kind}_{args.query}_{args.layout}_leaf{args.max_leaf}_"
-            f"{'x'.join(map(str, shape))}_{args.ray_order}_{schedule}_{order}.json")
+            f"{'x'.join(map(str, shape))}_{args.ray_order}_{schedule}_{order}_w{waves}.json")
     with open(os.path.join(PROFILES, name), "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
@@ -520,7 +524,8 @@ def bench_batched(args):
     best = None
 
     def batched(shape=None):
-        batch.trace(rays, out=out, workspace=ws, shape=shape or best)
+        batch.trace(rays, out=out, workspace=ws, shape=shape or best,
+                    waves_per_simd=args.waves_per_simd)
 
     def separate():
         for sc, r, o in zip(sc_list, views, outs):
@@ -565,7 +570,8 @@ def bench_batched(args):
         "config": {"workload": f"batched_{len(scenes)}_scenes", "n_scenes": len(scenes),
                    "node_layout": args.layout, "max_leaf": args.max_leaf,
                    "n_tris": int(sum(s["vertices"].shape[0] for s in scenes)), "n_rays": int(n),
-                   "launch_shape": list(best)},
+                   "launch_shape": list(best),
+                   "waves_per_simd": args.waves_per_simd or rtx.RT_DEFAULT_WAVES_PER_SIMD},
         "mrays_s": {k: round(n / v / 1e3, 2) for k, v in ms.items()},
         "ms": {k: round(v, 4) for k, v in ms.items()},
         "autotune_ms": tune_ms,
@@ -706,6 +712,10 @@ def main():
                          "longest-first for the alpha-mask closest hit on the billboards "
                          "(measured +7.5 %%), index otherwise (measured -3 to -4 %% with it: "
                          "accept-all, any hit, the spheres' mixed primary and bounce rays)")
+    ap.add_argument("--waves-per-simd", type=int, default=None,
+                    help="most resident waves per SIMD of a queue launch's persistent grid "
+                         "(RT_FLAG_WAVES_PER_SIMD, 1..15; results unchanged); default: the "
+                         "library's, 7")
     ap.add_argument("--query", default="closest", choices=["closest", "any", "multi"])
     ap.add_argument("--k", type=int, default=4, help="hits kept per ray by --query multi")
     ap.add_argument("--workload", default="billboards",
@@ -776,8 +786,9 @@ def main():
         args.max_leaf, args.layout = tuned["max_leaf"], tuned["layout"]
         args.shape = ",".join(map(str, tuned["shape"]))
         args.order = "longest-first" if tuned["longest_first"] else "index"
+        args.waves_per_simd = tuned["waves_per_simd"]
         log(f"autotuner: leaves <= {args.max_leaf}, {args.layout} nodes, shape {args.shape}, "
-            f"{args.order} chunk order")
+            f"{args.order} chunk order, {args.waves_per_simd} waves per SIMD")
     log(f"workload {wl.name}: gen {t_gen:.2f} s, host BVH build + upload {t_build:.2f} s, "
         f"{scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}")
     rays = torch.from_numpy(wl.rays).to(dev)
@@ -817,7 +828,8 @@ def main():
         args.steps launches over rays r into o, after args.warmup."""
         def step():
             rtx.trace(scene, r, kind, query=query, k=args.k, alpha_min=128, out=o, workspace=ws,
-                      shape=shape, image_width=image_width, longest_first=lf)
+                      shape=shape, image_width=image_width, longest_first=lf,
+                      waves_per_simd=args.waves_per_simd)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -863,7 +875,8 @@ def main():
 
     counters_rec = find_counters(kernel_source_sha(), wl.name, kind, query, args.layout,
                                  args.max_leaf, list(shape or rtx.rt_launch_shapes()[0]),
-                                 args.ray_order, "tiles" if width else "index", args.order)
+                                 args.ray_order, "tiles" if width else "index", args.order,
+                                 args.waves_per_simd or rtx.RT_DEFAULT_WAVES_PER_SIMD)
 
     cpu = None
     if not args.no_cpu_baseline and query == "closest":
@@ -910,6 +923,7 @@ def main():
                                 args.layout, "64-B nodes, float32 child boxes"),
             "launch_shape": ([int(x) for x in args.shape.split(",")] if args.shape
                              else list(rtx.rt_launch_shapes()[0])),
+            "waves_per_simd": args.waves_per_simd or rtx.RT_DEFAULT_WAVES_PER_SIMD,
         },
         "roofline": roofline(kernel_ms, alg_bytes, counters_rec) | {
             "kernel": f"trace_kernel<{kind}_intersector, {query}>",

@@ -136,6 +136,21 @@ typedef enum rt_isect_kind {
 #define RT_FLAG_TILE_MASK 0x0FFF0000u
 #define RT_FLAG_TILE_WIDTH(width) ((((uint32_t)(width) / 8u) << RT_FLAG_TILE_SHIFT) & RT_FLAG_TILE_MASK)
 
+/* Persistent-grid size, and so rays per lane, of launch shapes with a queue:
+ * bits 28..31 of flags hold W, the most waves per SIMD the launch keeps
+ * resident (1..15; 0 selects RT_DEFAULT_WAVES_PER_SIMD).  A queue launch
+ * puts min(W, what the kernel's registers and LDS allow) waves on each of a
+ * CU's 4 SIMDs (at least one block per CU), and its lanes take rays until the
+ * queue drains, so each lane traces n_rays / (64 x the grid's waves) rays on
+ * average.  Fewer resident waves keep fewer rays' node paths in a CU's
+ * caches at once.  Results and counters never depend on W; shapes without a
+ * queue (one lane per ray) ignore it.  Every entry point that takes flags
+ * takes it. */
+#define RT_FLAG_WAVES_SHIFT 28u
+#define RT_FLAG_WAVES_MASK 0xF0000000u
+#define RT_FLAG_WAVES_PER_SIMD(w) ((((uint32_t)(w)) << RT_FLAG_WAVES_SHIFT) & RT_FLAG_WAVES_MASK)
+#define RT_DEFAULT_WAVES_PER_SIMD 7u
+
 /* Alpha-mask intersector (Listing 5).  For a candidate (prim, u, v):
  *   (s, t) = (1-u-v) tc[prim][0] + u tc[prim][1] + v tc[prim][2],
  *   texel  = nearest texel (clamp to edge) of texture geom_id(prim),

@@ -7,7 +7,8 @@ trace calls (``shape=``), which select it per call.  Results do not depend on
 the shape, only speed does.  :func:`tune_scene`
 also chooses how a scene is built: the BVH leaf size limit and the node
 layout (binary nodes with float32 or compressed 8-bit child boxes, or
-four-wide nodes with float32 child boxes).  Those change the per-ray
+four-wide nodes with float32 child boxes), the chunk order, and the
+persistent grid's waves per SIMD, which sets the rays each lane traces.  Those change the per-ray
 box and triangle counts, and among hits of exactly equal t possibly which one
 is reported, but not the closest or any-hit answer otherwise.  Choices are
 cached per device and key in a JSON file.
@@ -113,15 +114,18 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
                texcoords=None, textures=None, alpha_min: int = 128, checker_n: int = 8,
                leaf_sizes=(2, 3, 4), layouts=("f32", "q8", "wide4"),
                cache_path: str | None = DEFAULT_CACHE, longest_first=(False, True),
-               image_width: int | None = None,
+               image_width: int | None = None, waves=(4, 5, 6, 7, 8),
                steps: int = 5, warmup: int = 1, retune: bool = False, device="cuda"):
     """Chooses the BVH leaf size, node layout, launch shape and chunk order
     (index or longest-path-first) that trace ``rays`` (device float32 [N, 8],
     closest hit; an image of ``image_width`` in scanline order when given)
-    fastest through the scene, and returns ``(scene, choice)``: the scene
-    built that way and ``{"max_leaf", "layout", "shape", "longest_first",
-    "ms"}``; pass ``choice["shape"]`` and ``choice["longest_first"]`` to the
-    trace calls.  A cached choice for this device and key is reused unless
+    fastest through the scene, then, for a queue shape, the most resident
+    waves per SIMD among ``waves`` for that choice.  Returns ``(scene,
+    choice)``: the scene built that way and ``{"max_leaf", "layout", "shape",
+    "longest_first", "waves_per_simd", "ms", "waves_ms"}`` (``waves_per_simd``
+    None for shapes without a queue); pass ``choice["shape"]``,
+    ``choice["longest_first"]`` and ``choice["waves_per_simd"]`` to the trace
+    calls.  A cached choice for this device and key is reused unless
     ``retune``."""
     import torch
     dev_name = _device_name(torch)
@@ -134,7 +138,7 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
         return rtx.upload_scene(vertices, geom_ids, texcoords, textures, device=device,
                                 layout=layout, max_leaf=max_leaf)
 
-    if entry and not retune and tuple(entry["shape"]) in valid:
+    if entry and not retune and tuple(entry["shape"]) in valid and "waves_per_simd" in entry:
         choice = entry
     else:
         ws = rtx.Workspace(device)
@@ -153,9 +157,22 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
                 del scene
         best = min(timings, key=timings.get)
         choice = {"max_leaf": best[0], "layout": best[1], "shape": list(best[2]),
-                  "longest_first": best[3],
+                  "longest_first": best[3], "waves_per_simd": None,
                   "ms": {f"{k[0]}/{k[1]}/{','.join(map(str, k[2]))}/{'lf' if k[3] else 'index'}": v
-                         for k, v in timings.items()}}
+                         for k, v in timings.items()}, "waves_ms": {}}
+        if best[2][3] and waves:  # queue shape: size its persistent grid
+            scene = build(best[0], best[1])
+            wt = {}
+            for w in waves:
+                t = time_shapes(lambda sh: rtx.trace(scene, rays, intersector, out=out,
+                                                     workspace=ws, shape=sh,
+                                                     image_width=image_width,
+                                                     longest_first=best[3], waves_per_simd=w,
+                                                     **kw), steps, warmup, shapes=[best[2]])
+                wt[int(w)] = t[best[2]]
+            del scene
+            choice["waves_per_simd"] = min(wt, key=wt.get)
+            choice["waves_ms"] = {str(w): v for w, v in wt.items()}
         if cache_path:
             cache.setdefault(dev_name, {})[key] = choice
             _store(cache_path, cache)

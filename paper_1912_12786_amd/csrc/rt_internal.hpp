@@ -95,6 +95,7 @@ struct TraceRequest {
     LaunchShape shape;
     uint32_t tile_w8;   // tiled schedule: image width / 8 (0: index order)
     void *order;        // longest-path-first: the chunk-order area (else null)
+    uint32_t waves_per_simd;  // queue shapes: most resident waves per SIMD (1..15)
     void *stream;
 };
 

@@ -51,6 +51,27 @@ uint32_t resident_blocks(Kernel kernel, uint32_t block, std::atomic<uint32_t> (&
     return cache[dev].load(std::memory_order_relaxed);
 }
 
+// Compute units of the current device (cached per device), or 0 with *err set.
+inline uint32_t device_cus(const char **err)
+{
+    static std::atomic<uint32_t> cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        *err = "hipGetDevice failed";
+        return 0;
+    }
+    if (cache[dev].load(std::memory_order_relaxed) == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0) {
+            *err = "device attribute query failed";
+            return 0;
+        }
+        cache[dev].store(uint32_t(cus), std::memory_order_relaxed);
+    }
+    return cache[dev].load(std::memory_order_relaxed);
+}
+
 // Kernel arguments for one scene; the workspace holds the queue heads (queue
 // shapes) and then the stack spill columns.
 inline kernel_args scene_args(const rt_scene &scene, const void *rays, uint32_t n_rays, void *out,
@@ -79,11 +100,12 @@ inline kernel_args scene_args(const rt_scene &scene, const void *rays, uint32_t 
 }
 
 // Enqueues one traversal kernel (and, for a queue shape, the reset of the
-// queue heads before it); returns RT_OK or RT_ERR_HIP.
+// queue heads before it); returns RT_OK or RT_ERR_HIP.  A queue shape's grid
+// holds at most waves_per_simd waves per SIMD (4 SIMDs per CU).
 template <class Isect, class Result, int kSlots, int kBlock, int kChunk, bool kQueue,
           bool kBatched = false, uint32_t kLayout = RT_LAYOUT_F32>
 rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipStream_t s,
-                     const char **err)
+                     const char **err, uint32_t waves_per_simd = RT_DEFAULT_WAVES_PER_SIMD)
 {
     const LaunchShape sh{kBlock, kSlots, kChunk, kQueue};
     auto kernel = trace_kernel<Isect, Result, kSlots, kBlock, kChunk, kQueue, kBatched, kLayout>;
@@ -95,6 +117,11 @@ rt_status launch_one(const kernel_args &a, const typename Isect::params &p, hipS
         const uint32_t resident = resident_blocks(kernel, kBlock, occupancy_cache, err);
         if (resident == 0) return RT_ERR_HIP;
         grid = grid < resident ? grid : resident;
+        const uint32_t cus = device_cus(err);
+        if (cus == 0) return RT_ERR_HIP;
+        const uint32_t per_cu = 4 * waves_per_simd / uint32_t(kBlock / 64);
+        const uint32_t cap = cus * (per_cu > 0 ? per_cu : 1u);
+        grid = grid < cap ? grid : cap;
         // A wave draws from the queue only after its static first chunk, and
         // a drawn chunk is first_dynamic (= the grid's waves) + head + 8 k.
         // When the grid has a wave for every chunk, no draw can name a chunk,

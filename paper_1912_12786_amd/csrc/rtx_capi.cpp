@@ -27,7 +27,8 @@ thread_local std::string g_last_error;
 // Flag bits every single-scene trace call knows: the intersector options and
 // the launch-shape field.
 constexpr uint32_t kKnownFlags = RT_FLAG_COUNT | RT_FLAG_RUNTIME_SWITCH | RT_FLAG_RUNTIME_CALL |
-                                 RT_FLAG_SHAPE_MASK | RT_FLAG_TILE_MASK | RT_FLAG_LONGEST_FIRST;
+                                 RT_FLAG_SHAPE_MASK | RT_FLAG_TILE_MASK | RT_FLAG_LONGEST_FIRST |
+                                 RT_FLAG_WAVES_MASK;
 
 rt_status fail(rt_status s, const std::string &msg)
 {
@@ -165,6 +166,8 @@ rt_status trace_common(Query query, const rt_scene *scene, const rt_ray *rays, u
     TraceRequest q;
     q.runtime_dispatch = runtime == RT_FLAG_RUNTIME_SWITCH ? 1u : (runtime ? 2u : 0u);
     q.tile_w8 = (flags & RT_FLAG_TILE_MASK) >> RT_FLAG_TILE_SHIFT;
+    const uint32_t waves = (flags & RT_FLAG_WAVES_MASK) >> RT_FLAG_WAVES_SHIFT;
+    q.waves_per_simd = waves ? waves : RT_DEFAULT_WAVES_PER_SIMD;
     if (q.tile_w8 && batch)
         return fail(RT_ERR_UNSUPPORTED, "the tiled schedule is for single-scene calls");
     const bool longest_first = (flags & RT_FLAG_LONGEST_FIRST) != 0;
@@ -449,7 +452,8 @@ rt_status rt_trace_batch_workspace_bytes(const rt_batch_info *info, uint32_t fla
 {
     g_last_error.clear();
     if (!info || !bytes) return fail(RT_ERR_INVALID_ARG, "info/bytes are NULL");
-    if (flags & ~(RT_FLAG_COUNT | RT_FLAG_SHAPE_MASK)) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    if (flags & ~(RT_FLAG_COUNT | RT_FLAG_SHAPE_MASK | RT_FLAG_WAVES_MASK))
+        return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
     LaunchShape shape;
     if (!shape_of(flags, shape)) return fail(RT_ERR_UNSUPPORTED, "launch shape index not compiled in");
     rt_bvh_info bi{};

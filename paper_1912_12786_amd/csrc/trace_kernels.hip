@@ -88,26 +88,26 @@ rt_status dispatch_query(const TraceRequest &q, const kernel_args &a,
             *err = "batched launches support the closest-hit query only";
             return RT_ERR_UNSUPPORTED;
         }
-        return launch_one<Isect, closest_result, kSlots, kBlock, kChunk, kQueue, true, kLayout>(a, p, s,
-                                                                                               err);
+        return launch_one<Isect, closest_result, kSlots, kBlock, kChunk, kQueue, true, kLayout>(
+            a, p, s, err, q.waves_per_simd);
     }
     switch (q.query) {
     case Query::Any:
-        return launch_one<Isect, any_result, kSlots, kBlock, kChunk, kQueue, false, kLayout>(a, p, s,
-                                                                                            err);
+        return launch_one<Isect, any_result, kSlots, kBlock, kChunk, kQueue, false, kLayout>(
+            a, p, s, err, q.waves_per_simd);
     case Query::Multi:
         // the kept list lives in registers: a short list for small k keeps
         // the kernel's register use (and so its occupancy) closer to closest-hit
         if (q.multi_k <= 4)
-            return launch_one<Isect, multi_result<4>, kSlots, kBlock, kChunk, kQueue, false, kLayout>(
-                a, p, s, err);
+            return launch_one<Isect, multi_result<4>, kSlots, kBlock, kChunk, kQueue, false,
+                              kLayout>(a, p, s, err, q.waves_per_simd);
         return launch_one<Isect, multi_result<RT_MAX_MULTI>, kSlots, kBlock, kChunk, kQueue, false,
-                          kLayout>(a, p, s, err);
+                          kLayout>(a, p, s, err, q.waves_per_simd);
     case Query::Closest:
         break;
     }
-    return launch_one<Isect, closest_result, kSlots, kBlock, kChunk, kQueue, false, kLayout>(a, p, s,
-                                                                                            err);
+    return launch_one<Isect, closest_result, kSlots, kBlock, kChunk, kQueue, false, kLayout>(
+        a, p, s, err, q.waves_per_simd);
 }
 
 template <class Base, int kSlots, int kBlock, int kChunk, bool kQueue, uint32_t kLayout>
@@ -134,9 +134,9 @@ rt_status dispatch_runtime(const TraceRequest &q, const kernel_args &a, const ch
     hipStream_t s = static_cast<hipStream_t>(q.stream);
     if (q.runtime_dispatch == 1)
         return launch_one<runtime_switch_intersector, closest_result, kSlots, kBlock, kChunk, kQueue>(
-            a, rp, s, err);
+            a, rp, s, err, q.waves_per_simd);
     return launch_one<runtime_call_intersector, closest_result, kSlots, kBlock, kChunk, kQueue>(
-        a, rp, s, err);
+        a, rp, s, err, q.waves_per_simd);
 }
 
 template <int kSlots, int kBlock, int kChunk, bool kQueue, uint32_t kLayout = RT_LAYOUT_F32>

@@ -31,6 +31,9 @@ RT_FLAG_SHAPE_SHIFT = 8
 RT_FLAG_SHAPE_MASK = 0xFF00
 RT_FLAG_TILE_SHIFT = 16
 RT_FLAG_TILE_MASK = 0x0FFF0000
+RT_FLAG_WAVES_SHIFT = 28
+RT_FLAG_WAVES_MASK = 0xF0000000
+RT_DEFAULT_WAVES_PER_SIMD = 7
 RT_NODE_BYTES = 64
 RT_NODE_BYTES_Q8 = 32
 RT_NODE_BYTES_WIDE4 = 128
@@ -634,10 +637,21 @@ def tile_flag(image_width: int | None) -> int:
     return (image_width // 8) << RT_FLAG_TILE_SHIFT
 
 
+def waves_flag(waves_per_simd: int | None) -> int:
+    """Flag bits capping a queue launch's persistent grid at this many waves
+    per SIMD (1..15; None or 0: the library default, 7)."""
+    if not waves_per_simd:
+        return 0
+    if not 1 <= int(waves_per_simd) <= 15:
+        raise ValueError("waves per SIMD must be within 1..15")
+    return int(waves_per_simd) << RT_FLAG_WAVES_SHIFT
+
+
 def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "closest",
           count: bool = False, alpha_min: int = 128, checker_n: int = 8, k: int = 4, out=None,
           counters=None, workspace: Workspace | None = None, stream=None, shape=None,
-          image_width: int | None = None, longest_first: bool = False):
+          image_width: int | None = None, longest_first: bool = False,
+          waves_per_simd: int | None = None):
     """Traces device rays ``float32 [N, 8]``.
 
     closest: returns ``hits float32 [N, 4]`` = (t, prim_id bits, u, v); view
@@ -652,23 +666,26 @@ def trace(scene: Scene, rays, intersector: str = "default", *, query: str = "clo
     lanes then take them in 8 x 8 tiles (same results, see
     ``RT_FLAG_TILE_WIDTH``).  ``longest_first``: hand out the chunks of rays
     that cross the most scene first (same results, see
-    ``RT_FLAG_LONGEST_FIRST``)."""
+    ``RT_FLAG_LONGEST_FIRST``).  ``waves_per_simd``: most resident waves per
+    SIMD of a queue shape's persistent grid, which sets the rays per lane
+    (same results, see ``RT_FLAG_WAVES_PER_SIMD``; None: the default, 7)."""
     torch = _torch()
     if rays.dtype != torch.float32 or rays.dim() != 2 or rays.shape[1] != 8 or not rays.is_contiguous():
         raise ValueError("rays must be a contiguous float32 [N, 8] tensor")
     with _on_stream(rays.device, stream) as s:
         return _trace_on(scene, rays, intersector, query, count, alpha_min, checker_n, k, out,
-                         counters, workspace, s, shape, image_width, longest_first)
+                         counters, workspace, s, shape, image_width, longest_first,
+                         waves_per_simd)
 
 
 def _trace_on(scene, rays, intersector, query, count, alpha_min, checker_n, k, out, counters,
-              workspace, s, shape, image_width=None, longest_first=False):
+              workspace, s, shape, image_width=None, longest_first=False, waves_per_simd=None):
     torch = _torch()
     n = int(rays.shape[0])
     dev = rays.device
     params = _params(scene, intersector, alpha_min, checker_n)
     flags = ((RT_FLAG_COUNT if count else 0) | shape_flag(shape) | tile_flag(image_width)
-             | (RT_FLAG_LONGEST_FIRST if longest_first else 0))
+             | (RT_FLAG_LONGEST_FIRST if longest_first else 0) | waves_flag(waves_per_simd))
     sc = scene.view
     if query == "closest":
         if out is None:
@@ -725,23 +742,26 @@ class Batch:
         self.offsets = np.concatenate([[0], np.cumsum(np.asarray(n_rays, np.int64))])
 
     def trace(self, rays, *, count=False, checker_n: int = 8, out=None, counters=None,
-              workspace: Workspace | None = None, stream=None, shape=None):
+              workspace: Workspace | None = None, stream=None, shape=None,
+              waves_per_simd: int | None = None):
         """Closest hits of all rays (scene order) in one launch (``shape``,
-        ``stream``: as for :func:`trace`)."""
+        ``stream``, ``waves_per_simd``: as for :func:`trace`)."""
         torch = _torch()
         n = int(self.info.n_rays)
         if rays.shape != (n, 8) or rays.dtype != torch.float32 or not rays.is_contiguous():
             raise ValueError(f"rays must be a contiguous float32 [{n}, 8] tensor")
         with _on_stream(rays.device, stream) as s:
-            return self._trace_on(rays, count, checker_n, out, counters, workspace, s, shape)
+            return self._trace_on(rays, count, checker_n, out, counters, workspace, s, shape,
+                                  waves_per_simd)
 
-    def _trace_on(self, rays, count, checker_n, out, counters, workspace, s, shape):
+    def _trace_on(self, rays, count, checker_n, out, counters, workspace, s, shape,
+                  waves_per_simd=None):
         torch = _torch()
         n = int(self.info.n_rays)
         dev = rays.device
         if out is None:
             out = torch.empty((n, 4), dtype=torch.float32, device=dev)
-        flags = (RT_FLAG_COUNT if count else 0) | shape_flag(shape)
+        flags = (RT_FLAG_COUNT if count else 0) | shape_flag(shape) | waves_flag(waves_per_simd)
         if count and counters is None:
             counters = torch.empty((n, 4), dtype=torch.int32, device=dev)
         params = None

@@ -754,3 +754,43 @@ def test_longest_first_workspace(lib):
     info = rtx.rt_batch_info()
     assert lib.rt_trace_batch(0x10000, C.byref(info), 0x30000, 0, None, rtx.RT_FLAG_LONGEST_FIRST,
                               0x40000, None, None, 0, None) == -3
+
+
+def test_waves_per_simd_flag(lib, tmp_path):
+    """The persistent-grid cap (RT_FLAG_WAVES_PER_SIMD): the header's field
+    and default equal the binding's; every value passes flag validation (the
+    call then stops only at its missing workspace) and leaves the workspace
+    size unchanged; the binding refuses values outside 1..15."""
+    import subprocess
+    probe = tmp_path / "waves.c"
+    probe.write_text(r"""
+#include <stdio.h>
+#include "rtx.h"
+int main(void) {
+  printf("%u %u %u %u\n", RT_FLAG_WAVES_SHIFT, RT_FLAG_WAVES_MASK, RT_DEFAULT_WAVES_PER_SIMD,
+         RT_FLAG_WAVES_PER_SIMD(5));
+  return 0;
+}
+""")
+    exe = tmp_path / "waves"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(probe), "-o",
+                    str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals == [rtx.RT_FLAG_WAVES_SHIFT, rtx.RT_FLAG_WAVES_MASK,
+                    rtx.RT_DEFAULT_WAVES_PER_SIMD, rtx.waves_flag(5)]
+    sc = _fake_scene(max_depth=3)
+    for w in range(16):
+        f = w << rtx.RT_FLAG_WAVES_SHIFT
+        assert _closest(lib, sc, flags=f) == -4
+        for n in (1, 65, 2_073_600):
+            assert rtx.rt_trace_workspace_bytes(sc, n, f) == rtx.rt_trace_workspace_bytes(sc, n, 0)
+    info = rtx.rt_batch_info()
+    info.n_rays, info.max_depth = 100_000, 20
+    for w in range(16):
+        assert (rtx.rt_trace_batch_workspace_bytes(info, w << rtx.RT_FLAG_WAVES_SHIFT)
+                == rtx.rt_trace_batch_workspace_bytes(info, 0))
+    assert rtx.waves_flag(None) == 0 and rtx.waves_flag(0) == 0
+    for bad in (16, -1):
+        with pytest.raises(ValueError):
+            rtx.waves_flag(bad)

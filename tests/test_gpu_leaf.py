@@ -103,10 +103,17 @@ def test_tune_scene_chooses_a_build_and_shape(env, oracle_lib, tmp_path):
     # four-wide ones the default shape and its 16-slot variant; each in index
     # and longest-path-first chunk order
     assert len(choice["ms"]) == 2 * 2 * (n_shapes + 1 + 2)
+    # a queue shape's grid size is tuned next, over 4..8 waves per SIMD
+    if choice["shape"][3]:
+        assert sorted(choice["waves_ms"]) == ["4", "5", "6", "7", "8"]
+        assert choice["waves_per_simd"] in (4, 5, 6, 7, 8)
+    else:
+        assert choice["waves_per_simd"] is None and choice["waves_ms"] == {}
     assert sc.info.max_leaf == choice["max_leaf"]
     assert sc.info.layout == rtx.LAYOUTS[choice["layout"]]
     hits, cnt = rtx.trace(sc, rays, "alpha", count=True, alpha_min=128,
-                          shape=tuple(choice["shape"]), longest_first=choice["longest_first"])
+                          shape=tuple(choice["shape"]), longest_first=choice["longest_first"],
+                          waves_per_simd=choice["waves_per_simd"])
     torch.cuda.synchronize()
     bvh = oracle_lib.build_bvh(wl.vertices, max_leaf=choice["max_leaf"])
     B = oracle_lib.traverse(wl.vertices, bvh, wl.rays, "alpha", layout=choice["layout"],

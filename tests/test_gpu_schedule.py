@@ -182,3 +182,55 @@ def test_longest_first_spheres_and_empty(env):
     h = rtx.trace(empty, rays[:1000].contiguous(), longest_first=True)
     torch.cuda.synchronize()
     assert np.all(P.hits_to_numpy(h)["prim"] == 0xFFFFFFFF)
+
+
+@pytest.mark.parametrize("waves", [1, 3, 5, 8, 15])
+def test_waves_per_simd_matches_default(env, billboards, waves):
+    """Capping the persistent grid (RT_FLAG_WAVES_PER_SIMD, which sets the
+    rays each lane traces) changes no result or counter: closest, any and
+    multi-hit with counters, tiled and longest-first, every queue shape, into
+    sentinel-filled outputs, against the default grid (7)."""
+    torch, rtx = env
+    wl, scenes, rays = billboards
+    sc = scenes["f32"]
+    for query in ("closest", "any", "multi"):
+        announce(f"billboards alpha {query}: {waves} waves per SIMD vs the default grid")
+        ref, rc = rtx.trace(sc, rays, "alpha", query=query, k=2, count=True, alpha_min=128)
+        if query == "closest":
+            out = torch.full((wl.n_rays, 4), 7.0, device="cuda")
+            got, gc = rtx.trace(sc, rays, "alpha", count=True, alpha_min=128, out=out,
+                                image_width=1920, longest_first=True, waves_per_simd=waves)
+        else:
+            got, gc = rtx.trace(sc, rays, "alpha", query=query, k=2, count=True, alpha_min=128,
+                                waves_per_simd=waves)
+        torch.cuda.synchronize()
+        if query == "multi":
+            assert same_bits(got[0], ref[0]) and same_bits(got[1], ref[1])
+        else:
+            assert same_bits(got, ref)
+        assert same_bits(gc, rc)
+    r = rays[:300_001].contiguous()
+    ref = rtx.trace(sc, r, "default")
+    for shape in rtx.rt_launch_shapes():
+        if not shape[3]:
+            continue
+        announce(f"billboards default, 300001 rays, shape {tuple(shape)}, {waves} waves per SIMD")
+        got = rtx.trace(sc, r, "default", shape=tuple(shape), waves_per_simd=waves)
+        torch.cuda.synchronize()
+        assert same_bits(got, ref)
+
+
+def test_waves_per_simd_batch(env):
+    """A batched launch with its grid capped at 1 and at 4 waves per SIMD
+    equals the default grid, hits and counters."""
+    torch, rtx = env
+    scenes = [W.tiny(), W.tiny()]
+    sc_list = [rtx.upload_scene(s.vertices) for s in scenes]
+    rays = torch.from_numpy(np.concatenate([scenes[0].rays, scenes[1].rays[:777]])).cuda()
+    batch = rtx.Batch(sc_list, [scenes[0].n_rays, 777], "default")
+    ref, rc = batch.trace(rays, count=True)
+    for waves in (1, 4):
+        announce(f"batch of two tiny scenes, {waves} waves per SIMD")
+        got, gc = batch.trace(rays, count=True, waves_per_simd=waves)
+        torch.cuda.synchronize()
+        assert same_bits(got, ref) and same_bits(gc, rc)
