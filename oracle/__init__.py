@@ -11,7 +11,9 @@ Oracle B (:func:`build_bvh`, :func:`traverse`): its own binned-SAH BVH and a
 float32 while-while traversal (Algorithm 1) that counts ray/box and
 ray/triangle tests the way the heat-map intersector of Section 4 does; with
 ``layout="q8"`` the inner nodes' child boxes are the 8-bit quantized boxes of
-the 32-byte node layout (:func:`quantize`), which the paper does not cover.
+the 32-byte node layout (:func:`quantize`), with ``layout="f32p"`` the stored
+boxes of the 48-byte packed-reference layout (:func:`pack`); the paper covers
+neither.
 
 The C source is ``rt_oracle.c``; :func:`build` compiles it with gcc.
 """
@@ -92,6 +94,10 @@ def _load():
         lib.orc_widen.restype = C.c_int
         lib.orc_quantize.argtypes = [P, C.c_uint32, P, P, P]
         lib.orc_quantize.restype = C.c_int
+        lib.orc_pack.argtypes = [P, C.c_uint32, P, P]
+        lib.orc_pack.restype = C.c_int
+        lib.orc_move_word.argtypes = [C.c_float, C.c_uint32, C.c_int, C.POINTER(C.c_float)]
+        lib.orc_move_word.restype = C.c_int
         lib.orc_node_size.restype = C.c_uint32
         lib.orc_fixed_hit64.argtypes = [P, P, P, P, C.c_uint32, P]
         lib.orc_fixed_hit64.restype = C.c_int
@@ -184,6 +190,7 @@ class OracleBVH:
     max_depth: int
     qbox: np.ndarray | None = field(default=None, repr=False)  # quantize()'s boxes, once computed
     wide: dict | None = field(default=None, repr=False)        # widen()'s layout, once computed
+    pbox: np.ndarray | None = field(default=None, repr=False)  # pack()'s boxes, once computed
 
     @property
     def n_nodes(self) -> int:
@@ -225,6 +232,36 @@ def quantize(bvh: OracleBVH) -> dict:
     return {"frames": frames, "q": q, "qbox": qbox}
 
 
+def pack(bvh: OracleBVH) -> dict:
+    """The packed-reference (48-byte) layout of every inner node of an oracle
+    BVH: ``box [n_nodes, 12]`` float32, the stored child boxes (lo0, hi0,
+    lo1, hi1) with each child's reference in the low bytes of its lo.x, lo.y,
+    lo.z, hi.x, and ``refs [n_nodes, 2]`` uint32, the canonical child
+    references (inner-node preorder index, or count << 29 | first); leaf
+    entries are zero."""
+    lib = _load()
+    n = bvh.n_nodes
+    box = np.zeros((n, 12), np.float32)
+    refs = np.zeros((n, 2), np.uint32)
+    rc = lib.orc_pack(_ptr(bvh.nodes), n, _ptr(box), _ptr(refs))
+    if rc == -1:
+        raise ValueError("orc_pack: a box bound cannot move without reaching an infinity")
+    if rc != 0:
+        raise MemoryError("orc_pack failed")
+    return {"box": box, "refs": refs}
+
+
+def move_word(x, byte: int, lower: bool):
+    """The packed layout's move of one box word: the float32 nearest to ``x``
+    outward (down if ``lower``) whose bit pattern's low byte is ``byte``, or
+    None if the walk reaches an infinity."""
+    out = C.c_float()
+    if _load().orc_move_word(C.c_float(np.float32(x)), int(byte), int(bool(lower)),
+                             C.byref(out)) != 0:
+        return None
+    return np.float32(out.value)
+
+
 WIDE_DTYPE = np.dtype([("n", "<u4"), ("child", "<u4", 4)])
 WIDE_STACK = 128  # entries of oracle B's traversal stack
 
@@ -254,7 +291,8 @@ def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, t
     ``multi_k > 0`` (multi-hit) ``t, u, v, prim`` are ``[N, multi_k]`` (nearest
     first, padded with misses) and ``n_hits [N]`` counts the kept hits.
     ``layout``: "f32" (float32 child boxes), "q8" (the 32-byte layout's
-    quantized child boxes) or "wide4" (the four-wide layout of the same BVH)."""
+    quantized child boxes), "f32p" (the 48-byte layout's stored child boxes)
+    or "wide4" (the four-wide layout of the same BVH)."""
     lib = _load()
     verts = np.ascontiguousarray(vertices, np.float32).reshape(-1, 9)
     r = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
@@ -268,13 +306,17 @@ def traverse(vertices, bvh: OracleBVH, rays, kind="default", *, geom_ids=None, t
     nh = np.empty(m, np.uint32) if multi_k else None
     cnt = np.empty((m, 4), np.uint32) if count else None
     is_, keep = _isect(texcoords, textures, alpha_min, checker_n)
-    if layout not in ("f32", "q8", "wide4"):
+    if layout not in ("f32", "q8", "f32p", "wide4"):
         raise ValueError(f"unknown layout {layout!r}")
     qbox = None
     if layout == "q8":
         if bvh.qbox is None:
             bvh.qbox = quantize(bvh)["qbox"]
         qbox = bvh.qbox
+    if layout == "f32p":
+        if bvh.pbox is None:
+            bvh.pbox = pack(bvh)["box"]
+        qbox = bvh.pbox
     if layout == "wide4":
         if bvh.wide is None:
             bvh.wide = widen(bvh)

@@ -621,6 +621,84 @@ int orc_quantize(const orc_node *nodes, uint32_t n_nodes, uint32_t *frames, uint
 }
 
 /* ======================================================================
+ * Oracle B part 1b': the packed-reference layout (48-byte nodes)
+ *
+ * Not in the paper (it leaves the node format open); defined in words:
+ *   words     the twelve child-box words lo0.xyz, hi0.xyz, lo1.xyz, hi1.xyz.
+ *   refs      child c's reference -- the index of an inner child among the
+ *             inner nodes in depth-first preorder, or count << 29 | first
+ *             for a leaf child -- is split into bytes, least significant
+ *             first; byte k is the low byte of the bit pattern of the
+ *             child's k-th word among lo.x, lo.y, lo.z, hi.x.
+ *   moving    each of those four words becomes the nearest float, outward
+ *             (down for lo, up for hi), whose pattern has that low byte;
+ *             hi.y and hi.z stay.
+ * The traversal tests the stored words as the child boxes.
+ * ====================================================================== */
+
+/* Walks from x one float at a time (nextafterf, downward for a lower bound,
+ * upward for an upper one) until the bit pattern's low byte is `byte`; -1 if
+ * the walk reaches an infinity. */
+static int move_to_byte(float x, uint32_t byte, int lower, float *out)
+{
+    float y = x;
+    for (int step = 0; step <= 512; ++step) {
+        if (isinf(y)) return -1;
+        if ((bits_of(y) & 0xFFu) == byte) {
+            *out = y;
+            return 0;
+        }
+        y = nextafterf(y, lower ? -INFINITY : INFINITY);
+    }
+    return -1;
+}
+
+/* One word's move, for the tests: 0 and *out, or -1. */
+int orc_move_word(float x, uint32_t byte, int lower, float *out)
+{
+    return move_to_byte(x, byte & 0xFFu, lower, out);
+}
+
+/* The packed child boxes pbox [n_nodes][12] (lo0, hi0, lo1, hi1, as stored)
+ * and the canonical child references refs [n_nodes][2] of every inner node
+ * of an oracle BVH (leaf entries zero).  Returns -1 if a word cannot move. */
+int orc_pack(const orc_node *nodes, uint32_t n_nodes, float *pbox, uint32_t *refs)
+{
+    memset(pbox, 0, sizeof(float) * 12 * (size_t)n_nodes);
+    memset(refs, 0, sizeof(uint32_t) * 2 * (size_t)n_nodes);
+    uint32_t *inner_index = (uint32_t *)malloc(sizeof(uint32_t) * (n_nodes ? n_nodes : 1));
+    if (!inner_index) return -2;
+    uint32_t k = 0;
+    for (uint32_t n = 0; n < n_nodes; ++n)  /* node ids are preorder */
+        inner_index[n] = nodes[n].count == 0 ? k++ : 0;
+    for (uint32_t n = 0; n < n_nodes; ++n) {
+        const orc_node *nd = &nodes[n];
+        if (nd->count > 0) continue;
+        const uint32_t child[2] = {nd->left, nd->right};
+        for (int c = 0; c < 2; ++c) {
+            const orc_node *ch = &nodes[child[c]];
+            const uint32_t ref = ch->count > 0 ? (ch->count << 29 | ch->first) : inner_index[child[c]];
+            refs[2 * (size_t)n + c] = ref;
+            float *b = pbox + 12 * (size_t)n + 6 * c;
+            for (int a = 0; a < 3; ++a) {
+                b[a] = ch->lo[a];
+                b[3 + a] = ch->hi[a];
+            }
+            /* bytes 0..2 into lo.x, lo.y, lo.z; byte 3 into hi.x */
+            for (int j = 0; j < 4; ++j) {
+                const int w = j < 3 ? j : 3;
+                if (move_to_byte(b[w], (ref >> (8 * j)) & 0xFFu, j < 3, &b[w]) != 0) {
+                    free(inner_index);
+                    return -1;
+                }
+            }
+        }
+    }
+    free(inner_index);
+    return 0;
+}
+
+/* ======================================================================
  * Oracle B part 1c: the four-wide layout
  *
  * Not in the paper (it leaves the BVH's arity open); defined in words:
@@ -1041,8 +1119,9 @@ int orc_traverse(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
                                n_threads);
 }
 
-/* The same traversal; with qbox (orc_quantize's decoded child boxes) the
- * inner nodes' box tests use the 32-byte layout's boxes. */
+/* The same traversal; with qbox (orc_quantize's decoded child boxes, or
+ * orc_pack's stored ones) the inner nodes' box tests use that layout's
+ * boxes. */
 int orc_traverse_layout(const float *verts, const uint32_t *geom_ids, uint32_t n_tris,
                         const orc_node *nodes, const uint32_t *perm, uint32_t n_nodes,
                         const float *qbox, const float *rays, uint32_t n_rays, int kind,
