@@ -174,6 +174,7 @@ typedef struct rt_procedural_params {
 #define RT_LAYOUT_F32 0u  /* 64-B nodes with float32 child boxes (rt_bvh_build) */
 #define RT_LAYOUT_Q8 1u   /* 32-B nodes with 8-bit child boxes (rt_bvh_compress) */
 #define RT_LAYOUT_WIDE4 2u /* 128-B nodes with up to four float32 child boxes (rt_bvh_widen) */
+#define RT_LAYOUT_F32P 3u  /* 48-B nodes, float32 child boxes carrying the child references (rt_bvh_pack) */
 
 /* Description of a built BVH (filled by rt_bvh_build). */
 typedef struct rt_bvh_info {
@@ -192,7 +193,7 @@ typedef struct rt_bvh_info {
  * RT_LAYOUT_Q8) wrote (the kernels follow the child references without
  * bounds checks; only the root is validated). */
 typedef struct rt_scene {
-    const void *nodes;       /* device, n_nodes records of RT_NODE_BYTES or RT_NODE_BYTES_Q8 */
+    const void *nodes;       /* device, n_nodes records of the layout's size (RT_NODE_BYTES*) */
     const void *tris;        /* device, n_tris records of RT_TRI_BYTES */
     rt_bvh_info info;
 } rt_scene;
@@ -200,6 +201,7 @@ typedef struct rt_scene {
 #define RT_NODE_BYTES 64u
 #define RT_NODE_BYTES_Q8 32u
 #define RT_NODE_BYTES_WIDE4 128u
+#define RT_NODE_BYTES_F32P 48u
 #define RT_WIDE_EMPTY_REF 0xFFFFFFFFu  /* reference of an unused four-wide child slot */
 #define RT_TRI_BYTES 48u
 #define RT_MAX_TRIS 0x1FFFFFFFu  /* 2^29 - 1 */
@@ -292,6 +294,31 @@ rt_status rt_bvh_compress(const void *nodes, const rt_bvh_info *info, void *out,
  * range. */
 rt_status rt_bvh_widen(const void *nodes, const rt_bvh_info *info, void *out, size_t out_cap,
                        rt_bvh_info *out_info);
+
+/* Converts the inner nodes of a built BVH (host, from rt_bvh_build) to the
+ * packed-reference layout: 48-byte nodes, three 16-byte fetches instead of
+ * four (the paper leaves the node format open; Section 3.2's traversal
+ * needs each child's box and reference).  A node is the twelve box words of
+ * the 64-byte node, lo0.xyz, hi0.xyz, lo1.xyz, hi1.xyz, with no reference
+ * words: child c's reference (as in the 64-byte node) is split into bytes,
+ * least significant first, and byte k becomes the low byte of the bit
+ * pattern of the child's k-th word among lo.x, lo.y, lo.z, hi.x.  Each such
+ * word is moved outward to the nearest float32 whose pattern has that low
+ * byte (the largest <= the bound for lo, the smallest >= it for hi,
+ * walking patterns in value order with -0 just below +0: at most 255
+ * patterns, 511 across zero); hi.y and hi.z are unchanged.  The traversal
+ * uses the stored words as the child boxes and gathers the references from
+ * their low bytes.  The boxes contain the exact ones, so closest and any-hit
+ * answers equal the 64-byte layout's except among hits of exactly equal t,
+ * while the counters are the packed traversal's own.
+ *   nodes     host, info->n_nodes records of RT_NODE_BYTES (RT_LAYOUT_F32)
+ *   out       host output, capacity out_cap >= n_nodes * RT_NODE_BYTES_F32P, 16-byte aligned
+ *   out_info  host output: *info with layout = RT_LAYOUT_F32P (may alias info)
+ * Fails if info->layout is not RT_LAYOUT_F32, a box is not finite, or a
+ * moved word would reach an infinity (bounds within 255 patterns of the
+ * float range's end). */
+rt_status rt_bvh_pack(const void *nodes, const rt_bvh_info *info, void *out, size_t out_cap,
+                      rt_bvh_info *out_info);
 
 /* Device workspace a trace call needs (bytes, possibly 0): the ray queue
  * head of persistent launch shapes and overflow space for traversal stacks

@@ -243,6 +243,8 @@ def pack(bvh: OracleBVH) -> dict:
     n = bvh.n_nodes
     box = np.zeros((n, 12), np.float32)
     refs = np.zeros((n, 2), np.uint32)
+    if bvh.perm.size == 0:  # no triangles: the node array is a placeholder root
+        return {"box": box, "refs": refs}
     rc = lib.orc_pack(_ptr(bvh.nodes), n, _ptr(box), _ptr(refs))
     if rc == -1:
         raise ValueError("orc_pack: a box bound cannot move without reaching an infinity")

@@ -6,8 +6,9 @@ caller-supplied workload and returns the fastest; the caller passes it to its
 trace calls (``shape=``), which select it per call.  Results do not depend on
 the shape, only speed does.  :func:`tune_scene`
 also chooses how a scene is built: the BVH leaf size limit and the node
-layout (binary nodes with float32 or compressed 8-bit child boxes, or
-four-wide nodes with float32 child boxes), the chunk order, and the
+layout (binary nodes with float32 or compressed 8-bit child boxes, binary
+48-byte nodes with packed references, or four-wide nodes with float32 child
+boxes), the chunk order, and the
 persistent grid's waves per SIMD, which sets the rays each lane traces.  Those change the per-ray
 box and triangle counts, and among hits of exactly equal t possibly which one
 is reported, but not the closest or any-hit answer otherwise.  Choices are
@@ -30,8 +31,8 @@ def _device_name(torch) -> str:
 
 def time_shapes(run, steps: int = 10, warmup: int = 2, shapes=None) -> dict:
     """Mean milliseconds per call of ``run(shape)`` for each launch shape that
-    the traced scenes can use (compressed-node scenes run with the default
-    shape only, four-wide ones with the default shape and its 16-slot
+    the traced scenes can use (compressed- and packed-node scenes run with the
+    default shape only, four-wide ones with the default shape and its 16-slot
     variant: the library refuses the others before launching anything).
     ``run`` receives the shape tuple and passes it to its trace calls."""
     import torch
@@ -112,7 +113,7 @@ def _store(cache_path, cache):
 
 def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_ids=None,
                texcoords=None, textures=None, alpha_min: int = 128, checker_n: int = 8,
-               leaf_sizes=(2, 3, 4), layouts=("f32", "q8", "wide4"),
+               leaf_sizes=(2, 3, 4), layouts=("f32", "q8", "f32p", "wide4"),
                cache_path: str | None = DEFAULT_CACHE, longest_first=(False, True),
                image_width: int | None = None, waves=(4, 5, 6, 7, 8),
                steps: int = 5, warmup: int = 1, retune: bool = False, device="cuda"):

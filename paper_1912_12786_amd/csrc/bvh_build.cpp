@@ -27,6 +27,9 @@
 //     with e1 = v1 - v0 and e2 = v2 - v0 rounded to float.
 //   compressed inner node, 32 B (compress_nodes): {F.x F.y F.z Q0} {Q1 Q2 ref0 ref1}
 //     with frame words F and twelve 8-bit child coordinates Q (see below).
+//   packed inner node, 48 B (pack_nodes): the twelve box words of the 64-B
+//     node, child c's reference carried in the low bytes of its lo.x, lo.y,
+//     lo.z, hi.x words (byte k in the k-th), each moved outward to carry it.
 //   four-wide inner node, 128 B (widen_nodes): {lo.x[4]} {hi.x[4]} {lo.y[4]}
 //     {hi.y[4]} {lo.z[4]} {hi.z[4]} {ref[4]} {0 0 0 0}, child c in lane c,
 //     unused slots (the last ones) with ref 0xFFFFFFFF and a zero box.
@@ -390,6 +393,77 @@ rt_status compress_nodes(const NodeRecord *in, uint32_t n_nodes, NodeQ8Record *o
                          uint32_t(q[4 * w + 2]) << 16 | uint32_t(q[4 * w + 3]) << 24;
         o.u[6] = nd.u[12];
         o.u[7] = nd.u[13];
+    }
+    return RT_OK;
+}
+
+// -------------------------------------------------------------------------
+// Packed nodes.  On the key ord(b) = b ^ 0x80000000 (b >= 0) or ~b (b < 0)
+// float32 patterns are ordered by value with -0 just below +0, and the low
+// byte of a pattern is the key's low byte on the non-negative side and 255
+// minus it on the negative side.  Moving a word down to the nearest pattern
+// with low byte p steps the key back by the distance between key bytes on
+// the word's side; if that crosses below the key of +0, the answer is the
+// first key of the negative side with the wanted byte.  Moving up mirrors
+// it.  Keys of infinities or NaNs are errors.
+// -------------------------------------------------------------------------
+namespace {
+
+constexpr uint32_t kZeroKey = 0x80000000u;           // key of +0
+constexpr uint32_t kMinFiniteKey = 0x00800000u;      // key of -FLT_MAX
+constexpr uint32_t kMaxFiniteKey = 0xFF7FFFFFu;      // key of +FLT_MAX
+
+uint32_t key_of(uint32_t b) { return (b >> 31) ? ~b : b ^ 0x80000000u; }
+uint32_t pattern_of_key(uint32_t k) { return k >= kZeroKey ? k ^ 0x80000000u : ~k; }
+
+// The nearest pattern outward from key k (down if lower) whose low byte is
+// p, as a key; false if it would leave the finite range.
+bool move_key(uint32_t k, uint32_t p, bool lower, uint32_t &out)
+{
+    if (k < kMinFiniteKey || k > kMaxFiniteKey) return false;
+    int64_t r;
+    if (lower) {
+        if (k >= kZeroKey) {
+            r = int64_t(k) - int64_t(((k & 0xFFu) - p) & 0xFFu);
+            if (r < int64_t(kZeroKey)) r = int64_t(kZeroKey - 0x100u) | int64_t(0xFFu - p);
+        } else {
+            r = int64_t(k) - int64_t(((k & 0xFFu) - (0xFFu - p)) & 0xFFu);
+        }
+        if (r < int64_t(kMinFiniteKey)) return false;
+    } else {
+        if (k < kZeroKey) {
+            r = int64_t(k) + int64_t(((0xFFu - p) - (k & 0xFFu)) & 0xFFu);
+            if (r >= int64_t(kZeroKey)) r = int64_t(kZeroKey | p);
+        } else {
+            r = int64_t(k) + int64_t((p - (k & 0xFFu)) & 0xFFu);
+        }
+        if (r > int64_t(kMaxFiniteKey)) return false;
+    }
+    out = uint32_t(r);
+    return true;
+}
+
+}  // namespace
+
+rt_status pack_nodes(const NodeRecord *in, uint32_t n_nodes, NodePackedRecord *out)
+{
+    for (uint32_t n = 0; n < n_nodes; ++n) {
+        const NodeRecord &nd = in[n];
+        NodePackedRecord &o = out[n];
+        for (int w = 0; w < 12; ++w) {
+            if (!std::isfinite(nd.f[w])) return RT_ERR_INVALID_ARG;
+            o.u[w] = nd.u[w];
+        }
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t ref = nd.u[12 + c];
+            for (int j = 0; j < 4; ++j) {  // bytes into lo.x, lo.y, lo.z, hi.x
+                uint32_t &word = o.u[6 * c + j];
+                uint32_t k;
+                if (!move_key(key_of(word), (ref >> (8 * j)) & 0xFFu, j < 3, k))
+                    return RT_ERR_INVALID_ARG;
+                word = pattern_of_key(k);
+            }
+        }
     }
     return RT_OK;
 }

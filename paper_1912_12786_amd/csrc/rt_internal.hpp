@@ -30,6 +30,11 @@ struct alignas(16) NodeQ8Record {
 };
 static_assert(sizeof(NodeQ8Record) == RT_NODE_BYTES_Q8, "compressed node record size");
 
+struct alignas(16) NodePackedRecord {
+    uint32_t u[12];
+};
+static_assert(sizeof(NodePackedRecord) == RT_NODE_BYTES_F32P, "packed node record size");
+
 struct alignas(16) NodeW4Record {
     union {
         float f[32];
@@ -46,6 +51,9 @@ rt_status build_bvh(const float *verts, const uint32_t *geom_ids, uint32_t n_tri
                     uint32_t max_leaf, NodeRecord *nodes, TriRecord *tris, rt_bvh_info *info);
 // 64-B nodes -> 32-B nodes (RT_ERR_INVALID_ARG if a box is not finite).
 rt_status compress_nodes(const NodeRecord *in, uint32_t n_nodes, NodeQ8Record *out);
+// 64-B nodes -> 48-B nodes carrying their references in moved box words
+// (RT_ERR_INVALID_ARG if a box is not finite or a word cannot move).
+rt_status pack_nodes(const NodeRecord *in, uint32_t n_nodes, NodePackedRecord *out);
 // 64-B binary nodes -> 128-B four-wide nodes (at most info.n_nodes of them);
 // RT_ERR_INVALID_ARG if a child reference is out of range.
 rt_status widen_nodes(const NodeRecord *in, const rt_bvh_info &info, NodeW4Record *out,

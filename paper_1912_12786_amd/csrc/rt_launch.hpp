@@ -182,7 +182,7 @@ rt_status trace_custom(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
         return RT_ERR_INVALID_ARG;
     }
     if (scene->info.layout != RT_LAYOUT_F32 && scene->info.layout != RT_LAYOUT_Q8 &&
-        scene->info.layout != RT_LAYOUT_WIDE4) {
+        scene->info.layout != RT_LAYOUT_WIDE4 && scene->info.layout != RT_LAYOUT_F32P) {
         *err = "unknown scene node layout";
         return RT_ERR_INVALID_ARG;
     }
@@ -202,6 +202,9 @@ rt_status trace_custom(const rt_scene *scene, const rt_ray *rays, uint32_t n_ray
     if (scene->info.layout == RT_LAYOUT_WIDE4)
         return launch_one<Isect, Result, int(s.lds_stack), int(s.block), int(s.chunk),
                           s.queue != 0, false, RT_LAYOUT_WIDE4>(a, p, stream, err);
+    if (scene->info.layout == RT_LAYOUT_F32P)
+        return launch_one<Isect, Result, int(s.lds_stack), int(s.block), int(s.chunk),
+                          s.queue != 0, false, RT_LAYOUT_F32P>(a, p, stream, err);
     return launch_one<Isect, Result, int(s.lds_stack), int(s.block), int(s.chunk), s.queue != 0>(
         a, p, stream, err);
 }

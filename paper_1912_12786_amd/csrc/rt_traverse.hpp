@@ -281,25 +281,43 @@ struct ring_stack {
 };
 
 struct scene_view {
-    const float4 *nodes;  // 4 float4 per inner node (2 with RT_LAYOUT_Q8, 8 with RT_LAYOUT_WIDE4)
+    const float4 *nodes;  // 4 float4 per inner node (2 with RT_LAYOUT_Q8, 3 with RT_LAYOUT_F32P,
+                          // 8 with RT_LAYOUT_WIDE4)
     const float4 *tris;   // 3 float4 per triangle record
     float root_lo[3], root_hi[3];
     uint32_t root_ref;
     uint32_t n_tris;
-    uint32_t layout;      // RT_LAYOUT_F32, RT_LAYOUT_Q8 or RT_LAYOUT_WIDE4
+    uint32_t layout;      // RT_LAYOUT_F32, RT_LAYOUT_Q8, RT_LAYOUT_F32P or RT_LAYOUT_WIDE4
 };
+
+// A child reference of a RT_LAYOUT_F32P node: byte k is the low byte of the
+// bit pattern of the child's k-th box word (lo.x, lo.y, lo.z, hi.x).
+__device__ __forceinline__ uint32_t packed_ref(float a, float b, float c, float d)
+{
+    return (__float_as_uint(a) & 0xFFu) | (__float_as_uint(b) & 0xFFu) << 8 |
+           (__float_as_uint(c) & 0xFFu) << 16 | __float_as_uint(d) << 24;
+}
 
 // The two child boxes (lo0, hi0, lo1, hi1) and references of inner node
 // `cur`.  RT_LAYOUT_Q8: per axis a, origin = frame word with its low byte
 // cleared and scale = 2^(low byte - 127) (both as bit patterns), and each
-// 8-bit coordinate q decodes to fma(q, scale, origin).  The layout is a
-// compile-time choice: a run-time branch here merges the two paths' loads
-// and costs the float32 layout 6-13 %.
+// 8-bit coordinate q decodes to fma(q, scale, origin).  RT_LAYOUT_F32P: the
+// stored words are the boxes as they are, and the references are gathered
+// from their low bytes.  The layout is a compile-time choice: a run-time
+// branch here merges the paths' loads and costs the float32 layout 6-13 %.
 template <uint32_t kLayout>
 __device__ __forceinline__ void node_children(const scene_view &sc, uint32_t cur, float (&b)[12],
                                               uint32_t &ref0, uint32_t &ref1)
 {
-    if constexpr (kLayout == RT_LAYOUT_Q8) {
+    if constexpr (kLayout == RT_LAYOUT_F32P) {
+        const float4 *nd = sc.nodes + 3 * size_t(cur);
+        const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2];
+        b[0] = n0.x; b[1] = n0.y; b[2] = n0.z; b[3] = n0.w;
+        b[4] = n1.x; b[5] = n1.y; b[6] = n1.z; b[7] = n1.w;
+        b[8] = n2.x; b[9] = n2.y; b[10] = n2.z; b[11] = n2.w;
+        ref0 = packed_ref(b[0], b[1], b[2], b[3]);
+        ref1 = packed_ref(b[6], b[7], b[8], b[9]);
+    } else if constexpr (kLayout == RT_LAYOUT_Q8) {
         const uint4 *nd = reinterpret_cast<const uint4 *>(sc.nodes) + 2 * size_t(cur);
         const uint4 w0 = nd[0], w1 = nd[1];
         const uint32_t frame[3] = {w0.x, w0.y, w0.z};

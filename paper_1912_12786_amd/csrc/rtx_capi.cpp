@@ -57,7 +57,8 @@ rt_status check_scene(const rt_scene *sc)
     if (!sc->tris) return fail(RT_ERR_INVALID_ARG, "scene triangle records are NULL");
     if (!aligned(sc->tris, 16)) return fail(RT_ERR_MISALIGNED, "scene triangle records not 16-byte aligned");
     if (in.max_depth >= 128) return fail(RT_ERR_INVALID_ARG, "scene max_depth must be < 128");
-    if (in.layout != RT_LAYOUT_F32 && in.layout != RT_LAYOUT_Q8 && in.layout != RT_LAYOUT_WIDE4)
+    if (in.layout != RT_LAYOUT_F32 && in.layout != RT_LAYOUT_Q8 && in.layout != RT_LAYOUT_WIDE4 &&
+        in.layout != RT_LAYOUT_F32P)
         return fail(RT_ERR_INVALID_ARG, "unknown scene node layout");
     const uint32_t cnt = in.root_ref >> 29, idx = in.root_ref & 0x1FFFFFFFu;
     if (cnt == 0) {
@@ -307,6 +308,29 @@ rt_status rt_bvh_compress(const void *nodes, const rt_bvh_info *info, void *out,
     return RT_OK;
 }
 
+rt_status rt_bvh_pack(const void *nodes, const rt_bvh_info *info, void *out, size_t out_cap,
+                      rt_bvh_info *out_info)
+{
+    g_last_error.clear();
+    if (!info || !out_info) return fail(RT_ERR_INVALID_ARG, "info/out_info are NULL");
+    if (info->layout != RT_LAYOUT_F32) return fail(RT_ERR_INVALID_ARG, "input nodes are not RT_LAYOUT_F32");
+    const size_t need = size_t(info->n_nodes) * RT_NODE_BYTES_F32P;
+    if (info->n_nodes > 0) {
+        if (!nodes || !out) return fail(RT_ERR_INVALID_ARG, "nodes/out are NULL");
+        if (out_cap < need) return fail(RT_ERR_INVALID_ARG, "out smaller than n_nodes * RT_NODE_BYTES_F32P");
+        if (!aligned(nodes, 16) || !aligned(out, 16))
+            return fail(RT_ERR_MISALIGNED, "nodes/out must be 16-byte aligned");
+        const rt_status st = pack_nodes(static_cast<const NodeRecord *>(nodes), info->n_nodes,
+                                        static_cast<NodePackedRecord *>(out));
+        if (st != RT_OK)
+            return fail(st, "a node box is not finite or too close to the float range's end");
+    }
+    rt_bvh_info o = *info;
+    o.layout = RT_LAYOUT_F32P;
+    *out_info = o;
+    return RT_OK;
+}
+
 rt_status rt_bvh_widen(const void *nodes, const rt_bvh_info *info, void *out, size_t out_cap,
                        rt_bvh_info *out_info)
 {
@@ -485,7 +509,7 @@ rt_status rt_trace_batch(const void *table, const rt_batch_info *info, const rt_
     }
     // a stand-in scene carries the batch-wide sizes through the common checks
     if (info->layout != RT_LAYOUT_F32 && info->layout != RT_LAYOUT_Q8 &&
-        info->layout != RT_LAYOUT_WIDE4)
+        info->layout != RT_LAYOUT_WIDE4 && info->layout != RT_LAYOUT_F32P)
         return fail(RT_ERR_INVALID_ARG, "unknown batch node layout");
     rt_scene proxy{};
     proxy.info.max_depth = info->max_depth;

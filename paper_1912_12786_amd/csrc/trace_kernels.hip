@@ -286,6 +286,18 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
     }
 
     const LaunchShape &sh = q.shape;
+    // 48-byte nodes: compiled for the default launch shape only
+    if (q.scene->info.layout == RT_LAYOUT_F32P) {
+        constexpr LaunchShape d = kDefaultShape;
+        if (sh.block != d.block || sh.lds_stack != d.lds_stack || sh.chunk != d.chunk ||
+            sh.queue != d.queue || q.runtime_dispatch) {
+            *err = "the packed node layout is compiled for the default launch shape and the "
+                   "compile-time intersectors only";
+            return RT_ERR_UNSUPPORTED;
+        }
+        return dispatch_kind<int(d.lds_stack), int(d.block), int(d.chunk), d.queue != 0,
+                             RT_LAYOUT_F32P>(q, a, err);
+    }
     // 32-byte nodes: compiled for the default launch shape only
     if (q.scene->info.layout == RT_LAYOUT_Q8) {
         constexpr LaunchShape d = kDefaultShape;

@@ -37,10 +37,11 @@ RT_DEFAULT_WAVES_PER_SIMD = 7
 RT_NODE_BYTES = 64
 RT_NODE_BYTES_Q8 = 32
 RT_NODE_BYTES_WIDE4 = 128
+RT_NODE_BYTES_F32P = 48
 RT_WIDE_EMPTY_REF = 0xFFFFFFFF
 RT_TRI_BYTES = 48
 RT_NOALLOC_SCRATCH_BYTES = 64 << 20
-LAYOUTS = {"f32": 0, "q8": 1, "wide4": 2}
+LAYOUTS = {"f32": 0, "q8": 1, "wide4": 2, "f32p": 3}
 KINDS = {"default": 0, "alpha": 1, "procedural": 2}
 
 
@@ -109,6 +110,7 @@ SIGNATURES = [
                                   C.POINTER(rt_bvh_info)]),
     ("rt_bvh_compress", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_bvh_widen", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
+    ("rt_bvh_pack", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_trace_workspace_bytes", C.c_int, [C.POINTER(rt_scene), _U32, _U32, C.POINTER(_SZ)]),
     ("rt_trace_closest", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                    _SZ, _P]),
@@ -534,6 +536,22 @@ def rt_bvh_compress(nodes: np.ndarray, info: rt_bvh_info):
     return out.view(np.uint8)[: n * RT_NODE_BYTES_Q8], oinfo
 
 
+def rt_bvh_pack(nodes: np.ndarray, info: rt_bvh_info):
+    """64-byte nodes (from rt_bvh_build) -> 48-byte nodes carrying the child
+    references in the low bytes of moved box words.  Returns ``(nodes uint8,
+    info)`` with ``info.layout = 3``."""
+    n = int(info.n_nodes)
+    src = np.ascontiguousarray(nodes, np.uint8)
+    src16 = np.zeros(max(1, n * RT_NODE_BYTES // 16), dtype=np.dtype((np.void, 16)))
+    src16.view(np.uint8)[: n * RT_NODE_BYTES] = src[: n * RT_NODE_BYTES]
+    out = np.zeros(max(1, n * RT_NODE_BYTES_F32P // 16), dtype=np.dtype((np.void, 16)))
+    oinfo = rt_bvh_info()
+    _check(load_library().rt_bvh_pack(src16.ctypes.data if n else None, C.byref(info),
+                                       out.ctypes.data if n else None, n * RT_NODE_BYTES_F32P,
+                                       C.byref(oinfo)), "rt_bvh_pack")
+    return out.view(np.uint8)[: n * RT_NODE_BYTES_F32P], oinfo
+
+
 def rt_bvh_widen(nodes: np.ndarray, info: rt_bvh_info):
     """64-byte binary nodes (from rt_bvh_build) -> 128-byte four-wide nodes.
     Returns ``(nodes uint8, info)`` with ``info.layout = 2``, ``info.n_nodes``
@@ -553,14 +571,17 @@ def rt_bvh_widen(nodes: np.ndarray, info: rt_bvh_info):
 def upload_scene(vertices, geom_ids=None, texcoords=None, textures=None, device="cuda",
                  layout: str = "f32", max_leaf: int = 4) -> Scene:
     """Builds the BVH on the host (rt_bvh_build_ex with leaves of at most
-    ``max_leaf`` triangles, then rt_bvh_compress for ``layout="q8"`` or
-    rt_bvh_widen for ``layout="wide4"``) and copies it to ``device``."""
+    ``max_leaf`` triangles, then rt_bvh_compress for ``layout="q8"``,
+    rt_bvh_pack for ``layout="f32p"`` or rt_bvh_widen for ``layout="wide4"``)
+    and copies it to ``device``."""
     torch = _torch()
     if layout not in LAYOUTS:
         raise ValueError(f"unknown layout {layout!r}")
     nodes, tris, info = rt_bvh_build(vertices, geom_ids, max_leaf)
     if layout == "q8":
         nodes, info = rt_bvh_compress(nodes, info)
+    elif layout == "f32p":
+        nodes, info = rt_bvh_pack(nodes, info)
     elif layout == "wide4":
         nodes, info = rt_bvh_widen(nodes, info)
     dn = torch.from_numpy(nodes.copy()).to(device) if nodes.size else None

@@ -539,7 +539,7 @@ def test_compress_validation(lib):
     _, ei = rtx.rt_bvh_compress(np.zeros(0, np.uint8), empty)
     assert ei.layout == 1 and ei.n_nodes == 0
     sc = _fake_scene()
-    sc.info.layout = 3
+    sc.info.layout = 4
     assert _closest(lib, sc) == -1
     assert b"unknown scene node layout" in lib.rt_last_error()
     sc.info.layout = 1
@@ -794,3 +794,45 @@ int main(void) {
     for bad in (16, -1):
         with pytest.raises(ValueError):
             rtx.waves_flag(bad)
+
+
+@pytest.mark.parametrize("name", ["tiny", "billboards", "negative_flat", "far"])
+def test_pack_matches_oracle(lib, oracle_lib, name):
+    """The product's 48-byte nodes equal the oracle's packing of its own
+    (identical) BVH word for word, and their gathered bytes are the 64-byte
+    nodes' references."""
+    v = _q8_scenes()[name]
+    for max_leaf in (1, 2, 4):
+        nodes, tris, info = rtx.rt_bvh_build(v, None, max_leaf)
+        p, pi = rtx.rt_bvh_pack(nodes, info)
+        assert pi.layout == 3 and pi.n_nodes == info.n_nodes and pi.root_ref == info.root_ref
+        b = oracle_lib.build_bvh(v, max_leaf=max_leaf)
+        P = oracle_lib.pack(b)
+        inner = np.nonzero(b.nodes["count"] == 0)[0]
+        assert inner.size == info.n_nodes
+        w = p.view(np.uint32).reshape(-1, 12)
+        assert np.array_equal(w, P["box"][inner].view(np.uint32))
+        refs = nodes.view(np.uint32).reshape(-1, 16)[:, 12:14]
+        assert np.array_equal(refs, P["refs"][inner])
+
+
+def test_pack_validation(lib):
+    v = _q8_scenes()["tiny"]
+    nodes, tris, info = rtx.rt_bvh_build(v)
+    p, pi = rtx.rt_bvh_pack(nodes, info)
+    with pytest.raises(rtx.RtxError, match="not RT_LAYOUT_F32"):
+        rtx.rt_bvh_pack(nodes, pi)
+    bad = nodes.copy()
+    bad.view(np.float32)[3] = np.inf                          # hi0.x of node 0
+    with pytest.raises(rtx.RtxError, match="not finite"):
+        rtx.rt_bvh_pack(bad, info)
+    # hi0.x 15 patterns below +FLT_MAX must carry ref0's top byte (< 0xF0):
+    # its upward walk would reach +infinity
+    edge = nodes.copy()
+    edge.view(np.uint32)[3] = 0x7F7FFFF0
+    assert int(edge.view(np.uint32)[12]) >> 24 < 0xF0
+    with pytest.raises(rtx.RtxError, match="float range"):
+        rtx.rt_bvh_pack(edge, info)
+    empty = rtx.rt_bvh_info()
+    _, ei = rtx.rt_bvh_pack(np.zeros(0, np.uint8), empty)
+    assert ei.layout == 3 and ei.n_nodes == 0

@@ -35,11 +35,11 @@ def billboards(env):
     wl = W.billboards()
     scenes = {layout: rtx.upload_scene(wl.vertices, wl.geom_ids, wl.texcoords, wl.textures,
                                        max_leaf=2, layout=layout)
-              for layout in ("f32", "q8", "wide4")}
+              for layout in ("f32", "q8", "f32p", "wide4")}
     return wl, scenes, torch.from_numpy(wl.rays).cuda()
 
 
-@pytest.mark.parametrize("layout", ["f32", "q8", "wide4"])
+@pytest.mark.parametrize("layout", ["f32", "q8", "f32p", "wide4"])
 def test_tiled_schedule_matches_index_order(env, billboards, layout):
     torch, rtx = env
     wl, scenes, rays = billboards
@@ -113,7 +113,7 @@ def test_tiled_schedule_noalloc_and_spheres(env):
     assert same_bits(h, ref)
 
 
-@pytest.mark.parametrize("layout", ["f32", "q8", "wide4"])
+@pytest.mark.parametrize("layout", ["f32", "q8", "f32p", "wide4"])
 def test_longest_first_matches_index_order(env, billboards, layout):
     """Longest-path-first chunk order (with and without tiles) equals index
     order for every query and node layout."""

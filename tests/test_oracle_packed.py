@@ -210,3 +210,14 @@ def test_packed_root_leaf_counts(oracle_lib):
     F = oracle_lib.traverse(verts, bvh, rays)
     Pk = oracle_lib.traverse(verts, bvh, rays, layout="f32p")
     assert np.array_equal(F["counters"], Pk["counters"])
+
+
+def test_packed_empty_scene(oracle_lib):
+    """No triangles: nothing to pack, every ray misses with no box test."""
+    bvh = oracle_lib.build_bvh(np.zeros((0, 3, 3), np.float32))
+    P = oracle_lib.pack(bvh)
+    assert not P["box"].any() and not P["refs"].any()
+    rays = np.zeros((5, 8), np.float32)
+    rays[:, 6], rays[:, 7] = -1.0, np.inf
+    B = oracle_lib.traverse(np.zeros((0, 3, 3), np.float32), bvh, rays, layout="f32p")
+    assert np.all(B["prim"] == MISS) and not B["counters"].any()
