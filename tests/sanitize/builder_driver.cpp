@@ -1,4 +1,4 @@
-// Runs the library's host BVH builder and node compressor on seeded random
+// Runs the library's host BVH builder, node compressor and node packer on seeded random
 // scenes under AddressSanitizer / UndefinedBehaviorSanitizer (built and run by
 // tests/test_sanitizers.py; exit status 0 iff every build succeeded and its
 // basic invariants hold).
@@ -44,6 +44,15 @@ int main()
         }
         std::vector<rtx::NodeQ8Record> q(info.n_nodes ? info.n_nodes : 1);
         if (info.n_nodes && rtx::compress_nodes(nodes.data(), info.n_nodes, q.data()) != RT_OK) return 4;
+        std::vector<rtx::NodePackedRecord> pk(info.n_nodes ? info.n_nodes : 1);
+        if (info.n_nodes && rtx::pack_nodes(nodes.data(), info.n_nodes, pk.data()) != RT_OK) return 5;
+        for (uint32_t i = 0; i < info.n_nodes; ++i)  // the references gather back
+            for (int c = 0; c < 2; ++c) {
+                const uint32_t *w = pk[i].u + 6 * c;
+                const uint32_t ref = (w[0] & 0xFFu) | (w[1] & 0xFFu) << 8 | (w[2] & 0xFFu) << 16 |
+                                     (w[3] & 0xFFu) << 24;
+                if (ref != nodes[i].u[12 + c]) return 6;
+            }
     }
     std::puts("builder ok");
     return 0;

@@ -1,4 +1,4 @@
-/* Runs the oracle's builder, quantizer and traversals on seeded random scenes
+/* Runs the oracle's builder, quantizer, packer and traversals on seeded random scenes
  * under AddressSanitizer / UndefinedBehaviorSanitizer (built and run by
  * tests/test_sanitizers.py; exit status 0 iff every call succeeded). */
 #include "../../oracle/rt_oracle.c"
@@ -43,6 +43,9 @@ int main(void)
         uint8_t *q = malloc(12 * (size_t)nn);
         float *qbox = malloc(sizeof(float) * 12 * nn);
         if (orc_quantize(nodes, nn, frames, q, qbox) != 0) return 2;
+        float *pbox = malloc(sizeof(float) * 12 * nn);
+        uint32_t *prefs = malloc(sizeof(uint32_t) * 2 * nn);
+        if (orc_pack(nodes, nn, pbox, prefs) != 0) return 6;
         orc_isect is;
         memset(&is, 0, sizeof is);
         is.texcoords = tc;
@@ -57,8 +60,8 @@ int main(void)
         uint32_t *prim = malloc(sizeof(uint32_t) * 3 * m), *nh = malloc(sizeof(uint32_t) * m),
                  *cnt = malloc(sizeof(uint32_t) * 4 * m);
         for (int kind = ORC_DEFAULT; kind <= ORC_PROCEDURAL; ++kind)
-            for (int layout = 0; layout < 2; ++layout) {
-                const float *qb = layout ? qbox : NULL;
+            for (int layout = 0; layout < 3; ++layout) {
+                const float *qb = layout == 2 ? pbox : (layout ? qbox : NULL);
                 if (orc_traverse_layout(v, geom, n, nodes, perm, nn, qb, rays, m, kind, &is, 0, 0, t,
                                         prim, u, w, NULL, cnt, 2) != 0) return 3;
                 if (orc_traverse_layout(v, geom, n, nodes, perm, nn, qb, rays, m, kind, &is, 1, 0, t,
@@ -67,7 +70,7 @@ int main(void)
                                         prim, u, w, nh, cnt, 2) != 0) return 5;
             }
         free(v); free(rays); free(geom); free(tc); free(nodes); free(perm); free(frames); free(q);
-        free(qbox); free(t); free(u); free(w); free(prim); free(nh); free(cnt);
+        free(qbox); free(pbox); free(prefs); free(t); free(u); free(w); free(prim); free(nh); free(cnt);
     }
     puts("oracle ok");
     return 0;
