@@ -646,10 +646,12 @@ def bench_instanced(args):
     ids = torch.empty((n,), dtype=torch.int32, device=dev)
     ws = rtx.Workspace(dev)
     stream = torch.cuda.current_stream(dev)
-    ms_i = timed(lambda: isc.trace(rays, kind, out=out, inst_ids=ids, workspace=ws), args.steps,
-                 args.warmup, stream)
-    ms_f = timed(lambda: rtx.trace(fsc, rays, kind, out=out, workspace=ws), args.steps,
-                 args.warmup, stream)
+    # both launches take the image's rays in 8x8 tiles unless --schedule index
+    tw = int(wl["width"]) if args.schedule == "tiles" else None
+    ms_i = timed(lambda: isc.trace(rays, kind, out=out, inst_ids=ids, workspace=ws,
+                                   image_width=tw), args.steps, args.warmup, stream)
+    ms_f = timed(lambda: rtx.trace(fsc, rays, kind, out=out, workspace=ws, image_width=tw),
+                 args.steps, args.warmup, stream)
     bytes_i = sum(int(b.tris.numel()) + (int(b.nodes.numel()) if b.nodes is not None else 0)
                   for b in isc.blas) + int(isc.tlas_tris.numel()) + int(isc.tlas_nodes.numel()) \
         + int(isc.table.numel())
@@ -663,7 +665,8 @@ def bench_instanced(args):
         "warmup": args.warmup, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl["name"], "n_instances": 2000, "n_rays": n,
                    "max_leaf": args.max_leaf,
-                   "world_tris": int(flat.shape[0]), "intersector": kind},
+                   "world_tris": int(flat.shape[0]), "intersector": kind,
+                   "schedule": ("8x8 pixel tiles" if tw else "index order")},
         "instanced_mrays_s": round(n / ms_i / 1e3, 2), "flattened_mrays_s": round(n / ms_f / 1e3, 2),
         "ms": {"instanced": round(ms_i, 4), "flattened": round(ms_f, 4)},
         "scene_bytes": {"instanced": bytes_i, "flattened": bytes_f}})
@@ -709,7 +712,7 @@ def main():
     ap.add_argument("--schedule", default="tiles", choices=["tiles", "index"],
                     help="tiles: the image's rays are handed to lanes in 8x8 pixel tiles "
                          "(RT_FLAG_TILE_WIDTH; results and their order unchanged); index: in "
-                         "ray-index order. Applies to the billboards, tiny and spheres "
+                         "ray-index order. Applies to the billboards, tiny, spheres and instanced "
                          "workloads (the spheres' primary rays)")
     ap.add_argument("--order", default=None, choices=["longest-first", "index"],
                     help="longest-first: chunks of rays handed out by decreasing stretch inside "

@@ -131,7 +131,8 @@ typedef enum rt_isect_kind {
  * when, changes: every ray's result and counters, and where they are written
  * (at the ray's index), are those of the untiled call.  Single-scene calls
  * (rt_trace_closest, rt_trace_closest_noalloc, rt_trace_any, rt_trace_multi)
- * take it; an image wider than 32760 is RT_ERR_INVALID_ARG. */
+ * and rt_trace_instanced (one wave per tile) take it; an image wider than
+ * 32760 is RT_ERR_INVALID_ARG. */
 #define RT_FLAG_TILE_SHIFT 16u
 #define RT_FLAG_TILE_MASK 0x0FFF0000u
 #define RT_FLAG_TILE_WIDTH(width) ((((uint32_t)(width) / 8u) << RT_FLAG_TILE_SHIFT) & RT_FLAG_TILE_MASK)

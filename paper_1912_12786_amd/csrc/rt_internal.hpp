@@ -161,6 +161,7 @@ struct InstancedRequest {
     uint32_t *inst_ids;    // may be null
     void *counters;
     void *spill;
+    uint32_t tile_w8;      // tiled schedule: image width / 8 (0: index order)
     void *stream;
 };
 

@@ -913,9 +913,10 @@ __global__ __launch_bounds__(64) void trace_instanced_kernel(kernel_args a, cons
 {
     __shared__ uint2 ring[kSlots][64];
     const uint32_t tid = threadIdx.x;
-    const uint32_t i = blockIdx.x * 64 + tid;
-    if (i >= a.n_rays) return;
-    ring_stack<kSlots, 64> st{ring, (global_ptr<uint64_t>)(a.spill + i), tid, gridDim.x * 64u};
+    const uint32_t pos = blockIdx.x * 64 + tid;
+    if (pos >= a.n_rays) return;
+    const uint32_t i = scheduled_ray(a, pos);  // tiled schedule, else pos
+    ring_stack<kSlots, 64> st{ring, (global_ptr<uint64_t>)(a.spill + pos), tid, gridDim.x * 64u};
     ray_state rw = make_ray(a.rays[2 * size_t(i)], a.rays[2 * size_t(i) + 1]);
     Isect isect(p);
     Result res;

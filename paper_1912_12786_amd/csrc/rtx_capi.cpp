@@ -645,7 +645,7 @@ rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, const rt_inst
     if (st != RT_OK) return st;
     if (tlas->info.layout != RT_LAYOUT_F32)
         return fail(RT_ERR_UNSUPPORTED, "instancing takes an RT_LAYOUT_F32 top-level scene");
-    if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    if (flags & ~(RT_FLAG_COUNT | RT_FLAG_TILE_MASK)) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
     st = check_instance_info(info);
     if (st != RT_OK) return st;
     *bytes = instanced_workspace(tlas->info, info->max_blas_depth, n_rays);
@@ -663,7 +663,7 @@ rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, const rt_i
     if (st != RT_OK) return st;
     if (tlas->info.layout != RT_LAYOUT_F32)
         return fail(RT_ERR_UNSUPPORTED, "instancing takes an RT_LAYOUT_F32 top-level scene");
-    if (flags & ~RT_FLAG_COUNT) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
+    if (flags & ~(RT_FLAG_COUNT | RT_FLAG_TILE_MASK)) return fail(RT_ERR_UNSUPPORTED, "unknown flag bits");
     st = check_instance_info(info);
     if (st != RT_OK) return st;
     InstancedRequest q{};
@@ -710,6 +710,7 @@ rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, const rt_i
     q.inst_ids = inst_ids;
     q.counters = count ? counters : nullptr;
     q.spill = workspace;
+    q.tile_w8 = (flags & RT_FLAG_TILE_MASK) >> RT_FLAG_TILE_SHIFT;
     q.stream = stream;
     const char *err = "";
     st = launch_instanced(q, &err);

@@ -228,6 +228,11 @@ rt_status launch_instanced(const InstancedRequest &q, const char **err)
     a.multi_k = 1;
     a.counters = static_cast<uint4 *>(q.counters);
     a.spill = static_cast<uint64_t *>(q.spill);
+    if (q.tile_w8) {  // whole rows of 8 x 8 tiles: one wave per tile
+        const uint64_t per_row = 64ull * q.tile_w8;
+        a.tile_w8 = q.tile_w8;
+        a.tiled = uint32_t(uint64_t(q.n_rays) / per_row * per_row);
+    }
     switch (q.kind) {
     case RT_ISECT_DEFAULT:
         return launch_inst_count<default_intersector>(q, a, default_intersector::params{}, err);

@@ -388,15 +388,16 @@ class InstancedScene:
         return p
 
     def trace(self, rays, intersector="default", *, any_hit=False, count=False, checker_n=8,
-              alpha_min=128, out=None, inst_ids=None, workspace=None, stream=None):
+              alpha_min=128, out=None, inst_ids=None, workspace=None, stream=None,
+              image_width: int | None = None):
         """Returns (hits [N,4] float32 or occluders [N] int32, inst_ids [N] int32[,
-        counters]).  ``stream``: as for :func:`trace`."""
+        counters]).  ``stream``, ``image_width``: as for :func:`trace`."""
         with _on_stream(rays.device, stream) as s:
             return self._trace_on(rays, intersector, any_hit, count, checker_n, alpha_min, out,
-                                  inst_ids, workspace, s)
+                                  inst_ids, workspace, s, image_width)
 
     def _trace_on(self, rays, intersector, any_hit, count, checker_n, alpha_min, out, inst_ids,
-                  workspace, s):
+                  workspace, s, image_width=None):
         torch = _torch()
         n = int(rays.shape[0])
         dev = rays.device
@@ -414,7 +415,7 @@ class InstancedScene:
             params = self._alpha_params(alpha_min)
         elif intersector != "default":
             raise ValueError(f"unknown intersector {intersector!r}")
-        flags = RT_FLAG_COUNT if count else 0
+        flags = (RT_FLAG_COUNT if count else 0) | tile_flag(image_width)
         tl = self.tlas
         lib = load_library()
         b = C.c_size_t()

@@ -602,7 +602,7 @@ def instanced(n_instances: int = 2000, width: int = 1920, height: int = 1080):
     lo, hi = tight_world_boxes(wfo, blas, ids)
     rays = pinhole_rays(width, height, BILLBOARD_EYE, BILLBOARD_CENTER, 60.0)
     return {"blas": blas, "inst_blas": ids, "inst_m": m, "world_lo": lo, "world_hi": hi,
-            "rays": rays, "world_from_object": wfo,
+            "rays": rays, "world_from_object": wfo, "width": width, "height": height,
             "name": f"instanced_{n_instances}_x3_meshes_{width}x{height}"}
 
 

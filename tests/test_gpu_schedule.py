@@ -234,3 +234,27 @@ def test_waves_per_simd_batch(env):
         got, gc = batch.trace(rays, count=True, waves_per_simd=waves)
         torch.cuda.synchronize()
         assert same_bits(got, ref) and same_bits(gc, rc)
+
+
+@pytest.mark.parametrize("kind", ["default", "alpha"])
+def test_tiled_instanced_matches_index_order(env, kind):
+    """The instanced traversal with one wave per 8 x 8 tile equals index
+    order: hits or occluders, instance ids and counters, into sentinel-filled
+    outputs, whole and partial rows of tiles."""
+    torch, rtx = env
+    wl = W.instanced(300, 256, 120)
+    akw = W.instanced_alpha(wl) if kind == "alpha" else {}
+    sc = rtx.InstancedScene(wl["blas"], wl["inst_blas"], wl["inst_m"], wl["world_lo"],
+                            wl["world_hi"], **akw)
+    for n in (wl["rays"].shape[0], wl["rays"].shape[0] - 777, 100):
+        rays = torch.from_numpy(wl["rays"][:n].copy()).cuda()
+        for any_hit in (False, True):
+            announce(f"instanced {kind} n={n} any={any_hit}: tiles of the 256-wide image vs index order")
+            ref, rid, rc = sc.trace(rays, kind, any_hit=any_hit, count=True)
+            out = (torch.full((n,), 7, dtype=torch.int32, device="cuda") if any_hit
+                   else torch.full((n, 4), 7.0, device="cuda"))
+            ids = torch.full((n,), 7, dtype=torch.int32, device="cuda")
+            got, gid, gc = sc.trace(rays, kind, any_hit=any_hit, count=True, out=out, inst_ids=ids,
+                                    image_width=256)
+            torch.cuda.synchronize()
+            assert same_bits(got, ref) and torch.equal(gid, rid) and same_bits(gc, rc)
