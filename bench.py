@@ -448,7 +448,9 @@ def bench_diff(args):
     from paper_1912_12786_amd import workloads as W
     shape = parse_shape(args.shape)
     dev = torch.device("cuda:0")
-    wl = W.diff_scene()
+    width = 512
+    wl = W.diff_scene(width=width, height=width)
+    tw = width if args.schedule == "tiles" else None  # 8x8 tiles of the square image
     scene = rtx.upload_scene(wl.triangles, wl.geom_ids, wl.texcoords, wl.textures, device=dev,
                              max_leaf=args.max_leaf)
     rays = torch.from_numpy(wl.rays).to(dev)
@@ -463,7 +465,8 @@ def bench_diff(args):
     stream = torch.cuda.current_stream(dev)
 
     def fwd():
-        rtx.trace(scene, rays, "alpha", alpha_min=128, out=hits, workspace=ws, shape=shape)
+        rtx.trace(scene, rays, "alpha", alpha_min=128, out=hits, workspace=ws, shape=shape,
+                  image_width=tw)
 
     def fwd_bwd():
         fwd()
@@ -473,7 +476,7 @@ def bench_diff(args):
                             stream.cuda_stream)
 
     def plain():
-        rtx.trace(scene, rays, "default", out=hits, workspace=ws, shape=shape)
+        rtx.trace(scene, rays, "default", out=hits, workspace=ws, shape=shape, image_width=tw)
 
     ms_f = timed(fwd, args.steps, args.warmup, stream)
     ms_fb = timed(fwd_bwd, args.steps, args.warmup, stream)
@@ -485,7 +488,8 @@ def bench_diff(args):
         "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "n_tris": int(wl.faces.shape[0]), "max_leaf": args.max_leaf,
-                   "n_vertices": int(wl.vertices.shape[0]), "n_rays": n},
+                   "n_vertices": int(wl.vertices.shape[0]), "n_rays": n,
+                   "schedule": ("8x8 pixel tiles" if tw else "index order")},
         "forward_mrays_s": round(n / ms_f / 1e3, 2),
         "forward_backward_mrays_s": round(n / ms_fb / 1e3, 2),
         "plain_default_mrays_s": round(n / ms_p / 1e3, 2),

@@ -28,19 +28,20 @@ def _same_cuda_device(**tensors):
 
 class DifferentiableHit(torch.autograd.Function):
     """``tuv, prim, hit = DifferentiableHit.apply(rays, vertices, faces, geom_ids,
-    texcoords, textures, intersector, alpha_min, checker_n, max_leaf)``
+    texcoords, textures, intersector, alpha_min, checker_n, max_leaf, image_width)``
 
     rays float32 [N, 8] and vertices float32 [nv, 3] on one GPU (both may
     require grad; anything else raises ValueError before a launch); faces
     uint32/int32 [n, 3] on any device (copied to the vertices' device);
     geom_ids, texcoords, textures as
     numpy arrays (alpha intersector) or None; max_leaf: leaf size limit of the
-    forward's BVH build (1..7).  Returns tuv float32 [N, 3]
+    forward's BVH build (1..7); image_width: the rays form an image of that
+    width in scanline order, traced in 8 x 8 tiles (same results).  Returns tuv float32 [N, 3]
     (zeros for misses), prim int32 [N] (-1 for misses) and hit bool [N]."""
 
     @staticmethod
     def forward(ctx, rays, vertices, faces, geom_ids, texcoords, textures, intersector="default",
-                alpha_min=128, checker_n=8, max_leaf=4):
+                alpha_min=128, checker_n=8, max_leaf=4, image_width=None):
         _same_cuda_device(rays=rays, vertices=vertices)
         v = vertices.detach()
         f = faces.detach().to(torch.int64)
@@ -48,7 +49,7 @@ class DifferentiableHit(torch.autograd.Function):
         scene = rtx.upload_scene(tris, geom_ids, texcoords, textures, device=rays.device,
                                  max_leaf=max_leaf)
         hits = rtx.trace(scene, rays.detach().contiguous(), intersector, alpha_min=alpha_min,
-                         checker_n=checker_n)
+                         checker_n=checker_n, image_width=image_width)
         prim = hits[:, 1].view(torch.int32).clone()
         hit = prim != -1
         tuv = hits[:, [0, 2, 3]].clone()
@@ -72,7 +73,7 @@ class DifferentiableHit(torch.autograd.Function):
                             vertices.data_ptr(), vertices.shape[0], faces.data_ptr(),
                             faces.shape[0], grad_vertices.data_ptr(), grad_rays.data_ptr(),
                             stream)
-        return grad_rays, grad_vertices, None, None, None, None, None, None, None, None
+        return grad_rays, grad_vertices, None, None, None, None, None, None, None, None, None
 
 
 def hit_backward(rays, hits, grad_tuv, vertices, faces, grad_vertices=None, grad_rays=True):

@@ -157,6 +157,32 @@ def test_autograd_function(diff_setup):
     assert torch.all(tuv[~hit] == 0)
 
 
+def test_autograd_tiled_forward(diff_setup):
+    """The forward with the tiled schedule (image_width) gives the same
+    (t, u, v), primitives and gradients as index order."""
+    import torch
+    from paper_1912_12786_amd import diff
+    wl, tris, scene, bvh = diff_setup
+    announce("DifferentiableHit tiled vs index order on the 512x512 diff rays")
+    V = torch.from_numpy(wl.vertices).cuda()
+    F = torch.from_numpy(wl.faces.astype(np.int32)).cuda()
+    w = torch.from_numpy(wl.weights).cuda()
+    res = []
+    for width in (None, 512):
+        rays = torch.from_numpy(wl.rays).cuda().requires_grad_(True)
+        Vg = V.clone().requires_grad_(True)
+        tuv, prim, hit = diff.DifferentiableHit.apply(rays, Vg, F, wl.geom_ids, wl.texcoords,
+                                                      wl.textures, "alpha", 128, 8, 2, width)
+        (tuv * w).sum().backward()
+        torch.cuda.synchronize()
+        res.append((tuv.detach(), prim, rays.grad, Vg.grad))
+    assert torch.equal(res[0][0].view(torch.int32), res[1][0].view(torch.int32))
+    assert torch.equal(res[0][1], res[1][1])
+    assert torch.equal(res[0][2].view(torch.int32), res[1][2].view(torch.int32))
+    d = (res[0][3] - res[1][3]).norm(dim=1)
+    assert torch.all(d <= 1e-4 * res[0][3].norm(dim=1) + 1e-7 * res[0][3].norm(dim=1).max())
+
+
 def test_host_faces_are_moved_to_the_vertices_device(diff_setup):
     """Faces given as a host tensor reach the backward kernel on the GPU
     (forward keeps a device copy); the gradients equal those of device faces."""
