@@ -30,7 +30,8 @@ def _device_name(torch) -> str:
 
 
 def time_shapes(run, steps: int = 10, warmup: int = 2, shapes=None) -> dict:
-    """Mean milliseconds per call of ``run(shape)`` for each launch shape that
+    """Median milliseconds per call of ``run(shape)`` (HIP events around each
+    call, so that one delayed launch does not decide) for each launch shape that
     the traced scenes can use (compressed- and packed-node scenes run with the
     default shape only, four-wide ones with the default shape and its 16-slot
     variant: the library refuses the others before launching anything).
@@ -50,14 +51,15 @@ def time_shapes(run, steps: int = 10, warmup: int = 2, shapes=None) -> dict:
         for _ in range(warmup):
             run(sh)
         torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(steps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for a, b in ev:
+            a.record(stream)
             run(sh)
-        b.record(stream)
+            b.record(stream)
         torch.cuda.synchronize()
-        times[sh] = a.elapsed_time(b) / steps
+        ms = sorted(a.elapsed_time(b) for a, b in ev)
+        times[sh] = 0.5 * (ms[(steps - 1) // 2] + ms[steps // 2])
     return times
 
 
