@@ -711,8 +711,8 @@ def main():
                          "(rt_bvh_pack), wide4 = 128-B "
                          "four-wide nodes with float32 boxes (rt_bvh_widen). Default: q8 for the "
                          "spheres and batched workloads (measured faster: BVHs beyond the "
-                         "caches), f32p for the alpha-mask closest and any hit on the "
-                         "billboards (measured +1.6 %% closest, +2.6 %% any hit), f32 otherwise")
+                         "caches), f32p for the alpha mask on the billboards (measured +1.6 %% "
+                         "closest, +2.6 %% any hit), f32 otherwise")
     ap.add_argument("--schedule", default="tiles", choices=["tiles", "index"],
                     help="tiles: the image's rays are handed to lanes in 8x8 pixel tiles "
                          "(RT_FLAG_TILE_WIDTH; results and their order unchanged); index: in "
@@ -740,11 +740,8 @@ def main():
         args.max_leaf = 4 if args.workload == "instanced" else 2
     if args.layout is None:
         kind0 = args.intersector or {"billboards": "alpha"}.get(args.workload)
-        # the multi-hit query keeps f32: its fastest launch shape is one the
-        # packed layout is not compiled for
         args.layout = ("q8" if args.workload in ("spheres", "batched") else
-                       "f32p" if ((args.workload, kind0) == ("billboards", "alpha")
-                                  and args.query != "multi") else "f32")
+                       "f32p" if (args.workload, kind0) == ("billboards", "alpha") else "f32")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the traversal shards by rays with no exchange "
               "step, so multi-GPU runs are not part of this benchmark", file=sys.stderr)
@@ -819,23 +816,24 @@ def main():
     ws = rtx.Workspace(dev)
     stream = torch.cuda.current_stream(dev)
     shape_ms = None
+    # rays in scanline order over an image: lanes may take them in tiles
+    width = int(wl.extra["width"]) if (args.schedule == "tiles" and args.ray_order == "scanline"
+                                       and "width" in wl.extra) else None
     if query == "multi" and not args.shape:
         # the k-hit lists favour another launch shape than the closest hit
         # (lanes refilled from the queue lose more coherence over their longer
-        # traversals), so the autotuner picks it here, untimed
+        # traversals), so the autotuner picks it here, untimed, on the same
+        # schedule as the timed launches
         from paper_1912_12786_amd import autotune
         best, shape_ms = autotune.tune(
             f"bench-{wl.name}-{kind}-multi{args.k}",
             lambda sh: rtx.trace(scene, rays, kind, query="multi", k=args.k, alpha_min=128, out=hits,
-                                 workspace=ws, shape=sh),
+                                 workspace=ws, shape=sh, image_width=width),
             cache_path=None, steps=10, warmup=2)
         args.shape = ",".join(map(str, best))
         log(f"autotuner: multi-hit launch shape {args.shape}")
 
     shape = parse_shape(args.shape)
-    # rays in scanline order over an image: lanes may take them in tiles
-    width = int(wl.extra["width"]) if (args.schedule == "tiles" and args.ray_order == "scanline"
-                                       and "width" in wl.extra) else None
     if args.order is None:
         args.order = default_order(args.workload, kind, query)
     lf = args.order == "longest-first"

@@ -32,9 +32,10 @@ def _device_name(torch) -> str:
 def time_shapes(run, steps: int = 10, warmup: int = 2, shapes=None) -> dict:
     """Median milliseconds per call of ``run(shape)`` (HIP events around each
     call, so that one delayed launch does not decide) for each launch shape that
-    the traced scenes can use (compressed- and packed-node scenes run with the
-    default shape only, four-wide ones with the default shape and its 16-slot
-    variant: the library refuses the others before launching anything).
+    the traced scenes can use (compressed-node scenes run with the default
+    shape only, packed-node ones with it and its variant without the queue,
+    four-wide ones with the default shape and its 16-slot variant: the library
+    refuses the others before launching anything).
     ``run`` receives the shape tuple and passes it to its trace calls."""
     import torch
     shapes = shapes or rtx.rt_launch_shapes()

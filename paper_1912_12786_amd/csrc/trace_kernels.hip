@@ -291,17 +291,20 @@ rt_status launch_trace(const TraceRequest &q, const char **err)
     }
 
     const LaunchShape &sh = q.shape;
-    // 48-byte nodes: compiled for the default launch shape only
+    // 48-byte nodes: the default launch shape and its variant without the
+    // queue (a lane per ray, the multi-hit query's fastest)
     if (q.scene->info.layout == RT_LAYOUT_F32P) {
-        constexpr LaunchShape d = kDefaultShape;
-        if (sh.block != d.block || sh.lds_stack != d.lds_stack || sh.chunk != d.chunk ||
-            sh.queue != d.queue || q.runtime_dispatch) {
-            *err = "the packed node layout is compiled for the default launch shape and the "
-                   "compile-time intersectors only";
+        if (q.runtime_dispatch) {
+            *err = "the packed node layout is compiled for the compile-time intersectors only";
             return RT_ERR_UNSUPPORTED;
         }
-        return dispatch_kind<int(d.lds_stack), int(d.block), int(d.chunk), d.queue != 0,
-                             RT_LAYOUT_F32P>(q, a, err);
+        if (sh.block == 64 && sh.lds_stack == 8 && sh.chunk == 64 && sh.queue == 1)
+            return dispatch_kind<8, 64, 64, true, RT_LAYOUT_F32P>(q, a, err);
+        if (sh.block == 64 && sh.lds_stack == 8 && sh.chunk == 64 && sh.queue == 0)
+            return dispatch_kind<8, 64, 64, false, RT_LAYOUT_F32P>(q, a, err);
+        *err = "the packed node layout is compiled for launch shapes (64, 8, 64, 1) and "
+               "(64, 8, 64, 0) only";
+        return RT_ERR_UNSUPPORTED;
     }
     // 32-byte nodes: compiled for the default launch shape only
     if (q.scene->info.layout == RT_LAYOUT_Q8) {

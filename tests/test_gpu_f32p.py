@@ -82,24 +82,38 @@ def test_tiny_f32p_parity(env, oracle_lib, tiny_f32p, kind, query):
         assert same_bits(plain[0], hits)
 
 
-def test_tiny_f32p_launch_shapes(env, tiny_f32p):
-    """Packed-reference scenes run with the default launch shape; the other
-    compiled shapes and the run-time dispatch variants refuse them."""
+def test_tiny_f32p_launch_shapes(env, oracle_lib, tiny_f32p):
+    """Packed-reference scenes run with the default launch shape and its
+    variant without the queue (the same bits); the other compiled shapes and
+    the run-time dispatch variants refuse them."""
     torch, rtx = env
-    wl, ai, sc, _ = tiny_f32p
-    shapes = rtx.rt_launch_shapes()
+    wl, ai, sc, bvh = tiny_f32p
+    shapes = [tuple(s) for s in rtx.rt_launch_shapes()]
     rays = torch.from_numpy(wl.rays).cuda()
     for shape in shapes[1:]:
-        with pytest.raises(rtx.RtxError, match="default launch shape"):
+        if shape == (64, 8, 64, 0):
+            continue
+        with pytest.raises(rtx.RtxError, match="packed node layout"):
             rtx.trace(sc, rays, "alpha", alpha_min=128, shape=shape)
     from tests.test_gpu_dispatch import trace_flags
     for flags in (rtx.RT_FLAG_RUNTIME_SWITCH, rtx.RT_FLAG_RUNTIME_CALL):
         with pytest.raises(rtx.RtxError, match="compile-time intersectors"):
             trace_flags(torch, rtx, sc, rays, "alpha", flags)
-    announce("tiny f32p alpha, default shape after refusals")
-    hits = rtx.trace(sc, rays, "alpha", alpha_min=128)
-    torch.cuda.synchronize()
-    assert (P.hits_to_numpy(hits)["prim"] != MISS).any()
+    announce("tiny f32p alpha, both compiled shapes after refusals")
+    okw = kind_kwargs("alpha", ai)
+    B = oracle_lib.traverse(wl.vertices, bvh, wl.rays, "alpha", layout="f32p", **okw)
+    for shape in ((64, 8, 64, 1), (64, 8, 64, 0)):
+        for query in ("closest", "multi"):
+            out, cnt = rtx.trace(sc, rays, "alpha", alpha_min=128, shape=shape, query=query, k=3,
+                                 count=True)
+            ref, rc = rtx.trace(sc, rays, "alpha", alpha_min=128, query=query, k=3, count=True)
+            torch.cuda.synchronize()
+            if query == "closest":
+                P.assert_exact_vs_b(P.hits_to_numpy(out), B, f"tiny f32p {shape}")
+                P.assert_counters_vs_b(cnt, B, f"tiny f32p {shape}")
+            else:
+                assert same_bits(out[0], ref[0]) and same_bits(out[1], ref[1])
+                assert same_bits(cnt, rc)
 
 
 @pytest.mark.parametrize("seed", range(6))

@@ -99,10 +99,11 @@ def test_tune_scene_chooses_a_build_and_shape(env, oracle_lib, tmp_path):
     sc, choice = autotune.tune_scene("tiny-alpha", wl.vertices, rays, "alpha", cache_path=cache,
                                      leaf_sizes=(2, 4), steps=2, warmup=1, **ai)
     n_shapes = len(rtx.rt_launch_shapes())
-    # f32 builds time every shape, compressed and packed ones the default
-    # shape only, four-wide ones the default shape and its 16-slot variant;
-    # each in index and longest-path-first chunk order
-    assert len(choice["ms"]) == 2 * 2 * (n_shapes + 1 + 1 + 2)
+    # f32 builds time every shape, compressed ones the default shape only,
+    # packed ones the default shape and its variant without the queue,
+    # four-wide ones the default shape and its 16-slot variant; each in index
+    # and longest-path-first chunk order
+    assert len(choice["ms"]) == 2 * 2 * (n_shapes + 1 + 2 + 2)
     # a queue shape's grid size is tuned next, over 4..8 waves per SIMD
     if choice["shape"][3]:
         assert sorted(choice["waves_ms"]) == ["4", "5", "6", "7", "8"]
