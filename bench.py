@@ -62,9 +62,12 @@ def kernel_source_sha() -> str:
 
 def default_order(workload: str, kind: str, query: str) -> str:
     """The chunk order bench.py uses unless ``--order`` names one: longest
-    path first for the alpha-mask closest hit on the billboards, where it was
-    measured faster, ray-index order elsewhere, where it was measured slower."""
-    return "longest-first" if (workload, kind, query) == ("billboards", "alpha", "closest") else "index"
+    path first for the alpha-mask closest and any hit on the billboards,
+    where it was measured faster, ray-index order elsewhere, where it was
+    measured slower (or, for the multi-hit query's lane-per-ray shape, has no
+    queue to order)."""
+    return ("longest-first" if (workload, kind) == ("billboards", "alpha")
+            and query in ("closest", "any") else "index")
 
 
 def find_counters(sha, workload, kind, query, layout, max_leaf, shape, ray_order,
@@ -721,9 +724,10 @@ def main():
     ap.add_argument("--order", default=None, choices=["longest-first", "index"],
                     help="longest-first: chunks of rays handed out by decreasing stretch inside "
                          "the scene box (RT_FLAG_LONGEST_FIRST; results unchanged); default: "
-                         "longest-first for the alpha-mask closest hit on the billboards "
-                         "(measured +7.5 %%), index otherwise (measured -3 to -4 %% with it: "
-                         "accept-all, any hit, the spheres' mixed primary and bounce rays)")
+                         "longest-first for the alpha-mask closest and any hit on the "
+                         "billboards (measured +7.5 %% and +9 %%), index otherwise (measured "
+                         "-0.5 to -3 %% with it: accept-all, the spheres' mixed primary and "
+                         "bounce rays)")
     ap.add_argument("--waves-per-simd", type=int, default=None,
                     help="most resident waves per SIMD of a queue launch's persistent grid "
                          "(RT_FLAG_WAVES_PER_SIMD, 1..15; results unchanged); default: the "
