@@ -489,7 +489,9 @@ rt_status rt_trace_instanced_workspace_bytes(const rt_scene *tlas, const rt_inst
  * rt_alpha_params whose texture array serves every mesh (its texcoords and
  * n_texcoord_prims are ignored: each mesh uses the texture coordinates given
  * to rt_instance_pack, and texture ids come from each mesh's rt_bvh_build).
- * RT_FLAG_COUNT counts the box tests of both levels and the triangle tests. */
+ * RT_FLAG_COUNT counts the box tests of both levels and the triangle tests;
+ * RT_FLAG_TILE_WIDTH gives each wave one 8 x 8 tile of an image's rays
+ * (results unchanged); other flag bits are RT_ERR_UNSUPPORTED. */
 rt_status rt_trace_instanced(const rt_scene *tlas, const void *table, const rt_instance_info *info,
                              const rt_ray *rays, uint32_t n_rays, rt_isect_kind kind,
                              const void *params, uint32_t flags, int any_hit, void *out,
