@@ -94,6 +94,8 @@ def _load():
         lib.orc_widen.restype = C.c_int
         lib.orc_quantize.argtypes = [P, C.c_uint32, P, P, P]
         lib.orc_quantize.restype = C.c_int
+        lib.orc_refit.argtypes = [P, C.c_uint32, P, C.c_uint32, P, C.c_uint32, P]
+        lib.orc_refit.restype = C.c_int
         lib.orc_pack.argtypes = [P, C.c_uint32, P, P]
         lib.orc_pack.restype = C.c_int
         lib.orc_move_word.argtypes = [C.c_float, C.c_uint32, C.c_int, C.POINTER(C.c_float)]
@@ -214,6 +216,24 @@ def build_bvh(vertices, max_leaf: int = 4) -> OracleBVH:
     if rc != 0:
         raise MemoryError("orc_build failed")
     return OracleBVH(nodes[: nn.value].copy(), perm[:n].copy(), int(md.value))
+
+
+def refit(bvh: OracleBVH, vertices, faces) -> OracleBVH:
+    """The same tree with every box recomputed from an indexed mesh
+    (``vertices [nv, 3]`` float32, ``faces [n, 3]`` by input triangle index):
+    boxes grow from (+inf, -inf) by strict comparisons, a triangle's over its
+    vertices 0, 1, 2, a leaf's over its triangles in leaf order, an inner
+    node's over its first child's box then its second's; an index >= nv reads
+    NaN.  Returns a new OracleBVH (the input is unchanged)."""
+    lib = _load()
+    v = np.ascontiguousarray(vertices, np.float32).reshape(-1, 3)
+    f = np.ascontiguousarray(faces, np.uint32).reshape(-1, 3)
+    nodes = bvh.nodes.copy()
+    rc = lib.orc_refit(_ptr(nodes), bvh.n_nodes, _ptr(bvh.perm), int(bvh.perm.size), _ptr(v),
+                       v.shape[0], _ptr(f))
+    if rc != 0:
+        raise ValueError("orc_refit: a leaf references a triangle past the mesh")
+    return OracleBVH(nodes, bvh.perm.copy(), bvh.max_depth)
 
 
 def quantize(bvh: OracleBVH) -> dict:

@@ -527,6 +527,63 @@ int orc_build_leaf(const float *verts, uint32_t n_tris, uint32_t max_leaf, orc_n
 }
 
 /* ======================================================================
+ * Oracle B part 1a': refit to new vertex positions
+ *
+ * Not in the paper; defined in words: the topology stays; every box grows
+ * from (+inf, -inf) by strict comparisons -- a triangle's over its vertices
+ * 0, 1, 2, a leaf's over its triangles in leaf order, an inner node's over its
+ * first child's box, then its second's.  A vertex index >= n_vertices reads
+ * NaN coordinates, which never pass a strict comparison.
+ * ====================================================================== */
+
+/* Grows (lo, hi) by the box (blo, bhi) -- a point when blo == bhi -- with
+ * strict comparisons: a bound moves only to a strictly smaller (larger)
+ * value, so the first of equal values, and its sign of zero, stays. */
+static void grow_strict(float lo[3], float hi[3], const float blo[3], const float bhi[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        if (blo[a] < lo[a]) lo[a] = blo[a];
+        if (bhi[a] > hi[a]) hi[a] = bhi[a];
+    }
+}
+
+/* Recomputes every node box of an oracle BVH (nodes, in place) from the
+ * indexed mesh (vertices [n_vertices][3], faces [n_tris][3] by input
+ * triangle index); perm maps leaf order to input index.  Node ids are
+ * preorder, so children come after their parent and a backward sweep sees
+ * them first. */
+int orc_refit(orc_node *nodes, uint32_t n_nodes, const uint32_t *perm, uint32_t n_tris,
+              const float *vertices, uint32_t n_vertices, const uint32_t *faces)
+{
+    if (n_tris == 0) return 0;
+    for (uint32_t k = n_nodes; k-- > 0;) {
+        orc_node *nd = &nodes[k];
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (nd->count > 0) {
+            for (uint32_t j = nd->first; j < nd->first + nd->count; ++j) {
+                const uint32_t prim = perm[j];
+                if (prim >= n_tris) return -1;
+                for (int c = 0; c < 3; ++c) {
+                    const uint32_t vi = faces[3 * (size_t)prim + c];
+                    float p[3] = {NAN, NAN, NAN};
+                    if (vi < n_vertices)
+                        for (int a = 0; a < 3; ++a) p[a] = vertices[3 * (size_t)vi + a];
+                    grow_strict(lo, hi, p, p);
+                }
+            }
+        } else {
+            grow_strict(lo, hi, nodes[nd->left].lo, nodes[nd->left].hi);
+            grow_strict(lo, hi, nodes[nd->right].lo, nodes[nd->right].hi);
+        }
+        for (int a = 0; a < 3; ++a) {
+            nd->lo[a] = lo[a];
+            nd->hi[a] = hi[a];
+        }
+    }
+    return 0;
+}
+
+/* ======================================================================
  * Oracle B part 1b: the 32-byte node layout (8-bit child boxes)
  *
  * Not in the paper (its BVH format is open); the layout is defined in words:
