@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "librtx.so")
-SOURCES = ["rtx_capi.cpp", "bvh_build.cpp", "trace_kernels.hip", "hit_backward.hip"]
+SOURCES = ["rtx_capi.cpp", "bvh_build.cpp", "trace_kernels.hip", "hit_backward.hip",
+           "bvh_refit.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1,8 +1,10 @@
 """Differentiable closest hit: ``(t, u, v)`` of the nearest accepted hit as a
 function of the rays and of the mesh's vertex positions.
 
-Forward: host BVH build over ``vertices[faces]`` (rt_bvh_build) and one
-rt_trace_closest launch with the chosen intersector.  Backward: one
+Forward: host BVH build over ``vertices[faces]`` (rt_bvh_build) -- or, given
+a ``rtx.RefitScene`` built once from the mesh, a device refit of that tree to
+the current vertices (rt_bvh_refit) -- and one rt_trace_closest launch with
+the chosen intersector.  Backward: one
 rt_hit_backward launch (implicit differentiation of o + t d = P(u, v) for the
 fixed hit triangle).  The hit triangle and the intersector's decision are
 discrete and are not differentiated; misses return zeros with zero gradient.
@@ -28,7 +30,8 @@ def _same_cuda_device(**tensors):
 
 class DifferentiableHit(torch.autograd.Function):
     """``tuv, prim, hit = DifferentiableHit.apply(rays, vertices, faces, geom_ids,
-    texcoords, textures, intersector, alpha_min, checker_n, max_leaf, image_width)``
+    texcoords, textures, intersector, alpha_min, checker_n, max_leaf, image_width,
+    refit)``
 
     rays float32 [N, 8] and vertices float32 [nv, 3] on one GPU (both may
     require grad; anything else raises ValueError before a launch); faces
@@ -36,18 +39,25 @@ class DifferentiableHit(torch.autograd.Function):
     geom_ids, texcoords, textures as
     numpy arrays (alpha intersector) or None; max_leaf: leaf size limit of the
     forward's BVH build (1..7); image_width: the rays form an image of that
-    width in scanline order, traced in 8 x 8 tiles (same results).  Returns tuv float32 [N, 3]
+    width in scanline order, traced in 8 x 8 tiles (same results); refit: a
+    ``rtx.RefitScene`` of this mesh (its faces, texture data and leaf limit
+    replace the arguments'), refitted on the device to ``vertices`` instead
+    of a host rebuild.  Returns tuv float32 [N, 3]
     (zeros for misses), prim int32 [N] (-1 for misses) and hit bool [N]."""
 
     @staticmethod
     def forward(ctx, rays, vertices, faces, geom_ids, texcoords, textures, intersector="default",
-                alpha_min=128, checker_n=8, max_leaf=4, image_width=None):
+                alpha_min=128, checker_n=8, max_leaf=4, image_width=None, refit=None):
         _same_cuda_device(rays=rays, vertices=vertices)
         v = vertices.detach()
-        f = faces.detach().to(torch.int64)
-        tris = v.cpu().numpy()[f.cpu().numpy()]
-        scene = rtx.upload_scene(tris, geom_ids, texcoords, textures, device=rays.device,
-                                 max_leaf=max_leaf)
+        if refit is not None:
+            scene = refit.update(v.contiguous())
+            f = refit.faces
+        else:
+            f = faces.detach().to(torch.int64)
+            tris = v.cpu().numpy()[f.cpu().numpy()]
+            scene = rtx.upload_scene(tris, geom_ids, texcoords, textures, device=rays.device,
+                                     max_leaf=max_leaf)
         hits = rtx.trace(scene, rays.detach().contiguous(), intersector, alpha_min=alpha_min,
                          checker_n=checker_n, image_width=image_width)
         prim = hits[:, 1].view(torch.int32).clone()
@@ -73,7 +83,7 @@ class DifferentiableHit(torch.autograd.Function):
                             vertices.data_ptr(), vertices.shape[0], faces.data_ptr(),
                             faces.shape[0], grad_vertices.data_ptr(), grad_rays.data_ptr(),
                             stream)
-        return grad_rays, grad_vertices, None, None, None, None, None, None, None, None, None
+        return grad_rays, grad_vertices, None, None, None, None, None, None, None, None, None, None
 
 
 def hit_backward(rays, hits, grad_tuv, vertices, faces, grad_vertices=None, grad_rays=True):

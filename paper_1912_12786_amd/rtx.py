@@ -111,6 +111,9 @@ SIGNATURES = [
     ("rt_bvh_compress", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_bvh_widen", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_bvh_pack", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
+    ("rt_bvh_refit_plan", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, _P, _U32,
+                                    C.POINTER(C.c_uint32)]),
+    ("rt_bvh_refit", C.c_int, [C.POINTER(rt_scene), _P, _P, _U32, _P, _U32, _P, _P, _P]),
     ("rt_trace_workspace_bytes", C.c_int, [C.POINTER(rt_scene), _U32, _U32, C.POINTER(_SZ)]),
     ("rt_trace_closest", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                    _SZ, _P]),
@@ -553,6 +556,26 @@ def rt_bvh_pack(nodes: np.ndarray, info: rt_bvh_info):
     return out.view(np.uint8)[: n * RT_NODE_BYTES_F32P], oinfo
 
 
+def rt_bvh_refit_plan(nodes: np.ndarray, info: rt_bvh_info):
+    """The refit plan of a built tree (64-byte nodes): ``(order uint32
+    [n_nodes], level_start uint32 [n_levels + 1])``, inner nodes by depth,
+    deepest first (both empty for a root leaf)."""
+    n = int(info.n_nodes)
+    src = np.ascontiguousarray(nodes, np.uint8)
+    src16 = np.zeros(max(1, n * RT_NODE_BYTES // 16), dtype=np.dtype((np.void, 16)))
+    src16.view(np.uint8)[: n * RT_NODE_BYTES] = src[: n * RT_NODE_BYTES]
+    order = np.zeros(max(1, n), np.uint32)
+    cap = int(info.max_depth) + 2
+    level_start = np.zeros(cap, np.uint32)
+    nl = C.c_uint32()
+    _check(load_library().rt_bvh_refit_plan(src16.ctypes.data if n else None, C.byref(info),
+                                             order.ctypes.data, n, level_start.ctypes.data, cap,
+                                             C.byref(nl)), "rt_bvh_refit_plan")
+    if nl.value == 0:
+        return np.zeros(0, np.uint32), np.zeros(0, np.uint32)
+    return order[:n].copy(), level_start[: nl.value + 1].copy()
+
+
 def rt_bvh_widen(nodes: np.ndarray, info: rt_bvh_info):
     """64-byte binary nodes (from rt_bvh_build) -> 128-byte four-wide nodes.
     Returns ``(nodes uint8, info)`` with ``info.layout = 2``, ``info.n_nodes``
@@ -592,6 +615,59 @@ def upload_scene(vertices, geom_ids=None, texcoords=None, textures=None, device=
     tx = None if textures is None else torch.from_numpy(
         np.ascontiguousarray(textures, np.uint32).view(np.int32)).to(device)
     return Scene(dn, dt, info, tc, tx)
+
+
+class RefitScene:
+    """A scene built once from an indexed mesh whose vertices then move:
+    ``update(vertices)`` refits it on the device (rt_bvh_refit, the topology
+    kept) instead of rebuilding it on the host.  ``scene`` is the traceable
+    Scene (64-byte nodes); ``faces`` stays on the device."""
+
+    def __init__(self, vertices, faces, geom_ids=None, texcoords=None, textures=None,
+                 device="cuda", max_leaf: int = 4):
+        torch = _torch()
+        v = np.ascontiguousarray(vertices, np.float32).reshape(-1, 3)
+        f = np.ascontiguousarray(faces, np.int64).reshape(-1, 3)
+        if f.size and (f.min() < 0 or f.max() >= v.shape[0]):
+            raise ValueError("faces must index the vertices")
+        nodes, tris, info = rt_bvh_build(v[f], geom_ids, max_leaf)
+        order, self.level_start = rt_bvh_refit_plan(nodes, info)
+        dn = torch.from_numpy(nodes.copy()).to(device) if nodes.size else None
+        dt = torch.from_numpy(tris.copy()).to(device)
+        tc = None if texcoords is None else torch.from_numpy(
+            np.ascontiguousarray(texcoords, np.float32)).to(device)
+        tx = None if textures is None else torch.from_numpy(
+            np.ascontiguousarray(textures, np.uint32).view(np.int32)).to(device)
+        self.scene = Scene(dn, dt, info, tc, tx)
+        self.order = torch.from_numpy(order).to(device) if order.size else None
+        self.faces = torch.from_numpy(f.astype(np.int32)).to(device)
+        self.n_vertices = v.shape[0]
+        self.root_box = torch.empty(6, dtype=torch.float32, device=device)
+
+    def update(self, vertices, stream=None):
+        """Refits to ``vertices`` (device float32 [n_vertices, 3]) and sets the
+        scene's root box (one 24-byte copy to the host, which waits for the
+        refit)."""
+        torch = _torch()
+        if (vertices.dtype != torch.float32 or vertices.dim() != 2 or vertices.shape[1] != 3
+                or not vertices.is_contiguous() or vertices.shape[0] != self.n_vertices):
+            raise ValueError(f"vertices must be a contiguous float32 [{self.n_vertices}, 3] tensor")
+        if vertices.device != self.faces.device:
+            raise ValueError("vertices must be on the scene's device")
+        with _on_stream(vertices.device, stream) as s:
+            ls = self.level_start
+            sc = self.scene.view
+            _check(load_library().rt_bvh_refit(
+                C.byref(sc), None if self.order is None else self.order.data_ptr(),
+                ls.ctypes.data if ls.size else None, max(0, ls.size - 1), vertices.data_ptr(),
+                self.n_vertices, self.faces.data_ptr(), self.root_box.data_ptr(), s),
+                "rt_bvh_refit")
+            if int(self.scene.info.n_tris) > 0:
+                box = self.root_box.cpu().numpy()
+                for a in range(3):
+                    self.scene.info.root_lo[a] = float(box[a])
+                    self.scene.info.root_hi[a] = float(box[3 + a])
+        return self.scene
 
 
 def _params(scene: Scene, intersector: str, alpha_min: int, checker_n: int):
