@@ -481,9 +481,32 @@ def bench_diff(args):
     def plain():
         rtx.trace(scene, rays, "default", out=hits, workspace=ws, shape=shape, image_width=tw)
 
+    # moving geometry: the same forward on a tree refitted on the device to
+    # the vertices every step (rt_bvh_refit, then the 24-byte root box to the
+    # host), against rebuilding the tree on the host (timed by wall clock)
+    rs = rtx.RefitScene(wl.vertices, wl.faces, wl.geom_ids, wl.texcoords, wl.textures,
+                        device=dev, max_leaf=args.max_leaf)
+
+    def refit_only():
+        rs.update(V)
+
+    def refit_fwd():
+        rs.update(V)
+        rtx.trace(rs.scene, rays, "alpha", alpha_min=128, out=hits, workspace=ws, shape=shape,
+                  image_width=tw)
+
     ms_f = timed(fwd, args.steps, args.warmup, stream)
     ms_fb = timed(fwd_bwd, args.steps, args.warmup, stream)
     ms_p = timed(plain, args.steps, args.warmup, stream)
+    ms_r = timed(refit_only, args.steps, args.warmup, stream)
+    ms_rf = timed(refit_fwd, args.steps, args.warmup, stream)
+    rebuild = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        rtx.upload_scene(wl.triangles, wl.geom_ids, wl.texcoords, wl.textures, device=dev,
+                         max_leaf=args.max_leaf)
+        torch.cuda.synchronize()
+        rebuild.append((time.perf_counter() - t0) * 1e3)
     emit({
         "metric": "Mrays/s differentiable closest hit (alpha mask): forward, forward+backward, "
                   "plain default-intersector kernel on the same scene",
@@ -496,8 +519,11 @@ def bench_diff(args):
         "forward_mrays_s": round(n / ms_f / 1e3, 2),
         "forward_backward_mrays_s": round(n / ms_fb / 1e3, 2),
         "plain_default_mrays_s": round(n / ms_p / 1e3, 2),
+        "refit_forward_mrays_s": round(n / ms_rf / 1e3, 2),
         "ms": {"forward": round(ms_f, 4), "forward_backward": round(ms_fb, 4),
-               "plain_default": round(ms_p, 4)},
+               "plain_default": round(ms_p, 4), "device_refit": round(ms_r, 4),
+               "device_refit_forward": round(ms_rf, 4),
+               "host_rebuild_upload": round(float(np.median(rebuild)), 2)},
     })
     del diff
 
@@ -738,7 +764,8 @@ def main():
                     choices=["billboards", "tiny", "spheres", "diff", "batched", "dispatch",
                              "instanced"],
                     help="diff = differentiable hit on the perturbed icosphere (forward, "
-                         "forward+backward and the plain kernel), reported on its own line")
+                         "forward+backward, the plain kernel, and the forward on a tree "
+                         "refitted on the device), reported on its own line")
     args = ap.parse_args()
     if args.max_leaf is None:
         args.max_leaf = 4 if args.workload == "instanced" else 2
