@@ -40,6 +40,10 @@ PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1912_12786_amd", "csrc", f)
                   for f in ("rt_traverse.hpp", "trace_kernels.hip", "rt_launch.hpp",
                             "rt_batch_layout.hpp")]
+# the differentiable hit's other kernels (adjoint, refit), hashed apart so that
+# the traversal's counter records stay keyed to the traversal sources alone
+AUX_KERNEL_SOURCES = [os.path.join(ROOT, "paper_1912_12786_amd", "csrc", f)
+                      for f in ("hit_backward.hip", "bvh_refit.hip")]
 
 
 def log(*a):
@@ -52,9 +56,9 @@ def emit(line: dict):
     print(json.dumps(line), flush=True)
 
 
-def kernel_source_sha() -> str:
+def kernel_source_sha(sources=None) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -524,6 +528,7 @@ def bench_diff(args):
                "plain_default": round(ms_p, 4), "device_refit": round(ms_r, 4),
                "device_refit_forward": round(ms_rf, 4),
                "host_rebuild_upload": round(float(np.median(rebuild)), 2)},
+        "aux_kernel_source_sha": kernel_source_sha(AUX_KERNEL_SOURCES),
     })
     del diff
 

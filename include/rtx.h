@@ -321,18 +321,16 @@ rt_status rt_bvh_widen(const void *nodes, const rt_bvh_info *info, void *out, si
 rt_status rt_bvh_pack(const void *nodes, const rt_bvh_info *info, void *out, size_t out_cap,
                       rt_bvh_info *out_info);
 
-/* Refit plan of a built BVH (host, 64-byte nodes from rt_bvh_build): the
- * inner nodes grouped by depth, deepest first, for rt_bvh_refit.
- *   order        host output, info->n_nodes node numbers (order_cap entries)
- *   level_start  host output, n_levels + 1 offsets into order: level l
- *                (l = 0 the deepest) is order[level_start[l] .. level_start[l+1])
- *                (level_cap entries; max_depth + 2 always suffice)
- *   n_levels     output; 0 for a root leaf or an empty tree (nothing to plan)
+/* Refit plan of a built BVH (host, 64-byte nodes from rt_bvh_build), for
+ * rt_bvh_refit: plan[k] = 2 * p + c when inner node k is child c (0 or 1)
+ * of inner node p, and 0xFFFFFFFF for the root (node 0).
+ *   plan  host output, info->n_nodes words (plan_cap entries); untouched for
+ *         a root leaf or an empty tree (nothing to plan)
  * Fails for another layout (RT_ERR_UNSUPPORTED) or a tree whose child
- * references do not point to later nodes. */
-rt_status rt_bvh_refit_plan(const void *nodes, const rt_bvh_info *info, uint32_t *order,
-                            size_t order_cap, uint32_t *level_start, uint32_t level_cap,
-                            uint32_t *n_levels);
+ * references do not point to later nodes, each node below the root from
+ * exactly one parent. */
+rt_status rt_bvh_refit_plan(const void *nodes, const rt_bvh_info *info, uint32_t *plan,
+                            size_t plan_cap);
 
 /* Refit (device): the scene's triangle records and node boxes recomputed in
  * place from new vertex positions, the topology unchanged -- for geometry
@@ -350,15 +348,19 @@ rt_status rt_bvh_refit_plan(const void *nodes, const rt_bvh_info *info, uint32_t
  * triangle is never hit.  root_box (device, 6 floats: lo.xyz, hi.xyz)
  * receives the new root box, which the caller copies into the scene's
  * rt_bvh_info.root_lo/root_hi before tracing (the traversal's root test
- * reads the host info).  order and level_start are rt_bvh_refit_plan's
- * (order copied to the device, level_start on the host).  The scene's node
- * and triangle buffers are written (one launch for the triangles, one per
- * level): calls must be ordered against traces of the same scene on one
- * stream.  Boxes stay exact as the vertices move; their quality drops with
- * distance from the built positions.  RT_LAYOUT_F32 scenes only. */
-rt_status rt_bvh_refit(const rt_scene *scene, const uint32_t *order, const uint32_t *level_start,
-                       uint32_t n_levels, const float *vertices, uint32_t n_vertices,
-                       const uint32_t *faces, float *root_box, void *stream);
+ * reads the host info).
+ *   plan      device, rt_bvh_refit_plan's words (NULL for a root leaf)
+ *   counters  device scratch, n_nodes uint32 (contents need no
+ *             initialisation; NULL for a root leaf)
+ * Two launches: the triangle records, then every node's box bottom-up, a
+ * lane per inner node climbing while it completes nodes.  The scene's node
+ * and triangle buffers and the counters are written: calls must be ordered
+ * against each other and against traces of the same scene on one stream.
+ * Boxes stay exact as the vertices move; their quality drops with distance
+ * from the built positions.  RT_LAYOUT_F32 scenes only. */
+rt_status rt_bvh_refit(const rt_scene *scene, const uint32_t *plan, uint32_t *counters,
+                       const float *vertices, uint32_t n_vertices, const uint32_t *faces,
+                       float *root_box, void *stream);
 
 /* Device workspace a trace call needs (bytes, possibly 0): the ray queue
  * head of persistent launch shapes and overflow space for traversal stacks

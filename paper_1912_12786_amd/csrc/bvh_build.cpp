@@ -398,34 +398,25 @@ rt_status compress_nodes(const NodeRecord *in, uint32_t n_nodes, NodeQ8Record *o
 }
 
 // -------------------------------------------------------------------------
-// Refit plan: depths by one preorder sweep (an inner child's number is larger
-// than its parent's), then a counting sort by depth, deepest first.
+// Refit plan: each inner node's parent and slot, from the parents' child
+// references (an inner child's number is larger than its parent's).
 // -------------------------------------------------------------------------
-uint32_t refit_plan(const NodeRecord *nodes, const rt_bvh_info &info, uint32_t *order,
-                    uint32_t *level_start, uint32_t level_cap)
+bool refit_parents(const NodeRecord *nodes, const rt_bvh_info &info, uint32_t *parent)
 {
     const uint32_t n = info.n_nodes;
-    if (n == 0 || (info.root_ref >> 29) != 0) return 0;
-    std::vector<uint32_t> depth(n, 0);
-    uint32_t deepest = 0;
+    for (uint32_t k = 0; k < n; ++k) parent[k] = kRefitNoParent;
+    uint32_t linked = 0;
     for (uint32_t k = 0; k < n; ++k) {
-        for (int c = 0; c < 2; ++c) {
+        for (uint32_t c = 0; c < 2; ++c) {
             const uint32_t ref = nodes[k].u[12 + c];
             if ((ref >> 29) != 0) continue;
             const uint32_t ch = ref & kRefIndexMaskHost;
-            if (ch <= k || ch >= n) return UINT32_MAX;
-            depth[ch] = depth[k] + 1;
-            deepest = depth[ch] > deepest ? depth[ch] : deepest;
+            if (ch <= k || ch >= n || parent[ch] != kRefitNoParent) return false;
+            parent[ch] = 2 * k + c;
+            ++linked;
         }
     }
-    const uint32_t levels = deepest + 1;
-    if (levels > level_cap) return UINT32_MAX;
-    std::vector<uint32_t> count(levels + 1, 0);
-    for (uint32_t k = 0; k < n; ++k) ++count[deepest - depth[k] + 1];
-    for (uint32_t l = 0; l < levels; ++l) count[l + 1] += count[l];
-    for (uint32_t l = 0; l <= levels; ++l) level_start[l] = count[l];
-    for (uint32_t k = 0; k < n; ++k) order[count[deepest - depth[k]]++] = k;
-    return levels;
+    return n == 0 || linked == n - 1;  // every node but the root has one parent
 }
 
 // -------------------------------------------------------------------------

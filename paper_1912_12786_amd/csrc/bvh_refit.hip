@@ -11,11 +11,17 @@
 // returns the build's boxes bit for bit, signs of zero included.  A vertex
 // index past the mesh reads NaN, which no strict comparison accepts.
 //
-// One lane per triangle rewrites the records; then one launch per tree
-// level, deepest first (the host plan from rt_bvh_refit_plan), gives each
-// inner node of that level a lane that writes its two child boxes: a leaf
-// child's from its triangles' vertices, an inner child's from the child's
-// own record, written by the previous launch.
+// Two launches.  The first rewrites the triangle records (a lane per
+// triangle) and zeroes one arrival counter per inner node.  The second gives
+// each inner node a lane that writes the boxes of its leaf children into the
+// node and adds their number to the node's counter; every inner child adds
+// one when its own box is in place.  The lane whose addition completes a
+// node's two children (the counter reaching 2) computes that node's box,
+// writes it into the parent's slot (the host plan's parent words) and adds
+// one there, and so on up; the root's completer writes the root box.  No
+// lane waits: every other lane stops at its first incomplete node.  The
+// additions are acquire-release at device scope, so a completer reads the
+// slot its sibling's lane wrote before adding.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -79,9 +85,13 @@ __device__ __forceinline__ void grow_leaf(const refit_mesh &m, const TriRecord *
     }
 }
 
-__global__ __launch_bounds__(kRefitBlock) void refit_tris_kernel(TriRecord *tris, refit_mesh m)
+// Triangle records, and the counters zeroed (a lane per triangle or node).
+__global__ __launch_bounds__(kRefitBlock) void refit_tris_kernel(TriRecord *tris, refit_mesh m,
+                                                                 uint32_t *counters,
+                                                                 uint32_t n_nodes)
 {
     const uint32_t i = blockIdx.x * kRefitBlock + threadIdx.x;
+    if (i < n_nodes) counters[i] = 0;
     if (i >= m.n_tris) return;
     TriRecord &t = tris[i];
     const uint32_t prim = t.u[3];
@@ -97,50 +107,67 @@ __global__ __launch_bounds__(kRefitBlock) void refit_tris_kernel(TriRecord *tris
     }
 }
 
-// The inner nodes order[first .. first + count) of one level: both child
-// boxes; the root (node 0) also writes the root box.
-__global__ __launch_bounds__(kRefitBlock) void refit_level_kernel(NodeRecord *nodes,
-                                                                  const TriRecord *tris,
-                                                                  const uint32_t *order,
-                                                                  uint32_t first, uint32_t count,
-                                                                  refit_mesh m, float *root_box)
+__device__ __forceinline__ void store_slot(NodeRecord &nd, uint32_t c, const float lo[3],
+                                           const float hi[3])
 {
-    const uint32_t k = blockIdx.x * kRefitBlock + threadIdx.x;
-    if (k >= count) return;
-    const uint32_t n = order[first + k];
-    NodeRecord &nd = nodes[n];
-    float lo[2][3], hi[2][3];
-    for (int c = 0; c < 2; ++c) {
-        const uint32_t ref = nd.u[12 + c];
-        const uint32_t cnt = ref >> 29, idx = ref & kRefIndexMaskHost;
-        empty_box(lo[c], hi[c]);
-        if (cnt) {
-            grow_leaf(m, tris, idx, cnt, lo[c], hi[c]);
-        } else {
-            const NodeRecord &ch = nodes[idx];
-            const float l0[3] = {ch.f[0], ch.f[1], ch.f[2]}, h0[3] = {ch.f[3], ch.f[4], ch.f[5]};
-            const float l1[3] = {ch.f[6], ch.f[7], ch.f[8]}, h1[3] = {ch.f[9], ch.f[10], ch.f[11]};
-            grow(lo[c], hi[c], l0, h0);
-            grow(lo[c], hi[c], l1, h1);
-        }
-    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        nd.f[a] = lo[0][a];
-        nd.f[3 + a] = hi[0][a];
-        nd.f[6 + a] = lo[1][a];
-        nd.f[9 + a] = hi[1][a];
+        nd.f[6 * c + a] = lo[a];
+        nd.f[6 * c + 3 + a] = hi[a];
     }
-    if (n == 0 && root_box) {
-        float rlo[3], rhi[3];
-        empty_box(rlo, rhi);
-        grow(rlo, rhi, lo[0], hi[0]);
-        grow(rlo, rhi, lo[1], hi[1]);
+}
+
+// Adds `arrivals` to node n's counter; true if that completes both children.
+__device__ __forceinline__ bool arrive(uint32_t *counters, uint32_t n, uint32_t arrivals)
+{
+    const uint32_t before = __hip_atomic_fetch_add(counters + n, arrivals, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    return before + arrivals == 2;
+}
+
+__global__ __launch_bounds__(kRefitBlock) void refit_nodes_kernel(NodeRecord *nodes,
+                                                                  uint32_t n_nodes,
+                                                                  const TriRecord *tris,
+                                                                  const uint32_t *parents,
+                                                                  uint32_t *counters, refit_mesh m,
+                                                                  float *root_box)
+{
+    uint32_t n = blockIdx.x * kRefitBlock + threadIdx.x;
+    if (n >= n_nodes) return;
+    uint32_t leaves = 0;
+    for (uint32_t c = 0; c < 2; ++c) {
+        const uint32_t ref = nodes[n].u[12 + c];
+        const uint32_t cnt = ref >> 29;
+        if (cnt == 0) continue;
+        float lo[3], hi[3];
+        empty_box(lo, hi);
+        grow_leaf(m, tris, ref & kRefIndexMaskHost, cnt, lo, hi);
+        store_slot(nodes[n], c, lo, hi);
+        ++leaves;
+    }
+    if (leaves == 0 || !arrive(counters, n, leaves)) return;
+    // n's children are in place: climb while this lane completes nodes
+    for (;;) {
+        const NodeRecord &nd = nodes[n];
+        const float l0[3] = {nd.f[0], nd.f[1], nd.f[2]}, h0[3] = {nd.f[3], nd.f[4], nd.f[5]};
+        const float l1[3] = {nd.f[6], nd.f[7], nd.f[8]}, h1[3] = {nd.f[9], nd.f[10], nd.f[11]};
+        float lo[3], hi[3];
+        empty_box(lo, hi);
+        grow(lo, hi, l0, h0);
+        grow(lo, hi, l1, h1);
+        const uint32_t up = parents[n];
+        if (up == kRefitNoParent) {  // the root
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            root_box[a] = rlo[a];
-            root_box[3 + a] = rhi[a];
+            for (int a = 0; a < 3; ++a) {
+                root_box[a] = lo[a];
+                root_box[3 + a] = hi[a];
+            }
+            return;
         }
+        const uint32_t p = up >> 1;
+        store_slot(nodes[p], up & 1u, lo, hi);
+        if (!arrive(counters, p, 1)) return;
+        n = p;
     }
 }
 
@@ -166,21 +193,17 @@ rt_status launch_refit(const RefitRequest &q, const char **err)
     refit_mesh m{q.vertices, q.faces, q.n_vertices, q.n_tris};
     TriRecord *tris = static_cast<TriRecord *>(q.tris);
     NodeRecord *nodes = static_cast<NodeRecord *>(q.nodes);
-    if (q.n_tris > 0)
-        hipLaunchKernelGGL(refit_tris_kernel, dim3((q.n_tris + kRefitBlock - 1) / kRefitBlock),
-                           dim3(kRefitBlock), 0, s, tris, m);
-    if (q.n_levels == 0) {  // a root leaf (or no triangles)
-        if (q.root_count > 0 && q.root_box)
-            hipLaunchKernelGGL(refit_root_leaf_kernel, dim3(1), dim3(64), 0, s, tris, q.root_first,
-                               q.root_count, m, q.root_box);
-    }
-    for (uint32_t l = 0; l < q.n_levels; ++l) {
-        const uint32_t first = q.level_start[l], count = q.level_start[l + 1] - first;
-        if (count == 0) continue;
-        hipLaunchKernelGGL(refit_level_kernel, dim3((count + kRefitBlock - 1) / kRefitBlock),
-                           dim3(kRefitBlock), 0, s, nodes, tris, q.order, first, count, m,
-                           q.root_box);
-    }
+    const uint32_t lanes = q.n_tris > q.n_nodes ? q.n_tris : q.n_nodes;
+    if (lanes > 0)
+        hipLaunchKernelGGL(refit_tris_kernel, dim3((lanes + kRefitBlock - 1) / kRefitBlock),
+                           dim3(kRefitBlock), 0, s, tris, m, q.counters, q.n_nodes);
+    if (q.n_nodes > 0)
+        hipLaunchKernelGGL(refit_nodes_kernel, dim3((q.n_nodes + kRefitBlock - 1) / kRefitBlock),
+                           dim3(kRefitBlock), 0, s, nodes, q.n_nodes, tris, q.parents, q.counters,
+                           m, q.root_box);
+    else if (q.root_count > 0)
+        hipLaunchKernelGGL(refit_root_leaf_kernel, dim3(1), dim3(64), 0, s, tris, q.root_first,
+                           q.root_count, m, q.root_box);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         *err = hipGetErrorString(e);

@@ -165,25 +165,24 @@ struct InstancedRequest {
     void *stream;
 };
 
-// Refit plan of a built BVH: the inner nodes by depth, deepest first
-// (order[n_nodes]); level_start[l] .. level_start[l + 1] is level l of
-// n_levels (l = 0 the deepest).  Returns n_levels, or UINT32_MAX if a child
-// reference is out of range or the levels exceed level_cap.
-uint32_t refit_plan(const NodeRecord *nodes, const rt_bvh_info &info, uint32_t *order,
-                    uint32_t *level_start, uint32_t level_cap);
+// Refit plan of a built BVH: parent[k] = 2 * (k's parent) + (k's slot in
+// it) for every inner node k but the root, kRefitNoParent for the root.
+// false if a child reference is not a later node or a node has no parent.
+constexpr uint32_t kRefitNoParent = 0xFFFFFFFFu;
+bool refit_parents(const NodeRecord *nodes, const rt_bvh_info &info, uint32_t *parent);
 
 struct RefitRequest {
     void *nodes;              // device, n_nodes 64-byte records (rewritten)
+    uint32_t n_nodes;
     void *tris;               // device, n_tris triangle records (rewritten)
     uint32_t n_tris;
-    const uint32_t *order;    // device, the plan's node order
-    const uint32_t *level_start;  // host, n_levels + 1 offsets into order
-    uint32_t n_levels;
-    uint32_t root_first, root_count;  // a root leaf's triangles (n_levels == 0)
+    const uint32_t *parents;  // device, the plan (n_nodes words)
+    uint32_t *counters;       // device, n_nodes words of scratch
+    uint32_t root_first, root_count;  // a root leaf's triangles (n_nodes == 0)
     const float *vertices;    // device [n_vertices][3]
     uint32_t n_vertices;
     const uint32_t *faces;    // device [n_tris][3]
-    float *root_box;          // device, 6 floats out (may be null)
+    float *root_box;          // device, 6 floats out
     void *stream;
 };
 rt_status launch_refit(const RefitRequest &req, const char **err);

@@ -308,31 +308,26 @@ rt_status rt_bvh_compress(const void *nodes, const rt_bvh_info *info, void *out,
     return RT_OK;
 }
 
-rt_status rt_bvh_refit_plan(const void *nodes, const rt_bvh_info *info, uint32_t *order,
-                            size_t order_cap, uint32_t *level_start, uint32_t level_cap,
-                            uint32_t *n_levels)
+rt_status rt_bvh_refit_plan(const void *nodes, const rt_bvh_info *info, uint32_t *plan,
+                            size_t plan_cap)
 {
     g_last_error.clear();
-    if (!info || !n_levels) return fail(RT_ERR_INVALID_ARG, "info/n_levels are NULL");
+    if (!info) return fail(RT_ERR_INVALID_ARG, "info is NULL");
     if (info->layout != RT_LAYOUT_F32) return fail(RT_ERR_UNSUPPORTED, "refit takes RT_LAYOUT_F32 trees");
-    *n_levels = 0;
     if (info->n_nodes == 0 || (info->root_ref >> 29) != 0) return RT_OK;  // a root leaf
-    if (!nodes || !order || !level_start) return fail(RT_ERR_INVALID_ARG, "nodes/order/level_start are NULL");
-    if (order_cap < info->n_nodes) return fail(RT_ERR_INVALID_ARG, "order smaller than n_nodes");
+    if (!nodes || !plan) return fail(RT_ERR_INVALID_ARG, "nodes/plan are NULL");
+    if (plan_cap < info->n_nodes) return fail(RT_ERR_INVALID_ARG, "plan smaller than n_nodes");
     if ((info->root_ref & kRefIndexMaskHost) != 0)
         return fail(RT_ERR_INVALID_ARG, "the root is not node 0 (not a tree from rt_bvh_build)");
-    const uint32_t levels = refit_plan(static_cast<const NodeRecord *>(nodes), *info, order,
-                                       level_start, level_cap ? level_cap - 1 : 0);
-    if (levels == UINT32_MAX)
-        return fail(RT_ERR_INVALID_ARG, "a child reference is not a later node, or level_start "
-                                        "has fewer than depth + 2 entries");
-    *n_levels = levels;
+    if (!refit_parents(static_cast<const NodeRecord *>(nodes), *info, plan))
+        return fail(RT_ERR_INVALID_ARG, "a child reference is not a later node, or a node is not "
+                                        "the child of exactly one node");
     return RT_OK;
 }
 
-rt_status rt_bvh_refit(const rt_scene *scene, const uint32_t *order, const uint32_t *level_start,
-                       uint32_t n_levels, const float *vertices, uint32_t n_vertices,
-                       const uint32_t *faces, float *root_box, void *stream)
+rt_status rt_bvh_refit(const rt_scene *scene, const uint32_t *plan, uint32_t *counters,
+                       const float *vertices, uint32_t n_vertices, const uint32_t *faces,
+                       float *root_box, void *stream)
 {
     g_last_error.clear();
     rt_status st = check_scene(scene);
@@ -344,28 +339,22 @@ rt_status rt_bvh_refit(const rt_scene *scene, const uint32_t *order, const uint3
     if (!aligned(vertices, 4) || !aligned(faces, 4) || !aligned(root_box, 4))
         return fail(RT_ERR_MISALIGNED, "vertices, faces and root_box must be 4-byte aligned");
     RefitRequest q{};
-    const bool inner_root = (in.root_ref >> 29) == 0;
-    if (inner_root) {
-        if (n_levels == 0 || n_levels > 129 || !order || !level_start)
-            return fail(RT_ERR_INVALID_ARG, "an inner root needs the plan's order and 1..129 levels");
-        if (level_start[0] != 0 || level_start[n_levels] != in.n_nodes)
-            return fail(RT_ERR_INVALID_ARG, "level_start must run from 0 to n_nodes");
-        for (uint32_t l = 0; l < n_levels; ++l)
-            if (level_start[l + 1] < level_start[l])
-                return fail(RT_ERR_INVALID_ARG, "level_start must not decrease");
+    if ((in.root_ref >> 29) == 0) {
+        if (!plan || !counters) return fail(RT_ERR_INVALID_ARG, "an inner root needs the plan and counters");
+        if (!aligned(plan, 4) || !aligned(counters, 4))
+            return fail(RT_ERR_MISALIGNED, "plan and counters must be 4-byte aligned");
         if ((in.root_ref & kRefIndexMaskHost) != 0)
             return fail(RT_ERR_INVALID_ARG, "the root is not node 0 (not a tree from rt_bvh_build)");
+        q.n_nodes = in.n_nodes;
     } else {
-        if (n_levels != 0) return fail(RT_ERR_INVALID_ARG, "a root leaf has no levels");
         q.root_first = in.root_ref & kRefIndexMaskHost;
         q.root_count = in.root_ref >> 29;
     }
     q.nodes = const_cast<void *>(scene->nodes);
     q.tris = const_cast<void *>(scene->tris);
     q.n_tris = in.n_tris;
-    q.order = order;
-    q.level_start = level_start;
-    q.n_levels = n_levels;
+    q.parents = plan;
+    q.counters = counters;
     q.vertices = vertices;
     q.n_vertices = n_vertices;
     q.faces = faces;

@@ -111,9 +111,8 @@ SIGNATURES = [
     ("rt_bvh_compress", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_bvh_widen", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_bvh_pack", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
-    ("rt_bvh_refit_plan", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, _P, _U32,
-                                    C.POINTER(C.c_uint32)]),
-    ("rt_bvh_refit", C.c_int, [C.POINTER(rt_scene), _P, _P, _U32, _P, _U32, _P, _P, _P]),
+    ("rt_bvh_refit_plan", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ]),
+    ("rt_bvh_refit", C.c_int, [C.POINTER(rt_scene), _P, _P, _P, _U32, _P, _P, _P]),
     ("rt_trace_workspace_bytes", C.c_int, [C.POINTER(rt_scene), _U32, _U32, C.POINTER(_SZ)]),
     ("rt_trace_closest", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                    _SZ, _P]),
@@ -556,24 +555,22 @@ def rt_bvh_pack(nodes: np.ndarray, info: rt_bvh_info):
     return out.view(np.uint8)[: n * RT_NODE_BYTES_F32P], oinfo
 
 
-def rt_bvh_refit_plan(nodes: np.ndarray, info: rt_bvh_info):
-    """The refit plan of a built tree (64-byte nodes): ``(order uint32
-    [n_nodes], level_start uint32 [n_levels + 1])``, inner nodes by depth,
-    deepest first (both empty for a root leaf)."""
+def rt_bvh_refit_plan(nodes: np.ndarray, info: rt_bvh_info) -> np.ndarray:
+    """The refit plan of a built tree (64-byte nodes): uint32 [n_nodes], inner
+    node k's parent word 2 * parent + slot (0xFFFFFFFF for the root); empty
+    for a root leaf."""
     n = int(info.n_nodes)
+    if n == 0 or int(info.root_ref) >> 29:
+        _check(load_library().rt_bvh_refit_plan(None, C.byref(info), None, 0),
+               "rt_bvh_refit_plan")
+        return np.zeros(0, np.uint32)
     src = np.ascontiguousarray(nodes, np.uint8)
-    src16 = np.zeros(max(1, n * RT_NODE_BYTES // 16), dtype=np.dtype((np.void, 16)))
-    src16.view(np.uint8)[: n * RT_NODE_BYTES] = src[: n * RT_NODE_BYTES]
-    order = np.zeros(max(1, n), np.uint32)
-    cap = int(info.max_depth) + 2
-    level_start = np.zeros(cap, np.uint32)
-    nl = C.c_uint32()
-    _check(load_library().rt_bvh_refit_plan(src16.ctypes.data if n else None, C.byref(info),
-                                             order.ctypes.data, n, level_start.ctypes.data, cap,
-                                             C.byref(nl)), "rt_bvh_refit_plan")
-    if nl.value == 0:
-        return np.zeros(0, np.uint32), np.zeros(0, np.uint32)
-    return order[:n].copy(), level_start[: nl.value + 1].copy()
+    src16 = np.zeros(n * RT_NODE_BYTES // 16, dtype=np.dtype((np.void, 16)))
+    src16.view(np.uint8)[:] = src[: n * RT_NODE_BYTES]
+    plan = np.zeros(n, np.uint32)
+    _check(load_library().rt_bvh_refit_plan(src16.ctypes.data, C.byref(info), plan.ctypes.data, n),
+           "rt_bvh_refit_plan")
+    return plan
 
 
 def rt_bvh_widen(nodes: np.ndarray, info: rt_bvh_info):
@@ -631,7 +628,7 @@ class RefitScene:
         if f.size and (f.min() < 0 or f.max() >= v.shape[0]):
             raise ValueError("faces must index the vertices")
         nodes, tris, info = rt_bvh_build(v[f], geom_ids, max_leaf)
-        order, self.level_start = rt_bvh_refit_plan(nodes, info)
+        plan = rt_bvh_refit_plan(nodes, info)
         dn = torch.from_numpy(nodes.copy()).to(device) if nodes.size else None
         dt = torch.from_numpy(tris.copy()).to(device)
         tc = None if texcoords is None else torch.from_numpy(
@@ -639,7 +636,9 @@ class RefitScene:
         tx = None if textures is None else torch.from_numpy(
             np.ascontiguousarray(textures, np.uint32).view(np.int32)).to(device)
         self.scene = Scene(dn, dt, info, tc, tx)
-        self.order = torch.from_numpy(order).to(device) if order.size else None
+        self.plan = torch.from_numpy(plan.view(np.int32)).to(device) if plan.size else None
+        self.counters = (torch.empty(plan.size, dtype=torch.int32, device=device)
+                         if plan.size else None)
         self.faces = torch.from_numpy(f.astype(np.int32)).to(device)
         self.n_vertices = v.shape[0]
         self.root_box = torch.empty(6, dtype=torch.float32, device=device)
@@ -655,11 +654,10 @@ class RefitScene:
         if vertices.device != self.faces.device:
             raise ValueError("vertices must be on the scene's device")
         with _on_stream(vertices.device, stream) as s:
-            ls = self.level_start
             sc = self.scene.view
             _check(load_library().rt_bvh_refit(
-                C.byref(sc), None if self.order is None else self.order.data_ptr(),
-                ls.ctypes.data if ls.size else None, max(0, ls.size - 1), vertices.data_ptr(),
+                C.byref(sc), None if self.plan is None else self.plan.data_ptr(),
+                None if self.counters is None else self.counters.data_ptr(), vertices.data_ptr(),
                 self.n_vertices, self.faces.data_ptr(), self.root_box.data_ptr(), s),
                 "rt_bvh_refit")
             if int(self.scene.info.n_tris) > 0:

@@ -839,51 +839,52 @@ def test_pack_validation(lib):
 
 
 def test_refit_plan(lib):
-    """rt_bvh_refit_plan lists every inner node once, grouped by depth
-    (recomputed here from the decoded tree), deepest first, the root last;
-    a root leaf and an empty tree have no levels; other layouts are refused."""
+    """rt_bvh_refit_plan gives every inner node but the root its parent and
+    slot (recomputed here from the decoded tree) and the root 0xFFFFFFFF; a
+    root leaf has no plan; other layouts are refused."""
     from paper_1912_12786_amd import workloads as W
     for verts, leaf in ((W.tiny().vertices, 2), (W.billboards(3000).vertices, 1),
                         (W.tiny().vertices[:3], 4)):
         nodes, tris, info = rtx.rt_bvh_build(verts, None, leaf)
-        order, ls = rtx.rt_bvh_refit_plan(nodes, info)
+        plan = rtx.rt_bvh_refit_plan(nodes, info)
         if info.n_nodes == 0:
-            assert order.size == 0 and ls.size == 0
+            assert plan.size == 0
             continue
         nu = nodes.view(np.uint32).reshape(-1, 16)
-        depth = {0: 0}
-        for k in range(info.n_nodes):      # preorder: parents first
-            for c in (12, 13):
-                if nu[k, c] >> 29 == 0:
-                    depth[int(nu[k, c])] = depth[k] + 1
-        assert sorted(order.tolist()) == list(range(info.n_nodes))
-        assert ls[0] == 0 and ls[-1] == info.n_nodes and np.all(np.diff(ls) > 0)
-        deepest = max(depth.values())
-        assert ls.size == deepest + 2
-        for lvl in range(ls.size - 1):
-            assert {depth[int(n)] for n in order[ls[lvl]:ls[lvl + 1]]} == {deepest - lvl}
-        assert order[-1] == 0
+        want = np.full(info.n_nodes, 0xFFFFFFFF, np.uint64)
+        for k in range(info.n_nodes):
+            for c in (0, 1):
+                ref = int(nu[k, 12 + c])
+                if ref >> 29 == 0:
+                    want[ref] = 2 * k + c
+        assert np.array_equal(plan, want.astype(np.uint32))
+        assert plan[0] == 0xFFFFFFFF and np.all(plan[1:] != 0xFFFFFFFF)
     nodes, tris, info = rtx.rt_bvh_build(W.tiny().vertices)
     q, qi = rtx.rt_bvh_compress(nodes, info)
     with pytest.raises(rtx.RtxError, match="RT_LAYOUT_F32"):
         rtx.rt_bvh_refit_plan(nodes, qi)
+    # a child reference pointing back up is refused
+    bad = nodes.copy()
+    bu = bad.view(np.uint32).reshape(-1, 16)
+    inner = [c for c in (12, 13) if bu[1, c] >> 29 == 0]
+    bu[1, inner[0] if inner else 12] = 0
+    with pytest.raises(rtx.RtxError, match="later node"):
+        rtx.rt_bvh_refit_plan(bad, info)
 
 
 def test_refit_validation(lib):
     """Argument errors of rt_bvh_refit are found before any device work."""
     sc = _fake_scene(n_tris=10, n_nodes=3, max_depth=3)
-    ls = (C.c_uint32 * 3)(0, 1, 3)
-    bad = (C.c_uint32 * 3)(0, 2, 1)
     f = lib.rt_bvh_refit
-    V, F, R, O = 0x10000, 0x20000, 0x30000, 0x40000
-    assert f(C.byref(sc), O, ls, 2, None, 10, F, R, None) == -1        # vertices NULL
-    assert f(C.byref(sc), O, ls, 2, V, 10, F, None, None) == -1        # root box NULL
-    assert f(C.byref(sc), O, ls, 2, V + 2, 10, F, R, None) == -2       # misaligned
-    assert f(C.byref(sc), None, ls, 2, V, 10, F, R, None) == -1        # inner root, no order
-    assert f(C.byref(sc), O, ls, 0, V, 10, F, R, None) == -1           # no levels
-    assert f(C.byref(sc), O, bad, 2, V, 10, F, R, None) == -1          # decreasing
-    assert f(C.byref(sc), O, ls, 1, V, 10, F, R, None) == -1           # does not end at n_nodes
+    P, CN, V, F, R = 0x10000, 0x20000, 0x30000, 0x40000, 0x50000
+    assert f(C.byref(sc), P, CN, None, 10, F, R, None) == -1           # vertices NULL
+    assert f(C.byref(sc), P, CN, V, 10, F, None, None) == -1           # root box NULL
+    assert f(C.byref(sc), P, CN, V + 2, 10, F, R, None) == -2          # misaligned
+    assert f(C.byref(sc), None, CN, V, 10, F, R, None) == -1           # inner root, no plan
+    assert f(C.byref(sc), P, None, V, 10, F, R, None) == -1            # no counters
+    assert f(C.byref(sc), P, CN + 2, V, 10, F, R, None) == -2          # misaligned counters
+    sc.info.root_ref = 1
+    assert f(C.byref(sc), P, CN, V, 10, F, R, None) == -1              # root not node 0
+    sc.info.root_ref = 0
     sc.info.layout = 1
-    assert f(C.byref(sc), O, ls, 2, V, 10, F, R, None) == -3           # another layout
-    leaf = _fake_scene(n_tris=3, n_nodes=0, root_ref=(3 << 29), max_depth=0)
-    assert f(C.byref(leaf), O, ls, 2, V, 10, F, R, None) == -1         # a root leaf has no levels
+    assert f(C.byref(sc), P, CN, V, 10, F, R, None) == -3              # another layout

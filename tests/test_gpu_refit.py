@@ -76,15 +76,19 @@ def test_refit_to_build_vertices_is_identity(env, mesh):
 
 @pytest.mark.parametrize("sigma,max_leaf", [(0.003, 2), (0.05, 4), (0.3, 1)])
 def test_refit_moved_matches_oracle(env, oracle_lib, mesh, sigma, max_leaf):
-    """Moved vertices: the refitted tree equals oracle B's refit bit for bit,
-    and alpha closest and any-hit traversals of it equal oracle B's on the
-    moved mesh (hits, occluders, counters)."""
+    """Moved vertices (the second of two refits in a row): the refitted tree
+    equals oracle B's refit bit for bit, and alpha closest and any-hit
+    traversals of it equal oracle B's on the moved mesh (hits, occluders,
+    counters)."""
     torch, rtx = env
     rng = np.random.default_rng(int(sigma * 1000) + max_leaf)
     moved = (mesh.vertices + rng.normal(0.0, sigma, size=mesh.vertices.shape)).astype(np.float32)
     rs = rtx.RefitScene(mesh.vertices, mesh.faces, mesh.geom_ids, mesh.texcoords, mesh.textures,
                         max_leaf=max_leaf)
-    announce(f"refit diff scene sigma={sigma} max_leaf={max_leaf}")
+    announce(f"refit diff scene sigma={sigma} max_leaf={max_leaf} (after a first refit)")
+    first = (mesh.vertices + rng.normal(0.0, 2 * sigma, size=mesh.vertices.shape)
+             ).astype(np.float32)
+    rs.update(torch.from_numpy(first).cuda())     # the counters must start from zero again
     rs.update(torch.from_numpy(moved).cuda())
     torch.cuda.synchronize()
     ob = oracle_lib.refit(oracle_lib.build_bvh(mesh.triangles, max_leaf=max_leaf), moved,
