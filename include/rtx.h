@@ -322,15 +322,20 @@ rt_status rt_bvh_pack(const void *nodes, const rt_bvh_info *info, void *out, siz
                       rt_bvh_info *out_info);
 
 /* Refit plan of a built BVH (host, 64-byte nodes from rt_bvh_build), for
- * rt_bvh_refit: plan[k] = 2 * p + c when inner node k is child c (0 or 1)
- * of inner node p, and 0xFFFFFFFF for the root (node 0).
- *   plan  host output, info->n_nodes words (plan_cap entries); untouched for
- *         a root leaf or an empty tree (nothing to plan)
+ * rt_bvh_refit, in plan (host output, plan_cap >= 3 * info->n_nodes words):
+ *   plan[k]              2 * p + c when inner node k is child c (0 or 1) of
+ *                        inner node p; 0xFFFFFFFF for the root (node 0)
+ *   plan[n_nodes + k]    k's depth (root 0), with bit 31 set when k is a
+ *                        "top" node: its subtree (inner nodes k .. k + size - 1
+ *                        in preorder) leaves the block of 256 numbers that
+ *                        contains k
+ *   plan[2 n_nodes + i]  the *n_top top nodes, i < *n_top
+ * Nothing is planned (and *n_top = 0) for a root leaf or an empty tree.
  * Fails for another layout (RT_ERR_UNSUPPORTED) or a tree whose child
  * references do not point to later nodes, each node below the root from
- * exactly one parent. */
+ * exactly one parent, within max_depth. */
 rt_status rt_bvh_refit_plan(const void *nodes, const rt_bvh_info *info, uint32_t *plan,
-                            size_t plan_cap);
+                            size_t plan_cap, uint32_t *n_top);
 
 /* Refit (device): the scene's triangle records and node boxes recomputed in
  * place from new vertex positions, the topology unchanged -- for geometry
@@ -350,15 +355,16 @@ rt_status rt_bvh_refit_plan(const void *nodes, const rt_bvh_info *info, uint32_t
  * rt_bvh_info.root_lo/root_hi before tracing (the traversal's root test
  * reads the host info).
  *   plan      device, rt_bvh_refit_plan's words (NULL for a root leaf)
- *   counters  device scratch, n_nodes uint32 (contents need no
- *             initialisation; NULL for a root leaf)
- * Two launches: the triangle records, then every node's box bottom-up, a
- * lane per inner node climbing while it completes nodes.  The scene's node
- * and triangle buffers and the counters are written: calls must be ordered
+ *   n_top     its *n_top
+ * Three launches, no atomics: the triangle records; then blocks of 256
+ * inner nodes (by number) that write their leaf children's boxes and finish,
+ * depth by depth with block barriers, every node whose subtree lies in the
+ * block; then one block that finishes the top nodes depth by depth.  The
+ * scene's node and triangle buffers are written: calls must be ordered
  * against each other and against traces of the same scene on one stream.
  * Boxes stay exact as the vertices move; their quality drops with distance
  * from the built positions.  RT_LAYOUT_F32 scenes only. */
-rt_status rt_bvh_refit(const rt_scene *scene, const uint32_t *plan, uint32_t *counters,
+rt_status rt_bvh_refit(const rt_scene *scene, const uint32_t *plan, uint32_t n_top,
                        const float *vertices, uint32_t n_vertices, const uint32_t *faces,
                        float *root_box, void *stream);
 

@@ -398,25 +398,43 @@ rt_status compress_nodes(const NodeRecord *in, uint32_t n_nodes, NodeQ8Record *o
 }
 
 // -------------------------------------------------------------------------
-// Refit plan: each inner node's parent and slot, from the parents' child
-// references (an inner child's number is larger than its parent's).
+// Refit plan: parents and depths by one preorder sweep (an inner child's
+// number is larger than its parent's), subtree sizes by one reverse sweep;
+// a node is "top" when its subtree's preorder range leaves its block's.
 // -------------------------------------------------------------------------
-bool refit_parents(const NodeRecord *nodes, const rt_bvh_info &info, uint32_t *parent)
+uint32_t refit_plan(const NodeRecord *nodes, const rt_bvh_info &info, uint32_t *plan)
 {
     const uint32_t n = info.n_nodes;
-    for (uint32_t k = 0; k < n; ++k) parent[k] = kRefitNoParent;
+    uint32_t *parent = plan, *depth = plan + n, *top = plan + 2 * size_t(n);
+    for (uint32_t k = 0; k < n; ++k) {
+        parent[k] = kRefitNoParent;
+        depth[k] = 0;
+    }
     uint32_t linked = 0;
     for (uint32_t k = 0; k < n; ++k) {
         for (uint32_t c = 0; c < 2; ++c) {
             const uint32_t ref = nodes[k].u[12 + c];
             if ((ref >> 29) != 0) continue;
             const uint32_t ch = ref & kRefIndexMaskHost;
-            if (ch <= k || ch >= n || parent[ch] != kRefitNoParent) return false;
+            if (ch <= k || ch >= n || parent[ch] != kRefitNoParent) return UINT32_MAX;
             parent[ch] = 2 * k + c;
+            depth[ch] = depth[k] + 1;
+            if (depth[ch] > info.max_depth) return UINT32_MAX;  // the kernels sweep 0..max_depth
             ++linked;
         }
     }
-    return n == 0 || linked == n - 1;  // every node but the root has one parent
+    if (n > 0 && linked != n - 1) return UINT32_MAX;  // every node but the root has one parent
+    std::vector<uint32_t> size(n, 1);
+    for (uint32_t k = n; k-- > 1;) size[parent[k] >> 1] += size[k];
+    uint32_t t = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint64_t block_end = (uint64_t(k) / kRefitBlockNodes + 1) * kRefitBlockNodes;
+        if (uint64_t(k) + size[k] > block_end) {
+            depth[k] |= kRefitTopBit;
+            top[t++] = k;
+        }
+    }
+    return t;
 }
 
 // -------------------------------------------------------------------------

@@ -11,17 +11,17 @@
 // returns the build's boxes bit for bit, signs of zero included.  A vertex
 // index past the mesh reads NaN, which no strict comparison accepts.
 //
-// Two launches.  The first rewrites the triangle records (a lane per
-// triangle) and zeroes one arrival counter per inner node.  The second gives
-// each inner node a lane that writes the boxes of its leaf children into the
-// node and adds their number to the node's counter; every inner child adds
-// one when its own box is in place.  The lane whose addition completes a
-// node's two children (the counter reaching 2) computes that node's box,
-// writes it into the parent's slot (the host plan's parent words) and adds
-// one there, and so on up; the root's completer writes the root box.  No
-// lane waits: every other lane stops at its first incomplete node.  The
-// additions are acquire-release at device scope, so a completer reads the
-// slot its sibling's lane wrote before adding.
+// Three launches, no atomics.  The first rewrites the triangle records (a
+// lane per triangle).  In the second, block b owns the inner nodes numbered
+// [256 b, 256 b + 256) (preorder numbers: a subtree is a contiguous range)
+// and gives each a lane: every lane writes its node's leaf-child boxes, then,
+// for depth d from the deepest to 0 with a block barrier between depths, the
+// lanes whose node is at depth d and whose whole subtree lies in the block's
+// range write their node's box into the parent's slot (or the root box).
+// The nodes left -- "top" nodes, whose subtree leaves their block's range,
+// listed by the host plan -- form the upper part of the tree; in the third
+// launch one block finishes them the same way, depth by depth, their lower
+// children being complete after the second launch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -85,13 +85,10 @@ __device__ __forceinline__ void grow_leaf(const refit_mesh &m, const TriRecord *
     }
 }
 
-// Triangle records, and the counters zeroed (a lane per triangle or node).
-__global__ __launch_bounds__(kRefitBlock) void refit_tris_kernel(TriRecord *tris, refit_mesh m,
-                                                                 uint32_t *counters,
-                                                                 uint32_t n_nodes)
+// Triangle records (a lane per triangle).
+__global__ __launch_bounds__(kRefitBlock) void refit_tris_kernel(TriRecord *tris, refit_mesh m)
 {
     const uint32_t i = blockIdx.x * kRefitBlock + threadIdx.x;
-    if (i < n_nodes) counters[i] = 0;
     if (i >= m.n_tris) return;
     TriRecord &t = tris[i];
     const uint32_t prim = t.u[3];
@@ -117,57 +114,75 @@ __device__ __forceinline__ void store_slot(NodeRecord &nd, uint32_t c, const flo
     }
 }
 
-// Adds `arrivals` to node n's counter; true if that completes both children.
-__device__ __forceinline__ bool arrive(uint32_t *counters, uint32_t n, uint32_t arrivals)
+// Node n's box from its two slots, written into its parent's slot (or, for
+// the root, to root_box).
+__device__ __forceinline__ void finish_node(NodeRecord *nodes, const uint32_t *parents,
+                                            uint32_t n, float *root_box)
 {
-    const uint32_t before = __hip_atomic_fetch_add(counters + n, arrivals, __ATOMIC_ACQ_REL,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-    return before + arrivals == 2;
+    const NodeRecord &nd = nodes[n];
+    const float l0[3] = {nd.f[0], nd.f[1], nd.f[2]}, h0[3] = {nd.f[3], nd.f[4], nd.f[5]};
+    const float l1[3] = {nd.f[6], nd.f[7], nd.f[8]}, h1[3] = {nd.f[9], nd.f[10], nd.f[11]};
+    float lo[3], hi[3];
+    empty_box(lo, hi);
+    grow(lo, hi, l0, h0);
+    grow(lo, hi, l1, h1);
+    const uint32_t up = parents[n];
+    if (up == kRefitNoParent) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            root_box[a] = lo[a];
+            root_box[3 + a] = hi[a];
+        }
+        return;
+    }
+    store_slot(nodes[up >> 1], up & 1u, lo, hi);
 }
 
-__global__ __launch_bounds__(kRefitBlock) void refit_nodes_kernel(NodeRecord *nodes,
-                                                                  uint32_t n_nodes,
-                                                                  const TriRecord *tris,
-                                                                  const uint32_t *parents,
-                                                                  uint32_t *counters, refit_mesh m,
-                                                                  float *root_box)
+static_assert(kRefitBlock == kRefitBlockNodes, "a refit block owns the plan's range of nodes");
+
+__global__ __launch_bounds__(kRefitBlock) void refit_blocks_kernel(NodeRecord *nodes,
+                                                                   uint32_t n_nodes,
+                                                                   uint32_t max_depth,
+                                                                   const TriRecord *tris,
+                                                                   const uint32_t *plan,
+                                                                   refit_mesh m, float *root_box)
 {
-    uint32_t n = blockIdx.x * kRefitBlock + threadIdx.x;
-    if (n >= n_nodes) return;
-    uint32_t leaves = 0;
-    for (uint32_t c = 0; c < 2; ++c) {
-        const uint32_t ref = nodes[n].u[12 + c];
-        const uint32_t cnt = ref >> 29;
-        if (cnt == 0) continue;
-        float lo[3], hi[3];
-        empty_box(lo, hi);
-        grow_leaf(m, tris, ref & kRefIndexMaskHost, cnt, lo, hi);
-        store_slot(nodes[n], c, lo, hi);
-        ++leaves;
-    }
-    if (leaves == 0 || !arrive(counters, n, leaves)) return;
-    // n's children are in place: climb while this lane completes nodes
-    for (;;) {
-        const NodeRecord &nd = nodes[n];
-        const float l0[3] = {nd.f[0], nd.f[1], nd.f[2]}, h0[3] = {nd.f[3], nd.f[4], nd.f[5]};
-        const float l1[3] = {nd.f[6], nd.f[7], nd.f[8]}, h1[3] = {nd.f[9], nd.f[10], nd.f[11]};
-        float lo[3], hi[3];
-        empty_box(lo, hi);
-        grow(lo, hi, l0, h0);
-        grow(lo, hi, l1, h1);
-        const uint32_t up = parents[n];
-        if (up == kRefitNoParent) {  // the root
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                root_box[a] = lo[a];
-                root_box[3 + a] = hi[a];
-            }
-            return;
+    const uint32_t n = blockIdx.x * kRefitBlock + threadIdx.x;
+    const bool mine = n < n_nodes;
+    uint32_t depth_word = kRefitTopBit;
+    if (mine) {
+        depth_word = plan[n_nodes + n];
+        for (uint32_t c = 0; c < 2; ++c) {
+            const uint32_t ref = nodes[n].u[12 + c];
+            const uint32_t cnt = ref >> 29;
+            if (cnt == 0) continue;
+            float lo[3], hi[3];
+            empty_box(lo, hi);
+            grow_leaf(m, tris, ref & kRefIndexMaskHost, cnt, lo, hi);
+            store_slot(nodes[n], c, lo, hi);
         }
-        const uint32_t p = up >> 1;
-        store_slot(nodes[p], up & 1u, lo, hi);
-        if (!arrive(counters, p, 1)) return;
-        n = p;
+    }
+    for (uint32_t d = max_depth + 1; d-- > 0;) {
+        __syncthreads();
+        if (depth_word == d) finish_node(nodes, plan, n, root_box);  // in range, not top
+    }
+}
+
+// The top nodes, one block, depth by depth.
+constexpr uint32_t kRefitTopBlock = 1024;
+__global__ __launch_bounds__(kRefitTopBlock) void refit_top_kernel(NodeRecord *nodes,
+                                                                   uint32_t n_nodes,
+                                                                   uint32_t max_depth,
+                                                                   const uint32_t *plan,
+                                                                   uint32_t n_top, float *root_box)
+{
+    const uint32_t *top = plan + 2 * size_t(n_nodes);
+    for (uint32_t d = max_depth + 1; d-- > 0;) {
+        for (uint32_t i = threadIdx.x; i < n_top; i += kRefitTopBlock) {
+            const uint32_t n = top[i];
+            if ((plan[n_nodes + n] & ~kRefitTopBit) == d) finish_node(nodes, plan, n, root_box);
+        }
+        __syncthreads();
     }
 }
 
@@ -193,17 +208,20 @@ rt_status launch_refit(const RefitRequest &q, const char **err)
     refit_mesh m{q.vertices, q.faces, q.n_vertices, q.n_tris};
     TriRecord *tris = static_cast<TriRecord *>(q.tris);
     NodeRecord *nodes = static_cast<NodeRecord *>(q.nodes);
-    const uint32_t lanes = q.n_tris > q.n_nodes ? q.n_tris : q.n_nodes;
-    if (lanes > 0)
-        hipLaunchKernelGGL(refit_tris_kernel, dim3((lanes + kRefitBlock - 1) / kRefitBlock),
-                           dim3(kRefitBlock), 0, s, tris, m, q.counters, q.n_nodes);
-    if (q.n_nodes > 0)
-        hipLaunchKernelGGL(refit_nodes_kernel, dim3((q.n_nodes + kRefitBlock - 1) / kRefitBlock),
-                           dim3(kRefitBlock), 0, s, nodes, q.n_nodes, tris, q.parents, q.counters,
-                           m, q.root_box);
-    else if (q.root_count > 0)
+    if (q.n_tris > 0)
+        hipLaunchKernelGGL(refit_tris_kernel, dim3((q.n_tris + kRefitBlock - 1) / kRefitBlock),
+                           dim3(kRefitBlock), 0, s, tris, m);
+    if (q.n_nodes > 0) {
+        hipLaunchKernelGGL(refit_blocks_kernel, dim3((q.n_nodes + kRefitBlock - 1) / kRefitBlock),
+                           dim3(kRefitBlock), 0, s, nodes, q.n_nodes, q.max_depth, tris, q.plan, m,
+                           q.root_box);
+        if (q.n_top > 0)
+            hipLaunchKernelGGL(refit_top_kernel, dim3(1), dim3(kRefitTopBlock), 0, s, nodes,
+                               q.n_nodes, q.max_depth, q.plan, q.n_top, q.root_box);
+    } else if (q.root_count > 0) {
         hipLaunchKernelGGL(refit_root_leaf_kernel, dim3(1), dim3(64), 0, s, tris, q.root_first,
                            q.root_count, m, q.root_box);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         *err = hipGetErrorString(e);

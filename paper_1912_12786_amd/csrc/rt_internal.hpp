@@ -165,19 +165,28 @@ struct InstancedRequest {
     void *stream;
 };
 
-// Refit plan of a built BVH: parent[k] = 2 * (k's parent) + (k's slot in
-// it) for every inner node k but the root, kRefitNoParent for the root.
-// false if a child reference is not a later node or a node has no parent.
+// Refit plan of a built BVH, 3 * n_nodes words at most:
+//   [0, n)        parent words: 2 * (k's parent) + (k's slot in it) for every
+//                 inner node k but the root, kRefitNoParent for the root;
+//   [n, 2n)       depth of node k, | kRefitTopBit if k's subtree (the
+//                 preorder range [k, k + size)) leaves the range of
+//                 kRefitBlockNodes numbers that k's block of the refit owns;
+//   [2n, 2n + t)  the t such "top" nodes.
+// Returns t, or UINT32_MAX if a child reference is not a later node or a
+// node is not the child of exactly one node.
 constexpr uint32_t kRefitNoParent = 0xFFFFFFFFu;
-bool refit_parents(const NodeRecord *nodes, const rt_bvh_info &info, uint32_t *parent);
+constexpr uint32_t kRefitTopBit = 0x80000000u;
+constexpr uint32_t kRefitBlockNodes = 256;
+uint32_t refit_plan(const NodeRecord *nodes, const rt_bvh_info &info, uint32_t *plan);
 
 struct RefitRequest {
     void *nodes;              // device, n_nodes 64-byte records (rewritten)
     uint32_t n_nodes;
+    uint32_t max_depth;       // deepest inner node's depth bound (the tree's max_depth)
     void *tris;               // device, n_tris triangle records (rewritten)
     uint32_t n_tris;
-    const uint32_t *parents;  // device, the plan (n_nodes words)
-    uint32_t *counters;       // device, n_nodes words of scratch
+    const uint32_t *plan;     // device, the plan (2 * n_nodes + n_top words)
+    uint32_t n_top;
     uint32_t root_first, root_count;  // a root leaf's triangles (n_nodes == 0)
     const float *vertices;    // device [n_vertices][3]
     uint32_t n_vertices;

@@ -309,23 +309,27 @@ rt_status rt_bvh_compress(const void *nodes, const rt_bvh_info *info, void *out,
 }
 
 rt_status rt_bvh_refit_plan(const void *nodes, const rt_bvh_info *info, uint32_t *plan,
-                            size_t plan_cap)
+                            size_t plan_cap, uint32_t *n_top)
 {
     g_last_error.clear();
-    if (!info) return fail(RT_ERR_INVALID_ARG, "info is NULL");
+    if (!info || !n_top) return fail(RT_ERR_INVALID_ARG, "info/n_top are NULL");
     if (info->layout != RT_LAYOUT_F32) return fail(RT_ERR_UNSUPPORTED, "refit takes RT_LAYOUT_F32 trees");
+    *n_top = 0;
     if (info->n_nodes == 0 || (info->root_ref >> 29) != 0) return RT_OK;  // a root leaf
     if (!nodes || !plan) return fail(RT_ERR_INVALID_ARG, "nodes/plan are NULL");
-    if (plan_cap < info->n_nodes) return fail(RT_ERR_INVALID_ARG, "plan smaller than n_nodes");
+    if (plan_cap < 3 * size_t(info->n_nodes))
+        return fail(RT_ERR_INVALID_ARG, "plan smaller than 3 * n_nodes words");
     if ((info->root_ref & kRefIndexMaskHost) != 0)
         return fail(RT_ERR_INVALID_ARG, "the root is not node 0 (not a tree from rt_bvh_build)");
-    if (!refit_parents(static_cast<const NodeRecord *>(nodes), *info, plan))
+    const uint32_t t = refit_plan(static_cast<const NodeRecord *>(nodes), *info, plan);
+    if (t == UINT32_MAX)
         return fail(RT_ERR_INVALID_ARG, "a child reference is not a later node, or a node is not "
                                         "the child of exactly one node");
+    *n_top = t;
     return RT_OK;
 }
 
-rt_status rt_bvh_refit(const rt_scene *scene, const uint32_t *plan, uint32_t *counters,
+rt_status rt_bvh_refit(const rt_scene *scene, const uint32_t *plan, uint32_t n_top,
                        const float *vertices, uint32_t n_vertices, const uint32_t *faces,
                        float *root_box, void *stream)
 {
@@ -340,21 +344,24 @@ rt_status rt_bvh_refit(const rt_scene *scene, const uint32_t *plan, uint32_t *co
         return fail(RT_ERR_MISALIGNED, "vertices, faces and root_box must be 4-byte aligned");
     RefitRequest q{};
     if ((in.root_ref >> 29) == 0) {
-        if (!plan || !counters) return fail(RT_ERR_INVALID_ARG, "an inner root needs the plan and counters");
-        if (!aligned(plan, 4) || !aligned(counters, 4))
-            return fail(RT_ERR_MISALIGNED, "plan and counters must be 4-byte aligned");
+        if (!plan) return fail(RT_ERR_INVALID_ARG, "an inner root needs the plan");
+        if (!aligned(plan, 4)) return fail(RT_ERR_MISALIGNED, "plan must be 4-byte aligned");
         if ((in.root_ref & kRefIndexMaskHost) != 0)
             return fail(RT_ERR_INVALID_ARG, "the root is not node 0 (not a tree from rt_bvh_build)");
+        if (n_top > in.n_nodes) return fail(RT_ERR_INVALID_ARG, "n_top exceeds n_nodes");
+        if (in.n_nodes > kRefitBlockNodes && n_top == 0)
+            return fail(RT_ERR_INVALID_ARG, "a tree of more than one refit block has top nodes");
         q.n_nodes = in.n_nodes;
     } else {
         q.root_first = in.root_ref & kRefIndexMaskHost;
         q.root_count = in.root_ref >> 29;
     }
     q.nodes = const_cast<void *>(scene->nodes);
+    q.max_depth = in.max_depth;
     q.tris = const_cast<void *>(scene->tris);
     q.n_tris = in.n_tris;
-    q.parents = plan;
-    q.counters = counters;
+    q.plan = plan;
+    q.n_top = n_top;
     q.vertices = vertices;
     q.n_vertices = n_vertices;
     q.faces = faces;

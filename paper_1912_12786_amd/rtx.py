@@ -111,8 +111,8 @@ SIGNATURES = [
     ("rt_bvh_compress", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_bvh_widen", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
     ("rt_bvh_pack", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(rt_bvh_info)]),
-    ("rt_bvh_refit_plan", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ]),
-    ("rt_bvh_refit", C.c_int, [C.POINTER(rt_scene), _P, _P, _P, _U32, _P, _P, _P]),
+    ("rt_bvh_refit_plan", C.c_int, [_P, C.POINTER(rt_bvh_info), _P, _SZ, C.POINTER(C.c_uint32)]),
+    ("rt_bvh_refit", C.c_int, [C.POINTER(rt_scene), _P, _U32, _P, _U32, _P, _P, _P]),
     ("rt_trace_workspace_bytes", C.c_int, [C.POINTER(rt_scene), _U32, _U32, C.POINTER(_SZ)]),
     ("rt_trace_closest", C.c_int, [C.POINTER(rt_scene), _P, _U32, C.c_int, _P, _U32, _P, _P, _P,
                                    _SZ, _P]),
@@ -555,22 +555,23 @@ def rt_bvh_pack(nodes: np.ndarray, info: rt_bvh_info):
     return out.view(np.uint8)[: n * RT_NODE_BYTES_F32P], oinfo
 
 
-def rt_bvh_refit_plan(nodes: np.ndarray, info: rt_bvh_info) -> np.ndarray:
-    """The refit plan of a built tree (64-byte nodes): uint32 [n_nodes], inner
-    node k's parent word 2 * parent + slot (0xFFFFFFFF for the root); empty
-    for a root leaf."""
+def rt_bvh_refit_plan(nodes: np.ndarray, info: rt_bvh_info):
+    """The refit plan of a built tree (64-byte nodes): ``(plan uint32
+    [2 n_nodes + n_top], n_top)`` -- parent words, depths (bit 31: top node),
+    the top nodes; ``(empty, 0)`` for a root leaf."""
     n = int(info.n_nodes)
+    nt = C.c_uint32()
     if n == 0 or int(info.root_ref) >> 29:
-        _check(load_library().rt_bvh_refit_plan(None, C.byref(info), None, 0),
+        _check(load_library().rt_bvh_refit_plan(None, C.byref(info), None, 0, C.byref(nt)),
                "rt_bvh_refit_plan")
-        return np.zeros(0, np.uint32)
+        return np.zeros(0, np.uint32), 0
     src = np.ascontiguousarray(nodes, np.uint8)
     src16 = np.zeros(n * RT_NODE_BYTES // 16, dtype=np.dtype((np.void, 16)))
     src16.view(np.uint8)[:] = src[: n * RT_NODE_BYTES]
-    plan = np.zeros(n, np.uint32)
-    _check(load_library().rt_bvh_refit_plan(src16.ctypes.data, C.byref(info), plan.ctypes.data, n),
-           "rt_bvh_refit_plan")
-    return plan
+    plan = np.zeros(3 * n, np.uint32)
+    _check(load_library().rt_bvh_refit_plan(src16.ctypes.data, C.byref(info), plan.ctypes.data,
+                                             plan.size, C.byref(nt)), "rt_bvh_refit_plan")
+    return plan[: 2 * n + nt.value].copy(), int(nt.value)
 
 
 def rt_bvh_widen(nodes: np.ndarray, info: rt_bvh_info):
@@ -628,7 +629,7 @@ class RefitScene:
         if f.size and (f.min() < 0 or f.max() >= v.shape[0]):
             raise ValueError("faces must index the vertices")
         nodes, tris, info = rt_bvh_build(v[f], geom_ids, max_leaf)
-        plan = rt_bvh_refit_plan(nodes, info)
+        plan, self.n_top = rt_bvh_refit_plan(nodes, info)
         dn = torch.from_numpy(nodes.copy()).to(device) if nodes.size else None
         dt = torch.from_numpy(tris.copy()).to(device)
         tc = None if texcoords is None else torch.from_numpy(
@@ -637,8 +638,6 @@ class RefitScene:
             np.ascontiguousarray(textures, np.uint32).view(np.int32)).to(device)
         self.scene = Scene(dn, dt, info, tc, tx)
         self.plan = torch.from_numpy(plan.view(np.int32)).to(device) if plan.size else None
-        self.counters = (torch.empty(plan.size, dtype=torch.int32, device=device)
-                         if plan.size else None)
         self.faces = torch.from_numpy(f.astype(np.int32)).to(device)
         self.n_vertices = v.shape[0]
         self.root_box = torch.empty(6, dtype=torch.float32, device=device)
@@ -656,9 +655,9 @@ class RefitScene:
         with _on_stream(vertices.device, stream) as s:
             sc = self.scene.view
             _check(load_library().rt_bvh_refit(
-                C.byref(sc), None if self.plan is None else self.plan.data_ptr(),
-                None if self.counters is None else self.counters.data_ptr(), vertices.data_ptr(),
-                self.n_vertices, self.faces.data_ptr(), self.root_box.data_ptr(), s),
+                C.byref(sc), None if self.plan is None else self.plan.data_ptr(), self.n_top,
+                vertices.data_ptr(), self.n_vertices, self.faces.data_ptr(),
+                self.root_box.data_ptr(), s),
                 "rt_bvh_refit")
             if int(self.scene.info.n_tris) > 0:
                 box = self.root_box.cpu().numpy()

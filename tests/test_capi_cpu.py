@@ -839,26 +839,39 @@ def test_pack_validation(lib):
 
 
 def test_refit_plan(lib):
-    """rt_bvh_refit_plan gives every inner node but the root its parent and
-    slot (recomputed here from the decoded tree) and the root 0xFFFFFFFF; a
-    root leaf has no plan; other layouts are refused."""
+    """rt_bvh_refit_plan: every inner node's parent and slot and its depth
+    (recomputed here from the decoded tree), the top flag exactly on the nodes
+    whose preorder subtree range leaves their block of 256 numbers, and the
+    list of those nodes; a root leaf has no plan; other layouts and trees
+    with a reference back up are refused."""
     from paper_1912_12786_amd import workloads as W
     for verts, leaf in ((W.tiny().vertices, 2), (W.billboards(3000).vertices, 1),
-                        (W.tiny().vertices[:3], 4)):
+                        (W.tiny().vertices[:200], 1), (W.tiny().vertices[:3], 4)):
         nodes, tris, info = rtx.rt_bvh_build(verts, None, leaf)
-        plan = rtx.rt_bvh_refit_plan(nodes, info)
-        if info.n_nodes == 0:
-            assert plan.size == 0
+        plan, n_top = rtx.rt_bvh_refit_plan(nodes, info)
+        n = info.n_nodes
+        if n == 0:
+            assert plan.size == 0 and n_top == 0
             continue
         nu = nodes.view(np.uint32).reshape(-1, 16)
-        want = np.full(info.n_nodes, 0xFFFFFFFF, np.uint64)
-        for k in range(info.n_nodes):
+        parent = np.full(n, 0xFFFFFFFF, np.uint64)
+        depth = np.zeros(n, np.int64)
+        for k in range(n):
             for c in (0, 1):
                 ref = int(nu[k, 12 + c])
                 if ref >> 29 == 0:
-                    want[ref] = 2 * k + c
-        assert np.array_equal(plan, want.astype(np.uint32))
-        assert plan[0] == 0xFFFFFFFF and np.all(plan[1:] != 0xFFFFFFFF)
+                    parent[ref] = 2 * k + c
+                    depth[ref] = depth[k] + 1
+        size = np.ones(n, np.int64)
+        for k in range(n - 1, 0, -1):
+            size[int(parent[k]) >> 1] += size[k]
+        top = (np.arange(n) + size) > (np.arange(n) // 256 + 1) * 256
+        assert plan.size == 2 * n + n_top
+        assert np.array_equal(plan[:n], parent.astype(np.uint32))
+        assert np.array_equal(plan[n:2 * n] & 0x7FFFFFFF, depth.astype(np.uint32))
+        assert np.array_equal((plan[n:2 * n] >> 31).astype(bool), top)
+        assert np.array_equal(plan[2 * n:], np.nonzero(top)[0].astype(np.uint32))
+        assert (n_top > 0) == (n > 256)
     nodes, tris, info = rtx.rt_bvh_build(W.tiny().vertices)
     q, qi = rtx.rt_bvh_compress(nodes, info)
     with pytest.raises(rtx.RtxError, match="RT_LAYOUT_F32"):
@@ -874,17 +887,18 @@ def test_refit_plan(lib):
 
 def test_refit_validation(lib):
     """Argument errors of rt_bvh_refit are found before any device work."""
-    sc = _fake_scene(n_tris=10, n_nodes=3, max_depth=3)
+    sc = _fake_scene(n_tris=1000, n_nodes=300, max_depth=3)
     f = lib.rt_bvh_refit
-    P, CN, V, F, R = 0x10000, 0x20000, 0x30000, 0x40000, 0x50000
-    assert f(C.byref(sc), P, CN, None, 10, F, R, None) == -1           # vertices NULL
-    assert f(C.byref(sc), P, CN, V, 10, F, None, None) == -1           # root box NULL
-    assert f(C.byref(sc), P, CN, V + 2, 10, F, R, None) == -2          # misaligned
-    assert f(C.byref(sc), None, CN, V, 10, F, R, None) == -1           # inner root, no plan
-    assert f(C.byref(sc), P, None, V, 10, F, R, None) == -1            # no counters
-    assert f(C.byref(sc), P, CN + 2, V, 10, F, R, None) == -2          # misaligned counters
+    P, V, F, R = 0x10000, 0x30000, 0x40000, 0x50000
+    assert f(C.byref(sc), P, 5, None, 10, F, R, None) == -1            # vertices NULL
+    assert f(C.byref(sc), P, 5, V, 10, F, None, None) == -1            # root box NULL
+    assert f(C.byref(sc), P, 5, V + 2, 10, F, R, None) == -2           # misaligned
+    assert f(C.byref(sc), None, 5, V, 10, F, R, None) == -1            # inner root, no plan
+    assert f(C.byref(sc), P + 2, 5, V, 10, F, R, None) == -2           # misaligned plan
+    assert f(C.byref(sc), P, 301, V, 10, F, R, None) == -1             # n_top > n_nodes
+    assert f(C.byref(sc), P, 0, V, 10, F, R, None) == -1               # > 256 nodes, no top
     sc.info.root_ref = 1
-    assert f(C.byref(sc), P, CN, V, 10, F, R, None) == -1              # root not node 0
+    assert f(C.byref(sc), P, 5, V, 10, F, R, None) == -1               # root not node 0
     sc.info.root_ref = 0
     sc.info.layout = 1
-    assert f(C.byref(sc), P, CN, V, 10, F, R, None) == -3              # another layout
+    assert f(C.byref(sc), P, 5, V, 10, F, R, None) == -3               # another layout
