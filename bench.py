@@ -839,6 +839,10 @@ def main():
         args.waves_per_simd = tuned["waves_per_simd"]
         log(f"autotuner: leaves <= {args.max_leaf}, {args.layout} nodes, shape {args.shape}, "
             f"{args.order} chunk order, {args.waves_per_simd} waves per SIMD")
+        for name, tab in (("first pass, fastest 6", dict(sorted(tuned["ms"].items(),
+                                                                 key=lambda kv: kv[1])[:6])),
+                          ("finals", tuned["finals_ms"]), ("waves per SIMD", tuned["waves_ms"])):
+            log(f"  {name}: " + ", ".join(f"{k} {v:.4f} ms" for k, v in tab.items()))
     log(f"workload {wl.name}: gen {t_gen:.2f} s, host BVH build + upload {t_build:.2f} s, "
         f"{scene.info.n_nodes} inner nodes, depth {scene.info.max_depth}")
     rays = torch.from_numpy(wl.rays).to(dev)

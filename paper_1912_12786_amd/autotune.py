@@ -64,6 +64,22 @@ def time_shapes(run, steps: int = 10, warmup: int = 2, shapes=None) -> dict:
     return times
 
 
+def _interleaved(cands, runner, shape_of, steps, warmup, rounds) -> dict:
+    """Median over ``rounds`` of each candidate's median milliseconds per call,
+    the candidates taken in turn within every round (``runner(c)`` is the
+    ``run(shape)`` of candidate ``c``, ``shape_of(c)`` its launch shape)."""
+    samples = {c: [] for c in cands}
+    for _ in range(rounds):
+        for c in cands:
+            sh = tuple(shape_of(c))
+            samples[c].append(time_shapes(runner(c), steps, warmup, shapes=[sh])[sh])
+    out = {}
+    for c, v in samples.items():
+        v = sorted(v)
+        out[c] = 0.5 * (v[(len(v) - 1) // 2] + v[len(v) // 2])
+    return out
+
+
 def tune(key: str, run, cache_path: str | None = DEFAULT_CACHE, steps: int = 10,
          warmup: int = 2, retune: bool = False):
     """Returns ``(shape, times)``: the fastest shape for ``run(shape)`` under
@@ -119,15 +135,22 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
                leaf_sizes=(2, 3, 4), layouts=("f32", "q8", "f32p", "wide4"),
                cache_path: str | None = DEFAULT_CACHE, longest_first=(False, True),
                image_width: int | None = None, waves=(4, 5, 6, 7, 8),
-               steps: int = 5, warmup: int = 1, retune: bool = False, device="cuda"):
+               steps: int = 5, warmup: int = 1, finals: int = 4, final_margin: float = 0.04,
+               rounds: int = 3, retune: bool = False, device="cuda"):
     """Chooses the BVH leaf size, node layout, launch shape and chunk order
     (index or longest-path-first) that trace ``rays`` (device float32 [N, 8],
     closest hit; an image of ``image_width`` in scanline order when given)
     fastest through the scene, then, for a queue shape, the most resident
-    waves per SIMD among ``waves`` for that choice.  Returns ``(scene,
-    choice)``: the scene built that way and ``{"max_leaf", "layout", "shape",
-    "longest_first", "waves_per_simd", "ms", "waves_ms"}`` (``waves_per_simd``
-    None for shapes without a queue); pass ``choice["shape"]``,
+    waves per SIMD among ``waves`` for that choice.  The first pass times
+    each candidate once, in a fixed order; the (at most ``finals``) fastest
+    within ``final_margin`` of the best are then timed again in ``rounds``
+    interleaved rounds, and so are the grid sizes, so that a drift of the
+    clocks over the sweep does not decide between candidates a few percent
+    apart: the median over the rounds decides.  Returns ``(scene, choice)``:
+    the scene built that way and ``{"max_leaf", "layout", "shape",
+    "longest_first", "waves_per_simd", "ms", "finals_ms", "waves_ms"}``
+    (``waves_per_simd`` None for shapes without a queue; ``finals_ms`` empty
+    when one candidate stood out); pass ``choice["shape"]``,
     ``choice["longest_first"]`` and ``choice["waves_per_simd"]`` to the trace
     calls.  A cached choice for this device and key is reused unless
     ``retune``."""
@@ -159,21 +182,37 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
                     for shape, ms in t.items():
                         timings[(int(max_leaf), layout, shape, bool(lf))] = ms
                 del scene
-        best = min(timings, key=timings.get)
+        ranked = sorted(timings, key=timings.get)
+        finalists = [k for k in ranked[:max(1, finals)]
+                     if timings[k] <= timings[ranked[0]] * (1.0 + final_margin)]
+        finals_ms = {}
+        if len(finalists) > 1 and rounds > 0:
+            scenes = {k[:2]: None for k in finalists}
+            for lk in scenes:
+                scenes[lk] = build(*lk)
+            finals_ms = _interleaved(
+                finalists, lambda k: (lambda sh: rtx.trace(scenes[k[:2]], rays, intersector,
+                                                            out=out, workspace=ws, shape=sh,
+                                                            image_width=image_width,
+                                                            longest_first=k[3], **kw)),
+                lambda k: k[2], steps, warmup, rounds)
+            del scenes
+            best = min(finals_ms, key=finals_ms.get)
+        else:
+            best = ranked[0]
+        label = lambda k: f"{k[0]}/{k[1]}/{','.join(map(str, k[2]))}/{'lf' if k[3] else 'index'}"
         choice = {"max_leaf": best[0], "layout": best[1], "shape": list(best[2]),
                   "longest_first": best[3], "waves_per_simd": None,
-                  "ms": {f"{k[0]}/{k[1]}/{','.join(map(str, k[2]))}/{'lf' if k[3] else 'index'}": v
-                         for k, v in timings.items()}, "waves_ms": {}}
+                  "ms": {label(k): v for k, v in timings.items()},
+                  "finals_ms": {label(k): v for k, v in finals_ms.items()}, "waves_ms": {}}
         if best[2][3] and waves:  # queue shape: size its persistent grid
             scene = build(best[0], best[1])
-            wt = {}
-            for w in waves:
-                t = time_shapes(lambda sh: rtx.trace(scene, rays, intersector, out=out,
-                                                     workspace=ws, shape=sh,
-                                                     image_width=image_width,
-                                                     longest_first=best[3], waves_per_simd=w,
-                                                     **kw), steps, warmup, shapes=[best[2]])
-                wt[int(w)] = t[best[2]]
+            wt = _interleaved(
+                [int(w) for w in waves],
+                lambda w: (lambda sh: rtx.trace(scene, rays, intersector, out=out, workspace=ws,
+                                                shape=sh, image_width=image_width,
+                                                longest_first=best[3], waves_per_simd=w, **kw)),
+                lambda w: best[2], steps, warmup, max(1, rounds))
             del scene
             choice["waves_per_simd"] = min(wt, key=wt.get)
             choice["waves_ms"] = {str(w): v for w, v in wt.items()}

@@ -104,6 +104,17 @@ def test_tune_scene_chooses_a_build_and_shape(env, oracle_lib, tmp_path):
     # four-wide ones the default shape and its 16-slot variant; each in index
     # and longest-path-first chunk order
     assert len(choice["ms"]) == 2 * 2 * (n_shapes + 1 + 2 + 2)
+    # the close finalists of that pass are timed again, interleaved, and the
+    # choice is the fastest of them
+    label = (f"{choice['max_leaf']}/{choice['layout']}/{','.join(map(str, choice['shape']))}/"
+             f"{'lf' if choice['longest_first'] else 'index'}")
+    assert set(choice["finals_ms"]) <= set(choice["ms"]) and len(choice["finals_ms"]) <= 4
+    if choice["finals_ms"]:
+        assert min(choice["finals_ms"], key=choice["finals_ms"].get) == label
+        first = min(choice["ms"], key=choice["ms"].get)
+        assert first in choice["finals_ms"]
+    else:
+        assert min(choice["ms"], key=choice["ms"].get) == label
     # a queue shape's grid size is tuned next, over 4..8 waves per SIMD
     if choice["shape"][3]:
         assert sorted(choice["waves_ms"]) == ["4", "5", "6", "7", "8"]
