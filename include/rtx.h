@@ -327,8 +327,8 @@ rt_status rt_bvh_pack(const void *nodes, const rt_bvh_info *info, void *out, siz
  *                        inner node p; 0xFFFFFFFF for the root (node 0)
  *   plan[n_nodes + k]    k's depth (root 0), with bit 31 set when k is a
  *                        "top" node: its subtree (inner nodes k .. k + size - 1
- *                        in preorder) leaves the block of 256 numbers that
- *                        contains k
+ *                        in preorder) leaves the block of 1024 numbers
+ *                        that contains k
  *   plan[2 n_nodes + i]  the *n_top top nodes, i < *n_top
  * Nothing is planned (and *n_top = 0) for a root leaf or an empty tree.
  * Fails for another layout (RT_ERR_UNSUPPORTED) or a tree whose child
@@ -356,10 +356,11 @@ rt_status rt_bvh_refit_plan(const void *nodes, const rt_bvh_info *info, uint32_t
  * reads the host info).
  *   plan      device, rt_bvh_refit_plan's words (NULL for a root leaf)
  *   n_top     its *n_top
- * Three launches, no atomics: the triangle records; then blocks of 256
- * inner nodes (by number) that write their leaf children's boxes and finish,
- * depth by depth with block barriers, every node whose subtree lies in the
- * block; then one block that finishes the top nodes depth by depth.  The
+ * Two launches, no atomics: blocks of 1024 inner nodes (by number) that
+ * also rewrite the triangle records, compute their leaf children's boxes and
+ * finish, depth by depth with block barriers in on-chip memory, every node
+ * whose subtree lies in the block; then one block that finishes the top
+ * nodes depth by depth (in on-chip memory for up to 2048 of them).  The
  * scene's node and triangle buffers are written: calls must be ordered
  * against each other and against traces of the same scene on one stream.
  * Boxes stay exact as the vertices move; their quality drops with distance

@@ -176,7 +176,7 @@ struct InstancedRequest {
 // node is not the child of exactly one node.
 constexpr uint32_t kRefitNoParent = 0xFFFFFFFFu;
 constexpr uint32_t kRefitTopBit = 0x80000000u;
-constexpr uint32_t kRefitBlockNodes = 256;
+constexpr uint32_t kRefitBlockNodes = 1024;
 uint32_t refit_plan(const NodeRecord *nodes, const rt_bvh_info &info, uint32_t *plan);
 
 struct RefitRequest {

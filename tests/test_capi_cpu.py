@@ -841,7 +841,7 @@ def test_pack_validation(lib):
 def test_refit_plan(lib):
     """rt_bvh_refit_plan: every inner node's parent and slot and its depth
     (recomputed here from the decoded tree), the top flag exactly on the nodes
-    whose preorder subtree range leaves their block of 256 numbers, and the
+    whose preorder subtree range leaves their block of 1024 numbers, and the
     list of those nodes; a root leaf has no plan; other layouts and trees
     with a reference back up are refused."""
     from paper_1912_12786_amd import workloads as W
@@ -865,13 +865,13 @@ def test_refit_plan(lib):
         size = np.ones(n, np.int64)
         for k in range(n - 1, 0, -1):
             size[int(parent[k]) >> 1] += size[k]
-        top = (np.arange(n) + size) > (np.arange(n) // 256 + 1) * 256
+        top = (np.arange(n) + size) > (np.arange(n) // 1024 + 1) * 1024
         assert plan.size == 2 * n + n_top
         assert np.array_equal(plan[:n], parent.astype(np.uint32))
         assert np.array_equal(plan[n:2 * n] & 0x7FFFFFFF, depth.astype(np.uint32))
         assert np.array_equal((plan[n:2 * n] >> 31).astype(bool), top)
         assert np.array_equal(plan[2 * n:], np.nonzero(top)[0].astype(np.uint32))
-        assert (n_top > 0) == (n > 256)
+        assert (n_top > 0) == (n > 1024)
     nodes, tris, info = rtx.rt_bvh_build(W.tiny().vertices)
     q, qi = rtx.rt_bvh_compress(nodes, info)
     with pytest.raises(rtx.RtxError, match="RT_LAYOUT_F32"):
@@ -887,7 +887,7 @@ def test_refit_plan(lib):
 
 def test_refit_validation(lib):
     """Argument errors of rt_bvh_refit are found before any device work."""
-    sc = _fake_scene(n_tris=1000, n_nodes=300, max_depth=3)
+    sc = _fake_scene(n_tris=3000, n_nodes=1300, max_depth=3)
     f = lib.rt_bvh_refit
     P, V, F, R = 0x10000, 0x30000, 0x40000, 0x50000
     assert f(C.byref(sc), P, 5, None, 10, F, R, None) == -1            # vertices NULL
@@ -895,8 +895,8 @@ def test_refit_validation(lib):
     assert f(C.byref(sc), P, 5, V + 2, 10, F, R, None) == -2           # misaligned
     assert f(C.byref(sc), None, 5, V, 10, F, R, None) == -1            # inner root, no plan
     assert f(C.byref(sc), P + 2, 5, V, 10, F, R, None) == -2           # misaligned plan
-    assert f(C.byref(sc), P, 301, V, 10, F, R, None) == -1             # n_top > n_nodes
-    assert f(C.byref(sc), P, 0, V, 10, F, R, None) == -1               # > 256 nodes, no top
+    assert f(C.byref(sc), P, 1301, V, 10, F, R, None) == -1            # n_top > n_nodes
+    assert f(C.byref(sc), P, 0, V, 10, F, R, None) == -1               # > 1024 nodes, no top
     sc.info.root_ref = 1
     assert f(C.byref(sc), P, 5, V, 10, F, R, None) == -1               # root not node 0
     sc.info.root_ref = 0

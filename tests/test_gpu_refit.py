@@ -74,7 +74,7 @@ def test_refit_to_build_vertices_is_identity(env, mesh):
     assert list(rs.scene.info.root_lo) == lo and list(rs.scene.info.root_hi) == hi
 
 
-@pytest.mark.parametrize("sigma,max_leaf", [(0.003, 2), (0.05, 4), (0.3, 1)])
+@pytest.mark.parametrize("sigma,max_leaf", [(0.003, 2), (0.05, 4), (0.3, 1), (0.01, 7)])
 def test_refit_moved_matches_oracle(env, oracle_lib, mesh, sigma, max_leaf):
     """Moved vertices (the second of two refits in a row): the refitted tree
     equals oracle B's refit bit for bit, and alpha closest and any-hit
@@ -108,6 +108,57 @@ def test_refit_moved_matches_oracle(env, oracle_lib, mesh, sigma, max_leaf):
     assert np.array_equal(P.occluders_to_numpy(occ), Ba["prim"])
     P.assert_counters_vs_b(acnt, Ba, f"refit any sigma={sigma}")
     assert (B["prim"] != MISS).mean() > 0.05
+
+
+def oracle_slots(ob):
+    """Oracle B's tree as the 64-byte nodes' child slots: for each inner node
+    in preorder (the library's numbering), lo, hi of its first child then of
+    its second, float32 [n_inner, 12]."""
+    nd = ob.nodes
+    inner = np.nonzero(nd["count"] == 0)[0]
+    L, R = nd["left"][inner], nd["right"][inner]
+    return np.concatenate([nd["lo"][L], nd["hi"][L], nd["lo"][R], nd["hi"][R]], axis=1)
+
+
+@pytest.mark.parametrize("scene,max_leaf,top_range", [
+    ("billboards", 1, (1025, 2048)),   # the top block's on-chip version, near full
+    ("spheres", 2, (2049, 1 << 30)),   # more than it holds: the global version
+])
+def test_refit_long_top_lists(env, oracle_lib, scene, max_leaf, top_range):
+    """Large trees whose top lists take each version of the top block (the
+    on-chip one holds 2,048 nodes): every child slot, every triangle record
+    and the root box bit for bit against oracle B's refit of its own build,
+    after two refits in a row."""
+    torch, rtx = env
+    wl = W.billboards() if scene == "billboards" else W.spheres()
+    v = wl.vertices.reshape(-1, 3).copy()
+    f = np.arange(v.shape[0], dtype=np.uint32).reshape(-1, 3)
+    rs = rtx.RefitScene(v, f, max_leaf=max_leaf)
+    assert top_range[0] <= rs.n_top <= top_range[1]
+    rng = np.random.default_rng(11)
+    scale = float(np.abs(v).max())
+    first = (v + rng.normal(0.0, 1e-3 * scale, size=v.shape)).astype(np.float32)
+    moved = (v + rng.normal(0.0, 3e-4 * scale, size=v.shape)).astype(np.float32)
+    announce(f"refit {scene} max_leaf={max_leaf}: {rs.scene.info.n_nodes} nodes, "
+             f"{rs.n_top} top nodes")
+    rs.update(torch.from_numpy(first).cuda())
+    rs.update(torch.from_numpy(moved).cuda())
+    torch.cuda.synchronize()
+    ob = oracle_lib.refit(oracle_lib.build_bvh(wl.vertices, max_leaf=max_leaf), moved, f)
+    nodes, tris = download(rs)
+    got = nodes.view(np.uint32).reshape(-1, 16)[:, :12]
+    assert np.array_equal(got, oracle_slots(ob).view(np.uint32))
+    assert np.array_equal(np.array(rs.scene.info.root_lo[:], np.float32).view(np.uint32),
+                          ob.nodes["lo"][0].view(np.uint32))
+    assert np.array_equal(np.array(rs.scene.info.root_hi[:], np.float32).view(np.uint32),
+                          ob.nodes["hi"][0].view(np.uint32))
+    tf = tris.view(np.float32).reshape(-1, 12)
+    tu = tris.view(np.uint32).reshape(-1, 12)
+    sv = moved[f][ob.perm]
+    assert np.array_equal(tu[:, 3], ob.perm)
+    assert np.array_equal(tf[:, 0:3].view(np.uint32), sv[:, 0].view(np.uint32))
+    assert np.array_equal(tf[:, 4:7].view(np.uint32), (sv[:, 1] - sv[:, 0]).view(np.uint32))
+    assert np.array_equal(tf[:, 8:11].view(np.uint32), (sv[:, 2] - sv[:, 0]).view(np.uint32))
 
 
 def test_refit_invalid_indices_and_root_leaf(env, oracle_lib):
