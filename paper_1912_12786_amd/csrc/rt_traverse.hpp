@@ -292,10 +292,15 @@ struct scene_view {
 
 // A child reference of a RT_LAYOUT_F32P node: byte k is the low byte of the
 // bit pattern of the child's k-th box word (lo.x, lo.y, lo.z, hi.x).
+// Two byte permutes and a shift-or: v_perm_b32 picks each result byte from
+// the eight bytes of its operand pair (selector 0-3: the second operand's
+// bytes, 4-7: the first's, 0x0c: zero), so perm(b, a, 0x0c0c0400) is
+// (a0, b0, 0, 0) -- three instructions where the masks and shifts take six.
 __device__ __forceinline__ uint32_t packed_ref(float a, float b, float c, float d)
 {
-    return (__float_as_uint(a) & 0xFFu) | (__float_as_uint(b) & 0xFFu) << 8 |
-           (__float_as_uint(c) & 0xFFu) << 16 | __float_as_uint(d) << 24;
+    const uint32_t lo = __builtin_amdgcn_perm(__float_as_uint(b), __float_as_uint(a), 0x0c0c0400u);
+    const uint32_t hi = __builtin_amdgcn_perm(__float_as_uint(d), __float_as_uint(c), 0x0c0c0400u);
+    return lo | hi << 16;
 }
 
 // The two child boxes (lo0, hi0, lo1, hi1) and references of inner node
