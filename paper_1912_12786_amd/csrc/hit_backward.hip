@@ -12,12 +12,16 @@
 //
 // One lane per ray; the per-ray algebra runs in float64 (half the float32
 // vector rate on gfx950, ample for ~150 operations per ray) from the float32
-// inputs.  Vertex gradients are scattered with float32 hardware atomics
-// (coarse-grained device memory): neighbouring rays of a wave usually hit the
-// same triangle, so each run of consecutive lanes with the same triangle first
-// sums its contributions (a segmented suffix scan over the wave) and only the
-// run's first lane issues the nine atomics.  The summation order -- and the
-// last bits of the sums -- still vary from run to run.
+// inputs.  Vertex gradients end in float32 hardware atomics (coarse-grained
+// device memory), which are the kernel's cost, so they are merged first:
+// neighbouring rays of a wave usually hit the same triangle, so each run of
+// consecutive lanes with the same triangle sums its contributions (a
+// segmented suffix scan over the wave); the runs' heads then add their three
+// vertices' sums into a hash table in LDS keyed by vertex index, shared by
+// the block's 1024 rays (two rows of a 512-wide image: neighbouring triangles
+// share vertices), and one lane per table entry issues the three global
+// atomics.  The summation order -- and the last bits of the sums -- vary from
+// run to run.
 #include <hip/hip_runtime.h>
 
 #include "rt_internal.hpp"
@@ -51,9 +55,20 @@ __device__ __forceinline__ float run_suffix_sum(float v, uint32_t lane, uint32_t
     return v;
 }
 
-__global__ __launch_bounds__(256) void hit_backward_kernel(backward_args a)
+constexpr uint32_t kBackwardBlock = 1024;
+constexpr uint32_t kTable = 4096;  // > 3 * kBackwardBlock keys, so probing always ends
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+static_assert((kTable & (kTable - 1)) == 0 && kTable > 3 * kBackwardBlock, "table size");
+
+__global__ __launch_bounds__(kBackwardBlock) void hit_backward_kernel(backward_args a)
 {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    __shared__ uint32_t tkey[kTable];
+    __shared__ float tval[3][kTable];
+    for (uint32_t s = threadIdx.x; s < kTable; s += kBackwardBlock) {
+        tkey[s] = kEmpty;
+        tval[0][s] = tval[1][s] = tval[2][s] = 0.0f;
+    }
+    const uint32_t i = blockIdx.x * kBackwardBlock + threadIdx.x;
     const bool in_range = i < a.n_rays;  // no early exit: the wave scans together
     uint32_t prim = kNoPrim;
     if (in_range) prim = __float_as_uint(a.hits[i].y);
@@ -131,19 +146,32 @@ __global__ __launch_bounds__(256) void hit_backward_kernel(backward_args a)
     const bool head = lane == 0 || prev_key != key;
 #pragma unroll
     for (int k = 0; k < 9; ++k) g[k] = run_suffix_sum(g[k], lane, run_end);
+    __syncthreads();  // the table is cleared
     if (ok && head) {
-        float *g0 = a.grad_vertices + 3 * size_t(f0);
-        float *g1 = a.grad_vertices + 3 * size_t(f1);
-        float *g2 = a.grad_vertices + 3 * size_t(f2);
-        unsafeAtomicAdd(g0 + 0, g[0]);
-        unsafeAtomicAdd(g0 + 1, g[1]);
-        unsafeAtomicAdd(g0 + 2, g[2]);
-        unsafeAtomicAdd(g1 + 0, g[3]);
-        unsafeAtomicAdd(g1 + 1, g[4]);
-        unsafeAtomicAdd(g1 + 2, g[5]);
-        unsafeAtomicAdd(g2 + 0, g[6]);
-        unsafeAtomicAdd(g2 + 1, g[7]);
-        unsafeAtomicAdd(g2 + 2, g[8]);
+        const uint32_t fv[3] = {f0, f1, f2};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            // open addressing with linear probing: at most 3 * kBackwardBlock
+            // keys in kTable slots, so an empty or matching slot is found
+            uint32_t slot = (fv[k] * 2654435761u) >> 20;  // 12 bits: kTable = 4096
+            for (;;) {
+                const uint32_t old = atomicCAS(&tkey[slot], kEmpty, fv[k]);
+                if (old == kEmpty || old == fv[k]) break;
+                slot = (slot + 1) & (kTable - 1);
+            }
+            atomicAdd(&tval[0][slot], g[3 * k]);
+            atomicAdd(&tval[1][slot], g[3 * k + 1]);
+            atomicAdd(&tval[2][slot], g[3 * k + 2]);
+        }
+    }
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < kTable; s += kBackwardBlock) {
+        const uint32_t vtx = tkey[s];
+        if (vtx == kEmpty) continue;
+        float *gp = a.grad_vertices + 3 * size_t(vtx);
+        unsafeAtomicAdd(gp + 0, tval[0][s]);
+        unsafeAtomicAdd(gp + 1, tval[1][s]);
+        unsafeAtomicAdd(gp + 2, tval[2][s]);
     }
     if (in_range && a.grad_rays) {
         a.grad_rays[2 * size_t(i)] = make_float4(lx, ly, lz, 0.0f);
@@ -164,8 +192,8 @@ rt_status launch_hit_backward(const BackwardRequest &q, const char **err)
     a.n_tris = q.n_tris;
     a.grad_vertices = q.grad_vertices;
     a.grad_rays = static_cast<float4 *>(q.grad_rays);
-    const uint32_t grid = (q.n_rays + 255) / 256;
-    hipLaunchKernelGGL(hit_backward_kernel, dim3(grid), dim3(256), 0,
+    const uint32_t grid = (q.n_rays + kBackwardBlock - 1) / kBackwardBlock;
+    hipLaunchKernelGGL(hit_backward_kernel, dim3(grid), dim3(kBackwardBlock), 0,
                        static_cast<hipStream_t>(q.stream), a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
