@@ -449,11 +449,12 @@ def bench_diff(args):
     plus 5k alpha billboards; loss = sum w.(t, u, v).  Forward = one alpha
     closest-hit launch; forward+backward adds the zeroing of the vertex
     gradient and one rt_hit_backward launch; beside them the plain default
-    intersector on the same scene and rays."""
+    intersector on the same scene and rays.  Without --shape the autotuner
+    picks the launch shape of these 262 k rays (fewer than the resident
+    lanes) first, untimed, on the alpha forward."""
     import torch
-    from paper_1912_12786_amd import diff, rtx
+    from paper_1912_12786_amd import autotune, diff, rtx
     from paper_1912_12786_amd import workloads as W
-    shape = parse_shape(args.shape)
     dev = torch.device("cuda:0")
     width = 512
     wl = W.diff_scene(width=width, height=width)
@@ -470,6 +471,16 @@ def bench_diff(args):
     gR = torch.empty_like(rays)
     ws = rtx.Workspace(dev)
     stream = torch.cuda.current_stream(dev)
+    shape_ms = None
+    if args.shape:
+        shape = parse_shape(args.shape)
+    else:
+        shape, shape_ms = autotune.tune(
+            "bench-diff-alpha",
+            lambda sh: rtx.trace(scene, rays, "alpha", alpha_min=128, out=hits, workspace=ws,
+                                 shape=sh, image_width=tw),
+            cache_path=None, steps=10, warmup=2)
+        log(f"autotuner: differentiable-hit launch shape {','.join(map(str, shape))}")
 
     def fwd():
         rtx.trace(scene, rays, "alpha", alpha_min=128, out=hits, workspace=ws, shape=shape,
@@ -519,7 +530,9 @@ def bench_diff(args):
         "data": "synthetic",
         "config": {"workload": wl.name, "n_tris": int(wl.faces.shape[0]), "max_leaf": args.max_leaf,
                    "n_vertices": int(wl.vertices.shape[0]), "n_rays": n,
-                   "schedule": ("8x8 pixel tiles" if tw else "index order")},
+                   "schedule": ("8x8 pixel tiles" if tw else "index order"),
+                   "launch_shape": list(shape) if shape else None},
+        "autotuned_shape_ms": shape_ms,
         "forward_mrays_s": round(n / ms_f / 1e3, 2),
         "forward_backward_mrays_s": round(n / ms_fb / 1e3, 2),
         "plain_default_mrays_s": round(n / ms_p / 1e3, 2),

@@ -31,7 +31,7 @@ def _same_cuda_device(**tensors):
 class DifferentiableHit(torch.autograd.Function):
     """``tuv, prim, hit = DifferentiableHit.apply(rays, vertices, faces, geom_ids,
     texcoords, textures, intersector, alpha_min, checker_n, max_leaf, image_width,
-    refit)``
+    refit, shape)``
 
     rays float32 [N, 8] and vertices float32 [nv, 3] on one GPU (both may
     require grad; anything else raises ValueError before a launch); faces
@@ -42,12 +42,16 @@ class DifferentiableHit(torch.autograd.Function):
     width in scanline order, traced in 8 x 8 tiles (same results); refit: a
     ``rtx.RefitScene`` of this mesh (its faces, texture data and leaf limit
     replace the arguments'), refitted on the device to ``vertices`` instead
-    of a host rebuild.  Returns tuv float32 [N, 3]
+    of a host rebuild; shape: the forward's launch shape (one of
+    ``rtx.rt_launch_shapes()``, None for the default; results do not depend
+    on it -- a launch with fewer rays than resident lanes runs faster without
+    the persistent queue).  Returns tuv float32 [N, 3]
     (zeros for misses), prim int32 [N] (-1 for misses) and hit bool [N]."""
 
     @staticmethod
     def forward(ctx, rays, vertices, faces, geom_ids, texcoords, textures, intersector="default",
-                alpha_min=128, checker_n=8, max_leaf=4, image_width=None, refit=None):
+                alpha_min=128, checker_n=8, max_leaf=4, image_width=None, refit=None,
+                shape=None):
         _same_cuda_device(rays=rays, vertices=vertices)
         v = vertices.detach()
         if refit is not None:
@@ -59,7 +63,7 @@ class DifferentiableHit(torch.autograd.Function):
             scene = rtx.upload_scene(tris, geom_ids, texcoords, textures, device=rays.device,
                                      max_leaf=max_leaf)
         hits = rtx.trace(scene, rays.detach().contiguous(), intersector, alpha_min=alpha_min,
-                         checker_n=checker_n, image_width=image_width)
+                         checker_n=checker_n, image_width=image_width, shape=shape)
         prim = hits[:, 1].view(torch.int32).clone()
         hit = prim != -1
         tuv = hits[:, [0, 2, 3]].clone()
@@ -83,7 +87,8 @@ class DifferentiableHit(torch.autograd.Function):
                             vertices.data_ptr(), vertices.shape[0], faces.data_ptr(),
                             faces.shape[0], grad_vertices.data_ptr(), grad_rays.data_ptr(),
                             stream)
-        return grad_rays, grad_vertices, None, None, None, None, None, None, None, None, None, None
+        return (grad_rays, grad_vertices, None, None, None, None, None, None, None, None, None,
+                None, None)
 
 
 def hit_backward(rays, hits, grad_tuv, vertices, faces, grad_vertices=None, grad_rays=True):

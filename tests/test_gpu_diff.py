@@ -183,6 +183,34 @@ def test_autograd_tiled_forward(diff_setup):
     assert torch.all(d <= 1e-4 * res[0][3].norm(dim=1) + 1e-7 * res[0][3].norm(dim=1).max())
 
 
+def test_autograd_forward_launch_shapes(diff_setup):
+    """The forward in every compiled launch shape that traces float32 nodes
+    gives the same (t, u, v), primitives and ray gradients as the default
+    shape, tiled and with a refit scene too."""
+    import torch
+    from paper_1912_12786_amd import diff, rtx
+    wl, tris, scene, bvh = diff_setup
+    V = torch.from_numpy(wl.vertices).cuda()
+    F = torch.from_numpy(wl.faces.astype(np.int32)).cuda()
+    w = torch.from_numpy(wl.weights).cuda()
+    rs = rtx.RefitScene(wl.vertices, wl.faces, wl.geom_ids, wl.texcoords, wl.textures,
+                        max_leaf=2)
+    ref = None
+    for sh in [None] + [tuple(x) for x in rtx.rt_launch_shapes()]:
+        announce(f"DifferentiableHit with launch shape {sh}")
+        for refit in (None, rs):
+            rays = torch.from_numpy(wl.rays).cuda().requires_grad_(True)
+            tuv, prim, hit = diff.DifferentiableHit.apply(rays, V, F, wl.geom_ids, wl.texcoords,
+                                                          wl.textures, "alpha", 128, 8, 2, 512,
+                                                          refit, sh)
+            (tuv * w).sum().backward()
+            torch.cuda.synchronize()
+            got = (tuv.detach().view(torch.int32), prim, rays.grad.view(torch.int32))
+            if ref is None:
+                ref = got
+            assert all(torch.equal(a, b) for a, b in zip(ref, got)), (sh, refit is not None)
+
+
 def test_host_faces_are_moved_to_the_vertices_device(diff_setup):
     """Faces given as a host tensor reach the backward kernel on the GPU
     (forward keeps a device copy); the gradients equal those of device faces."""
