@@ -66,12 +66,15 @@ def kernel_source_sha(sources=None) -> str:
 
 def default_order(workload: str, kind: str, query: str) -> str:
     """The chunk order bench.py uses unless ``--order`` names one: longest
-    path first for the alpha-mask closest and any hit on the billboards,
-    where it was measured faster, ray-index order elsewhere, where it was
-    measured slower (or, for the multi-hit query's lane-per-ray shape, has no
-    queue to order)."""
-    return ("longest-first" if (workload, kind) == ("billboards", "alpha")
-            and query in ("closest", "any") else "index")
+    path first for the alpha-mask closest and any hit and the accept-all
+    closest hit on the billboards, where it was measured faster, ray-index
+    order elsewhere, where it was measured slower (or, for the multi-hit
+    query's lane-per-ray shape, has no queue to order)."""
+    if workload != "billboards":
+        return "index"
+    if kind == "alpha" and query in ("closest", "any"):
+        return "longest-first"
+    return "longest-first" if (kind, query) == ("default", "closest") else "index"
 
 
 def find_counters(sha, workload, kind, query, layout, max_leaf, shape, ray_order,
@@ -787,10 +790,16 @@ def main():
     args = ap.parse_args()
     if args.max_leaf is None:
         args.max_leaf = 4 if args.workload == "instanced" else 2
+    kind0 = args.intersector or {"billboards": "alpha"}.get(args.workload)
+    accept_all = (args.workload, kind0, args.query) == ("billboards", "default", "closest")
     if args.layout is None:
-        kind0 = args.intersector or {"billboards": "alpha"}.get(args.workload)
         args.layout = ("q8" if args.workload in ("spheres", "batched") else
-                       "f32p" if (args.workload, kind0) == ("billboards", "alpha") else "f32")
+                       "f32p" if (args.workload == "billboards" and kind0 in ("alpha", "default"))
+                       else "f32")
+    if args.shape is None and accept_all and not args.tune_build:
+        # the build autotuner's choice there: a lane per ray, no queue (short,
+        # even rays lose more coherence to refills than they gain)
+        args.shape = "64,8,64,0"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the traversal shards by rays with no exchange "
               "step, so multi-GPU runs are not part of this benchmark", file=sys.stderr)
@@ -843,9 +852,9 @@ def main():
         tw = int(wl.extra["width"]) if (args.schedule == "tiles" and args.ray_order == "scanline"
                                         and "width" in wl.extra) else None
         scene, tuned = autotune.tune_scene(
-            f"bench-{wl.name}-{kind}", wl.vertices, torch.from_numpy(wl.rays).to(dev), kind,
-            geom_ids=wl.geom_ids, texcoords=wl.texcoords, textures=wl.textures, cache_path=None,
-            image_width=tw, device=dev)
+            f"bench-{wl.name}-{kind}-{args.query}", wl.vertices, torch.from_numpy(wl.rays).to(dev),
+            kind, query=args.query, k=args.k, geom_ids=wl.geom_ids, texcoords=wl.texcoords,
+            textures=wl.textures, cache_path=None, image_width=tw, device=dev)
         args.max_leaf, args.layout = tuned["max_leaf"], tuned["layout"]
         args.shape = ",".join(map(str, tuned["shape"]))
         args.order = "longest-first" if tuned["longest_first"] else "index"

@@ -130,7 +130,8 @@ def _store(cache_path, cache):
     os.replace(tmp, cache_path)
 
 
-def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_ids=None,
+def tune_scene(key: str, vertices, rays, intersector: str = "default", *, query: str = "closest",
+               k: int = 1, geom_ids=None,
                texcoords=None, textures=None, alpha_min: int = 128, checker_n: int = 8,
                leaf_sizes=(2, 3, 4), layouts=("f32", "q8", "f32p", "wide4"),
                cache_path: str | None = DEFAULT_CACHE, longest_first=(False, True),
@@ -138,8 +139,9 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
                steps: int = 5, warmup: int = 1, finals: int = 4, final_margin: float = 0.04,
                rounds: int = 3, retune: bool = False, device="cuda"):
     """Chooses the BVH leaf size, node layout, launch shape and chunk order
-    (index or longest-path-first) that trace ``rays`` (device float32 [N, 8],
-    closest hit; an image of ``image_width`` in scanline order when given)
+    (index or longest-path-first) that trace ``rays`` (device float32 [N, 8];
+    ``query`` "closest", "any" or "multi" with ``k``; an image of
+    ``image_width`` in scanline order when given)
     fastest through the scene, then, for a queue shape, the most resident
     waves per SIMD among ``waves`` for that choice.  The first pass times
     each candidate once, in a fixed order; the (at most ``finals``) fastest
@@ -169,14 +171,17 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
         choice = entry
     else:
         ws = rtx.Workspace(device)
-        out = torch.empty((rays.shape[0], 4), dtype=torch.float32, device=rays.device)
+        # the output of the timed query: [N, 4] hits, [N] occluders (fit in
+        # the same), or [N, k, 4] for the k nearest hits
+        out = torch.empty((rays.shape[0], 4 * (max(1, k) if query == "multi" else 1)),
+                          dtype=torch.float32, device=rays.device)
         timings = {}
         for max_leaf in leaf_sizes:
             for layout in layouts:
                 scene = build(max_leaf, layout)
                 for lf in longest_first:
-                    t = time_shapes(lambda sh: rtx.trace(scene, rays, intersector, out=out,
-                                                         workspace=ws, shape=sh,
+                    t = time_shapes(lambda sh: rtx.trace(scene, rays, intersector, query=query,
+                                                         k=k, out=out, workspace=ws, shape=sh,
                                                          image_width=image_width,
                                                          longest_first=lf, **kw), steps, warmup)
                     for shape, ms in t.items():
@@ -191,11 +196,12 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
             for lk in scenes:
                 scenes[lk] = build(*lk)
             finals_ms = _interleaved(
-                finalists, lambda k: (lambda sh: rtx.trace(scenes[k[:2]], rays, intersector,
-                                                            out=out, workspace=ws, shape=sh,
+                finalists, lambda c: (lambda sh: rtx.trace(scenes[c[:2]], rays, intersector,
+                                                            query=query, k=k, out=out,
+                                                            workspace=ws, shape=sh,
                                                             image_width=image_width,
-                                                            longest_first=k[3], **kw)),
-                lambda k: k[2], steps, warmup, rounds)
+                                                            longest_first=c[3], **kw)),
+                lambda c: c[2], steps, warmup, rounds)
             del scenes
             best = min(finals_ms, key=finals_ms.get)
         else:
@@ -209,8 +215,9 @@ def tune_scene(key: str, vertices, rays, intersector: str = "default", *, geom_i
             scene = build(best[0], best[1])
             wt = _interleaved(
                 [int(w) for w in waves],
-                lambda w: (lambda sh: rtx.trace(scene, rays, intersector, out=out, workspace=ws,
-                                                shape=sh, image_width=image_width,
+                lambda w: (lambda sh: rtx.trace(scene, rays, intersector, query=query, k=k,
+                                                out=out, workspace=ws, shape=sh,
+                                                image_width=image_width,
                                                 longest_first=best[3], waves_per_simd=w, **kw)),
                 lambda w: best[2], steps, warmup, max(1, rounds))
             del scene

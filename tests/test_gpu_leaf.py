@@ -137,6 +137,38 @@ def test_tune_scene_chooses_a_build_and_shape(env, oracle_lib, tmp_path):
     assert again == choice
 
 
+def test_tune_scene_times_the_given_query(env, oracle_lib):
+    """tune_scene with the any-hit and the multi-hit query (its output buffer
+    sized for k hits): the chosen build's occluders equal oracle B's, and its
+    k nearest hits equal those of the same scene in the default shape."""
+    torch, rtx = env
+    from paper_1912_12786_amd import autotune
+    wl = W.tiny()
+    ai = tiny_alpha_inputs(wl.n_tris)
+    rays = torch.from_numpy(wl.rays).cuda()
+    kw = dict(leaf_sizes=(2,), layouts=("f32", "f32p"), waves=(6, 7), steps=1, warmup=1,
+              rounds=1, cache_path=None, **ai)
+    announce("tune_scene with the any-hit query")
+    sc, choice = autotune.tune_scene("tiny-any", wl.vertices, rays, "alpha", query="any", **kw)
+    occ = rtx.trace(sc, rays, "alpha", query="any", alpha_min=128, shape=tuple(choice["shape"]),
+                    longest_first=choice["longest_first"], waves_per_simd=choice["waves_per_simd"])
+    torch.cuda.synchronize()
+    bvh = oracle_lib.build_bvh(wl.vertices, max_leaf=choice["max_leaf"])
+    B = oracle_lib.traverse(wl.vertices, bvh, wl.rays, "alpha", any_hit=True,
+                            layout=choice["layout"], alpha_min=128, **ai)
+    assert np.array_equal(P.occluders_to_numpy(occ), B["prim"])
+    announce("tune_scene with the 3-nearest query")
+    sc, choice = autotune.tune_scene("tiny-multi", wl.vertices, rays, "alpha", query="multi", k=3,
+                                     **kw)
+    got, n_got = rtx.trace(sc, rays, "alpha", query="multi", k=3, alpha_min=128,
+                           shape=tuple(choice["shape"]), longest_first=choice["longest_first"],
+                           waves_per_simd=choice["waves_per_simd"])
+    ref, n_ref = rtx.trace(sc, rays, "alpha", query="multi", k=3, alpha_min=128)
+    torch.cuda.synchronize()
+    assert torch.equal(n_got, n_ref)
+    assert torch.equal(got.view(torch.int32), ref.view(torch.int32))
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_random_builds_bit_exact(env, oracle_lib, seed):
     """The random sweep's scenes and rays with a random leaf size limit and
