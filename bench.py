@@ -66,13 +66,14 @@ def kernel_source_sha(sources=None) -> str:
 
 def default_order(workload: str, kind: str, query: str) -> str:
     """The chunk order bench.py uses unless ``--order`` names one: longest
-    path first for the alpha-mask closest and any hit and the accept-all
-    closest hit on the billboards, where it was measured faster, ray-index
-    order elsewhere, where it was measured slower (or, for the multi-hit
-    query's lane-per-ray shape, has no queue to order)."""
+    path first for the alpha mask's closest, any and k-nearest hits and the
+    accept-all closest hit on the billboards, where it was measured faster
+    (also in a lane-per-ray shape without the queue, whose waves take their
+    chunks in that order), ray-index order elsewhere, where it was measured
+    slower."""
     if workload != "billboards":
         return "index"
-    if kind == "alpha" and query in ("closest", "any"):
+    if kind == "alpha" and query in ("closest", "any", "multi"):
         return "longest-first"
     return "longest-first" if (kind, query) == ("default", "closest") else "index"
 
