@@ -768,6 +768,14 @@ struct ray_feed {
 // kLeafBreak/16 of its busy lanes are still at inner nodes: waiting for the
 // last lane to reach a leaf would issue every node fetch for a few lanes.
 constexpr uint32_t kLeafBreak = 8;
+// Lane masks from compares: an LLVM integer-compare predicate code for
+// __builtin_amdgcn_uicmp (ne, unsigned less-than), the first reference of
+// a leaf (count 1 << 29: inner references are below it), and the key of a
+// finished lane.
+constexpr int kIcmpNE = 33, kIcmpULT = 36;
+constexpr uint32_t kRefCountUnit = 1u << 29;
+constexpr uint32_t kNoRef = 0xFFFFFFFFu;
+
 __device__ __forceinline__ bool leave_inner_phase(uint32_t n_inner, uint32_t n_leaf)
 {
     return 16u * n_inner < kLeafBreak * (n_inner + n_leaf);
@@ -867,10 +875,16 @@ void trace_kernel(kernel_args a, typename Isect::params p)
             // +2.6 % alpha billboards, +1.8 % spheres, default unchanged)
             __builtin_amdgcn_s_setprio(1);
             for (;;) {
-                const bool in_inner = active && ref_count(cur) == 0;
-                const uint64_t mi = __ballot(in_inner);
+                // the two lane masks straight from compares (a ballot of a
+                // combined condition costs a select and a compare more
+                // each): finished lanes carry the key kNoRef, which no
+                // reference equals (a leaf of 7 triangles at index 2^29 - 1
+                // would end past the largest triangle count)
+                const uint32_t key = active ? cur : kNoRef;
+                const uint64_t mi = __builtin_amdgcn_uicmp(key, kRefCountUnit, kIcmpULT);
                 if (mi == 0) break;
-                const uint64_t ml = __ballot(active && !in_inner);
+                const uint64_t ml = __builtin_amdgcn_uicmp(key, kNoRef, kIcmpNE) & ~mi;
+                const bool in_inner = key < kRefCountUnit;
                 if (ml != 0 && leave_inner_phase(uint32_t(__popcll(mi)), uint32_t(__popcll(ml))))
                     break;
                 if (in_inner && !inner_step<kLayout>(sc, r, isect, st, cur)) active = false;
