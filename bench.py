@@ -78,6 +78,21 @@ def default_order(workload: str, kind: str, query: str) -> str:
     return "longest-first" if (kind, query) == ("default", "closest") else "index"
 
 
+def default_build(workload: str, intersector, query: str):
+    """(node layout, launch shape or None) bench.py uses unless --layout or
+    --shape name them: 8-bit nodes for the spheres and the batch, where the
+    node working set outgrows the caches, packed 48-byte nodes on the
+    billboards, float32 nodes otherwise; the library's default shape except
+    for the accept-all closest hit on the billboards, where the build
+    autotuner chose a lane per ray without the queue (short, even rays lose
+    more coherence to refills than the queue saves)."""
+    kind = intersector or {"billboards": "alpha"}.get(workload)
+    layout = ("q8" if workload in ("spheres", "batched") else
+              "f32p" if workload == "billboards" and kind in ("alpha", "default") else "f32")
+    shape = "64,8,64,0" if (workload, kind, query) == ("billboards", "default", "closest") else None
+    return layout, shape
+
+
 def find_counters(sha, workload, kind, query, layout, max_leaf, shape, ray_order,
                   schedule="index", order="index", waves=7):
     """The rocprofv3 counter record (``profiles/counters_*.json``) taken on
@@ -791,16 +806,11 @@ def main():
     args = ap.parse_args()
     if args.max_leaf is None:
         args.max_leaf = 4 if args.workload == "instanced" else 2
-    kind0 = args.intersector or {"billboards": "alpha"}.get(args.workload)
-    accept_all = (args.workload, kind0, args.query) == ("billboards", "default", "closest")
+    layout0, shape0 = default_build(args.workload, args.intersector, args.query)
     if args.layout is None:
-        args.layout = ("q8" if args.workload in ("spheres", "batched") else
-                       "f32p" if (args.workload == "billboards" and kind0 in ("alpha", "default"))
-                       else "f32")
-    if args.shape is None and accept_all and not args.tune_build:
-        # the build autotuner's choice there: a lane per ray, no queue (short,
-        # even rays lose more coherence to refills than they gain)
-        args.shape = "64,8,64,0"
+        args.layout = layout0
+    if args.shape is None and not args.tune_build:
+        args.shape = shape0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the traversal shards by rays with no exchange "
               "step, so multi-GPU runs are not part of this benchmark", file=sys.stderr)

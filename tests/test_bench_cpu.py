@@ -67,3 +67,23 @@ def test_bytes_per_ray_wide_nodes():
     c = np.array([[9, 2, 1, 1]], np.uint32)
     assert bench.bytes_per_ray(c, "default", node_bytes=128, children=4).tolist() == \
         [48 + 8 * 32 + 2 * 48]
+
+
+def test_default_builds_and_orders():
+    """bench.py's per-workload defaults: the measured choices (packed nodes
+    and longest-first order on the billboards for the alpha mask's queries
+    and the accept-all closest hit, the latter without the queue; 8-bit
+    nodes for the spheres and the batch)."""
+    assert bench.default_build("billboards", None, "closest") == ("f32p", None)
+    assert bench.default_build("billboards", "alpha", "any") == ("f32p", None)
+    assert bench.default_build("billboards", "default", "closest") == ("f32p", "64,8,64,0")
+    assert bench.default_build("billboards", "default", "any") == ("f32p", None)
+    assert bench.default_build("spheres", None, "closest") == ("q8", None)
+    assert bench.default_build("batched", None, "closest") == ("q8", None)
+    assert bench.default_build("tiny", None, "closest") == ("f32", None)
+    for q in ("closest", "any", "multi"):
+        assert bench.default_order("billboards", "alpha", q) == "longest-first"
+    assert bench.default_order("billboards", "default", "closest") == "longest-first"
+    assert bench.default_order("billboards", "default", "any") == "index"
+    assert bench.default_order("spheres", "procedural", "closest") == "index"
+    assert bench.default_order("tiny", "default", "closest") == "index"
